@@ -1,0 +1,222 @@
+"""Seeded synthetic inputs shared by the oracle and the HIP path.
+
+This module holds no arithmetic of the solver itself: only the workload
+descriptions (grid sizes, viscosity, body geometry and motion parameters),
+a counter-based random generator, and closed-form initial velocity fields
+sampled at the staggered face positions.
+
+Layout convention used by every array produced here (numpy, float64):
+component ``i`` of a velocity field is an array of shape ``(N0+2, N1+2[, N2+2])``
+indexed ``[I0, I1, I2]`` over the padded grid (one ghost layer per side).
+Cell ``I`` has its centre at ``x = I - 1/2`` (grid units, h = 1) and
+``u_i[I]`` sits on the lower ``i``-face of cell ``I``, i.e. at ``x_i = I_i - 1``.
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+from typing import Optional, Sequence, Tuple
+
+import numpy as np
+
+# ---------------------------------------------------------------------------
+# counter-based SplitMix64 (Steele, Lea & Flood 2014, "Fast splittable
+# pseudorandom number generators"); state_k = seed + (k+1)*gamma, then the
+# published 64-bit finaliser.
+# ---------------------------------------------------------------------------
+_GAMMA = np.uint64(0x9E3779B97F4A7C15)
+_M1 = np.uint64(0xBF58476D1CE4E5B9)
+_M2 = np.uint64(0x94D049BB133111EB)
+
+
+def splitmix64(counter: np.ndarray, seed: int = 0) -> np.ndarray:
+    """64-bit SplitMix64 output for each counter value (uint64 array)."""
+    with np.errstate(over="ignore"):
+        z = np.uint64(seed) + (counter.astype(np.uint64) + np.uint64(1)) * _GAMMA
+        z = (z ^ (z >> np.uint64(30))) * _M1
+        z = (z ^ (z >> np.uint64(27))) * _M2
+        z = z ^ (z >> np.uint64(31))
+    return z
+
+
+def uniform01(counter: np.ndarray, seed: int = 0) -> np.ndarray:
+    """Doubles in [0, 1) from the top 53 bits of SplitMix64."""
+    return (splitmix64(counter, seed) >> np.uint64(11)).astype(np.float64) * (2.0 ** -53)
+
+
+def face_noise(shape: Sequence[int], comp: int, amp: float, seed: int = 0) -> np.ndarray:
+    """iid U[-amp, amp) per (component, padded linear index), x fastest."""
+    shape = tuple(int(s) for s in shape)
+    size = int(np.prod(shape))
+    # linear index with axis 0 (x) fastest
+    lin = np.arange(size, dtype=np.uint64).reshape(shape[::-1]).T
+    counter = np.uint64(comp) * np.uint64(size) + lin
+    return (2.0 * uniform01(counter, seed) - 1.0) * amp
+
+
+# ---------------------------------------------------------------------------
+# bodies and workloads
+# ---------------------------------------------------------------------------
+@dataclasses.dataclass
+class Body:
+    """Analytic rigid body.  ``kind`` is 'none', 'sphere' (circle in 2-D) or 'box'.
+
+    Motion: centre c(t) = center + heave_amp*sin(2 pi freq t + phase_h) e_y;
+    rotation angle about e_z through c(t) + pivot_offset:
+    theta(t) = pitch_amp*sin(2 pi freq t + phase_p) + spin_omega*t.
+    """
+    kind: str = "none"
+    center: Tuple[float, ...] = (0.0, 0.0, 0.0)
+    radius: float = 0.0
+    half_extent: Tuple[float, ...] = (0.0, 0.0, 0.0)
+    heave_amp: float = 0.0
+    pitch_amp: float = 0.0
+    freq: float = 0.0
+    phase_h: float = 0.0
+    phase_p: float = 0.0
+    pivot_offset: Tuple[float, ...] = (0.0, 0.0, 0.0)
+    spin_omega: float = 0.0
+
+    @property
+    def moving(self) -> bool:
+        return self.kind != "none" and (self.heave_amp != 0.0 or self.pitch_amp != 0.0
+                                        or self.spin_omega != 0.0)
+
+
+@dataclasses.dataclass
+class Workload:
+    name: str
+    n: Tuple[int, ...]                 # interior cells per axis (x first)
+    U: Tuple[float, ...]               # free-stream velocity
+    nu: float
+    body: Body = dataclasses.field(default_factory=Body)
+    periodic: Tuple[bool, ...] = ()
+    convective_exit: bool = False
+    steps: int = 100
+    tol: float = 1e-6
+    noise: float = 1e-3                # amplitude relative to |U|
+    init: str = "uniform"              # 'uniform' or 'tgv'
+    L: float = 1.0                     # length scale used for coefficients
+
+    @property
+    def ndim(self) -> int:
+        return len(self.n)
+
+    @property
+    def cells(self) -> int:
+        return int(np.prod(self.n))
+
+    def periodic_mask(self) -> Tuple[bool, ...]:
+        if self.periodic:
+            return tuple(self.periodic)
+        return tuple(False for _ in self.n)
+
+
+def circle_2d(n=(128, 64), R=8.0, center=(32.0, 32.0), Re=250.0, steps=100, tol=1e-6) -> Workload:
+    """2-D circle in uniform inflow (the small parity case)."""
+    D = 2 * R
+    return Workload("circle2d_%dx%d" % tuple(n), tuple(n), (1.0, 0.0), D / Re,
+                    Body("sphere", center=tuple(center), radius=R), steps=steps, tol=tol, L=D)
+
+
+def tgv_3d(N=128, Re=1600.0, steps=500, tol=1e-6) -> Workload:
+    """Periodic Taylor-Green vortex box, kappa = 2 pi / N, U = 1, Re = U/(kappa nu)."""
+    kappa = 2 * math.pi / N
+    return Workload("tgv3d_%d" % N, (N, N, N), (0.0, 0.0, 0.0), 1.0 / (kappa * Re),
+                    periodic=(True, True, True), steps=steps, tol=tol, noise=0.0, init="tgv",
+                    L=N / (2 * math.pi))
+
+
+def sphere_3d(n=(256, 128, 128), D=32.0, center=(64.0, 64.0, 64.0), Re=3700.0, steps=1000,
+              tol=1e-6) -> Workload:
+    return Workload("sphere3d_%dx%dx%d" % tuple(n), tuple(n), (1.0, 0.0, 0.0), D / Re,
+                    Body("sphere", center=tuple(center), radius=D / 2), convective_exit=True,
+                    steps=steps, tol=tol, L=D)
+
+
+def rotating_cylinder_2d(n=(512, 256), D=32.0, center=(128.0, 128.0), Re=200.0, xi=1.0,
+                         steps=400, tol=1e-12) -> Workload:
+    """Rotation rate xi = (1/2) D Omega / U (counter-clockwise)."""
+    omega = 2.0 * xi * 1.0 / D
+    return Workload("rotcyl2d_%dx%d" % tuple(n), tuple(n), (1.0, 0.0), D / Re,
+                    Body("sphere", center=tuple(center), radius=D / 2, spin_omega=omega),
+                    steps=steps, tol=tol, L=D)
+
+
+def plate_3d(scale: int = 1, steps=200, tol=1e-5) -> Workload:
+    """Heaving-pitching flat plate; scale=1 is 768x384x384 cells (113 M).
+
+    Chord c = 64/scale, thickness 4/scale (min 2), span 2c, heave 0.25 c,
+    pitch 20 degrees about the quarter chord, pitch leading heave by 90 degrees,
+    Strouhal f (2 h0)/U = 0.3, Re = U c / nu = 5000.
+    """
+    n = (768 // scale, 384 // scale, 384 // scale)
+    c = 64.0 / scale
+    th = max(4.0 / scale, 2.0)
+    h0 = 0.25 * c
+    f = 0.3 / (2 * h0)
+    ctr = (n[0] / 4.0, n[1] / 2.0, n[2] / 2.0)
+    body = Body("box", center=ctr, half_extent=(c / 2, th / 2, c), heave_amp=h0,
+                pitch_amp=math.radians(20.0), freq=f, phase_h=0.0, phase_p=math.pi / 2,
+                pivot_offset=(-c / 4, 0.0, 0.0))
+    return Workload("plate3d_%dx%dx%d" % n, n, (1.0, 0.0, 0.0), c / 5000.0, body,
+                    convective_exit=True, steps=steps, tol=tol, L=c)
+
+
+# ---------------------------------------------------------------------------
+# initial velocity fields (inputs, sampled at face positions)
+# ---------------------------------------------------------------------------
+def face_coords(n: Sequence[int], comp: int):
+    """Coordinates of the padded face points of component ``comp``."""
+    axes = []
+    for a, N in enumerate(n):
+        I = np.arange(N + 2, dtype=np.float64)
+        axes.append(I - 1.0 if a == comp else I - 0.5)
+    return np.meshgrid(*axes, indexing="ij")
+
+
+def initial_velocity(w: Workload, seed: int = 0):
+    """Initial face velocities (list of padded float64 arrays).
+
+    'uniform': u = U + U[-1e-3, 1e-3)*|U| iid noise (seeded SplitMix64).
+    'tgv': u = sin(kx)cos(ky)cos(kz), v = -cos(kx)sin(ky)cos(kz), w = 0, k = 2 pi / N.
+    """
+    shape = tuple(N + 2 for N in w.n)
+    out = []
+    if w.init == "tgv":
+        k = 2 * math.pi / w.n[0]
+        for i in range(w.ndim):
+            X = face_coords(w.n, i)
+            if i == 0:
+                f = np.sin(k * X[0]) * np.cos(k * X[1])
+            elif i == 1:
+                f = -np.cos(k * X[0]) * np.sin(k * X[1])
+            else:
+                f = np.zeros(shape)
+            if w.ndim == 3 and i < 2:
+                f = f * np.cos(k * X[2])
+            out.append(np.ascontiguousarray(f))
+        return out
+    Umag = math.sqrt(sum(u * u for u in w.U))
+    for i in range(w.ndim):
+        f = np.full(shape, float(w.U[i]))
+        if w.noise > 0:
+            f = f + face_noise(shape, i, w.noise * Umag, seed)
+        out.append(f)
+    return out
+
+
+def tgv2d_exact(n: int, nu: float, t: float, U: float = 1.0):
+    """2-D Taylor-Green closed form at the face points of a periodic n x n grid."""
+    k = 2 * math.pi / n
+    F = math.exp(-2 * nu * k * k * t)
+    X0 = face_coords((n, n), 0)
+    X1 = face_coords((n, n), 1)
+    u = U * np.sin(k * X0[0]) * np.cos(k * X0[1]) * F
+    v = -U * np.cos(k * X1[0]) * np.sin(k * X1[1]) * F
+    return [u, v]
+
+
+def random_field(shape, seed: int, comp: int = 0, amp: float = 1.0):
+    """Generic seeded test field U[-amp, amp)."""
+    return face_noise(shape, comp, amp, seed)
