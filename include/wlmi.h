@@ -1,0 +1,203 @@
+/*
+ * wlmi.h - C ABI of the MI355X BDIM projection solver step.
+ *
+ * The library computes one time step of the boundary-data-immersion method
+ * (BDIM) on a staggered uniform Cartesian grid, as described in the
+ * numerical-methods section of Weymouth & Font, "WaterLily.jl: a
+ * differentiable and backend-agnostic Julia solver for incompressible viscous
+ * flow around dynamic bodies" (arXiv 2407.16032): the limited-QUICK
+ * convection-diffusion flux, the BDIM blend of the fluid update with the
+ * body's kernel moments mu0/mu1, and the pressure projection solved by
+ * geometric multigrid with a Jacobi-PCG smoother, inside an explicit
+ * predictor-corrector step with an adaptive CFL time step.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Units: grid units, h = 1 cell.  Cell I (0-based padded index, interior
+ *   1..n[d], one ghost layer per side; the paper's inside(p)) has its centre
+ *   at x = I - 1/2.  Velocity component i at index I sits on the lower
+ *   i-face of cell I (x_i = I_i - 1).
+ * Layout: every field is a device array of the simulation's precision (float
+ *   or double), one array per component, x fastest:
+ *     element (i, j, k) at  ((k * py) + j) * px + i,
+ *   px >= n[0]+2 (row pitch, a multiple of 64 elements), py = n[1]+2,
+ *   pz = n[2]+2 (pz = 1 in 2-D).  wl_field() reports shapes and strides.
+ * Memory: the caller allocates ONE device workspace of wl_workspace_bytes()
+ *   bytes and owns it; the library never allocates device memory and keeps
+ *   only a small host object (plus 64 bytes of pinned host memory for
+ *   scalar read-back).  All fields live inside the workspace.
+ * Streams: all device work is enqueued on the hipStream_t given at creation.
+ *   Calls return after enqueueing, except that the multigrid solve reads one
+ *   residual norm per V-cycle back to the host (a stream synchronisation)
+ *   and wl_step reads the new time step at its end.
+ * Errors: every call returns wl_status; nothing throws across the ABI.
+ *   Argument errors are detected before any work is enqueued.  A multigrid
+ *   solve that reaches its cycle limit is NOT an error (converged = 0).
+ *   wl_last_error() gives a thread-local message for the last failure.
+ * Threading: a wl_sim is not thread-safe; distinct sims are independent.
+ */
+#ifndef WLMI_H
+#define WLMI_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  WL_OK = 0,
+  WL_ERR_INVALID_ARG = 1,
+  WL_ERR_WORKSPACE_TOO_SMALL = 2,
+  WL_ERR_HIP = 3,
+  WL_ERR_NONFINITE = 4,
+  WL_ERR_UNSUPPORTED = 5
+} wl_status;
+
+typedef enum { WL_F32 = 0, WL_F64 = 1 } wl_prec;
+
+/* Simulation description (paper, software-design section: Simulation takes
+ * the grid size, length/velocity scales, viscosity, boundary conditions, the
+ * body, the float type T).  Defaults in brackets are applied when a field is
+ * zero. */
+typedef struct {
+  int ndim;              /* 2 or 3 */
+  int64_t n[3];          /* interior cells per axis; n[2] ignored in 2-D.  Each >= 4. */
+  double U[3];           /* free-stream velocity (inflow/slip normal faces take U_i) */
+  double nu;             /* kinematic viscosity (>= 0) */
+  unsigned periodic_mask;/* bit d set -> axis d periodic */
+  int convective_exit;   /* 1 -> convective outlet on the +x face (needs U[0] != 0, x not periodic) */
+  int prec;              /* wl_prec: field precision; reductions are always FP64 */
+  double eps;            /* BDIM kernel half-width in cells [1] */
+  double dt0;            /* first time step [0.25] */
+  double dt_max;         /* upper bound of the CFL step [10] */
+  double cfl_nu_coef;    /* dt = min(dt_max, 1/(max outflux + cfl_nu_coef*nu)) [5] */
+  double mg_tol;         /* residual max-norm tolerance of the projection solve [1e-6] */
+  int mg_itmax;          /* maximum V-cycles per solve [32] */
+  int pcg_iters;         /* PCG smoothing iterations per level [6] */
+} wl_sim_desc;
+
+typedef enum { WL_BODY_NONE = 0, WL_BODY_SPHERE = 1, WL_BODY_BOX = 2 } wl_body_kind;
+
+/* Analytic rigid body (the paper's AutoBody restricted to a sphere/circle or
+ * a box moved rigidly).  Centre c(t) = center + heave_amp*sin(2 pi freq t +
+ * phase_h) e_y.  Rotation angle about e_z through P(t) = c(t) + pivot_offset:
+ * theta(t) = pitch_amp*sin(2 pi freq t + phase_p) + spin_omega*t.  Body-frame
+ * coordinates x_b = Rot(-theta)(x - P) + pivot_offset; SDF < 0 inside.
+ * The body must stay at least 3 cells away from non-periodic domain faces. */
+typedef struct {
+  int kind;                 /* wl_body_kind */
+  double center[3];
+  double radius;            /* sphere/circle */
+  double half_extent[3];    /* box */
+  double heave_amp, pitch_amp, freq, phase_h, phase_p;
+  double pivot_offset[3];
+  double spin_omega;
+} wl_body_desc;
+
+typedef struct {
+  double dt;            /* step just taken */
+  double t;             /* time after the step */
+  double dt_next;       /* CFL step for the next call */
+  int vcycles[2];       /* predictor / corrector multigrid V-cycles */
+  double res_linf[2];   /* final residual max-norms of the two solves (FP64) */
+  int converged;        /* 1 if both solves met mg_tol */
+} wl_step_stats;
+
+typedef struct {
+  int vcycles;
+  double res0_linf;     /* residual max-norm before the first cycle */
+  double res_linf;      /* after the last cycle */
+  int converged;
+} wl_solve_stats;
+
+typedef struct wl_sim wl_sim;
+
+/* Bytes of device workspace needed for (desc, body); 0 on invalid input. */
+size_t wl_workspace_bytes(const wl_sim_desc* desc, const wl_body_desc* body);
+
+/* Create a simulation in a caller-owned device workspace (256-byte aligned,
+ * at least wl_workspace_bytes bytes) on the given hipStream_t (NULL = the
+ * null stream).  Initialises u = U (with boundary conditions), p = 0, t = 0,
+ * dt = dt0, and measures the body at t = 0.  body may be NULL (no body). */
+wl_status wl_sim_create(const wl_sim_desc* desc, const wl_body_desc* body, void* dev_workspace,
+                        size_t bytes, void* hip_stream, wl_sim** out);
+
+/* Release the host object; the workspace stays the caller's. */
+wl_status wl_sim_destroy(wl_sim* sim);
+
+/* measure! (paper, performance section): evaluate d, n, V of the body at time
+ * t at every velocity point, store mu0 (which is also the fine Poisson
+ * coefficient L, with non-periodic boundary faces set to 0), mu1 = mu1(d) n,
+ * V, and rebuild the Poisson coefficients and inverse diagonals of every
+ * multigrid level. */
+wl_status wl_measure_body(wl_sim* sim, double t);
+
+/* One predictor-corrector time step n -> n+1 (numerical-methods section).
+ * remeasure != 0 re-runs measure at t_n first when the body moves.  Writes
+ * stats if non-NULL.  Returns WL_ERR_NONFINITE if the new time step is not
+ * finite (the velocity blew up). */
+wl_status wl_step(wl_sim* sim, int remeasure, wl_step_stats* stats);
+
+/* Apply the velocity boundary conditions to the current velocity field
+ * (call after writing u through a wl_field view). */
+wl_status wl_apply_bc(wl_sim* sim);
+
+/* Convection-diffusion residual R(u) of the current velocity into the
+ * scratch field WL_FIELD_F (R on the unknown faces, 0 elsewhere). */
+wl_status wl_conv_diff(wl_sim* sim);
+
+/* Projection stage alone on the current velocity with weight w (1 in the
+ * predictor, 1/2 in the corrector): z = div u, x0 = p w dt, multigrid solve of
+ * A x = z to mg_tol, u_i -= L_i (x[I] - x[I-e_i]), p = x/(w dt), then the
+ * boundary conditions. */
+wl_status wl_project(wl_sim* sim, double w, wl_solve_stats* stats);
+
+/* Multigrid solve of A x = rhs on the fine level (software-design section:
+ * the Poisson coefficients c; numerical-methods section: geometric
+ * multigrid).  rhs: device array in the pressure layout, or NULL for the
+ * divergence of the current velocity.  x_inout: device array in the pressure
+ * layout holding the initial guess, overwritten by the solution; NULL uses
+ * the internal WL_FIELD_X.  tol <= 0 or itmax <= 0 take the sim defaults. */
+wl_status wl_poisson_solve(wl_sim* sim, const void* rhs, void* x_inout, double tol, int itmax,
+                           wl_solve_stats* stats);
+
+/* Pressure and viscous force on the body at the current time (FP64 sums):
+ * F_p = -sum p n K_eps(d), F_v = sum 2 nu S n K_eps(d) over cell centres. */
+wl_status wl_forces(wl_sim* sim, double f_pressure[3], double f_viscous[3]);
+
+enum {
+  WL_FIELD_U = 0,     /* velocity, ndim components */
+  WL_FIELD_U0 = 1,    /* start-of-step velocity (after a step: the previous velocity) */
+  WL_FIELD_F = 2,     /* scratch f~ / R, ndim components */
+  WL_FIELD_V = 3,     /* body velocity, ndim components */
+  WL_FIELD_MU0 = 4,   /* mu0 = fine-level L, ndim components */
+  WL_FIELD_MU1 = 5,   /* mu1_ij at component i*ndim + j */
+  WL_FIELD_P = 6,     /* pressure */
+  WL_FIELD_X = 7,     /* multigrid solution on level `level` */
+  WL_FIELD_R = 8,     /* multigrid residual on level `level` */
+  WL_FIELD_L = 9,     /* Poisson coefficients on level `level`, ndim components */
+  WL_FIELD_ID = 10    /* inverse diagonal on level `level` (0 on solid cells) */
+};
+
+/* Zero-copy view of a field inside the workspace.  shape = {components, pz,
+ * py, px_used} with px_used = n[0]+2 of that level; strides in elements
+ * {component, z, y, x}.  level selects the multigrid level for X, R, L, ID. */
+wl_status wl_field(wl_sim* sim, int which, int level, void** dev_ptr, int64_t shape[4],
+                   int64_t strides[4]);
+
+/* Number of multigrid levels and the interior size of one of them. */
+wl_status wl_levels(wl_sim* sim, int* nlevels, int level, int64_t n_out[3]);
+
+/* Set the clock and the next time step. */
+wl_status wl_set_time(wl_sim* sim, double t, double dt_next);
+wl_status wl_get_time(wl_sim* sim, double* t, double* dt_next);
+
+/* Thread-local message describing the last non-WL_OK status. */
+const char* wl_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* WLMI_H */

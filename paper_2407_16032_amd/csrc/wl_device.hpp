@@ -1,0 +1,118 @@
+// Device-side helpers shared by the BDIM step kernels (gfx950, wave64).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace wl {
+
+constexpr int kBlock = 256;       // threads per block (4 waves of 64)
+constexpr int kMaxBlocks = 2048;  // grid-stride launches never exceed this (partial-sum slots)
+constexpr int kMaxLevels = 16;
+constexpr int kMaxPcg = 15;
+
+// reduction slots (each kMaxBlocks doubles)
+constexpr int kSlotRho0 = 0;                   // rho_k for k = 0..kMaxPcg
+constexpr int kSlotSig0 = kMaxPcg + 1;         // sigma_k for k = 0..kMaxPcg-1
+constexpr int kSlotRmax = 2 * kMaxPcg + 1;     // residual max-norm
+constexpr int kSlotCfl = kSlotRmax + 1;        // max outflux
+constexpr int kSlotExit = kSlotCfl + 1;        // exit-plane flux
+constexpr int kSlotForce = kSlotExit + 1;      // 6 slots: pressure xyz, viscous xyz
+constexpr int kNumSlots = kSlotForce + 6;
+
+// scalar results (doubles)
+constexpr int kScalRmax = 0;
+constexpr int kScalCfl = 1;
+constexpr int kScalExitShift = 2;
+constexpr int kNumScal = 8;
+
+// One grid level.  n[2] = 1 and s[2] unused in 2-D.
+struct Grid3 {
+  int n[3];    // interior cells
+  int s[3];    // element strides, s[0] = 1
+  int per[3];  // periodic flags
+};
+
+template <typename T>
+struct Vec3 {
+  T* c[3];
+};
+template <typename T>
+struct Vec9 {
+  T* c[9];
+};
+
+// Periodic wrap of a padded coordinate x in [-1, N+2] into 1..N (no-op otherwise).
+__device__ __forceinline__ int wrapc(int x, int a, const Grid3& g) {
+  if (g.per[a]) {
+    const int N = g.n[a];
+    if (x < 1) x += N;
+    else if (x > N) x -= N;
+  }
+  return x;
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+  return v;
+}
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_down(v, o, 64));
+  return v;
+}
+
+// Block-wide reductions; every thread receives the result.  Fixed order:
+// wave tree, then waves 0..3 in order, so results are bitwise reproducible.
+__device__ __forceinline__ double block_sum(double v) {
+  __shared__ double sh[kBlock / 64];
+  v = wave_sum(v);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) sh[w] = v;
+  __syncthreads();
+  double r = sh[0];
+#pragma unroll
+  for (int i = 1; i < kBlock / 64; ++i) r += sh[i];
+  __syncthreads();
+  return r;
+}
+__device__ __forceinline__ double block_max(double v) {
+  __shared__ double shm[kBlock / 64];
+  v = wave_max(v);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) shm[w] = v;
+  __syncthreads();
+  double r = shm[0];
+#pragma unroll
+  for (int i = 1; i < kBlock / 64; ++i) r = fmax(r, shm[i]);
+  __syncthreads();
+  return r;
+}
+
+// Sum / max of the n per-block partials a producer kernel wrote.
+__device__ __forceinline__ double total_of(const double* part, int n) {
+  double v = 0.0;
+  for (int i = threadIdx.x; i < n; i += kBlock) v += part[i];
+  return block_sum(v);
+}
+__device__ __forceinline__ double max_of(const double* part, int n) {
+  double v = 0.0;
+  for (int i = threadIdx.x; i < n; i += kBlock) v = fmax(v, part[i]);
+  return block_max(v);
+}
+
+template <typename T>
+__device__ __forceinline__ T median3(T a, T b, T c) {
+  return fmax(fmin(a, b), fmin(fmax(a, b), c));
+}
+
+// kappa = 1/3 upwind-biased face value, clamped by the median-form limiter.
+template <typename T>
+__device__ __forceinline__ T quick_lim(T far, T c, T d) {
+  const T q = (T(5) * c + T(2) * d - far) / T(6);
+  return median3(c, q, median3(c, d, c + T(9) * (c - far)));
+}
+
+}  // namespace wl

@@ -1,0 +1,697 @@
+// HIP kernels of the BDIM projection step (gfx950).  Each kernel cites the
+// part of the method it computes; the discrete formulas are documented in
+// include/wlmi.h and the design notes.  All kernels are grid-stride loops
+// with kBlock threads and at most kMaxBlocks blocks, so that per-block
+// partial sums fit the reduction slots.
+#pragma once
+#include "wl_device.hpp"
+
+namespace wl {
+
+// ---------------------------------------------------------------------------
+// body description and rigid motion (the paper's AutoBody, analytic subset)
+// ---------------------------------------------------------------------------
+struct BodyP {
+  int kind;  // 0 none, 1 sphere/circle, 2 box
+  double R;
+  double h[3];
+  double po[3];  // pivot offset
+};
+struct Motion {  // evaluated on the host at time t
+  double P[3];   // pivot position
+  double ct, st; // cos/sin of the rotation angle
+  double cdot[3];
+  double omega;
+};
+
+// signed distance, unit normal and rigid velocity at point x (FP64).
+template <int D>
+__device__ inline void body_eval(const BodyP& b, const Motion& m, const double x[3], double& d,
+                                 double n[3], double V[3]) {
+#pragma clang fp contract(off)
+  const double rx = x[0] - m.P[0], ry = x[1] - m.P[1], rz = (D == 3) ? x[2] - m.P[2] : 0.0;
+  double xb[3];
+  xb[0] = m.ct * rx + m.st * ry + b.po[0];
+  xb[1] = -m.st * rx + m.ct * ry + b.po[1];
+  xb[2] = (D == 3) ? rz + b.po[2] : 0.0;
+  double nb[3] = {0.0, 0.0, 0.0};
+  if (b.kind == 1) {
+    double r2 = xb[0] * xb[0] + xb[1] * xb[1];
+    if (D == 3) r2 = r2 + xb[2] * xb[2];
+    const double r = sqrt(r2);
+    d = r - b.R;
+    if (r > 0.0) {
+      for (int k = 0; k < D; ++k) nb[k] = xb[k] / r;
+    } else {
+      nb[0] = 1.0;
+    }
+  } else {
+    double q[3], o[3];
+    for (int k = 0; k < D; ++k) {
+      q[k] = fabs(xb[k]) - b.h[k];
+      o[k] = fmax(q[k], 0.0);
+    }
+    double ol2 = o[0] * o[0] + o[1] * o[1];
+    if (D == 3) ol2 = ol2 + o[2] * o[2];
+    const double olen = sqrt(ol2);
+    double qmax = q[0];
+    int arg = 0;
+    for (int k = 1; k < D; ++k) {
+      qmax = fmax(qmax, q[k]);
+      if (q[k] > q[arg]) arg = k;
+    }
+    d = olen + fmin(qmax, 0.0);
+    for (int k = 0; k < D; ++k) {
+      const double sg = xb[k] >= 0.0 ? 1.0 : -1.0;
+      nb[k] = (olen > 0.0) ? sg * o[k] / olen : (k == arg ? sg : 0.0);
+    }
+  }
+  n[0] = m.ct * nb[0] - m.st * nb[1];
+  n[1] = m.st * nb[0] + m.ct * nb[1];
+  n[2] = nb[2];
+  V[0] = m.cdot[0] - m.omega * ry;
+  V[1] = m.cdot[1] + m.omega * rx;
+  V[2] = m.cdot[2];
+}
+
+__device__ inline double kern_mu0(double d, double eps) {
+#pragma clang fp contract(off)
+  double s = fmin(fmax(d / eps, -1.0), 1.0);
+  return 0.5 * (1.0 + s) + sin(M_PI * s) / (2.0 * M_PI);
+}
+__device__ inline double kern_mu1(double d, double eps) {
+#pragma clang fp contract(off)
+  double s = fmin(fmax(d / eps, -1.0), 1.0);
+  return eps * (0.25 * (1.0 - s * s) - (s * sin(M_PI * s) + (1.0 + cos(M_PI * s)) / M_PI) / (2.0 * M_PI));
+}
+__device__ inline double kern_K(double d, double eps) {
+#pragma clang fp contract(off)
+  const double s = d / eps;
+  return fabs(s) < 1.0 ? 0.5 * (1.0 + cos(M_PI * s)) / eps : 0.0;
+}
+
+constexpr double kMu0Cut = 1e-6;  // faces with mu0 below this are solid
+
+// measure!: mu0 (= fine Poisson L, 0 on non-periodic boundary faces), mu1 = mu1(d) n, V.
+// blockIdx.y = component.
+template <typename T, int D>
+__global__ void __launch_bounds__(kBlock) k_measure(Grid3 g, BodyP b, Motion m, double eps,
+                                                    Vec3<T> mu0, Vec9<T> mu1, Vec3<T> V) {
+  const int c = blockIdx.y;
+  const int P0 = g.n[0] + 2, P1 = g.n[1] + 2, P2 = (D == 3) ? g.n[2] + 2 : 1;
+  const int total = P0 * P1 * P2;
+  for (int lin = blockIdx.x * kBlock + threadIdx.x; lin < total; lin += gridDim.x * kBlock) {
+    const int I0 = lin % P0, t = lin / P0, I1 = t % P1, I2 = t / P1;
+    const int I[3] = {I0, I1, I2};
+    const int idx = I0 + I1 * g.s[1] + I2 * g.s[2];
+    double m0 = 1.0, m1 = 0.0, vb[3] = {0.0, 0.0, 0.0}, nn[3] = {0.0, 0.0, 0.0}, d = 1e300;
+    if (b.kind != 0) {
+      double x[3];
+      for (int a = 0; a < 3; ++a) x[a] = (a == c) ? I[a] - 1.0 : I[a] - 0.5;
+      body_eval<D>(b, m, x, d, nn, vb);
+      m0 = kern_mu0(d, eps);
+      m1 = kern_mu1(d, eps);
+      if (m0 < kMu0Cut) {
+        m0 = 0.0;
+        m1 = 0.0;
+      }
+    }
+    const bool bnd = !g.per[c] && (I[c] <= 1 || I[c] == g.n[c] + 1);
+    mu0.c[c][idx] = bnd ? T(0) : T(m0);
+    if (b.kind != 0) {
+      for (int j = 0; j < D; ++j) mu1.c[c * D + j][idx] = T(m1 * nn[j]);
+      V.c[c][idx] = (d < 2.0 + eps) ? T(vb[c]) : T(0);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// multigrid coefficients: inverse diagonal and coefficient restriction
+// ---------------------------------------------------------------------------
+template <typename T, int D>
+__global__ void __launch_bounds__(kBlock) k_inv_diag(Grid3 g, Vec3<T> L, T* iD) {
+  const int total = g.n[0] * g.n[1] * ((D == 3) ? g.n[2] : 1);
+  for (int lin = blockIdx.x * kBlock + threadIdx.x; lin < total; lin += gridDim.x * kBlock) {
+    const int I0 = lin % g.n[0] + 1, t = lin / g.n[0], I1 = t % g.n[1] + 1, I2 = (D == 3) ? t / g.n[1] + 1 : 0;
+    const int I[3] = {I0, I1, I2};
+    const int idx = I0 + I1 * g.s[1] + I2 * g.s[2];
+    T Dg = T(0);
+    for (int a = 0; a < D; ++a) {
+      const int off = (g.per[a] && I[a] == g.n[a]) ? -(g.n[a] - 1) * g.s[a] : g.s[a];
+      Dg = Dg - (L.c[a][idx] + L.c[a][idx + off]);
+    }
+    iD[idx] = (Dg != T(0)) ? T(1) / Dg : T(0);
+  }
+}
+
+// L_c,a[J] = 1/2 * sum of the fine a-faces covering the coarse a-face.  blockIdx.y = a.
+template <typename T, int D>
+__global__ void __launch_bounds__(kBlock) k_restrict_L(Grid3 f, Grid3 c, Vec3<T> Lf, Vec3<T> Lc) {
+  const int a = blockIdx.y;
+  // coarse faces: J_a in 1..Nc_a+1, other axes 1..Nc
+  int m[3];
+  for (int k = 0; k < 3; ++k) m[k] = (k < D) ? (c.n[k] + (k == a ? 1 : 0)) : 1;
+  const int total = m[0] * m[1] * m[2];
+  for (int lin = blockIdx.x * kBlock + threadIdx.x; lin < total; lin += gridDim.x * kBlock) {
+    const int J0 = lin % m[0] + 1, t = lin / m[0], J1 = t % m[1] + 1, J2 = (D == 3) ? t / m[1] + 1 : 0;
+    const int J[3] = {J0, J1, J2};
+    int base = 0;
+    for (int k = 0; k < D; ++k) base += (2 * J[k] - 1) * f.s[k];
+    // pair sums along the remaining axes, in axis order
+    const int b0 = (a == 0) ? 1 : 0, b1 = (a == 2) ? 1 : 2;  // the other axes (D==3)
+    T v;
+    if (D == 2) {
+      const int o = (a == 0) ? f.s[1] : f.s[0];
+      v = Lf.c[a][base] + Lf.c[a][base + o];
+    } else {
+      const int ob0 = f.s[b0], ob1 = f.s[b1];
+      v = (Lf.c[a][base] + Lf.c[a][base + ob0]) + (Lf.c[a][base + ob1] + Lf.c[a][base + ob0 + ob1]);
+    }
+    const int cidx = J0 + J1 * c.s[1] + J2 * c.s[2];
+    Lc.c[a][cidx] = T(0.5) * v;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// convection-diffusion flux and f~ = u0 + dt R(u) - V
+// ---------------------------------------------------------------------------
+template <typename T, int D>
+__device__ __forceinline__ int lin3(const Grid3& g, int a, int b, int c) {
+  return a + b * g.s[1] + ((D == 3) ? c * g.s[2] : 0);
+}
+
+// Flux Phi_cj at the (wrapped) index J.
+template <typename T, int D>
+__device__ __forceinline__ T phi_cj(const Grid3& g, const Vec3<T>& u, int c, int j, const int J[3], T nu) {
+  int Jc[3] = {J[0], J[1], J[2]};
+  Jc[c] = wrapc(J[c] - 1, c, g);
+  int Jj[3] = {J[0], J[1], J[2]};
+  Jj[j] = wrapc(J[j] - 1, j, g);
+  const int iJ = lin3<T, D>(g, J[0], J[1], J[2]);
+  const T a = T(0.5) * (u.c[j][iJ] + u.c[j][lin3<T, D>(g, Jc[0], Jc[1], Jc[2])]);
+  const T uc = u.c[c][iJ];
+  const T m1 = u.c[c][lin3<T, D>(g, Jj[0], Jj[1], Jj[2])];
+  const bool up = a >= T(0);
+  int F[3] = {J[0], J[1], J[2]};
+  const int fx = up ? J[j] - 2 : J[j] + 1;
+  bool ok;
+  if (g.per[j]) {
+    F[j] = wrapc(fx, j, g);
+    ok = true;
+  } else {
+    F[j] = fx;
+    ok = fx >= 1 && fx <= (j == c ? g.n[j] + 1 : g.n[j]);
+  }
+  T Q;
+  if (ok) {
+    const T far = u.c[c][lin3<T, D>(g, F[0], F[1], F[2])];
+    Q = up ? quick_lim(far, m1, uc) : quick_lim(far, uc, m1);
+  } else {
+    Q = T(0.5) * (uc + m1);
+  }
+  return a * Q - nu * (uc - m1);
+}
+
+template <typename T, int D>
+__device__ __forceinline__ T resid_c(const Grid3& g, const Vec3<T>& u, int c, const int I[3], T nu) {
+  T acc = T(0);
+  for (int j = 0; j < D; ++j) {
+    int Jp[3] = {I[0], I[1], I[2]};
+    Jp[j] = wrapc(I[j] + 1, j, g);
+    acc = acc + (phi_cj<T, D>(g, u, c, j, I, nu) - phi_cj<T, D>(g, u, c, j, Jp, nu));
+  }
+  return acc;
+}
+
+// f~_c = u0_c + dt R_c(u) - V_c on every padded face (R = 0 off the unknown faces).
+// mode 0: f~ (with body velocity if has_body); mode 1: f = R only.  blockIdx.y = c.
+template <typename T, int D>
+__global__ void __launch_bounds__(kBlock) k_flux(Grid3 g, Vec3<T> u, Vec3<T> u0, Vec3<T> V,
+                                                 Vec3<T> f, T dt, T nu, int has_body, int mode) {
+  const int c = blockIdx.y;
+  const int P0 = g.n[0] + 2, P1 = g.n[1] + 2, P2 = (D == 3) ? g.n[2] + 2 : 1;
+  const int total = P0 * P1 * P2;
+  for (int lin = blockIdx.x * kBlock + threadIdx.x; lin < total; lin += gridDim.x * kBlock) {
+    const int I0 = lin % P0, t = lin / P0, I1 = t % P1, I2 = t / P1;
+    const int I[3] = {I0, I1, I2};
+    const int idx = lin3<T, D>(g, I0, I1, I2);
+    bool unknown = true;
+    for (int a = 0; a < D; ++a) {
+      const int lo = (a == c && !g.per[a]) ? 2 : 1;
+      unknown = unknown && I[a] >= lo && I[a] <= g.n[a];
+    }
+    T R = unknown ? resid_c<T, D>(g, u, c, I, nu) : T(0);
+    if (mode == 1) {
+      f.c[c][idx] = R;
+    } else {
+      T v = u0.c[c][idx] + dt * R;
+      if (has_body) v = v - V.c[c][idx];
+      f.c[c][idx] = v;
+    }
+  }
+}
+
+// BDIM blend: out = V + mu0 f + sum_j mu1_cj (f[I+e_j]-f[I-e_j])/2.
+// CORR = 0: u = out (predictor); CORR = 1: u = (u + out)/2 (corrector).
+template <typename T, int D, int CORR>
+__global__ void __launch_bounds__(kBlock) k_bdim(Grid3 g, Vec3<T> f, Vec3<T> V, Vec3<T> mu0,
+                                                 Vec9<T> mu1, Vec3<T> u, int has_body) {
+  const int c = blockIdx.y;
+  const int P0 = g.n[0] + 2, P1 = g.n[1] + 2, P2 = (D == 3) ? g.n[2] + 2 : 1;
+  const int total = P0 * P1 * P2;
+  for (int lin = blockIdx.x * kBlock + threadIdx.x; lin < total; lin += gridDim.x * kBlock) {
+    const int I0 = lin % P0, t = lin / P0, I1 = t % P1, I2 = t / P1;
+    const int I[3] = {I0, I1, I2};
+    const int idx = lin3<T, D>(g, I0, I1, I2);
+    T acc;
+    if (has_body) {
+      acc = V.c[c][idx] + mu0.c[c][idx] * f.c[c][idx];
+      for (int j = 0; j < D; ++j) {
+        int Jp[3] = {I0, I1, I2}, Jm[3] = {I0, I1, I2};
+        const int xp = I[j] + 1, xm = I[j] - 1;
+        bool ok = true;
+        if (g.per[j]) {
+          Jp[j] = wrapc(xp, j, g);
+          Jm[j] = wrapc(xm, j, g);
+        } else {
+          ok = xp <= g.n[j] + 1 && xm >= 0;
+          Jp[j] = xp;
+          Jm[j] = xm;
+        }
+        T grad = T(0);
+        if (ok)
+          grad = T(0.5) * (f.c[c][lin3<T, D>(g, Jp[0], Jp[1], Jp[2])] -
+                           f.c[c][lin3<T, D>(g, Jm[0], Jm[1], Jm[2])]);
+        acc = acc + mu1.c[c * D + j][idx] * grad;
+      }
+    } else {
+      acc = f.c[c][idx];  // mu0 = 1, mu1 = 0, V = 0 (boundary faces are reset by the BCs)
+    }
+    if (CORR) u.c[c][idx] = T(0.5) * (u.c[c][idx] + acc);
+    else u.c[c][idx] = acc;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// boundary conditions (closed form of the axis-by-axis rule) and convective exit
+// ---------------------------------------------------------------------------
+struct Plane {
+  int comp, axis, idx;
+};
+struct Planes {
+  Plane p[27];
+  int count;
+};
+
+template <typename T, int D>
+__global__ void __launch_bounds__(kBlock) k_bc(Grid3 g, Vec3<T> u, Planes pl, double U0, double U1,
+                                               double U2, const T* ebuf, const double* scal,
+                                               int use_exit) {
+  const Plane P = pl.p[blockIdx.y];
+  const int c = P.comp, ax = P.axis;
+  // the two other axes of the plane
+  const int o0 = (ax == 0) ? 1 : 0, o1 = (ax == 2) ? 1 : 2;
+  const int m0 = g.n[o0] + 2, m1 = (D == 3) ? g.n[o1] + 2 : 1;
+  const int total = m0 * m1;
+  const double Uc = (c == 0) ? U0 : (c == 1 ? U1 : U2);
+  for (int lin = blockIdx.x * kBlock + threadIdx.x; lin < total; lin += gridDim.x * kBlock) {
+    int I[3] = {0, 0, 0};
+    I[ax] = P.idx;
+    I[o0] = lin % m0;
+    if (D == 3) I[o1] = lin / m0;
+    const int idx = lin3<T, D>(g, I[0], I[1], I[2]);
+    // source index: ghosts map to the nearest interior (or across the period)
+    int S[3] = {I[0], I[1], I[2]};
+    for (int a = 0; a < D; ++a) {
+      const int N = g.n[a];
+      if (I[a] == 0) S[a] = g.per[a] ? N : 1;
+      else if (I[a] == N + 1) S[a] = g.per[a] ? 1 : N;
+    }
+    T val;
+    const int Nc = g.n[c];
+    if (!g.per[c] && (I[c] <= 1 || I[c] == Nc + 1)) {
+      if (use_exit && c == 0 && I[0] == Nc + 1) {
+        const int e = S[1] + ((D == 3) ? S[2] * (g.n[1] + 2) : 0);
+        val = T(double(ebuf[e]) + scal[kScalExitShift]);
+      } else {
+        val = T(Uc);
+      }
+    } else {
+      val = u.c[c][lin3<T, D>(g, S[0], S[1], S[2])];
+    }
+    u.c[c][idx] = val;
+  }
+}
+
+// exit value e = u0_x[N+1] - dt U (u0_x[N+1] - u0_x[N]) on the interior of the +x plane.
+template <typename T, int D>
+__global__ void __launch_bounds__(kBlock) k_exit_raw(Grid3 g, const T* u0x, T* ebuf, T dtU, double* part) {
+  const int m0 = g.n[1], m1 = (D == 3) ? g.n[2] : 1;
+  const int total = m0 * m1;
+  const int N = g.n[0];
+  double s = 0.0;
+  for (int lin = blockIdx.x * kBlock + threadIdx.x; lin < total; lin += gridDim.x * kBlock) {
+    const int j = lin % m0 + 1, k = (D == 3) ? lin / m0 + 1 : 0;
+    const int base = j * g.s[1] + ((D == 3) ? k * g.s[2] : 0);
+    const T ue = u0x[base + N + 1], ub = u0x[base + N];
+    const T e = ue - dtU * (ue - ub);
+    ebuf[j + ((D == 3) ? k * (g.n[1] + 2) : 0)] = e;
+    s += double(e);
+  }
+  s = block_sum(s);
+  if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+// shift = (inlet flux - exit flux)/count  (single block)
+__global__ void __launch_bounds__(kBlock) k_exit_shift(const double* part, int nparts, double inlet,
+                                                       double count, double* scal) {
+  const double s = total_of(part, nparts);
+  if (threadIdx.x == 0) scal[kScalExitShift] = (inlet - s) / count;
+}
+
+// ---------------------------------------------------------------------------
+// projection: divergence + initial residual, multigrid passes, velocity update
+// ---------------------------------------------------------------------------
+template <int D>
+struct Cell {
+  int I[3];
+  int idx;
+};
+
+template <int D>
+__device__ __forceinline__ void cell_of(const Grid3& g, int lin, int I[3], int& idx) {
+  I[0] = lin % g.n[0] + 1;
+  const int t = lin / g.n[0];
+  I[1] = t % g.n[1] + 1;
+  I[2] = (D == 3) ? t / g.n[1] + 1 : 0;
+  idx = I[0] + I[1] * g.s[1] + I[2] * g.s[2];
+}
+
+// +/- neighbour offsets of an interior cell (periodic wrap, else ghost)
+template <int D>
+__device__ __forceinline__ void nbr_offsets(const Grid3& g, const int I[3], int op[3], int om[3]) {
+#pragma unroll
+  for (int a = 0; a < D; ++a) {
+    op[a] = (g.per[a] && I[a] == g.n[a]) ? -(g.n[a] - 1) * g.s[a] : g.s[a];
+    om[a] = (g.per[a] && I[a] == 1) ? (g.n[a] - 1) * g.s[a] : -g.s[a];
+  }
+}
+
+// r = z - A x0 on active cells (0 on solid cells), z = rhs or div u, x0 = p wdt (if p) else x.
+// Writes x (if p), r; partials: max|r|, sum r iD r; resets the level's PCG flag.
+template <typename T, int D>
+__global__ void __launch_bounds__(kBlock) k_div_res(Grid3 g, Vec3<T> u, const T* rhs, const T* p,
+                                                    T wdt, Vec3<T> L, const T* iD, T* x, T* r,
+                                                    double* part_max, double* part_rho, int* flag) {
+  const int total = g.n[0] * g.n[1] * ((D == 3) ? g.n[2] : 1);
+  double mx = 0.0, rho = 0.0;
+  if (blockIdx.x == 0 && threadIdx.x == 0) *flag = 0;
+  for (int lin = blockIdx.x * kBlock + threadIdx.x; lin < total; lin += gridDim.x * kBlock) {
+    int I[3], idx, op[3], om[3];
+    cell_of<D>(g, lin, I, idx);
+    nbr_offsets<D>(g, I, op, om);
+    T z;
+    if (rhs) {
+      z = rhs[idx];
+    } else {
+      z = T(0);
+      for (int a = 0; a < D; ++a) z = z + (u.c[a][idx + op[a]] - u.c[a][idx]);
+    }
+    const T di = iD[idx];
+    T rr = T(0);
+    const T xc = p ? p[idx] * wdt : x[idx];
+    if (di != T(0)) {
+      T Ax = T(0);
+      for (int a = 0; a < D; ++a) {
+        const T xp = p ? p[idx + op[a]] * wdt : x[idx + op[a]];
+        const T xm = p ? p[idx + om[a]] * wdt : x[idx + om[a]];
+        Ax = Ax + L.c[a][idx + op[a]] * (xp - xc) - L.c[a][idx] * (xc - xm);
+      }
+      rr = z - Ax;
+    }
+    if (p) x[idx] = xc;
+    r[idx] = rr;
+    mx = fmax(mx, fabs(double(rr)));
+    rho += double(rr) * (double(di) * double(rr));
+  }
+  mx = block_max(mx);
+  rho = block_sum(rho);
+  if (threadIdx.x == 0) {
+    part_max[blockIdx.x] = mx;
+    part_rho[blockIdx.x] = rho;
+  }
+}
+
+// rho partial of the current residual (used when the grid has a single level)
+template <typename T, int D>
+__global__ void __launch_bounds__(kBlock) k_rho0(Grid3 g, const T* iD, const T* r, double* part_rho, int* flag) {
+  const int total = g.n[0] * g.n[1] * ((D == 3) ? g.n[2] : 1);
+  double rho = 0.0;
+  if (blockIdx.x == 0 && threadIdx.x == 0) *flag = 0;
+  for (int lin = blockIdx.x * kBlock + threadIdx.x; lin < total; lin += gridDim.x * kBlock) {
+    int I[3], idx;
+    cell_of<D>(g, lin, I, idx);
+    const T rr = r[idx];
+    rho += double(rr) * (double(iD[idx]) * double(rr));
+  }
+  rho = block_sum(rho);
+  if (threadIdx.x == 0) part_rho[blockIdx.x] = rho;
+}
+
+// restriction: r_c = sum of the 2^D children (0 on solid coarse cells), x_c = 0; rho partial.
+template <typename T, int D>
+__global__ void __launch_bounds__(kBlock) k_restrict(Grid3 f, Grid3 c, const T* rf, const T* iDc, T* rc,
+                                                     T* xc, double* part_rho, int* flag) {
+  const int total = c.n[0] * c.n[1] * ((D == 3) ? c.n[2] : 1);
+  double rho = 0.0;
+  if (blockIdx.x == 0 && threadIdx.x == 0) *flag = 0;
+  for (int lin = blockIdx.x * kBlock + threadIdx.x; lin < total; lin += gridDim.x * kBlock) {
+    int J[3], cidx;
+    cell_of<D>(c, lin, J, cidx);
+    int base = (2 * J[0] - 1) + (2 * J[1] - 1) * f.s[1] + ((D == 3) ? (2 * J[2] - 1) * f.s[2] : 0);
+    T s = rf[base] + rf[base + 1] + rf[base + f.s[1]] + rf[base + 1 + f.s[1]];
+    if (D == 3) {
+      const int b2 = base + f.s[2];
+      s = s + (rf[b2] + rf[b2 + 1] + rf[b2 + f.s[1]] + rf[b2 + 1 + f.s[1]]);
+    }
+    const T di = iDc[cidx];
+    const T rr = (di != T(0)) ? s : T(0);
+    rc[cidx] = rr;
+    xc[cidx] = T(0);
+    rho += double(rr) * (double(di) * double(rr));
+  }
+  rho = block_sum(rho);
+  if (threadIdx.x == 0) part_rho[blockIdx.x] = rho;
+}
+
+// prolongation + correction: e = x_c[parent]; x_f += e; r_f -= A_f e; rho partial.
+template <typename T, int D>
+__device__ __forceinline__ int parent_idx(const Grid3& c, int I0, int I1, int I2) {
+  // fine padded coordinate -> coarse padded coordinate (ghosts map to ghosts)
+  return ((I0 + 1) >> 1) + ((I1 + 1) >> 1) * c.s[1] + ((D == 3) ? ((I2 + 1) >> 1) * c.s[2] : 0);
+}
+
+template <typename T, int D>
+__global__ void __launch_bounds__(kBlock) k_prolong(Grid3 f, Grid3 c, const T* xc, Vec3<T> L, const T* iD,
+                                                    T* xf, T* rf, double* part_rho, int* flag) {
+  const int total = f.n[0] * f.n[1] * ((D == 3) ? f.n[2] : 1);
+  double rho = 0.0;
+  if (blockIdx.x == 0 && threadIdx.x == 0) *flag = 0;
+  for (int lin = blockIdx.x * kBlock + threadIdx.x; lin < total; lin += gridDim.x * kBlock) {
+    int I[3], idx;
+    cell_of<D>(f, lin, I, idx);
+    const T ec = xc[parent_idx<T, D>(c, I[0], I[1], I[2])];
+    xf[idx] = xf[idx] + ec;
+    const T di = iD[idx];
+    T rr = rf[idx];
+    if (di != T(0)) {
+      T Ae = T(0);
+      for (int a = 0; a < D; ++a) {
+        int Jp[3] = {I[0], I[1], I[2]}, Jm[3] = {I[0], I[1], I[2]};
+        Jp[a] = wrapc(I[a] + 1, a, f);
+        Jm[a] = wrapc(I[a] - 1, a, f);
+        const T ep = xc[parent_idx<T, D>(c, Jp[0], Jp[1], Jp[2])];
+        const T em = xc[parent_idx<T, D>(c, Jm[0], Jm[1], Jm[2])];
+        const int op = (f.per[a] && I[a] == f.n[a]) ? -(f.n[a] - 1) * f.s[a] : f.s[a];
+        Ae = Ae + L.c[a][idx + op] * (ep - ec) - L.c[a][idx] * (ec - em);
+      }
+      rr = rr - Ae;
+      rf[idx] = rr;
+    }
+    rho += double(rr) * (double(di) * double(rr));
+  }
+  rho = block_sum(rho);
+  if (threadIdx.x == 0) part_rho[blockIdx.x] = rho;
+}
+
+// PCG pass A (iteration k): e_new = iD r + beta e_old (beta = rho_k/rho_{k-1}, 0 at k = 0),
+// q = A e_new (0 on solid cells); sigma partial = sum e_new q.  Stops if rho_k == 0.
+template <typename T, int D>
+__global__ void __launch_bounds__(kBlock) k_pcg_a(Grid3 g, Vec3<T> L, const T* iD, const T* r, const T* eo,
+                                                  T* en, T* q, const double* red, int k, int nparts,
+                                                  double* part_sig, int* flag) {
+  if (*flag) return;
+  const double rho = total_of(red + (size_t)(kSlotRho0 + k) * kMaxBlocks, nparts);
+  if (rho == 0.0) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) *flag = 1;
+    return;
+  }
+  T beta = T(0);
+  if (k > 0) beta = T(rho / total_of(red + (size_t)(kSlotRho0 + k - 1) * kMaxBlocks, nparts));
+  const int total = g.n[0] * g.n[1] * ((D == 3) ? g.n[2] : 1);
+  double sig = 0.0;
+  for (int lin = blockIdx.x * kBlock + threadIdx.x; lin < total; lin += gridDim.x * kBlock) {
+    int I[3], idx, op[3], om[3];
+    cell_of<D>(g, lin, I, idx);
+    nbr_offsets<D>(g, I, op, om);
+    const T ec = (k > 0) ? iD[idx] * r[idx] + beta * eo[idx] : iD[idx] * r[idx];
+    en[idx] = ec;
+    T qq = T(0);
+    if (iD[idx] != T(0)) {
+      for (int a = 0; a < D; ++a) {
+        const int ip = idx + op[a], im = idx + om[a];
+        const T ep = (k > 0) ? iD[ip] * r[ip] + beta * eo[ip] : iD[ip] * r[ip];
+        const T em = (k > 0) ? iD[im] * r[im] + beta * eo[im] : iD[im] * r[im];
+        qq = qq + L.c[a][ip] * (ep - ec) - L.c[a][idx] * (ec - em);
+      }
+    }
+    q[idx] = qq;
+    sig += double(ec) * double(qq);
+  }
+  sig = block_sum(sig);
+  if (threadIdx.x == 0) part_sig[blockIdx.x] = sig;
+}
+
+// PCG pass B (iteration k): alpha = rho_k/sigma_k; x += alpha e; r -= alpha q;
+// partials: rho_{k+1} (if want_rho) and max|r| (if want_max).  Stops if |sigma| < 1e-300.
+template <typename T, int D>
+__global__ void __launch_bounds__(kBlock) k_pcg_b(Grid3 g, const T* iD, const T* e, const T* q, T* x, T* r,
+                                                  const double* red, int k, int nparts, double* part_rho_next,
+                                                  double* part_max, int want_rho, int want_max, int* flag) {
+  const int total = g.n[0] * g.n[1] * ((D == 3) ? g.n[2] : 1);
+  bool skip = (*flag) != 0;
+  T alpha = T(0);
+  if (!skip) {
+    const double sig = total_of(red + (size_t)(kSlotSig0 + k) * kMaxBlocks, nparts);
+    if (fabs(sig) < 1e-300) {
+      skip = true;
+      if (blockIdx.x == 0 && threadIdx.x == 0) *flag = 1;
+    } else {
+      alpha = T(total_of(red + (size_t)(kSlotRho0 + k) * kMaxBlocks, nparts) / sig);
+    }
+  }
+  if (skip && !want_max) return;
+  double rho = 0.0, mx = 0.0;
+  for (int lin = blockIdx.x * kBlock + threadIdx.x; lin < total; lin += gridDim.x * kBlock) {
+    int I[3], idx;
+    cell_of<D>(g, lin, I, idx);
+    T rr = r[idx];
+    if (!skip) {
+      x[idx] = x[idx] + alpha * e[idx];
+      rr = rr - alpha * q[idx];
+      r[idx] = rr;
+    }
+    rho += double(rr) * (double(iD[idx]) * double(rr));
+    mx = fmax(mx, fabs(double(rr)));
+  }
+  if (want_rho && !skip) {
+    rho = block_sum(rho);
+    if (threadIdx.x == 0) part_rho_next[blockIdx.x] = rho;
+  }
+  if (want_max) {
+    mx = block_max(mx);
+    if (threadIdx.x == 0) part_max[blockIdx.x] = mx;
+  }
+}
+
+// single-block max / sum of partials into a scalar slot
+__global__ void __launch_bounds__(kBlock) k_finalize_max(const double* part, int n, double* out) {
+  const double v = max_of(part, n);
+  if (threadIdx.x == 0) *out = v;
+}
+
+// projection update u_a -= L_a (x[I] - x[I-e_a]) on interior cells; p = x / wdt.
+template <typename T, int D>
+__global__ void __launch_bounds__(kBlock) k_project(Grid3 g, Vec3<T> u, Vec3<T> L, const T* x, T* p, T wdt) {
+  const int total = g.n[0] * g.n[1] * ((D == 3) ? g.n[2] : 1);
+  for (int lin = blockIdx.x * kBlock + threadIdx.x; lin < total; lin += gridDim.x * kBlock) {
+    int I[3], idx, op[3], om[3];
+    cell_of<D>(g, lin, I, idx);
+    nbr_offsets<D>(g, I, op, om);
+    const T xc = x[idx];
+    for (int a = 0; a < D; ++a) u.c[a][idx] = u.c[a][idx] - L.c[a][idx] * (xc - x[idx + om[a]]);
+    if (p) p[idx] = xc / wdt;
+  }
+}
+
+// CFL: max over interior cells of sum_a max(0, u_a[I+e_a]) + max(0, -u_a[I]).
+template <typename T, int D>
+__global__ void __launch_bounds__(kBlock) k_cfl(Grid3 g, Vec3<T> u, double* part) {
+  const int total = g.n[0] * g.n[1] * ((D == 3) ? g.n[2] : 1);
+  double mx = 0.0;
+  for (int lin = blockIdx.x * kBlock + threadIdx.x; lin < total; lin += gridDim.x * kBlock) {
+    int I[3], idx, op[3], om[3];
+    cell_of<D>(g, lin, I, idx);
+    nbr_offsets<D>(g, I, op, om);
+    T s = T(0);
+    for (int a = 0; a < D; ++a) s = s + fmax(T(0), u.c[a][idx + op[a]]) + fmax(T(0), -u.c[a][idx]);
+    mx = fmax(mx, double(s));
+  }
+  mx = block_max(mx);
+  if (threadIdx.x == 0) part[blockIdx.x] = mx;
+}
+
+// forces: F_p = -sum p n K_eps(d), F_v = sum 2 nu S n K_eps(d) at cell centres (FP64).
+template <typename T, int D>
+__global__ void __launch_bounds__(kBlock) k_forces(Grid3 g, BodyP b, Motion m, double eps, double nu,
+                                                   Vec3<T> u, const T* p, double* red) {
+#pragma clang fp contract(off)
+  const int total = g.n[0] * g.n[1] * ((D == 3) ? g.n[2] : 1);
+  double fp[3] = {0, 0, 0}, fv[3] = {0, 0, 0};
+  for (int lin = blockIdx.x * kBlock + threadIdx.x; lin < total; lin += gridDim.x * kBlock) {
+    int I[3], idx;
+    cell_of<D>(g, lin, I, idx);
+    double x[3] = {I[0] - 0.5, I[1] - 0.5, I[2] - 0.5}, d, n[3], V[3];
+    body_eval<D>(b, m, x, d, n, V);
+    const double w = kern_K(d, eps);
+    if (w == 0.0) continue;
+    const double pc = double(p[idx]);
+    for (int a = 0; a < D; ++a) fp[a] += pc * n[a] * w;
+    // velocity gradient G[i][j] = d u_i / d x_j at the cell centre
+    double G[3][3];
+    for (int i = 0; i < D; ++i) {
+      const T* ui = u.c[i];
+      const int si = g.s[i];
+      for (int j = 0; j < D; ++j) {
+        if (j == i) {
+          G[i][j] = double(ui[idx + si]) - double(ui[idx]);
+        } else {
+          const int sj = g.s[j];
+          const double bp = 0.5 * (double(ui[idx + sj]) + double(ui[idx + sj + si]));
+          const double bm = 0.5 * (double(ui[idx - sj]) + double(ui[idx - sj + si]));
+          G[i][j] = 0.5 * (bp - bm);
+        }
+      }
+    }
+    for (int i = 0; i < D; ++i) {
+      double acc = 0.0;
+      for (int j = 0; j < D; ++j) acc = acc + 0.5 * (G[i][j] + G[j][i]) * n[j];
+      fv[i] += 2.0 * nu * acc * w;
+    }
+  }
+  for (int a = 0; a < 3; ++a) {
+    const double sp = block_sum(-fp[a]);
+    const double sv = block_sum(fv[a]);
+    if (threadIdx.x == 0) {
+      red[(size_t)(kSlotForce + a) * kMaxBlocks + blockIdx.x] = sp;
+      red[(size_t)(kSlotForce + 3 + a) * kMaxBlocks + blockIdx.x] = sv;
+    }
+  }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_fill(T* a, int64_t n, T v) {
+  for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock) a[i] = v;
+}
+
+}  // namespace wl

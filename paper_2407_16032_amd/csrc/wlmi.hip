@@ -1,0 +1,715 @@
+// Host orchestration and C ABI of the BDIM projection step (see include/wlmi.h).
+//
+// One time step (paper, numerical-methods section) is enqueued as:
+//   [measure]  flux(u0) -> f~  bdim -> u*  [exit]  bc  project(w=1)  bc
+//   flux(u') -> f~  bdim(avg) -> u**  bc  project(w=1/2)  bc  cfl
+// with the projection = div/residual, multigrid V(0,1) cycles with a PCG(k)
+// smoother on every level plus a fine PCG(k), and the velocity update.
+// Velocity ping-pongs between two buffers so u0 never needs a copy.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "wlmi.h"
+#include "wl_kernels.hpp"
+
+using namespace wl;
+
+namespace {
+
+thread_local std::string g_err;
+
+wl_status fail(wl_status s, const std::string& msg) {
+  g_err = msg;
+  return s;
+}
+
+#define WL_HIP(call)                                                              \
+  do {                                                                            \
+    hipError_t e_ = (call);                                                       \
+    if (e_ != hipSuccess)                                                         \
+      return fail(WL_ERR_HIP, std::string(#call) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+inline int blocks_for(int64_t work) {
+  int64_t b = (work + kBlock - 1) / kBlock;
+  if (b < 1) b = 1;
+  if (b > kMaxBlocks) b = kMaxBlocks;
+  return (int)b;
+}
+
+inline size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
+
+// ---------------------------------------------------------------------------
+// workspace plan
+// ---------------------------------------------------------------------------
+struct LevelPlan {
+  int n[3];
+  int px, py, pz;
+  int64_t elems;  // px*py*pz
+};
+
+struct Plan {
+  int ndim = 0, nlev = 0;
+  size_t esize = 4;
+  LevelPlan lev[kMaxLevels];
+  size_t bytes = 0;
+};
+
+wl_status validate_and_default(const wl_sim_desc* in, wl_sim_desc* d) {
+  if (!in) return fail(WL_ERR_INVALID_ARG, "desc is NULL");
+  *d = *in;
+  if (d->ndim != 2 && d->ndim != 3) return fail(WL_ERR_INVALID_ARG, "ndim must be 2 or 3");
+  if (d->ndim == 2) d->n[2] = 1;
+  for (int a = 0; a < d->ndim; ++a)
+    if (d->n[a] < 4 || d->n[a] > (1 << 20)) return fail(WL_ERR_INVALID_ARG, "n[a] must be in [4, 2^20]");
+  if (d->prec != WL_F32 && d->prec != WL_F64) return fail(WL_ERR_INVALID_ARG, "prec must be WL_F32 or WL_F64");
+  if (!(d->nu >= 0.0) || !std::isfinite(d->nu)) return fail(WL_ERR_INVALID_ARG, "nu must be finite and >= 0");
+  for (int a = 0; a < 3; ++a)
+    if (!std::isfinite(d->U[a])) return fail(WL_ERR_INVALID_ARG, "U must be finite");
+  if (d->eps == 0.0) d->eps = 1.0;
+  if (d->dt0 == 0.0) d->dt0 = 0.25;
+  if (d->dt_max == 0.0) d->dt_max = 10.0;
+  if (d->cfl_nu_coef == 0.0) d->cfl_nu_coef = 5.0;
+  if (d->mg_tol == 0.0) d->mg_tol = 1e-6;
+  if (d->mg_itmax == 0) d->mg_itmax = 32;
+  if (d->pcg_iters == 0) d->pcg_iters = 6;
+  if (!(d->eps > 0.0) || !(d->dt0 > 0.0) || !(d->dt_max > 0.0) || !(d->mg_tol > 0.0) || d->mg_itmax < 1)
+    return fail(WL_ERR_INVALID_ARG, "eps, dt0, dt_max, mg_tol must be > 0 and mg_itmax >= 1");
+  if (d->pcg_iters < 1 || d->pcg_iters > kMaxPcg) return fail(WL_ERR_INVALID_ARG, "pcg_iters must be in [1, 15]");
+  if (d->convective_exit) {
+    if (d->periodic_mask & 1u) return fail(WL_ERR_INVALID_ARG, "convective exit needs a non-periodic x axis");
+    if (d->U[0] == 0.0) return fail(WL_ERR_INVALID_ARG, "convective exit needs U[0] != 0");
+  }
+  return WL_OK;
+}
+
+wl_status validate_body(const wl_sim_desc& d, const wl_body_desc* b) {
+  if (!b || b->kind == WL_BODY_NONE) return WL_OK;
+  if (b->kind != WL_BODY_SPHERE && b->kind != WL_BODY_BOX)
+    return fail(WL_ERR_UNSUPPORTED, "body kind not supported (sphere and box are)");
+  const double vals[] = {b->radius, b->heave_amp, b->pitch_amp, b->freq, b->phase_h, b->phase_p, b->spin_omega};
+  for (double v : vals)
+    if (!std::isfinite(v)) return fail(WL_ERR_INVALID_ARG, "body parameters must be finite");
+  if (b->kind == WL_BODY_SPHERE && !(b->radius > 0.0)) return fail(WL_ERR_INVALID_ARG, "sphere radius must be > 0");
+  if (b->kind == WL_BODY_BOX)
+    for (int a = 0; a < d.ndim; ++a)
+      if (!(b->half_extent[a] > 0.0)) return fail(WL_ERR_INVALID_ARG, "box half extents must be > 0");
+  // reach of the body (bounding radius + rigid heave) must stay 3 cells inside non-periodic faces
+  double reach = (b->kind == WL_BODY_SPHERE) ? b->radius : 0.0;
+  if (b->kind == WL_BODY_BOX) {
+    double s = 0;
+    for (int a = 0; a < d.ndim; ++a) s += b->half_extent[a] * b->half_extent[a];
+    reach = std::sqrt(s);
+  }
+  double po = 0;
+  for (int a = 0; a < d.ndim; ++a) po += b->pivot_offset[a] * b->pivot_offset[a];
+  reach += std::sqrt(po) + d.eps + 2.0;
+  for (int a = 0; a < d.ndim; ++a) {
+    if (d.periodic_mask & (1u << a)) continue;
+    const double lo = b->center[a] - reach - (a == 1 ? std::fabs(b->heave_amp) : 0.0);
+    const double hi = b->center[a] + reach + (a == 1 ? std::fabs(b->heave_amp) : 0.0);
+    if (lo < 3.0 || hi > double(d.n[a]) - 3.0)
+      return fail(WL_ERR_INVALID_ARG, "body must stay at least 3 cells from non-periodic boundaries");
+  }
+  return WL_OK;
+}
+
+Plan make_plan(const wl_sim_desc& d, bool has_body) {
+  Plan P;
+  P.ndim = d.ndim;
+  P.esize = d.prec == WL_F64 ? 8 : 4;
+  int n[3] = {(int)d.n[0], (int)d.n[1], d.ndim == 3 ? (int)d.n[2] : 1};
+  for (;;) {
+    LevelPlan& L = P.lev[P.nlev++];
+    for (int a = 0; a < 3; ++a) L.n[a] = n[a];
+    const int w = n[0] + 2;
+    L.px = (w >= 128) ? ((w + 63) / 64) * 64 : ((w + 7) / 8) * 8;
+    L.py = n[1] + 2;
+    L.pz = d.ndim == 3 ? n[2] + 2 : 1;
+    L.elems = (int64_t)L.px * L.py * L.pz;
+    bool even = true;
+    int mn = 1 << 30;
+    for (int a = 0; a < d.ndim; ++a) {
+      even = even && (n[a] % 2 == 0);
+      mn = std::min(mn, n[a] / 2);
+    }
+    if (!even || mn < 4 || P.nlev == kMaxLevels) break;
+    for (int a = 0; a < d.ndim; ++a) n[a] /= 2;
+  }
+  const int D = d.ndim;
+  size_t b = 0;
+  const size_t f0 = align256(P.lev[0].elems * P.esize);
+  int nf0 = D /*ua*/ + D /*ub*/ + D /*ft*/ + D /*V*/ + D /*mu0*/ + D * D /*mu1*/ + 1 /*p*/ + 6 /*x r ea eb q iD*/;
+  (void)has_body;
+  b += nf0 * f0;
+  b += align256((size_t)P.lev[0].py * P.lev[0].pz * P.esize);  // exit plane
+  for (int l = 1; l < P.nlev; ++l) b += (6 + D) * align256(P.lev[l].elems * P.esize);
+  b += align256((size_t)kNumSlots * kMaxBlocks * sizeof(double));
+  b += align256(kNumScal * sizeof(double));
+  b += align256(kMaxLevels * sizeof(int));
+  P.bytes = b;
+  return P;
+}
+
+void host_motion(const wl_body_desc& b, double t, Motion& m) {
+  const double w = 2.0 * M_PI * b.freq;
+  double c[3] = {b.center[0], b.center[1], b.center[2]};
+  c[1] += b.heave_amp * std::sin(w * t + b.phase_h);
+  for (int k = 0; k < 3; ++k) m.P[k] = c[k] + b.pivot_offset[k];
+  const double theta = b.pitch_amp * std::sin(w * t + b.phase_p) + b.spin_omega * t;
+  m.ct = std::cos(theta);
+  m.st = std::sin(theta);
+  m.cdot[0] = 0.0;
+  m.cdot[1] = b.heave_amp * w * std::cos(w * t + b.phase_h);
+  m.cdot[2] = 0.0;
+  m.omega = b.pitch_amp * w * std::cos(w * t + b.phase_p) + b.spin_omega;
+}
+
+// ---------------------------------------------------------------------------
+// the simulation object
+// ---------------------------------------------------------------------------
+struct SimBase {
+  virtual ~SimBase() {}
+  virtual wl_status init() = 0;
+  virtual wl_status measure(double t) = 0;
+  virtual wl_status step(int remeasure, wl_step_stats* st) = 0;
+  virtual wl_status apply_bc_cur() = 0;
+  virtual wl_status conv_diff() = 0;
+  virtual wl_status project_cur(double w, wl_solve_stats* st) = 0;
+  virtual wl_status poisson(const void* rhs, void* x, double tol, int itmax, wl_solve_stats* st) = 0;
+  virtual wl_status forces(double fp[3], double fv[3]) = 0;
+  virtual wl_status field(int which, int level, void** ptr, int64_t shape[4], int64_t strides[4]) = 0;
+  wl_sim_desc desc;
+  wl_body_desc bdesc;
+  Plan plan;
+  hipStream_t stream = nullptr;
+  double t = 0.0, dt = 0.25;
+  double* host_pin = nullptr;
+};
+
+template <typename T, int D>
+struct Impl : SimBase {
+  Grid3 g[kMaxLevels];
+  int nb[kMaxLevels];
+  int nlev = 1;
+  int nb_face = 1;
+  BodyP body{};
+  bool has_body = false, moving = false;
+  T* u[2][3] = {};
+  int cur = 0;
+  T *ft[3] = {}, *V[3] = {}, *mu0[3] = {}, *mu1[9] = {}, *p = nullptr, *ebuf = nullptr;
+  T *x[kMaxLevels] = {}, *r[kMaxLevels] = {}, *e[kMaxLevels][2] = {}, *q[kMaxLevels] = {}, *iD[kMaxLevels] = {};
+  T* L[kMaxLevels][3] = {};
+  double* red = nullptr;
+  double* scal = nullptr;
+  int* flags = nullptr;
+  Planes planes{};
+  int plane_blocks = 1;
+  bool exit_valid = false;
+
+  Vec3<T> v3(T* const a[3]) const {
+    Vec3<T> v;
+    for (int k = 0; k < 3; ++k) v.c[k] = a[k];
+    return v;
+  }
+  Vec9<T> v9(T* const a[9]) const {
+    Vec9<T> v;
+    for (int k = 0; k < 9; ++k) v.c[k] = a[k];
+    return v;
+  }
+  double* slot(int s) const { return red + (size_t)s * kMaxBlocks; }
+
+  void carve(char* base) {
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+      char* p_ = base + off;
+      off += align256(bytes);
+      return p_;
+    };
+    const size_t f0 = plan.lev[0].elems * sizeof(T);
+    for (int k = 0; k < D; ++k) u[0][k] = (T*)take(f0);
+    for (int k = 0; k < D; ++k) u[1][k] = (T*)take(f0);
+    for (int k = 0; k < D; ++k) ft[k] = (T*)take(f0);
+    for (int k = 0; k < D; ++k) V[k] = (T*)take(f0);
+    for (int k = 0; k < D; ++k) mu0[k] = (T*)take(f0);
+    for (int k = 0; k < D * D; ++k) mu1[k] = (T*)take(f0);
+    p = (T*)take(f0);
+    x[0] = (T*)take(f0);
+    r[0] = (T*)take(f0);
+    e[0][0] = (T*)take(f0);
+    e[0][1] = (T*)take(f0);
+    q[0] = (T*)take(f0);
+    iD[0] = (T*)take(f0);
+    for (int k = 0; k < D; ++k) L[0][k] = mu0[k];
+    ebuf = (T*)take((size_t)plan.lev[0].py * plan.lev[0].pz * sizeof(T));
+    for (int l = 1; l < nlev; ++l) {
+      const size_t fl = plan.lev[l].elems * sizeof(T);
+      x[l] = (T*)take(fl);
+      r[l] = (T*)take(fl);
+      e[l][0] = (T*)take(fl);
+      e[l][1] = (T*)take(fl);
+      q[l] = (T*)take(fl);
+      iD[l] = (T*)take(fl);
+      for (int k = 0; k < D; ++k) L[l][k] = (T*)take(fl);
+    }
+    red = (double*)take((size_t)kNumSlots * kMaxBlocks * sizeof(double));
+    scal = (double*)take(kNumScal * sizeof(double));
+    flags = (int*)take(kMaxLevels * sizeof(int));
+  }
+
+  void setup_grids() {
+    nlev = plan.nlev;
+    for (int l = 0; l < nlev; ++l) {
+      const LevelPlan& P = plan.lev[l];
+      for (int a = 0; a < 3; ++a) {
+        g[l].n[a] = P.n[a];
+        g[l].per[a] = (a < D) ? ((desc.periodic_mask >> a) & 1u) : 0;
+      }
+      g[l].s[0] = 1;
+      g[l].s[1] = P.px;
+      g[l].s[2] = P.px * P.py;
+      nb[l] = blocks_for((int64_t)P.n[0] * P.n[1] * (D == 3 ? P.n[2] : 1));
+    }
+    nb_face = blocks_for((int64_t)(g[0].n[0] + 2) * (g[0].n[1] + 2) * (D == 3 ? g[0].n[2] + 2 : 1));
+    planes.count = 0;
+    int maxarea = 1;
+    for (int c = 0; c < D; ++c)
+      for (int a = 0; a < D; ++a) {
+        const int N = g[0].n[a];
+        int ids[3] = {0, N + 1, 1};
+        const int cnt = (a == c && !g[0].per[a]) ? 3 : 2;
+        for (int k = 0; k < cnt; ++k) planes.p[planes.count++] = Plane{c, a, ids[k]};
+        int area = 1;
+        for (int o = 0; o < D; ++o)
+          if (o != a) area *= g[0].n[o] + 2;
+        maxarea = std::max(maxarea, area);
+      }
+    plane_blocks = blocks_for(maxarea);
+  }
+
+  wl_status init() override {
+    has_body = bdesc.kind != WL_BODY_NONE;
+    body.kind = bdesc.kind;
+    body.R = bdesc.radius;
+    for (int k = 0; k < 3; ++k) {
+      body.h[k] = bdesc.half_extent[k];
+      body.po[k] = bdesc.pivot_offset[k];
+    }
+    moving = has_body && (bdesc.heave_amp != 0.0 || bdesc.pitch_amp != 0.0 || bdesc.spin_omega != 0.0);
+    setup_grids();
+    for (int c = 0; c < D; ++c) {
+      k_fill<T><<<blocks_for(plan.lev[0].elems), kBlock, 0, stream>>>(u[cur][c], plan.lev[0].elems, T(desc.U[c]));
+      k_fill<T><<<blocks_for(plan.lev[0].elems), kBlock, 0, stream>>>(u[1 - cur][c], plan.lev[0].elems, T(desc.U[c]));
+    }
+    WL_HIP(hipGetLastError());
+    t = 0.0;
+    dt = desc.dt0;
+    return measure(0.0);
+  }
+
+  wl_status coefficients() {
+    k_inv_diag<T, D><<<nb[0], kBlock, 0, stream>>>(g[0], v3(L[0]), iD[0]);
+    for (int l = 1; l < nlev; ++l) {
+      int m = 1;
+      for (int a = 0; a < D; ++a) m *= g[l].n[a] + 1;
+      k_restrict_L<T, D><<<dim3(blocks_for(m), D), kBlock, 0, stream>>>(g[l - 1], g[l], v3(L[l - 1]), v3(L[l]));
+      k_inv_diag<T, D><<<nb[l], kBlock, 0, stream>>>(g[l], v3(L[l]), iD[l]);
+    }
+    WL_HIP(hipGetLastError());
+    return WL_OK;
+  }
+
+  wl_status measure(double tm) override {
+    Motion m{};
+    if (has_body) host_motion(bdesc, tm, m);
+    k_measure<T, D><<<dim3(nb_face, D), kBlock, 0, stream>>>(g[0], body, m, desc.eps, v3(mu0), v9(mu1), v3(V));
+    WL_HIP(hipGetLastError());
+    return coefficients();
+  }
+
+  wl_status bc(T* const uu[3], bool use_exit) {
+    k_bc<T, D><<<dim3(plane_blocks, planes.count), kBlock, 0, stream>>>(
+        g[0], v3(uu), planes, desc.U[0], desc.U[1], desc.U[2], ebuf, scal, use_exit ? 1 : 0);
+    WL_HIP(hipGetLastError());
+    return WL_OK;
+  }
+
+  wl_status apply_bc_cur() override { return bc(u[cur], false); }
+
+  wl_status read_scalar_max(int s, int n, double* out) {
+    k_finalize_max<<<1, kBlock, 0, stream>>>(slot(s), n, scal + kScalRmax);
+    WL_HIP(hipGetLastError());
+    WL_HIP(hipMemcpyAsync(host_pin, scal + kScalRmax, sizeof(double), hipMemcpyDeviceToHost, stream));
+    WL_HIP(hipStreamSynchronize(stream));
+    *out = host_pin[0];
+    return WL_OK;
+  }
+
+  void pcg(int l, bool fine) {
+    const int K = desc.pcg_iters;
+    T* eo = e[l][0];
+    T* en = e[l][1];
+    for (int k = 0; k < K; ++k) {
+      k_pcg_a<T, D><<<nb[l], kBlock, 0, stream>>>(g[l], v3(L[l]), iD[l], r[l], eo, en, q[l], red, k, nb[l],
+                                                   slot(kSlotSig0 + k), flags + l);
+      k_pcg_b<T, D><<<nb[l], kBlock, 0, stream>>>(g[l], iD[l], en, q[l], x[l], r[l], red, k, nb[l],
+                                                   slot(kSlotRho0 + k + 1), slot(kSlotRmax), k < K - 1 ? 1 : 0,
+                                                   (fine && k == K - 1) ? 1 : 0, flags + l);
+      std::swap(eo, en);
+    }
+  }
+
+  void vcycle(int l) {
+    k_restrict<T, D><<<nb[l + 1], kBlock, 0, stream>>>(g[l], g[l + 1], r[l], iD[l + 1], r[l + 1], x[l + 1],
+                                                       slot(kSlotRho0), flags + l + 1);
+    if (l + 2 < nlev) vcycle(l + 1);
+    pcg(l + 1, false);
+    k_prolong<T, D><<<nb[l], kBlock, 0, stream>>>(g[l], g[l + 1], x[l + 1], v3(L[l]), iD[l], x[l], r[l],
+                                                  slot(kSlotRho0), flags + l);
+  }
+
+  // initial residual already in r[0] / rmax slot
+  wl_status mg_loop(double tol, int itmax, wl_solve_stats* st) {
+    double res0;
+    wl_status s = read_scalar_max(kSlotRmax, nb[0], &res0);
+    if (s != WL_OK) return s;
+    double res = res0;
+    int n = 0;
+    while (res >= tol && n < itmax) {
+      if (nlev > 1) vcycle(0);
+      else k_rho0<T, D><<<nb[0], kBlock, 0, stream>>>(g[0], iD[0], r[0], slot(kSlotRho0), flags);
+      pcg(0, true);
+      ++n;
+      s = read_scalar_max(kSlotRmax, nb[0], &res);
+      if (s != WL_OK) return s;
+      if (!std::isfinite(res)) return fail(WL_ERR_NONFINITE, "multigrid residual is not finite");
+    }
+    if (!std::isfinite(res0)) return fail(WL_ERR_NONFINITE, "initial residual is not finite");
+    if (st) {
+      st->vcycles = n;
+      st->res0_linf = res0;
+      st->res_linf = res;
+      st->converged = res < tol ? 1 : 0;
+    }
+    return WL_OK;
+  }
+
+  wl_status project(T* const uu[3], double w, wl_solve_stats* st) {
+    const T wdt = T(w * dt);
+    k_div_res<T, D><<<nb[0], kBlock, 0, stream>>>(g[0], v3(uu), nullptr, p, wdt, v3(L[0]), iD[0], x[0], r[0],
+                                                  slot(kSlotRmax), slot(kSlotRho0), flags);
+    WL_HIP(hipGetLastError());
+    wl_status s = mg_loop(desc.mg_tol, desc.mg_itmax, st);
+    if (s != WL_OK) return s;
+    k_project<T, D><<<nb[0], kBlock, 0, stream>>>(g[0], v3(uu), v3(L[0]), x[0], p, wdt);
+    WL_HIP(hipGetLastError());
+    return WL_OK;
+  }
+
+  wl_status project_cur(double w, wl_solve_stats* st) override {
+    wl_status s = project(u[cur], w, st);
+    if (s != WL_OK) return s;
+    return bc(u[cur], false);
+  }
+
+  wl_status poisson(const void* rhs, void* xin, double tol, int itmax, wl_solve_stats* st) override {
+    T* xs = x[0];
+    if (xin) x[0] = (T*)xin;
+    k_div_res<T, D><<<nb[0], kBlock, 0, stream>>>(g[0], v3(u[cur]), (const T*)rhs, nullptr, T(0), v3(L[0]),
+                                                  iD[0], x[0], r[0], slot(kSlotRmax), slot(kSlotRho0), flags);
+    wl_status s = WL_OK;
+    hipError_t he = hipGetLastError();
+    if (he != hipSuccess) s = fail(WL_ERR_HIP, hipGetErrorString(he));
+    if (s == WL_OK) s = mg_loop(tol > 0 ? tol : desc.mg_tol, itmax > 0 ? itmax : desc.mg_itmax, st);
+    x[0] = xs;
+    return s;
+  }
+
+  wl_status conv_diff() override {
+    k_flux<T, D><<<dim3(nb_face, D), kBlock, 0, stream>>>(g[0], v3(u[cur]), v3(u[cur]), v3(V), v3(ft), T(0),
+                                                          T(desc.nu), 0, 1);
+    WL_HIP(hipGetLastError());
+    return WL_OK;
+  }
+
+  wl_status step(int remeasure, wl_step_stats* st) override {
+    wl_status s;
+    if (remeasure && moving) {
+      s = measure(t);
+      if (s != WL_OK) return s;
+    }
+    T* const* A = u[cur];
+    T* const* B = u[1 - cur];
+    const int hb = has_body ? 1 : 0;
+    // predictor
+    k_flux<T, D><<<dim3(nb_face, D), kBlock, 0, stream>>>(g[0], v3(A), v3(A), v3(V), v3(ft), T(dt), T(desc.nu), hb, 0);
+    k_bdim<T, D, 0><<<dim3(nb_face, D), kBlock, 0, stream>>>(g[0], v3(ft), v3(V), v3(mu0), v9(mu1), v3(B), hb);
+    const bool ex = desc.convective_exit != 0;
+    if (ex) {
+      const int m = g[0].n[1] * (D == 3 ? g[0].n[2] : 1);
+      const int be = blocks_for(m);
+      k_exit_raw<T, D><<<be, kBlock, 0, stream>>>(g[0], A[0], ebuf, T(dt * desc.U[0]), slot(kSlotExit));
+      const double inlet = double(m) * double(T(desc.U[0]));
+      k_exit_shift<<<1, kBlock, 0, stream>>>(slot(kSlotExit), be, inlet, double(m), scal);
+      exit_valid = true;
+    }
+    WL_HIP(hipGetLastError());
+    if ((s = bc(B, ex)) != WL_OK) return s;
+    wl_solve_stats s1{}, s2{};
+    if ((s = project(B, 1.0, &s1)) != WL_OK) return s;
+    if ((s = bc(B, ex)) != WL_OK) return s;
+    // corrector
+    k_flux<T, D><<<dim3(nb_face, D), kBlock, 0, stream>>>(g[0], v3(B), v3(A), v3(V), v3(ft), T(dt), T(desc.nu), hb, 0);
+    k_bdim<T, D, 1><<<dim3(nb_face, D), kBlock, 0, stream>>>(g[0], v3(ft), v3(V), v3(mu0), v9(mu1), v3(B), hb);
+    WL_HIP(hipGetLastError());
+    if ((s = bc(B, ex)) != WL_OK) return s;
+    if ((s = project(B, 0.5, &s2)) != WL_OK) return s;
+    if ((s = bc(B, ex)) != WL_OK) return s;
+    cur = 1 - cur;
+    const double dt_used = dt;
+    t += dt;
+    // CFL
+    k_cfl<T, D><<<nb[0], kBlock, 0, stream>>>(g[0], v3(u[cur]), slot(kSlotCfl));
+    WL_HIP(hipGetLastError());
+    double smax;
+    if ((s = read_scalar_max(kSlotCfl, nb[0], &smax)) != WL_OK) return s;
+    const double denom = smax + desc.cfl_nu_coef * desc.nu;
+    dt = denom <= 0.0 ? desc.dt_max : std::min(desc.dt_max, 1.0 / denom);
+    if (st) {
+      st->dt = dt_used;
+      st->t = t;
+      st->dt_next = dt;
+      st->vcycles[0] = s1.vcycles;
+      st->vcycles[1] = s2.vcycles;
+      st->res_linf[0] = s1.res_linf;
+      st->res_linf[1] = s2.res_linf;
+      st->converged = s1.converged && s2.converged;
+    }
+    if (!std::isfinite(smax) || !std::isfinite(dt)) return fail(WL_ERR_NONFINITE, "velocity is not finite");
+    return WL_OK;
+  }
+
+  wl_status forces(double fp[3], double fv[3]) override {
+    for (int a = 0; a < 3; ++a) fp[a] = fv[a] = 0.0;
+    if (!has_body) return WL_OK;
+    Motion m{};
+    host_motion(bdesc, t, m);
+    k_forces<T, D><<<nb[0], kBlock, 0, stream>>>(g[0], body, m, desc.eps, desc.nu, v3(u[cur]), p, red);
+    WL_HIP(hipGetLastError());
+    std::vector<double> h((size_t)6 * kMaxBlocks);
+    WL_HIP(hipMemcpyAsync(h.data(), slot(kSlotForce), h.size() * sizeof(double), hipMemcpyDeviceToHost, stream));
+    WL_HIP(hipStreamSynchronize(stream));
+    for (int a = 0; a < 3; ++a) {
+      double sp = 0, sv = 0;
+      for (int b = 0; b < nb[0]; ++b) {
+        sp += h[(size_t)a * kMaxBlocks + b];
+        sv += h[(size_t)(3 + a) * kMaxBlocks + b];
+      }
+      fp[a] = sp;
+      fv[a] = sv;
+    }
+    return WL_OK;
+  }
+
+  wl_status field(int which, int level, void** ptr, int64_t shape[4], int64_t strides[4]) override {
+    if (level < 0 || level >= nlev) return fail(WL_ERR_INVALID_ARG, "level out of range");
+    const bool lev_field = which == WL_FIELD_X || which == WL_FIELD_R || which == WL_FIELD_L || which == WL_FIELD_ID;
+    if (!lev_field && level != 0) return fail(WL_ERR_INVALID_ARG, "only X, R, L, ID have coarse levels");
+    const LevelPlan& P = plan.lev[level];
+    int ncomp = 1;
+    T* base = nullptr;
+    T* second = nullptr;
+    switch (which) {
+      case WL_FIELD_U: ncomp = D; base = u[cur][0]; second = D > 1 ? u[cur][1] : nullptr; break;
+      case WL_FIELD_U0: ncomp = D; base = u[1 - cur][0]; second = u[1 - cur][1]; break;
+      case WL_FIELD_F: ncomp = D; base = ft[0]; second = ft[1]; break;
+      case WL_FIELD_V: ncomp = D; base = V[0]; second = V[1]; break;
+      case WL_FIELD_MU0: ncomp = D; base = mu0[0]; second = mu0[1]; break;
+      case WL_FIELD_MU1: ncomp = D * D; base = mu1[0]; second = mu1[1]; break;
+      case WL_FIELD_P: base = p; break;
+      case WL_FIELD_X: base = x[level]; break;
+      case WL_FIELD_R: base = r[level]; break;
+      case WL_FIELD_L: ncomp = D; base = L[level][0]; second = L[level][1]; break;
+      case WL_FIELD_ID: base = iD[level]; break;
+      default: return fail(WL_ERR_INVALID_ARG, "unknown field id");
+    }
+    *ptr = base;
+    shape[0] = ncomp;
+    shape[1] = P.pz;
+    shape[2] = P.py;
+    shape[3] = P.n[0] + 2;
+    strides[0] = second ? (int64_t)(second - base) : 0;
+    strides[1] = (int64_t)P.px * P.py;
+    strides[2] = P.px;
+    strides[3] = 1;
+    return WL_OK;
+  }
+};
+
+SimBase* make_impl(int prec, int ndim) {
+  if (prec == WL_F32) return ndim == 2 ? (SimBase*)new Impl<float, 2>() : (SimBase*)new Impl<float, 3>();
+  return ndim == 2 ? (SimBase*)new Impl<double, 2>() : (SimBase*)new Impl<double, 3>();
+}
+
+template <typename T, int D>
+void carve_impl(SimBase* s, void* ws) {
+  static_cast<Impl<T, D>*>(s)->carve((char*)ws);
+}
+
+}  // namespace
+
+struct wl_sim {
+  SimBase* impl;
+};
+
+extern "C" {
+
+size_t wl_workspace_bytes(const wl_sim_desc* desc, const wl_body_desc* body) {
+  wl_sim_desc d;
+  if (validate_and_default(desc, &d) != WL_OK) return 0;
+  if (validate_body(d, body) != WL_OK) return 0;
+  return make_plan(d, body && body->kind != WL_BODY_NONE).bytes;
+}
+
+wl_status wl_sim_create(const wl_sim_desc* desc, const wl_body_desc* body, void* ws, size_t bytes, void* hip_stream,
+                        wl_sim** out) {
+  if (!out) return fail(WL_ERR_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  wl_sim_desc d;
+  wl_status s = validate_and_default(desc, &d);
+  if (s != WL_OK) return s;
+  if ((s = validate_body(d, body)) != WL_OK) return s;
+  Plan P = make_plan(d, body && body->kind != WL_BODY_NONE);
+  if (!ws) return fail(WL_ERR_INVALID_ARG, "workspace is NULL");
+  if (((uintptr_t)ws) & 255u) return fail(WL_ERR_INVALID_ARG, "workspace must be 256-byte aligned");
+  if (bytes < P.bytes) return fail(WL_ERR_WORKSPACE_TOO_SMALL, "workspace smaller than wl_workspace_bytes()");
+  if (P.lev[0].elems >= (int64_t(1) << 31)) return fail(WL_ERR_UNSUPPORTED, "grid too large for 32-bit indexing");
+  SimBase* impl = make_impl(d.prec, d.ndim);
+  impl->desc = d;
+  std::memset(&impl->bdesc, 0, sizeof(impl->bdesc));
+  if (body) impl->bdesc = *body;
+  impl->plan = P;
+  impl->stream = (hipStream_t)hip_stream;
+  if (hipHostMalloc((void**)&impl->host_pin, 64, hipHostMallocDefault) != hipSuccess) {
+    delete impl;
+    return fail(WL_ERR_HIP, "hipHostMalloc of the 64-byte read-back buffer failed");
+  }
+  if (d.prec == WL_F32) {
+    if (d.ndim == 2) carve_impl<float, 2>(impl, ws); else carve_impl<float, 3>(impl, ws);
+  } else {
+    if (d.ndim == 2) carve_impl<double, 2>(impl, ws); else carve_impl<double, 3>(impl, ws);
+  }
+  hipError_t he = hipMemsetAsync(ws, 0, P.bytes, impl->stream);
+  if (he != hipSuccess) {
+    (void)hipHostFree(impl->host_pin);
+    delete impl;
+    return fail(WL_ERR_HIP, std::string("hipMemsetAsync: ") + hipGetErrorString(he));
+  }
+  s = impl->init();
+  if (s != WL_OK) {
+    (void)hipHostFree(impl->host_pin);
+    delete impl;
+    return s;
+  }
+  wl_sim* h = new wl_sim{impl};
+  *out = h;
+  return WL_OK;
+}
+
+wl_status wl_sim_destroy(wl_sim* sim) {
+  if (!sim) return fail(WL_ERR_INVALID_ARG, "sim is NULL");
+  if (sim->impl) {
+    if (sim->impl->stream) (void)hipStreamSynchronize(sim->impl->stream);
+    else (void)hipDeviceSynchronize();
+    if (sim->impl->host_pin) (void)hipHostFree(sim->impl->host_pin);
+    delete sim->impl;
+  }
+  delete sim;
+  return WL_OK;
+}
+
+#define WL_SIM_CHECK(sim) \
+  if (!(sim) || !(sim)->impl) return fail(WL_ERR_INVALID_ARG, "sim is NULL")
+
+wl_status wl_measure_body(wl_sim* sim, double t) {
+  WL_SIM_CHECK(sim);
+  if (!std::isfinite(t)) return fail(WL_ERR_INVALID_ARG, "t must be finite");
+  return sim->impl->measure(t);
+}
+
+wl_status wl_step(wl_sim* sim, int remeasure, wl_step_stats* stats) {
+  WL_SIM_CHECK(sim);
+  return sim->impl->step(remeasure, stats);
+}
+
+wl_status wl_apply_bc(wl_sim* sim) {
+  WL_SIM_CHECK(sim);
+  return sim->impl->apply_bc_cur();
+}
+
+wl_status wl_conv_diff(wl_sim* sim) {
+  WL_SIM_CHECK(sim);
+  return sim->impl->conv_diff();
+}
+
+wl_status wl_project(wl_sim* sim, double w, wl_solve_stats* stats) {
+  WL_SIM_CHECK(sim);
+  if (!(w > 0.0) || !std::isfinite(w)) return fail(WL_ERR_INVALID_ARG, "w must be > 0");
+  return sim->impl->project_cur(w, stats);
+}
+
+wl_status wl_poisson_solve(wl_sim* sim, const void* rhs, void* x_inout, double tol, int itmax,
+                           wl_solve_stats* stats) {
+  WL_SIM_CHECK(sim);
+  if (!std::isfinite(tol)) return fail(WL_ERR_INVALID_ARG, "tol must be finite");
+  return sim->impl->poisson(rhs, x_inout, tol, itmax, stats);
+}
+
+wl_status wl_forces(wl_sim* sim, double f_pressure[3], double f_viscous[3]) {
+  WL_SIM_CHECK(sim);
+  if (!f_pressure || !f_viscous) return fail(WL_ERR_INVALID_ARG, "force outputs are NULL");
+  return sim->impl->forces(f_pressure, f_viscous);
+}
+
+wl_status wl_field(wl_sim* sim, int which, int level, void** dev_ptr, int64_t shape[4], int64_t strides[4]) {
+  WL_SIM_CHECK(sim);
+  if (!dev_ptr || !shape || !strides) return fail(WL_ERR_INVALID_ARG, "outputs are NULL");
+  return sim->impl->field(which, level, dev_ptr, shape, strides);
+}
+
+wl_status wl_levels(wl_sim* sim, int* nlevels, int level, int64_t n_out[3]) {
+  WL_SIM_CHECK(sim);
+  const Plan& P = sim->impl->plan;
+  if (nlevels) *nlevels = P.nlev;
+  if (n_out) {
+    if (level < 0 || level >= P.nlev) return fail(WL_ERR_INVALID_ARG, "level out of range");
+    for (int a = 0; a < 3; ++a) n_out[a] = P.lev[level].n[a];
+  }
+  return WL_OK;
+}
+
+wl_status wl_set_time(wl_sim* sim, double t, double dt_next) {
+  WL_SIM_CHECK(sim);
+  if (!std::isfinite(t) || !(dt_next > 0.0) || !std::isfinite(dt_next))
+    return fail(WL_ERR_INVALID_ARG, "t must be finite and dt_next > 0");
+  sim->impl->t = t;
+  sim->impl->dt = dt_next;
+  return WL_OK;
+}
+
+wl_status wl_get_time(wl_sim* sim, double* t, double* dt_next) {
+  WL_SIM_CHECK(sim);
+  if (t) *t = sim->impl->t;
+  if (dt_next) *dt_next = sim->impl->dt;
+  return WL_OK;
+}
+
+const char* wl_last_error(void) { return g_err.c_str(); }
+
+}  // extern "C"

@@ -1,0 +1,198 @@
+"""Python face of the C ABI: a Simulation whose workspace is one torch device tensor.
+
+Only marshalling lives here; every step of the method runs in the HIP library.
+"""
+from __future__ import annotations
+
+import ctypes as C
+from typing import Optional, Sequence
+
+import torch
+
+from . import _lib as L
+
+
+def _body_desc(body) -> L.BodyDesc:
+    b = L.BodyDesc()
+    if body is None or getattr(body, "kind", "none") == "none":
+        b.kind = 0
+        return b
+    b.kind = L.BODY_KIND[body.kind]
+    for k, v in enumerate(tuple(body.center)[:3]):
+        b.center[k] = v
+    b.radius = float(body.radius)
+    for k, v in enumerate(tuple(body.half_extent)[:3]):
+        b.half_extent[k] = v
+    b.heave_amp, b.pitch_amp, b.freq = float(body.heave_amp), float(body.pitch_amp), float(body.freq)
+    b.phase_h, b.phase_p, b.spin_omega = float(body.phase_h), float(body.phase_p), float(body.spin_omega)
+    for k, v in enumerate(tuple(body.pivot_offset)[:3]):
+        b.pivot_offset[k] = v
+    return b
+
+
+class Simulation:
+    """BDIM projection solver on one GPU (fields live in ``self.workspace``).
+
+    Parameters mirror ``wl_sim_desc`` / ``wl_body_desc`` in include/wlmi.h.
+    ``body`` is any object with the attributes of ``wl_body_desc`` (kind is
+    'none', 'sphere' or 'box').
+    """
+
+    def __init__(self, n: Sequence[int], U: Sequence[float], nu: float, body=None,
+                 periodic: Sequence[bool] = (), convective_exit: bool = False, prec: str = "f32",
+                 eps: float = 1.0, dt0: float = 0.25, dt_max: float = 10.0, cfl_nu: float = 5.0,
+                 tol: float = 1e-6, itmax: int = 32, pcg_iters: int = 6, device="cuda:0",
+                 stream: Optional[torch.cuda.Stream] = None):
+        self.lib = L.load()
+        nd = len(n)
+        d = L.SimDesc()
+        d.ndim = nd
+        for k in range(nd):
+            d.n[k] = int(n[k])
+            d.U[k] = float(U[k])
+        d.nu = float(nu)
+        d.periodic_mask = sum((1 << k) for k, p in enumerate(periodic) if p)
+        d.convective_exit = 1 if convective_exit else 0
+        d.prec = L.WL_F64 if prec == "f64" else L.WL_F32
+        d.eps, d.dt0, d.dt_max, d.cfl_nu_coef = eps, dt0, dt_max, cfl_nu
+        d.mg_tol, d.mg_itmax, d.pcg_iters = tol, itmax, pcg_iters
+        self.desc = d
+        self.bdesc = _body_desc(body)
+        self.ndim = nd
+        self.n = tuple(int(v) for v in n)
+        self.dtype = torch.float64 if prec == "f64" else torch.float32
+        self.device = torch.device(device)
+        nbytes = self.lib.wl_workspace_bytes(C.byref(d), C.byref(self.bdesc))
+        if nbytes == 0:
+            raise L.WlError("invalid simulation description: %s" % self.lib.wl_last_error().decode())
+        # workspace: one caller-owned allocation (torch), 256-byte aligned
+        self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        base = self.workspace.data_ptr()
+        self._off = (-base) % 256
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        h = C.c_void_p()
+        L.check(self.lib.wl_sim_create(C.byref(d), C.byref(self.bdesc), C.c_void_p(base + self._off),
+                                       C.c_size_t(nbytes), C.c_void_p(self.stream.cuda_stream),
+                                       C.byref(h)), "wl_sim_create")
+        self._h = h
+
+    # ------------------------------------------------------------------ life
+    def close(self):
+        if getattr(self, "_h", None):
+            self.lib.wl_sim_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ------------------------------------------------------------- the method
+    def measure(self, t: float):
+        L.check(self.lib.wl_measure_body(self._h, float(t)), "wl_measure_body")
+
+    def step(self, remeasure: bool = True) -> dict:
+        st = L.StepStats()
+        L.check(self.lib.wl_step(self._h, 1 if remeasure else 0, C.byref(st)), "wl_step")
+        return {"dt": st.dt, "t": st.t, "dt_next": st.dt_next, "vcycles": (st.vcycles[0], st.vcycles[1]),
+                "res_linf": (st.res_linf[0], st.res_linf[1]), "converged": bool(st.converged)}
+
+    def apply_bc(self):
+        L.check(self.lib.wl_apply_bc(self._h), "wl_apply_bc")
+
+    def conv_diff(self):
+        L.check(self.lib.wl_conv_diff(self._h), "wl_conv_diff")
+        return self.field("f")
+
+    def project(self, w: float) -> dict:
+        st = L.SolveStats()
+        L.check(self.lib.wl_project(self._h, float(w), C.byref(st)), "wl_project")
+        return self._solve_dict(st)
+
+    def poisson_solve(self, rhs: Optional[torch.Tensor] = None, x: Optional[torch.Tensor] = None,
+                      tol: float = 0.0, itmax: int = 0) -> dict:
+        st = L.SolveStats()
+        rp = C.c_void_p(rhs.data_ptr()) if rhs is not None else None
+        xp = C.c_void_p(x.data_ptr()) if x is not None else None
+        L.check(self.lib.wl_poisson_solve(self._h, rp, xp, float(tol), int(itmax), C.byref(st)),
+                "wl_poisson_solve")
+        return self._solve_dict(st)
+
+    @staticmethod
+    def _solve_dict(st) -> dict:
+        return {"vcycles": st.vcycles, "res0_linf": st.res0_linf, "res_linf": st.res_linf,
+                "converged": bool(st.converged)}
+
+    def forces(self):
+        fp = (C.c_double * 3)()
+        fv = (C.c_double * 3)()
+        L.check(self.lib.wl_forces(self._h, fp, fv), "wl_forces")
+        return list(fp)[:self.ndim], list(fv)[:self.ndim]
+
+    # ------------------------------------------------------------- state
+    def field(self, name: str, level: int = 0) -> torch.Tensor:
+        """Zero-copy view (components, pz, py, nx+2) into the workspace."""
+        ptr = C.c_void_p()
+        shape = (C.c_int64 * 4)()
+        strides = (C.c_int64 * 4)()
+        L.check(self.lib.wl_field(self._h, L.FIELDS[name], int(level), C.byref(ptr), shape, strides),
+                "wl_field")
+        esz = torch.tensor([], dtype=self.dtype).element_size()
+        off = (ptr.value - self.workspace.data_ptr())
+        assert off % esz == 0
+        flat = self.workspace.view(self.dtype) if self.workspace.numel() % esz == 0 else \
+            self.workspace[: (self.workspace.numel() // esz) * esz].view(self.dtype)
+        return flat.as_strided(tuple(shape), tuple(strides), off // esz)
+
+    def scalar_buffer(self) -> torch.Tensor:
+        """A new zeroed device array in the pressure layout, returned as the
+        (pz, py, nx+2) view of a (pz, py, px) allocation; pass it to poisson_solve."""
+        v = self.field("p")
+        pz, py, nxp = v.shape[1], v.shape[2], v.shape[3]
+        px = v.stride(2)
+        store = torch.zeros((pz, py, px), dtype=self.dtype, device=self.device)
+        return store[:, :, :nxp]
+
+    def levels(self):
+        nl = C.c_int()
+        L.check(self.lib.wl_levels(self._h, C.byref(nl), 0, None), "wl_levels")
+        out = []
+        for l in range(nl.value):
+            nn = (C.c_int64 * 3)()
+            L.check(self.lib.wl_levels(self._h, None, l, nn), "wl_levels")
+            out.append(tuple(nn)[:self.ndim])
+        return out
+
+    def set_time(self, t: float, dt_next: float):
+        L.check(self.lib.wl_set_time(self._h, float(t), float(dt_next)), "wl_set_time")
+
+    def time(self):
+        t = C.c_double()
+        dt = C.c_double()
+        L.check(self.lib.wl_get_time(self._h, C.byref(t), C.byref(dt)), "wl_get_time")
+        return t.value, dt.value
+
+    # convenience converters between the padded [comp][z][y][x] views and
+    # per-component arrays indexed [x, y(, z)]
+    def get(self, name: str, level: int = 0):
+        v = self.field(name, level)
+        torch.cuda.synchronize(self.device)
+        out = []
+        for c in range(v.shape[0]):
+            a = v[c]
+            a = a[0].transpose(0, 1) if self.ndim == 2 else a.permute(2, 1, 0)
+            out.append(a.to("cpu", torch.float64).numpy().copy())
+        return out
+
+    def set(self, name: str, arrays, level: int = 0):
+        v = self.field(name, level)
+        for c, arr in enumerate(arrays):
+            t = torch.as_tensor(arr, dtype=self.dtype)
+            t = t.transpose(0, 1).unsqueeze(0) if self.ndim == 2 else t.permute(2, 1, 0)
+            v[c].copy_(t.to(self.device))
+        torch.cuda.synchronize(self.device)
+
+    def set_velocity(self, arrays):
+        self.set("u", arrays)
+        self.apply_bc()

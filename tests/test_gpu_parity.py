@@ -1,0 +1,212 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 oracle on the same inputs."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import wlsynth
+from oracle import poisson as OP
+from oracle.flux import conv_diff
+from oracle.solver import apply_bc
+
+from gpu_util import CD_REL, FP32_10STEP, FP32_STEP, FP64_STEP, gauge_free, make_pair, rel_l2, small_cases
+
+pytestmark = pytest.mark.gpu
+CASES = small_cases()
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.mark.parametrize("name", ["circle2d", "sphere3d", "plate3d", "rotcyl2d"])
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_measure_and_coefficients(name, prec):
+    _say("measure", name, prec)
+    w = CASES[name]
+    ref, gpu = make_pair(w, prec, 1e-6)
+    tol = 1e-13 if prec == "f64" else 2e-7
+    g = ref.grid
+    mu0 = gpu.get("mu0")
+    for i in range(g.ndim):
+        np.testing.assert_allclose(mu0[i], ref.L[i], atol=tol, rtol=0)
+    mu1 = gpu.get("mu1")
+    V = gpu.get("V")
+    for i in range(g.ndim):
+        np.testing.assert_allclose(V[i], ref.V[i], atol=tol, rtol=0)
+        for j in range(g.ndim):
+            np.testing.assert_allclose(mu1[i * g.ndim + j], ref.mu1[i][j], atol=tol, rtol=0)
+    assert len(gpu.levels()) == len(ref.levels)
+    for l, lev in enumerate(ref.levels):
+        Lg = gpu.get("L", l)
+        for i in range(g.ndim):
+            np.testing.assert_allclose(Lg[i], lev.L[i], atol=4 * tol * 2 ** l, rtol=0)
+        iD = gpu.get("iD", l)[0]
+        act = lev.active
+        assert np.array_equal(iD != 0, act)
+        np.testing.assert_allclose(iD[act], lev.iD[act], rtol=1e-12 if prec == "f64" else 1e-5)
+    gpu.close()
+
+
+def test_measure_moving_body_at_later_time():
+    w = CASES["plate3d"]
+    ref, gpu = make_pair(w, "f64", 1e-6)
+    for t in (3.7, 41.0):
+        ref.measure(t)
+        gpu.measure(t)
+        mu0 = gpu.get("mu0")
+        V = gpu.get("V")
+        for i in range(3):
+            np.testing.assert_allclose(mu0[i], ref.L[i], atol=1e-13, rtol=0)
+            np.testing.assert_allclose(V[i], ref.V[i], atol=1e-13, rtol=0)
+    gpu.close()
+
+
+@pytest.mark.parametrize("name", ["circle2d", "sphere3d", "tgv3d"])
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_conv_diff(name, prec):
+    _say("conv_diff", name, prec)
+    w = CASES[name]
+    ref, gpu = make_pair(w, prec, 1e-6)
+    g = ref.grid
+    # a rough field: initial field plus seeded noise, boundary conditions applied on both sides
+    u = [ref.u[i] + wlsynth.random_field(g.shape, seed=7, comp=i, amp=0.3) for i in range(g.ndim)]
+    ref.set_velocity(u)
+    gpu.set_velocity(u)
+    R = conv_diff(g, ref.u, ref.nu)
+    Rg = gpu.conv_diff()
+    Rg = gpu.get("f")
+    scale = max(float(np.abs(R[i]).max()) for i in range(g.ndim))
+    tol = 1e-13 if prec == "f64" else 3e-6
+    for i in range(g.ndim):
+        np.testing.assert_allclose(Rg[i], R[i], atol=tol * scale, rtol=0)
+    gpu.close()
+
+
+@pytest.mark.parametrize("name", ["sphere3d", "tgv3d", "circle2d"])
+def test_boundary_conditions(name):
+    w = CASES[name]
+    ref, gpu = make_pair(w, "f64", 1e-6)
+    g = ref.grid
+    u = [wlsynth.random_field(g.shape, seed=5, comp=i) for i in range(g.ndim)]
+    gpu.set("u", u)
+    gpu.apply_bc()
+    apply_bc(g, ref.U, u)
+    got = gpu.get("u")
+    for i in range(g.ndim):
+        np.testing.assert_array_equal(got[i], u[i])
+    gpu.close()
+
+
+@pytest.mark.parametrize("name", ["circle2d", "sphere3d", "tgv3d"])
+def test_poisson_solve(name):
+    _say("poisson", name)
+    w = CASES[name]
+    ref, gpu = make_pair(w, "f64", 1e-12)
+    g = ref.grid
+    lev = ref.levels[0]
+    rng = np.random.default_rng(3)
+    z = g.zeros()
+    z[g.interior()] = rng.normal(size=g.n)
+    z = np.where(lev.active, z, 0.0)
+    z[lev.active] -= z[lev.active].mean()
+    x = g.zeros()
+    st = OP.solve(ref.levels, x, z, tol=1e-11, itmax=200)
+    assert st["converged"]
+    import torch
+    rhs = gpu.scalar_buffer()          # pressure-layout device arrays
+    xg = gpu.scalar_buffer()
+    zz = torch.as_tensor(z, dtype=torch.float64)
+    zz = zz.transpose(0, 1).unsqueeze(0) if g.ndim == 2 else zz.permute(2, 1, 0)
+    rhs.copy_(zz.to(rhs.device))
+    sg = gpu.poisson_solve(rhs=rhs, x=xg, tol=1e-11, itmax=200)
+    assert sg["converged"], sg
+    xa = xg.cpu().numpy()
+    xa = xa[0].T if g.ndim == 2 else xa.transpose(2, 1, 0)
+    np.testing.assert_allclose(gauge_free(xa, lev.active), gauge_free(x, lev.active), atol=1e-8)
+    # same number of cycles up to rounding-order effects
+    assert abs(sg["vcycles"] - st["vcycles"]) <= 1
+    gpu.close()
+
+
+@pytest.mark.parametrize("name", ["circle2d", "sphere3d", "tgv3d", "plate3d", "rotcyl2d"])
+def test_one_step_fp64(name):
+    _say("step f64", name)
+    w = CASES[name]
+    ref, gpu = make_pair(w, "f64", 1e-13)
+    ref.tol = 1e-13
+    s_ref = ref.step()
+    s_gpu = gpu.step()
+    err = rel_l2(gpu.get("u"), ref.u, ref.grid)
+    _say("  rel-L2 u", err, s_ref["vcycles"], s_gpu["vcycles"])
+    assert err <= FP64_STEP
+    act = ref.levels[0].active
+    p_err = np.abs(gauge_free(gpu.get("p")[0], act) - gauge_free(ref.p, act)).max()
+    assert p_err <= 1e-9 * max(1.0, np.abs(ref.p[act]).max())
+    assert abs(s_gpu["dt_next"] - ref.dt) <= 1e-12 * ref.dt
+    gpu.close()
+
+
+@pytest.mark.parametrize("name", ["circle2d", "sphere3d", "tgv3d", "plate3d"])
+def test_one_step_fp32(name):
+    _say("step f32", name)
+    w = CASES[name]
+    ref, gpu = make_pair(w, "f32", 1e-6)
+    ref.tol = 1e-13
+    ref.step()
+    gpu.step()
+    err = rel_l2(gpu.get("u"), ref.u, ref.grid)
+    _say("  rel-L2 u", err)
+    assert err <= FP32_STEP
+    gpu.close()
+
+
+@pytest.mark.parametrize("name", ["circle2d", "sphere3d"])
+def test_ten_steps_fp32(name):
+    _say("10 steps f32", name)
+    w = CASES[name]
+    ref, gpu = make_pair(w, "f32", 1e-6)
+    ref.tol = 1e-13
+    for _ in range(10):
+        ref.step()
+        gpu.step()
+    err = rel_l2(gpu.get("u"), ref.u, ref.grid)
+    _say("  rel-L2 u", err)
+    assert err <= FP32_10STEP
+    gpu.close()
+
+
+def test_drag_coefficient_window_circle():
+    # 2-D circle, 128 x 64, R = 8, Re = 250: mean C_D over steps 51-100 (A_ref = D = 16)
+    _say("drag window")
+    w = CASES["circle2d"]
+    ref, gpu = make_pair(w, "f32", 1e-6)
+    ref.tol = 1e-10
+    cd_r, cd_g = [], []
+    for k in range(100):
+        ref.step()
+        gpu.step()
+        if k >= 50:
+            fp, fv = ref.forces()
+            cd_r.append(2 * (fp[0] + fv[0]) / 16.0)
+            gp, gv = gpu.forces()
+            cd_g.append(2 * (gp[0] + gv[0]) / 16.0)
+    mr, mg = float(np.mean(cd_r)), float(np.mean(cd_g))
+    _say("  mean C_D oracle %.6f gpu %.6f" % (mr, mg))
+    assert abs(mg - mr) <= CD_REL * abs(mr)
+    gpu.close()
+
+
+def test_forces_fp64_match():
+    w = CASES["sphere3d"]
+    ref, gpu = make_pair(w, "f64", 1e-13)
+    ref.tol = 1e-13
+    ref.step()
+    gpu.step()
+    fp, fv = ref.forces()
+    gp, gv = gpu.forces()
+    np.testing.assert_allclose(gp, fp, rtol=1e-9, atol=1e-12)
+    np.testing.assert_allclose(gv, fv, rtol=1e-9, atol=1e-12)
+    gpu.close()
