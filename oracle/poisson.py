@@ -20,7 +20,12 @@ Readings used (the paper names the method only):
     the solve alternates one V-cycle and one fine PCG(k) until the max-norm
     of the residual is below tol (zero cycles if it already is), at most
     itmax cycles;
-  * all inner products and norms are FP64 sums.
+  * all inner products and norms are FP64 sums;
+  * A has the constants (on the connected active cells) in its null space,
+    since every boundary is Neumann or periodic, so each PCG sweep starts by
+    removing the residual's mean over the active cells (projection onto the
+    range of A).  This is exact for a consistent system and keeps rounding
+    from driving the solution along the null space.
 """
 from __future__ import annotations
 
@@ -129,6 +134,9 @@ def prolong(gf: Grid, xc):
 
 def pcg(lev: Level, x, r, iters):
     """Jacobi-preconditioned CG on A x = b, given x and r = b - A x (updated in place)."""
+    act = lev.active
+    if act.any():
+        r[act] -= np.mean(r[act])
     z = lev.iD * r
     e = z.copy()
     rho = dot(r, z)

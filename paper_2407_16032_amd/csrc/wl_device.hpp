@@ -17,7 +17,9 @@ constexpr int kSlotRmax = 2 * kMaxPcg + 1;     // residual max-norm
 constexpr int kSlotCfl = kSlotRmax + 1;        // max outflux
 constexpr int kSlotExit = kSlotCfl + 1;        // exit-plane flux
 constexpr int kSlotForce = kSlotExit + 1;      // 6 slots: pressure xyz, viscous xyz
-constexpr int kNumSlots = kSlotForce + 6;
+constexpr int kSlotSumR = kSlotForce + 6;      // sum of the residual over active cells
+constexpr int kSlotCnt = kSlotSumR + 1;        // number of active cells
+constexpr int kNumSlots = kSlotCnt + 1;
 
 // scalar results (doubles)
 constexpr int kScalRmax = 0;

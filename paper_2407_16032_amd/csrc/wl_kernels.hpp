@@ -397,14 +397,26 @@ __device__ __forceinline__ void nbr_offsets(const Grid3& g, const int I[3], int 
   }
 }
 
+// The kernels that hand a residual to a PCG sweep (div_res, restrict, prolong,
+// mean0) also emit per-block partials of sum(r) and of the active-cell count
+// over active cells: the sweep removes the residual's mean first.
+__device__ __forceinline__ void put_mean_partials(double sr, double cnt, double* red) {
+  sr = block_sum(sr);
+  cnt = block_sum(cnt);
+  if (threadIdx.x == 0) {
+    red[(size_t)kSlotSumR * kMaxBlocks + blockIdx.x] = sr;
+    red[(size_t)kSlotCnt * kMaxBlocks + blockIdx.x] = cnt;
+  }
+}
+
 // r = z - A x0 on active cells (0 on solid cells), z = rhs or div u, x0 = p wdt (if p) else x.
-// Writes x (if p), r; partials: max|r|, sum r iD r; resets the level's PCG flag.
+// Writes x (if p), r; partials: max|r|, sum r, active count; resets the level's PCG flag.
 template <typename T, int D>
 __global__ void __launch_bounds__(kBlock) k_div_res(Grid3 g, Vec3<T> u, const T* rhs, const T* p,
                                                     T wdt, Vec3<T> L, const T* iD, T* x, T* r,
-                                                    double* part_max, double* part_rho, int* flag) {
+                                                    double* part_max, double* red, int* flag) {
   const int total = g.n[0] * g.n[1] * ((D == 3) ? g.n[2] : 1);
-  double mx = 0.0, rho = 0.0;
+  double mx = 0.0, sr = 0.0, cnt = 0.0;
   if (blockIdx.x == 0 && threadIdx.x == 0) *flag = 0;
   for (int lin = blockIdx.x * kBlock + threadIdx.x; lin < total; lin += gridDim.x * kBlock) {
     int I[3], idx, op[3], om[3];
@@ -432,38 +444,39 @@ __global__ void __launch_bounds__(kBlock) k_div_res(Grid3 g, Vec3<T> u, const T*
     if (p) x[idx] = xc;
     r[idx] = rr;
     mx = fmax(mx, fabs(double(rr)));
-    rho += double(rr) * (double(di) * double(rr));
+    if (di != T(0)) {
+      sr += double(rr);
+      cnt += 1.0;
+    }
   }
   mx = block_max(mx);
-  rho = block_sum(rho);
-  if (threadIdx.x == 0) {
-    part_max[blockIdx.x] = mx;
-    part_rho[blockIdx.x] = rho;
-  }
+  if (threadIdx.x == 0) part_max[blockIdx.x] = mx;
+  put_mean_partials(sr, cnt, red);
 }
 
-// rho partial of the current residual (used when the grid has a single level)
+// mean partials of the current residual (used when the grid has a single level)
 template <typename T, int D>
-__global__ void __launch_bounds__(kBlock) k_rho0(Grid3 g, const T* iD, const T* r, double* part_rho, int* flag) {
+__global__ void __launch_bounds__(kBlock) k_mean0(Grid3 g, const T* iD, const T* r, double* red, int* flag) {
   const int total = g.n[0] * g.n[1] * ((D == 3) ? g.n[2] : 1);
-  double rho = 0.0;
+  double sr = 0.0, cnt = 0.0;
   if (blockIdx.x == 0 && threadIdx.x == 0) *flag = 0;
   for (int lin = blockIdx.x * kBlock + threadIdx.x; lin < total; lin += gridDim.x * kBlock) {
     int I[3], idx;
     cell_of<D>(g, lin, I, idx);
-    const T rr = r[idx];
-    rho += double(rr) * (double(iD[idx]) * double(rr));
+    if (iD[idx] != T(0)) {
+      sr += double(r[idx]);
+      cnt += 1.0;
+    }
   }
-  rho = block_sum(rho);
-  if (threadIdx.x == 0) part_rho[blockIdx.x] = rho;
+  put_mean_partials(sr, cnt, red);
 }
 
 // restriction: r_c = sum of the 2^D children (0 on solid coarse cells), x_c = 0; rho partial.
 template <typename T, int D>
 __global__ void __launch_bounds__(kBlock) k_restrict(Grid3 f, Grid3 c, const T* rf, const T* iDc, T* rc,
-                                                     T* xc, double* part_rho, int* flag) {
+                                                     T* xc, double* red, int* flag) {
   const int total = c.n[0] * c.n[1] * ((D == 3) ? c.n[2] : 1);
-  double rho = 0.0;
+  double sr = 0.0, cnt = 0.0;
   if (blockIdx.x == 0 && threadIdx.x == 0) *flag = 0;
   for (int lin = blockIdx.x * kBlock + threadIdx.x; lin < total; lin += gridDim.x * kBlock) {
     int J[3], cidx;
@@ -478,10 +491,12 @@ __global__ void __launch_bounds__(kBlock) k_restrict(Grid3 f, Grid3 c, const T* 
     const T rr = (di != T(0)) ? s : T(0);
     rc[cidx] = rr;
     xc[cidx] = T(0);
-    rho += double(rr) * (double(di) * double(rr));
+    if (di != T(0)) {
+      sr += double(rr);
+      cnt += 1.0;
+    }
   }
-  rho = block_sum(rho);
-  if (threadIdx.x == 0) part_rho[blockIdx.x] = rho;
+  put_mean_partials(sr, cnt, red);
 }
 
 // prolongation + correction: e = x_c[parent]; x_f += e; r_f -= A_f e; rho partial.
@@ -493,9 +508,9 @@ __device__ __forceinline__ int parent_idx(const Grid3& c, int I0, int I1, int I2
 
 template <typename T, int D>
 __global__ void __launch_bounds__(kBlock) k_prolong(Grid3 f, Grid3 c, const T* xc, Vec3<T> L, const T* iD,
-                                                    T* xf, T* rf, double* part_rho, int* flag) {
+                                                    T* xf, T* rf, double* red, int* flag) {
   const int total = f.n[0] * f.n[1] * ((D == 3) ? f.n[2] : 1);
-  double rho = 0.0;
+  double sr = 0.0, cnt = 0.0;
   if (blockIdx.x == 0 && threadIdx.x == 0) *flag = 0;
   for (int lin = blockIdx.x * kBlock + threadIdx.x; lin < total; lin += gridDim.x * kBlock) {
     int I[3], idx;
@@ -517,49 +532,68 @@ __global__ void __launch_bounds__(kBlock) k_prolong(Grid3 f, Grid3 c, const T* x
       }
       rr = rr - Ae;
       rf[idx] = rr;
+      sr += double(rr);
+      cnt += 1.0;
     }
-    rho += double(rr) * (double(di) * double(rr));
   }
-  rho = block_sum(rho);
-  if (threadIdx.x == 0) part_rho[blockIdx.x] = rho;
+  put_mean_partials(sr, cnt, red);
 }
 
-// PCG pass A (iteration k): e_new = iD r + beta e_old (beta = rho_k/rho_{k-1}, 0 at k = 0),
-// q = A e_new (0 on solid cells); sigma partial = sum e_new q.  Stops if rho_k == 0.
+// mean of the residual over the active cells, from the producer's partials
+__device__ __forceinline__ double residual_mean(const double* red, int nparts) {
+  const double cnt = total_of(red + (size_t)kSlotCnt * kMaxBlocks, nparts);
+  const double sr = total_of(red + (size_t)kSlotSumR * kMaxBlocks, nparts);
+  return cnt > 0.0 ? sr / cnt : 0.0;
+}
+
+// PCG pass A (iteration k).  k = 0: e = iD (r - m) with m the residual mean over
+// active cells, rho_0 partial = sum (r - m) e.  k > 0: e_new = iD r + beta e_old with
+// beta = rho_k/rho_{k-1} (stops if rho_k == 0).  Then q = A e_new (0 on solid
+// cells) and the sigma partial = sum e_new q.
 template <typename T, int D>
 __global__ void __launch_bounds__(kBlock) k_pcg_a(Grid3 g, Vec3<T> L, const T* iD, const T* r, const T* eo,
-                                                  T* en, T* q, const double* red, int k, int nparts,
+                                                  T* en, T* q, double* red, int k, int nparts,
                                                   double* part_sig, int* flag) {
   if (*flag) return;
-  const double rho = total_of(red + (size_t)(kSlotRho0 + k) * kMaxBlocks, nparts);
-  if (rho == 0.0) {
-    if (blockIdx.x == 0 && threadIdx.x == 0) *flag = 1;
-    return;
+  T beta = T(0), mean = T(0);
+  if (k > 0) {
+    const double rho = total_of(red + (size_t)(kSlotRho0 + k) * kMaxBlocks, nparts);
+    if (rho == 0.0) {
+      if (blockIdx.x == 0 && threadIdx.x == 0) *flag = 1;
+      return;
+    }
+    beta = T(rho / total_of(red + (size_t)(kSlotRho0 + k - 1) * kMaxBlocks, nparts));
+  } else {
+    mean = T(residual_mean(red, nparts));
   }
-  T beta = T(0);
-  if (k > 0) beta = T(rho / total_of(red + (size_t)(kSlotRho0 + k - 1) * kMaxBlocks, nparts));
   const int total = g.n[0] * g.n[1] * ((D == 3) ? g.n[2] : 1);
-  double sig = 0.0;
+  double sig = 0.0, rho0 = 0.0;
   for (int lin = blockIdx.x * kBlock + threadIdx.x; lin < total; lin += gridDim.x * kBlock) {
     int I[3], idx, op[3], om[3];
     cell_of<D>(g, lin, I, idx);
     nbr_offsets<D>(g, I, op, om);
-    const T ec = (k > 0) ? iD[idx] * r[idx] + beta * eo[idx] : iD[idx] * r[idx];
+    const T di = iD[idx];
+    const T ec = (k > 0) ? di * r[idx] + beta * eo[idx] : di * (r[idx] - mean);
     en[idx] = ec;
     T qq = T(0);
-    if (iD[idx] != T(0)) {
+    if (di != T(0)) {
       for (int a = 0; a < D; ++a) {
         const int ip = idx + op[a], im = idx + om[a];
-        const T ep = (k > 0) ? iD[ip] * r[ip] + beta * eo[ip] : iD[ip] * r[ip];
-        const T em = (k > 0) ? iD[im] * r[im] + beta * eo[im] : iD[im] * r[im];
+        const T ep = (k > 0) ? iD[ip] * r[ip] + beta * eo[ip] : iD[ip] * (r[ip] - mean);
+        const T em = (k > 0) ? iD[im] * r[im] + beta * eo[im] : iD[im] * (r[im] - mean);
         qq = qq + L.c[a][ip] * (ep - ec) - L.c[a][idx] * (ec - em);
       }
+      if (k == 0) rho0 += double(r[idx] - mean) * double(ec);
     }
     q[idx] = qq;
     sig += double(ec) * double(qq);
   }
   sig = block_sum(sig);
   if (threadIdx.x == 0) part_sig[blockIdx.x] = sig;
+  if (k == 0) {
+    rho0 = block_sum(rho0);
+    if (threadIdx.x == 0) red[(size_t)kSlotRho0 * kMaxBlocks + blockIdx.x] = rho0;
+  }
 }
 
 // PCG pass B (iteration k): alpha = rho_k/sigma_k; x += alpha e; r -= alpha q;
@@ -571,6 +605,8 @@ __global__ void __launch_bounds__(kBlock) k_pcg_b(Grid3 g, const T* iD, const T*
   const int total = g.n[0] * g.n[1] * ((D == 3) ? g.n[2] : 1);
   bool skip = (*flag) != 0;
   T alpha = T(0);
+  // k = 0 also moves the residual mean over active cells out of r
+  const T mean = (k == 0) ? T(residual_mean(red, nparts)) : T(0);
   if (!skip) {
     const double sig = total_of(red + (size_t)(kSlotSig0 + k) * kMaxBlocks, nparts);
     if (fabs(sig) < 1e-300) {
@@ -580,17 +616,19 @@ __global__ void __launch_bounds__(kBlock) k_pcg_b(Grid3 g, const T* iD, const T*
       alpha = T(total_of(red + (size_t)(kSlotRho0 + k) * kMaxBlocks, nparts) / sig);
     }
   }
-  if (skip && !want_max) return;
+  if (skip && !want_max && mean == T(0)) return;
   double rho = 0.0, mx = 0.0;
   for (int lin = blockIdx.x * kBlock + threadIdx.x; lin < total; lin += gridDim.x * kBlock) {
     int I[3], idx;
     cell_of<D>(g, lin, I, idx);
     T rr = r[idx];
+    const bool act = iD[idx] != T(0);
+    if (act && mean != T(0)) rr = rr - mean;
     if (!skip) {
       x[idx] = x[idx] + alpha * e[idx];
       rr = rr - alpha * q[idx];
-      r[idx] = rr;
     }
+    if (!skip || (act && mean != T(0))) r[idx] = rr;
     rho += double(rr) * (double(iD[idx]) * double(rr));
     mx = fmax(mx, fabs(double(rr)));
   }

@@ -225,7 +225,9 @@ struct Impl : SimBase {
   }
   double* slot(int s) const { return red + (size_t)s * kMaxBlocks; }
 
-  void carve(char* base) {
+  // Assign every field an offset in the workspace; returns the bytes used.
+  size_t carve(char* base) {
+    nlev = plan.nlev;
     size_t off = 0;
     auto take = [&](size_t bytes) {
       char* p_ = base + off;
@@ -261,6 +263,20 @@ struct Impl : SimBase {
     red = (double*)take((size_t)kNumSlots * kMaxBlocks * sizeof(double));
     scal = (double*)take(kNumScal * sizeof(double));
     flags = (int*)take(kMaxLevels * sizeof(int));
+    return off;
+  }
+
+  // every buffer a kernel may touch is carved (non-NULL) and inside [base, base + bytes)
+  bool carved_ok(const char* base, size_t bytes) const {
+    auto in = [&](const void* q) { return q && (const char*)q >= base && (const char*)q < base + bytes; };
+    bool ok = in(p) && in(ebuf) && in(red) && in(scal) && in(flags);
+    for (int k = 0; k < D; ++k) ok = ok && in(u[0][k]) && in(u[1][k]) && in(ft[k]) && in(V[k]) && in(mu0[k]);
+    for (int k = 0; k < D * D; ++k) ok = ok && in(mu1[k]);
+    for (int l = 0; l < nlev; ++l) {
+      ok = ok && in(x[l]) && in(r[l]) && in(e[l][0]) && in(e[l][1]) && in(q[l]) && in(iD[l]);
+      for (int k = 0; k < D; ++k) ok = ok && in(L[l][k]);
+    }
+    return ok;
   }
 
   void setup_grids() {
@@ -367,11 +383,11 @@ struct Impl : SimBase {
 
   void vcycle(int l) {
     k_restrict<T, D><<<nb[l + 1], kBlock, 0, stream>>>(g[l], g[l + 1], r[l], iD[l + 1], r[l + 1], x[l + 1],
-                                                       slot(kSlotRho0), flags + l + 1);
+                                                       red, flags + l + 1);
     if (l + 2 < nlev) vcycle(l + 1);
     pcg(l + 1, false);
     k_prolong<T, D><<<nb[l], kBlock, 0, stream>>>(g[l], g[l + 1], x[l + 1], v3(L[l]), iD[l], x[l], r[l],
-                                                  slot(kSlotRho0), flags + l);
+                                                  red, flags + l);
   }
 
   // initial residual already in r[0] / rmax slot
@@ -383,7 +399,7 @@ struct Impl : SimBase {
     int n = 0;
     while (res >= tol && n < itmax) {
       if (nlev > 1) vcycle(0);
-      else k_rho0<T, D><<<nb[0], kBlock, 0, stream>>>(g[0], iD[0], r[0], slot(kSlotRho0), flags);
+      else k_mean0<T, D><<<nb[0], kBlock, 0, stream>>>(g[0], iD[0], r[0], red, flags);
       pcg(0, true);
       ++n;
       s = read_scalar_max(kSlotRmax, nb[0], &res);
@@ -403,7 +419,7 @@ struct Impl : SimBase {
   wl_status project(T* const uu[3], double w, wl_solve_stats* st) {
     const T wdt = T(w * dt);
     k_div_res<T, D><<<nb[0], kBlock, 0, stream>>>(g[0], v3(uu), nullptr, p, wdt, v3(L[0]), iD[0], x[0], r[0],
-                                                  slot(kSlotRmax), slot(kSlotRho0), flags);
+                                                  slot(kSlotRmax), red, flags);
     WL_HIP(hipGetLastError());
     wl_status s = mg_loop(desc.mg_tol, desc.mg_itmax, st);
     if (s != WL_OK) return s;
@@ -422,7 +438,7 @@ struct Impl : SimBase {
     T* xs = x[0];
     if (xin) x[0] = (T*)xin;
     k_div_res<T, D><<<nb[0], kBlock, 0, stream>>>(g[0], v3(u[cur]), (const T*)rhs, nullptr, T(0), v3(L[0]),
-                                                  iD[0], x[0], r[0], slot(kSlotRmax), slot(kSlotRho0), flags);
+                                                  iD[0], x[0], r[0], slot(kSlotRmax), red, flags);
     wl_status s = WL_OK;
     hipError_t he = hipGetLastError();
     if (he != hipSuccess) s = fail(WL_ERR_HIP, hipGetErrorString(he));
@@ -558,8 +574,25 @@ SimBase* make_impl(int prec, int ndim) {
 }
 
 template <typename T, int D>
-void carve_impl(SimBase* s, void* ws) {
-  static_cast<Impl<T, D>*>(s)->carve((char*)ws);
+bool carve_impl(SimBase* s, void* ws, size_t bytes) {
+  Impl<T, D>* im = static_cast<Impl<T, D>*>(s);
+  const size_t used = im->carve((char*)ws);
+  return used <= bytes && im->carved_ok((const char*)ws, bytes);
+}
+
+bool carve_any(SimBase* impl, const wl_sim_desc& d, void* ws, size_t bytes) {
+  if (d.prec == WL_F32) return d.ndim == 2 ? carve_impl<float, 2>(impl, ws, bytes) : carve_impl<float, 3>(impl, ws, bytes);
+  return d.ndim == 2 ? carve_impl<double, 2>(impl, ws, bytes) : carve_impl<double, 3>(impl, ws, bytes);
+}
+
+// Host-only dry run of the carving at a fake base address (never dereferenced).
+bool plan_consistent(const wl_sim_desc& d, const Plan& P) {
+  SimBase* impl = make_impl(d.prec, d.ndim);
+  impl->desc = d;
+  impl->plan = P;
+  const bool ok = carve_any(impl, d, (void*)(uintptr_t)4096, P.bytes);
+  delete impl;
+  return ok;
 }
 
 }  // namespace
@@ -574,7 +607,12 @@ size_t wl_workspace_bytes(const wl_sim_desc* desc, const wl_body_desc* body) {
   wl_sim_desc d;
   if (validate_and_default(desc, &d) != WL_OK) return 0;
   if (validate_body(d, body) != WL_OK) return 0;
-  return make_plan(d, body && body->kind != WL_BODY_NONE).bytes;
+  const Plan P = make_plan(d, body && body->kind != WL_BODY_NONE);
+  if (!plan_consistent(d, P)) {
+    fail(WL_ERR_INVALID_ARG, "internal: workspace plan and field carving disagree");
+    return 0;
+  }
+  return P.bytes;
 }
 
 wl_status wl_sim_create(const wl_sim_desc* desc, const wl_body_desc* body, void* ws, size_t bytes, void* hip_stream,
@@ -596,15 +634,15 @@ wl_status wl_sim_create(const wl_sim_desc* desc, const wl_body_desc* body, void*
   if (body) impl->bdesc = *body;
   impl->plan = P;
   impl->stream = (hipStream_t)hip_stream;
+  if (!carve_any(impl, d, ws, P.bytes)) {
+    delete impl;
+    return fail(WL_ERR_WORKSPACE_TOO_SMALL, "internal: workspace plan and field carving disagree");
+  }
   if (hipHostMalloc((void**)&impl->host_pin, 64, hipHostMallocDefault) != hipSuccess) {
     delete impl;
     return fail(WL_ERR_HIP, "hipHostMalloc of the 64-byte read-back buffer failed");
   }
-  if (d.prec == WL_F32) {
-    if (d.ndim == 2) carve_impl<float, 2>(impl, ws); else carve_impl<float, 3>(impl, ws);
-  } else {
-    if (d.ndim == 2) carve_impl<double, 2>(impl, ws); else carve_impl<double, 3>(impl, ws);
-  }
+
   hipError_t he = hipMemsetAsync(ws, 0, P.bytes, impl->stream);
   if (he != hipSuccess) {
     (void)hipHostFree(impl->host_pin);

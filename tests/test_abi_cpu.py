@@ -96,6 +96,21 @@ def test_workspace_bytes_and_validation(lib):
     assert lib.wl_workspace_bytes(C.byref(d), C.byref(body)) == nb
 
 
+@pytest.mark.parametrize("n", [(128, 64), (512, 256), (64, 32, 32), (96, 48, 48), (768, 384, 384),
+                               (24, 20, 10), (6, 5)])
+@pytest.mark.parametrize("prec", [L.WL_F32, L.WL_F64])
+def test_workspace_plan_is_consistent(lib, n, prec):
+    # wl_workspace_bytes dry-runs the field carving on the host and returns 0 if any
+    # buffer of any multigrid level would be missing or outside the workspace
+    d = _desc(n=n, prec=prec)
+    nb = lib.wl_workspace_bytes(C.byref(d), None)
+    assert nb > 0, lib.wl_last_error()
+    cells = 1
+    for v in n:
+        cells *= v + 2
+    assert nb >= cells * (4 if prec == L.WL_F32 else 8) * (5 * len(n) + len(n) ** 2 + 7)
+
+
 def test_create_rejects_bad_arguments_before_any_gpu_work(lib):
     d = _desc()
     out = C.c_void_p()
