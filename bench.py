@@ -1,0 +1,214 @@
+#!/usr/bin/env python3
+"""Throughput of the FP32 BDIM projection step on one MI355X.
+
+Metric: ns per grid point per time step (lower is better), with the MG
+V-cycles per step and the HBM-roofline fraction of the dominant kernel.
+
+Default workload: the heaving-pitching flat plate, 768 x 384 x 384 cells
+(113 M), chord 64 cells, Re = 5000, body re-measured every step, convective
+exit, FP32 fields with FP64 reductions, multigrid to a residual max-norm of
+1e-5.  Synthetic input: uniform inflow plus seeded 1e-3 noise.
+
+Usage: python bench.py [--steps K] [--warmup W] [--workload NAME] [--no-cpu-baseline]
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
+
+
+def workloads():
+    import wlsynth
+    return {
+        "plate3d": wlsynth.plate_3d(scale=1),
+        "tgv3d": wlsynth.tgv_3d(N=128),
+        "sphere3d": wlsynth.sphere_3d(),
+        "circle2d": wlsynth.circle_2d(),
+    }
+
+
+def kernel_bytes(name, ndim, cells, faces, esize, has_body, pcg_iters):
+    """Algorithmic bytes of one launch: each input field read once, each output written once.
+
+    cells = interior cells of the fine level, faces = padded points per component.
+    """
+    n = ndim
+    if name == "pcg_a":
+        # reads r, iD, L (n), and e_old except in the first sweep; writes e_new, q
+        fields = ((3 + n) + (pcg_iters - 1) * (4 + n)) / pcg_iters + 2
+        return fields * cells * esize
+    if name == "pcg_b":
+        return (5 + 2) * cells * esize          # reads iD, e, q, x, r; writes x, r
+    if name == "divres":
+        return (n + 1 + n + 1 + 2) * cells * esize   # u (n), p, L (n), iD; writes x, r
+    if name == "project":
+        return (n + n + 1 + n + 1) * cells * esize   # u (n), L (n), x; writes u (n), p
+    if name == "prolong":
+        return (1 / 2 ** n + n + 1 + 2 + 2) * cells * esize  # x_c, L, iD, x, r; writes x, r
+    if name == "restrict":
+        return (1 + 2 / 2 ** n) * cells * esize      # r; writes r_c, x_c
+    if name == "flux":
+        # average of predictor (u = u0: n) and corrector (u, u0: 2n); + V (n if body); writes f (n)
+        return (1.5 * n + (n if has_body else 0) + n) * faces * esize
+    if name == "bdim":
+        body = (n + n + n * n) if has_body else 0    # V, mu0, mu1
+        return (n + body + 0.5 * n + n) * faces * esize  # f, [body], u (corrector), writes u
+    if name == "cfl":
+        return n * cells * esize
+    return None
+
+
+def run_cpu_baseline(w_name):
+    """The FP64 oracle (numpy, one thread) on a bounded sample: one step of the same
+    case at 1/4 of the linear size (plate: 192 x 96 x 96 cells)."""
+    import wlsynth
+    import oracle
+    if w_name == "plate3d":
+        w = wlsynth.plate_3d(scale=4)
+    elif w_name == "tgv3d":
+        w = wlsynth.tgv_3d(N=64)
+    elif w_name == "sphere3d":
+        w = wlsynth.sphere_3d(n=(128, 64, 64), D=16.0, center=(32.0, 32.0, 32.0))
+    else:
+        w = wlsynth.circle_2d()
+    body = w.body if w.body.kind != "none" else None
+    s = oracle.Sim(w.n, w.U, w.nu, body, periodic=w.periodic_mask(), convective_exit=w.convective_exit,
+                   tol=w.tol)
+    s.set_velocity(wlsynth.initial_velocity(w))
+    t0 = time.perf_counter()
+    s.step()
+    dt = time.perf_counter() - t0
+    return {"value": dt / w.cells * 1e9, "unit": "ns/point/step", "cores": 1, "kind": "oracle",
+            "sample": "one FP64 step of %s (%d cells), numpy single thread, %.1f s" % (w.name, w.cells, dt)}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default="plate3d", choices=sorted(workloads().keys()))
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-profile", action="store_true", help="skip per-kernel event timing")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py: this build runs on one GPU only (the multi-GPU domain decomposition is a "
+              "design, not an implementation); use --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import wlsynth
+    from paper_2407_16032_amd import Simulation
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    w = workloads()[args.workload]
+    body = w.body if w.body.kind != "none" else None
+    print("[bench] workload %s (%d cells), building initial field" % (w.name, w.cells), file=sys.stderr,
+          flush=True)
+    sim = Simulation(w.n, w.U, w.nu, body, periodic=w.periodic_mask(), convective_exit=w.convective_exit,
+                     prec="f32", tol=w.tol, itmax=32, device="cuda:0")
+    sim.set_velocity(wlsynth.initial_velocity(w, seed=0))
+    for k in range(args.warmup):
+        sim.step()
+    print("[bench] warmup done (%d steps)" % args.warmup, file=sys.stderr, flush=True)
+
+    profile = not args.no_profile
+    if profile:
+        sim.profile(True)
+    torch.cuda.synchronize()
+    start = torch.cuda.Event(enable_timing=True)
+    stop = torch.cuda.Event(enable_timing=True)
+    stream = sim.stream
+    start.record(stream)
+    t0 = time.perf_counter()
+    vc = []
+    for k in range(args.steps):
+        st = sim.step()
+        vc.append(st["vcycles"][0] + st["vcycles"][1])
+    stop.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms = start.elapsed_time(stop)
+    ms_per_step = ms / args.steps
+    ns_pt = ms_per_step * 1e6 / w.cells
+    print("[bench] timed %d steps: %.3f ms/step (wall %.3f ms/step), %.3f ns/pt/step, %.2f V-cycles/step"
+          % (args.steps, ms_per_step, wall * 1e3 / args.steps, ns_pt, float(np.mean(vc))), file=sys.stderr,
+          flush=True)
+
+    roof = None
+    kernels = {}
+    if profile:
+        prof = sim.profile_read()
+        sim.profile(False)
+        cells = w.cells
+        faces = 1
+        for N in w.n:
+            faces *= N + 2
+        best = None
+        for name, (tms, cnt) in prof.items():
+            if cnt == 0:
+                continue
+            b = kernel_bytes(name, w.ndim, cells, faces, 4, body is not None, 6)
+            avg_ms = tms / cnt
+            ent = {"total_ms_per_step": tms / args.steps, "launches_per_step": cnt / args.steps,
+                   "avg_us": avg_ms * 1e3}
+            if b is not None:
+                ent["GBps"] = b / (avg_ms * 1e-3) / 1e9
+            kernels[name] = ent
+            if b is not None and (best is None or tms > best[1]):
+                best = (name, tms, b, avg_ms)
+        if best is not None:
+            name, tms, b, avg_ms = best
+            ach = b / (avg_ms * 1e-3) / 1e9
+            roof = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None, "kernel": name,
+                    "bytes_per_launch": b, "avg_launch_us": round(avg_ms * 1e3, 2)}
+        for name, ent in sorted(kernels.items(), key=lambda kv: -kv[1]["total_ms_per_step"]):
+            print("[bench]   %-9s %8.3f ms/step %6.1f launches/step %9.1f us avg %s" % (
+                name, ent["total_ms_per_step"], ent["launches_per_step"], ent["avg_us"],
+                ("%7.0f GB/s" % ent["GBps"]) if "GBps" in ent else ""), file=sys.stderr, flush=True)
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        print("[bench] timing the FP64 oracle on a bounded CPU sample", file=sys.stderr, flush=True)
+        cpu = run_cpu_baseline(args.workload)
+
+    out = {
+        "metric": "ns per grid point per time step (FP32 BDIM step)",
+        "value": round(ns_pt, 4),
+        "unit": "ns/point/step",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 3),
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": w.name, "cells": w.cells, "Re": round(w.U[0] * w.L / w.nu, 1) if w.nu else None,
+                   "mg_tol": w.tol, "moving_body": bool(body is not None and body.moving),
+                   "convective_exit": w.convective_exit, "parallelism": "single GPU"},
+        "vcycles_per_step": round(float(np.mean(vc)), 3),
+        "roofline": roof,
+        "kernels": kernels,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out))
+    sim.close()
+
+
+if __name__ == "__main__":
+    main()

@@ -194,6 +194,37 @@ wl_status wl_levels(wl_sim* sim, int* nlevels, int level, int64_t n_out[3]);
 wl_status wl_set_time(wl_sim* sim, double t, double dt_next);
 wl_status wl_get_time(wl_sim* sim, double* t, double* dt_next);
 
+/* Kernel groups timed by the profiler. Fine-level launches are timed per
+ * kernel; every launch on a coarser multigrid level counts as WL_K_COARSE. */
+enum {
+  WL_K_MEASURE = 0,  /* measure: d, n, V -> mu0, mu1, V */
+  WL_K_COEF = 1,     /* inverse diagonals and coefficient restriction */
+  WL_K_FLUX = 2,     /* convection-diffusion flux and f~ */
+  WL_K_BDIM = 3,     /* BDIM blend */
+  WL_K_BC = 4,       /* boundary conditions */
+  WL_K_EXIT = 5,     /* convective exit plane */
+  WL_K_DIVRES = 6,   /* divergence and initial residual */
+  WL_K_PCG_A = 7,    /* fine PCG pass A: search direction and A e */
+  WL_K_PCG_B = 8,    /* fine PCG pass B: x and r update */
+  WL_K_RESTRICT = 9, /* fine -> first coarse residual restriction */
+  WL_K_PROLONG = 10, /* first coarse -> fine prolongation and correction */
+  WL_K_PROJECT = 11, /* velocity update u -= L grad x */
+  WL_K_CFL = 12,     /* CFL outflux maximum */
+  WL_K_FORCES = 13,  /* force integrals */
+  WL_K_COARSE = 14,  /* all work on multigrid levels >= 1 */
+  WL_K_REDUCE = 15,  /* single-block finalisations of reductions */
+  WL_K_COUNT = 16
+};
+
+/* Per-kernel timing with HIP events recorded around each launch on the sim's
+ * stream.  enable = 1 creates the events (host objects) and zeroes the
+ * counters; 0 stops recording.  Timing adds one event pair per launch. */
+wl_status wl_profile(wl_sim* sim, int enable);
+
+/* Accumulated time (ms) and launch count of one kernel group since the last
+ * wl_profile(sim, 1); call after the timed work has completed. */
+wl_status wl_profile_read(wl_sim* sim, int kernel, double* total_ms, int64_t* launches);
+
 /* Thread-local message describing the last non-WL_OK status. */
 const char* wl_last_error(void);
 

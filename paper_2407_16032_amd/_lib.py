@@ -17,7 +17,9 @@ FIELDS = {"u": 0, "u0": 1, "f": 2, "V": 3, "mu0": 4, "mu1": 5, "p": 6, "x": 7, "
 # every symbol include/wlmi.h declares
 EXPORTS = ["wl_workspace_bytes", "wl_sim_create", "wl_sim_destroy", "wl_measure_body", "wl_step",
            "wl_apply_bc", "wl_conv_diff", "wl_project", "wl_poisson_solve", "wl_forces", "wl_field",
-           "wl_levels", "wl_set_time", "wl_get_time", "wl_last_error"]
+           "wl_levels", "wl_set_time", "wl_get_time", "wl_profile", "wl_profile_read", "wl_last_error"]
+KERNELS = ["measure", "coef", "flux", "bdim", "bc", "exit", "divres", "pcg_a", "pcg_b", "restrict",
+           "prolong", "project", "cfl", "forces", "coarse", "reduce"]
 
 
 class SimDesc(C.Structure):
@@ -89,6 +91,10 @@ def load(path: str = LIB_PATH):
     lib.wl_set_time.argtypes = [P, C.c_double, C.c_double]
     lib.wl_get_time.restype = C.c_int
     lib.wl_get_time.argtypes = [P, C.POINTER(C.c_double), C.POINTER(C.c_double)]
+    lib.wl_profile.restype = C.c_int
+    lib.wl_profile.argtypes = [P, C.c_int]
+    lib.wl_profile_read.restype = C.c_int
+    lib.wl_profile_read.argtypes = [P, C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_int64)]
     lib.wl_last_error.restype = C.c_char_p
     lib.wl_last_error.argtypes = []
     _lib = lib

@@ -550,7 +550,8 @@ __device__ __forceinline__ double residual_mean(const double* red, int nparts) {
 // active cells, rho_0 partial = sum (r - m) e.  k > 0: e_new = iD r + beta e_old with
 // beta = rho_k/rho_{k-1} (stops if rho_k == 0).  Then q = A e_new (0 on solid
 // cells) and the sigma partial = sum e_new q.
-template <typename T, int D>
+// FINE = 1 only makes the fine-level launches a separate kernel symbol in traces.
+template <typename T, int D, int FINE>
 __global__ void __launch_bounds__(kBlock) k_pcg_a(Grid3 g, Vec3<T> L, const T* iD, const T* r, const T* eo,
                                                   T* en, T* q, double* red, int k, int nparts,
                                                   double* part_sig, int* flag) {
@@ -598,7 +599,7 @@ __global__ void __launch_bounds__(kBlock) k_pcg_a(Grid3 g, Vec3<T> L, const T* i
 
 // PCG pass B (iteration k): alpha = rho_k/sigma_k; x += alpha e; r -= alpha q;
 // partials: rho_{k+1} (if want_rho) and max|r| (if want_max).  Stops if |sigma| < 1e-300.
-template <typename T, int D>
+template <typename T, int D, int FINE>
 __global__ void __launch_bounds__(kBlock) k_pcg_b(Grid3 g, const T* iD, const T* e, const T* q, T* x, T* r,
                                                   const double* red, int k, int nparts, double* part_rho_next,
                                                   double* part_max, int want_rho, int want_max, int* flag) {

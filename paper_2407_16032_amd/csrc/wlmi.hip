@@ -172,6 +172,74 @@ void host_motion(const wl_body_desc& b, double t, Motion& m) {
 }
 
 // ---------------------------------------------------------------------------
+// per-kernel timing with HIP events (host objects; enabled on demand)
+// ---------------------------------------------------------------------------
+struct Profiler {
+  static constexpr int kPairs = 1024;
+  bool on = false;
+  hipStream_t st = nullptr;
+  std::vector<hipEvent_t> pool;
+  std::vector<int> kid;
+  int cur = -1;
+  double ms[WL_K_COUNT] = {};
+  int64_t cnt[WL_K_COUNT] = {};
+
+  wl_status enable(hipStream_t s) {
+    st = s;
+    if (pool.empty()) {
+      pool.resize(2 * kPairs);
+      for (auto& e : pool)
+        if (hipEventCreate(&e) != hipSuccess) return fail(WL_ERR_HIP, "hipEventCreate failed");
+    }
+    kid.clear();
+    for (int k = 0; k < WL_K_COUNT; ++k) {
+      ms[k] = 0.0;
+      cnt[k] = 0;
+    }
+    on = true;
+    return WL_OK;
+  }
+  void begin(int k) {
+    if (!on) return;
+    if ((int)kid.size() == kPairs) flush();
+    (void)hipEventRecord(pool[2 * kid.size()], st);
+    cur = k;
+  }
+  void end() {
+    if (!on || cur < 0) return;
+    (void)hipEventRecord(pool[2 * kid.size() + 1], st);
+    kid.push_back(cur);
+    cur = -1;
+  }
+  // call only when the stream is idle (after a synchronisation)
+  void harvest() {
+    for (size_t i = 0; i < kid.size(); ++i) {
+      float t = 0.f;
+      if (hipEventElapsedTime(&t, pool[2 * i], pool[2 * i + 1]) == hipSuccess) {
+        ms[kid[i]] += t;
+        cnt[kid[i]] += 1;
+      }
+    }
+    kid.clear();
+  }
+  void flush() {
+    if (kid.empty()) return;
+    (void)hipStreamSynchronize(st);
+    harvest();
+  }
+  ~Profiler() {
+    for (auto& e : pool) (void)hipEventDestroy(e);
+  }
+};
+
+#define WL_TIMED(K, LAUNCH) \
+  do {                      \
+    prof.begin(K);          \
+    LAUNCH;                 \
+    prof.end();             \
+  } while (0)
+
+// ---------------------------------------------------------------------------
 // the simulation object
 // ---------------------------------------------------------------------------
 struct SimBase {
@@ -185,6 +253,20 @@ struct SimBase {
   virtual wl_status poisson(const void* rhs, void* x, double tol, int itmax, wl_solve_stats* st) = 0;
   virtual wl_status forces(double fp[3], double fv[3]) = 0;
   virtual wl_status field(int which, int level, void** ptr, int64_t shape[4], int64_t strides[4]) = 0;
+  virtual wl_status profile(int enable) {
+    if (enable) return prof.enable(stream);
+    prof.flush();
+    prof.on = false;
+    return WL_OK;
+  }
+  virtual wl_status profile_read(int k, double* ms, int64_t* n) {
+    if (k < 0 || k >= WL_K_COUNT) return fail(WL_ERR_INVALID_ARG, "kernel id out of range");
+    prof.flush();
+    if (ms) *ms = prof.ms[k];
+    if (n) *n = prof.cnt[k];
+    return WL_OK;
+  }
+  Profiler prof;
   wl_sim_desc desc;
   wl_body_desc bdesc;
   Plan plan;
@@ -330,12 +412,13 @@ struct Impl : SimBase {
   }
 
   wl_status coefficients() {
-    k_inv_diag<T, D><<<nb[0], kBlock, 0, stream>>>(g[0], v3(L[0]), iD[0]);
+    WL_TIMED(WL_K_COEF, (k_inv_diag<T, D><<<nb[0], kBlock, 0, stream>>>(g[0], v3(L[0]), iD[0])));
     for (int l = 1; l < nlev; ++l) {
       int m = 1;
       for (int a = 0; a < D; ++a) m *= g[l].n[a] + 1;
-      k_restrict_L<T, D><<<dim3(blocks_for(m), D), kBlock, 0, stream>>>(g[l - 1], g[l], v3(L[l - 1]), v3(L[l]));
-      k_inv_diag<T, D><<<nb[l], kBlock, 0, stream>>>(g[l], v3(L[l]), iD[l]);
+      WL_TIMED(WL_K_COEF, (k_restrict_L<T, D><<<dim3(blocks_for(m), D), kBlock, 0, stream>>>(
+                              g[l - 1], g[l], v3(L[l - 1]), v3(L[l]))));
+      WL_TIMED(WL_K_COEF, (k_inv_diag<T, D><<<nb[l], kBlock, 0, stream>>>(g[l], v3(L[l]), iD[l])));
     }
     WL_HIP(hipGetLastError());
     return WL_OK;
@@ -344,14 +427,15 @@ struct Impl : SimBase {
   wl_status measure(double tm) override {
     Motion m{};
     if (has_body) host_motion(bdesc, tm, m);
-    k_measure<T, D><<<dim3(nb_face, D), kBlock, 0, stream>>>(g[0], body, m, desc.eps, v3(mu0), v9(mu1), v3(V));
+    WL_TIMED(WL_K_MEASURE, (k_measure<T, D><<<dim3(nb_face, D), kBlock, 0, stream>>>(g[0], body, m, desc.eps,
+                                                                                   v3(mu0), v9(mu1), v3(V))));
     WL_HIP(hipGetLastError());
     return coefficients();
   }
 
   wl_status bc(T* const uu[3], bool use_exit) {
-    k_bc<T, D><<<dim3(plane_blocks, planes.count), kBlock, 0, stream>>>(
-        g[0], v3(uu), planes, desc.U[0], desc.U[1], desc.U[2], ebuf, scal, use_exit ? 1 : 0);
+    WL_TIMED(WL_K_BC, (k_bc<T, D><<<dim3(plane_blocks, planes.count), kBlock, 0, stream>>>(
+                          g[0], v3(uu), planes, desc.U[0], desc.U[1], desc.U[2], ebuf, scal, use_exit ? 1 : 0)));
     WL_HIP(hipGetLastError());
     return WL_OK;
   }
@@ -359,10 +443,11 @@ struct Impl : SimBase {
   wl_status apply_bc_cur() override { return bc(u[cur], false); }
 
   wl_status read_scalar_max(int s, int n, double* out) {
-    k_finalize_max<<<1, kBlock, 0, stream>>>(slot(s), n, scal + kScalRmax);
+    WL_TIMED(WL_K_REDUCE, (k_finalize_max<<<1, kBlock, 0, stream>>>(slot(s), n, scal + kScalRmax)));
     WL_HIP(hipGetLastError());
     WL_HIP(hipMemcpyAsync(host_pin, scal + kScalRmax, sizeof(double), hipMemcpyDeviceToHost, stream));
     WL_HIP(hipStreamSynchronize(stream));
+    prof.harvest();
     *out = host_pin[0];
     return WL_OK;
   }
@@ -372,22 +457,35 @@ struct Impl : SimBase {
     T* eo = e[l][0];
     T* en = e[l][1];
     for (int k = 0; k < K; ++k) {
-      k_pcg_a<T, D><<<nb[l], kBlock, 0, stream>>>(g[l], v3(L[l]), iD[l], r[l], eo, en, q[l], red, k, nb[l],
-                                                   slot(kSlotSig0 + k), flags + l);
-      k_pcg_b<T, D><<<nb[l], kBlock, 0, stream>>>(g[l], iD[l], en, q[l], x[l], r[l], red, k, nb[l],
-                                                   slot(kSlotRho0 + k + 1), slot(kSlotRmax), k < K - 1 ? 1 : 0,
-                                                   (fine && k == K - 1) ? 1 : 0, flags + l);
+      const int wr = k < K - 1 ? 1 : 0, wm = (fine && k == K - 1) ? 1 : 0;
+      if (l == 0) {
+        WL_TIMED(WL_K_PCG_A, (k_pcg_a<T, D, 1><<<nb[l], kBlock, 0, stream>>>(
+                                 g[l], v3(L[l]), iD[l], r[l], eo, en, q[l], red, k, nb[l], slot(kSlotSig0 + k),
+                                 flags + l)));
+        WL_TIMED(WL_K_PCG_B, (k_pcg_b<T, D, 1><<<nb[l], kBlock, 0, stream>>>(
+                                 g[l], iD[l], en, q[l], x[l], r[l], red, k, nb[l], slot(kSlotRho0 + k + 1),
+                                 slot(kSlotRmax), wr, wm, flags + l)));
+      } else {
+        WL_TIMED(WL_K_COARSE, (k_pcg_a<T, D, 0><<<nb[l], kBlock, 0, stream>>>(
+                                  g[l], v3(L[l]), iD[l], r[l], eo, en, q[l], red, k, nb[l], slot(kSlotSig0 + k),
+                                  flags + l)));
+        WL_TIMED(WL_K_COARSE, (k_pcg_b<T, D, 0><<<nb[l], kBlock, 0, stream>>>(
+                                  g[l], iD[l], en, q[l], x[l], r[l], red, k, nb[l], slot(kSlotRho0 + k + 1),
+                                  slot(kSlotRmax), wr, wm, flags + l)));
+      }
       std::swap(eo, en);
     }
   }
 
   void vcycle(int l) {
-    k_restrict<T, D><<<nb[l + 1], kBlock, 0, stream>>>(g[l], g[l + 1], r[l], iD[l + 1], r[l + 1], x[l + 1],
-                                                       red, flags + l + 1);
+    WL_TIMED(l == 0 ? WL_K_RESTRICT : WL_K_COARSE,
+             (k_restrict<T, D><<<nb[l + 1], kBlock, 0, stream>>>(g[l], g[l + 1], r[l], iD[l + 1], r[l + 1],
+                                                                 x[l + 1], red, flags + l + 1)));
     if (l + 2 < nlev) vcycle(l + 1);
     pcg(l + 1, false);
-    k_prolong<T, D><<<nb[l], kBlock, 0, stream>>>(g[l], g[l + 1], x[l + 1], v3(L[l]), iD[l], x[l], r[l],
-                                                  red, flags + l);
+    WL_TIMED(l == 0 ? WL_K_PROLONG : WL_K_COARSE,
+             (k_prolong<T, D><<<nb[l], kBlock, 0, stream>>>(g[l], g[l + 1], x[l + 1], v3(L[l]), iD[l], x[l],
+                                                            r[l], red, flags + l)));
   }
 
   // initial residual already in r[0] / rmax slot
@@ -399,7 +497,7 @@ struct Impl : SimBase {
     int n = 0;
     while (res >= tol && n < itmax) {
       if (nlev > 1) vcycle(0);
-      else k_mean0<T, D><<<nb[0], kBlock, 0, stream>>>(g[0], iD[0], r[0], red, flags);
+      else WL_TIMED(WL_K_DIVRES, (k_mean0<T, D><<<nb[0], kBlock, 0, stream>>>(g[0], iD[0], r[0], red, flags)));
       pcg(0, true);
       ++n;
       s = read_scalar_max(kSlotRmax, nb[0], &res);
@@ -418,12 +516,13 @@ struct Impl : SimBase {
 
   wl_status project(T* const uu[3], double w, wl_solve_stats* st) {
     const T wdt = T(w * dt);
-    k_div_res<T, D><<<nb[0], kBlock, 0, stream>>>(g[0], v3(uu), nullptr, p, wdt, v3(L[0]), iD[0], x[0], r[0],
-                                                  slot(kSlotRmax), red, flags);
+    WL_TIMED(WL_K_DIVRES, (k_div_res<T, D><<<nb[0], kBlock, 0, stream>>>(g[0], v3(uu), nullptr, p, wdt, v3(L[0]),
+                                                                          iD[0], x[0], r[0], slot(kSlotRmax), red,
+                                                                          flags)));
     WL_HIP(hipGetLastError());
     wl_status s = mg_loop(desc.mg_tol, desc.mg_itmax, st);
     if (s != WL_OK) return s;
-    k_project<T, D><<<nb[0], kBlock, 0, stream>>>(g[0], v3(uu), v3(L[0]), x[0], p, wdt);
+    WL_TIMED(WL_K_PROJECT, (k_project<T, D><<<nb[0], kBlock, 0, stream>>>(g[0], v3(uu), v3(L[0]), x[0], p, wdt)));
     WL_HIP(hipGetLastError());
     return WL_OK;
   }
@@ -464,15 +563,18 @@ struct Impl : SimBase {
     T* const* B = u[1 - cur];
     const int hb = has_body ? 1 : 0;
     // predictor
-    k_flux<T, D><<<dim3(nb_face, D), kBlock, 0, stream>>>(g[0], v3(A), v3(A), v3(V), v3(ft), T(dt), T(desc.nu), hb, 0);
-    k_bdim<T, D, 0><<<dim3(nb_face, D), kBlock, 0, stream>>>(g[0], v3(ft), v3(V), v3(mu0), v9(mu1), v3(B), hb);
+    WL_TIMED(WL_K_FLUX, (k_flux<T, D><<<dim3(nb_face, D), kBlock, 0, stream>>>(g[0], v3(A), v3(A), v3(V), v3(ft),
+                                                                              T(dt), T(desc.nu), hb, 0)));
+    WL_TIMED(WL_K_BDIM, (k_bdim<T, D, 0><<<dim3(nb_face, D), kBlock, 0, stream>>>(g[0], v3(ft), v3(V), v3(mu0),
+                                                                                 v9(mu1), v3(B), hb)));
     const bool ex = desc.convective_exit != 0;
     if (ex) {
       const int m = g[0].n[1] * (D == 3 ? g[0].n[2] : 1);
       const int be = blocks_for(m);
-      k_exit_raw<T, D><<<be, kBlock, 0, stream>>>(g[0], A[0], ebuf, T(dt * desc.U[0]), slot(kSlotExit));
+      WL_TIMED(WL_K_EXIT, (k_exit_raw<T, D><<<be, kBlock, 0, stream>>>(g[0], A[0], ebuf, T(dt * desc.U[0]),
+                                                                      slot(kSlotExit))));
       const double inlet = double(m) * double(T(desc.U[0]));
-      k_exit_shift<<<1, kBlock, 0, stream>>>(slot(kSlotExit), be, inlet, double(m), scal);
+      WL_TIMED(WL_K_EXIT, (k_exit_shift<<<1, kBlock, 0, stream>>>(slot(kSlotExit), be, inlet, double(m), scal)));
       exit_valid = true;
     }
     WL_HIP(hipGetLastError());
@@ -481,8 +583,10 @@ struct Impl : SimBase {
     if ((s = project(B, 1.0, &s1)) != WL_OK) return s;
     if ((s = bc(B, ex)) != WL_OK) return s;
     // corrector
-    k_flux<T, D><<<dim3(nb_face, D), kBlock, 0, stream>>>(g[0], v3(B), v3(A), v3(V), v3(ft), T(dt), T(desc.nu), hb, 0);
-    k_bdim<T, D, 1><<<dim3(nb_face, D), kBlock, 0, stream>>>(g[0], v3(ft), v3(V), v3(mu0), v9(mu1), v3(B), hb);
+    WL_TIMED(WL_K_FLUX, (k_flux<T, D><<<dim3(nb_face, D), kBlock, 0, stream>>>(g[0], v3(B), v3(A), v3(V), v3(ft),
+                                                                              T(dt), T(desc.nu), hb, 0)));
+    WL_TIMED(WL_K_BDIM, (k_bdim<T, D, 1><<<dim3(nb_face, D), kBlock, 0, stream>>>(g[0], v3(ft), v3(V), v3(mu0),
+                                                                                 v9(mu1), v3(B), hb)));
     WL_HIP(hipGetLastError());
     if ((s = bc(B, ex)) != WL_OK) return s;
     if ((s = project(B, 0.5, &s2)) != WL_OK) return s;
@@ -491,7 +595,7 @@ struct Impl : SimBase {
     const double dt_used = dt;
     t += dt;
     // CFL
-    k_cfl<T, D><<<nb[0], kBlock, 0, stream>>>(g[0], v3(u[cur]), slot(kSlotCfl));
+    WL_TIMED(WL_K_CFL, (k_cfl<T, D><<<nb[0], kBlock, 0, stream>>>(g[0], v3(u[cur]), slot(kSlotCfl))));
     WL_HIP(hipGetLastError());
     double smax;
     if ((s = read_scalar_max(kSlotCfl, nb[0], &smax)) != WL_OK) return s;
@@ -516,11 +620,13 @@ struct Impl : SimBase {
     if (!has_body) return WL_OK;
     Motion m{};
     host_motion(bdesc, t, m);
-    k_forces<T, D><<<nb[0], kBlock, 0, stream>>>(g[0], body, m, desc.eps, desc.nu, v3(u[cur]), p, red);
+    WL_TIMED(WL_K_FORCES, (k_forces<T, D><<<nb[0], kBlock, 0, stream>>>(g[0], body, m, desc.eps, desc.nu,
+                                                                         v3(u[cur]), p, red)));
     WL_HIP(hipGetLastError());
     std::vector<double> h((size_t)6 * kMaxBlocks);
     WL_HIP(hipMemcpyAsync(h.data(), slot(kSlotForce), h.size() * sizeof(double), hipMemcpyDeviceToHost, stream));
     WL_HIP(hipStreamSynchronize(stream));
+    prof.harvest();
     for (int a = 0; a < 3; ++a) {
       double sp = 0, sv = 0;
       for (int b = 0; b < nb[0]; ++b) {
@@ -746,6 +852,16 @@ wl_status wl_get_time(wl_sim* sim, double* t, double* dt_next) {
   if (t) *t = sim->impl->t;
   if (dt_next) *dt_next = sim->impl->dt;
   return WL_OK;
+}
+
+wl_status wl_profile(wl_sim* sim, int enable) {
+  WL_SIM_CHECK(sim);
+  return sim->impl->profile(enable);
+}
+
+wl_status wl_profile_read(wl_sim* sim, int kernel, double* total_ms, int64_t* launches) {
+  WL_SIM_CHECK(sim);
+  return sim->impl->profile_read(kernel, total_ms, launches);
 }
 
 const char* wl_last_error(void) { return g_err.c_str(); }

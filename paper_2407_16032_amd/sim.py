@@ -164,6 +164,18 @@ class Simulation:
             out.append(tuple(nn)[:self.ndim])
         return out
 
+    def profile(self, enable: bool = True):
+        L.check(self.lib.wl_profile(self._h, 1 if enable else 0), "wl_profile")
+
+    def profile_read(self) -> dict:
+        out = {}
+        for k, name in enumerate(L.KERNELS):
+            ms = C.c_double()
+            n = C.c_int64()
+            L.check(self.lib.wl_profile_read(self._h, k, C.byref(ms), C.byref(n)), "wl_profile_read")
+            out[name] = (ms.value, n.value)
+        return out
+
     def set_time(self, t: float, dt_next: float):
         L.check(self.lib.wl_set_time(self._h, float(t), float(dt_next)), "wl_set_time")
 
