@@ -68,11 +68,11 @@ def kernel_bytes(name, ndim, cells, faces, esize, has_body, pcg_iters):
 
 def run_cpu_baseline(w_name):
     """The FP64 oracle (numpy, one thread) on a bounded sample: one step of the same
-    case at 1/4 of the linear size (plate: 192 x 96 x 96 cells)."""
+    case at 1/3 of the linear size (plate: 256 x 128 x 128 cells)."""
     import wlsynth
     import oracle
     if w_name == "plate3d":
-        w = wlsynth.plate_3d(scale=4)
+        w = wlsynth.plate_3d(scale=3)
     elif w_name == "tgv3d":
         w = wlsynth.tgv_3d(N=64)
     elif w_name == "sphere3d":
