@@ -6,7 +6,9 @@
 namespace wl {
 
 constexpr int kBlock = 256;       // threads per block (4 waves of 64)
-constexpr int kMaxBlocks = 2048;  // grid-stride launches never exceed this (partial-sum slots)
+constexpr int kMaxBlocks = 8192;  // no launch that writes partial sums exceeds this
+constexpr int kGridStride = 2048; // grid-stride launches use at most this many blocks
+constexpr int kFrontPad = 15;     // elements before every field, so interior rows start 64-B aligned
 constexpr int kMaxLevels = 16;
 constexpr int kMaxPcg = 15;
 
@@ -64,10 +66,12 @@ __device__ __forceinline__ double wave_max(double v) {
   return v;
 }
 
-// Block-wide reductions; every thread receives the result.  Fixed order:
-// wave tree, then waves 0..3 in order, so results are bitwise reproducible.
+// Block-wide reductions over NT threads (1-D block); every thread receives the
+// result.  Fixed order: wave tree, then the waves in order, so results are
+// bitwise reproducible run to run.
+template <int NT = kBlock>
 __device__ __forceinline__ double block_sum(double v) {
-  __shared__ double sh[kBlock / 64];
+  __shared__ double sh[NT / 64];
   v = wave_sum(v);
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   __syncthreads();
@@ -75,12 +79,13 @@ __device__ __forceinline__ double block_sum(double v) {
   __syncthreads();
   double r = sh[0];
 #pragma unroll
-  for (int i = 1; i < kBlock / 64; ++i) r += sh[i];
+  for (int i = 1; i < NT / 64; ++i) r += sh[i];
   __syncthreads();
   return r;
 }
+template <int NT = kBlock>
 __device__ __forceinline__ double block_max(double v) {
-  __shared__ double shm[kBlock / 64];
+  __shared__ double shm[NT / 64];
   v = wave_max(v);
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   __syncthreads();
@@ -88,22 +93,37 @@ __device__ __forceinline__ double block_max(double v) {
   __syncthreads();
   double r = shm[0];
 #pragma unroll
-  for (int i = 1; i < kBlock / 64; ++i) r = fmax(r, shm[i]);
+  for (int i = 1; i < NT / 64; ++i) r = fmax(r, shm[i]);
   __syncthreads();
   return r;
 }
 
 // Sum / max of the n per-block partials a producer kernel wrote.
+template <int NT = kBlock>
 __device__ __forceinline__ double total_of(const double* part, int n) {
   double v = 0.0;
-  for (int i = threadIdx.x; i < n; i += kBlock) v += part[i];
-  return block_sum(v);
+  for (int i = threadIdx.x; i < n; i += NT) v += part[i];
+  return block_sum<NT>(v);
 }
+template <int NT = kBlock>
 __device__ __forceinline__ double max_of(const double* part, int n) {
   double v = 0.0;
-  for (int i = threadIdx.x; i < n; i += kBlock) v = fmax(v, part[i]);
-  return block_max(v);
+  for (int i = threadIdx.x; i < n; i += NT) v = fmax(v, part[i]);
+  return block_max<NT>(v);
 }
+
+// Number of partials each consumed slot holds (the producer's grid size).
+struct RedN {
+  int mean;      // kSlotSumR / kSlotCnt
+  int rho;       // rho_k
+  int rho_prev;  // rho_{k-1}
+  int sig;       // sigma_k
+};
+
+// 16-byte vector of T for the flat (pointwise) kernels
+template <typename T> struct Vec16;
+template <> struct Vec16<float> { typedef float4 type; static constexpr int W = 4; };
+template <> struct Vec16<double> { typedef double2 type; static constexpr int W = 2; };
 
 template <typename T>
 __device__ __forceinline__ T median3(T a, T b, T c) {

@@ -8,6 +8,9 @@
 
 namespace wl {
 
+// tile of the z-marching stencil kernels: 64 x 8 columns, 32 planes deep
+constexpr int kTX = 64, kTY = 8, kTZ = 32, kTileThreads = kTX * kTY;
+
 // ---------------------------------------------------------------------------
 // body description and rigid motion (the paper's AutoBody, analytic subset)
 // ---------------------------------------------------------------------------
@@ -94,14 +97,17 @@ constexpr double kMu0Cut = 1e-6;  // faces with mu0 below this are solid
 
 // measure!: mu0 (= fine Poisson L, 0 on non-periodic boundary faces), mu1 = mu1(d) n, V.
 // blockIdx.y = component.
+// Points outside the box [lo, hi] (padded coordinates) keep their previous values:
+// the caller guarantees they lie outside the body's reach at both the previous and
+// the current measure time.
 template <typename T, int D>
 __global__ void __launch_bounds__(kBlock) k_measure(Grid3 g, BodyP b, Motion m, double eps,
-                                                    Vec3<T> mu0, Vec9<T> mu1, Vec3<T> V) {
+                                                    Vec3<T> mu0, Vec9<T> mu1, Vec3<T> V, int3 lo, int3 hi) {
   const int c = blockIdx.y;
-  const int P0 = g.n[0] + 2, P1 = g.n[1] + 2, P2 = (D == 3) ? g.n[2] + 2 : 1;
+  const int P0 = hi.x - lo.x + 1, P1 = hi.y - lo.y + 1, P2 = (D == 3) ? hi.z - lo.z + 1 : 1;
   const int total = P0 * P1 * P2;
   for (int lin = blockIdx.x * kBlock + threadIdx.x; lin < total; lin += gridDim.x * kBlock) {
-    const int I0 = lin % P0, t = lin / P0, I1 = t % P1, I2 = t / P1;
+    const int I0 = lo.x + lin % P0, t = lin / P0, I1 = lo.y + t % P1, I2 = (D == 3) ? lo.z + t / P1 : 0;
     const int I[3] = {I0, I1, I2};
     const int idx = I0 + I1 * g.s[1] + I2 * g.s[2];
     double m0 = 1.0, m1 = 0.0, vb[3] = {0.0, 0.0, 0.0}, nn[3] = {0.0, 0.0, 0.0}, d = 1e300;
@@ -223,6 +229,30 @@ __device__ __forceinline__ T resid_c(const Grid3& g, const Vec3<T>& u, int c, co
   return acc;
 }
 
+// Same flux with plain offsets, valid when every +-2 stencil point is interior.
+template <typename T, int D>
+__device__ __forceinline__ T phi_fast(const Vec3<T>& u, int c, int j, int id, int sc, int sj, T nu) {
+  const T a = T(0.5) * (u.c[j][id] + u.c[j][id - sc]);
+  const T uc = u.c[c][id];
+  const T m1 = u.c[c][id - sj];
+  const bool up = a >= T(0);
+  const T far = up ? u.c[c][id - 2 * sj] : u.c[c][id + sj];
+  const T Q = up ? quick_lim(far, m1, uc) : quick_lim(far, uc, m1);
+  return a * Q - nu * (uc - m1);
+}
+
+template <typename T, int D>
+__device__ __forceinline__ T resid_fast(const Grid3& g, const Vec3<T>& u, int c, int id, T nu) {
+  const int sc = g.s[c];
+  T acc = T(0);
+#pragma unroll
+  for (int j = 0; j < D; ++j) {
+    const int sj = g.s[j];
+    acc = acc + (phi_fast<T, D>(u, c, j, id, sc, sj, nu) - phi_fast<T, D>(u, c, j, id + sj, sc, sj, nu));
+  }
+  return acc;
+}
+
 // f~_c = u0_c + dt R_c(u) - V_c on every padded face (R = 0 off the unknown faces).
 // mode 0: f~ (with body velocity if has_body); mode 1: f = R only.  blockIdx.y = c.
 template <typename T, int D>
@@ -240,7 +270,13 @@ __global__ void __launch_bounds__(kBlock) k_flux(Grid3 g, Vec3<T> u, Vec3<T> u0,
       const int lo = (a == c && !g.per[a]) ? 2 : 1;
       unknown = unknown && I[a] >= lo && I[a] <= g.n[a];
     }
-    T R = unknown ? resid_c<T, D>(g, u, c, I, nu) : T(0);
+    T R = T(0);
+    if (unknown) {
+      // interior fast path: the +-2 stencil needs no wrap and every far point is valid
+      bool fast = true;
+      for (int a = 0; a < D; ++a) fast = fast && I[a] >= 3 && I[a] <= g.n[a] - 2;
+      R = fast ? resid_fast<T, D>(g, u, c, idx, nu) : resid_c<T, D>(g, u, c, I, nu);
+    }
     if (mode == 1) {
       f.c[c][idx] = R;
     } else {
@@ -264,7 +300,16 @@ __global__ void __launch_bounds__(kBlock) k_bdim(Grid3 g, Vec3<T> f, Vec3<T> V, 
     const int I[3] = {I0, I1, I2};
     const int idx = lin3<T, D>(g, I0, I1, I2);
     T acc;
-    if (has_body) {
+    bool fast = true;
+    for (int a = 0; a < D; ++a) fast = fast && I[a] >= 2 && I[a] <= g.n[a] - 1;
+    if (has_body && fast) {
+      acc = V.c[c][idx] + mu0.c[c][idx] * f.c[c][idx];
+#pragma unroll
+      for (int j = 0; j < D; ++j) {
+        const int sj = g.s[j];
+        acc = acc + mu1.c[c * D + j][idx] * (T(0.5) * (f.c[c][idx + sj] - f.c[c][idx - sj]));
+      }
+    } else if (has_body) {
       acc = V.c[c][idx] + mu0.c[c][idx] * f.c[c][idx];
       for (int j = 0; j < D; ++j) {
         int Jp[3] = {I0, I1, I2}, Jm[3] = {I0, I1, I2};
@@ -539,34 +584,103 @@ __global__ void __launch_bounds__(kBlock) k_prolong(Grid3 f, Grid3 c, const T* x
   put_mean_partials(sr, cnt, red);
 }
 
+// Prolongation + correction, tiled z-marching form for large 3-D levels (same tile
+// order as the tiled PCG pass A): e = x_c[parent]; x += e; r -= A e; mean partials.
+template <typename T>
+__global__ void __launch_bounds__(kTileThreads) k_prolong_tile(Grid3 f, Grid3 c, const T* xc, Vec3<T> L, const T* iD,
+                                                      T* xf, T* rf, double* red, int* flag, int tiles_x,
+                                                      int tiles_y, int ntiles) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) *flag = 0;
+  const int b = blockIdx.x;
+  const int full = (ntiles / 8) * 8;
+  const int tile = (b < full) ? (b % 8) * (ntiles / 8) + b / 8 : b;
+  const int txi = tile % tiles_x, rem = tile / tiles_x, tyi = rem % tiles_y, tzi = rem / tiles_y;
+  const int x0 = 1 + txi * kTX, y0 = 1 + tyi * kTY, z0 = 1 + tzi * kTZ;
+  const int z1 = min(z0 + kTZ, f.n[2] + 1);
+  const int tx = threadIdx.x % kTX, ty = threadIdx.x / kTX;
+  const int i = x0 + tx, j = y0 + ty;
+  const bool own = i <= f.n[0] && j <= f.n[1];
+  double sr = 0.0, cnt = 0.0;
+  if (own) {
+    const int s1 = f.s[1], s2 = f.s[2], cs1 = c.s[1], cs2 = c.s[2];
+    const int col = i + j * s1;
+    const int pi = (i + 1) >> 1, pj = (j + 1) >> 1;
+    const int pxp = (wrapc(i + 1, 0, f) + 1) >> 1, pxm = (wrapc(i - 1, 0, f) + 1) >> 1;
+    const int pyp = (wrapc(j + 1, 1, f) + 1) >> 1, pym = (wrapc(j - 1, 1, f) + 1) >> 1;
+    const int cc = pi + pj * cs1, cxp = pxp + pj * cs1, cxm = pxm + pj * cs1, cyp = pi + pyp * cs1,
+              cym = pi + pym * cs1;
+    const int opx = (f.per[0] && i == f.n[0]) ? -(f.n[0] - 1) : 1;
+    const int opy = (f.per[1] && j == f.n[1]) ? -(f.n[1] - 1) * s1 : s1;
+    T L2c = L.c[2][col + z0 * s2];
+    for (int z = z0; z < z1; ++z) {
+      const int id = col + z * s2;
+      const int zp = wrapc(z + 1, 2, f), zm = wrapc(z - 1, 2, f);
+      const int pz = ((z + 1) >> 1) * cs2, pzp = ((zp + 1) >> 1) * cs2, pzm = ((zm + 1) >> 1) * cs2;
+      const T L2p = L.c[2][col + zp * s2];
+      const T ec = xc[cc + pz];
+      xf[id] = xf[id] + ec;
+      const T di = iD[id];
+      if (di != T(0)) {
+        T Ae = T(0);
+        Ae = Ae + L.c[0][id + opx] * (xc[cxp + pz] - ec) - L.c[0][id] * (ec - xc[cxm + pz]);
+        Ae = Ae + L.c[1][id + opy] * (xc[cyp + pz] - ec) - L.c[1][id] * (ec - xc[cym + pz]);
+        Ae = Ae + L2p * (xc[cc + pzp] - ec) - L2c * (ec - xc[cc + pzm]);
+        const T rr = rf[id] - Ae;
+        rf[id] = rr;
+        sr += double(rr);
+        cnt += 1.0;
+      }
+      L2c = L2p;
+    }
+  }
+  sr = block_sum<kTileThreads>(sr);
+  cnt = block_sum<kTileThreads>(cnt);
+  if (threadIdx.x == 0) {
+    red[(size_t)kSlotSumR * kMaxBlocks + blockIdx.x] = sr;
+    red[(size_t)kSlotCnt * kMaxBlocks + blockIdx.x] = cnt;
+  }
+}
+
 // mean of the residual over the active cells, from the producer's partials
+template <int NT = kBlock>
 __device__ __forceinline__ double residual_mean(const double* red, int nparts) {
-  const double cnt = total_of(red + (size_t)kSlotCnt * kMaxBlocks, nparts);
-  const double sr = total_of(red + (size_t)kSlotSumR * kMaxBlocks, nparts);
+  const double cnt = total_of<NT>(red + (size_t)kSlotCnt * kMaxBlocks, nparts);
+  const double sr = total_of<NT>(red + (size_t)kSlotSumR * kMaxBlocks, nparts);
   return cnt > 0.0 ? sr / cnt : 0.0;
 }
 
-// PCG pass A (iteration k).  k = 0: e = iD (r - m) with m the residual mean over
-// active cells, rho_0 partial = sum (r - m) e.  k > 0: e_new = iD r + beta e_old with
-// beta = rho_k/rho_{k-1} (stops if rho_k == 0).  Then q = A e_new (0 on solid
-// cells) and the sigma partial = sum e_new q.
+// Scalars of PCG pass A at sweep k: beta (k > 0) or the residual mean (k = 0).
+// Returns false (and sets the stop flag) when rho_k == 0 for k > 0.
+template <typename T, int NT>
+__device__ __forceinline__ bool pcg_a_scalars(const double* red, int k, const RedN& rn, int* flag, T& beta,
+                                              T& mean) {
+  beta = T(0);
+  mean = T(0);
+  if (k > 0) {
+    const double rho = total_of<NT>(red + (size_t)(kSlotRho0 + k) * kMaxBlocks, rn.rho);
+    if (rho == 0.0) {
+      if (blockIdx.x == 0 && threadIdx.x == 0) *flag = 1;
+      return false;
+    }
+    beta = T(rho / total_of<NT>(red + (size_t)(kSlotRho0 + k - 1) * kMaxBlocks, rn.rho_prev));
+  } else {
+    mean = T(residual_mean<NT>(red, rn.mean));
+  }
+  return true;
+}
+
+// PCG pass A (sweep k), generic grid-stride form.  k = 0: e = iD (r - m) with m the
+// residual mean over active cells, rho_0 partial = sum (r - m) e.  k > 0:
+// e_new = iD r + beta e_old, beta = rho_k/rho_{k-1} (stops if rho_k == 0).  Then
+// q = A e_new (0 on solid cells) and the sigma partial = sum e_new q.
 // FINE = 1 only makes the fine-level launches a separate kernel symbol in traces.
 template <typename T, int D, int FINE>
 __global__ void __launch_bounds__(kBlock) k_pcg_a(Grid3 g, Vec3<T> L, const T* iD, const T* r, const T* eo,
-                                                  T* en, T* q, double* red, int k, int nparts,
+                                                  T* en, T* q, double* red, int k, RedN rn,
                                                   double* part_sig, int* flag) {
   if (*flag) return;
-  T beta = T(0), mean = T(0);
-  if (k > 0) {
-    const double rho = total_of(red + (size_t)(kSlotRho0 + k) * kMaxBlocks, nparts);
-    if (rho == 0.0) {
-      if (blockIdx.x == 0 && threadIdx.x == 0) *flag = 1;
-      return;
-    }
-    beta = T(rho / total_of(red + (size_t)(kSlotRho0 + k - 1) * kMaxBlocks, nparts));
-  } else {
-    mean = T(residual_mean(red, nparts));
-  }
+  T beta, mean;
+  if (!pcg_a_scalars<T, kBlock>(red, k, rn, flag, beta, mean)) return;
   const int total = g.n[0] * g.n[1] * ((D == 3) ? g.n[2] : 1);
   double sig = 0.0, rho0 = 0.0;
   for (int lin = blockIdx.x * kBlock + threadIdx.x; lin < total; lin += gridDim.x * kBlock) {
@@ -597,41 +711,188 @@ __global__ void __launch_bounds__(kBlock) k_pcg_a(Grid3 g, Vec3<T> L, const T* i
   }
 }
 
-// PCG pass B (iteration k): alpha = rho_k/sigma_k; x += alpha e; r -= alpha q;
-// partials: rho_{k+1} (if want_rho) and max|r| (if want_max).  Stops if |sigma| < 1e-300.
-template <typename T, int D, int FINE>
-__global__ void __launch_bounds__(kBlock) k_pcg_b(Grid3 g, const T* iD, const T* e, const T* q, T* x, T* r,
-                                                  const double* red, int k, int nparts, double* part_rho_next,
+// PCG pass A, tiled 2.5-D form for large 3-D levels: one block per (64 x 8 x kTZ)
+// tile, marching in z.  The search direction of the current plane (tile + 1-cell
+// halo) lives in LDS, the planes z-1 and z+1 of the block's own columns in
+// registers, so every input field is read from memory once per cell.
+
+template <typename T, int FINE>
+__global__ void __launch_bounds__(kTileThreads) k_pcg_a_tile(Grid3 g, Vec3<T> L, const T* iD, const T* r,
+                                                             const T* eo, T* en, T* q, double* red, int k,
+                                                             RedN rn, double* part_sig, int* flag, int tiles_x,
+                                                             int tiles_y, int ntiles) {
+  if (*flag) return;
+  T beta, mean;
+  if (!pcg_a_scalars<T, kTileThreads>(red, k, rn, flag, beta, mean)) return;
+  __shared__ T sE[kTY + 2][kTX + 2];
+  // XCD-aware tile order: consecutive hardware blocks round-robin over the 8 XCDs,
+  // so give each XCD a contiguous range of tiles (shared halos stay in its L2).
+  const int b = blockIdx.x;
+  const int full = (ntiles / 8) * 8;
+  const int tile = (b < full) ? (b % 8) * (ntiles / 8) + b / 8 : b;
+  const int txi = tile % tiles_x, rem = tile / tiles_x, tyi = rem % tiles_y, tzi = rem / tiles_y;
+  const int x0 = 1 + txi * kTX, y0 = 1 + tyi * kTY, z0 = 1 + tzi * kTZ;
+  const int z1 = min(z0 + kTZ, g.n[2] + 1);
+  const int tx = threadIdx.x % kTX, ty = threadIdx.x / kTX;
+  const int n0 = g.n[0], n1 = g.n[1], n2 = g.n[2];
+  const int s1 = g.s[1], s2 = g.s[2];
+  // own column
+  const int i = x0 + tx, j = y0 + ty;
+  const bool inb = i <= n0 + 1 && j <= n1 + 1;
+  const bool own = i <= n0 && j <= n1;
+  const int wi = wrapc(i, 0, g), wj = wrapc(j, 1, g);
+  const int col = wi + wj * s1;
+  // halo cell of this thread (148 ring cells)
+  const int t = threadIdx.x;
+  int hx = 0, hy = 0, sx = 0, sy = 0;
+  bool hb = false;
+  if (t < 2 * (kTX + 2) + 2 * kTY) {
+    if (t < kTX + 2) { sx = t; sy = 0; }
+    else if (t < 2 * (kTX + 2)) { sx = t - (kTX + 2); sy = kTY + 1; }
+    else if (t < 2 * (kTX + 2) + kTY) { sx = 0; sy = 1 + t - 2 * (kTX + 2); }
+    else { sx = kTX + 1; sy = 1 + t - 2 * (kTX + 2) - kTY; }
+    const int rx = x0 - 1 + sx, ry = y0 - 1 + sy;
+    hb = rx >= 0 && rx <= n0 + 1 && ry >= 0 && ry <= n1 + 1;
+    hx = wrapc(rx, 0, g);
+    hy = wrapc(ry, 1, g);
+  }
+  const int hcol = hx + hy * s1;
+  auto eps_at = [&](int id) -> T {
+    return (k > 0) ? iD[id] * r[id] + beta * eo[id] : iD[id] * (r[id] - mean);
+  };
+  // x/y neighbour offsets of the own column (periodic wrap)
+  const int opx = (g.per[0] && i == n0) ? -(n0 - 1) : 1;
+  const int opy = (g.per[1] && j == n1) ? -(n1 - 1) * s1 : s1;
+  // prologue: planes z0-1 and z0
+  T em = T(0), ec = T(0), rc = T(0), dc = T(0), L2c = T(0);
+  if (inb) {
+    const int zm = wrapc(z0 - 1, 2, g);
+    em = eps_at(col + zm * s2);
+    const int id = col + z0 * s2;
+    dc = iD[id];
+    rc = r[id];
+    ec = (k > 0) ? dc * rc + beta * eo[id] : dc * (rc - mean);
+    L2c = L.c[2][id];
+  }
+  double sig = 0.0, rho0 = 0.0;
+  for (int z = z0; z < z1; ++z) {
+    const int zp = wrapc(z + 1, 2, g);
+    T ep = T(0), dp = T(0), rp = T(0), L2p = T(0);
+    if (inb) {
+      const int id = col + zp * s2;
+      dp = iD[id];
+      rp = r[id];
+      ep = (k > 0) ? dp * rp + beta * eo[id] : dp * (rp - mean);
+      L2p = L.c[2][id];
+    }
+    sE[ty + 1][tx + 1] = ec;
+    if (t < 2 * (kTX + 2) + 2 * kTY) sE[sy][sx] = hb ? eps_at(hcol + z * s2) : T(0);
+    __syncthreads();
+    if (own) {
+      const int id = col + z * s2;
+      T qq = T(0);
+      if (dc != T(0)) {
+        const T xm = sE[ty + 1][tx], xp = sE[ty + 1][tx + 2];
+        const T ym = sE[ty][tx + 1], yp = sE[ty + 2][tx + 1];
+        qq = qq + L.c[0][id + opx] * (xp - ec) - L.c[0][id] * (ec - xm);
+        qq = qq + L.c[1][id + opy] * (yp - ec) - L.c[1][id] * (ec - ym);
+        qq = qq + L2p * (ep - ec) - L2c * (ec - em);
+        if (k == 0) rho0 += double(rc - mean) * double(ec);
+      }
+      en[id] = ec;
+      q[id] = qq;
+      sig += double(ec) * double(qq);
+    }
+    __syncthreads();
+    em = ec;
+    ec = ep;
+    dc = dp;
+    rc = rp;
+    L2c = L2p;
+  }
+  sig = block_sum<kTileThreads>(sig);
+  if (threadIdx.x == 0) part_sig[blockIdx.x] = sig;
+  if (k == 0) {
+    rho0 = block_sum<kTileThreads>(rho0);
+    if (threadIdx.x == 0) red[(size_t)kSlotRho0 * kMaxBlocks + blockIdx.x] = rho0;
+  }
+}
+
+// PCG pass B (sweep k), flat and vectorised over the whole padded array (ghost and
+// padding cells have iD = e = q = 0, so they are left unchanged):
+// alpha = rho_k/sigma_k; x += alpha e; r -= alpha q; partials rho_{k+1}
+// (want_rho) and max|r| (want_max).  Sweep 0 also removes the residual mean from
+// r on active cells.  Stops if |sigma| < 1e-300.
+template <typename T, int FINE>
+__global__ void __launch_bounds__(kBlock) k_pcg_b(int64_t nvec, const T* iD, const T* e, const T* q, T* x,
+                                                  T* r, double* red, int k, RedN rn, double* part_rho_next,
                                                   double* part_max, int want_rho, int want_max, int* flag) {
-  const int total = g.n[0] * g.n[1] * ((D == 3) ? g.n[2] : 1);
+  typedef typename Vec16<T>::type V;
+  constexpr int W = Vec16<T>::W;
   bool skip = (*flag) != 0;
   T alpha = T(0);
-  // k = 0 also moves the residual mean over active cells out of r
-  const T mean = (k == 0) ? T(residual_mean(red, nparts)) : T(0);
+  const T mean = (k == 0) ? T(residual_mean(red, rn.mean)) : T(0);
   if (!skip) {
-    const double sig = total_of(red + (size_t)(kSlotSig0 + k) * kMaxBlocks, nparts);
+    const double sig = total_of(red + (size_t)(kSlotSig0 + k) * kMaxBlocks, rn.sig);
     if (fabs(sig) < 1e-300) {
       skip = true;
       if (blockIdx.x == 0 && threadIdx.x == 0) *flag = 1;
     } else {
-      alpha = T(total_of(red + (size_t)(kSlotRho0 + k) * kMaxBlocks, nparts) / sig);
+      alpha = T(total_of(red + (size_t)(kSlotRho0 + k) * kMaxBlocks, rn.rho) / sig);
     }
   }
   if (skip && !want_max && mean == T(0)) return;
   double rho = 0.0, mx = 0.0;
-  for (int lin = blockIdx.x * kBlock + threadIdx.x; lin < total; lin += gridDim.x * kBlock) {
-    int I[3], idx;
-    cell_of<D>(g, lin, I, idx);
-    T rr = r[idx];
-    const bool act = iD[idx] != T(0);
-    if (act && mean != T(0)) rr = rr - mean;
-    if (!skip) {
-      x[idx] = x[idx] + alpha * e[idx];
-      rr = rr - alpha * q[idx];
+  const V* iDv = reinterpret_cast<const V*>(iD);
+  const V* ev = reinterpret_cast<const V*>(e);
+  const V* qv = reinterpret_cast<const V*>(q);
+  V* xv = reinterpret_cast<V*>(x);
+  V* rv = reinterpret_cast<V*>(r);
+  const int64_t stride = (int64_t)gridDim.x * kBlock;
+  // two vectors per thread and trip, both coalesced, so twice the loads are in flight
+  for (int64_t v0 = blockIdx.x * (int64_t)kBlock + threadIdx.x; v0 < nvec; v0 += 2 * stride) {
+    const int64_t vv[2] = {v0, v0 + stride};
+    const bool has[2] = {true, v0 + stride < nvec};
+    V dv[2], rr[2], ee[2], qq[2], xx[2];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      if (!has[h]) continue;
+      dv[h] = iDv[vv[h]];
+      rr[h] = rv[vv[h]];
+      if (!skip) {
+        ee[h] = ev[vv[h]];
+        qq[h] = qv[vv[h]];
+        xx[h] = xv[vv[h]];
+      }
     }
-    if (!skip || (act && mean != T(0))) r[idx] = rr;
-    rho += double(rr) * (double(iD[idx]) * double(rr));
-    mx = fmax(mx, fabs(double(rr)));
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      if (!has[h]) continue;
+      T* rs = reinterpret_cast<T*>(&rr[h]);
+      const T* ds = reinterpret_cast<const T*>(&dv[h]);
+      if (mean != T(0)) {
+#pragma unroll
+        for (int w = 0; w < W; ++w)
+          if (ds[w] != T(0)) rs[w] = rs[w] - mean;
+      }
+      if (!skip) {
+        const T* es = reinterpret_cast<const T*>(&ee[h]);
+        const T* qs = reinterpret_cast<const T*>(&qq[h]);
+        T* xs = reinterpret_cast<T*>(&xx[h]);
+#pragma unroll
+        for (int w = 0; w < W; ++w) {
+          xs[w] = xs[w] + alpha * es[w];
+          rs[w] = rs[w] - alpha * qs[w];
+        }
+        xv[vv[h]] = xx[h];
+      }
+      if (!skip || mean != T(0)) rv[vv[h]] = rr[h];
+#pragma unroll
+      for (int w = 0; w < W; ++w) {
+        rho += double(rs[w]) * (double(ds[w]) * double(rs[w]));
+        mx = fmax(mx, fabs(double(rs[w])));
+      }
+    }
   }
   if (want_rho && !skip) {
     rho = block_sum(rho);

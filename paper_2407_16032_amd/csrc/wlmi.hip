@@ -39,7 +39,7 @@ wl_status fail(wl_status s, const std::string& msg) {
 inline int blocks_for(int64_t work) {
   int64_t b = (work + kBlock - 1) / kBlock;
   if (b < 1) b = 1;
-  if (b > kMaxBlocks) b = kMaxBlocks;
+  if (b > kGridStride) b = kGridStride;
   return (int)b;
 }
 
@@ -52,6 +52,7 @@ struct LevelPlan {
   int n[3];
   int px, py, pz;
   int64_t elems;  // px*py*pz
+  int64_t alloc;  // elems + front padding (16-element multiple)
 };
 
 struct Plan {
@@ -129,10 +130,11 @@ Plan make_plan(const wl_sim_desc& d, bool has_body) {
     LevelPlan& L = P.lev[P.nlev++];
     for (int a = 0; a < 3; ++a) L.n[a] = n[a];
     const int w = n[0] + 2;
-    L.px = (w >= 128) ? ((w + 63) / 64) * 64 : ((w + 7) / 8) * 8;
+    L.px = ((w + 15) / 16) * 16;  // rows of 64 bytes (FP32) / 128 bytes (FP64)
     L.py = n[1] + 2;
     L.pz = d.ndim == 3 ? n[2] + 2 : 1;
     L.elems = (int64_t)L.px * L.py * L.pz;
+    L.alloc = L.elems + 16;
     bool even = true;
     int mn = 1 << 30;
     for (int a = 0; a < d.ndim; ++a) {
@@ -144,12 +146,12 @@ Plan make_plan(const wl_sim_desc& d, bool has_body) {
   }
   const int D = d.ndim;
   size_t b = 0;
-  const size_t f0 = align256(P.lev[0].elems * P.esize);
+  const size_t f0 = align256(P.lev[0].alloc * P.esize);
   int nf0 = D /*ua*/ + D /*ub*/ + D /*ft*/ + D /*V*/ + D /*mu0*/ + D * D /*mu1*/ + 1 /*p*/ + 6 /*x r ea eb q iD*/;
   (void)has_body;
   b += nf0 * f0;
   b += align256((size_t)P.lev[0].py * P.lev[0].pz * P.esize);  // exit plane
-  for (int l = 1; l < P.nlev; ++l) b += (6 + D) * align256(P.lev[l].elems * P.esize);
+  for (int l = 1; l < P.nlev; ++l) b += (6 + D) * align256(P.lev[l].alloc * P.esize);
   b += align256((size_t)kNumSlots * kMaxBlocks * sizeof(double));
   b += align256(kNumScal * sizeof(double));
   b += align256(kMaxLevels * sizeof(int));
@@ -294,6 +296,10 @@ struct Impl : SimBase {
   Planes planes{};
   int plane_blocks = 1;
   bool exit_valid = false;
+  int slot_n[kNumSlots] = {};  // partials written by the last producer of each slot
+  int box_lo[3] = {}, box_hi[3] = {};
+  bool have_box = false;
+  int tiles[kMaxLevels][4] = {};  // tiled pass A: tiles_x, tiles_y, ntiles (0 = generic kernel)
 
   Vec3<T> v3(T* const a[3]) const {
     Vec3<T> v;
@@ -316,31 +322,32 @@ struct Impl : SimBase {
       off += align256(bytes);
       return p_;
     };
-    const size_t f0 = plan.lev[0].elems * sizeof(T);
-    for (int k = 0; k < D; ++k) u[0][k] = (T*)take(f0);
-    for (int k = 0; k < D; ++k) u[1][k] = (T*)take(f0);
-    for (int k = 0; k < D; ++k) ft[k] = (T*)take(f0);
-    for (int k = 0; k < D; ++k) V[k] = (T*)take(f0);
-    for (int k = 0; k < D; ++k) mu0[k] = (T*)take(f0);
-    for (int k = 0; k < D * D; ++k) mu1[k] = (T*)take(f0);
-    p = (T*)take(f0);
-    x[0] = (T*)take(f0);
-    r[0] = (T*)take(f0);
-    e[0][0] = (T*)take(f0);
-    e[0][1] = (T*)take(f0);
-    q[0] = (T*)take(f0);
-    iD[0] = (T*)take(f0);
+    // a field starts kFrontPad elements into its allocation: interior rows are then
+    // 64-byte aligned and the flat kernels sweep the whole aligned allocation
+    auto field = [&](int l) { return (T*)take(plan.lev[l].alloc * sizeof(T)) + kFrontPad; };
+    for (int k = 0; k < D; ++k) u[0][k] = field(0);
+    for (int k = 0; k < D; ++k) u[1][k] = field(0);
+    for (int k = 0; k < D; ++k) ft[k] = field(0);
+    for (int k = 0; k < D; ++k) V[k] = field(0);
+    for (int k = 0; k < D; ++k) mu0[k] = field(0);
+    for (int k = 0; k < D * D; ++k) mu1[k] = field(0);
+    p = field(0);
+    x[0] = field(0);
+    r[0] = field(0);
+    e[0][0] = field(0);
+    e[0][1] = field(0);
+    q[0] = field(0);
+    iD[0] = field(0);
     for (int k = 0; k < D; ++k) L[0][k] = mu0[k];
     ebuf = (T*)take((size_t)plan.lev[0].py * plan.lev[0].pz * sizeof(T));
     for (int l = 1; l < nlev; ++l) {
-      const size_t fl = plan.lev[l].elems * sizeof(T);
-      x[l] = (T*)take(fl);
-      r[l] = (T*)take(fl);
-      e[l][0] = (T*)take(fl);
-      e[l][1] = (T*)take(fl);
-      q[l] = (T*)take(fl);
-      iD[l] = (T*)take(fl);
-      for (int k = 0; k < D; ++k) L[l][k] = (T*)take(fl);
+      x[l] = field(l);
+      r[l] = field(l);
+      e[l][0] = field(l);
+      e[l][1] = field(l);
+      q[l] = field(l);
+      iD[l] = field(l);
+      for (int k = 0; k < D; ++k) L[l][k] = field(l);
     }
     red = (double*)take((size_t)kNumSlots * kMaxBlocks * sizeof(double));
     scal = (double*)take(kNumScal * sizeof(double));
@@ -373,6 +380,15 @@ struct Impl : SimBase {
       g[l].s[1] = P.px;
       g[l].s[2] = P.px * P.py;
       nb[l] = blocks_for((int64_t)P.n[0] * P.n[1] * (D == 3 ? P.n[2] : 1));
+      tiles[l][0] = tiles[l][1] = tiles[l][2] = 0;
+      if (D == 3 && P.n[0] >= 32 && P.n[1] >= 8 && (int64_t)P.n[0] * P.n[1] * P.n[2] >= (1 << 18)) {
+        const int tx = (P.n[0] + kTX - 1) / kTX, ty = (P.n[1] + kTY - 1) / kTY, tz = (P.n[2] + kTZ - 1) / kTZ;
+        if ((int64_t)tx * ty * tz <= kMaxBlocks) {
+          tiles[l][0] = tx;
+          tiles[l][1] = ty;
+          tiles[l][2] = tx * ty * tz;
+        }
+      }
     }
     nb_face = blocks_for((int64_t)(g[0].n[0] + 2) * (g[0].n[1] + 2) * (D == 3 ? g[0].n[2] + 2 : 1));
     planes.count = 0;
@@ -424,13 +440,71 @@ struct Impl : SimBase {
     return WL_OK;
   }
 
-  wl_status measure(double tm) override {
+  // Index box (padded coordinates) outside of which measure leaves mu0 = 1 (0 on
+  // boundary faces), mu1 = 0, V = 0 at time tm: every body point lies within
+  // |shape| + |pivot offset| of the pivot, and nothing is set beyond d = 2 + eps.
+  void body_box(double tm, int lo[3], int hi[3]) const {
+    Motion m{};
+    host_motion(bdesc, tm, m);
+    double shape = body.R;
+    if (bdesc.kind == WL_BODY_BOX) {
+      double s2 = 0;
+      for (int a = 0; a < D; ++a) s2 += body.h[a] * body.h[a];
+      shape = std::sqrt(s2);
+    }
+    double po2 = 0;
+    for (int a = 0; a < D; ++a) po2 += body.po[a] * body.po[a];
+    const double reach = shape + std::sqrt(po2) + 2.0 + desc.eps + 3.0;  // 3-cell margin
+    for (int a = 0; a < 3; ++a) {
+      if (a >= D) {
+        lo[a] = hi[a] = 0;
+        continue;
+      }
+      lo[a] = std::max(0, (int)std::floor(m.P[a] - reach));
+      hi[a] = std::min(g[0].n[a] + 1, (int)std::ceil(m.P[a] + reach) + 2);
+    }
+  }
+
+  wl_status measure_box(double tm, const int lo[3], const int hi[3]) {
     Motion m{};
     if (has_body) host_motion(bdesc, tm, m);
-    WL_TIMED(WL_K_MEASURE, (k_measure<T, D><<<dim3(nb_face, D), kBlock, 0, stream>>>(g[0], body, m, desc.eps,
-                                                                                   v3(mu0), v9(mu1), v3(V))));
+    int64_t vol = 1;
+    for (int a = 0; a < D; ++a) vol *= hi[a] - lo[a] + 1;
+    const int3 l3 = make_int3(lo[0], lo[1], lo[2]), h3 = make_int3(hi[0], hi[1], hi[2]);
+    WL_TIMED(WL_K_MEASURE, (k_measure<T, D><<<dim3(blocks_for(vol), D), kBlock, 0, stream>>>(
+                               g[0], body, m, desc.eps, v3(mu0), v9(mu1), v3(V), l3, h3)));
     WL_HIP(hipGetLastError());
     return coefficients();
+  }
+
+  // full-domain measure (creation and explicit calls)
+  wl_status measure(double tm) override {
+    int lo[3] = {0, 0, 0}, hi[3] = {g[0].n[0] + 1, g[0].n[1] + 1, D == 3 ? g[0].n[2] + 1 : 0};
+    wl_status s = measure_box(tm, lo, hi);
+    if (s == WL_OK && has_body) {
+      body_box(tm, box_lo, box_hi);
+      have_box = true;
+    }
+    return s;
+  }
+
+  // per-step re-measure of a moving body: only the union of the previous and the
+  // current body boxes can change
+  wl_status remeasure_moving(double tm) {
+    if (!have_box) return measure(tm);
+    int lo[3], hi[3];
+    body_box(tm, lo, hi);
+    int ul[3], uh[3];
+    for (int a = 0; a < 3; ++a) {
+      ul[a] = std::min(lo[a], box_lo[a]);
+      uh[a] = std::max(hi[a], box_hi[a]);
+    }
+    wl_status s = measure_box(tm, ul, uh);
+    for (int a = 0; a < 3; ++a) {
+      box_lo[a] = lo[a];
+      box_hi[a] = hi[a];
+    }
+    return s;
   }
 
   wl_status bc(T* const uu[3], bool use_exit) {
@@ -442,8 +516,8 @@ struct Impl : SimBase {
 
   wl_status apply_bc_cur() override { return bc(u[cur], false); }
 
-  wl_status read_scalar_max(int s, int n, double* out) {
-    WL_TIMED(WL_K_REDUCE, (k_finalize_max<<<1, kBlock, 0, stream>>>(slot(s), n, scal + kScalRmax)));
+  wl_status read_scalar_max(int s, double* out) {
+    WL_TIMED(WL_K_REDUCE, (k_finalize_max<<<1, kBlock, 0, stream>>>(slot(s), slot_n[s], scal + kScalRmax)));
     WL_HIP(hipGetLastError());
     WL_HIP(hipMemcpyAsync(host_pin, scal + kScalRmax, sizeof(double), hipMemcpyDeviceToHost, stream));
     WL_HIP(hipStreamSynchronize(stream));
@@ -452,27 +526,57 @@ struct Impl : SimBase {
     return WL_OK;
   }
 
+  void set_mean_producer(int grid) { slot_n[kSlotSumR] = slot_n[kSlotCnt] = grid; }
+
   void pcg(int l, bool fine) {
     const int K = desc.pcg_iters;
     T* eo = e[l][0];
     T* en = e[l][1];
+    const int64_t nvec = plan.lev[l].alloc / Vec16<T>::W;
+    const int gb = blocks_for(nvec);
+    const int kidA = l == 0 ? WL_K_PCG_A : WL_K_COARSE, kidB = l == 0 ? WL_K_PCG_B : WL_K_COARSE;
     for (int k = 0; k < K; ++k) {
       const int wr = k < K - 1 ? 1 : 0, wm = (fine && k == K - 1) ? 1 : 0;
-      if (l == 0) {
-        WL_TIMED(WL_K_PCG_A, (k_pcg_a<T, D, 1><<<nb[l], kBlock, 0, stream>>>(
-                                 g[l], v3(L[l]), iD[l], r[l], eo, en, q[l], red, k, nb[l], slot(kSlotSig0 + k),
-                                 flags + l)));
-        WL_TIMED(WL_K_PCG_B, (k_pcg_b<T, D, 1><<<nb[l], kBlock, 0, stream>>>(
-                                 g[l], iD[l], en, q[l], x[l], r[l], red, k, nb[l], slot(kSlotRho0 + k + 1),
-                                 slot(kSlotRmax), wr, wm, flags + l)));
+      RedN rn{slot_n[kSlotSumR], slot_n[kSlotRho0 + k], k > 0 ? slot_n[kSlotRho0 + k - 1] : 0, 0};
+      int ga;
+      if (tiles[l][2] > 0) {
+        ga = tiles[l][2];
+        if (l == 0)
+          WL_TIMED(kidA, (k_pcg_a_tile<T, 1><<<ga, kTileThreads, 0, stream>>>(
+                              g[l], v3(L[l]), iD[l], r[l], eo, en, q[l], red, k, rn, slot(kSlotSig0 + k),
+                              flags + l, tiles[l][0], tiles[l][1], tiles[l][2])));
+        else
+          WL_TIMED(kidA, (k_pcg_a_tile<T, 0><<<ga, kTileThreads, 0, stream>>>(
+                              g[l], v3(L[l]), iD[l], r[l], eo, en, q[l], red, k, rn, slot(kSlotSig0 + k),
+                              flags + l, tiles[l][0], tiles[l][1], tiles[l][2])));
       } else {
-        WL_TIMED(WL_K_COARSE, (k_pcg_a<T, D, 0><<<nb[l], kBlock, 0, stream>>>(
-                                  g[l], v3(L[l]), iD[l], r[l], eo, en, q[l], red, k, nb[l], slot(kSlotSig0 + k),
-                                  flags + l)));
-        WL_TIMED(WL_K_COARSE, (k_pcg_b<T, D, 0><<<nb[l], kBlock, 0, stream>>>(
-                                  g[l], iD[l], en, q[l], x[l], r[l], red, k, nb[l], slot(kSlotRho0 + k + 1),
-                                  slot(kSlotRmax), wr, wm, flags + l)));
+        ga = nb[l];
+        if (l == 0)
+          WL_TIMED(kidA, (k_pcg_a<T, D, 1><<<ga, kBlock, 0, stream>>>(g[l], v3(L[l]), iD[l], r[l], eo, en, q[l],
+                                                                      red, k, rn, slot(kSlotSig0 + k), flags + l)));
+        else
+          WL_TIMED(kidA, (k_pcg_a<T, D, 0><<<ga, kBlock, 0, stream>>>(g[l], v3(L[l]), iD[l], r[l], eo, en, q[l],
+                                                                      red, k, rn, slot(kSlotSig0 + k), flags + l)));
       }
+      slot_n[kSlotSig0 + k] = ga;
+      if (k == 0) slot_n[kSlotRho0] = ga;
+      rn.sig = ga;
+      rn.rho = slot_n[kSlotRho0 + k];
+      T* b_iD = iD[l] - kFrontPad;
+      T* b_e = en - kFrontPad;
+      T* b_q = q[l] - kFrontPad;
+      T* b_x = x[l] - kFrontPad;
+      T* b_r = r[l] - kFrontPad;
+      if (l == 0)
+        WL_TIMED(kidB, (k_pcg_b<T, 1><<<gb, kBlock, 0, stream>>>(nvec, b_iD, b_e, b_q, b_x, b_r, red, k, rn,
+                                                                 slot(kSlotRho0 + k + 1), slot(kSlotRmax), wr, wm,
+                                                                 flags + l)));
+      else
+        WL_TIMED(kidB, (k_pcg_b<T, 0><<<gb, kBlock, 0, stream>>>(nvec, b_iD, b_e, b_q, b_x, b_r, red, k, rn,
+                                                                 slot(kSlotRho0 + k + 1), slot(kSlotRmax), wr, wm,
+                                                                 flags + l)));
+      if (wr) slot_n[kSlotRho0 + k + 1] = gb;
+      if (wm) slot_n[kSlotRmax] = gb;
       std::swap(eo, en);
     }
   }
@@ -481,26 +585,39 @@ struct Impl : SimBase {
     WL_TIMED(l == 0 ? WL_K_RESTRICT : WL_K_COARSE,
              (k_restrict<T, D><<<nb[l + 1], kBlock, 0, stream>>>(g[l], g[l + 1], r[l], iD[l + 1], r[l + 1],
                                                                  x[l + 1], red, flags + l + 1)));
+    set_mean_producer(nb[l + 1]);
     if (l + 2 < nlev) vcycle(l + 1);
     pcg(l + 1, false);
-    WL_TIMED(l == 0 ? WL_K_PROLONG : WL_K_COARSE,
-             (k_prolong<T, D><<<nb[l], kBlock, 0, stream>>>(g[l], g[l + 1], x[l + 1], v3(L[l]), iD[l], x[l],
-                                                            r[l], red, flags + l)));
+    if (tiles[l][2] > 0) {
+      WL_TIMED(l == 0 ? WL_K_PROLONG : WL_K_COARSE,
+               (k_prolong_tile<T><<<tiles[l][2], kTileThreads, 0, stream>>>(
+                   g[l], g[l + 1], x[l + 1], v3(L[l]), iD[l], x[l], r[l], red, flags + l, tiles[l][0],
+                   tiles[l][1], tiles[l][2])));
+      set_mean_producer(tiles[l][2]);
+    } else {
+      WL_TIMED(l == 0 ? WL_K_PROLONG : WL_K_COARSE,
+               (k_prolong<T, D><<<nb[l], kBlock, 0, stream>>>(g[l], g[l + 1], x[l + 1], v3(L[l]), iD[l], x[l],
+                                                              r[l], red, flags + l)));
+      set_mean_producer(nb[l]);
+    }
   }
 
   // initial residual already in r[0] / rmax slot
   wl_status mg_loop(double tol, int itmax, wl_solve_stats* st) {
     double res0;
-    wl_status s = read_scalar_max(kSlotRmax, nb[0], &res0);
+    wl_status s = read_scalar_max(kSlotRmax, &res0);
     if (s != WL_OK) return s;
     double res = res0;
     int n = 0;
     while (res >= tol && n < itmax) {
       if (nlev > 1) vcycle(0);
-      else WL_TIMED(WL_K_DIVRES, (k_mean0<T, D><<<nb[0], kBlock, 0, stream>>>(g[0], iD[0], r[0], red, flags)));
+      else {
+        WL_TIMED(WL_K_DIVRES, (k_mean0<T, D><<<nb[0], kBlock, 0, stream>>>(g[0], iD[0], r[0], red, flags)));
+        set_mean_producer(nb[0]);
+      }
       pcg(0, true);
       ++n;
-      s = read_scalar_max(kSlotRmax, nb[0], &res);
+      s = read_scalar_max(kSlotRmax, &res);
       if (s != WL_OK) return s;
       if (!std::isfinite(res)) return fail(WL_ERR_NONFINITE, "multigrid residual is not finite");
     }
@@ -519,6 +636,8 @@ struct Impl : SimBase {
     WL_TIMED(WL_K_DIVRES, (k_div_res<T, D><<<nb[0], kBlock, 0, stream>>>(g[0], v3(uu), nullptr, p, wdt, v3(L[0]),
                                                                           iD[0], x[0], r[0], slot(kSlotRmax), red,
                                                                           flags)));
+    set_mean_producer(nb[0]);
+    slot_n[kSlotRmax] = nb[0];
     WL_HIP(hipGetLastError());
     wl_status s = mg_loop(desc.mg_tol, desc.mg_itmax, st);
     if (s != WL_OK) return s;
@@ -534,16 +653,20 @@ struct Impl : SimBase {
   }
 
   wl_status poisson(const void* rhs, void* xin, double tol, int itmax, wl_solve_stats* st) override {
-    T* xs = x[0];
-    if (xin) x[0] = (T*)xin;
-    k_div_res<T, D><<<nb[0], kBlock, 0, stream>>>(g[0], v3(u[cur]), (const T*)rhs, nullptr, T(0), v3(L[0]),
-                                                  iD[0], x[0], r[0], slot(kSlotRmax), red, flags);
-    wl_status s = WL_OK;
-    hipError_t he = hipGetLastError();
-    if (he != hipSuccess) s = fail(WL_ERR_HIP, hipGetErrorString(he));
-    if (s == WL_OK) s = mg_loop(tol > 0 ? tol : desc.mg_tol, itmax > 0 ? itmax : desc.mg_itmax, st);
-    x[0] = xs;
-    return s;
+    // a caller-supplied x (pressure layout, no front padding) is copied in and out of
+    // the internal fine-level x, which the vectorised kernels require
+    const size_t bytes = (size_t)plan.lev[0].elems * sizeof(T);
+    if (xin) WL_HIP(hipMemcpyAsync(x[0], xin, bytes, hipMemcpyDeviceToDevice, stream));
+    WL_TIMED(WL_K_DIVRES, (k_div_res<T, D><<<nb[0], kBlock, 0, stream>>>(g[0], v3(u[cur]), (const T*)rhs, nullptr,
+                                                                          T(0), v3(L[0]), iD[0], x[0], r[0],
+                                                                          slot(kSlotRmax), red, flags)));
+    WL_HIP(hipGetLastError());
+    set_mean_producer(nb[0]);
+    slot_n[kSlotRmax] = nb[0];
+    wl_status s = mg_loop(tol > 0 ? tol : desc.mg_tol, itmax > 0 ? itmax : desc.mg_itmax, st);
+    if (s != WL_OK) return s;
+    if (xin) WL_HIP(hipMemcpyAsync(xin, x[0], bytes, hipMemcpyDeviceToDevice, stream));
+    return WL_OK;
   }
 
   wl_status conv_diff() override {
@@ -556,7 +679,7 @@ struct Impl : SimBase {
   wl_status step(int remeasure, wl_step_stats* st) override {
     wl_status s;
     if (remeasure && moving) {
-      s = measure(t);
+      s = remeasure_moving(t);
       if (s != WL_OK) return s;
     }
     T* const* A = u[cur];
@@ -596,9 +719,10 @@ struct Impl : SimBase {
     t += dt;
     // CFL
     WL_TIMED(WL_K_CFL, (k_cfl<T, D><<<nb[0], kBlock, 0, stream>>>(g[0], v3(u[cur]), slot(kSlotCfl))));
+    slot_n[kSlotCfl] = nb[0];
     WL_HIP(hipGetLastError());
     double smax;
-    if ((s = read_scalar_max(kSlotCfl, nb[0], &smax)) != WL_OK) return s;
+    if ((s = read_scalar_max(kSlotCfl, &smax)) != WL_OK) return s;
     const double denom = smax + desc.cfl_nu_coef * desc.nu;
     dt = denom <= 0.0 ? desc.dt_max : std::min(desc.dt_max, 1.0 / denom);
     if (st) {
