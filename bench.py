@@ -90,6 +90,52 @@ def run_cpu_baseline(w_name):
             "sample": "one FP64 step of %s (%d cells), numpy single thread, %.1f s" % (w.name, w.cells, dt)}
 
 
+def kernel_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("wl_kernels.hpp", "wl_device.hpp"):
+        with open(os.path.join(ROOT, "paper_2407_16032_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(workload, kernel):
+    """HBM bytes per launch from the committed PMC summary, only if the kernel sources
+    are unchanged since the counters were taken (else None)."""
+    path = os.path.join(ROOT, "profiles", "pmc_%s.md" % workload)
+    if not os.path.exists(path):
+        return None
+    key = {"pcg_a": "k_pcg_a_tile_fine", "pcg_b": "k_pcg_b_fine"}.get(kernel)
+    src, val = None, None
+    with open(path) as f:
+        for line in f:
+            if line.startswith("kernel-source-sha256-16:"):
+                src = line.split(":", 1)[1].strip()
+            if key and line.startswith("traffic_bytes " + key + " "):
+                val = float(line.split()[2])
+    if src != kernel_source_hash():
+        return None
+    return val
+
+
+def copy_probe(nbytes):
+    """A plain device-to-device copy of known size: reads and writes nbytes each. Its
+    FETCH_SIZE / WRITE_SIZE counter values calibrate the counters of the solver kernels."""
+    import torch
+    a = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda:0")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    start = torch.cuda.Event(enable_timing=True)
+    stop = torch.cuda.Event(enable_timing=True)
+    start.record()
+    b.copy_(a)
+    stop.record()
+    torch.cuda.synchronize()
+    ms = start.elapsed_time(stop)
+    print(json.dumps({"copy_bytes": nbytes, "ms": ms, "GBps_read_plus_write": 2 * nbytes / (ms * 1e-3) / 1e9}))
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -98,7 +144,12 @@ def main():
     ap.add_argument("--workload", default="plate3d", choices=sorted(workloads().keys()))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true", help="skip per-kernel event timing")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
+                    help="only run a plain device copy of BYTES bytes (calibrates HBM counters)")
     args = ap.parse_args()
+    if args.copy_probe:
+        copy_probe(args.copy_probe)
+        return
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only (the multi-GPU domain decomposition is a "
               "design, not an implementation); use --gpus 1", file=sys.stderr)
@@ -173,7 +224,8 @@ def main():
             name, tms, b, avg_ms = best
             ach = b / (avg_ms * 1e-3) / 1e9
             roof = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                    "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None, "kernel": name,
+                    "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": measured_traffic(w.name, name),
+                    "kernel": name,
                     "bytes_per_launch": b, "avg_launch_us": round(avg_ms * 1e3, 2)}
         for name, ent in sorted(kernels.items(), key=lambda kv: -kv[1]["total_ms_per_step"]):
             print("[bench]   %-9s %8.3f ms/step %6.1f launches/step %9.1f us avg %s" % (
