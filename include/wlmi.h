@@ -76,6 +76,7 @@ typedef struct {
   double mg_tol;         /* residual max-norm tolerance of the projection solve [1e-6] */
   int mg_itmax;          /* maximum V-cycles per solve [32] */
   int pcg_iters;         /* PCG smoothing iterations per level [6] */
+  int learned_guess;     /* 1 -> plan the buffers of the learned initial guess (3-D only) */
 } wl_sim_desc;
 
 typedef enum { WL_BODY_NONE = 0, WL_BODY_SPHERE = 1, WL_BODY_BOX = 2 } wl_body_kind;
@@ -194,6 +195,48 @@ wl_status wl_levels(wl_sim* sim, int* nlevels, int level, int64_t n_out[3]);
 wl_status wl_set_time(wl_sim* sim, double t, double dt_next);
 wl_status wl_get_time(wl_sim* sim, double* t, double* dt_next);
 
+/* ---------------------------------------------------------------------------
+ * Learned multigrid initial guess (an extension of the method, not in the
+ * paper): a 3-layer 3x3x3 conv net (3 -> 16 -> 16 -> 1 channels, ReLU, BF16
+ * weights and activations, FP32 accumulation on MFMA) maps the previous two
+ * pressures and the current divergence, normalised by the mean and RMS
+ * deviation of p_{m-1} over active cells, to the pressure change of the next
+ * solve; x0 = (p_{m-1} + s * out) w dt replaces the warm start x0 = p w dt.  The
+ * multigrid solve to the same tolerance stays the judge of the guess.  Online
+ * training: after each guided solve, random crops (64^3 or the grid) of the
+ * features and the target (p_m - p_{m-1})/s enter a ring buffer; each solve then
+ * runs train_iters Adam steps (FP32 master weights) on ring crops, loss = mean
+ * over the crop's inner cells (3 cells from its faces) of the squared
+ * mean-removed error.  Needs desc.learned_guess = 1 and ndim = 3.
+ * Parameters: a flat FP32 vector of WL_PG_PARAMS values
+ *   W1[27][3][16] b1[16] W2[27][16][16] b2[16] W3[27][16][1] b3[1],
+ * taps ordered 9 (dz+1) + 3 (dy+1) + (dx+1), out[p] = b + sum W[tap]^T in[p + off].
+ * Box arrays (wl_pg_forward / wl_pg_train_step): channels-last on a box of
+ * interior n[0] x n[1] x n[2] (each <= 64 and <= the grid) with a one-cell zero
+ * halo, point (x, y, z) at ((z (n1+2) + y) (n0+2) + x), x fastest.
+ * ------------------------------------------------------------------------- */
+#define WL_PG_PARAMS 8673
+
+/* Set the FP32 master parameters (host array of WL_PG_PARAMS), reset Adam. */
+wl_status wl_pg_set_weights(wl_sim* sim, const float* host_params);
+/* Copy the FP32 master parameters to a host array of WL_PG_PARAMS. */
+wl_status wl_pg_get_weights(wl_sim* sim, float* host_params);
+/* mode 0: plain warm start; 1: learned guess; 2: learned guess + online training.
+ * lr: Adam learning rate; train_iters: Adam steps per solve; crops: crops taken
+ * per solve; seed: crop placement / sampling. */
+wl_status wl_pg_mode(wl_sim* sim, int mode, double lr, int train_iters, int crops, uint64_t seed);
+/* Forward pass on a caller box: x_box device bfloat16 [P][4] (channel 3 = 0),
+ * y_out device float [P] (written on the interior). */
+wl_status wl_pg_forward(wl_sim* sim, const void* x_box, const int64_t n[3], float* y_out);
+/* One training step on a caller box: forward, loss against target (device float
+ * [P]) over mask (device uint8 [P]), backward; grad_out (host, WL_PG_PARAMS, may be
+ * NULL) receives the FP32 gradient, loss (may be NULL) the loss; apply != 0 then
+ * takes the Adam step with the mode's learning rate. */
+wl_status wl_pg_train_step(wl_sim* sim, const void* x_box, const float* target, const unsigned char* mask,
+                           const int64_t n[3], float* grad_out, double* loss, int apply);
+/* Loss of the last training step, training steps and snapshots taken so far. */
+wl_status wl_pg_stats(wl_sim* sim, double* last_loss, int64_t* train_steps, int64_t* snapshots);
+
 /* Kernel groups timed by the profiler. Fine-level launches are timed per
  * kernel; every launch on a coarser multigrid level counts as WL_K_COARSE. */
 enum {
@@ -213,7 +256,9 @@ enum {
   WL_K_FORCES = 13,  /* force integrals */
   WL_K_COARSE = 14,  /* all work on multigrid levels >= 1 */
   WL_K_REDUCE = 15,  /* single-block finalisations of reductions */
-  WL_K_COUNT = 16
+  WL_K_PG_INFER = 16,/* learned guess: features, conv net, guess */
+  WL_K_PG_TRAIN = 17,/* learned guess: snapshots, training steps */
+  WL_K_COUNT = 18
 };
 
 /* Per-kernel timing with HIP events recorded around each launch on the sim's

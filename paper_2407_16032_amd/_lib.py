@@ -17,9 +17,11 @@ FIELDS = {"u": 0, "u0": 1, "f": 2, "V": 3, "mu0": 4, "mu1": 5, "p": 6, "x": 7, "
 # every symbol include/wlmi.h declares
 EXPORTS = ["wl_workspace_bytes", "wl_sim_create", "wl_sim_destroy", "wl_measure_body", "wl_step",
            "wl_apply_bc", "wl_conv_diff", "wl_project", "wl_poisson_solve", "wl_forces", "wl_field",
-           "wl_levels", "wl_set_time", "wl_get_time", "wl_profile", "wl_profile_read", "wl_last_error"]
+           "wl_levels", "wl_set_time", "wl_get_time", "wl_profile", "wl_profile_read", "wl_pg_set_weights",
+           "wl_pg_get_weights", "wl_pg_mode", "wl_pg_forward", "wl_pg_train_step", "wl_pg_stats", "wl_last_error"]
+PG_PARAMS = 8673
 KERNELS = ["measure", "coef", "flux", "bdim", "bc", "exit", "divres", "pcg_a", "pcg_b", "restrict",
-           "prolong", "project", "cfl", "forces", "coarse", "reduce"]
+           "prolong", "project", "cfl", "forces", "coarse", "reduce", "pg_infer", "pg_train"]
 
 
 class SimDesc(C.Structure):
@@ -27,7 +29,7 @@ class SimDesc(C.Structure):
                 ("periodic_mask", C.c_uint), ("convective_exit", C.c_int), ("prec", C.c_int),
                 ("eps", C.c_double), ("dt0", C.c_double), ("dt_max", C.c_double),
                 ("cfl_nu_coef", C.c_double), ("mg_tol", C.c_double), ("mg_itmax", C.c_int),
-                ("pcg_iters", C.c_int)]
+                ("pcg_iters", C.c_int), ("learned_guess", C.c_int)]
 
 
 class BodyDesc(C.Structure):
@@ -95,6 +97,19 @@ def load(path: str = LIB_PATH):
     lib.wl_profile.argtypes = [P, C.c_int]
     lib.wl_profile_read.restype = C.c_int
     lib.wl_profile_read.argtypes = [P, C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_int64)]
+    FP = C.POINTER(C.c_float)
+    lib.wl_pg_set_weights.restype = C.c_int
+    lib.wl_pg_set_weights.argtypes = [P, FP]
+    lib.wl_pg_get_weights.restype = C.c_int
+    lib.wl_pg_get_weights.argtypes = [P, FP]
+    lib.wl_pg_mode.restype = C.c_int
+    lib.wl_pg_mode.argtypes = [P, C.c_int, C.c_double, C.c_int, C.c_int, C.c_uint64]
+    lib.wl_pg_forward.restype = C.c_int
+    lib.wl_pg_forward.argtypes = [P, P, C.POINTER(C.c_int64), P]
+    lib.wl_pg_train_step.restype = C.c_int
+    lib.wl_pg_train_step.argtypes = [P, P, P, P, C.POINTER(C.c_int64), FP, C.POINTER(C.c_double), C.c_int]
+    lib.wl_pg_stats.restype = C.c_int
+    lib.wl_pg_stats.argtypes = [P, C.POINTER(C.c_double), C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
     lib.wl_last_error.restype = C.c_char_p
     lib.wl_last_error.argtypes = []
     _lib = lib

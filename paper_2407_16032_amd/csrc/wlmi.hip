@@ -17,6 +17,7 @@
 
 #include "wlmi.h"
 #include "wl_kernels.hpp"
+#include "wl_pgnet.hpp"
 
 using namespace wl;
 
@@ -121,6 +122,24 @@ wl_status validate_body(const wl_sim_desc& d, const wl_body_desc* b) {
   return WL_OK;
 }
 
+// learned-guess buffer sizes: the whole padded grid (inference) and one crop box
+constexpr int kPgRing = 64;     // crops kept for training
+constexpr int kPgWaves = 1024;  // waves of the weight-gradient kernels (256 blocks)
+struct PgSizes {
+  int64_t Pd, Pc;
+  int cn[3];
+};
+PgSizes pg_sizes(const Plan& P) {
+  PgSizes S;
+  S.Pd = (int64_t)(P.lev[0].n[0] + 2) * (P.lev[0].n[1] + 2) * (P.lev[0].n[2] + 2);
+  S.Pc = 1;
+  for (int a = 0; a < 3; ++a) {
+    S.cn[a] = std::min(kPgCrop, P.lev[0].n[a]);
+    S.Pc *= S.cn[a] + 2;
+  }
+  return S;
+}
+
 Plan make_plan(const wl_sim_desc& d, bool has_body) {
   Plan P;
   P.ndim = d.ndim;
@@ -155,6 +174,17 @@ Plan make_plan(const wl_sim_desc& d, bool has_body) {
   b += align256((size_t)kNumSlots * kMaxBlocks * sizeof(double));
   b += align256(kNumScal * sizeof(double));
   b += align256(kMaxLevels * sizeof(int));
+  if (d.learned_guess && d.ndim == 3) {
+    const PgSizes S = pg_sizes(P);
+    b += align256(P.lev[0].alloc * P.esize);  // p_{m-2}
+    b += align256(S.Pd * 8) + 2 * align256(S.Pd * 32) + align256(S.Pd * 4);
+    b += align256(S.Pc * 8) + 5 * align256(S.Pc * 32) + align256(S.Pc * 4);
+    b += kPgRing * (align256(S.Pc * 8) + align256(S.Pc * 4) + align256(S.Pc));
+    b += 4 * align256(kPgParams * sizeof(float));
+    b += align256(27 * 64 * 2) + 4 * align256(27 * 256 * 2) + 3 * align256(16 * sizeof(float));
+    b += align256((size_t)kPgWaves * (27 * 256 + 16) * sizeof(float));
+    b += align256(8192 * sizeof(double)) + align256(8 * sizeof(double));
+  }
   P.bytes = b;
   return P;
 }
@@ -255,6 +285,13 @@ struct SimBase {
   virtual wl_status poisson(const void* rhs, void* x, double tol, int itmax, wl_solve_stats* st) = 0;
   virtual wl_status forces(double fp[3], double fv[3]) = 0;
   virtual wl_status field(int which, int level, void** ptr, int64_t shape[4], int64_t strides[4]) = 0;
+  virtual wl_status pg_set_weights(const float* w) = 0;
+  virtual wl_status pg_get_weights(float* w) = 0;
+  virtual wl_status pg_set_mode(int mode, double lr, int iters, int crops, uint64_t seed) = 0;
+  virtual wl_status pg_forward(const void* x, const int64_t n[3], float* y) = 0;
+  virtual wl_status pg_train(const void* x, const float* t, const unsigned char* m, const int64_t n[3], float* grad,
+                             double* loss, int apply) = 0;
+  virtual wl_status pg_stats(double* loss, int64_t* steps, int64_t* snaps) = 0;
   virtual wl_status profile(int enable) {
     if (enable) return prof.enable(stream);
     prof.flush();
@@ -299,6 +336,28 @@ struct Impl : SimBase {
   int slot_n[kNumSlots] = {};  // partials written by the last producer of each slot
   int box_lo[3] = {}, box_hi[3] = {};
   bool have_box = false;
+  // learned initial guess
+  bool pg_on = false, pg_weights_set = false;
+  int pg_mode = 0, pg_iters = 1, pg_crops = 2, pg_hist = 0, ring_used = 0, ring_next = 0;
+  double pg_lr = 1e-3;
+  uint64_t pg_rng = 0;
+  int64_t pg_train_steps = 0, pg_snaps = 0, pg_adam_t = 0;
+  bool pg_loss_pending = false;
+  double pg_last_loss = NAN;
+  T* p2 = nullptr;
+  unsigned short *pgXd = nullptr, *pgA1d = nullptr, *pgA2d = nullptr;
+  float* pgYd = nullptr;
+  unsigned short *pgXc = nullptr, *pgA1c = nullptr, *pgA2c = nullptr, *pgG3 = nullptr, *pgG2 = nullptr,
+                 *pgG1 = nullptr;
+  float* pgYc = nullptr;
+  unsigned short* ringX[kPgRing] = {};
+  float* ringT[kPgRing] = {};
+  unsigned char* ringM[kPgRing] = {};
+  float *pgW = nullptr, *pgM = nullptr, *pgV = nullptr, *pgGrad = nullptr, *pgPart = nullptr;
+  PgWeights pgK{};
+  double *pgRed = nullptr, *pgScal = nullptr;
+  PgBox bd{}, bcrop{};
+  int64_t pgPc = 0;
   int tiles[kMaxLevels][4] = {};  // tiled pass A: tiles_x, tiles_y, ntiles (0 = generic kernel)
 
   Vec3<T> v3(T* const a[3]) const {
@@ -352,6 +411,49 @@ struct Impl : SimBase {
     red = (double*)take((size_t)kNumSlots * kMaxBlocks * sizeof(double));
     scal = (double*)take(kNumScal * sizeof(double));
     flags = (int*)take(kMaxLevels * sizeof(int));
+    pg_on = desc.learned_guess && D == 3;
+    if (pg_on) {
+      const PgSizes S = pg_sizes(plan);
+      p2 = field(0);
+      pgXd = (unsigned short*)take(S.Pd * 8);
+      pgA1d = (unsigned short*)take(S.Pd * 32);
+      pgA2d = (unsigned short*)take(S.Pd * 32);
+      pgYd = (float*)take(S.Pd * 4);
+      pgXc = (unsigned short*)take(S.Pc * 8);
+      pgA1c = (unsigned short*)take(S.Pc * 32);
+      pgA2c = (unsigned short*)take(S.Pc * 32);
+      pgG3 = (unsigned short*)take(S.Pc * 32);
+      pgG2 = (unsigned short*)take(S.Pc * 32);
+      pgG1 = (unsigned short*)take(S.Pc * 32);
+      pgYc = (float*)take(S.Pc * 4);
+      for (int k = 0; k < kPgRing; ++k) {
+        ringX[k] = (unsigned short*)take(S.Pc * 8);
+        ringT[k] = (float*)take(S.Pc * 4);
+        ringM[k] = (unsigned char*)take(S.Pc);
+      }
+      pgW = (float*)take(kPgParams * sizeof(float));
+      pgM = (float*)take(kPgParams * sizeof(float));
+      pgV = (float*)take(kPgParams * sizeof(float));
+      pgGrad = (float*)take(kPgParams * sizeof(float));
+      pgK.w1f = (unsigned short*)take(27 * 64 * 2);
+      pgK.w2f = (unsigned short*)take(27 * 256 * 2);
+      pgK.w3f = (unsigned short*)take(27 * 256 * 2);
+      pgK.w3b = (unsigned short*)take(27 * 256 * 2);
+      pgK.w2b = (unsigned short*)take(27 * 256 * 2);
+      pgK.b1 = (float*)take(16 * sizeof(float));
+      pgK.b2 = (float*)take(16 * sizeof(float));
+      pgK.b3 = (float*)take(16 * sizeof(float));
+      pgPart = (float*)take((size_t)kPgWaves * (27 * 256 + 16) * sizeof(float));
+      pgRed = (double*)take(8192 * sizeof(double));
+      pgScal = (double*)take(8 * sizeof(double));
+      for (int a = 0; a < 3; ++a) {
+        bd.n[a] = plan.lev[0].n[a];
+        bd.P[a] = bd.n[a] + 2;
+        bcrop.n[a] = S.cn[a];
+        bcrop.P[a] = bcrop.n[a] + 2;
+      }
+      pgPc = S.Pc;
+    }
     return off;
   }
 
@@ -364,6 +466,15 @@ struct Impl : SimBase {
     for (int l = 0; l < nlev; ++l) {
       ok = ok && in(x[l]) && in(r[l]) && in(e[l][0]) && in(e[l][1]) && in(q[l]) && in(iD[l]);
       for (int k = 0; k < D; ++k) ok = ok && in(L[l][k]);
+    }
+    if (pg_on) {
+      ok = ok && in(p2) && in(pgXd) && in(pgA1d) && in(pgA2d) && in(pgYd) && in(pgXc) && in(pgA1c) && in(pgA2c) &&
+           in(pgG3) && in(pgG2) && in(pgG1) && in(pgYc) && in(pgW) && in(pgM) && in(pgV) && in(pgGrad) &&
+           in(pgK.w1f) && in(pgK.w2f) && in(pgK.w3f) && in(pgK.w3b) && in(pgK.w2b) && in(pgK.b1) && in(pgK.b2) &&
+           in(pgK.b3) && in(pgPart) && in(pgRed) && in(pgScal);
+      for (int k = 0; k < kPgRing; ++k) ok = ok && in(ringX[k]) && in(ringT[k]) && in(ringM[k]);
+      // the last byte of the last buffer must be inside the workspace too
+      ok = ok && (const char*)(pgScal + 8) <= base + bytes;
     }
     return ok;
   }
@@ -633,16 +744,217 @@ struct Impl : SimBase {
 
   wl_status project(T* const uu[3], double w, wl_solve_stats* st) {
     const T wdt = T(w * dt);
-    WL_TIMED(WL_K_DIVRES, (k_div_res<T, D><<<nb[0], kBlock, 0, stream>>>(g[0], v3(uu), nullptr, p, wdt, v3(L[0]),
-                                                                          iD[0], x[0], r[0], slot(kSlotRmax), red,
-                                                                          flags)));
+    const bool guided = pg_on && pg_mode >= 1 && pg_hist >= 2;
+    if (guided) {
+      pg_guess(uu, w * dt);  // x[0] = learned guess
+      WL_TIMED(WL_K_DIVRES, (k_div_res<T, D><<<nb[0], kBlock, 0, stream>>>(g[0], v3(uu), nullptr, nullptr, wdt,
+                                                                            v3(L[0]), iD[0], x[0], r[0],
+                                                                            slot(kSlotRmax), red, flags)));
+    } else {
+      WL_TIMED(WL_K_DIVRES, (k_div_res<T, D><<<nb[0], kBlock, 0, stream>>>(g[0], v3(uu), nullptr, p, wdt, v3(L[0]),
+                                                                            iD[0], x[0], r[0], slot(kSlotRmax), red,
+                                                                            flags)));
+    }
     set_mean_producer(nb[0]);
     slot_n[kSlotRmax] = nb[0];
     WL_HIP(hipGetLastError());
     wl_status s = mg_loop(desc.mg_tol, desc.mg_itmax, st);
     if (s != WL_OK) return s;
+    if (guided && pg_mode == 2) pg_snapshot(w * dt);
+    if (pg_on) WL_HIP(hipMemcpyAsync(p2, p, plan.lev[0].elems * sizeof(T), hipMemcpyDeviceToDevice, stream));
     WL_TIMED(WL_K_PROJECT, (k_project<T, D><<<nb[0], kBlock, 0, stream>>>(g[0], v3(uu), v3(L[0]), x[0], p, wdt)));
     WL_HIP(hipGetLastError());
+    if (pg_on) ++pg_hist;
+    if (pg_on && pg_mode == 2 && ring_used > 0) {
+      for (int k = 0; k < pg_iters; ++k) {
+        const int slot_k = (int)(next_rand() % (uint64_t)ring_used);
+        pg_train_box(bcrop, ringX[slot_k], ringT[slot_k], ringM[slot_k], true);
+      }
+    }
+    return WL_OK;
+  }
+
+  // ---- learned initial guess --------------------------------------------------
+  uint64_t next_rand() {  // SplitMix64 stream
+    uint64_t z = (pg_rng += 0x9E3779B97F4A7C15ull);
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+  }
+
+  void pg_net(const PgBox& b, const unsigned short* X, unsigned short* a1, unsigned short* a2, float* y, int kid) {
+    const int64_t tasks = (int64_t)((b.n[0] + 15) / 16) * b.n[1] * b.n[2];
+    const int grid = (int)std::max<int64_t>(1, std::min<int64_t>((tasks + 3) / 4, kGridStride));
+    WL_TIMED(kid, (k_pg_conv<4, 0><<<grid, kBlock, 0, stream>>>(b, X, pgK.w1f, pgK.b1, a1, nullptr, nullptr)));
+    WL_TIMED(kid, (k_pg_conv<16, 0><<<grid, kBlock, 0, stream>>>(b, a1, pgK.w2f, pgK.b2, a2, nullptr, nullptr)));
+    WL_TIMED(kid, (k_pg_conv<16, 1><<<grid, kBlock, 0, stream>>>(b, a2, pgK.w3f, pgK.b3, nullptr, y, nullptr)));
+  }
+
+  void pg_guess(T* const uu[3], double wdt) {
+    WL_TIMED(WL_K_PG_INFER, (k_pg_moments<T, D><<<nb[0], kBlock, 0, stream>>>(g[0], p, iD[0], pgRed)));
+    WL_TIMED(WL_K_PG_INFER, (k_pg_norm<<<1, kBlock, 0, stream>>>(pgRed, nb[0], pgScal)));
+    WL_TIMED(WL_K_PG_INFER, (k_pg_features<T, D><<<nb[0], kBlock, 0, stream>>>(g[0], bd, v3(uu), p, p2, iD[0],
+                                                                                pgScal, wdt, pgXd)));
+    pg_net(bd, pgXd, pgA1d, pgA2d, pgYd, WL_K_PG_INFER);
+    WL_TIMED(WL_K_PG_INFER, (k_pg_guess<T, D><<<nb[0], kBlock, 0, stream>>>(g[0], bd, p, iD[0], pgYd, pgScal, wdt,
+                                                                             x[0])));
+  }
+
+  void pg_snapshot(double wdt) {
+    for (int c = 0; c < pg_crops; ++c) {
+      int o[3];
+      for (int a = 0; a < 3; ++a) o[a] = 1 + (int)(next_rand() % (uint64_t)(bd.n[a] - bcrop.n[a] + 1));
+      const int k = ring_next;
+      WL_TIMED(WL_K_PG_TRAIN, (k_pg_crop<T, D><<<blocks_for((int64_t)bcrop.n[0] * bcrop.n[1] * bcrop.n[2]), kBlock, 0, stream>>>(
+                                  g[0], bd, pgXd, x[0], p, iD[0], pgScal, wdt, o[0], o[1], o[2], bcrop, ringX[k], ringT[k],
+                                  ringM[k])));
+      ring_next = (ring_next + 1) % kPgRing;
+      ring_used = std::min(ring_used + 1, kPgRing);
+      ++pg_snaps;
+    }
+  }
+
+  // forward + loss + backward on a box (the crop buffers hold the activations);
+  // gradient into pgGrad, Adam step if apply
+  void pg_train_box(const PgBox& b, const unsigned short* X, const float* tgt, const unsigned char* msk, bool apply) {
+    const int K = WL_K_PG_TRAIN;
+    pg_net(b, X, pgA1c, pgA2c, pgYc, K);
+    const int gb = blocks_for((int64_t)b.n[0] * b.n[1] * b.n[2]);
+    WL_TIMED(K, (k_pg_err<<<gb, kBlock, 0, stream>>>(b, pgYc, tgt, msk, pgRed)));
+    WL_TIMED(K, (k_pg_dy<<<gb, kBlock, 0, stream>>>(b, pgYc, tgt, msk, pgRed, gb, pgG3, pgRed + 4096)));
+    pg_loss_blocks = gb;
+    pg_loss_pending = true;
+    const int64_t tasks = (int64_t)((b.n[0] + 15) / 16) * b.n[1] * b.n[2];
+    const int grid = (int)std::max<int64_t>(1, std::min<int64_t>((tasks + 3) / 4, kGridStride));
+    WL_TIMED(K, (k_pg_conv<16, 2><<<grid, kBlock, 0, stream>>>(b, pgG3, pgK.w3b, nullptr, pgG2, nullptr, pgA2c)));
+    WL_TIMED(K, (k_pg_conv<16, 2><<<grid, kBlock, 0, stream>>>(b, pgG2, pgK.w2b, nullptr, pgG1, nullptr, pgA1c)));
+    const int wb = kPgWaves / 4;
+    WL_TIMED(K, (k_pg_wgrad<16><<<wb, kBlock, 0, stream>>>(b, pgA2c, pgG3, pgPart)));
+    WL_TIMED(K, (k_pg_wgrad_reduce<<<32, kBlock, 0, stream>>>(pgPart, kPgWaves, 16, 1, pgGrad + kPgW3, pgGrad + kPgB3)));
+    WL_TIMED(K, (k_pg_wgrad<16><<<wb, kBlock, 0, stream>>>(b, pgA1c, pgG2, pgPart)));
+    WL_TIMED(K, (k_pg_wgrad_reduce<<<32, kBlock, 0, stream>>>(pgPart, kPgWaves, 16, 16, pgGrad + kPgW2, pgGrad + kPgB2)));
+    WL_TIMED(K, (k_pg_wgrad<4><<<wb, kBlock, 0, stream>>>(b, X, pgG1, pgPart)));
+    WL_TIMED(K, (k_pg_wgrad_reduce<<<32, kBlock, 0, stream>>>(pgPart, kPgWaves, 3, 16, pgGrad + kPgW1, pgGrad + kPgB1)));
+    ++pg_train_steps;
+    if (apply) {
+      ++pg_adam_t;
+      const float b1 = 0.9f, b2 = 0.999f;
+      const float c1 = 1.f - (float)std::pow(0.9, (double)pg_adam_t), c2 = 1.f - (float)std::pow(0.999, (double)pg_adam_t);
+      WL_TIMED(K, (k_pg_adam<<<blocks_for(kPgParams), kBlock, 0, stream>>>(pgW, pgM, pgV, pgGrad, (float)pg_lr, b1, b2,
+                                                                           c1, c2, 1e-8f, 1)));
+      WL_TIMED(K, (k_pg_pack<<<blocks_for(27 * 256), kBlock, 0, stream>>>(pgW, pgK)));
+    }
+  }
+  int pg_loss_blocks = 0;
+
+  wl_status pg_require() const {
+    if (!pg_on) return fail(WL_ERR_UNSUPPORTED, "learned guess needs desc.learned_guess = 1 and ndim = 3");
+    return WL_OK;
+  }
+
+  wl_status pg_set_weights(const float* w) override {
+    if (pg_require() != WL_OK) return WL_ERR_UNSUPPORTED;
+    if (!w) return fail(WL_ERR_INVALID_ARG, "weights are NULL");
+    for (int k = 0; k < kPgParams; ++k)
+      if (!std::isfinite(w[k])) return fail(WL_ERR_INVALID_ARG, "weights must be finite");
+    WL_HIP(hipMemcpyAsync(pgW, w, kPgParams * sizeof(float), hipMemcpyHostToDevice, stream));
+    WL_HIP(hipMemsetAsync(pgM, 0, kPgParams * sizeof(float), stream));
+    WL_HIP(hipMemsetAsync(pgV, 0, kPgParams * sizeof(float), stream));
+    k_pg_pack<<<blocks_for(27 * 256), kBlock, 0, stream>>>(pgW, pgK);
+    WL_HIP(hipGetLastError());
+    WL_HIP(hipStreamSynchronize(stream));
+    pg_adam_t = 0;
+    pg_weights_set = true;
+    return WL_OK;
+  }
+
+  wl_status pg_get_weights(float* w) override {
+    if (pg_require() != WL_OK) return WL_ERR_UNSUPPORTED;
+    if (!w) return fail(WL_ERR_INVALID_ARG, "output is NULL");
+    WL_HIP(hipMemcpyAsync(w, pgW, kPgParams * sizeof(float), hipMemcpyDeviceToHost, stream));
+    WL_HIP(hipStreamSynchronize(stream));
+    return WL_OK;
+  }
+
+  wl_status pg_set_mode(int mode, double lr, int iters, int crops, uint64_t seed) override {
+    if (pg_require() != WL_OK) return WL_ERR_UNSUPPORTED;
+    if (mode < 0 || mode > 2 || !(lr >= 0.0) || iters < 0 || crops < 0 || crops > kPgRing)
+      return fail(WL_ERR_INVALID_ARG, "mode in 0..2, lr >= 0, iters >= 0, crops in 0..64");
+    if (mode >= 1 && !pg_weights_set) return fail(WL_ERR_INVALID_ARG, "set the weights before enabling the guess");
+    pg_mode = mode;
+    pg_lr = lr;
+    pg_iters = iters;
+    pg_crops = crops;
+    pg_rng = seed;
+    return WL_OK;
+  }
+
+  wl_status pg_box(const int64_t n[3], PgBox& b) const {
+    if (!n) return fail(WL_ERR_INVALID_ARG, "box size is NULL");
+    for (int a = 0; a < 3; ++a) {
+      if (n[a] < 1 || n[a] > bcrop.n[a]) return fail(WL_ERR_INVALID_ARG, "box must fit the training crop");
+      b.n[a] = (int)n[a];
+      b.P[a] = b.n[a] + 2;
+    }
+    return WL_OK;
+  }
+
+  wl_status pg_forward(const void* xin, const int64_t n[3], float* y) override {
+    if (pg_require() != WL_OK) return WL_ERR_UNSUPPORTED;
+    PgBox b;
+    if (pg_box(n, b) != WL_OK) return WL_ERR_INVALID_ARG;
+    if (!xin || !y) return fail(WL_ERR_INVALID_ARG, "box arrays are NULL");
+    WL_HIP(hipMemsetAsync(pgA1c, 0, (size_t)pgPc * 32, stream));
+    WL_HIP(hipMemsetAsync(pgA2c, 0, (size_t)pgPc * 32, stream));
+    pg_net(b, (const unsigned short*)xin, pgA1c, pgA2c, y, WL_K_PG_INFER);
+    WL_HIP(hipGetLastError());
+    return WL_OK;
+  }
+
+  wl_status read_loss() {
+    if (!pg_loss_pending) return WL_OK;
+    std::vector<double> h(pg_loss_blocks);
+    WL_HIP(hipMemcpyAsync(h.data(), pgRed + 4096, h.size() * sizeof(double), hipMemcpyDeviceToHost, stream));
+    WL_HIP(hipStreamSynchronize(stream));
+    double l = 0;
+    for (double v : h) l += v;
+    pg_last_loss = l;
+    pg_loss_pending = false;
+    return WL_OK;
+  }
+
+  wl_status pg_train(const void* xin, const float* tg, const unsigned char* mk, const int64_t n[3], float* grad,
+                     double* loss, int apply) override {
+    if (pg_require() != WL_OK) return WL_ERR_UNSUPPORTED;
+    PgBox b;
+    if (pg_box(n, b) != WL_OK) return WL_ERR_INVALID_ARG;
+    if (!xin || !tg || !mk) return fail(WL_ERR_INVALID_ARG, "box arrays are NULL");
+    if (!pg_weights_set) return fail(WL_ERR_INVALID_ARG, "set the weights first");
+    // box layout differs from the crop layout: clear the halos of the activation buffers
+    for (unsigned short* bptr : {pgA1c, pgA2c, pgG3, pgG2, pgG1})
+      WL_HIP(hipMemsetAsync(bptr, 0, (size_t)pgPc * 32, stream));
+    pg_train_box(b, (const unsigned short*)xin, tg, mk, apply != 0);
+    WL_HIP(hipGetLastError());
+    if (grad) {
+      WL_HIP(hipMemcpyAsync(grad, pgGrad, kPgParams * sizeof(float), hipMemcpyDeviceToHost, stream));
+    }
+    wl_status s = read_loss();
+    if (s != WL_OK) return s;
+    if (loss) *loss = pg_last_loss;
+    // restore clean crop-layout buffers for the online training
+    for (unsigned short* bptr : {pgA1c, pgA2c, pgG3, pgG2, pgG1})
+      WL_HIP(hipMemsetAsync(bptr, 0, (size_t)pgPc * 32, stream));
+    WL_HIP(hipStreamSynchronize(stream));
+    return WL_OK;
+  }
+
+  wl_status pg_stats(double* loss, int64_t* steps, int64_t* snaps) override {
+    if (pg_require() != WL_OK) return WL_ERR_UNSUPPORTED;
+    wl_status s = read_loss();
+    if (s != WL_OK) return s;
+    if (loss) *loss = pg_last_loss;
+    if (steps) *steps = pg_train_steps;
+    if (snaps) *snaps = pg_snaps;
     return WL_OK;
   }
 
@@ -986,6 +1298,37 @@ wl_status wl_profile(wl_sim* sim, int enable) {
 wl_status wl_profile_read(wl_sim* sim, int kernel, double* total_ms, int64_t* launches) {
   WL_SIM_CHECK(sim);
   return sim->impl->profile_read(kernel, total_ms, launches);
+}
+
+wl_status wl_pg_set_weights(wl_sim* sim, const float* host_params) {
+  WL_SIM_CHECK(sim);
+  return sim->impl->pg_set_weights(host_params);
+}
+
+wl_status wl_pg_get_weights(wl_sim* sim, float* host_params) {
+  WL_SIM_CHECK(sim);
+  return sim->impl->pg_get_weights(host_params);
+}
+
+wl_status wl_pg_mode(wl_sim* sim, int mode, double lr, int train_iters, int crops, uint64_t seed) {
+  WL_SIM_CHECK(sim);
+  return sim->impl->pg_set_mode(mode, lr, train_iters, crops, seed);
+}
+
+wl_status wl_pg_forward(wl_sim* sim, const void* x_box, const int64_t n[3], float* y_out) {
+  WL_SIM_CHECK(sim);
+  return sim->impl->pg_forward(x_box, n, y_out);
+}
+
+wl_status wl_pg_train_step(wl_sim* sim, const void* x_box, const float* target, const unsigned char* mask,
+                           const int64_t n[3], float* grad_out, double* loss, int apply) {
+  WL_SIM_CHECK(sim);
+  return sim->impl->pg_train(x_box, target, mask, n, grad_out, loss, apply);
+}
+
+wl_status wl_pg_stats(wl_sim* sim, double* last_loss, int64_t* train_steps, int64_t* snapshots) {
+  WL_SIM_CHECK(sim);
+  return sim->impl->pg_stats(last_loss, train_steps, snapshots);
 }
 
 const char* wl_last_error(void) { return g_err.c_str(); }

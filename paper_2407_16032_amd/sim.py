@@ -42,7 +42,7 @@ class Simulation:
                  periodic: Sequence[bool] = (), convective_exit: bool = False, prec: str = "f32",
                  eps: float = 1.0, dt0: float = 0.25, dt_max: float = 10.0, cfl_nu: float = 5.0,
                  tol: float = 1e-6, itmax: int = 32, pcg_iters: int = 6, device="cuda:0",
-                 stream: Optional[torch.cuda.Stream] = None):
+                 stream: Optional[torch.cuda.Stream] = None, learned_guess: bool = False):
         self.lib = L.load()
         nd = len(n)
         d = L.SimDesc()
@@ -56,6 +56,7 @@ class Simulation:
         d.prec = L.WL_F64 if prec == "f64" else L.WL_F32
         d.eps, d.dt0, d.dt_max, d.cfl_nu_coef = eps, dt0, dt_max, cfl_nu
         d.mg_tol, d.mg_itmax, d.pcg_iters = tol, itmax, pcg_iters
+        d.learned_guess = 1 if learned_guess else 0
         self.desc = d
         self.bdesc = _body_desc(body)
         self.ndim = nd
@@ -175,6 +176,52 @@ class Simulation:
             L.check(self.lib.wl_profile_read(self._h, k, C.byref(ms), C.byref(n)), "wl_profile_read")
             out[name] = (ms.value, n.value)
         return out
+
+    # ------------------------------------------------ learned initial guess
+    def pg_set_weights(self, flat):
+        import numpy as np
+        w = np.ascontiguousarray(flat, dtype=np.float32)
+        assert w.size == L.PG_PARAMS
+        L.check(self.lib.wl_pg_set_weights(self._h, w.ctypes.data_as(C.POINTER(C.c_float))), "wl_pg_set_weights")
+
+    def pg_get_weights(self):
+        import numpy as np
+        w = np.zeros(L.PG_PARAMS, dtype=np.float32)
+        L.check(self.lib.wl_pg_get_weights(self._h, w.ctypes.data_as(C.POINTER(C.c_float))), "wl_pg_get_weights")
+        return w
+
+    def pg_mode(self, mode: int, lr: float = 1e-3, train_iters: int = 1, crops: int = 2, seed: int = 0):
+        L.check(self.lib.wl_pg_mode(self._h, int(mode), float(lr), int(train_iters), int(crops), int(seed)),
+                "wl_pg_mode")
+
+    @staticmethod
+    def _box(n):
+        return (C.c_int64 * 3)(*[int(v) for v in n])
+
+    def pg_forward(self, x_box: torch.Tensor, n) -> torch.Tensor:
+        """x_box: bfloat16 device tensor [P, 4] on the box n (with halo); returns y [P] float32."""
+        y = torch.zeros(x_box.shape[0], dtype=torch.float32, device=self.device)
+        L.check(self.lib.wl_pg_forward(self._h, C.c_void_p(x_box.data_ptr()), self._box(n),
+                                       C.c_void_p(y.data_ptr())), "wl_pg_forward")
+        torch.cuda.synchronize(self.device)
+        return y
+
+    def pg_train_step(self, x_box, target, mask, n, apply: bool = False):
+        import numpy as np
+        g = np.zeros(L.PG_PARAMS, dtype=np.float32)
+        loss = C.c_double()
+        L.check(self.lib.wl_pg_train_step(self._h, C.c_void_p(x_box.data_ptr()), C.c_void_p(target.data_ptr()),
+                                          C.c_void_p(mask.data_ptr()), self._box(n),
+                                          g.ctypes.data_as(C.POINTER(C.c_float)), C.byref(loss),
+                                          1 if apply else 0), "wl_pg_train_step")
+        return g, loss.value
+
+    def pg_stats(self):
+        loss = C.c_double()
+        steps = C.c_int64()
+        snaps = C.c_int64()
+        L.check(self.lib.wl_pg_stats(self._h, C.byref(loss), C.byref(steps), C.byref(snaps)), "wl_pg_stats")
+        return {"loss": loss.value, "train_steps": steps.value, "snapshots": snaps.value}
 
     def set_time(self, t: float, dt_next: float):
         L.check(self.lib.wl_set_time(self._h, float(t), float(dt_next)), "wl_set_time")

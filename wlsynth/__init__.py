@@ -220,3 +220,38 @@ def tgv2d_exact(n: int, nu: float, t: float, U: float = 1.0):
 def random_field(shape, seed: int, comp: int = 0, amp: float = 1.0):
     """Generic seeded test field U[-amp, amp)."""
     return face_noise(shape, comp, amp, seed)
+
+
+# ---------------------------------------------------------------------------
+# initial weights of the learned multigrid guess (an input: drawn here, used by
+# both the oracle and the HIP path)
+# ---------------------------------------------------------------------------
+PG_SHAPES = [(27, 3, 16), (16,), (27, 16, 16), (16,), (27, 16, 1), (1,)]
+
+
+def pg_init_weights(seed: int = 0) -> np.ndarray:
+    """Kaiming-uniform weights (bound sqrt(6 / fan_in), fan_in = 27 c_in), zero biases,
+    flat float32 in the order W1 b1 W2 b2 W3 b3 with W[tap][c_in][c_out]."""
+    parts = []
+    k = 0
+    for shp in PG_SHAPES:
+        n = int(np.prod(shp))
+        if len(shp) == 3:
+            bound = float(np.sqrt(6.0 / (27 * shp[1])))
+            counter = np.arange(k, k + n, dtype=np.uint64)
+            parts.append(((2.0 * uniform01(counter, seed + 12345) - 1.0) * bound).astype(np.float32))
+        else:
+            parts.append(np.zeros(n, dtype=np.float32))
+        k += n
+    return np.concatenate(parts)
+
+
+def pg_split(flat):
+    """Flat parameter vector -> [W1, b1, W2, b2, W3, b3] float64 arrays."""
+    out = []
+    k = 0
+    for shp in PG_SHAPES:
+        n = int(np.prod(shp))
+        out.append(np.asarray(flat[k:k + n], dtype=np.float64).reshape(shp))
+        k += n
+    return out
