@@ -26,15 +26,16 @@ MU0_CUT = 1e-6
 
 
 def motion(body, t):
-    """(c, P, theta, cdot, omega) at time t, each as float / 3-tuples."""
+    """(c, P, theta, cdot, omega) at time t (numpy scalars, so that complex parameters
+    carry complex-step derivatives)."""
     w = 2.0 * math.pi * body.freq
     c = list(body.center) + [0.0] * (3 - len(body.center))
-    c[1] += body.heave_amp * math.sin(w * t + body.phase_h)
+    c[1] += body.heave_amp * np.sin(w * t + body.phase_h)
     po = list(body.pivot_offset) + [0.0] * (3 - len(body.pivot_offset))
     P = [c[k] + po[k] for k in range(3)]
-    theta = body.pitch_amp * math.sin(w * t + body.phase_p) + body.spin_omega * t
-    cdot = [0.0, body.heave_amp * w * math.cos(w * t + body.phase_h), 0.0]
-    omega = body.pitch_amp * w * math.cos(w * t + body.phase_p) + body.spin_omega
+    theta = body.pitch_amp * np.sin(w * t + body.phase_p) + body.spin_omega * t
+    cdot = [0.0, body.heave_amp * w * np.cos(w * t + body.phase_h), 0.0]
+    omega = body.pitch_amp * w * np.cos(w * t + body.phase_p) + body.spin_omega
     return c, P, theta, cdot, omega
 
 
@@ -48,7 +49,7 @@ def sdf_normal_velocity(body, X, t):
     ndim = len(X)
     c, P, theta, cdot, omega = motion(body, t)
     po = list(body.pivot_offset) + [0.0] * 3
-    ct, st = math.cos(theta), math.sin(theta)
+    ct, st = np.cos(theta), np.sin(theta)
     rx = X[0] - P[0]
     ry = X[1] - P[1]
     # body frame coordinates
@@ -134,13 +135,15 @@ def measure(grid, body, t, eps=1.0):
     return m0, m1, V
 
 
-def forces(grid, body, t, u, p, nu, eps=1.0):
+def forces(grid, body, t, u, p, nu, eps=1.0, active=None):
     """Pressure and viscous force on the body (FP64 sums over interior cells).
 
     Surface integrals become volume sums weighted by the smoothed delta
-    K_eps(d) at the cell centres:  F_p = -sum p n K_eps,
+    K_eps(d) at the cell centres:  F_p = -sum (p - pbar) n K_eps,
     F_v = sum 2 nu S n K_eps with S = (grad u + grad u^T)/2 from central
     differences at the cell centre (face values averaged to the centre).
+    The pressure is defined up to a constant; pbar is its mean over the
+    cells passed as ``active`` (all interior cells if None), which fixes the gauge.
     """
     nd = grid.ndim
     Xc = cell_points(grid)
@@ -148,6 +151,8 @@ def forces(grid, body, t, u, p, nu, eps=1.0):
     w = kernel_eps(d, eps)
     inner = grid.interior_mask()
     w = np.where(inner, w, 0.0)
+    act = inner if active is None else active
+    p = p - np.mean(p[act])
     Fp = np.array([-np.sum(p * n[i] * w) for i in range(nd)])
     # velocity gradient at cell centres: G[i][j] = d u_i / d x_j
     G = [[None] * nd for _ in range(nd)]
@@ -160,7 +165,7 @@ def forces(grid, body, t, u, p, nu, eps=1.0):
                 G[i][j] = up - ui
             else:
                 G[i][j] = 0.5 * (grid.sh(ubar, j, +1) - grid.sh(ubar, j, -1))
-    Fv = np.zeros(nd)
+    Fv = np.zeros(nd, dtype=np.result_type(u[0], p, w))
     for i in range(nd):
         acc = np.zeros(grid.shape)
         for j in range(nd):

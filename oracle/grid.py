@@ -70,8 +70,8 @@ class Grid:
         m[tuple(sl)] = True
         return m
 
-    def zeros(self) -> np.ndarray:
-        return np.zeros(self.shape, dtype=np.float64)
+    def zeros(self, dtype=np.float64) -> np.ndarray:
+        return np.zeros(self.shape, dtype=dtype)
 
     def coarsenable(self) -> bool:
         """Multigrid coarsening rule: every interior size even, coarse min >= 4."""

@@ -16,21 +16,21 @@ import numpy as np
 
 
 def kernel(s):
-    s = np.asarray(s, dtype=np.float64)
-    return np.where(np.abs(s) < 1.0, 0.5 * (1.0 + np.cos(np.pi * s)), 0.0)
+    s = np.asarray(s)
+    return np.where(np.abs(np.real(s)) < 1.0, 0.5 * (1.0 + np.cos(np.pi * s)), 0.0)
 
 
 def kernel_eps(d, eps=1.0):
     """Smoothed surface delta K(d/eps)/eps."""
-    return kernel(np.asarray(d, dtype=np.float64) / eps) / eps
+    return kernel(np.asarray(d) / eps) / eps
 
 
 def mu0(d, eps=1.0):
-    s = np.clip(np.asarray(d, dtype=np.float64) / eps, -1.0, 1.0)
+    s = np.clip(np.asarray(d) / eps, -1.0, 1.0)
     return 0.5 * (1.0 + s) + np.sin(np.pi * s) / (2.0 * np.pi)
 
 
 def mu1(d, eps=1.0):
-    s = np.clip(np.asarray(d, dtype=np.float64) / eps, -1.0, 1.0)
+    s = np.clip(np.asarray(d) / eps, -1.0, 1.0)
     return eps * (0.25 * (1.0 - s * s)
                   - (s * np.sin(np.pi * s) + (1.0 + np.cos(np.pi * s)) / np.pi) / (2.0 * np.pi))

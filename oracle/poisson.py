@@ -66,7 +66,7 @@ def boundary_zeroed(grid: Grid, mu0):
 def coarsen_L(gf: Grid, Lf, gc: Grid):
     Lc = []
     for i in range(gf.ndim):
-        a = gc.zeros()
+        a = gc.zeros(Lf[i].dtype)
         src = Lf[i]
         # along i: fine face index 2J-1 for J = 1..Nc+1
         sl = [slice(None)] * gf.ndim
@@ -109,7 +109,8 @@ def apply_A(lev: Level, x):
 
 
 def dot(a, b):
-    return float(np.sum(a * b))
+    # bilinear (no conjugation), so complex-step derivatives pass through the solve
+    return np.sum(a * b)
 
 
 def restrict(gf: Grid, gc: Grid, r):
@@ -118,7 +119,7 @@ def restrict(gf: Grid, gc: Grid, r):
     for Nc in gc.n:
         shp += [Nc, 2]
     s = s.reshape(shp).sum(axis=tuple(range(1, 2 * gf.ndim, 2)))
-    out = gc.zeros()
+    out = gc.zeros(r.dtype)
     out[gc.interior()] = s
     return out
 
@@ -127,7 +128,7 @@ def prolong(gf: Grid, xc):
     s = xc[tuple(slice(1, N + 1) for N in (v // 2 for v in gf.n))]
     for k in range(gf.ndim):
         s = np.repeat(s, 2, axis=k)
-    out = gf.zeros()
+    out = gf.zeros(xc.dtype)
     out[gf.interior()] = s
     return out
 
@@ -163,7 +164,7 @@ def pcg(lev: Level, x, r, iters):
 def vcycle(levels, l, x, r, iters):
     f, c = levels[l], levels[l + 1]
     rc = np.where(c.active, restrict(f.grid, c.grid, r), 0.0)
-    xc = c.grid.zeros()
+    xc = c.grid.zeros(rc.dtype)
     if l + 2 < len(levels):
         vcycle(levels, l + 1, xc, rc, iters)
     pcg(c, xc, rc, iters)
@@ -190,7 +191,7 @@ def solve(levels, x, z, tol, itmax=32, iters=6):
         n += 1
         res = float(np.max(np.abs(r)))
     return {"vcycles": n, "res0_linf": res0, "res_linf": res,
-            "res_l2": float(np.sqrt(np.sum(r * r))), "converged": res < tol, "r": r}
+            "res_l2": float(np.sqrt(np.sum(np.abs(r) ** 2))), "converged": res < tol, "r": r}
 
 
 def divergence(grid: Grid, u):

@@ -68,8 +68,8 @@ def exit_plane(grid: Grid, U, u0, dt):
     ub = u0[0][(N,) + inner]
     e = ue - dt * U[0] * (ue - ub)
     count = e.size
-    inlet = float(np.sum(np.full(e.shape, float(U[0]))))
-    shift = (inlet - float(np.sum(e))) / count
+    inlet = np.sum(np.full(e.shape, float(U[0])))
+    shift = (inlet - np.sum(e)) / count
     return e + shift
 
 
@@ -90,7 +90,7 @@ def cfl(grid: Grid, u, nu, dt_max=10.0, cfl_nu=5.0):
     s = grid.zeros()
     for i in range(grid.ndim):
         s = s + np.maximum(0.0, grid.sh(u[i], i, +1)) + np.maximum(0.0, -u[i])
-    smax = float(np.max(s[grid.interior()]))
+    smax = float(np.max(np.real(s[grid.interior()])))
     denom = smax + cfl_nu * nu
     return dt_max if denom <= 0.0 else min(dt_max, 1.0 / denom)
 
@@ -114,6 +114,7 @@ class Sim:
         self.itmax = int(itmax)
         self.pcg_iters = int(pcg_iters)
         self.t = 0.0
+        self.dt_schedule = None          # frozen time steps (list), else CFL
         self.u = [np.full(g.shape, self.U[i]) for i in range(g.ndim)]
         self.p = g.zeros()
         self.exit_e = None
@@ -138,7 +139,7 @@ class Sim:
     def project(self, w, tol=None):
         g = self.grid
         z = _poisson.divergence(g, self.u)
-        x = self.p * (w * self.dt)
+        x = (self.p * (w * self.dt)).astype(np.result_type(self.p, z, self.L[0], self.dt))
         st = _poisson.solve(self.levels, x, z, self.tol if tol is None else tol, self.itmax,
                             self.pcg_iters)
         for i in range(g.ndim):
@@ -172,6 +173,8 @@ class Sim:
         apply_bc(g, self.U, self.u, self.exit_e)
         self.t += dt
         self.dt = cfl(g, self.u, self.nu, self.dt_max, self.cfl_nu)
+        if self.dt_schedule is not None and len(self.stats) + 1 < len(self.dt_schedule):
+            self.dt = self.dt_schedule[len(self.stats) + 1]
         st = {"dt": dt, "t": self.t, "vcycles": (s1["vcycles"], s2["vcycles"]),
               "res_linf": (s1["res_linf"], s2["res_linf"]),
               "div_linf": float(np.max(np.abs(_poisson.divergence(g, self.u)[
@@ -182,7 +185,8 @@ class Sim:
     def forces(self):
         if self.body is None:
             return np.zeros(self.grid.ndim), np.zeros(self.grid.ndim)
-        return _body.forces(self.grid, self.body, self.t, self.u, self.p, self.nu, self.eps)
+        return _body.forces(self.grid, self.body, self.t, self.u, self.p, self.nu, self.eps,
+                            active=self.levels[0].active)
 
     def ke(self):
         """Kinetic energy sum of u_i^2/2 over the interior faces (diagnostic)."""

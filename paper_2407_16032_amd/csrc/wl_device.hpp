@@ -18,8 +18,9 @@ constexpr int kSlotSig0 = kMaxPcg + 1;         // sigma_k for k = 0..kMaxPcg-1
 constexpr int kSlotRmax = 2 * kMaxPcg + 1;     // residual max-norm
 constexpr int kSlotCfl = kSlotRmax + 1;        // max outflux
 constexpr int kSlotExit = kSlotCfl + 1;        // exit-plane flux
-constexpr int kSlotForce = kSlotExit + 1;      // 6 slots: pressure xyz, viscous xyz
-constexpr int kSlotSumR = kSlotForce + 6;      // sum of the residual over active cells
+constexpr int kSlotForce = kSlotExit + 1;      // 11 slots: sum p n K (3), viscous (3), sum n K (3),
+                                               // sum p and count over active cells
+constexpr int kSlotSumR = kSlotForce + 11;     // sum of the residual over active cells
 constexpr int kSlotCnt = kSlotSumR + 1;        // number of active cells
 constexpr int kNumSlots = kSlotCnt + 1;
 

@@ -941,22 +941,31 @@ __global__ void __launch_bounds__(kBlock) k_cfl(Grid3 g, Vec3<T> u, double* part
   if (threadIdx.x == 0) part[blockIdx.x] = mx;
 }
 
-// forces: F_p = -sum p n K_eps(d), F_v = sum 2 nu S n K_eps(d) at cell centres (FP64).
+// forces: F_p = -sum (p - pbar) n K_eps(d), F_v = sum 2 nu S n K_eps(d) at cell centres
+// (FP64), pbar = mean of p over active cells.  Partials: sum p n K, sum 2 nu S n K,
+// sum n K, sum_active p, active count; the host combines them.
 template <typename T, int D>
 __global__ void __launch_bounds__(kBlock) k_forces(Grid3 g, BodyP b, Motion m, double eps, double nu,
-                                                   Vec3<T> u, const T* p, double* red) {
+                                                   Vec3<T> u, const T* p, const T* iD, double* red) {
 #pragma clang fp contract(off)
   const int total = g.n[0] * g.n[1] * ((D == 3) ? g.n[2] : 1);
-  double fp[3] = {0, 0, 0}, fv[3] = {0, 0, 0};
+  double fp[3] = {0, 0, 0}, fv[3] = {0, 0, 0}, nk[3] = {0, 0, 0}, ps = 0.0, pc = 0.0;
   for (int lin = blockIdx.x * kBlock + threadIdx.x; lin < total; lin += gridDim.x * kBlock) {
     int I[3], idx;
     cell_of<D>(g, lin, I, idx);
+    if (iD[idx] != T(0)) {
+      ps += double(p[idx]);
+      pc += 1.0;
+    }
     double x[3] = {I[0] - 0.5, I[1] - 0.5, I[2] - 0.5}, d, n[3], V[3];
     body_eval<D>(b, m, x, d, n, V);
     const double w = kern_K(d, eps);
     if (w == 0.0) continue;
-    const double pc = double(p[idx]);
-    for (int a = 0; a < D; ++a) fp[a] += pc * n[a] * w;
+    const double pv = double(p[idx]);
+    for (int a = 0; a < D; ++a) {
+      fp[a] += pv * n[a] * w;
+      nk[a] += n[a] * w;
+    }
     // velocity gradient G[i][j] = d u_i / d x_j at the cell centre
     double G[3][3];
     for (int i = 0; i < D; ++i) {
@@ -980,12 +989,20 @@ __global__ void __launch_bounds__(kBlock) k_forces(Grid3 g, BodyP b, Motion m, d
     }
   }
   for (int a = 0; a < 3; ++a) {
-    const double sp = block_sum(-fp[a]);
+    const double sp = block_sum(fp[a]);
     const double sv = block_sum(fv[a]);
+    const double sn = block_sum(nk[a]);
     if (threadIdx.x == 0) {
       red[(size_t)(kSlotForce + a) * kMaxBlocks + blockIdx.x] = sp;
       red[(size_t)(kSlotForce + 3 + a) * kMaxBlocks + blockIdx.x] = sv;
+      red[(size_t)(kSlotForce + 6 + a) * kMaxBlocks + blockIdx.x] = sn;
     }
+  }
+  ps = block_sum(ps);
+  pc = block_sum(pc);
+  if (threadIdx.x == 0) {
+    red[(size_t)(kSlotForce + 9) * kMaxBlocks + blockIdx.x] = ps;
+    red[(size_t)(kSlotForce + 10) * kMaxBlocks + blockIdx.x] = pc;
   }
 }
 

@@ -1057,20 +1057,22 @@ struct Impl : SimBase {
     Motion m{};
     host_motion(bdesc, t, m);
     WL_TIMED(WL_K_FORCES, (k_forces<T, D><<<nb[0], kBlock, 0, stream>>>(g[0], body, m, desc.eps, desc.nu,
-                                                                         v3(u[cur]), p, red)));
+                                                                         v3(u[cur]), p, iD[0], red)));
     WL_HIP(hipGetLastError());
-    std::vector<double> h((size_t)6 * kMaxBlocks);
+    std::vector<double> h((size_t)11 * kMaxBlocks);
     WL_HIP(hipMemcpyAsync(h.data(), slot(kSlotForce), h.size() * sizeof(double), hipMemcpyDeviceToHost, stream));
     WL_HIP(hipStreamSynchronize(stream));
     prof.harvest();
+    auto tot = [&](int k) {
+      double s_ = 0;
+      for (int b = 0; b < nb[0]; ++b) s_ += h[(size_t)k * kMaxBlocks + b];
+      return s_;
+    };
+    const double cnt = tot(10);
+    const double pbar = cnt > 0 ? tot(9) / cnt : 0.0;
     for (int a = 0; a < 3; ++a) {
-      double sp = 0, sv = 0;
-      for (int b = 0; b < nb[0]; ++b) {
-        sp += h[(size_t)a * kMaxBlocks + b];
-        sv += h[(size_t)(3 + a) * kMaxBlocks + b];
-      }
-      fp[a] = sp;
-      fv[a] = sv;
+      fp[a] = -(tot(a) - pbar * tot(6 + a));
+      fv[a] = tot(3 + a);
     }
     return WL_OK;
   }

@@ -96,10 +96,14 @@ def test_gradients_and_adam_match_oracle():
     _say("  loss gpu %.6f oracle %.6f" % (loss, loss_ref))
     assert loss == pytest.approx(loss_ref, rel=2e-2)
     gs = wlsynth.pg_split(g)
-    for k, name in enumerate(["W1", "b1", "W2", "b2", "W3", "b3"]):
+    for k, name in enumerate(["W1", "b1", "W2", "b2", "W3"]):
         err = _rel(gs[k], g_ref[k])
         _say("  grad %s rel err %.3e" % (name, err))
         assert err < 2e-2, name
+    # the loss is invariant to a constant output shift: d loss / d b3 = sum dy = 0 exactly;
+    # on the GPU it is the sum of the BF16-rounded dy
+    _say("  grad b3 gpu %.3e oracle %.3e" % (gs[5][0], g_ref[5][0]))
+    assert abs(g_ref[5][0]) < 1e-12 and abs(gs[5][0]) < 1e-3
     # one Adam step on the master weights with the GPU's own gradient
     g2, _ = sim.pg_train_step(_box_tensor(x, 4), _box_scalar(t, np.float32),
                               _box_scalar(m.astype(np.uint8), np.uint8), n, apply=True)
