@@ -77,6 +77,7 @@ typedef struct {
   int mg_itmax;          /* maximum V-cycles per solve [32] */
   int pcg_iters;         /* PCG smoothing iterations per level [6] */
   int learned_guess;     /* 1 -> plan the buffers of the learned initial guess (3-D only) */
+  int adjoint;           /* 1 -> plan the buffers of the discrete adjoint (wl_adj_*) */
 } wl_sim_desc;
 
 typedef enum { WL_BODY_NONE = 0, WL_BODY_SPHERE = 1, WL_BODY_BOX = 2 } wl_body_kind;
@@ -164,8 +165,12 @@ wl_status wl_project(wl_sim* sim, double w, wl_solve_stats* stats);
 wl_status wl_poisson_solve(wl_sim* sim, const void* rhs, void* x_inout, double tol, int itmax,
                            wl_solve_stats* stats);
 
-/* Pressure and viscous force on the body at the current time (FP64 sums):
- * F_p = -sum p n K_eps(d), F_v = sum 2 nu S n K_eps(d) over cell centres. */
+/* Pressure and viscous force on the body at the current time (FP64 sums over
+ * cell centres; paper, results sections: forces as integrals of the surface
+ * stress weighted by the smoothed surface delta K_eps(d)):
+ *   F_p = -sum (p - pbar) n K_eps(d),   F_v = sum 2 nu S n K_eps(d),
+ * pbar = mean of p over active cells (the pressure's gauge drops out), S the
+ * strain rate of u interpolated to the cell centre. */
 wl_status wl_forces(wl_sim* sim, double f_pressure[3], double f_viscous[3]);
 
 enum {
@@ -179,7 +184,9 @@ enum {
   WL_FIELD_X = 7,     /* multigrid solution on level `level` */
   WL_FIELD_R = 8,     /* multigrid residual on level `level` */
   WL_FIELD_L = 9,     /* Poisson coefficients on level `level`, ndim components */
-  WL_FIELD_ID = 10    /* inverse diagonal on level `level` (0 on solid cells) */
+  WL_FIELD_ID = 10,   /* inverse diagonal on level `level` (0 on solid cells) */
+  WL_FIELD_ADJ_U = 11,/* adjoint of the current velocity, ndim components (desc.adjoint) */
+  WL_FIELD_ADJ_P = 12 /* adjoint of the current pressure (desc.adjoint) */
 };
 
 /* Zero-copy view of a field inside the workspace.  shape = {components, pz,
@@ -194,6 +201,58 @@ wl_status wl_levels(wl_sim* sim, int* nlevels, int level, int64_t n_out[3]);
 /* Set the clock and the next time step. */
 wl_status wl_set_time(wl_sim* sim, double t, double dt_next);
 wl_status wl_get_time(wl_sim* sim, double* t, double* dt_next);
+
+/* Replace the body's parameters (same kind) and re-measure at the current time. */
+wl_status wl_body_update(wl_sim* sim, const wl_body_desc* body);
+
+/* ---------------------------------------------------------------------------
+ * Discrete adjoint of the time step (the paper obtains derivatives of the
+ * solver by running it on dual numbers, software-design section and the
+ * rotating-cylinder example; this is the reverse-mode equivalent, built from
+ * the transposes of the step's kernels).  Needs desc.adjoint = 1, no
+ * convective exit, and a body whose shape does not move (none, a fixed box,
+ * or a sphere/circle that may spin).  Conventions: the time step is frozen
+ * to the value the forward used; the QUICK limiter is linearised on the
+ * branch the forward took; each multigrid solve counts as the exact solution
+ * of A x = z on the active cells with the mean of z removed, so its
+ * transpose is one more solve with the same operator (A is symmetric).
+ * Adjoint state: ubar (WL_FIELD_ADJ_U) and pbar (WL_FIELD_ADJ_P) belong to
+ * the current state; accumulators hold the adjoints of mu0 (with the Poisson
+ * coefficient L, which is the same field), mu1 and V over all reversed steps.
+ * Scatter transposes use atomics: results agree to rounding, not bitwise.
+ * Typical reverse sweep of an objective J = sum_k w_k dir . F(state k):
+ *   wl_adj_reset; for k = K .. 1: [set the state to k, wl_adj_forces(w_k)],
+ *   set the state to k-1 (u, p, t, frozen dt via wl_set_time), wl_adj_step;
+ *   then wl_adj_body_grad.
+ * ------------------------------------------------------------------------- */
+
+/* Zero ubar, pbar and the accumulators. */
+wl_status wl_adj_reset(wl_sim* sim);
+
+/* Add the gradient of weight * dir . (F_p + F_v) (wl_forces) at the current
+ * state: into ubar (viscous term), pbar (pressure term, gauge-free), and, for a
+ * sphere, the direct radius derivative through K_eps(d) into the accumulators.
+ * value (may be NULL) receives dir . (F_p + F_v).  Synchronises the stream. */
+wl_status wl_adj_forces(wl_sim* sim, const double dir[3], double weight, double* value);
+
+/* Reverse of one time step.  On entry the current state (u, p, t) is the
+ * state n at the START of the step and dt_next (wl_set_time) its frozen
+ * step; ubar/pbar hold the adjoints of the state n+1.  The call recomputes
+ * the step forward (remeasuring a spinning body as wl_step does), recording
+ * its intermediates, then runs the transposes in reverse order.  On return the
+ * current state is n+1 (and dt_next its CFL value), ubar holds the adjoint of
+ * u^n, pbar is 0 (p^n does not influence the step), and the mu0/mu1/V
+ * accumulators have grown.  tol: residual max-norm of the two adjoint solves
+ * (<= 0: desc.mg_tol); adjoint_stats (may be NULL) receives the predictor and
+ * corrector adjoint solves' statistics, forward_stats the recomputed step's. */
+wl_status wl_adj_step(wl_sim* sim, double tol, wl_step_stats* forward_stats, wl_solve_stats adjoint_stats[2]);
+
+/* Gradient of the objective with respect to the sphere's radius (at fixed
+ * spin rate) and spin rate omega, from the accumulators: mu0 = mu0(d) and
+ * mu1 = mu1(d) n with d = |x - c| - R, V = omega e_z x (x - c) where
+ * measure sets it, plus the force functionals' direct radius terms.  Sphere
+ * bodies only.  Synchronises the stream. */
+wl_status wl_adj_body_grad(wl_sim* sim, double* dJ_dradius, double* dJ_dspin);
 
 /* ---------------------------------------------------------------------------
  * Learned multigrid initial guess (an extension of the method, not in the
@@ -258,7 +317,8 @@ enum {
   WL_K_REDUCE = 15,  /* single-block finalisations of reductions */
   WL_K_PG_INFER = 16,/* learned guess: features, conv net, guess */
   WL_K_PG_TRAIN = 17,/* learned guess: snapshots, training steps */
-  WL_K_COUNT = 18
+  WL_K_ADJOINT = 18, /* transposes of the step's kernels (adjoint solves count as multigrid) */
+  WL_K_COUNT = 19
 };
 
 /* Per-kernel timing with HIP events recorded around each launch on the sim's

@@ -12,16 +12,18 @@ STATUS = {0: "WL_OK", 1: "WL_ERR_INVALID_ARG", 2: "WL_ERR_WORKSPACE_TOO_SMALL", 
           4: "WL_ERR_NONFINITE", 5: "WL_ERR_UNSUPPORTED"}
 WL_F32, WL_F64 = 0, 1
 BODY_KIND = {"none": 0, "sphere": 1, "box": 2}
-FIELDS = {"u": 0, "u0": 1, "f": 2, "V": 3, "mu0": 4, "mu1": 5, "p": 6, "x": 7, "r": 8, "L": 9, "iD": 10}
+FIELDS = {"u": 0, "u0": 1, "f": 2, "V": 3, "mu0": 4, "mu1": 5, "p": 6, "x": 7, "r": 8, "L": 9, "iD": 10,
+          "adj_u": 11, "adj_p": 12}
 
 # every symbol include/wlmi.h declares
 EXPORTS = ["wl_workspace_bytes", "wl_sim_create", "wl_sim_destroy", "wl_measure_body", "wl_step",
            "wl_apply_bc", "wl_conv_diff", "wl_project", "wl_poisson_solve", "wl_forces", "wl_field",
            "wl_levels", "wl_set_time", "wl_get_time", "wl_profile", "wl_profile_read", "wl_pg_set_weights",
-           "wl_pg_get_weights", "wl_pg_mode", "wl_pg_forward", "wl_pg_train_step", "wl_pg_stats", "wl_last_error"]
+           "wl_pg_get_weights", "wl_pg_mode", "wl_pg_forward", "wl_pg_train_step", "wl_pg_stats", "wl_body_update",
+           "wl_adj_reset", "wl_adj_forces", "wl_adj_step", "wl_adj_body_grad", "wl_last_error"]
 PG_PARAMS = 8673
 KERNELS = ["measure", "coef", "flux", "bdim", "bc", "exit", "divres", "pcg_a", "pcg_b", "restrict",
-           "prolong", "project", "cfl", "forces", "coarse", "reduce", "pg_infer", "pg_train"]
+           "prolong", "project", "cfl", "forces", "coarse", "reduce", "pg_infer", "pg_train", "adjoint"]
 
 
 class SimDesc(C.Structure):
@@ -29,7 +31,7 @@ class SimDesc(C.Structure):
                 ("periodic_mask", C.c_uint), ("convective_exit", C.c_int), ("prec", C.c_int),
                 ("eps", C.c_double), ("dt0", C.c_double), ("dt_max", C.c_double),
                 ("cfl_nu_coef", C.c_double), ("mg_tol", C.c_double), ("mg_itmax", C.c_int),
-                ("pcg_iters", C.c_int), ("learned_guess", C.c_int)]
+                ("pcg_iters", C.c_int), ("learned_guess", C.c_int), ("adjoint", C.c_int)]
 
 
 class BodyDesc(C.Structure):
@@ -110,6 +112,17 @@ def load(path: str = LIB_PATH):
     lib.wl_pg_train_step.argtypes = [P, P, P, P, C.POINTER(C.c_int64), FP, C.POINTER(C.c_double), C.c_int]
     lib.wl_pg_stats.restype = C.c_int
     lib.wl_pg_stats.argtypes = [P, C.POINTER(C.c_double), C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
+    DP = C.POINTER(C.c_double)
+    lib.wl_body_update.restype = C.c_int
+    lib.wl_body_update.argtypes = [P, C.POINTER(BodyDesc)]
+    lib.wl_adj_reset.restype = C.c_int
+    lib.wl_adj_reset.argtypes = [P]
+    lib.wl_adj_forces.restype = C.c_int
+    lib.wl_adj_forces.argtypes = [P, DP, C.c_double, DP]
+    lib.wl_adj_step.restype = C.c_int
+    lib.wl_adj_step.argtypes = [P, C.c_double, C.POINTER(StepStats), C.POINTER(SolveStats)]
+    lib.wl_adj_body_grad.restype = C.c_int
+    lib.wl_adj_body_grad.argtypes = [P, DP, DP]
     lib.wl_last_error.restype = C.c_char_p
     lib.wl_last_error.argtypes = []
     _lib = lib

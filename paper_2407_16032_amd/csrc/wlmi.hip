@@ -18,6 +18,7 @@
 #include "wlmi.h"
 #include "wl_kernels.hpp"
 #include "wl_pgnet.hpp"
+#include "wl_adjoint.hpp"
 
 using namespace wl;
 
@@ -140,6 +141,12 @@ PgSizes pg_sizes(const Plan& P) {
   return S;
 }
 
+// fine-level fields of the discrete adjoint: ubar (2 x D, ping-pong), the
+// predictor-state adjoint (D), fbar (D), Vbar (D), mu0bar (D, also Lbar), mu1bar
+// (D*D), the recorded predictor state and flux (2 x D), x of both solves, pbar and
+// the adjoint right-hand side
+constexpr int kAdjFields(int D) { return 8 * D + D * D + 4; }
+
 Plan make_plan(const wl_sim_desc& d, bool has_body) {
   Plan P;
   P.ndim = d.ndim;
@@ -174,6 +181,7 @@ Plan make_plan(const wl_sim_desc& d, bool has_body) {
   b += align256((size_t)kNumSlots * kMaxBlocks * sizeof(double));
   b += align256(kNumScal * sizeof(double));
   b += align256(kMaxLevels * sizeof(int));
+  if (d.adjoint) b += (size_t)kAdjFields(D) * f0;
   if (d.learned_guess && d.ndim == 3) {
     const PgSizes S = pg_sizes(P);
     b += align256(P.lev[0].alloc * P.esize);  // p_{m-2}
@@ -292,6 +300,11 @@ struct SimBase {
   virtual wl_status pg_train(const void* x, const float* t, const unsigned char* m, const int64_t n[3], float* grad,
                              double* loss, int apply) = 0;
   virtual wl_status pg_stats(double* loss, int64_t* steps, int64_t* snaps) = 0;
+  virtual wl_status body_update(const wl_body_desc* b) = 0;
+  virtual wl_status adj_reset() = 0;
+  virtual wl_status adj_forces(const double dir[3], double weight, double* value) = 0;
+  virtual wl_status adj_step(double tol, wl_step_stats* fst, wl_solve_stats* ast) = 0;
+  virtual wl_status adj_body_grad(double* dR, double* dW) = 0;
   virtual wl_status profile(int enable) {
     if (enable) return prof.enable(stream);
     prof.flush();
@@ -359,6 +372,13 @@ struct Impl : SimBase {
   PgBox bd{}, bcrop{};
   int64_t pgPc = 0;
   int tiles[kMaxLevels][4] = {};  // tiled pass A: tiles_x, tiles_y, ntiles (0 = generic kernel)
+  // discrete adjoint
+  bool adj_on = false, rec = false;
+  T* au[2][3] = {};  // ubar ping-pong; au[acur] is the adjoint of the current state
+  int acur = 0;
+  T *aup[3] = {}, *afb[3] = {}, *aVb[3] = {}, *am0b[3] = {}, *am1b[9] = {}, *recB[3] = {}, *recF[3] = {};
+  T *recX1 = nullptr, *recX2 = nullptr, *apb = nullptr, *arhs = nullptr;
+  double adj_dR = 0.0;  // direct radius derivative of the force functionals so far
 
   Vec3<T> v3(T* const a[3]) const {
     Vec3<T> v;
@@ -371,6 +391,14 @@ struct Impl : SimBase {
     return v;
   }
   double* slot(int s) const { return red + (size_t)s * kMaxBlocks; }
+  // whole-allocation copy of a fine-level field (front padding included)
+  hipError_t copy_field(T* dst, const T* src) {
+    return hipMemcpyAsync(dst - kFrontPad, src - kFrontPad, plan.lev[0].alloc * sizeof(T), hipMemcpyDeviceToDevice,
+                          stream);
+  }
+  void fill_field(T* a, T v) {
+    k_fill<T><<<blocks_for(plan.lev[0].alloc), kBlock, 0, stream>>>(a - kFrontPad, plan.lev[0].alloc, v);
+  }
 
   // Assign every field an offset in the workspace; returns the bytes used.
   size_t carve(char* base) {
@@ -411,6 +439,22 @@ struct Impl : SimBase {
     red = (double*)take((size_t)kNumSlots * kMaxBlocks * sizeof(double));
     scal = (double*)take(kNumScal * sizeof(double));
     flags = (int*)take(kMaxLevels * sizeof(int));
+    adj_on = desc.adjoint != 0;
+    if (adj_on) {
+      for (int k = 0; k < D; ++k) au[0][k] = field(0);
+      for (int k = 0; k < D; ++k) au[1][k] = field(0);
+      for (int k = 0; k < D; ++k) aup[k] = field(0);
+      for (int k = 0; k < D; ++k) afb[k] = field(0);
+      for (int k = 0; k < D; ++k) aVb[k] = field(0);
+      for (int k = 0; k < D; ++k) am0b[k] = field(0);
+      for (int k = 0; k < D * D; ++k) am1b[k] = field(0);
+      for (int k = 0; k < D; ++k) recB[k] = field(0);
+      for (int k = 0; k < D; ++k) recF[k] = field(0);
+      recX1 = field(0);
+      recX2 = field(0);
+      apb = field(0);
+      arhs = field(0);
+    }
     pg_on = desc.learned_guess && D == 3;
     if (pg_on) {
       const PgSizes S = pg_sizes(plan);
@@ -463,6 +507,14 @@ struct Impl : SimBase {
     bool ok = in(p) && in(ebuf) && in(red) && in(scal) && in(flags);
     for (int k = 0; k < D; ++k) ok = ok && in(u[0][k]) && in(u[1][k]) && in(ft[k]) && in(V[k]) && in(mu0[k]);
     for (int k = 0; k < D * D; ++k) ok = ok && in(mu1[k]);
+    if (adj_on) {
+      ok = ok && in(recX1) && in(recX2) && in(apb) && in(arhs);
+      for (int k = 0; k < D; ++k)
+        ok = ok && in(au[0][k]) && in(au[1][k]) && in(aup[k]) && in(afb[k]) && in(aVb[k]) && in(am0b[k]) &&
+             in(recB[k]) && in(recF[k]);
+      for (int k = 0; k < D * D; ++k) ok = ok && in(am1b[k]);
+      ok = ok && (const char*)(arhs - kFrontPad + plan.lev[0].alloc) <= base + bytes;
+    }
     for (int l = 0; l < nlev; ++l) {
       ok = ok && in(x[l]) && in(r[l]) && in(e[l][0]) && in(e[l][1]) && in(q[l]) && in(iD[l]);
       for (int k = 0; k < D; ++k) ok = ok && in(L[l][k]);
@@ -1017,6 +1069,13 @@ struct Impl : SimBase {
     wl_solve_stats s1{}, s2{};
     if ((s = project(B, 1.0, &s1)) != WL_OK) return s;
     if ((s = bc(B, ex)) != WL_OK) return s;
+    if (rec) {  // intermediates the adjoint of this step reads
+      for (int k = 0; k < D; ++k) {
+        WL_HIP(copy_field(recB[k], B[k]));
+        WL_HIP(copy_field(recF[k], ft[k]));
+      }
+      WL_HIP(copy_field(recX1, x[0]));
+    }
     // corrector
     WL_TIMED(WL_K_FLUX, (k_flux<T, D><<<dim3(nb_face, D), kBlock, 0, stream>>>(g[0], v3(B), v3(A), v3(V), v3(ft),
                                                                               T(dt), T(desc.nu), hb, 0)));
@@ -1025,6 +1084,7 @@ struct Impl : SimBase {
     WL_HIP(hipGetLastError());
     if ((s = bc(B, ex)) != WL_OK) return s;
     if ((s = project(B, 0.5, &s2)) != WL_OK) return s;
+    if (rec) WL_HIP(copy_field(recX2, x[0]));
     if ((s = bc(B, ex)) != WL_OK) return s;
     cur = 1 - cur;
     const double dt_used = dt;
@@ -1051,9 +1111,8 @@ struct Impl : SimBase {
     return WL_OK;
   }
 
-  wl_status forces(double fp[3], double fv[3]) override {
-    for (int a = 0; a < 3; ++a) fp[a] = fv[a] = 0.0;
-    if (!has_body) return WL_OK;
+  // the 11 force sums of the current state (k_forces partials, totalled in block order)
+  wl_status force_sums(double tot[11]) {
     Motion m{};
     host_motion(bdesc, t, m);
     WL_TIMED(WL_K_FORCES, (k_forces<T, D><<<nb[0], kBlock, 0, stream>>>(g[0], body, m, desc.eps, desc.nu,
@@ -1063,17 +1122,197 @@ struct Impl : SimBase {
     WL_HIP(hipMemcpyAsync(h.data(), slot(kSlotForce), h.size() * sizeof(double), hipMemcpyDeviceToHost, stream));
     WL_HIP(hipStreamSynchronize(stream));
     prof.harvest();
-    auto tot = [&](int k) {
+    for (int k = 0; k < 11; ++k) {
       double s_ = 0;
       for (int b = 0; b < nb[0]; ++b) s_ += h[(size_t)k * kMaxBlocks + b];
-      return s_;
-    };
-    const double cnt = tot(10);
-    const double pbar = cnt > 0 ? tot(9) / cnt : 0.0;
-    for (int a = 0; a < 3; ++a) {
-      fp[a] = -(tot(a) - pbar * tot(6 + a));
-      fv[a] = tot(3 + a);
+      tot[k] = s_;
     }
+    return WL_OK;
+  }
+
+  wl_status forces(double fp[3], double fv[3]) override {
+    for (int a = 0; a < 3; ++a) fp[a] = fv[a] = 0.0;
+    if (!has_body) return WL_OK;
+    double tot[11];
+    wl_status s = force_sums(tot);
+    if (s != WL_OK) return s;
+    const double cnt = tot[10];
+    const double pbar = cnt > 0 ? tot[9] / cnt : 0.0;
+    for (int a = 0; a < 3; ++a) {
+      fp[a] = -(tot[a] - pbar * tot[6 + a]);
+      fv[a] = tot[3 + a];
+    }
+    return WL_OK;
+  }
+
+  // ---- body update and discrete adjoint -----------------------------------------
+  wl_status body_update(const wl_body_desc* b) override {
+    if (!b) return fail(WL_ERR_INVALID_ARG, "body is NULL");
+    if (b->kind != bdesc.kind) return fail(WL_ERR_INVALID_ARG, "the body kind cannot change");
+    wl_status s = validate_body(desc, b);
+    if (s != WL_OK) return s;
+    if (b->kind == WL_BODY_NONE) return WL_OK;
+    bdesc = *b;
+    body.R = bdesc.radius;
+    for (int k = 0; k < 3; ++k) {
+      body.h[k] = bdesc.half_extent[k];
+      body.po[k] = bdesc.pivot_offset[k];
+    }
+    moving = bdesc.heave_amp != 0.0 || bdesc.pitch_amp != 0.0 || bdesc.spin_omega != 0.0;
+    have_box = false;
+    return measure(t);
+  }
+
+  wl_status adj_require() {
+    if (!adj_on) return fail(WL_ERR_UNSUPPORTED, "the simulation has no adjoint buffers (desc.adjoint = 0)");
+    if (desc.convective_exit) return fail(WL_ERR_UNSUPPORTED, "the adjoint does not cover the convective exit");
+    if (has_body && (bdesc.heave_amp != 0.0 || bdesc.pitch_amp != 0.0 ||
+                     (bdesc.kind != WL_BODY_SPHERE && bdesc.spin_omega != 0.0)))
+      return fail(WL_ERR_UNSUPPORTED, "the adjoint needs a body whose shape does not move (spinning spheres are allowed)");
+    return WL_OK;
+  }
+
+  wl_status adj_reset() override {
+    wl_status s = adj_require();
+    if (s != WL_OK) return s;
+    for (int k = 0; k < D; ++k) {
+      fill_field(au[acur][k], T(0));
+      fill_field(aVb[k], T(0));
+      fill_field(am0b[k], T(0));
+    }
+    for (int k = 0; k < D * D; ++k) fill_field(am1b[k], T(0));
+    fill_field(apb, T(0));
+    WL_HIP(hipGetLastError());
+    adj_dR = 0.0;
+    return WL_OK;
+  }
+
+  void adj_bct(T* const w[3]) {
+    for (int k = D - 1; k >= 0; --k) {
+      int area = 1;
+      for (int o = 0; o < D; ++o)
+        if (o != k) area *= g[0].n[o] + 2;
+      WL_TIMED(WL_K_ADJOINT,
+               (k_adj_bc_axis<T, D><<<dim3(blocks_for(area), D), kBlock, 0, stream>>>(g[0], v3(w), k)));
+    }
+  }
+
+  // transpose of project(w) + its velocity update: w = ubar of the projected
+  // velocity in, of the unprojected velocity out; pbar (if with_p) consumed
+  wl_status adj_project(T* const w[3], double wdt, const T* xs, bool with_p, double tol, wl_solve_stats* st) {
+    WL_TIMED(WL_K_ADJOINT, (k_adj_proj_rhs<T, D><<<nb[0], kBlock, 0, stream>>>(
+                               g[0], v3(w), v3(L[0]), with_p ? apb : nullptr, T(1.0 / wdt), iD[0], arhs)));
+    fill_field(x[0], T(0));
+    WL_TIMED(WL_K_DIVRES, (k_div_res<T, D><<<nb[0], kBlock, 0, stream>>>(g[0], v3(u[cur]), arhs, nullptr, T(0),
+                                                                          v3(L[0]), iD[0], x[0], r[0],
+                                                                          slot(kSlotRmax), red, flags)));
+    set_mean_producer(nb[0]);
+    slot_n[kSlotRmax] = nb[0];
+    WL_HIP(hipGetLastError());
+    wl_status s = mg_loop(tol, desc.mg_itmax, st);
+    if (s != WL_OK) return s;
+    WL_TIMED(WL_K_ADJOINT, (k_mean0<T, D><<<nb[0], kBlock, 0, stream>>>(g[0], iD[0], x[0], red, flags)));
+    set_mean_producer(nb[0]);
+    int64_t faces = 1;
+    for (int a = 0; a < D; ++a) faces *= g[0].n[a] + 1;
+    WL_TIMED(WL_K_ADJOINT, (k_adj_proj_update<T, D><<<dim3(blocks_for(faces), D), kBlock, 0, stream>>>(
+                               g[0], v3(w), x[0], xs, iD[0], v3(am0b), red, nb[0])));
+    if (with_p) fill_field(apb, T(0));
+    WL_HIP(hipGetLastError());
+    return WL_OK;
+  }
+
+  wl_status adj_step(double tol, wl_step_stats* fst, wl_solve_stats* ast) override {
+    wl_status s = adj_require();
+    if (s != WL_OK) return s;
+    const double dts = dt;  // the (frozen) step of the recomputed forward
+    rec = true;
+    s = step(1, fst);
+    rec = false;
+    if (s != WL_OK) return s;
+    const double atol = tol > 0.0 ? tol : desc.mg_tol;
+    T* const* A = u[1 - cur];     // u^n
+    T* const* ub = au[acur];      // adjoint of u^{n+1}
+    T* const* ua = au[1 - acur];  // becomes the adjoint of u^n
+    const int hb = has_body ? 1 : 0;
+    for (int k = 0; k < D; ++k) fill_field(ua[k], T(0));
+    // corrector: bc, projection (w = 1/2, pbar), bc, blend (average), flux at the predictor state
+    adj_bct(ub);
+    if ((s = adj_project(ub, 0.5 * dts, recX2, true, atol, ast ? &ast[1] : nullptr)) != WL_OK) return s;
+    adj_bct(ub);
+    WL_TIMED(WL_K_ADJOINT, (k_adj_bdim<T, D, 1><<<dim3(nb_face, D), kBlock, 0, stream>>>(
+                               g[0], v3(ub), v3(ft), v3(mu0), v9(mu1), v3(afb), v3(aVb), v3(am0b), v9(am1b),
+                               v3(aup), hb)));
+    WL_TIMED(WL_K_ADJOINT, (k_adj_flux<T, D><<<dim3(nb_face, D), kBlock, 0, stream>>>(
+                               g[0], v3(recB), v3(afb), v3(aup), v3(ua), v3(aVb), T(dts), T(desc.nu), hb)));
+    // predictor: bc, projection (w = 1), bc, blend, flux at u^n
+    adj_bct(aup);
+    if ((s = adj_project(aup, dts, recX1, false, atol, ast ? &ast[0] : nullptr)) != WL_OK) return s;
+    adj_bct(aup);
+    WL_TIMED(WL_K_ADJOINT, (k_adj_bdim<T, D, 0><<<dim3(nb_face, D), kBlock, 0, stream>>>(
+                               g[0], v3(aup), v3(recF), v3(mu0), v9(mu1), v3(afb), v3(aVb), v3(am0b), v9(am1b),
+                               v3(aup), hb)));
+    WL_TIMED(WL_K_ADJOINT, (k_adj_flux<T, D><<<dim3(nb_face, D), kBlock, 0, stream>>>(
+                               g[0], v3(A), v3(afb), v3(ua), v3(ua), v3(aVb), T(dts), T(desc.nu), hb)));
+    WL_HIP(hipGetLastError());
+    acur = 1 - acur;
+    return WL_OK;
+  }
+
+  wl_status adj_forces(const double dir[3], double weight, double* value) override {
+    wl_status s = adj_require();
+    if (s != WL_OK) return s;
+    if (!has_body) return fail(WL_ERR_INVALID_ARG, "no body: the force functional is 0");
+    if (!dir || !std::isfinite(weight)) return fail(WL_ERR_INVALID_ARG, "dir is NULL or weight not finite");
+    double tot[11];
+    if ((s = force_sums(tot)) != WL_OK) return s;
+    const double cnt = tot[10];
+    const double pbar = cnt > 0 ? tot[9] / cnt : 0.0;
+    double val = 0.0, nkm = 0.0;
+    for (int a = 0; a < D; ++a) {
+      val += dir[a] * (-(tot[a] - pbar * tot[6 + a]) + tot[3 + a]);
+      nkm += dir[a] * (cnt > 0 ? tot[6 + a] / cnt : 0.0);
+    }
+    if (value) *value = val;
+    Motion m{};
+    host_motion(bdesc, t, m);
+    const double3 d3 = make_double3(dir[0], dir[1], D == 3 ? dir[2] : 0.0);
+    WL_TIMED(WL_K_ADJOINT, (k_adj_force_p<T, D><<<nb[0], kBlock, 0, stream>>>(g[0], body, m, desc.eps, iD[0], weight,
+                                                                               d3, nkm, apb)));
+    WL_TIMED(WL_K_ADJOINT, (k_adj_force_v<T, D><<<nb[0], kBlock, 0, stream>>>(
+                               g[0], body, m, desc.eps, desc.nu, weight, d3, v3(u[cur]), p, pbar, v3(au[acur]),
+                               slot(kSlotForce))));
+    WL_HIP(hipGetLastError());
+    std::vector<double> h((size_t)nb[0]);
+    WL_HIP(hipMemcpyAsync(h.data(), slot(kSlotForce), h.size() * sizeof(double), hipMemcpyDeviceToHost, stream));
+    WL_HIP(hipStreamSynchronize(stream));
+    prof.harvest();
+    for (double v : h) adj_dR += v;
+    return WL_OK;
+  }
+
+  wl_status adj_body_grad(double* dR, double* dW) override {
+    wl_status s = adj_require();
+    if (s != WL_OK) return s;
+    if (bdesc.kind != WL_BODY_SPHERE) return fail(WL_ERR_UNSUPPORTED, "body-parameter gradients need a sphere/circle");
+    Motion m{};
+    host_motion(bdesc, t, m);
+    const int gb = nb_face;
+    WL_TIMED(WL_K_ADJOINT, (k_adj_body<T, D><<<dim3(gb, D), kBlock, 0, stream>>>(
+                               g[0], body, m, desc.eps, v3(am0b), v9(am1b), v3(aVb), slot(kSlotForce))));
+    WL_HIP(hipGetLastError());
+    std::vector<double> h((size_t)6 * gb);
+    WL_HIP(hipMemcpyAsync(h.data(), slot(kSlotForce), h.size() * sizeof(double), hipMemcpyDeviceToHost, stream));
+    WL_HIP(hipStreamSynchronize(stream));
+    prof.harvest();
+    double r_ = 0.0, w_ = 0.0;
+    for (int c = 0; c < D; ++c)
+      for (int b = 0; b < gb; ++b) {
+        r_ += h[(size_t)c * gb + b];
+        w_ += h[(size_t)(3 + c) * gb + b];
+      }
+    if (dR) *dR = r_ + adj_dR;
+    if (dW) *dW = w_;
     return WL_OK;
   }
 
@@ -1097,6 +1336,17 @@ struct Impl : SimBase {
       case WL_FIELD_R: base = r[level]; break;
       case WL_FIELD_L: ncomp = D; base = L[level][0]; second = L[level][1]; break;
       case WL_FIELD_ID: base = iD[level]; break;
+      case WL_FIELD_ADJ_U:
+      case WL_FIELD_ADJ_P:
+        if (!adj_on) return fail(WL_ERR_UNSUPPORTED, "the simulation has no adjoint buffers");
+        if (which == WL_FIELD_ADJ_P) {
+          base = apb;
+        } else {
+          ncomp = D;
+          base = au[acur][0];
+          second = au[acur][1];
+        }
+        break;
       default: return fail(WL_ERR_INVALID_ARG, "unknown field id");
     }
     *ptr = base;
@@ -1326,6 +1576,32 @@ wl_status wl_pg_train_step(wl_sim* sim, const void* x_box, const float* target, 
                            const int64_t n[3], float* grad_out, double* loss, int apply) {
   WL_SIM_CHECK(sim);
   return sim->impl->pg_train(x_box, target, mask, n, grad_out, loss, apply);
+}
+
+wl_status wl_body_update(wl_sim* sim, const wl_body_desc* body) {
+  WL_SIM_CHECK(sim);
+  return sim->impl->body_update(body);
+}
+
+wl_status wl_adj_reset(wl_sim* sim) {
+  WL_SIM_CHECK(sim);
+  return sim->impl->adj_reset();
+}
+
+wl_status wl_adj_forces(wl_sim* sim, const double dir[3], double weight, double* value) {
+  WL_SIM_CHECK(sim);
+  return sim->impl->adj_forces(dir, weight, value);
+}
+
+wl_status wl_adj_step(wl_sim* sim, double tol, wl_step_stats* forward_stats, wl_solve_stats adjoint_stats[2]) {
+  WL_SIM_CHECK(sim);
+  if (!(tol >= 0.0)) return fail(WL_ERR_INVALID_ARG, "tol must be >= 0");
+  return sim->impl->adj_step(tol, forward_stats, adjoint_stats);
+}
+
+wl_status wl_adj_body_grad(wl_sim* sim, double* dJ_dradius, double* dJ_dspin) {
+  WL_SIM_CHECK(sim);
+  return sim->impl->adj_body_grad(dJ_dradius, dJ_dspin);
 }
 
 wl_status wl_pg_stats(wl_sim* sim, double* last_loss, int64_t* train_steps, int64_t* snapshots) {

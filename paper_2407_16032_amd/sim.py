@@ -42,7 +42,8 @@ class Simulation:
                  periodic: Sequence[bool] = (), convective_exit: bool = False, prec: str = "f32",
                  eps: float = 1.0, dt0: float = 0.25, dt_max: float = 10.0, cfl_nu: float = 5.0,
                  tol: float = 1e-6, itmax: int = 32, pcg_iters: int = 6, device="cuda:0",
-                 stream: Optional[torch.cuda.Stream] = None, learned_guess: bool = False):
+                 stream: Optional[torch.cuda.Stream] = None, learned_guess: bool = False,
+                 adjoint: bool = False):
         self.lib = L.load()
         nd = len(n)
         d = L.SimDesc()
@@ -57,6 +58,7 @@ class Simulation:
         d.eps, d.dt0, d.dt_max, d.cfl_nu_coef = eps, dt0, dt_max, cfl_nu
         d.mg_tol, d.mg_itmax, d.pcg_iters = tol, itmax, pcg_iters
         d.learned_guess = 1 if learned_guess else 0
+        d.adjoint = 1 if adjoint else 0
         self.desc = d
         self.bdesc = _body_desc(body)
         self.ndim = nd
@@ -222,6 +224,44 @@ class Simulation:
         snaps = C.c_int64()
         L.check(self.lib.wl_pg_stats(self._h, C.byref(loss), C.byref(steps), C.byref(snaps)), "wl_pg_stats")
         return {"loss": loss.value, "train_steps": steps.value, "snapshots": snaps.value}
+
+    # ---------------------------------------------------- discrete adjoint
+    def body_update(self, body):
+        self.bdesc = _body_desc(body)
+        L.check(self.lib.wl_body_update(self._h, C.byref(self.bdesc)), "wl_body_update")
+
+    def adj_reset(self):
+        L.check(self.lib.wl_adj_reset(self._h), "wl_adj_reset")
+
+    def adj_forces(self, direction, weight: float) -> float:
+        d = (C.c_double * 3)(*[float(v) for v in (list(direction) + [0.0, 0.0])[:3]])
+        val = C.c_double()
+        L.check(self.lib.wl_adj_forces(self._h, d, float(weight), C.byref(val)), "wl_adj_forces")
+        return val.value
+
+    def adj_step(self, tol: float = 0.0) -> dict:
+        fst = L.StepStats()
+        ast = (L.SolveStats * 2)()
+        L.check(self.lib.wl_adj_step(self._h, float(tol), C.byref(fst), ast), "wl_adj_step")
+        return {"dt": fst.dt, "vcycles": (fst.vcycles[0], fst.vcycles[1]),
+                "adj_vcycles": (ast[0].vcycles, ast[1].vcycles),
+                "adj_res_linf": (ast[0].res_linf, ast[1].res_linf)}
+
+    def adj_body_grad(self):
+        dR = C.c_double()
+        dW = C.c_double()
+        L.check(self.lib.wl_adj_body_grad(self._h, C.byref(dR), C.byref(dW)), "wl_adj_body_grad")
+        return dR.value, dW.value
+
+    def save_state(self):
+        """Device copies of (u, p) and the clock: a checkpoint."""
+        return (self.field("u").clone(), self.field("p").clone(), self.time())
+
+    def load_state(self, state, dt_next: Optional[float] = None):
+        u, p, (t, dt) = state
+        self.field("u").copy_(u)
+        self.field("p").copy_(p)
+        self.set_time(t, dt if dt_next is None else dt_next)
 
     def set_time(self, t: float, dt_next: float):
         L.check(self.lib.wl_set_time(self._h, float(t), float(dt_next)), "wl_set_time")

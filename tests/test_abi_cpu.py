@@ -44,7 +44,7 @@ def test_struct_layout_matches_header(tmp_path):
 #include "wlmi.h"
 int main(void) {
   printf("%zu %zu %zu %zu\\n", sizeof(wl_sim_desc), sizeof(wl_body_desc), sizeof(wl_step_stats), sizeof(wl_solve_stats));
-  printf("%zu %zu %zu %zu\\n", offsetof(wl_sim_desc, nu), offsetof(wl_sim_desc, mg_tol), offsetof(wl_body_desc, spin_omega), offsetof(wl_step_stats, converged));
+  printf("%zu %zu %zu %zu %zu\\n", offsetof(wl_sim_desc, nu), offsetof(wl_sim_desc, mg_tol), offsetof(wl_body_desc, spin_omega), offsetof(wl_step_stats, converged), offsetof(wl_sim_desc, adjoint));
   return 0;
 }
 """)
@@ -55,7 +55,7 @@ int main(void) {
     offs = [int(v) for v in lines[1].split()]
     assert sizes == [C.sizeof(L.SimDesc), C.sizeof(L.BodyDesc), C.sizeof(L.StepStats), C.sizeof(L.SolveStats)]
     assert offs == [L.SimDesc.nu.offset, L.SimDesc.mg_tol.offset, L.BodyDesc.spin_omega.offset,
-                    L.StepStats.converged.offset]
+                    L.StepStats.converged.offset, L.SimDesc.adjoint.offset]
 
 
 def _desc(n=(64, 32), prec=L.WL_F32):
@@ -109,6 +109,23 @@ def test_workspace_plan_is_consistent(lib, n, prec):
     for v in n:
         cells *= v + 2
     assert nb >= cells * (4 if prec == L.WL_F32 else 8) * (5 * len(n) + len(n) ** 2 + 7)
+
+
+@pytest.mark.parametrize("n", [(48, 24), (512, 256), (64, 32, 32)])
+def test_adjoint_buffers_in_the_plan(lib, n):
+    # desc.adjoint adds 8 D + D^2 + 4 fine-level fields (adjoint velocities, blend and
+    # flux adjoints, mu0/mu1/V accumulators, the recorded step, x of both solves, pbar, rhs)
+    D = len(n)
+    for prec, esz in ((L.WL_F32, 4), (L.WL_F64, 8)):
+        d = _desc(n=n, prec=prec)
+        base = lib.wl_workspace_bytes(C.byref(d), None)
+        d.adjoint = 1
+        more = lib.wl_workspace_bytes(C.byref(d), None)
+        assert more > base, lib.wl_last_error()
+        px = ((n[0] + 2 + 15) // 16) * 16
+        alloc = px * (n[1] + 2) * (n[2] + 2 if D == 3 else 1) + 16
+        f0 = (alloc * esz + 255) // 256 * 256
+        assert more - base == (8 * D + D * D + 4) * f0
 
 
 def test_create_rejects_bad_arguments_before_any_gpu_work(lib):

@@ -1,0 +1,140 @@
+"""The HIP discrete adjoint (through the C ABI) against the oracle's complex-step
+gradient, central differences of the HIP forward, and a one-step transpose check."""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import wlsynth
+from oracle import adjoint as OA
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _case():
+    # spinning circle, 48 x 24 cells, R = 3: small enough for the complex-step oracle
+    return wlsynth.rotating_cylinder_2d(n=(48, 24), D=6.0, center=(14.0, 12.0), xi=0.8)
+
+
+XI, R, STEPS, WIN = 0.8, 3.0, 12, 6
+
+
+@pytest.fixture(scope="module")
+def oracle_grad():
+    w = _case()
+    J, gx, gR, dts = OA.gradient(w, XI, R, STEPS, WIN)
+    return J, gx, gR, dts
+
+
+def _problem(ckpt, dts=None, prec="f64", tol=1e-12):
+    from paper_2407_16032_amd.adjoint import RotatingCylinderDrag
+    w = _case()
+    prob = RotatingCylinderDrag(w, wlsynth.initial_velocity(w), STEPS, WIN, ckpt=ckpt, prec=prec, tol=tol)
+    prob.dts = None if dts is None else list(dts)
+    return prob
+
+
+@pytest.mark.parametrize("ckpt", [1, 5, 20])
+def test_adjoint_gradient_matches_oracle_complex_step(oracle_grad, ckpt):
+    J0, gx0, gR0, dts = oracle_grad
+    _say("adjoint vs complex step, ckpt", ckpt)
+    prob = _problem(ckpt, dts)
+    J, gx, gR = prob.value_and_grad(XI, R)
+    _say("  J %.12g / %.12g  dxi %.10g / %.10g  dR %.10g / %.10g" % (J, J0, gx, gx0, gR, gR0), prob.stats)
+    assert J == pytest.approx(J0, rel=1e-10)
+    assert gx == pytest.approx(gx0, rel=1e-6, abs=1e-10)
+    assert gR == pytest.approx(gR0, rel=1e-6, abs=1e-10)
+    prob.sim.close()
+
+
+def test_adjoint_gradient_matches_gpu_central_differences():
+    _say("adjoint vs central differences of the HIP forward")
+    prob = _problem(4)
+    J, gx, gR = prob.value_and_grad(XI, R)  # records the frozen schedule
+    h = 1e-6
+    fx = (prob.value(XI + h, R) - prob.value(XI - h, R)) / (2 * h)
+    fR = (prob.value(XI, R + h) - prob.value(XI, R - h)) / (2 * h)
+    _say("  dxi %.10g fd %.10g   dR %.10g fd %.10g" % (gx, fx, gR, fR))
+    assert gx == pytest.approx(fx, rel=1e-5, abs=1e-8)
+    assert gR == pytest.approx(fR, rel=1e-5, abs=1e-8)
+    prob.sim.close()
+
+
+def test_autograd_function_backward():
+    from paper_2407_16032_amd.adjoint import rotating_cylinder_drag
+    _say("autograd.Function")
+    prob = _problem(5)
+    theta = torch.tensor([XI, R], dtype=torch.float64, requires_grad=True)
+    J = rotating_cylinder_drag(theta, prob)
+    J.backward()
+    J2, gx, gR = prob.value_and_grad(XI, R)
+    assert float(J) == pytest.approx(J2, rel=1e-12)
+    np.testing.assert_allclose(theta.grad.numpy(), [gx, gR], rtol=1e-9, atol=1e-14)
+    prob.sim.close()
+
+
+def _dot(a, b):
+    return float(sum(torch.sum(x.double() * y.double()) for x, y in zip(a, b)))
+
+
+def test_one_step_transpose_dot_product():
+    """<ubar, J du> + <pbar, J_p du> = <J^T (ubar, pbar), du> for one step (FP64, FD of the HIP step)."""
+    from paper_2407_16032_amd import Simulation
+    _say("one-step transpose")
+    w = _case()
+    body = OA.rotcyl_body(w, XI, R)
+    sim = Simulation(w.n, w.U, w.nu, body, prec="f64", tol=1e-13, itmax=300, device="cuda:0", adjoint=True)
+    sim.set_velocity(wlsynth.initial_velocity(w))
+    for _ in range(3):
+        sim.step()
+    base = sim.save_state()
+    dt = base[2][1]
+    gen = torch.Generator().manual_seed(7)
+    shp = base[0].shape
+    du = torch.randn(shp, generator=gen, dtype=torch.float64).to(base[0].device)
+    ubar = torch.randn(shp, generator=gen, dtype=torch.float64).to(base[0].device)
+    act = sim.field("iD") != 0
+    pbar = torch.randn(sim.field("p").shape, generator=gen, dtype=torch.float64).to(base[0].device)
+    pbar = torch.where(act, pbar, torch.zeros_like(pbar))
+    pbar[act] -= pbar[act].mean()  # the pressure's gauge is not a function of u
+
+    def run(sign, h):
+        u, p, (t, _) = base
+        sim.load_state((u + sign * h * du, p, (t, dt)))
+        sim.step()
+        return sim.field("u").clone(), sim.field("p").clone()
+
+    h = 1e-6
+    up, pp = run(+1, h)
+    um, pm = run(-1, h)
+    lhs = _dot([ubar], [(up - um) / (2 * h)]) + _dot([pbar], [(pp - pm) / (2 * h)])
+    sim.adj_reset()
+    sim.load_state(base, dt)
+    sim.field("adj_u").copy_(ubar)
+    sim.field("adj_p").copy_(pbar)
+    st = sim.adj_step(1e-13)
+    rhs = _dot([sim.field("adj_u").clone()], [du])
+    _say("  lhs %.15g rhs %.15g" % (lhs, rhs), st)
+    assert rhs == pytest.approx(lhs, rel=1e-6)
+    assert float(sim.field("adj_p").abs().max()) == 0.0
+    sim.close()
+
+
+def test_adjoint_needs_buffers_and_no_exit():
+    from paper_2407_16032_amd import Simulation
+    from paper_2407_16032_amd._lib import WlError
+    w = _case()
+    sim = Simulation(w.n, w.U, w.nu, OA.rotcyl_body(w, XI, R), prec="f64", device="cuda:0")
+    with pytest.raises(WlError, match="UNSUPPORTED"):
+        sim.adj_reset()
+    sim.close()
+    sim = Simulation(w.n, w.U, w.nu, None, prec="f32", device="cuda:0", convective_exit=True, adjoint=True)
+    with pytest.raises(WlError, match="UNSUPPORTED"):
+        sim.adj_step()
+    sim.close()
