@@ -205,6 +205,15 @@ wl_status wl_get_time(wl_sim* sim, double* t, double* dt_next);
 /* Replace the body's parameters (same kind) and re-measure at the current time. */
 wl_status wl_body_update(wl_sim* sim, const wl_body_desc* body);
 
+/* Index box (padded indices, inclusive; empty if lo[0] > hi[0]) of multigrid
+ * level `level` outside of which the coefficients are body-free: L = 1 on the
+ * fine level (times 2^(ndim-2) per coarsening) on interior faces, 0 on
+ * non-periodic boundary faces, iD from those, and on the fine level mu1 = 0,
+ * V = 0.  The kernels evaluate these in closed form there instead of loading
+ * them (paper, software-design section: measure! fills the coefficient fields
+ * only where the body has an influence).  Valid after the last measure. */
+wl_status wl_body_box(wl_sim* sim, int level, int lo[3], int hi[3]);
+
 /* ---------------------------------------------------------------------------
  * Discrete adjoint of the time step (the paper obtains derivatives of the
  * solver by running it on dual numbers, software-design section and the

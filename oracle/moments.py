@@ -26,11 +26,18 @@ def kernel_eps(d, eps=1.0):
 
 
 def mu0(d, eps=1.0):
+    """Zeroth moment; exactly 0 / 1 beyond the kernel support (|s| >= 1), where the
+    closed form would otherwise carry the rounding of sin(pi)."""
     s = np.clip(np.asarray(d) / eps, -1.0, 1.0)
-    return 0.5 * (1.0 + s) + np.sin(np.pi * s) / (2.0 * np.pi)
+    inner = 0.5 * (1.0 + s) + np.sin(np.pi * s) / (2.0 * np.pi)
+    rs = np.real(s)
+    return np.where(rs >= 1.0, 1.0, np.where(rs <= -1.0, 0.0, inner))
 
 
 def mu1(d, eps=1.0):
+    """First moment; exactly 0 beyond the kernel support, where the integral of s K
+    over the whole symmetric support vanishes."""
     s = np.clip(np.asarray(d) / eps, -1.0, 1.0)
-    return eps * (0.25 * (1.0 - s * s)
-                  - (s * np.sin(np.pi * s) + (1.0 + np.cos(np.pi * s)) / np.pi) / (2.0 * np.pi))
+    inner = eps * (0.25 * (1.0 - s * s)
+                   - (s * np.sin(np.pi * s) + (1.0 + np.cos(np.pi * s)) / np.pi) / (2.0 * np.pi))
+    return np.where(np.abs(np.real(s)) >= 1.0, 0.0, inner)

@@ -20,6 +20,7 @@ EXPORTS = ["wl_workspace_bytes", "wl_sim_create", "wl_sim_destroy", "wl_measure_
            "wl_apply_bc", "wl_conv_diff", "wl_project", "wl_poisson_solve", "wl_forces", "wl_field",
            "wl_levels", "wl_set_time", "wl_get_time", "wl_profile", "wl_profile_read", "wl_pg_set_weights",
            "wl_pg_get_weights", "wl_pg_mode", "wl_pg_forward", "wl_pg_train_step", "wl_pg_stats", "wl_body_update",
+           "wl_body_box",
            "wl_adj_reset", "wl_adj_forces", "wl_adj_step", "wl_adj_body_grad", "wl_last_error"]
 PG_PARAMS = 8673
 KERNELS = ["measure", "coef", "flux", "bdim", "bc", "exit", "divres", "pcg_a", "pcg_b", "restrict",
@@ -115,6 +116,8 @@ def load(path: str = LIB_PATH):
     DP = C.POINTER(C.c_double)
     lib.wl_body_update.restype = C.c_int
     lib.wl_body_update.argtypes = [P, C.POINTER(BodyDesc)]
+    lib.wl_body_box.restype = C.c_int
+    lib.wl_body_box.argtypes = [P, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int)]
     lib.wl_adj_reset.restype = C.c_int
     lib.wl_adj_reset.argtypes = [P]
     lib.wl_adj_forces.restype = C.c_int

@@ -77,14 +77,19 @@ __device__ inline void body_eval(const BodyP& b, const Motion& m, const double x
   V[2] = m.cdot[2];
 }
 
+// Moments of the kernel; beyond its support (|s| >= 1) they are the full integrals,
+// exactly 0 / 1 for mu0 and 0 for mu1 (the closed forms would leave sin(pi) rounding).
 __device__ inline double kern_mu0(double d, double eps) {
 #pragma clang fp contract(off)
-  double s = fmin(fmax(d / eps, -1.0), 1.0);
+  const double s = d / eps;
+  if (s >= 1.0) return 1.0;
+  if (s <= -1.0) return 0.0;
   return 0.5 * (1.0 + s) + sin(M_PI * s) / (2.0 * M_PI);
 }
 __device__ inline double kern_mu1(double d, double eps) {
 #pragma clang fp contract(off)
-  double s = fmin(fmax(d / eps, -1.0), 1.0);
+  const double s = d / eps;
+  if (fabs(s) >= 1.0) return 0.0;
   return eps * (0.25 * (1.0 - s * s) - (s * sin(M_PI * s) + (1.0 + cos(M_PI * s)) / M_PI) / (2.0 * M_PI));
 }
 __device__ inline double kern_K(double d, double eps) {
@@ -94,6 +99,63 @@ __device__ inline double kern_K(double d, double eps) {
 }
 
 constexpr double kMu0Cut = 1e-6;  // faces with mu0 below this are solid
+
+// ---------------------------------------------------------------------------
+// Closed-form coefficients away from the body.  Outside a level's body box
+// (padded indices, inclusive) measure leaves every coefficient at its body-free
+// value: L_a = Lstd on interior faces and 0 on non-periodic boundary faces, iD
+// from those L, and on the fine level mu0 = L, mu1 = 0, V = 0.  Kernels whose
+// whole stencil lies outside the box evaluate these instead of loading them;
+// the values are bit-identical to the stored ones (sums of 0 and a power of two,
+// then one correctly rounded division).
+// ---------------------------------------------------------------------------
+struct StdBox {
+  int lo[3], hi[3];  // empty when lo[0] > hi[0]
+  double Lstd;       // 1 on the fine level, times 2^(D-2) per coarsening
+};
+
+// Does the index range [a_k, b_k] per axis (may extend past the padded range) miss
+// the box?  On a periodic axis a range that leaves 1..N is taken as the whole axis.
+template <int D>
+__device__ __forceinline__ bool std_miss(const StdBox& B, const Grid3& g, const int a[3], const int b[3]) {
+  if (B.lo[0] > B.hi[0]) return true;
+#pragma unroll
+  for (int k = 0; k < D; ++k) {
+    int lo = a[k], hi = b[k];
+    if (g.per[k] && (lo < 1 || hi > g.n[k])) {
+      lo = 0;
+      hi = g.n[k] + 1;
+    }
+    if (hi < B.lo[k] || lo > B.hi[k]) return true;
+  }
+  return false;
+}
+
+// L_a at face index Ia (1..N_a+1) along a, body-free
+template <typename T>
+__device__ __forceinline__ T L_std(const Grid3& g, const StdBox& B, int a, int Ia) {
+  return (g.per[a] || (Ia >= 2 && Ia <= g.n[a])) ? T(B.Lstd) : T(0);
+}
+
+// inverse diagonal of cell (i, j, k), body-free (0 off the interior)
+template <typename T, int D>
+__device__ __forceinline__ T iD_std(const Grid3& g, const StdBox& B, int i, int j, int k) {
+  const int I[3] = {i, j, k};
+  int cnt = 2 * D;
+#pragma unroll
+  for (int a = 0; a < D; ++a) {
+    if (I[a] < 1 || I[a] > g.n[a]) return T(0);
+    if (!g.per[a]) cnt -= (I[a] == 1 ? 1 : 0) + (I[a] == g.n[a] ? 1 : 0);
+  }
+  return T(1) / (-(T(B.Lstd) * T(cnt)));
+}
+
+// is the cube [I - m, I + m] outside the box?
+template <int D>
+__device__ __forceinline__ bool std_point(const StdBox& B, const Grid3& g, const int I[3], int m) {
+  const int a[3] = {I[0] - m, I[1] - m, I[2] - m}, b[3] = {I[0] + m, I[1] + m, I[2] + m};
+  return std_miss<D>(B, g, a, b);
+}
 
 // measure!: mu0 (= fine Poisson L, 0 on non-periodic boundary faces), mu1 = mu1(d) n, V.
 // blockIdx.y = component.
@@ -257,7 +319,7 @@ __device__ __forceinline__ T resid_fast(const Grid3& g, const Vec3<T>& u, int c,
 // mode 0: f~ (with body velocity if has_body); mode 1: f = R only.  blockIdx.y = c.
 template <typename T, int D>
 __global__ void __launch_bounds__(kBlock) k_flux(Grid3 g, Vec3<T> u, Vec3<T> u0, Vec3<T> V,
-                                                 Vec3<T> f, T dt, T nu, int has_body, int mode) {
+                                                 Vec3<T> f, T dt, T nu, int has_body, int mode, StdBox B) {
   const int c = blockIdx.y;
   const int P0 = g.n[0] + 2, P1 = g.n[1] + 2, P2 = (D == 3) ? g.n[2] + 2 : 1;
   const int total = P0 * P1 * P2;
@@ -281,7 +343,7 @@ __global__ void __launch_bounds__(kBlock) k_flux(Grid3 g, Vec3<T> u, Vec3<T> u0,
       f.c[c][idx] = R;
     } else {
       T v = u0.c[c][idx] + dt * R;
-      if (has_body) v = v - V.c[c][idx];
+      if (has_body && !std_point<D>(B, g, I, 0)) v = v - V.c[c][idx];  // V = 0 outside the box
       f.c[c][idx] = v;
     }
   }
@@ -291,7 +353,7 @@ __global__ void __launch_bounds__(kBlock) k_flux(Grid3 g, Vec3<T> u, Vec3<T> u0,
 // CORR = 0: u = out (predictor); CORR = 1: u = (u + out)/2 (corrector).
 template <typename T, int D, int CORR>
 __global__ void __launch_bounds__(kBlock) k_bdim(Grid3 g, Vec3<T> f, Vec3<T> V, Vec3<T> mu0,
-                                                 Vec9<T> mu1, Vec3<T> u, int has_body) {
+                                                 Vec9<T> mu1, Vec3<T> u, int has_body, StdBox B) {
   const int c = blockIdx.y;
   const int P0 = g.n[0] + 2, P1 = g.n[1] + 2, P2 = (D == 3) ? g.n[2] + 2 : 1;
   const int total = P0 * P1 * P2;
@@ -302,7 +364,9 @@ __global__ void __launch_bounds__(kBlock) k_bdim(Grid3 g, Vec3<T> f, Vec3<T> V, 
     T acc;
     bool fast = true;
     for (int a = 0; a < D; ++a) fast = fast && I[a] >= 2 && I[a] <= g.n[a] - 1;
-    if (has_body && fast) {
+    if (has_body && std_point<D>(B, g, I, 0)) {
+      acc = L_std<T>(g, B, c, I[c]) * f.c[c][idx];  // V = 0, mu0 = L, mu1 = 0 outside the box
+    } else if (has_body && fast) {
       acc = V.c[c][idx] + mu0.c[c][idx] * f.c[c][idx];
 #pragma unroll
       for (int j = 0; j < D; ++j) {
@@ -459,7 +523,7 @@ __device__ __forceinline__ void put_mean_partials(double sr, double cnt, double*
 template <typename T, int D>
 __global__ void __launch_bounds__(kBlock) k_div_res(Grid3 g, Vec3<T> u, const T* rhs, const T* p,
                                                     T wdt, Vec3<T> L, const T* iD, T* x, T* r,
-                                                    double* part_max, double* red, int* flag) {
+                                                    double* part_max, double* red, int* flag, StdBox B) {
   const int total = g.n[0] * g.n[1] * ((D == 3) ? g.n[2] : 1);
   double mx = 0.0, sr = 0.0, cnt = 0.0;
   if (blockIdx.x == 0 && threadIdx.x == 0) *flag = 0;
@@ -474,7 +538,8 @@ __global__ void __launch_bounds__(kBlock) k_div_res(Grid3 g, Vec3<T> u, const T*
       z = T(0);
       for (int a = 0; a < D; ++a) z = z + (u.c[a][idx + op[a]] - u.c[a][idx]);
     }
-    const T di = iD[idx];
+    const bool sc = std_point<D>(B, g, I, 1);
+    const T di = sc ? iD_std<T, D>(g, B, I[0], I[1], I[2]) : iD[idx];
     T rr = T(0);
     const T xc = p ? p[idx] * wdt : x[idx];
     if (di != T(0)) {
@@ -482,7 +547,9 @@ __global__ void __launch_bounds__(kBlock) k_div_res(Grid3 g, Vec3<T> u, const T*
       for (int a = 0; a < D; ++a) {
         const T xp = p ? p[idx + op[a]] * wdt : x[idx + op[a]];
         const T xm = p ? p[idx + om[a]] * wdt : x[idx + om[a]];
-        Ax = Ax + L.c[a][idx + op[a]] * (xp - xc) - L.c[a][idx] * (xc - xm);
+        const T Lp = sc ? L_std<T>(g, B, a, I[a] + 1) : L.c[a][idx + op[a]];
+        const T Lc = sc ? L_std<T>(g, B, a, I[a]) : L.c[a][idx];
+        Ax = Ax + Lp * (xp - xc) - Lc * (xc - xm);
       }
       rr = z - Ax;
     }
@@ -589,7 +656,7 @@ __global__ void __launch_bounds__(kBlock) k_prolong(Grid3 f, Grid3 c, const T* x
 template <typename T>
 __global__ void __launch_bounds__(kTileThreads) k_prolong_tile(Grid3 f, Grid3 c, const T* xc, Vec3<T> L, const T* iD,
                                                       T* xf, T* rf, double* red, int* flag, int tiles_x,
-                                                      int tiles_y, int ntiles) {
+                                                      int tiles_y, int ntiles, StdBox B) {
   if (blockIdx.x == 0 && threadIdx.x == 0) *flag = 0;
   const int b = blockIdx.x;
   const int full = (ntiles / 8) * 8;
@@ -600,6 +667,8 @@ __global__ void __launch_bounds__(kTileThreads) k_prolong_tile(Grid3 f, Grid3 c,
   const int tx = threadIdx.x % kTX, ty = threadIdx.x / kTX;
   const int i = x0 + tx, j = y0 + ty;
   const bool own = i <= f.n[0] && j <= f.n[1];
+  const int ta[3] = {x0 - 2, y0 - 2, z0 - 2}, tb[3] = {x0 + kTX + 1, y0 + kTY + 1, z1 + 1};
+  const bool fast = std_miss<3>(B, f, ta, tb);  // L and iD in closed form
   double sr = 0.0, cnt = 0.0;
   if (own) {
     const int s1 = f.s[1], s2 = f.s[2], cs1 = c.s[1], cs2 = c.s[2];
@@ -611,19 +680,23 @@ __global__ void __launch_bounds__(kTileThreads) k_prolong_tile(Grid3 f, Grid3 c,
               cym = pi + pym * cs1;
     const int opx = (f.per[0] && i == f.n[0]) ? -(f.n[0] - 1) : 1;
     const int opy = (f.per[1] && j == f.n[1]) ? -(f.n[1] - 1) * s1 : s1;
-    T L2c = L.c[2][col + z0 * s2];
+    const T Lxp = fast ? L_std<T>(f, B, 0, i + 1) : T(0), Lxc = fast ? L_std<T>(f, B, 0, i) : T(0);
+    const T Lyp = fast ? L_std<T>(f, B, 1, j + 1) : T(0), Lyc = fast ? L_std<T>(f, B, 1, j) : T(0);
+    T L2c = fast ? L_std<T>(f, B, 2, z0) : L.c[2][col + z0 * s2];
     for (int z = z0; z < z1; ++z) {
       const int id = col + z * s2;
       const int zp = wrapc(z + 1, 2, f), zm = wrapc(z - 1, 2, f);
       const int pz = ((z + 1) >> 1) * cs2, pzp = ((zp + 1) >> 1) * cs2, pzm = ((zm + 1) >> 1) * cs2;
-      const T L2p = L.c[2][col + zp * s2];
+      const T L2p = fast ? L_std<T>(f, B, 2, zp) : L.c[2][col + zp * s2];
       const T ec = xc[cc + pz];
       xf[id] = xf[id] + ec;
-      const T di = iD[id];
+      const T di = fast ? iD_std<T, 3>(f, B, i, j, z) : iD[id];
       if (di != T(0)) {
         T Ae = T(0);
-        Ae = Ae + L.c[0][id + opx] * (xc[cxp + pz] - ec) - L.c[0][id] * (ec - xc[cxm + pz]);
-        Ae = Ae + L.c[1][id + opy] * (xc[cyp + pz] - ec) - L.c[1][id] * (ec - xc[cym + pz]);
+        const T lxp = fast ? Lxp : L.c[0][id + opx], lxc = fast ? Lxc : L.c[0][id];
+        const T lyp = fast ? Lyp : L.c[1][id + opy], lyc = fast ? Lyc : L.c[1][id];
+        Ae = Ae + lxp * (xc[cxp + pz] - ec) - lxc * (ec - xc[cxm + pz]);
+        Ae = Ae + lyp * (xc[cyp + pz] - ec) - lyc * (ec - xc[cym + pz]);
         Ae = Ae + L2p * (xc[cc + pzp] - ec) - L2c * (ec - xc[cc + pzm]);
         const T rr = rf[id] - Ae;
         rf[id] = rr;
@@ -720,7 +793,7 @@ template <typename T, int FINE>
 __global__ void __launch_bounds__(kTileThreads) k_pcg_a_tile(Grid3 g, Vec3<T> L, const T* iD, const T* r,
                                                              const T* eo, T* en, T* q, double* red, int k,
                                                              RedN rn, double* part_sig, int* flag, int tiles_x,
-                                                             int tiles_y, int ntiles) {
+                                                             int tiles_y, int ntiles, StdBox B) {
   if (*flag) return;
   T beta, mean;
   if (!pcg_a_scalars<T, kTileThreads>(red, k, rn, flag, beta, mean)) return;
@@ -757,8 +830,14 @@ __global__ void __launch_bounds__(kTileThreads) k_pcg_a_tile(Grid3 g, Vec3<T> L,
     hy = wrapc(ry, 1, g);
   }
   const int hcol = hx + hy * s1;
-  auto eps_at = [&](int id) -> T {
-    return (k > 0) ? iD[id] * r[id] + beta * eo[id] : iD[id] * (r[id] - mean);
+  // tiles whose stencil (with the halo's own neighbours) misses the body box take
+  // L and iD in closed form: only r, e_old are read and e_new, q written
+  const int ta[3] = {x0 - 2, y0 - 2, z0 - 2}, tb[3] = {x0 + kTX + 1, y0 + kTY + 1, z1 + 1};
+  const bool fast = std_miss<3>(B, g, ta, tb);
+  auto diag = [&](int id, int ci, int cj, int ck) -> T { return fast ? iD_std<T, 3>(g, B, ci, cj, ck) : iD[id]; };
+  auto eps_at = [&](int id, int ci, int cj, int ck) -> T {
+    const T d = diag(id, ci, cj, ck);
+    return (k > 0) ? d * r[id] + beta * eo[id] : d * (r[id] - mean);
   };
   // x/y neighbour offsets of the own column (periodic wrap)
   const int opx = (g.per[0] && i == n0) ? -(n0 - 1) : 1;
@@ -767,12 +846,12 @@ __global__ void __launch_bounds__(kTileThreads) k_pcg_a_tile(Grid3 g, Vec3<T> L,
   T em = T(0), ec = T(0), rc = T(0), dc = T(0), L2c = T(0);
   if (inb) {
     const int zm = wrapc(z0 - 1, 2, g);
-    em = eps_at(col + zm * s2);
+    em = eps_at(col + zm * s2, wi, wj, zm);
     const int id = col + z0 * s2;
-    dc = iD[id];
+    dc = diag(id, wi, wj, z0);
     rc = r[id];
     ec = (k > 0) ? dc * rc + beta * eo[id] : dc * (rc - mean);
-    L2c = L.c[2][id];
+    L2c = fast ? L_std<T>(g, B, 2, z0) : L.c[2][id];
   }
   double sig = 0.0, rho0 = 0.0;
   for (int z = z0; z < z1; ++z) {
@@ -780,13 +859,13 @@ __global__ void __launch_bounds__(kTileThreads) k_pcg_a_tile(Grid3 g, Vec3<T> L,
     T ep = T(0), dp = T(0), rp = T(0), L2p = T(0);
     if (inb) {
       const int id = col + zp * s2;
-      dp = iD[id];
+      dp = diag(id, wi, wj, zp);
       rp = r[id];
       ep = (k > 0) ? dp * rp + beta * eo[id] : dp * (rp - mean);
-      L2p = L.c[2][id];
+      L2p = fast ? L_std<T>(g, B, 2, zp) : L.c[2][id];
     }
     sE[ty + 1][tx + 1] = ec;
-    if (t < 2 * (kTX + 2) + 2 * kTY) sE[sy][sx] = hb ? eps_at(hcol + z * s2) : T(0);
+    if (t < 2 * (kTX + 2) + 2 * kTY) sE[sy][sx] = hb ? eps_at(hcol + z * s2, hx, hy, z) : T(0);
     __syncthreads();
     if (own) {
       const int id = col + z * s2;
@@ -794,8 +873,12 @@ __global__ void __launch_bounds__(kTileThreads) k_pcg_a_tile(Grid3 g, Vec3<T> L,
       if (dc != T(0)) {
         const T xm = sE[ty + 1][tx], xp = sE[ty + 1][tx + 2];
         const T ym = sE[ty][tx + 1], yp = sE[ty + 2][tx + 1];
-        qq = qq + L.c[0][id + opx] * (xp - ec) - L.c[0][id] * (ec - xm);
-        qq = qq + L.c[1][id + opy] * (yp - ec) - L.c[1][id] * (ec - ym);
+        const T Lxp = fast ? L_std<T>(g, B, 0, i + 1) : L.c[0][id + opx];
+        const T Lxc = fast ? L_std<T>(g, B, 0, i) : L.c[0][id];
+        const T Lyp = fast ? L_std<T>(g, B, 1, j + 1) : L.c[1][id + opy];
+        const T Lyc = fast ? L_std<T>(g, B, 1, j) : L.c[1][id];
+        qq = qq + Lxp * (xp - ec) - Lxc * (ec - xm);
+        qq = qq + Lyp * (yp - ec) - Lyc * (ec - ym);
         qq = qq + L2p * (ep - ec) - L2c * (ec - em);
         if (k == 0) rho0 += double(rc - mean) * double(ec);
       }
@@ -822,11 +905,13 @@ __global__ void __launch_bounds__(kTileThreads) k_pcg_a_tile(Grid3 g, Vec3<T> L,
 // padding cells have iD = e = q = 0, so they are left unchanged):
 // alpha = rho_k/sigma_k; x += alpha e; r -= alpha q; partials rho_{k+1}
 // (want_rho) and max|r| (want_max).  Sweep 0 also removes the residual mean from
-// r on active cells.  Stops if |sigma| < 1e-300.
-template <typename T, int FINE>
+// r on active cells.  Stops if |sigma| < 1e-300.  Vectors whose cells all lie
+// outside the body box (with a one-cell margin) take iD in closed form.
+template <typename T, int D, int FINE>
 __global__ void __launch_bounds__(kBlock) k_pcg_b(int64_t nvec, const T* iD, const T* e, const T* q, T* x,
                                                   T* r, double* red, int k, RedN rn, double* part_rho_next,
-                                                  double* part_max, int want_rho, int want_max, int* flag) {
+                                                  double* part_max, int want_rho, int want_max, int* flag,
+                                                  Grid3 g, StdBox B) {
   typedef typename Vec16<T>::type V;
   constexpr int W = Vec16<T>::W;
   bool skip = (*flag) != 0;
@@ -849,6 +934,37 @@ __global__ void __launch_bounds__(kBlock) k_pcg_b(int64_t nvec, const T* iD, con
   V* xv = reinterpret_cast<V*>(x);
   V* rv = reinterpret_cast<V*>(r);
   const int64_t stride = (int64_t)gridDim.x * kBlock;
+  const int px = g.s[1], py = g.n[1] + 2;
+  // iD of the W cells of vector v in closed form; false if any of them is near the box
+  auto std_vec = [&](int64_t v, V& out) -> bool {
+    T* o = reinterpret_cast<T*>(&out);
+    const int e0 = (int)(v * W) - kFrontPad;  // field index of lane 0 (< 2^31 by the plan)
+    int cx = -1, cy = 0, cz = 0;
+    if (e0 >= 0) {
+      const int row = e0 / px;
+      cx = e0 - row * px;
+      cy = row % py;
+      cz = row / py;
+    }
+#pragma unroll
+    for (int w = 0; w < W; ++w) {
+      int I[3] = {cx + w, cy, cz};
+      if (e0 + w < 0) {
+        o[w] = T(0);
+        continue;
+      }
+      if (I[0] >= px) {  // the vector crosses into the next row
+        I[0] -= px;
+        if (++I[1] == py) {
+          I[1] = 0;
+          ++I[2];
+        }
+      }
+      if (!std_point<D>(B, g, I, 1)) return false;
+      o[w] = iD_std<T, D>(g, B, I[0], I[1], I[2]);
+    }
+    return true;
+  };
   // two vectors per thread and trip, both coalesced, so twice the loads are in flight
   for (int64_t v0 = blockIdx.x * (int64_t)kBlock + threadIdx.x; v0 < nvec; v0 += 2 * stride) {
     const int64_t vv[2] = {v0, v0 + stride};
@@ -857,7 +973,7 @@ __global__ void __launch_bounds__(kBlock) k_pcg_b(int64_t nvec, const T* iD, con
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
       if (!has[h]) continue;
-      dv[h] = iDv[vv[h]];
+      if (!std_vec(vv[h], dv[h])) dv[h] = iDv[vv[h]];
       rr[h] = rv[vv[h]];
       if (!skip) {
         ee[h] = ev[vv[h]];
@@ -912,14 +1028,19 @@ __global__ void __launch_bounds__(kBlock) k_finalize_max(const double* part, int
 
 // projection update u_a -= L_a (x[I] - x[I-e_a]) on interior cells; p = x / wdt.
 template <typename T, int D>
-__global__ void __launch_bounds__(kBlock) k_project(Grid3 g, Vec3<T> u, Vec3<T> L, const T* x, T* p, T wdt) {
+__global__ void __launch_bounds__(kBlock) k_project(Grid3 g, Vec3<T> u, Vec3<T> L, const T* x, T* p, T wdt,
+                                                    StdBox B) {
   const int total = g.n[0] * g.n[1] * ((D == 3) ? g.n[2] : 1);
   for (int lin = blockIdx.x * kBlock + threadIdx.x; lin < total; lin += gridDim.x * kBlock) {
     int I[3], idx, op[3], om[3];
     cell_of<D>(g, lin, I, idx);
     nbr_offsets<D>(g, I, op, om);
     const T xc = x[idx];
-    for (int a = 0; a < D; ++a) u.c[a][idx] = u.c[a][idx] - L.c[a][idx] * (xc - x[idx + om[a]]);
+    const bool sc = std_point<D>(B, g, I, 0);
+    for (int a = 0; a < D; ++a) {
+      const T Lc = sc ? L_std<T>(g, B, a, I[a]) : L.c[a][idx];
+      u.c[a][idx] = u.c[a][idx] - Lc * (xc - x[idx + om[a]]);
+    }
     if (p) p[idx] = xc / wdt;
   }
 }

@@ -301,6 +301,7 @@ struct SimBase {
                              double* loss, int apply) = 0;
   virtual wl_status pg_stats(double* loss, int64_t* steps, int64_t* snaps) = 0;
   virtual wl_status body_update(const wl_body_desc* b) = 0;
+  virtual wl_status body_box_of(int level, int lo[3], int hi[3]) = 0;
   virtual wl_status adj_reset() = 0;
   virtual wl_status adj_forces(const double dir[3], double weight, double* value) = 0;
   virtual wl_status adj_step(double tol, wl_step_stats* fst, wl_solve_stats* ast) = 0;
@@ -372,6 +373,7 @@ struct Impl : SimBase {
   PgBox bd{}, bcrop{};
   int64_t pgPc = 0;
   int tiles[kMaxLevels][4] = {};  // tiled pass A: tiles_x, tiles_y, ntiles (0 = generic kernel)
+  StdBox sbox[kMaxLevels] = {};   // per level: outside, coefficients are body-free
   // discrete adjoint
   bool adj_on = false, rec = false;
   T* au[2][3] = {};  // ubar ping-pong; au[acur] is the adjoint of the current state
@@ -628,6 +630,32 @@ struct Impl : SimBase {
     }
   }
 
+  // Body boxes of every level from the fine one (box_lo/hi, or empty without a body).
+  // Coarse face/cell J covers fine indices 2J-1 and 2J, so J outside
+  // [floor(lo/2) - 1, floor((hi+1)/2) + 1] has all its fine indices outside [lo, hi].
+  void update_sbox() {
+    int lo[3] = {1, 1, 1}, hi[3] = {0, 0, 0};
+    if (has_body && have_box)
+      for (int a = 0; a < 3; ++a) {
+        lo[a] = a < D ? box_lo[a] : 0;
+        hi[a] = a < D ? box_hi[a] : 0;
+      }
+    double Ls = 1.0;
+    for (int l = 0; l < nlev; ++l) {
+      for (int a = 0; a < 3; ++a) {
+        sbox[l].lo[a] = lo[a];
+        sbox[l].hi[a] = hi[a];
+      }
+      sbox[l].Lstd = Ls;
+      if (lo[0] <= hi[0])
+        for (int a = 0; a < D; ++a) {
+          lo[a] = std::max(0, lo[a] / 2 - 1);
+          hi[a] = std::min(g[l + 1 < nlev ? l + 1 : l].n[a] + 1, (hi[a] + 1) / 2 + 1);
+        }
+      Ls *= (D == 3) ? 2.0 : 1.0;
+    }
+  }
+
   wl_status measure_box(double tm, const int lo[3], const int hi[3]) {
     Motion m{};
     if (has_body) host_motion(bdesc, tm, m);
@@ -648,6 +676,7 @@ struct Impl : SimBase {
       body_box(tm, box_lo, box_hi);
       have_box = true;
     }
+    update_sbox();
     return s;
   }
 
@@ -667,6 +696,7 @@ struct Impl : SimBase {
       box_lo[a] = lo[a];
       box_hi[a] = hi[a];
     }
+    update_sbox();
     return s;
   }
 
@@ -707,11 +737,11 @@ struct Impl : SimBase {
         if (l == 0)
           WL_TIMED(kidA, (k_pcg_a_tile<T, 1><<<ga, kTileThreads, 0, stream>>>(
                               g[l], v3(L[l]), iD[l], r[l], eo, en, q[l], red, k, rn, slot(kSlotSig0 + k),
-                              flags + l, tiles[l][0], tiles[l][1], tiles[l][2])));
+                              flags + l, tiles[l][0], tiles[l][1], tiles[l][2], sbox[l])));
         else
           WL_TIMED(kidA, (k_pcg_a_tile<T, 0><<<ga, kTileThreads, 0, stream>>>(
                               g[l], v3(L[l]), iD[l], r[l], eo, en, q[l], red, k, rn, slot(kSlotSig0 + k),
-                              flags + l, tiles[l][0], tiles[l][1], tiles[l][2])));
+                              flags + l, tiles[l][0], tiles[l][1], tiles[l][2], sbox[l])));
       } else {
         ga = nb[l];
         if (l == 0)
@@ -731,13 +761,13 @@ struct Impl : SimBase {
       T* b_x = x[l] - kFrontPad;
       T* b_r = r[l] - kFrontPad;
       if (l == 0)
-        WL_TIMED(kidB, (k_pcg_b<T, 1><<<gb, kBlock, 0, stream>>>(nvec, b_iD, b_e, b_q, b_x, b_r, red, k, rn,
-                                                                 slot(kSlotRho0 + k + 1), slot(kSlotRmax), wr, wm,
-                                                                 flags + l)));
+        WL_TIMED(kidB, (k_pcg_b<T, D, 1><<<gb, kBlock, 0, stream>>>(nvec, b_iD, b_e, b_q, b_x, b_r, red, k, rn,
+                                                                    slot(kSlotRho0 + k + 1), slot(kSlotRmax), wr,
+                                                                    wm, flags + l, g[l], sbox[l])));
       else
-        WL_TIMED(kidB, (k_pcg_b<T, 0><<<gb, kBlock, 0, stream>>>(nvec, b_iD, b_e, b_q, b_x, b_r, red, k, rn,
-                                                                 slot(kSlotRho0 + k + 1), slot(kSlotRmax), wr, wm,
-                                                                 flags + l)));
+        WL_TIMED(kidB, (k_pcg_b<T, D, 0><<<gb, kBlock, 0, stream>>>(nvec, b_iD, b_e, b_q, b_x, b_r, red, k, rn,
+                                                                    slot(kSlotRho0 + k + 1), slot(kSlotRmax), wr,
+                                                                    wm, flags + l, g[l], sbox[l])));
       if (wr) slot_n[kSlotRho0 + k + 1] = gb;
       if (wm) slot_n[kSlotRmax] = gb;
       std::swap(eo, en);
@@ -755,7 +785,7 @@ struct Impl : SimBase {
       WL_TIMED(l == 0 ? WL_K_PROLONG : WL_K_COARSE,
                (k_prolong_tile<T><<<tiles[l][2], kTileThreads, 0, stream>>>(
                    g[l], g[l + 1], x[l + 1], v3(L[l]), iD[l], x[l], r[l], red, flags + l, tiles[l][0],
-                   tiles[l][1], tiles[l][2])));
+                   tiles[l][1], tiles[l][2], sbox[l])));
       set_mean_producer(tiles[l][2]);
     } else {
       WL_TIMED(l == 0 ? WL_K_PROLONG : WL_K_COARSE,
@@ -801,11 +831,11 @@ struct Impl : SimBase {
       pg_guess(uu, w * dt);  // x[0] = learned guess
       WL_TIMED(WL_K_DIVRES, (k_div_res<T, D><<<nb[0], kBlock, 0, stream>>>(g[0], v3(uu), nullptr, nullptr, wdt,
                                                                             v3(L[0]), iD[0], x[0], r[0],
-                                                                            slot(kSlotRmax), red, flags)));
+                                                                            slot(kSlotRmax), red, flags, sbox[0])));
     } else {
       WL_TIMED(WL_K_DIVRES, (k_div_res<T, D><<<nb[0], kBlock, 0, stream>>>(g[0], v3(uu), nullptr, p, wdt, v3(L[0]),
                                                                             iD[0], x[0], r[0], slot(kSlotRmax), red,
-                                                                            flags)));
+                                                                            flags, sbox[0])));
     }
     set_mean_producer(nb[0]);
     slot_n[kSlotRmax] = nb[0];
@@ -814,7 +844,8 @@ struct Impl : SimBase {
     if (s != WL_OK) return s;
     if (guided && pg_mode == 2) pg_snapshot(w * dt);
     if (pg_on) WL_HIP(hipMemcpyAsync(p2, p, plan.lev[0].elems * sizeof(T), hipMemcpyDeviceToDevice, stream));
-    WL_TIMED(WL_K_PROJECT, (k_project<T, D><<<nb[0], kBlock, 0, stream>>>(g[0], v3(uu), v3(L[0]), x[0], p, wdt)));
+    WL_TIMED(WL_K_PROJECT, (k_project<T, D><<<nb[0], kBlock, 0, stream>>>(g[0], v3(uu), v3(L[0]), x[0], p, wdt,
+                                                                          sbox[0])));
     WL_HIP(hipGetLastError());
     if (pg_on) ++pg_hist;
     if (pg_on && pg_mode == 2 && ring_used > 0) {
@@ -1023,7 +1054,7 @@ struct Impl : SimBase {
     if (xin) WL_HIP(hipMemcpyAsync(x[0], xin, bytes, hipMemcpyDeviceToDevice, stream));
     WL_TIMED(WL_K_DIVRES, (k_div_res<T, D><<<nb[0], kBlock, 0, stream>>>(g[0], v3(u[cur]), (const T*)rhs, nullptr,
                                                                           T(0), v3(L[0]), iD[0], x[0], r[0],
-                                                                          slot(kSlotRmax), red, flags)));
+                                                                          slot(kSlotRmax), red, flags, sbox[0])));
     WL_HIP(hipGetLastError());
     set_mean_producer(nb[0]);
     slot_n[kSlotRmax] = nb[0];
@@ -1035,7 +1066,7 @@ struct Impl : SimBase {
 
   wl_status conv_diff() override {
     k_flux<T, D><<<dim3(nb_face, D), kBlock, 0, stream>>>(g[0], v3(u[cur]), v3(u[cur]), v3(V), v3(ft), T(0),
-                                                          T(desc.nu), 0, 1);
+                                                          T(desc.nu), 0, 1, sbox[0]);
     WL_HIP(hipGetLastError());
     return WL_OK;
   }
@@ -1051,9 +1082,9 @@ struct Impl : SimBase {
     const int hb = has_body ? 1 : 0;
     // predictor
     WL_TIMED(WL_K_FLUX, (k_flux<T, D><<<dim3(nb_face, D), kBlock, 0, stream>>>(g[0], v3(A), v3(A), v3(V), v3(ft),
-                                                                              T(dt), T(desc.nu), hb, 0)));
+                                                                              T(dt), T(desc.nu), hb, 0, sbox[0])));
     WL_TIMED(WL_K_BDIM, (k_bdim<T, D, 0><<<dim3(nb_face, D), kBlock, 0, stream>>>(g[0], v3(ft), v3(V), v3(mu0),
-                                                                                 v9(mu1), v3(B), hb)));
+                                                                                 v9(mu1), v3(B), hb, sbox[0])));
     const bool ex = desc.convective_exit != 0;
     if (ex) {
       const int m = g[0].n[1] * (D == 3 ? g[0].n[2] : 1);
@@ -1078,9 +1109,9 @@ struct Impl : SimBase {
     }
     // corrector
     WL_TIMED(WL_K_FLUX, (k_flux<T, D><<<dim3(nb_face, D), kBlock, 0, stream>>>(g[0], v3(B), v3(A), v3(V), v3(ft),
-                                                                              T(dt), T(desc.nu), hb, 0)));
+                                                                              T(dt), T(desc.nu), hb, 0, sbox[0])));
     WL_TIMED(WL_K_BDIM, (k_bdim<T, D, 1><<<dim3(nb_face, D), kBlock, 0, stream>>>(g[0], v3(ft), v3(V), v3(mu0),
-                                                                                 v9(mu1), v3(B), hb)));
+                                                                                 v9(mu1), v3(B), hb, sbox[0])));
     WL_HIP(hipGetLastError());
     if ((s = bc(B, ex)) != WL_OK) return s;
     if ((s = project(B, 0.5, &s2)) != WL_OK) return s;
@@ -1145,6 +1176,15 @@ struct Impl : SimBase {
     return WL_OK;
   }
 
+  wl_status body_box_of(int level, int lo[3], int hi[3]) override {
+    if (level < 0 || level >= nlev) return fail(WL_ERR_INVALID_ARG, "level out of range");
+    for (int a = 0; a < 3; ++a) {
+      lo[a] = sbox[level].lo[a];
+      hi[a] = sbox[level].hi[a];
+    }
+    return WL_OK;
+  }
+
   // ---- body update and discrete adjoint -----------------------------------------
   wl_status body_update(const wl_body_desc* b) override {
     if (!b) return fail(WL_ERR_INVALID_ARG, "body is NULL");
@@ -1205,7 +1245,7 @@ struct Impl : SimBase {
     fill_field(x[0], T(0));
     WL_TIMED(WL_K_DIVRES, (k_div_res<T, D><<<nb[0], kBlock, 0, stream>>>(g[0], v3(u[cur]), arhs, nullptr, T(0),
                                                                           v3(L[0]), iD[0], x[0], r[0],
-                                                                          slot(kSlotRmax), red, flags)));
+                                                                          slot(kSlotRmax), red, flags, sbox[0])));
     set_mean_producer(nb[0]);
     slot_n[kSlotRmax] = nb[0];
     WL_HIP(hipGetLastError());
@@ -1581,6 +1621,12 @@ wl_status wl_pg_train_step(wl_sim* sim, const void* x_box, const float* target, 
 wl_status wl_body_update(wl_sim* sim, const wl_body_desc* body) {
   WL_SIM_CHECK(sim);
   return sim->impl->body_update(body);
+}
+
+wl_status wl_body_box(wl_sim* sim, int level, int lo[3], int hi[3]) {
+  WL_SIM_CHECK(sim);
+  if (!lo || !hi) return fail(WL_ERR_INVALID_ARG, "lo/hi are NULL");
+  return sim->impl->body_box_of(level, lo, hi);
 }
 
 wl_status wl_adj_reset(wl_sim* sim) {

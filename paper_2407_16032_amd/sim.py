@@ -230,6 +230,13 @@ class Simulation:
         self.bdesc = _body_desc(body)
         L.check(self.lib.wl_body_update(self._h, C.byref(self.bdesc)), "wl_body_update")
 
+    def body_box(self, level: int = 0):
+        """(lo, hi) padded index box of a level outside of which coefficients are body-free."""
+        lo = (C.c_int * 3)()
+        hi = (C.c_int * 3)()
+        L.check(self.lib.wl_body_box(self._h, int(level), lo, hi), "wl_body_box")
+        return tuple(lo)[:self.ndim], tuple(hi)[:self.ndim]
+
     def adj_reset(self):
         L.check(self.lib.wl_adj_reset(self._h), "wl_adj_reset")
 

@@ -21,6 +21,10 @@ def test_moment_end_values(eps):
     # mu1(0) = eps (1/4 - 1/pi^2) ~ 0.148679 eps
     assert mu1(0.0, eps) == pytest.approx(eps * (0.25 - 1.0 / math.pi ** 2), rel=1e-14)
     assert mu1(0.0, 1.0) == pytest.approx(0.148679, abs=1e-6)
+    # beyond the support the moments are the full integrals, exactly (int K = 1, int s K = 0)
+    for d in (eps, 1.5 * eps, 40.0 * eps):
+        assert mu0(d, eps) == 1.0 and mu1(d, eps) == 0.0 and mu1(-d, eps) == 0.0
+        assert mu0(-d, eps) == 0.0
 
 
 def test_kernel_unit_integral():

@@ -143,6 +143,11 @@ def rotating_cylinder_2d(n=(512, 256), D=32.0, center=(128.0, 128.0), Re=200.0, 
                     steps=steps, tol=tol, L=D)
 
 
+def rotcyl_xi0(seed: int = 0) -> float:
+    """Seeded rotation rate in [0, 2) for the rotating-cylinder gradient case."""
+    return 2.0 * float(uniform01(np.array([0], dtype=np.uint64), seed=seed)[0])
+
+
 def plate_3d(scale: int = 1, steps=200, tol=1e-5) -> Workload:
     """Heaving-pitching flat plate; scale=1 is 768x384x384 cells (113 M).
 
