@@ -35,22 +35,27 @@ def workloads():
     }
 
 
-def kernel_bytes(name, ndim, cells, faces, esize, has_body, pcg_iters, box_cells=None, box_faces=None):
-    """Algorithmic bytes of one launch: each input field read once, each output written once.
+def kernel_bytes(name, ndim, cells, faces, esize, has_body, pcg_iters, box_cells=None, box_faces=None,
+                 tiled=False):
+    """Algorithmic bytes of one launch of the kernels as built: each field the pass
+    needs is read once, each output written once.
 
     cells = interior cells of the fine level, faces = padded points per component.
-    Coefficient fields (L, iD on cells; V, mu0, mu1 on faces) are only read inside
-    the body box (box_cells / box_faces; everything if not given): outside it the
-    kernels evaluate their body-free closed form.
+    Coefficient fields (L, iD on cells; V, mu0, mu1 on faces) are only needed inside
+    the body box (box_cells / box_faces): outside it the kernels evaluate their
+    body-free closed form.  On tiled levels (3-D, large) pass A does not store q and
+    pass B recomputes it from e (pass B then needs L and iD in the box).
     """
     n = ndim
     bc = cells if box_cells is None else box_cells
     bf = faces if box_faces is None else box_faces
     if name == "pcg_a":
-        # reads r, and e_old except in the first sweep; writes e_new, q; iD, L (n) in the box
-        fields = (1 + (pcg_iters - 1) / pcg_iters) + 2
+        # reads r, and e_old except in the first sweep; writes e_new (and q if not tiled); iD, L (n) in the box
+        fields = (1 + (pcg_iters - 1) / pcg_iters) + (1 if tiled else 2)
         return (fields * cells + (1 + n) * bc) * esize
     if name == "pcg_b":
+        if tiled:  # reads e, x, r; writes x, r; iD and L (n) in the box
+            return (5 * cells + (1 + n) * bc) * esize
         return ((4 + 2) * cells + bc) * esize    # reads e, q, x, r; writes x, r; iD in the box
     if name == "divres":
         return ((n + 1 + 2) * cells + (n + 1) * bc) * esize   # u (n), p; writes x, r; L (n), iD in the box
@@ -69,6 +74,15 @@ def kernel_bytes(name, ndim, cells, faces, esize, has_body, pcg_iters, box_cells
     if name == "cfl":
         return n * cells * esize
     return None
+
+
+def fine_level_tiled(n):
+    """The library tiles a 3-D level (64 x 8 x 32 z-marching tiles) when n0 >= 32,
+    n1 >= 8, it has >= 2^18 cells and at most 8192 tiles."""
+    if len(n) != 3:
+        return False
+    tiles = -(-n[0] // 64) * -(-n[1] // 8) * -(-n[2] // 32)
+    return n[0] >= 32 and n[1] >= 8 and n[0] * n[1] * n[2] >= (1 << 18) and tiles <= 8192
 
 
 def model_bytes(name, ndim, cells, esize):
@@ -163,6 +177,62 @@ def copy_probe(nbytes):
     print(json.dumps({"copy_bytes": nbytes, "ms": ms, "GBps_read_plus_write": 2 * nbytes / (ms * 1e-3) / 1e9}))
 
 
+def run_adjoint(args):
+    """The rotating-cylinder gradient case: 512 x 256 cells, D = 32, Re = 200, xi
+    seeded in [0, 2), 400 steps, mean C_D over steps 200..399, FP64 with multigrid to
+    1e-12, checkpoints every 20 steps.  Times the forward rollout (with checkpoints)
+    and the reverse sweep, and checks the gradient against central differences of
+    the HIP forward (h = 1e-3) and, if stored, the oracle's complex-step gradient."""
+    import torch
+    import wlsynth
+    from paper_2407_16032_amd.adjoint import RotatingCylinderDrag
+    w = wlsynth.rotating_cylinder_2d()
+    xi, R = wlsynth.rotcyl_xi0(0), float(w.body.radius)
+    steps = args.steps if args.steps_given else 400
+    win = steps // 2
+    golden = os.path.join(ROOT, "tests", "golden", "rotcyl_512x256_gradient.json")
+    ref = None
+    if os.path.exists(golden) and steps == 400:
+        with open(golden) as f:
+            ref = json.load(f)
+    prob = RotatingCylinderDrag(w, wlsynth.initial_velocity(w), steps, win, ckpt=20, prec="f64", tol=1e-12,
+                                itmax=200)
+    if ref is not None:
+        prob.dts = list(ref["dt_schedule"])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    J, ckpts = prob.value(xi, R, record=True)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    gx, gR = prob.gradient(xi, R, J, ckpts)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    print("[bench] adjoint: J %.10g dJ/dxi %.10g dJ/dR %.10g  forward %.2f s  reverse %.2f s" % (
+        J, gx, gR, t1 - t0, t2 - t1), file=sys.stderr, flush=True)
+    h = 1e-3
+    fx = (prob.value(xi + h, R) - prob.value(xi - h, R)) / (2 * h)
+    fR = (prob.value(xi, R + h) - prob.value(xi, R - h)) / (2 * h)
+    out = {
+        "metric": "adjoint / forward cost ratio (rotating-cylinder drag gradient, FP64)",
+        "value": round((t2 - t1) / (t1 - t0), 3),
+        "unit": "ratio",
+        "n_gpus": 1, "steps": steps, "higher_is_better": False, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": w.name, "cells": w.cells, "xi": xi, "R": R, "window_start": win,
+                   "checkpoint_every": 20, "mg_tol": 1e-12},
+        "forward_s": round(t1 - t0, 3), "reverse_s": round(t2 - t1, 3),
+        "J": J, "dJ_dxi": gx, "dJ_dR": gR,
+        "fd_h": h, "fd_dJ_dxi": fx, "fd_dJ_dR": fR,
+        "rel_vs_fd": [abs(gx - fx) / abs(fx), abs(gR - fR) / abs(fR)],
+        "stats": prob.stats,
+    }
+    if ref is not None:
+        out["oracle"] = {"J": ref["J"], "dJ_dxi": ref["dJ_dxi"], "dJ_dR": ref["dJ_dR"],
+                         "rel": [abs(gx - ref["dJ_dxi"]) / abs(ref["dJ_dxi"]),
+                                 abs(gR - ref["dJ_dR"]) / abs(ref["dJ_dR"])]}
+    print(json.dumps(out))
+    prob.sim.close()
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -171,9 +241,12 @@ def main():
     ap.add_argument("--workload", default="plate3d", choices=sorted(workloads().keys()))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true", help="skip per-kernel event timing")
+    ap.add_argument("--adjoint", action="store_true",
+                    help="run the rotating-cylinder gradient case instead (adjoint vs forward cost)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="only run a plain device copy of BYTES bytes (calibrates HBM counters)")
     args = ap.parse_args()
+    args.steps_given = any(a == "--steps" or a.startswith("--steps=") for a in sys.argv[1:])
     if args.copy_probe:
         copy_probe(args.copy_probe)
         return
@@ -191,6 +264,9 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
+    if args.adjoint:
+        run_adjoint(args)
+        return
     w = workloads()[args.workload]
     body = w.body if w.body.kind != "none" else None
     print("[bench] workload %s (%d cells), building initial field" % (w.name, w.cells), file=sys.stderr,
@@ -239,32 +315,28 @@ def main():
         for name, (tms, cnt) in prof.items():
             if cnt == 0:
                 continue
-            b = kernel_bytes(name, w.ndim, cells, faces, 4, body is not None, 6, bcells, bfaces)
+            b = kernel_bytes(name, w.ndim, cells, faces, 4, body is not None, 6, bcells, bfaces,
+                             fine_level_tiled(w.n))
             avg_ms = tms / cnt
             ent = {"total_ms_per_step": tms / args.steps, "launches_per_step": cnt / args.steps,
                    "avg_us": avg_ms * 1e3}
             if b is not None:
-                ent["loaded_GBps"] = b / (avg_ms * 1e-3) / 1e9
+                ent["GBps"] = b / (avg_ms * 1e-3) / 1e9
             kernels[name] = ent
             if b is not None and (best is None or tms > best[1]):
                 best = (name, tms, b, avg_ms)
         if best is not None:
-            name, tms, b_loaded, avg_ms = best
-            b = model_bytes(name, w.ndim, cells, 4)
-            if b is None:
-                b = b_loaded
+            name, tms, b, avg_ms = best
             ach = b / (avg_ms * 1e-3) / 1e9
-            traffic = measured_traffic(w.name, name)
             roof = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                    "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": traffic,
+                    "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": measured_traffic(w.name, name),
                     "kernel": name, "bytes_per_launch": b, "avg_launch_us": round(avg_ms * 1e3, 2),
-                    "loaded_bytes_per_launch": b_loaded,
-                    "loaded_GBps": round(b_loaded / (avg_ms * 1e-3) / 1e9, 1),
+                    "dense_model_bytes_per_launch": model_bytes(name, w.ndim, cells, 4),
                     "body_box_cells": bcells}
         for name, ent in sorted(kernels.items(), key=lambda kv: -kv[1]["total_ms_per_step"]):
             print("[bench]   %-9s %8.3f ms/step %6.1f launches/step %9.1f us avg %s" % (
                 name, ent["total_ms_per_step"], ent["launches_per_step"], ent["avg_us"],
-                ("%7.0f GB/s loaded" % ent["loaded_GBps"]) if "loaded_GBps" in ent else ""), file=sys.stderr, flush=True)
+                ("%7.0f GB/s" % ent["GBps"]) if "GBps" in ent else ""), file=sys.stderr, flush=True)
 
     cpu = None
     if not args.no_cpu_baseline:

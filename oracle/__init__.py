@@ -24,6 +24,10 @@ body      analytic bodies, rigid motion, ``measure``, force integrals
 flux      limited QUICK face value and the convection-diffusion residual R(u)
 poisson   variable-coefficient Poisson operator, multigrid V-cycle, PCG smoother
 solver    BDIM blend, boundary conditions, projection, CFL, the full step
+pgnet     the learned multigrid initial guess (an extension): conv net, its
+          backward pass and Adam, on BF16-rounded inputs, in FP64
+adjoint   the rollout objective's exact derivative by complex step (the paper
+          differentiates the solver with dual numbers)
 """
 from .grid import Grid
 from .moments import kernel, mu0, mu1

@@ -787,9 +787,11 @@ __global__ void __launch_bounds__(kBlock) k_pcg_a(Grid3 g, Vec3<T> L, const T* i
 // PCG pass A, tiled 2.5-D form for large 3-D levels: one block per (64 x 8 x kTZ)
 // tile, marching in z.  The search direction of the current plane (tile + 1-cell
 // halo) lives in LDS, the planes z-1 and z+1 of the block's own columns in
-// registers, so every input field is read from memory once per cell.
+// registers, so every input field is read from memory once per cell.  With
+// STOREQ = 0 q = A e is only reduced into sigma, not stored: the tiled pass B
+// recomputes it from e.
 
-template <typename T, int FINE>
+template <typename T, int FINE, int STOREQ = 1>
 __global__ void __launch_bounds__(kTileThreads) k_pcg_a_tile(Grid3 g, Vec3<T> L, const T* iD, const T* r,
                                                              const T* eo, T* en, T* q, double* red, int k,
                                                              RedN rn, double* part_sig, int* flag, int tiles_x,
@@ -883,7 +885,7 @@ __global__ void __launch_bounds__(kTileThreads) k_pcg_a_tile(Grid3 g, Vec3<T> L,
         if (k == 0) rho0 += double(rc - mean) * double(ec);
       }
       en[id] = ec;
-      q[id] = qq;
+      if (STOREQ) q[id] = qq;
       sig += double(ec) * double(qq);
     }
     __syncthreads();
@@ -898,6 +900,118 @@ __global__ void __launch_bounds__(kTileThreads) k_pcg_a_tile(Grid3 g, Vec3<T> L,
   if (k == 0) {
     rho0 = block_sum<kTileThreads>(rho0);
     if (threadIdx.x == 0) red[(size_t)kSlotRho0 * kMaxBlocks + blockIdx.x] = rho0;
+  }
+}
+
+// PCG pass B (sweep k), tiled z-marching form paired with pass A (STOREQ = 0):
+// q = A e is recomputed from e (LDS plane + registers, as in pass A) instead of
+// being stored and re-read; then x += alpha e, r -= alpha q on the interior, with
+// the same scalars, stopping rule, mean removal (sweep 0) and partials (rho_{k+1},
+// max|r|) as the flat pass B.
+template <typename T, int FINE>
+__global__ void __launch_bounds__(kTileThreads) k_pcg_b_tile(Grid3 g, Vec3<T> L, const T* iD, const T* e, T* x,
+                                                             T* r, double* red, int k, RedN rn, double* part_rho_next,
+                                                             double* part_max, int want_rho, int want_max, int* flag,
+                                                             int tiles_x, int tiles_y, int ntiles, StdBox B) {
+  bool skip = (*flag) != 0;
+  T alpha = T(0);
+  const T mean = (k == 0) ? T(residual_mean<kTileThreads>(red, rn.mean)) : T(0);
+  if (!skip) {
+    const double sig = total_of<kTileThreads>(red + (size_t)(kSlotSig0 + k) * kMaxBlocks, rn.sig);
+    if (fabs(sig) < 1e-300) {
+      skip = true;
+      if (blockIdx.x == 0 && threadIdx.x == 0) *flag = 1;
+    } else {
+      alpha = T(total_of<kTileThreads>(red + (size_t)(kSlotRho0 + k) * kMaxBlocks, rn.rho) / sig);
+    }
+  }
+  if (skip && !want_max && mean == T(0)) return;  // grid-uniform
+  __shared__ T sE[kTY + 2][kTX + 2];
+  const int b = blockIdx.x;
+  const int full = (ntiles / 8) * 8;
+  const int tile = (b < full) ? (b % 8) * (ntiles / 8) + b / 8 : b;
+  const int txi = tile % tiles_x, rem = tile / tiles_x, tyi = rem % tiles_y, tzi = rem / tiles_y;
+  const int x0 = 1 + txi * kTX, y0 = 1 + tyi * kTY, z0 = 1 + tzi * kTZ;
+  const int z1 = min(z0 + kTZ, g.n[2] + 1);
+  const int tx = threadIdx.x % kTX, ty = threadIdx.x / kTX;
+  const int n0 = g.n[0], n1 = g.n[1];
+  const int s1 = g.s[1], s2 = g.s[2];
+  const int i = x0 + tx, j = y0 + ty;
+  const bool inb = i <= n0 + 1 && j <= n1 + 1;
+  const bool own = i <= n0 && j <= n1;
+  const int wi = wrapc(i, 0, g), wj = wrapc(j, 1, g);
+  const int col = wi + wj * s1;
+  const int t = threadIdx.x;
+  int sx = 0, sy = 0, hcol = 0;
+  bool hb = false;
+  const bool ring = t < 2 * (kTX + 2) + 2 * kTY;
+  if (ring) {
+    if (t < kTX + 2) { sx = t; sy = 0; }
+    else if (t < 2 * (kTX + 2)) { sx = t - (kTX + 2); sy = kTY + 1; }
+    else if (t < 2 * (kTX + 2) + kTY) { sx = 0; sy = 1 + t - 2 * (kTX + 2); }
+    else { sx = kTX + 1; sy = 1 + t - 2 * (kTX + 2) - kTY; }
+    const int rx = x0 - 1 + sx, ry = y0 - 1 + sy;
+    hb = rx >= 0 && rx <= n0 + 1 && ry >= 0 && ry <= n1 + 1;
+    hcol = wrapc(rx, 0, g) + wrapc(ry, 1, g) * s1;
+  }
+  const int ta[3] = {x0 - 2, y0 - 2, z0 - 2}, tb[3] = {x0 + kTX + 1, y0 + kTY + 1, z1 + 1};
+  const bool fast = std_miss<3>(B, g, ta, tb);
+  const int opx = (g.per[0] && i == n0) ? -(n0 - 1) : 1;
+  const int opy = (g.per[1] && j == n1) ? -(n1 - 1) * s1 : s1;
+  T em = T(0), ec = T(0), L2c = T(0);
+  if (inb) {
+    em = e[col + wrapc(z0 - 1, 2, g) * s2];
+    ec = e[col + z0 * s2];
+    L2c = fast ? L_std<T>(g, B, 2, z0) : L.c[2][col + z0 * s2];
+  }
+  double rho = 0.0, mx = 0.0;
+  for (int z = z0; z < z1; ++z) {
+    const int zp = wrapc(z + 1, 2, g);
+    T ep = T(0), L2p = T(0);
+    if (inb) {
+      ep = e[col + zp * s2];
+      L2p = fast ? L_std<T>(g, B, 2, zp) : L.c[2][col + zp * s2];
+    }
+    sE[ty + 1][tx + 1] = ec;
+    if (ring) sE[sy][sx] = hb ? e[hcol + z * s2] : T(0);
+    __syncthreads();
+    if (own) {
+      const int id = col + z * s2;
+      const T dc = fast ? iD_std<T, 3>(g, B, i, j, z) : iD[id];
+      T rr = r[id];
+      if (mean != T(0) && dc != T(0)) rr = rr - mean;
+      if (!skip) {
+        T qq = T(0);
+        if (dc != T(0)) {
+          const T xm = sE[ty + 1][tx], xp = sE[ty + 1][tx + 2];
+          const T ym = sE[ty][tx + 1], yp = sE[ty + 2][tx + 1];
+          const T Lxp = fast ? L_std<T>(g, B, 0, i + 1) : L.c[0][id + opx];
+          const T Lxc = fast ? L_std<T>(g, B, 0, i) : L.c[0][id];
+          const T Lyp = fast ? L_std<T>(g, B, 1, j + 1) : L.c[1][id + opy];
+          const T Lyc = fast ? L_std<T>(g, B, 1, j) : L.c[1][id];
+          qq = qq + Lxp * (xp - ec) - Lxc * (ec - xm);
+          qq = qq + Lyp * (yp - ec) - Lyc * (ec - ym);
+          qq = qq + L2p * (ep - ec) - L2c * (ec - em);
+        }
+        x[id] = x[id] + alpha * ec;
+        rr = rr - alpha * qq;
+      }
+      if (!skip || mean != T(0)) r[id] = rr;
+      rho += double(rr) * (double(dc) * double(rr));
+      mx = fmax(mx, fabs(double(rr)));
+    }
+    __syncthreads();
+    em = ec;
+    ec = ep;
+    L2c = L2p;
+  }
+  if (want_rho && !skip) {
+    rho = block_sum<kTileThreads>(rho);
+    if (threadIdx.x == 0) part_rho_next[blockIdx.x] = rho;
+  }
+  if (want_max) {
+    mx = block_max<kTileThreads>(mx);
+    if (threadIdx.x == 0) part_max[blockIdx.x] = mx;
   }
 }
 

@@ -734,12 +734,13 @@ struct Impl : SimBase {
       int ga;
       if (tiles[l][2] > 0) {
         ga = tiles[l][2];
+        // q is not stored: the tiled pass B recomputes it
         if (l == 0)
-          WL_TIMED(kidA, (k_pcg_a_tile<T, 1><<<ga, kTileThreads, 0, stream>>>(
+          WL_TIMED(kidA, (k_pcg_a_tile<T, 1, 0><<<ga, kTileThreads, 0, stream>>>(
                               g[l], v3(L[l]), iD[l], r[l], eo, en, q[l], red, k, rn, slot(kSlotSig0 + k),
                               flags + l, tiles[l][0], tiles[l][1], tiles[l][2], sbox[l])));
         else
-          WL_TIMED(kidA, (k_pcg_a_tile<T, 0><<<ga, kTileThreads, 0, stream>>>(
+          WL_TIMED(kidA, (k_pcg_a_tile<T, 0, 0><<<ga, kTileThreads, 0, stream>>>(
                               g[l], v3(L[l]), iD[l], r[l], eo, en, q[l], red, k, rn, slot(kSlotSig0 + k),
                               flags + l, tiles[l][0], tiles[l][1], tiles[l][2], sbox[l])));
       } else {
@@ -760,16 +761,28 @@ struct Impl : SimBase {
       T* b_q = q[l] - kFrontPad;
       T* b_x = x[l] - kFrontPad;
       T* b_r = r[l] - kFrontPad;
-      if (l == 0)
+      int gbk = gb;
+      if (tiles[l][2] > 0) {
+        gbk = tiles[l][2];
+        if (l == 0)
+          WL_TIMED(kidB, (k_pcg_b_tile<T, 1><<<gbk, kTileThreads, 0, stream>>>(
+                              g[l], v3(L[l]), iD[l], en, x[l], r[l], red, k, rn, slot(kSlotRho0 + k + 1),
+                              slot(kSlotRmax), wr, wm, flags + l, tiles[l][0], tiles[l][1], tiles[l][2], sbox[l])));
+        else
+          WL_TIMED(kidB, (k_pcg_b_tile<T, 0><<<gbk, kTileThreads, 0, stream>>>(
+                              g[l], v3(L[l]), iD[l], en, x[l], r[l], red, k, rn, slot(kSlotRho0 + k + 1),
+                              slot(kSlotRmax), wr, wm, flags + l, tiles[l][0], tiles[l][1], tiles[l][2], sbox[l])));
+      } else if (l == 0) {
         WL_TIMED(kidB, (k_pcg_b<T, D, 1><<<gb, kBlock, 0, stream>>>(nvec, b_iD, b_e, b_q, b_x, b_r, red, k, rn,
                                                                     slot(kSlotRho0 + k + 1), slot(kSlotRmax), wr,
                                                                     wm, flags + l, g[l], sbox[l])));
-      else
+      } else {
         WL_TIMED(kidB, (k_pcg_b<T, D, 0><<<gb, kBlock, 0, stream>>>(nvec, b_iD, b_e, b_q, b_x, b_r, red, k, rn,
                                                                     slot(kSlotRho0 + k + 1), slot(kSlotRmax), wr,
                                                                     wm, flags + l, g[l], sbox[l])));
-      if (wr) slot_n[kSlotRho0 + k + 1] = gb;
-      if (wm) slot_n[kSlotRmax] = gb;
+      }
+      if (wr) slot_n[kSlotRho0 + k + 1] = gbk;
+      if (wm) slot_n[kSlotRmax] = gbk;
       std::swap(eo, en);
     }
   }
