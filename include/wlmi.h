@@ -302,8 +302,12 @@ wl_status wl_pg_forward(wl_sim* sim, const void* x_box, const int64_t n[3], floa
  * takes the Adam step with the mode's learning rate. */
 wl_status wl_pg_train_step(wl_sim* sim, const void* x_box, const float* target, const unsigned char* mask,
                            const int64_t n[3], float* grad_out, double* loss, int apply);
-/* Loss of the last training step, training steps and snapshots taken so far. */
-wl_status wl_pg_stats(wl_sim* sim, double* last_loss, int64_t* train_steps, int64_t* snapshots);
+/* Loss of the last training step, training steps and snapshots taken so far, and
+ * how many guided solves used the guess out of those that tried it: a guess is
+ * used only if its initial residual max-norm is below that of the plain warm
+ * start (multigrid stays the fallback and the judge).  Any pointer may be NULL. */
+wl_status wl_pg_stats(wl_sim* sim, double* last_loss, int64_t* train_steps, int64_t* snapshots,
+                      int64_t* guesses_used, int64_t* guesses_tried);
 
 /* Kernel groups timed by the profiler. Fine-level launches are timed per
  * kernel; every launch on a coarser multigrid level counts as WL_K_COARSE. */

@@ -112,7 +112,8 @@ def load(path: str = LIB_PATH):
     lib.wl_pg_train_step.restype = C.c_int
     lib.wl_pg_train_step.argtypes = [P, P, P, P, C.POINTER(C.c_int64), FP, C.POINTER(C.c_double), C.c_int]
     lib.wl_pg_stats.restype = C.c_int
-    lib.wl_pg_stats.argtypes = [P, C.POINTER(C.c_double), C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
+    lib.wl_pg_stats.argtypes = [P, C.POINTER(C.c_double), C.POINTER(C.c_int64), C.POINTER(C.c_int64),
+                                C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
     DP = C.POINTER(C.c_double)
     lib.wl_body_update.restype = C.c_int
     lib.wl_body_update.argtypes = [P, C.POINTER(BodyDesc)]

@@ -150,6 +150,27 @@ __device__ __forceinline__ T iD_std(const Grid3& g, const StdBox& B, int i, int 
   return T(1) / (-(T(B.Lstd) * T(cnt)));
 }
 
+// Closed-form inverse diagonals by the number of non-periodic boundary faces of
+// a cell (0..3), computed once per thread (same expression as iD_std).
+template <typename T, int D>
+struct StdDiag {
+  T v[4];
+  __device__ explicit StdDiag(const StdBox& B) {
+#pragma unroll
+    for (int c = 0; c < 4; ++c) v[c] = T(1) / (-(T(B.Lstd) * T(2 * D - c)));
+  }
+  __device__ __forceinline__ T at(const Grid3& g, int i, int j, int k) const {
+    const int I[3] = {i, j, k};
+    int nb = 0;
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+      if (I[a] < 1 || I[a] > g.n[a]) return T(0);
+      if (!g.per[a]) nb += (I[a] == 1 ? 1 : 0) + (I[a] == g.n[a] ? 1 : 0);
+    }
+    return v[nb];
+  }
+};
+
 // is the cube [I - m, I + m] outside the box?
 template <int D>
 __device__ __forceinline__ bool std_point(const StdBox& B, const Grid3& g, const int I[3], int m) {
@@ -332,6 +353,10 @@ __global__ void __launch_bounds__(kBlock) k_flux(Grid3 g, Vec3<T> u, Vec3<T> u0,
       const int lo = (a == c && !g.per[a]) ? 2 : 1;
       unknown = unknown && I[a] >= lo && I[a] <= g.n[a];
     }
+    // the point-wise loads go first, so they overlap the stencil's
+    const bool needV = mode == 0 && has_body && !std_point<D>(B, g, I, 0);  // V = 0 outside the box
+    const T vb = needV ? V.c[c][idx] : T(0);
+    const T u0v = (mode == 0) ? u0.c[c][idx] : T(0);
     T R = T(0);
     if (unknown) {
       // interior fast path: the +-2 stencil needs no wrap and every far point is valid
@@ -342,8 +367,8 @@ __global__ void __launch_bounds__(kBlock) k_flux(Grid3 g, Vec3<T> u, Vec3<T> u0,
     if (mode == 1) {
       f.c[c][idx] = R;
     } else {
-      T v = u0.c[c][idx] + dt * R;
-      if (has_body && !std_point<D>(B, g, I, 0)) v = v - V.c[c][idx];  // V = 0 outside the box
+      T v = u0v + dt * R;
+      if (needV) v = v - vb;
       f.c[c][idx] = v;
     }
   }
@@ -527,10 +552,39 @@ __global__ void __launch_bounds__(kBlock) k_div_res(Grid3 g, Vec3<T> u, const T*
   const int total = g.n[0] * g.n[1] * ((D == 3) ? g.n[2] : 1);
   double mx = 0.0, sr = 0.0, cnt = 0.0;
   if (blockIdx.x == 0 && threadIdx.x == 0) *flag = 0;
+  const StdDiag<T, D> SD(B);
   for (int lin = blockIdx.x * kBlock + threadIdx.x; lin < total; lin += gridDim.x * kBlock) {
     int I[3], idx, op[3], om[3];
     cell_of<D>(g, lin, I, idx);
     nbr_offsets<D>(g, I, op, om);
+    // every load is issued up front (the coefficients only near the body), so one
+    // memory round trip serves the cell
+    const bool sc = std_point<D>(B, g, I, 1);
+    T di, Lp[3], Lc[3];
+    if (sc) {
+      di = SD.at(g, I[0], I[1], I[2]);
+#pragma unroll
+      for (int a = 0; a < D; ++a) {
+        Lp[a] = L_std<T>(g, B, a, I[a] + 1);
+        Lc[a] = L_std<T>(g, B, a, I[a]);
+      }
+    } else {
+      di = iD[idx];
+#pragma unroll
+      for (int a = 0; a < D; ++a) {
+        Lp[a] = L.c[a][idx + op[a]];
+        Lc[a] = L.c[a][idx];
+      }
+    }
+    const T* xs = p ? p : x;
+    const T sx = p ? wdt : T(1);
+    const T xc = xs[idx] * sx;
+    T xp[3], xm[3];
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+      xp[a] = xs[idx + op[a]] * sx;
+      xm[a] = xs[idx + om[a]] * sx;
+    }
     T z;
     if (rhs) {
       z = rhs[idx];
@@ -538,19 +592,10 @@ __global__ void __launch_bounds__(kBlock) k_div_res(Grid3 g, Vec3<T> u, const T*
       z = T(0);
       for (int a = 0; a < D; ++a) z = z + (u.c[a][idx + op[a]] - u.c[a][idx]);
     }
-    const bool sc = std_point<D>(B, g, I, 1);
-    const T di = sc ? iD_std<T, D>(g, B, I[0], I[1], I[2]) : iD[idx];
     T rr = T(0);
-    const T xc = p ? p[idx] * wdt : x[idx];
     if (di != T(0)) {
       T Ax = T(0);
-      for (int a = 0; a < D; ++a) {
-        const T xp = p ? p[idx + op[a]] * wdt : x[idx + op[a]];
-        const T xm = p ? p[idx + om[a]] * wdt : x[idx + om[a]];
-        const T Lp = sc ? L_std<T>(g, B, a, I[a] + 1) : L.c[a][idx + op[a]];
-        const T Lc = sc ? L_std<T>(g, B, a, I[a]) : L.c[a][idx];
-        Ax = Ax + Lp * (xp - xc) - Lc * (xc - xm);
-      }
+      for (int a = 0; a < D; ++a) Ax = Ax + Lp[a] * (xp[a] - xc) - Lc[a] * (xc - xm[a]);
       rr = z - Ax;
     }
     if (p) x[idx] = xc;
@@ -784,13 +829,82 @@ __global__ void __launch_bounds__(kBlock) k_pcg_a(Grid3 g, Vec3<T> L, const T* i
   }
 }
 
-// PCG pass A, tiled 2.5-D form for large 3-D levels: one block per (64 x 8 x kTZ)
-// tile, marching in z.  The search direction of the current plane (tile + 1-cell
-// halo) lives in LDS, the planes z-1 and z+1 of the block's own columns in
-// registers, so every input field is read from memory once per cell.  With
-// STOREQ = 0 q = A e is only reduced into sigma, not stored: the tiled pass B
-// recomputes it from e.
+// ---------------------------------------------------------------------------
+// 2.5-D tiles of the large 3-D levels: one block of 64 x 8 threads per
+// (64 x 8 x kTZ) column stack, marching in z.  The values of the current plane
+// (tile + a one-cell ring) live in a double-buffered LDS plane, the planes z-1 and
+// z+1 of the block's own columns in registers; loads for the next planes are
+// issued one iteration ahead, so one barrier per plane suffices and the load
+// latency overlaps the stencil work.
+// ---------------------------------------------------------------------------
+struct TileGeo {
+  int x0, y0, z0, z1;  // tile origin and end plane (exclusive)
+  int tx, ty, i, j;    // own column
+  bool inb, own;       // column inside the padded grid / interior
+  int col;             // wrapped linear index of the own column (z = 0)
+  bool ring;           // this thread also carries one ring cell
+  int sx, sy, hx, hy;  // ring cell: LDS position, wrapped grid coordinates
+  bool hb;             // ring cell inside the padded grid
+  int hcol;
+  int opx, opy;        // +x / +y face offsets of the own column (periodic wrap)
+  bool fast;           // the stencil misses the body box: closed-form coefficients
 
+  __device__ TileGeo(const Grid3& g, const StdBox& B, int tiles_x, int tiles_y, int ntiles) {
+    // XCD-aware tile order: consecutive hardware blocks round-robin over the 8 XCDs,
+    // so give each XCD a contiguous range of tiles (shared halos stay in its L2)
+    const int b = blockIdx.x;
+    const int full = (ntiles / 8) * 8;
+    const int tile = (b < full) ? (b % 8) * (ntiles / 8) + b / 8 : b;
+    const int txi = tile % tiles_x, rem = tile / tiles_x, tyi = rem % tiles_y, tzi = rem / tiles_y;
+    x0 = 1 + txi * kTX;
+    y0 = 1 + tyi * kTY;
+    z0 = 1 + tzi * kTZ;
+    z1 = min(z0 + kTZ, g.n[2] + 1);
+    tx = threadIdx.x % kTX;
+    ty = threadIdx.x / kTX;
+    i = x0 + tx;
+    j = y0 + ty;
+    const int n0 = g.n[0], n1 = g.n[1];
+    inb = i <= n0 + 1 && j <= n1 + 1;
+    own = i <= n0 && j <= n1;
+    col = wrapc(i, 0, g) + wrapc(j, 1, g) * g.s[1];
+    const int t = threadIdx.x;
+    ring = t < 2 * (kTX + 2) + 2 * kTY;
+    sx = sy = hx = hy = hcol = 0;
+    hb = false;
+    if (ring) {
+      if (t < kTX + 2) {
+        sx = t;
+        sy = 0;
+      } else if (t < 2 * (kTX + 2)) {
+        sx = t - (kTX + 2);
+        sy = kTY + 1;
+      } else if (t < 2 * (kTX + 2) + kTY) {
+        sx = 0;
+        sy = 1 + t - 2 * (kTX + 2);
+      } else {
+        sx = kTX + 1;
+        sy = 1 + t - 2 * (kTX + 2) - kTY;
+      }
+      const int rx = x0 - 1 + sx, ry = y0 - 1 + sy;
+      hb = rx >= 0 && rx <= n0 + 1 && ry >= 0 && ry <= n1 + 1;
+      hx = wrapc(rx, 0, g);
+      hy = wrapc(ry, 1, g);
+      hcol = hx + hy * g.s[1];
+    }
+    opx = (g.per[0] && i == n0) ? -(n0 - 1) : 1;
+    opy = (g.per[1] && j == n1) ? -(n1 - 1) * g.s[1] : g.s[1];
+    const int ta[3] = {x0 - 2, y0 - 2, z0 - 2}, tb[3] = {x0 + kTX + 1, y0 + kTY + 1, z1 + 1};
+    fast = std_miss<3>(B, g, ta, tb);
+  }
+};
+
+// Loads run kPF planes ahead of the stencil (a register ring per thread): with
+// only two or three fields per cell the march is otherwise bound by load latency.
+constexpr int kPF = 4;
+
+// PCG pass A, tiled form (see k_pcg_a for the arithmetic).  With STOREQ = 0,
+// q = A e is only reduced into sigma, not stored: the tiled pass B recomputes it.
 template <typename T, int FINE, int STOREQ = 1>
 __global__ void __launch_bounds__(kTileThreads) k_pcg_a_tile(Grid3 g, Vec3<T> L, const T* iD, const T* r,
                                                              const T* eo, T* en, T* q, double* red, int k,
@@ -799,101 +913,92 @@ __global__ void __launch_bounds__(kTileThreads) k_pcg_a_tile(Grid3 g, Vec3<T> L,
   if (*flag) return;
   T beta, mean;
   if (!pcg_a_scalars<T, kTileThreads>(red, k, rn, flag, beta, mean)) return;
-  __shared__ T sE[kTY + 2][kTX + 2];
-  // XCD-aware tile order: consecutive hardware blocks round-robin over the 8 XCDs,
-  // so give each XCD a contiguous range of tiles (shared halos stay in its L2).
-  const int b = blockIdx.x;
-  const int full = (ntiles / 8) * 8;
-  const int tile = (b < full) ? (b % 8) * (ntiles / 8) + b / 8 : b;
-  const int txi = tile % tiles_x, rem = tile / tiles_x, tyi = rem % tiles_y, tzi = rem / tiles_y;
-  const int x0 = 1 + txi * kTX, y0 = 1 + tyi * kTY, z0 = 1 + tzi * kTZ;
-  const int z1 = min(z0 + kTZ, g.n[2] + 1);
-  const int tx = threadIdx.x % kTX, ty = threadIdx.x / kTX;
-  const int n0 = g.n[0], n1 = g.n[1], n2 = g.n[2];
-  const int s1 = g.s[1], s2 = g.s[2];
-  // own column
-  const int i = x0 + tx, j = y0 + ty;
-  const bool inb = i <= n0 + 1 && j <= n1 + 1;
-  const bool own = i <= n0 && j <= n1;
-  const int wi = wrapc(i, 0, g), wj = wrapc(j, 1, g);
-  const int col = wi + wj * s1;
-  // halo cell of this thread (148 ring cells)
-  const int t = threadIdx.x;
-  int hx = 0, hy = 0, sx = 0, sy = 0;
-  bool hb = false;
-  if (t < 2 * (kTX + 2) + 2 * kTY) {
-    if (t < kTX + 2) { sx = t; sy = 0; }
-    else if (t < 2 * (kTX + 2)) { sx = t - (kTX + 2); sy = kTY + 1; }
-    else if (t < 2 * (kTX + 2) + kTY) { sx = 0; sy = 1 + t - 2 * (kTX + 2); }
-    else { sx = kTX + 1; sy = 1 + t - 2 * (kTX + 2) - kTY; }
-    const int rx = x0 - 1 + sx, ry = y0 - 1 + sy;
-    hb = rx >= 0 && rx <= n0 + 1 && ry >= 0 && ry <= n1 + 1;
-    hx = wrapc(rx, 0, g);
-    hy = wrapc(ry, 1, g);
-  }
-  const int hcol = hx + hy * s1;
-  // tiles whose stencil (with the halo's own neighbours) misses the body box take
-  // L and iD in closed form: only r, e_old are read and e_new, q written
-  const int ta[3] = {x0 - 2, y0 - 2, z0 - 2}, tb[3] = {x0 + kTX + 1, y0 + kTY + 1, z1 + 1};
-  const bool fast = std_miss<3>(B, g, ta, tb);
-  auto diag = [&](int id, int ci, int cj, int ck) -> T { return fast ? iD_std<T, 3>(g, B, ci, cj, ck) : iD[id]; };
-  auto eps_at = [&](int id, int ci, int cj, int ck) -> T {
-    const T d = diag(id, ci, cj, ck);
-    return (k > 0) ? d * r[id] + beta * eo[id] : d * (r[id] - mean);
+  __shared__ T sE[2][kTY + 2][kTX + 2];
+  const TileGeo G(g, B, tiles_x, tiles_y, ntiles);
+  const StdDiag<T, 3> SD(B);
+  const bool fast = G.fast;
+  const int s2 = g.s[2];
+  const int wi = wrapc(G.i, 0, g), wj = wrapc(G.j, 1, g);
+  auto eps3 = [&](T d, T rv, T ev) -> T { return (k > 0) ? d * rv + beta * ev : d * (rv - mean); };
+  auto Lz = [&](int id, int z) -> T { return fast ? L_std<T>(g, B, 2, z) : L.c[2][id]; };
+  const T Lxp0 = L_std<T>(g, B, 0, G.i + 1), Lxc0 = L_std<T>(g, B, 0, G.i);
+  const T Lyp0 = L_std<T>(g, B, 1, G.j + 1), Lyc0 = L_std<T>(g, B, 1, G.j);
+  // register rings: own column planes z+1 .. z+kPF (slot = (plane - z0) mod kPF),
+  // ring cell planes z .. z+kPF-1
+  T od[kPF], orr[kPF], oe[kPF], ol[kPF], hd[kPF], hr[kPF], he[kPF];
+#pragma unroll
+  for (int i = 0; i < kPF; ++i) od[i] = orr[i] = oe[i] = ol[i] = hd[i] = hr[i] = he[i] = T(0);
+  auto own_load = [&](T& d, T& rv, T& ev, T& lv, int zz) {
+    if (G.inb && zz <= G.z1) {
+      const int zw = wrapc(zz, 2, g), id = G.col + zw * s2;
+      d = fast ? SD.at(g, wi, wj, zw) : iD[id];
+      rv = r[id];
+      ev = (k > 0) ? eo[id] : T(0);
+      lv = Lz(id, zw);
+    }
   };
-  // x/y neighbour offsets of the own column (periodic wrap)
-  const int opx = (g.per[0] && i == n0) ? -(n0 - 1) : 1;
-  const int opy = (g.per[1] && j == n1) ? -(n1 - 1) * s1 : s1;
-  // prologue: planes z0-1 and z0
-  T em = T(0), ec = T(0), rc = T(0), dc = T(0), L2c = T(0);
-  if (inb) {
-    const int zm = wrapc(z0 - 1, 2, g);
-    em = eps_at(col + zm * s2, wi, wj, zm);
-    const int id = col + z0 * s2;
-    dc = diag(id, wi, wj, z0);
-    rc = r[id];
-    ec = (k > 0) ? dc * rc + beta * eo[id] : dc * (rc - mean);
-    L2c = fast ? L_std<T>(g, B, 2, z0) : L.c[2][id];
+  auto ring_load = [&](T& d, T& rv, T& ev, int zz) {
+    if (G.ring && G.hb && zz < G.z1) {
+      const int id = G.hcol + zz * s2;
+      d = fast ? SD.at(g, G.hx, G.hy, zz) : iD[id];
+      rv = r[id];
+      ev = (k > 0) ? eo[id] : T(0);
+    }
+  };
+  T em = T(0), ec = T(0), dc = T(0), rc = T(0), L2c = T(0);
+  if (G.inb) {
+    const int zm = wrapc(G.z0 - 1, 2, g), idm = G.col + zm * s2, id0 = G.col + G.z0 * s2;
+    em = eps3(fast ? SD.at(g, wi, wj, zm) : iD[idm], r[idm], (k > 0) ? eo[idm] : T(0));
+    dc = fast ? SD.at(g, wi, wj, G.z0) : iD[id0];
+    rc = r[id0];
+    ec = eps3(dc, rc, (k > 0) ? eo[id0] : T(0));
+    L2c = Lz(id0, G.z0);
+  }
+#pragma unroll
+  for (int i = 0; i < kPF; ++i) {
+    own_load(od[(i + 1) % kPF], orr[(i + 1) % kPF], oe[(i + 1) % kPF], ol[(i + 1) % kPF], G.z0 + 1 + i);
+    ring_load(hd[i], hr[i], he[i], G.z0 + i);
   }
   double sig = 0.0, rho0 = 0.0;
-  for (int z = z0; z < z1; ++z) {
-    const int zp = wrapc(z + 1, 2, g);
-    T ep = T(0), dp = T(0), rp = T(0), L2p = T(0);
-    if (inb) {
-      const int id = col + zp * s2;
-      dp = diag(id, wi, wj, zp);
-      rp = r[id];
-      ep = (k > 0) ? dp * rp + beta * eo[id] : dp * (rp - mean);
-      L2p = fast ? L_std<T>(g, B, 2, zp) : L.c[2][id];
-    }
-    sE[ty + 1][tx + 1] = ec;
-    if (t < 2 * (kTX + 2) + 2 * kTY) sE[sy][sx] = hb ? eps_at(hcol + z * s2, hx, hy, z) : T(0);
-    __syncthreads();
-    if (own) {
-      const int id = col + z * s2;
-      T qq = T(0);
-      if (dc != T(0)) {
-        const T xm = sE[ty + 1][tx], xp = sE[ty + 1][tx + 2];
-        const T ym = sE[ty][tx + 1], yp = sE[ty + 2][tx + 1];
-        const T Lxp = fast ? L_std<T>(g, B, 0, i + 1) : L.c[0][id + opx];
-        const T Lxc = fast ? L_std<T>(g, B, 0, i) : L.c[0][id];
-        const T Lyp = fast ? L_std<T>(g, B, 1, j + 1) : L.c[1][id + opy];
-        const T Lyc = fast ? L_std<T>(g, B, 1, j) : L.c[1][id];
-        qq = qq + Lxp * (xp - ec) - Lxc * (ec - xm);
-        qq = qq + Lyp * (yp - ec) - Lyc * (ec - ym);
-        qq = qq + L2p * (ep - ec) - L2c * (ec - em);
-        if (k == 0) rho0 += double(rc - mean) * double(ec);
+  for (int zb = G.z0; zb < G.z1; zb += kPF) {
+#pragma unroll
+    for (int u = 0; u < kPF; ++u) {
+      const int z = zb + u;
+      if (z >= G.z1) break;
+      const int so = (u + 1) % kPF;
+      const T dp = od[so], rp = orr[so], L2p = ol[so];
+      const T ep = eps3(dp, rp, oe[so]);
+      own_load(od[so], orr[so], oe[so], ol[so], z + 1 + kPF);
+      const T hc = eps3(hd[u], hr[u], he[u]);
+      ring_load(hd[u], hr[u], he[u], z + kPF);
+      T(*P)[kTX + 2] = sE[z & 1];
+      P[G.ty + 1][G.tx + 1] = ec;
+      if (G.ring) P[G.sy][G.sx] = G.hb ? hc : T(0);
+      __syncthreads();
+      if (G.own) {
+        const int id = G.col + z * s2;
+        T qq = T(0);
+        if (dc != T(0)) {
+          const T xm = P[G.ty + 1][G.tx], xp = P[G.ty + 1][G.tx + 2];
+          const T ym = P[G.ty][G.tx + 1], yp = P[G.ty + 2][G.tx + 1];
+          const T Lxp = fast ? Lxp0 : L.c[0][id + G.opx], Lxc = fast ? Lxc0 : L.c[0][id];
+          const T Lyp = fast ? Lyp0 : L.c[1][id + G.opy], Lyc = fast ? Lyc0 : L.c[1][id];
+          qq = qq + Lxp * (xp - ec) - Lxc * (ec - xm);
+          qq = qq + Lyp * (yp - ec) - Lyc * (ec - ym);
+          qq = qq + L2p * (ep - ec) - L2c * (ec - em);
+          if (k == 0) rho0 += double(rc - mean) * double(ec);
+        }
+        en[id] = ec;
+        if (STOREQ) q[id] = qq;
+        sig += double(ec) * double(qq);
       }
-      en[id] = ec;
-      if (STOREQ) q[id] = qq;
-      sig += double(ec) * double(qq);
+      // the other LDS buffer is written next: no second barrier
+      em = ec;
+      ec = ep;
+      dc = dp;
+      rc = rp;
+      L2c = L2p;
     }
-    __syncthreads();
-    em = ec;
-    ec = ep;
-    dc = dp;
-    rc = rp;
-    L2c = L2p;
   }
   sig = block_sum<kTileThreads>(sig);
   if (threadIdx.x == 0) part_sig[blockIdx.x] = sig;
@@ -903,11 +1008,10 @@ __global__ void __launch_bounds__(kTileThreads) k_pcg_a_tile(Grid3 g, Vec3<T> L,
   }
 }
 
-// PCG pass B (sweep k), tiled z-marching form paired with pass A (STOREQ = 0):
-// q = A e is recomputed from e (LDS plane + registers, as in pass A) instead of
-// being stored and re-read; then x += alpha e, r -= alpha q on the interior, with
-// the same scalars, stopping rule, mean removal (sweep 0) and partials (rho_{k+1},
-// max|r|) as the flat pass B.
+// PCG pass B (sweep k), tiled form paired with pass A (STOREQ = 0): q = A e is
+// recomputed from e instead of being stored and re-read; then x += alpha e,
+// r -= alpha q on the interior, with the same scalars, stopping rule, mean removal
+// (sweep 0) and partials (rho_{k+1}, max|r|) as the flat pass B.
 template <typename T, int FINE>
 __global__ void __launch_bounds__(kTileThreads) k_pcg_b_tile(Grid3 g, Vec3<T> L, const T* iD, const T* e, T* x,
                                                              T* r, double* red, int k, RedN rn, double* part_rho_next,
@@ -926,84 +1030,91 @@ __global__ void __launch_bounds__(kTileThreads) k_pcg_b_tile(Grid3 g, Vec3<T> L,
     }
   }
   if (skip && !want_max && mean == T(0)) return;  // grid-uniform
-  __shared__ T sE[kTY + 2][kTX + 2];
-  const int b = blockIdx.x;
-  const int full = (ntiles / 8) * 8;
-  const int tile = (b < full) ? (b % 8) * (ntiles / 8) + b / 8 : b;
-  const int txi = tile % tiles_x, rem = tile / tiles_x, tyi = rem % tiles_y, tzi = rem / tiles_y;
-  const int x0 = 1 + txi * kTX, y0 = 1 + tyi * kTY, z0 = 1 + tzi * kTZ;
-  const int z1 = min(z0 + kTZ, g.n[2] + 1);
-  const int tx = threadIdx.x % kTX, ty = threadIdx.x / kTX;
-  const int n0 = g.n[0], n1 = g.n[1];
-  const int s1 = g.s[1], s2 = g.s[2];
-  const int i = x0 + tx, j = y0 + ty;
-  const bool inb = i <= n0 + 1 && j <= n1 + 1;
-  const bool own = i <= n0 && j <= n1;
-  const int wi = wrapc(i, 0, g), wj = wrapc(j, 1, g);
-  const int col = wi + wj * s1;
-  const int t = threadIdx.x;
-  int sx = 0, sy = 0, hcol = 0;
-  bool hb = false;
-  const bool ring = t < 2 * (kTX + 2) + 2 * kTY;
-  if (ring) {
-    if (t < kTX + 2) { sx = t; sy = 0; }
-    else if (t < 2 * (kTX + 2)) { sx = t - (kTX + 2); sy = kTY + 1; }
-    else if (t < 2 * (kTX + 2) + kTY) { sx = 0; sy = 1 + t - 2 * (kTX + 2); }
-    else { sx = kTX + 1; sy = 1 + t - 2 * (kTX + 2) - kTY; }
-    const int rx = x0 - 1 + sx, ry = y0 - 1 + sy;
-    hb = rx >= 0 && rx <= n0 + 1 && ry >= 0 && ry <= n1 + 1;
-    hcol = wrapc(rx, 0, g) + wrapc(ry, 1, g) * s1;
-  }
-  const int ta[3] = {x0 - 2, y0 - 2, z0 - 2}, tb[3] = {x0 + kTX + 1, y0 + kTY + 1, z1 + 1};
-  const bool fast = std_miss<3>(B, g, ta, tb);
-  const int opx = (g.per[0] && i == n0) ? -(n0 - 1) : 1;
-  const int opy = (g.per[1] && j == n1) ? -(n1 - 1) * s1 : s1;
+  __shared__ T sE[2][kTY + 2][kTX + 2];
+  const TileGeo G(g, B, tiles_x, tiles_y, ntiles);
+  const StdDiag<T, 3> SD(B);
+  const bool fast = G.fast;
+  const int s2 = g.s[2];
+  auto Lz = [&](int id, int z) -> T { return fast ? L_std<T>(g, B, 2, z) : L.c[2][id]; };
+  const T Lxp0 = L_std<T>(g, B, 0, G.i + 1), Lxc0 = L_std<T>(g, B, 0, G.i);
+  const T Lyp0 = L_std<T>(g, B, 1, G.j + 1), Lyc0 = L_std<T>(g, B, 1, G.j);
+  // rings: own e and L_z planes z+1 .. z+kPF; own x, r, iD planes z .. z+kPF-1;
+  // ring-cell e planes z .. z+kPF-1
+  T oe[kPF], ol[kPF], ox[kPF], orr[kPF], od[kPF], he[kPF];
+#pragma unroll
+  for (int i = 0; i < kPF; ++i) oe[i] = ol[i] = ox[i] = orr[i] = od[i] = he[i] = T(0);
+  auto e_load = [&](T& ev, T& lv, int zz) {
+    if (G.inb && zz <= G.z1) {
+      const int zw = wrapc(zz, 2, g), id = G.col + zw * s2;
+      ev = e[id];
+      lv = Lz(id, zw);
+    }
+  };
+  auto xr_load = [&](T& xv, T& rv, T& dv, int zz) {
+    if (G.own && zz < G.z1) {
+      const int id = G.col + zz * s2;
+      xv = x[id];
+      rv = r[id];
+      dv = fast ? SD.at(g, G.i, G.j, zz) : iD[id];
+    }
+  };
+  auto ring_load = [&](T& ev, int zz) {
+    if (G.ring && G.hb && zz < G.z1) ev = e[G.hcol + zz * s2];
+  };
   T em = T(0), ec = T(0), L2c = T(0);
-  if (inb) {
-    em = e[col + wrapc(z0 - 1, 2, g) * s2];
-    ec = e[col + z0 * s2];
-    L2c = fast ? L_std<T>(g, B, 2, z0) : L.c[2][col + z0 * s2];
+  if (G.inb) {
+    em = e[G.col + wrapc(G.z0 - 1, 2, g) * s2];
+    ec = e[G.col + G.z0 * s2];
+    L2c = Lz(G.col + G.z0 * s2, G.z0);
+  }
+#pragma unroll
+  for (int i = 0; i < kPF; ++i) {
+    e_load(oe[(i + 1) % kPF], ol[(i + 1) % kPF], G.z0 + 1 + i);
+    xr_load(ox[i], orr[i], od[i], G.z0 + i);
+    ring_load(he[i], G.z0 + i);
   }
   double rho = 0.0, mx = 0.0;
-  for (int z = z0; z < z1; ++z) {
-    const int zp = wrapc(z + 1, 2, g);
-    T ep = T(0), L2p = T(0);
-    if (inb) {
-      ep = e[col + zp * s2];
-      L2p = fast ? L_std<T>(g, B, 2, zp) : L.c[2][col + zp * s2];
-    }
-    sE[ty + 1][tx + 1] = ec;
-    if (ring) sE[sy][sx] = hb ? e[hcol + z * s2] : T(0);
-    __syncthreads();
-    if (own) {
-      const int id = col + z * s2;
-      const T dc = fast ? iD_std<T, 3>(g, B, i, j, z) : iD[id];
-      T rr = r[id];
-      if (mean != T(0) && dc != T(0)) rr = rr - mean;
-      if (!skip) {
-        T qq = T(0);
-        if (dc != T(0)) {
-          const T xm = sE[ty + 1][tx], xp = sE[ty + 1][tx + 2];
-          const T ym = sE[ty][tx + 1], yp = sE[ty + 2][tx + 1];
-          const T Lxp = fast ? L_std<T>(g, B, 0, i + 1) : L.c[0][id + opx];
-          const T Lxc = fast ? L_std<T>(g, B, 0, i) : L.c[0][id];
-          const T Lyp = fast ? L_std<T>(g, B, 1, j + 1) : L.c[1][id + opy];
-          const T Lyc = fast ? L_std<T>(g, B, 1, j) : L.c[1][id];
-          qq = qq + Lxp * (xp - ec) - Lxc * (ec - xm);
-          qq = qq + Lyp * (yp - ec) - Lyc * (ec - ym);
-          qq = qq + L2p * (ep - ec) - L2c * (ec - em);
+  for (int zb = G.z0; zb < G.z1; zb += kPF) {
+#pragma unroll
+    for (int u = 0; u < kPF; ++u) {
+      const int z = zb + u;
+      if (z >= G.z1) break;
+      const int so = (u + 1) % kPF;
+      const T ep = oe[so], L2p = ol[so];
+      e_load(oe[so], ol[so], z + 1 + kPF);
+      const T xc = ox[u], rcur = orr[u], dc = od[u], hc = he[u];
+      xr_load(ox[u], orr[u], od[u], z + kPF);
+      ring_load(he[u], z + kPF);
+      T(*P)[kTX + 2] = sE[z & 1];
+      P[G.ty + 1][G.tx + 1] = ec;
+      if (G.ring) P[G.sy][G.sx] = G.hb ? hc : T(0);
+      __syncthreads();
+      if (G.own) {
+        const int id = G.col + z * s2;
+        T rr = rcur;
+        if (mean != T(0) && dc != T(0)) rr = rr - mean;
+        if (!skip) {
+          T qq = T(0);
+          if (dc != T(0)) {
+            const T xm = P[G.ty + 1][G.tx], xp = P[G.ty + 1][G.tx + 2];
+            const T ym = P[G.ty][G.tx + 1], yp = P[G.ty + 2][G.tx + 1];
+            const T Lxp = fast ? Lxp0 : L.c[0][id + G.opx], Lxc = fast ? Lxc0 : L.c[0][id];
+            const T Lyp = fast ? Lyp0 : L.c[1][id + G.opy], Lyc = fast ? Lyc0 : L.c[1][id];
+            qq = qq + Lxp * (xp - ec) - Lxc * (ec - xm);
+            qq = qq + Lyp * (yp - ec) - Lyc * (ec - ym);
+            qq = qq + L2p * (ep - ec) - L2c * (ec - em);
+          }
+          x[id] = xc + alpha * ec;
+          rr = rr - alpha * qq;
         }
-        x[id] = x[id] + alpha * ec;
-        rr = rr - alpha * qq;
+        if (!skip || mean != T(0)) r[id] = rr;
+        rho += double(rr) * (double(dc) * double(rr));
+        mx = fmax(mx, fabs(double(rr)));
       }
-      if (!skip || mean != T(0)) r[id] = rr;
-      rho += double(rr) * (double(dc) * double(rr));
-      mx = fmax(mx, fabs(double(rr)));
+      em = ec;
+      ec = ep;
+      L2c = L2p;
     }
-    __syncthreads();
-    em = ec;
-    ec = ep;
-    L2c = L2p;
   }
   if (want_rho && !skip) {
     rho = block_sum<kTileThreads>(rho);
@@ -1049,6 +1160,7 @@ __global__ void __launch_bounds__(kBlock) k_pcg_b(int64_t nvec, const T* iD, con
   V* rv = reinterpret_cast<V*>(r);
   const int64_t stride = (int64_t)gridDim.x * kBlock;
   const int px = g.s[1], py = g.n[1] + 2;
+  const StdDiag<T, D> SD(B);
   // iD of the W cells of vector v in closed form; false if any of them is near the box
   auto std_vec = [&](int64_t v, V& out) -> bool {
     T* o = reinterpret_cast<T*>(&out);
@@ -1075,7 +1187,7 @@ __global__ void __launch_bounds__(kBlock) k_pcg_b(int64_t nvec, const T* iD, con
         }
       }
       if (!std_point<D>(B, g, I, 1)) return false;
-      o[w] = iD_std<T, D>(g, B, I[0], I[1], I[2]);
+      o[w] = SD.at(g, I[0], I[1], I[2]);
     }
     return true;
   };

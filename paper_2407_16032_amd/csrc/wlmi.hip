@@ -299,7 +299,7 @@ struct SimBase {
   virtual wl_status pg_forward(const void* x, const int64_t n[3], float* y) = 0;
   virtual wl_status pg_train(const void* x, const float* t, const unsigned char* m, const int64_t n[3], float* grad,
                              double* loss, int apply) = 0;
-  virtual wl_status pg_stats(double* loss, int64_t* steps, int64_t* snaps) = 0;
+  virtual wl_status pg_stats(double* loss, int64_t* steps, int64_t* snaps, int64_t* used, int64_t* tried) = 0;
   virtual wl_status body_update(const wl_body_desc* b) = 0;
   virtual wl_status body_box_of(int level, int lo[3], int hi[3]) = 0;
   virtual wl_status adj_reset() = 0;
@@ -355,7 +355,7 @@ struct Impl : SimBase {
   int pg_mode = 0, pg_iters = 1, pg_crops = 2, pg_hist = 0, ring_used = 0, ring_next = 0;
   double pg_lr = 1e-3;
   uint64_t pg_rng = 0;
-  int64_t pg_train_steps = 0, pg_snaps = 0, pg_adam_t = 0;
+  int64_t pg_train_steps = 0, pg_snaps = 0, pg_adam_t = 0, pg_used = 0, pg_tried = 0;
   bool pg_loss_pending = false;
   double pg_last_loss = NAN;
   T* p2 = nullptr;
@@ -841,10 +841,28 @@ struct Impl : SimBase {
     const T wdt = T(w * dt);
     const bool guided = pg_on && pg_mode >= 1 && pg_hist >= 2;
     if (guided) {
+      // multigrid judges the guess: it is used only if its initial residual is below
+      // that of the plain warm start x0 = p w dt
+      double res_plain = 0.0, res_guess = 0.0;
+      WL_TIMED(WL_K_DIVRES, (k_div_res<T, D><<<nb[0], kBlock, 0, stream>>>(g[0], v3(uu), nullptr, p, wdt, v3(L[0]),
+                                                                            iD[0], x[0], r[0], slot(kSlotRmax), red,
+                                                                            flags, sbox[0])));
+      slot_n[kSlotRmax] = nb[0];
+      wl_status s0 = read_scalar_max(kSlotRmax, &res_plain);
+      if (s0 != WL_OK) return s0;
       pg_guess(uu, w * dt);  // x[0] = learned guess
       WL_TIMED(WL_K_DIVRES, (k_div_res<T, D><<<nb[0], kBlock, 0, stream>>>(g[0], v3(uu), nullptr, nullptr, wdt,
                                                                             v3(L[0]), iD[0], x[0], r[0],
                                                                             slot(kSlotRmax), red, flags, sbox[0])));
+      if ((s0 = read_scalar_max(kSlotRmax, &res_guess)) != WL_OK) return s0;
+      ++pg_tried;
+      if (res_guess < res_plain) {
+        ++pg_used;
+      } else {
+        WL_TIMED(WL_K_DIVRES, (k_div_res<T, D><<<nb[0], kBlock, 0, stream>>>(g[0], v3(uu), nullptr, p, wdt,
+                                                                              v3(L[0]), iD[0], x[0], r[0],
+                                                                              slot(kSlotRmax), red, flags, sbox[0])));
+      }
     } else {
       WL_TIMED(WL_K_DIVRES, (k_div_res<T, D><<<nb[0], kBlock, 0, stream>>>(g[0], v3(uu), nullptr, p, wdt, v3(L[0]),
                                                                             iD[0], x[0], r[0], slot(kSlotRmax), red,
@@ -1044,13 +1062,15 @@ struct Impl : SimBase {
     return WL_OK;
   }
 
-  wl_status pg_stats(double* loss, int64_t* steps, int64_t* snaps) override {
+  wl_status pg_stats(double* loss, int64_t* steps, int64_t* snaps, int64_t* used, int64_t* tried) override {
     if (pg_require() != WL_OK) return WL_ERR_UNSUPPORTED;
     wl_status s = read_loss();
     if (s != WL_OK) return s;
     if (loss) *loss = pg_last_loss;
     if (steps) *steps = pg_train_steps;
     if (snaps) *snaps = pg_snaps;
+    if (used) *used = pg_used;
+    if (tried) *tried = pg_tried;
     return WL_OK;
   }
 
@@ -1663,9 +1683,10 @@ wl_status wl_adj_body_grad(wl_sim* sim, double* dJ_dradius, double* dJ_dspin) {
   return sim->impl->adj_body_grad(dJ_dradius, dJ_dspin);
 }
 
-wl_status wl_pg_stats(wl_sim* sim, double* last_loss, int64_t* train_steps, int64_t* snapshots) {
+wl_status wl_pg_stats(wl_sim* sim, double* last_loss, int64_t* train_steps, int64_t* snapshots,
+                      int64_t* guesses_used, int64_t* guesses_tried) {
   WL_SIM_CHECK(sim);
-  return sim->impl->pg_stats(last_loss, train_steps, snapshots);
+  return sim->impl->pg_stats(last_loss, train_steps, snapshots, guesses_used, guesses_tried);
 }
 
 const char* wl_last_error(void) { return g_err.c_str(); }

@@ -222,8 +222,12 @@ class Simulation:
         loss = C.c_double()
         steps = C.c_int64()
         snaps = C.c_int64()
-        L.check(self.lib.wl_pg_stats(self._h, C.byref(loss), C.byref(steps), C.byref(snaps)), "wl_pg_stats")
-        return {"loss": loss.value, "train_steps": steps.value, "snapshots": snaps.value}
+        used = C.c_int64()
+        tried = C.c_int64()
+        L.check(self.lib.wl_pg_stats(self._h, C.byref(loss), C.byref(steps), C.byref(snaps), C.byref(used),
+                                     C.byref(tried)), "wl_pg_stats")
+        return {"loss": loss.value, "train_steps": steps.value, "snapshots": snaps.value,
+                "guesses_used": used.value, "guesses_tried": tried.value}
 
     # ---------------------------------------------------- discrete adjoint
     def body_update(self, body):

@@ -20,7 +20,12 @@ def small_cases():
     tgv = wlsynth.tgv_3d(N=32)
     plate = wlsynth.plate_3d(scale=8)                                  # 96 x 48 x 48, moving
     rot = wlsynth.rotating_cylinder_2d(n=(96, 48), D=12.0, center=(30.0, 24.0), xi=1.0)
-    return {"circle2d": circle, "sphere3d": sphere, "tgv3d": tgv, "plate3d": plate, "rotcyl2d": rot}
+    # 64^3 = 2^18 cells: the fine level runs the tiled (z-marching) multigrid kernels,
+    # with tiles both inside and outside the body box (sphere) and periodic wraps (TGV)
+    sphere_t = wlsynth.sphere_3d(n=(64, 64, 64), D=16.0, center=(24.0, 32.0, 32.0))
+    tgv_t = wlsynth.tgv_3d(N=64)
+    return {"circle2d": circle, "sphere3d": sphere, "tgv3d": tgv, "plate3d": plate, "rotcyl2d": rot,
+            "sphere3d_tiled": sphere_t, "tgv3d_tiled": tgv_t}
 
 
 def make_pair(w, prec, tol, itmax=200, seed=0):

@@ -131,7 +131,8 @@ def test_poisson_solve(name):
     gpu.close()
 
 
-@pytest.mark.parametrize("name", ["circle2d", "sphere3d", "tgv3d", "plate3d", "rotcyl2d"])
+@pytest.mark.parametrize("name", ["circle2d", "sphere3d", "tgv3d", "plate3d", "rotcyl2d", "sphere3d_tiled",
+                                  "tgv3d_tiled"])
 def test_one_step_fp64(name):
     _say("step f64", name)
     w = CASES[name]
@@ -149,7 +150,7 @@ def test_one_step_fp64(name):
     gpu.close()
 
 
-@pytest.mark.parametrize("name", ["circle2d", "sphere3d", "tgv3d", "plate3d"])
+@pytest.mark.parametrize("name", ["circle2d", "sphere3d", "tgv3d", "plate3d", "sphere3d_tiled", "tgv3d_tiled"])
 def test_one_step_fp32(name):
     _say("step f32", name)
     w = CASES[name]

@@ -234,14 +234,17 @@ def random_field(shape, seed: int, comp: int = 0, amp: float = 1.0):
 PG_SHAPES = [(27, 3, 16), (16,), (27, 16, 16), (16,), (27, 16, 1), (1,)]
 
 
-def pg_init_weights(seed: int = 0) -> np.ndarray:
+def pg_init_weights(seed: int = 0, zero_output: bool = False) -> np.ndarray:
     """Kaiming-uniform weights (bound sqrt(6 / fan_in), fan_in = 27 c_in), zero biases,
-    flat float32 in the order W1 b1 W2 b2 W3 b3 with W[tap][c_in][c_out]."""
+    flat float32 in the order W1 b1 W2 b2 W3 b3 with W[tap][c_in][c_out].
+    zero_output: W3 = 0, so the untrained net predicts no change (the plain warm start)."""
     parts = []
     k = 0
-    for shp in PG_SHAPES:
+    for li, shp in enumerate(PG_SHAPES):
         n = int(np.prod(shp))
-        if len(shp) == 3:
+        if len(shp) == 3 and zero_output and li == len(PG_SHAPES) - 2:
+            parts.append(np.zeros(n, dtype=np.float32))
+        elif len(shp) == 3:
             bound = float(np.sqrt(6.0 / (27 * shp[1])))
             counter = np.arange(k, k + n, dtype=np.uint64)
             parts.append(((2.0 * uniform01(counter, seed + 12345) - 1.0) * bound).astype(np.float32))
