@@ -225,7 +225,7 @@ __device__ __forceinline__ void adj_phi(const Grid3& g, const Vec3<T>& u, const 
     iF = lin3<T, D>(g, F[0], F[1], F[2]);
     const T far = u.c[c][iF];
     const T cc = upw ? m1 : uc, dd = upw ? uc : m1;  // (far, c, d) of the upwind triple
-    const T q = (T(5) * cc + T(2) * dd - far) / T(6);
+    const T q = (T(5) * cc + T(2) * dd - far) * T(1.0 / 6.0);  // as in quick_lim (same branch)
     const T ex = cc + T(9) * (cc - far);
     const T inner = median3(cc, dd, ex);
     Q = median3(cc, q, inner);

@@ -134,7 +134,7 @@ __device__ __forceinline__ T median3(T a, T b, T c) {
 // kappa = 1/3 upwind-biased face value, clamped by the median-form limiter.
 template <typename T>
 __device__ __forceinline__ T quick_lim(T far, T c, T d) {
-  const T q = (T(5) * c + T(2) * d - far) / T(6);
+  const T q = (T(5) * c + T(2) * d - far) * T(1.0 / 6.0);  // a product: the divide is a long sequence
   return median3(c, q, median3(c, d, c + T(9) * (c - far)));
 }
 

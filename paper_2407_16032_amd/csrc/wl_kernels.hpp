@@ -698,6 +698,87 @@ __global__ void __launch_bounds__(kBlock) k_prolong(Grid3 f, Grid3 c, const T* x
 
 // Prolongation + correction, tiled z-marching form for large 3-D levels (same tile
 // order as the tiled PCG pass A): e = x_c[parent]; x += e; r -= A e; mean partials.
+// Like the PCG marches: branch-free loads issued two planes ahead, one marching body
+// per coefficient mode.
+template <typename T, bool FAST>
+__device__ __forceinline__ void prolong_march(const Grid3& f, const Grid3& c, const T* __restrict__ xc,
+                                              const Vec3<T>& L, const T* __restrict__ iD, T* __restrict__ xf,
+                                              T* __restrict__ rf, const StdBox& B, int i, int j, int z0, int z1,
+                                              double& sr, double& cnt) {
+  const StdDiag<T, 3> SD(B);
+  const int s1 = f.s[1], s2 = f.s[2], cs1 = c.s[1], cs2 = c.s[2];
+  const int col = i + j * s1;
+  const int pi = (i + 1) >> 1, pj = (j + 1) >> 1;
+  const int pxp = (wrapc(i + 1, 0, f) + 1) >> 1, pxm = (wrapc(i - 1, 0, f) + 1) >> 1;
+  const int pyp = (wrapc(j + 1, 1, f) + 1) >> 1, pym = (wrapc(j - 1, 1, f) + 1) >> 1;
+  const int cc = pi + pj * cs1, cxp = pxp + pj * cs1, cxm = pxm + pj * cs1, cyp = pi + pyp * cs1,
+            cym = pi + pym * cs1;
+  const int opx = (f.per[0] && i == f.n[0]) ? -(f.n[0] - 1) : 1;
+  const int opy = (f.per[1] && j == f.n[1]) ? -(f.n[1] - 1) * s1 : s1;
+  const T Lxp0 = L_std<T>(f, B, 0, i + 1), Lxc0 = L_std<T>(f, B, 0, i);
+  const T Lyp0 = L_std<T>(f, B, 1, j + 1), Lyc0 = L_std<T>(f, B, 1, j);
+  struct Raw {
+    T x, r, d, e, exp, exm, eyp, eym, ezp, ezm, lxp, lxc, lyp, lyc, lzp, lzc;
+  };
+  auto load = [&](int zz) -> Raw {
+    const int z = min(zz, f.n[2]);  // planes past the tile are clamped (not used)
+    const int id = col + z * s2;
+    const int zp = wrapc(z + 1, 2, f), zm = wrapc(z - 1, 2, f);
+    const int pz = ((z + 1) >> 1) * cs2, pzp = ((zp + 1) >> 1) * cs2, pzm = ((zm + 1) >> 1) * cs2;
+    Raw v;
+    v.x = xf[id];
+    v.r = rf[id];
+    v.e = xc[cc + pz];
+    v.exp = xc[cxp + pz];
+    v.exm = xc[cxm + pz];
+    v.eyp = xc[cyp + pz];
+    v.eym = xc[cym + pz];
+    v.ezp = xc[cc + pzp];
+    v.ezm = xc[cc + pzm];
+    if (FAST) {
+      v.d = SD.at(f, i, j, z);
+      v.lxp = Lxp0;
+      v.lxc = Lxc0;
+      v.lyp = Lyp0;
+      v.lyc = Lyc0;
+      v.lzp = L_std<T>(f, B, 2, zp);
+      v.lzc = L_std<T>(f, B, 2, z);
+    } else {
+      v.d = iD[id];
+      v.lxp = L.c[0][id + opx];
+      v.lxc = L.c[0][id];
+      v.lyp = L.c[1][id + opy];
+      v.lyc = L.c[1][id];
+      v.lzp = L.c[2][col + zp * s2];
+      v.lzc = L.c[2][id];
+    }
+    return v;
+  };
+  auto plane = [&](int z, const Raw& v, Raw& nxt) {
+    nxt = load(z + 2);
+    const int id = col + z * s2;
+    xf[id] = v.x + v.e;
+    if (v.d != T(0)) {
+      T Ae = T(0);
+      Ae = Ae + v.lxp * (v.exp - v.e) - v.lxc * (v.e - v.exm);
+      Ae = Ae + v.lyp * (v.eyp - v.e) - v.lyc * (v.e - v.eym);
+      Ae = Ae + v.lzp * (v.ezp - v.e) - v.lzc * (v.e - v.ezm);
+      const T rr = v.r - Ae;
+      rf[id] = rr;
+      sr += double(rr);
+      cnt += 1.0;
+    }
+  };
+  Raw A = load(z0), Bn = load(z0 + 1), C;
+  for (int z = z0; z < z1; z += 3) {
+    plane(z, A, C);
+    if (z + 1 >= z1) break;
+    plane(z + 1, Bn, A);
+    if (z + 2 >= z1) break;
+    plane(z + 2, C, Bn);
+  }
+}
+
 template <typename T>
 __global__ void __launch_bounds__(kTileThreads) k_prolong_tile(Grid3 f, Grid3 c, const T* xc, Vec3<T> L, const T* iD,
                                                       T* xf, T* rf, double* red, int* flag, int tiles_x,
@@ -716,40 +797,10 @@ __global__ void __launch_bounds__(kTileThreads) k_prolong_tile(Grid3 f, Grid3 c,
   const bool fast = std_miss<3>(B, f, ta, tb);  // L and iD in closed form
   double sr = 0.0, cnt = 0.0;
   if (own) {
-    const int s1 = f.s[1], s2 = f.s[2], cs1 = c.s[1], cs2 = c.s[2];
-    const int col = i + j * s1;
-    const int pi = (i + 1) >> 1, pj = (j + 1) >> 1;
-    const int pxp = (wrapc(i + 1, 0, f) + 1) >> 1, pxm = (wrapc(i - 1, 0, f) + 1) >> 1;
-    const int pyp = (wrapc(j + 1, 1, f) + 1) >> 1, pym = (wrapc(j - 1, 1, f) + 1) >> 1;
-    const int cc = pi + pj * cs1, cxp = pxp + pj * cs1, cxm = pxm + pj * cs1, cyp = pi + pyp * cs1,
-              cym = pi + pym * cs1;
-    const int opx = (f.per[0] && i == f.n[0]) ? -(f.n[0] - 1) : 1;
-    const int opy = (f.per[1] && j == f.n[1]) ? -(f.n[1] - 1) * s1 : s1;
-    const T Lxp = fast ? L_std<T>(f, B, 0, i + 1) : T(0), Lxc = fast ? L_std<T>(f, B, 0, i) : T(0);
-    const T Lyp = fast ? L_std<T>(f, B, 1, j + 1) : T(0), Lyc = fast ? L_std<T>(f, B, 1, j) : T(0);
-    T L2c = fast ? L_std<T>(f, B, 2, z0) : L.c[2][col + z0 * s2];
-    for (int z = z0; z < z1; ++z) {
-      const int id = col + z * s2;
-      const int zp = wrapc(z + 1, 2, f), zm = wrapc(z - 1, 2, f);
-      const int pz = ((z + 1) >> 1) * cs2, pzp = ((zp + 1) >> 1) * cs2, pzm = ((zm + 1) >> 1) * cs2;
-      const T L2p = fast ? L_std<T>(f, B, 2, zp) : L.c[2][col + zp * s2];
-      const T ec = xc[cc + pz];
-      xf[id] = xf[id] + ec;
-      const T di = fast ? iD_std<T, 3>(f, B, i, j, z) : iD[id];
-      if (di != T(0)) {
-        T Ae = T(0);
-        const T lxp = fast ? Lxp : L.c[0][id + opx], lxc = fast ? Lxc : L.c[0][id];
-        const T lyp = fast ? Lyp : L.c[1][id + opy], lyc = fast ? Lyc : L.c[1][id];
-        Ae = Ae + lxp * (xc[cxp + pz] - ec) - lxc * (ec - xc[cxm + pz]);
-        Ae = Ae + lyp * (xc[cyp + pz] - ec) - lyc * (ec - xc[cym + pz]);
-        Ae = Ae + L2p * (xc[cc + pzp] - ec) - L2c * (ec - xc[cc + pzm]);
-        const T rr = rf[id] - Ae;
-        rf[id] = rr;
-        sr += double(rr);
-        cnt += 1.0;
-      }
-      L2c = L2p;
-    }
+    if (fast)
+      prolong_march<T, true>(f, c, xc, L, iD, xf, rf, B, i, j, z0, z1, sr, cnt);
+    else
+      prolong_march<T, false>(f, c, xc, L, iD, xf, rf, B, i, j, z0, z1, sr, cnt);
   }
   sr = block_sum<kTileThreads>(sr);
   cnt = block_sum<kTileThreads>(cnt);
@@ -899,9 +950,103 @@ struct TileGeo {
   }
 };
 
-// Loads run kPF planes ahead of the stencil (a register ring per thread): with
-// only two or three fields per cell the march is otherwise bound by load latency.
-constexpr int kPF = 4;
+// The march loads every plane branch-free from clamped (always valid) addresses
+// and selects afterwards, with one marching body per coefficient mode (closed
+// form or loaded): loads behind data-dependent branches would each be waited for
+// at the branch's join, which serialises the march on memory latency.  Loads run
+// two planes ahead of their use.
+__device__ __forceinline__ int clamp_plane(const Grid3& g, int z) {
+  return wrapc(min(max(z, 0), g.n[2] + 1), 2, g);
+}
+
+template <typename T, int STOREQ, bool FAST>
+__device__ __forceinline__ void pcg_a_march(const Grid3& g, const Vec3<T>& L, const T* __restrict__ iD,
+                                            const T* __restrict__ r, const T* __restrict__ eo, T* __restrict__ en,
+                                            T* __restrict__ q, int k, T beta, T mean, const TileGeo& G,
+                                            const StdBox& B, T (*sE)[kTY + 2][kTX + 2], double& sig,
+                                            double& rho0) {
+  const StdDiag<T, 3> SD(B);
+  const int s1 = g.s[1], s2 = g.s[2];
+  // clamped columns: threads outside the padded grid read a valid column, unused
+  const int ci = min(G.i, g.n[0] + 1), cj = min(G.j, g.n[1] + 1);
+  const int wi = wrapc(ci, 0, g), wj = wrapc(cj, 1, g);
+  const int col = wi + wj * s1;
+  const int hcol = G.hb ? G.hcol : col;
+  const bool use_ring = G.ring && G.hb;
+  auto eps3 = [&](T d, T rv, T ev) -> T { return (k > 0) ? d * rv + beta * ev : d * (rv - mean); };
+  // raw loads of one plane; e is formed only when the plane is used, so a load is
+  // waited for two iterations after it was issued
+  struct Raw {
+    T d, r, e, l;
+  };
+  auto own = [&](int zz) -> Raw {
+    const int zw = clamp_plane(g, zz), id = col + zw * s2;
+    Raw v;
+    v.r = r[id];
+    v.e = eo[id];
+    v.d = FAST ? SD.at(g, wi, wj, zw) : iD[id];
+    v.l = FAST ? L_std<T>(g, B, 2, zw) : L.c[2][id];
+    return v;
+  };
+  auto ring = [&](int zz) -> Raw {
+    const int zw = clamp_plane(g, zz), id = hcol + zw * s2;
+    Raw v;
+    v.r = r[id];
+    v.e = eo[id];
+    v.d = FAST ? SD.at(g, G.hx, G.hy, zw) : iD[id];
+    v.l = T(0);
+    return v;
+  };
+  const T Lxp0 = L_std<T>(g, B, 0, G.i + 1), Lxc0 = L_std<T>(g, B, 0, G.i);
+  const T Lyp0 = L_std<T>(g, B, 1, G.j + 1), Lyc0 = L_std<T>(g, B, 1, G.j);
+  const Raw am = own(G.z0 - 1), a0 = own(G.z0);
+  T em = eps3(am.d, am.r, am.e), ec = eps3(a0.d, a0.r, a0.e), dc = a0.d, rc = a0.r, L2c = a0.l;
+  // one plane: consumes own plane z+1 (ap) and ring plane z (hr), issues the loads
+  // of own plane z+3 and ring plane z+2 (used two planes later)
+  auto plane = [&](int z, const Raw& ap, const Raw& hr, Raw& a_new, Raw& h_new) {
+    a_new = own(z + 3);
+    h_new = ring(z + 2);
+    const T ep = eps3(ap.d, ap.r, ap.e), L2p = ap.l;
+    T(*P)[kTX + 2] = sE[z & 1];
+    P[G.ty + 1][G.tx + 1] = ec;
+    if (G.ring) P[G.sy][G.sx] = use_ring ? eps3(hr.d, hr.r, hr.e) : T(0);
+    __syncthreads();
+    if (G.own) {
+      const int id = col + z * s2;
+      T qq = T(0);
+      if (dc != T(0)) {
+        const T xm = P[G.ty + 1][G.tx], xp = P[G.ty + 1][G.tx + 2];
+        const T ym = P[G.ty][G.tx + 1], yp = P[G.ty + 2][G.tx + 1];
+        const T Lxp = FAST ? Lxp0 : L.c[0][id + G.opx], Lxc = FAST ? Lxc0 : L.c[0][id];
+        const T Lyp = FAST ? Lyp0 : L.c[1][id + G.opy], Lyc = FAST ? Lyc0 : L.c[1][id];
+        qq = qq + Lxp * (xp - ec) - Lxc * (ec - xm);
+        qq = qq + Lyp * (yp - ec) - Lyc * (ec - ym);
+        qq = qq + L2p * (ep - ec) - L2c * (ec - em);
+        if (k == 0) rho0 += double(rc - mean) * double(ec);
+      }
+      en[id] = ec;
+      if (STOREQ) q[id] = qq;
+      sig += double(ec) * double(qq);
+    }
+    // the other LDS buffer is written next: no second barrier
+    em = ec;
+    ec = ep;
+    dc = ap.d;
+    rc = ap.r;
+    L2c = L2p;
+  };
+  // three planes per trip, so the register slots are renamed rather than copied
+  // (a copy of a register whose load is in flight would wait for it)
+  Raw A = own(G.z0 + 1), Bn = own(G.z0 + 2), C;
+  Raw HA = ring(G.z0), HB = ring(G.z0 + 1), HC;
+  for (int z = G.z0; z < G.z1; z += 3) {
+    plane(z, A, HA, C, HC);
+    if (z + 1 >= G.z1) break;
+    plane(z + 1, Bn, HB, A, HA);
+    if (z + 2 >= G.z1) break;
+    plane(z + 2, C, HC, Bn, HB);
+  }
+}
 
 // PCG pass A, tiled form (see k_pcg_a for the arithmetic).  With STOREQ = 0,
 // q = A e is only reduced into sigma, not stored: the tiled pass B recomputes it.
@@ -915,96 +1060,92 @@ __global__ void __launch_bounds__(kTileThreads) k_pcg_a_tile(Grid3 g, Vec3<T> L,
   if (!pcg_a_scalars<T, kTileThreads>(red, k, rn, flag, beta, mean)) return;
   __shared__ T sE[2][kTY + 2][kTX + 2];
   const TileGeo G(g, B, tiles_x, tiles_y, ntiles);
-  const StdDiag<T, 3> SD(B);
-  const bool fast = G.fast;
-  const int s2 = g.s[2];
-  const int wi = wrapc(G.i, 0, g), wj = wrapc(G.j, 1, g);
-  auto eps3 = [&](T d, T rv, T ev) -> T { return (k > 0) ? d * rv + beta * ev : d * (rv - mean); };
-  auto Lz = [&](int id, int z) -> T { return fast ? L_std<T>(g, B, 2, z) : L.c[2][id]; };
-  const T Lxp0 = L_std<T>(g, B, 0, G.i + 1), Lxc0 = L_std<T>(g, B, 0, G.i);
-  const T Lyp0 = L_std<T>(g, B, 1, G.j + 1), Lyc0 = L_std<T>(g, B, 1, G.j);
-  // register rings: own column planes z+1 .. z+kPF (slot = (plane - z0) mod kPF),
-  // ring cell planes z .. z+kPF-1
-  T od[kPF], orr[kPF], oe[kPF], ol[kPF], hd[kPF], hr[kPF], he[kPF];
-#pragma unroll
-  for (int i = 0; i < kPF; ++i) od[i] = orr[i] = oe[i] = ol[i] = hd[i] = hr[i] = he[i] = T(0);
-  auto own_load = [&](T& d, T& rv, T& ev, T& lv, int zz) {
-    if (G.inb && zz <= G.z1) {
-      const int zw = wrapc(zz, 2, g), id = G.col + zw * s2;
-      d = fast ? SD.at(g, wi, wj, zw) : iD[id];
-      rv = r[id];
-      ev = (k > 0) ? eo[id] : T(0);
-      lv = Lz(id, zw);
-    }
-  };
-  auto ring_load = [&](T& d, T& rv, T& ev, int zz) {
-    if (G.ring && G.hb && zz < G.z1) {
-      const int id = G.hcol + zz * s2;
-      d = fast ? SD.at(g, G.hx, G.hy, zz) : iD[id];
-      rv = r[id];
-      ev = (k > 0) ? eo[id] : T(0);
-    }
-  };
-  T em = T(0), ec = T(0), dc = T(0), rc = T(0), L2c = T(0);
-  if (G.inb) {
-    const int zm = wrapc(G.z0 - 1, 2, g), idm = G.col + zm * s2, id0 = G.col + G.z0 * s2;
-    em = eps3(fast ? SD.at(g, wi, wj, zm) : iD[idm], r[idm], (k > 0) ? eo[idm] : T(0));
-    dc = fast ? SD.at(g, wi, wj, G.z0) : iD[id0];
-    rc = r[id0];
-    ec = eps3(dc, rc, (k > 0) ? eo[id0] : T(0));
-    L2c = Lz(id0, G.z0);
-  }
-#pragma unroll
-  for (int i = 0; i < kPF; ++i) {
-    own_load(od[(i + 1) % kPF], orr[(i + 1) % kPF], oe[(i + 1) % kPF], ol[(i + 1) % kPF], G.z0 + 1 + i);
-    ring_load(hd[i], hr[i], he[i], G.z0 + i);
-  }
   double sig = 0.0, rho0 = 0.0;
-  for (int zb = G.z0; zb < G.z1; zb += kPF) {
-#pragma unroll
-    for (int u = 0; u < kPF; ++u) {
-      const int z = zb + u;
-      if (z >= G.z1) break;
-      const int so = (u + 1) % kPF;
-      const T dp = od[so], rp = orr[so], L2p = ol[so];
-      const T ep = eps3(dp, rp, oe[so]);
-      own_load(od[so], orr[so], oe[so], ol[so], z + 1 + kPF);
-      const T hc = eps3(hd[u], hr[u], he[u]);
-      ring_load(hd[u], hr[u], he[u], z + kPF);
-      T(*P)[kTX + 2] = sE[z & 1];
-      P[G.ty + 1][G.tx + 1] = ec;
-      if (G.ring) P[G.sy][G.sx] = G.hb ? hc : T(0);
-      __syncthreads();
-      if (G.own) {
-        const int id = G.col + z * s2;
-        T qq = T(0);
-        if (dc != T(0)) {
-          const T xm = P[G.ty + 1][G.tx], xp = P[G.ty + 1][G.tx + 2];
-          const T ym = P[G.ty][G.tx + 1], yp = P[G.ty + 2][G.tx + 1];
-          const T Lxp = fast ? Lxp0 : L.c[0][id + G.opx], Lxc = fast ? Lxc0 : L.c[0][id];
-          const T Lyp = fast ? Lyp0 : L.c[1][id + G.opy], Lyc = fast ? Lyc0 : L.c[1][id];
-          qq = qq + Lxp * (xp - ec) - Lxc * (ec - xm);
-          qq = qq + Lyp * (yp - ec) - Lyc * (ec - ym);
-          qq = qq + L2p * (ep - ec) - L2c * (ec - em);
-          if (k == 0) rho0 += double(rc - mean) * double(ec);
-        }
-        en[id] = ec;
-        if (STOREQ) q[id] = qq;
-        sig += double(ec) * double(qq);
-      }
-      // the other LDS buffer is written next: no second barrier
-      em = ec;
-      ec = ep;
-      dc = dp;
-      rc = rp;
-      L2c = L2p;
-    }
-  }
+  if (G.fast)
+    pcg_a_march<T, STOREQ, true>(g, L, iD, r, eo, en, q, k, beta, mean, G, B, sE, sig, rho0);
+  else
+    pcg_a_march<T, STOREQ, false>(g, L, iD, r, eo, en, q, k, beta, mean, G, B, sE, sig, rho0);
   sig = block_sum<kTileThreads>(sig);
   if (threadIdx.x == 0) part_sig[blockIdx.x] = sig;
   if (k == 0) {
     rho0 = block_sum<kTileThreads>(rho0);
     if (threadIdx.x == 0) red[(size_t)kSlotRho0 * kMaxBlocks + blockIdx.x] = rho0;
+  }
+}
+
+// PCG pass B march (see k_pcg_b_tile)
+template <typename T, bool FAST>
+__device__ __forceinline__ void pcg_b_march(const Grid3& g, const Vec3<T>& L, const T* __restrict__ iD,
+                                            const T* __restrict__ e, T* __restrict__ x, T* __restrict__ r, T alpha,
+                                            T mean, bool skip, const TileGeo& G, const StdBox& B,
+                                            T (*sE)[kTY + 2][kTX + 2], double& rho, double& mx) {
+  const StdDiag<T, 3> SD(B);
+  const int s1 = g.s[1], s2 = g.s[2];
+  const int ci = min(G.i, g.n[0] + 1), cj = min(G.j, g.n[1] + 1);
+  const int wi = wrapc(ci, 0, g), wj = wrapc(cj, 1, g);
+  const int col = wi + wj * s1;
+  const int hcol = G.hb ? G.hcol : col;
+  const bool use_ring = G.ring && G.hb;
+  // own column: e and L_z, x, r, iD of a plane (raw: used two iterations later)
+  struct Raw {
+    T e, l, x, r, d;
+  };
+  auto own = [&](int zz) -> Raw {
+    const int zw = clamp_plane(g, zz), id = col + zw * s2;
+    Raw v;
+    v.e = e[id];
+    v.l = FAST ? L_std<T>(g, B, 2, zw) : L.c[2][id];
+    v.x = x[id];
+    v.r = r[id];
+    v.d = FAST ? SD.at(g, wi, wj, zw) : iD[id];
+    return v;
+  };
+  auto ring = [&](int zz) -> T { return e[hcol + clamp_plane(g, zz) * s2]; };
+  const T Lxp0 = L_std<T>(g, B, 0, G.i + 1), Lxc0 = L_std<T>(g, B, 0, G.i);
+  const T Lyp0 = L_std<T>(g, B, 1, G.j + 1), Lyc0 = L_std<T>(g, B, 1, G.j);
+  T em = own(G.z0 - 1).e;
+  // one plane: consumes own planes z (cur) and z+1 (nxt) and ring plane z (hr),
+  // issues the loads of own plane z+2 and ring plane z+2
+  auto plane = [&](int z, const Raw& cur, const Raw& nxt, const T& hr, Raw& a_new, T& h_new) {
+    a_new = own(z + 2);
+    h_new = ring(z + 2);
+    const T ec = cur.e, ep = nxt.e, L2c = cur.l, L2p = nxt.l, dc = cur.d;
+    T(*P)[kTX + 2] = sE[z & 1];
+    P[G.ty + 1][G.tx + 1] = ec;
+    if (G.ring) P[G.sy][G.sx] = use_ring ? hr : T(0);
+    __syncthreads();
+    if (G.own) {
+      const int id = col + z * s2;
+      T rr = cur.r;
+      if (mean != T(0) && dc != T(0)) rr = rr - mean;
+      if (!skip) {
+        T qq = T(0);
+        if (dc != T(0)) {
+          const T xm = P[G.ty + 1][G.tx], xp = P[G.ty + 1][G.tx + 2];
+          const T ym = P[G.ty][G.tx + 1], yp = P[G.ty + 2][G.tx + 1];
+          const T Lxp = FAST ? Lxp0 : L.c[0][id + G.opx], Lxc = FAST ? Lxc0 : L.c[0][id];
+          const T Lyp = FAST ? Lyp0 : L.c[1][id + G.opy], Lyc = FAST ? Lyc0 : L.c[1][id];
+          qq = qq + Lxp * (xp - ec) - Lxc * (ec - xm);
+          qq = qq + Lyp * (yp - ec) - Lyc * (ec - ym);
+          qq = qq + L2p * (ep - ec) - L2c * (ec - em);
+        }
+        x[id] = cur.x + alpha * ec;
+        rr = rr - alpha * qq;
+      }
+      if (!skip || mean != T(0)) r[id] = rr;
+      rho += double(rr) * (double(dc) * double(rr));
+      mx = fmax(mx, fabs(double(rr)));
+    }
+    em = ec;
+  };
+  Raw A = own(G.z0), Bn = own(G.z0 + 1), C;
+  T HA = ring(G.z0), HB = ring(G.z0 + 1), HC;
+  for (int z = G.z0; z < G.z1; z += 3) {
+    plane(z, A, Bn, HA, C, HC);
+    if (z + 1 >= G.z1) break;
+    plane(z + 1, Bn, C, HB, A, HA);
+    if (z + 2 >= G.z1) break;
+    plane(z + 2, C, A, HC, Bn, HB);
   }
 }
 
@@ -1032,90 +1173,11 @@ __global__ void __launch_bounds__(kTileThreads) k_pcg_b_tile(Grid3 g, Vec3<T> L,
   if (skip && !want_max && mean == T(0)) return;  // grid-uniform
   __shared__ T sE[2][kTY + 2][kTX + 2];
   const TileGeo G(g, B, tiles_x, tiles_y, ntiles);
-  const StdDiag<T, 3> SD(B);
-  const bool fast = G.fast;
-  const int s2 = g.s[2];
-  auto Lz = [&](int id, int z) -> T { return fast ? L_std<T>(g, B, 2, z) : L.c[2][id]; };
-  const T Lxp0 = L_std<T>(g, B, 0, G.i + 1), Lxc0 = L_std<T>(g, B, 0, G.i);
-  const T Lyp0 = L_std<T>(g, B, 1, G.j + 1), Lyc0 = L_std<T>(g, B, 1, G.j);
-  // rings: own e and L_z planes z+1 .. z+kPF; own x, r, iD planes z .. z+kPF-1;
-  // ring-cell e planes z .. z+kPF-1
-  T oe[kPF], ol[kPF], ox[kPF], orr[kPF], od[kPF], he[kPF];
-#pragma unroll
-  for (int i = 0; i < kPF; ++i) oe[i] = ol[i] = ox[i] = orr[i] = od[i] = he[i] = T(0);
-  auto e_load = [&](T& ev, T& lv, int zz) {
-    if (G.inb && zz <= G.z1) {
-      const int zw = wrapc(zz, 2, g), id = G.col + zw * s2;
-      ev = e[id];
-      lv = Lz(id, zw);
-    }
-  };
-  auto xr_load = [&](T& xv, T& rv, T& dv, int zz) {
-    if (G.own && zz < G.z1) {
-      const int id = G.col + zz * s2;
-      xv = x[id];
-      rv = r[id];
-      dv = fast ? SD.at(g, G.i, G.j, zz) : iD[id];
-    }
-  };
-  auto ring_load = [&](T& ev, int zz) {
-    if (G.ring && G.hb && zz < G.z1) ev = e[G.hcol + zz * s2];
-  };
-  T em = T(0), ec = T(0), L2c = T(0);
-  if (G.inb) {
-    em = e[G.col + wrapc(G.z0 - 1, 2, g) * s2];
-    ec = e[G.col + G.z0 * s2];
-    L2c = Lz(G.col + G.z0 * s2, G.z0);
-  }
-#pragma unroll
-  for (int i = 0; i < kPF; ++i) {
-    e_load(oe[(i + 1) % kPF], ol[(i + 1) % kPF], G.z0 + 1 + i);
-    xr_load(ox[i], orr[i], od[i], G.z0 + i);
-    ring_load(he[i], G.z0 + i);
-  }
   double rho = 0.0, mx = 0.0;
-  for (int zb = G.z0; zb < G.z1; zb += kPF) {
-#pragma unroll
-    for (int u = 0; u < kPF; ++u) {
-      const int z = zb + u;
-      if (z >= G.z1) break;
-      const int so = (u + 1) % kPF;
-      const T ep = oe[so], L2p = ol[so];
-      e_load(oe[so], ol[so], z + 1 + kPF);
-      const T xc = ox[u], rcur = orr[u], dc = od[u], hc = he[u];
-      xr_load(ox[u], orr[u], od[u], z + kPF);
-      ring_load(he[u], z + kPF);
-      T(*P)[kTX + 2] = sE[z & 1];
-      P[G.ty + 1][G.tx + 1] = ec;
-      if (G.ring) P[G.sy][G.sx] = G.hb ? hc : T(0);
-      __syncthreads();
-      if (G.own) {
-        const int id = G.col + z * s2;
-        T rr = rcur;
-        if (mean != T(0) && dc != T(0)) rr = rr - mean;
-        if (!skip) {
-          T qq = T(0);
-          if (dc != T(0)) {
-            const T xm = P[G.ty + 1][G.tx], xp = P[G.ty + 1][G.tx + 2];
-            const T ym = P[G.ty][G.tx + 1], yp = P[G.ty + 2][G.tx + 1];
-            const T Lxp = fast ? Lxp0 : L.c[0][id + G.opx], Lxc = fast ? Lxc0 : L.c[0][id];
-            const T Lyp = fast ? Lyp0 : L.c[1][id + G.opy], Lyc = fast ? Lyc0 : L.c[1][id];
-            qq = qq + Lxp * (xp - ec) - Lxc * (ec - xm);
-            qq = qq + Lyp * (yp - ec) - Lyc * (ec - ym);
-            qq = qq + L2p * (ep - ec) - L2c * (ec - em);
-          }
-          x[id] = xc + alpha * ec;
-          rr = rr - alpha * qq;
-        }
-        if (!skip || mean != T(0)) r[id] = rr;
-        rho += double(rr) * (double(dc) * double(rr));
-        mx = fmax(mx, fabs(double(rr)));
-      }
-      em = ec;
-      ec = ep;
-      L2c = L2p;
-    }
-  }
+  if (G.fast)
+    pcg_b_march<T, true>(g, L, iD, e, x, r, alpha, mean, skip, G, B, sE, rho, mx);
+  else
+    pcg_b_march<T, false>(g, L, iD, e, x, r, alpha, mean, skip, G, B, sE, rho, mx);
   if (want_rho && !skip) {
     rho = block_sum<kTileThreads>(rho);
     if (threadIdx.x == 0) part_rho_next[blockIdx.x] = rho;
