@@ -979,8 +979,10 @@ __device__ __forceinline__ void pcg_a_march(const Grid3& g, const Vec3<T>& L, co
   struct Raw {
     T d, r, e, l;
   };
+  // planes past the tile's last needed one (z1 for the own column, z1-1 for the
+  // ring) re-read that plane, a cache hit, instead of fetching unused data
   auto own = [&](int zz) -> Raw {
-    const int zw = clamp_plane(g, zz), id = col + zw * s2;
+    const int zw = clamp_plane(g, min(zz, G.z1)), id = col + zw * s2;
     Raw v;
     v.r = r[id];
     v.e = eo[id];
@@ -989,7 +991,7 @@ __device__ __forceinline__ void pcg_a_march(const Grid3& g, const Vec3<T>& L, co
     return v;
   };
   auto ring = [&](int zz) -> Raw {
-    const int zw = clamp_plane(g, zz), id = hcol + zw * s2;
+    const int zw = clamp_plane(g, min(zz, G.z1 - 1)), id = hcol + zw * s2;
     Raw v;
     v.r = r[id];
     v.e = eo[id];
@@ -1091,7 +1093,7 @@ __device__ __forceinline__ void pcg_b_march(const Grid3& g, const Vec3<T>& L, co
     T e, l, x, r, d;
   };
   auto own = [&](int zz) -> Raw {
-    const int zw = clamp_plane(g, zz), id = col + zw * s2;
+    const int zw = clamp_plane(g, min(zz, G.z1)), id = col + zw * s2;  // see pcg_a_march
     Raw v;
     v.e = e[id];
     v.l = FAST ? L_std<T>(g, B, 2, zw) : L.c[2][id];
@@ -1100,7 +1102,7 @@ __device__ __forceinline__ void pcg_b_march(const Grid3& g, const Vec3<T>& L, co
     v.d = FAST ? SD.at(g, wi, wj, zw) : iD[id];
     return v;
   };
-  auto ring = [&](int zz) -> T { return e[hcol + clamp_plane(g, zz) * s2]; };
+  auto ring = [&](int zz) -> T { return e[hcol + clamp_plane(g, min(zz, G.z1 - 1)) * s2]; };
   const T Lxp0 = L_std<T>(g, B, 0, G.i + 1), Lxc0 = L_std<T>(g, B, 0, G.i);
   const T Lyp0 = L_std<T>(g, B, 1, G.j + 1), Lyc0 = L_std<T>(g, B, 1, G.j);
   T em = own(G.z0 - 1).e;
