@@ -336,8 +336,39 @@ __device__ __forceinline__ T resid_fast(const Grid3& g, const Vec3<T>& u, int c,
   return acc;
 }
 
-// f~_c = u0_c + dt R_c(u) - V_c on every padded face (R = 0 off the unknown faces).
-// mode 0: f~ (with body velocity if has_body); mode 1: f = R only.  blockIdx.y = c.
+// f~_c = u0_c + dt R_c(u) - V_c at padded face I (R = 0 off the unknown faces).
+// mode 0: f~ (with body velocity if has_body); mode 1: f = R only.
+template <typename T, int D>
+__device__ __forceinline__ void flux_face(const Grid3& g, const Vec3<T>& u, const Vec3<T>& u0, const Vec3<T>& V,
+                                          const Vec3<T>& f, T dt, T nu, int has_body, int mode, const StdBox& B,
+                                          int c, const int I[3]) {
+  const int idx = lin3<T, D>(g, I[0], I[1], I[2]);
+  bool unknown = true;
+  for (int a = 0; a < D; ++a) {
+    const int lo = (a == c && !g.per[a]) ? 2 : 1;
+    unknown = unknown && I[a] >= lo && I[a] <= g.n[a];
+  }
+  // the point-wise loads go first, so they overlap the stencil's
+  const bool needV = mode == 0 && has_body && !std_point<D>(B, g, I, 0);  // V = 0 outside the box
+  const T vb = needV ? V.c[c][idx] : T(0);
+  const T u0v = (mode == 0) ? u0.c[c][idx] : T(0);
+  T R = T(0);
+  if (unknown) {
+    // interior fast path: the +-2 stencil needs no wrap and every far point is valid
+    bool fast = true;
+    for (int a = 0; a < D; ++a) fast = fast && I[a] >= 3 && I[a] <= g.n[a] - 2;
+    R = fast ? resid_fast<T, D>(g, u, c, idx, nu) : resid_c<T, D>(g, u, c, I, nu);
+  }
+  if (mode == 1) {
+    f.c[c][idx] = R;
+  } else {
+    T v = u0v + dt * R;
+    if (needV) v = v - vb;
+    f.c[c][idx] = v;
+  }
+}
+
+// Every padded face, grid-stride (2-D, and the residual-only mode).  blockIdx.y = c.
 template <typename T, int D>
 __global__ void __launch_bounds__(kBlock) k_flux(Grid3 g, Vec3<T> u, Vec3<T> u0, Vec3<T> V,
                                                  Vec3<T> f, T dt, T nu, int has_body, int mode, StdBox B) {
@@ -345,32 +376,33 @@ __global__ void __launch_bounds__(kBlock) k_flux(Grid3 g, Vec3<T> u, Vec3<T> u0,
   const int P0 = g.n[0] + 2, P1 = g.n[1] + 2, P2 = (D == 3) ? g.n[2] + 2 : 1;
   const int total = P0 * P1 * P2;
   for (int lin = blockIdx.x * kBlock + threadIdx.x; lin < total; lin += gridDim.x * kBlock) {
-    const int I0 = lin % P0, t = lin / P0, I1 = t % P1, I2 = t / P1;
+    const int I[3] = {lin % P0, (lin / P0) % P1, (D == 3) ? lin / (P0 * P1) : 0};
+    flux_face<T, D>(g, u, u0, V, f, dt, nu, has_body, mode, B, c, I);
+  }
+}
+
+// 3-D form: one block per brick of 64 x 4 columns x kFZ planes, each thread marching
+// its column in z, so the +-2 neighbours of the stencil are re-read from cache; the
+// bricks are handed out XCD-aware (each XCD takes a contiguous range of bricks,
+// x fastest), which keeps the y/z halos of neighbouring bricks in one L2.
+constexpr int kFX = 64, kFY = 4, kFZ = 16;
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_flux_bricks(Grid3 g, Vec3<T> u, Vec3<T> u0, Vec3<T> V, Vec3<T> f,
+                                                        T dt, T nu, int has_body, StdBox B, int nbx, int nby,
+                                                        int nbz) {
+  const int c = blockIdx.y;
+  const int nb = nbx * nby * nbz;
+  const int b = blockIdx.x;
+  const int full = (nb / 8) * 8;
+  const int t = (b < full) ? (b % 8) * (nb / 8) + b / 8 : b;
+  const int bx = t % nbx, r1 = t / nbx, by = r1 % nby, bz = r1 / nby;
+  const int I0 = bx * kFX + (int)threadIdx.x % kFX, I1 = by * kFY + (int)threadIdx.x / kFX;
+  const int P0 = g.n[0] + 2, P1 = g.n[1] + 2, P2 = g.n[2] + 2;
+  if (I0 >= P0 || I1 >= P1) return;  // no barrier in this kernel
+  const int z1 = min((bz + 1) * kFZ, P2);
+  for (int I2 = bz * kFZ; I2 < z1; ++I2) {
     const int I[3] = {I0, I1, I2};
-    const int idx = lin3<T, D>(g, I0, I1, I2);
-    bool unknown = true;
-    for (int a = 0; a < D; ++a) {
-      const int lo = (a == c && !g.per[a]) ? 2 : 1;
-      unknown = unknown && I[a] >= lo && I[a] <= g.n[a];
-    }
-    // the point-wise loads go first, so they overlap the stencil's
-    const bool needV = mode == 0 && has_body && !std_point<D>(B, g, I, 0);  // V = 0 outside the box
-    const T vb = needV ? V.c[c][idx] : T(0);
-    const T u0v = (mode == 0) ? u0.c[c][idx] : T(0);
-    T R = T(0);
-    if (unknown) {
-      // interior fast path: the +-2 stencil needs no wrap and every far point is valid
-      bool fast = true;
-      for (int a = 0; a < D; ++a) fast = fast && I[a] >= 3 && I[a] <= g.n[a] - 2;
-      R = fast ? resid_fast<T, D>(g, u, c, idx, nu) : resid_c<T, D>(g, u, c, I, nu);
-    }
-    if (mode == 1) {
-      f.c[c][idx] = R;
-    } else {
-      T v = u0v + dt * R;
-      if (needV) v = v - vb;
-      f.c[c][idx] = v;
-    }
+    flux_face<T, 3>(g, u, u0, V, f, dt, nu, has_body, 0, B, c, I);
   }
 }
 
@@ -1307,6 +1339,169 @@ __global__ void __launch_bounds__(kBlock) k_pcg_b(int64_t nvec, const T* iD, con
   if (want_max) {
     mx = block_max(mx);
     if (threadIdx.x == 0) part_max[blockIdx.x] = mx;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// The smallest multigrid levels in one workgroup.  Below a few ten thousand
+// cells a level's passes are dominated by launch and reduction overhead, so
+// from level Lb down the whole remaining cycle runs in a single block of
+// kBottom threads: restriction down to the coarsest level, PCG there, then
+// prolongation + correction and PCG on the way up -- the same arithmetic as the
+// per-level kernels (the reductions are block-wide instead of per-block
+// partials, so sums differ only in rounding order).
+// ---------------------------------------------------------------------------
+constexpr int kBottom = 1024;
+constexpr int kBottomCells = 32768;  // a level this small or smaller joins the bottom solve
+
+template <typename T>
+struct LevelRef {
+  Grid3 g;
+  T *x, *r, *e, *q;
+  const T* iD;
+  Vec3<T> L;
+};
+constexpr int kBottomMax = 8;  // levels a bottom solve may hold (passed by value)
+template <typename T>
+struct BottomLevels {
+  int n, pcg_iters;          // levels lv[0] (the first bottom level) .. lv[n-1] (coarsest)
+  LevelRef<T> lv[kBottomMax];
+};
+
+template <typename T, int D>
+__device__ __forceinline__ T apply_A_cell(const LevelRef<T>& v, const T* x, const int I[3], int idx) {
+  int op[3], om[3];
+  nbr_offsets<D>(v.g, I, op, om);
+  const T xc = x[idx];
+  T Ax = T(0);
+  for (int a = 0; a < D; ++a)
+    Ax = Ax + v.L.c[a][idx + op[a]] * (x[idx + op[a]] - xc) - v.L.c[a][idx] * (xc - x[idx + om[a]]);
+  return Ax;
+}
+
+// PCG(K) on one level with the residual's mean removed first (as k_pcg_a/b)
+template <typename T, int D>
+__device__ void bottom_pcg(const LevelRef<T>& v, int K) {
+  const Grid3& g = v.g;
+  const int total = g.n[0] * g.n[1] * ((D == 3) ? g.n[2] : 1);
+  double s = 0.0, c = 0.0;
+  for (int lin = threadIdx.x; lin < total; lin += kBottom) {
+    int I[3], idx;
+    cell_of<D>(g, lin, I, idx);
+    if (v.iD[idx] != T(0)) {
+      s += double(v.r[idx]);
+      c += 1.0;
+    }
+  }
+  s = block_sum<kBottom>(s);
+  c = block_sum<kBottom>(c);
+  const T mean = T(c > 0.0 ? s / c : 0.0);
+  double rho = 0.0, rho_prev = 0.0;
+  for (int k = 0; k < K; ++k) {
+    T beta = T(0);
+    if (k > 0) {
+      if (rho == 0.0) return;
+      beta = T(rho / rho_prev);
+    }
+    for (int lin = threadIdx.x; lin < total; lin += kBottom) {
+      int I[3], idx;
+      cell_of<D>(g, lin, I, idx);
+      const T di = v.iD[idx];
+      v.e[idx] = (k > 0) ? di * v.r[idx] + beta * v.e[idx] : di * (v.r[idx] - mean);
+    }
+    __syncthreads();
+    double sig = 0.0, r0 = 0.0;
+    for (int lin = threadIdx.x; lin < total; lin += kBottom) {
+      int I[3], idx;
+      cell_of<D>(g, lin, I, idx);
+      const T ec = v.e[idx];
+      T qq = T(0);
+      if (v.iD[idx] != T(0)) {
+        qq = apply_A_cell<T, D>(v, v.e, I, idx);
+        if (k == 0) r0 += double(v.r[idx] - mean) * double(ec);
+      }
+      v.q[idx] = qq;
+      sig += double(ec) * double(qq);
+    }
+    sig = block_sum<kBottom>(sig);
+    if (k == 0) rho = block_sum<kBottom>(r0);
+    if (fabs(sig) < 1e-300) return;
+    const T alpha = T(rho / sig);
+    double rn = 0.0;
+    for (int lin = threadIdx.x; lin < total; lin += kBottom) {
+      int I[3], idx;
+      cell_of<D>(g, lin, I, idx);
+      const T di = v.iD[idx];
+      T rr = v.r[idx];
+      if (k == 0 && di != T(0)) rr = rr - mean;
+      v.x[idx] = v.x[idx] + alpha * v.e[idx];
+      rr = rr - alpha * v.q[idx];
+      v.r[idx] = rr;
+      rn += double(rr) * (double(di) * double(rr));
+    }
+    rho_prev = rho;
+    rho = block_sum<kBottom>(rn);  // also orders this sweep's writes before the next
+  }
+}
+
+// residual restriction f -> c (sum of the children, 0 on solid coarse cells), x_c = 0
+template <typename T, int D>
+__device__ void bottom_restrict(const LevelRef<T>& f, const LevelRef<T>& c) {
+  const int total = c.g.n[0] * c.g.n[1] * ((D == 3) ? c.g.n[2] : 1);
+  for (int lin = threadIdx.x; lin < total; lin += kBottom) {
+    int J[3], cidx;
+    cell_of<D>(c.g, lin, J, cidx);
+    const int base = (2 * J[0] - 1) + (2 * J[1] - 1) * f.g.s[1] + ((D == 3) ? (2 * J[2] - 1) * f.g.s[2] : 0);
+    T sum = f.r[base] + f.r[base + 1] + f.r[base + f.g.s[1]] + f.r[base + 1 + f.g.s[1]];
+    if (D == 3) {
+      const int b2 = base + f.g.s[2];
+      sum = sum + (f.r[b2] + f.r[b2 + 1] + f.r[b2 + f.g.s[1]] + f.r[b2 + 1 + f.g.s[1]]);
+    }
+    c.r[cidx] = (c.iD[cidx] != T(0)) ? sum : T(0);
+    c.x[cidx] = T(0);
+  }
+  __syncthreads();
+}
+
+// prolongation c -> f: x_f += x_c[parent]; r_f -= A_f e with e the injected x_c
+template <typename T, int D>
+__device__ void bottom_prolong(const LevelRef<T>& f, const LevelRef<T>& c) {
+  const int total = f.g.n[0] * f.g.n[1] * ((D == 3) ? f.g.n[2] : 1);
+  for (int lin = threadIdx.x; lin < total; lin += kBottom) {
+    int I[3], idx;
+    cell_of<D>(f.g, lin, I, idx);
+    const T ec = c.x[parent_idx<T, D>(c.g, I[0], I[1], I[2])];
+    f.x[idx] = f.x[idx] + ec;
+    if (f.iD[idx] != T(0)) {
+      T Ae = T(0);
+      for (int a = 0; a < D; ++a) {
+        int Jp[3] = {I[0], I[1], I[2]}, Jm[3] = {I[0], I[1], I[2]};
+        Jp[a] = wrapc(I[a] + 1, a, f.g);
+        Jm[a] = wrapc(I[a] - 1, a, f.g);
+        const T ep = c.x[parent_idx<T, D>(c.g, Jp[0], Jp[1], Jp[2])];
+        const T em = c.x[parent_idx<T, D>(c.g, Jm[0], Jm[1], Jm[2])];
+        const int op = (f.g.per[a] && I[a] == f.g.n[a]) ? -(f.g.n[a] - 1) * f.g.s[a] : f.g.s[a];
+        Ae = Ae + f.L.c[a][idx + op] * (ep - ec) - f.L.c[a][idx] * (ec - em);
+      }
+      f.r[idx] = f.r[idx] - Ae;
+    }
+  }
+  __syncthreads();
+}
+
+// The rest of the cycle from the first bottom level (whose residual the caller
+// restricted): restrict down, PCG on the coarsest level, then prolong + PCG up.
+// One block of kBottom threads.
+template <typename T, int D>
+__global__ void __launch_bounds__(kBottom) k_bottom(BottomLevels<T> bl) {
+  const int last = bl.n - 1;
+  for (int l = 0; l < last; ++l) bottom_restrict<T, D>(bl.lv[l], bl.lv[l + 1]);
+  bottom_pcg<T, D>(bl.lv[last], bl.pcg_iters);
+  __syncthreads();
+  for (int l = last - 1; l >= 0; --l) {
+    bottom_prolong<T, D>(bl.lv[l], bl.lv[l + 1]);
+    bottom_pcg<T, D>(bl.lv[l], bl.pcg_iters);
+    __syncthreads();
   }
 }
 

@@ -373,6 +373,7 @@ struct Impl : SimBase {
   PgBox bd{}, bcrop{};
   int64_t pgPc = 0;
   int tiles[kMaxLevels][4] = {};  // tiled pass A: tiles_x, tiles_y, ntiles (0 = generic kernel)
+  int lbot = 0;                   // first level of the single-workgroup bottom solve
   StdBox sbox[kMaxLevels] = {};   // per level: outside, coefficients are body-free
   // discrete adjoint
   bool adj_on = false, rec = false;
@@ -570,6 +571,7 @@ struct Impl : SimBase {
         maxarea = std::max(maxarea, area);
       }
     plane_blocks = blocks_for(maxarea);
+    lbot = bottom_level();
   }
 
   wl_status init() override {
@@ -787,13 +789,45 @@ struct Impl : SimBase {
     }
   }
 
+  // first level of the single-workgroup bottom solve (nlev if none): the first
+  // coarse level with at most kBottomCells cells, if the levels below fit
+  int bottom_level() const {
+    for (int l = 1; l < nlev; ++l) {
+      int64_t cells = 1;
+      for (int a = 0; a < D; ++a) cells *= g[l].n[a];
+      if (cells <= kBottomCells) return (nlev - l <= kBottomMax) ? l : nlev;
+    }
+    return nlev;
+  }
+
+  void bottom(int lb) {
+    BottomLevels<T> bl{};
+    bl.n = nlev - lb;
+    bl.pcg_iters = desc.pcg_iters;
+    for (int l = lb; l < nlev; ++l) {
+      LevelRef<T>& v = bl.lv[l - lb];
+      v.g = g[l];
+      v.x = x[l];
+      v.r = r[l];
+      v.e = e[l][0];
+      v.q = q[l];
+      v.iD = iD[l];
+      v.L = v3(L[l]);
+    }
+    WL_TIMED(WL_K_COARSE, (k_bottom<T, D><<<1, kBottom, 0, stream>>>(bl)));
+  }
+
   void vcycle(int l) {
     WL_TIMED(l == 0 ? WL_K_RESTRICT : WL_K_COARSE,
              (k_restrict<T, D><<<nb[l + 1], kBlock, 0, stream>>>(g[l], g[l + 1], r[l], iD[l + 1], r[l + 1],
                                                                  x[l + 1], red, flags + l + 1)));
     set_mean_producer(nb[l + 1]);
-    if (l + 2 < nlev) vcycle(l + 1);
-    pcg(l + 1, false);
+    if (l + 1 == lbot) {
+      bottom(l + 1);  // the rest of the cycle below, and PCG on level l+1
+    } else {
+      if (l + 2 < nlev) vcycle(l + 1);
+      pcg(l + 1, false);
+    }
     if (tiles[l][2] > 0) {
       WL_TIMED(l == 0 ? WL_K_PROLONG : WL_K_COARSE,
                (k_prolong_tile<T><<<tiles[l][2], kTileThreads, 0, stream>>>(
@@ -1097,6 +1131,21 @@ struct Impl : SimBase {
     return WL_OK;
   }
 
+  // f~ = u0 + dt R(u) - V on every padded face
+  wl_status flux(T* const uu[3], T* const uu0[3], int hb) {
+    if (D == 3) {
+      const int nbx = (g[0].n[0] + 2 + kFX - 1) / kFX, nby = (g[0].n[1] + 2 + kFY - 1) / kFY,
+                nbz = (g[0].n[2] + 2 + kFZ - 1) / kFZ;
+      WL_TIMED(WL_K_FLUX, (k_flux_bricks<T><<<dim3(nbx * nby * nbz, D), kBlock, 0, stream>>>(
+                              g[0], v3(uu), v3(uu0), v3(V), v3(ft), T(dt), T(desc.nu), hb, sbox[0], nbx, nby, nbz)));
+    } else {
+      WL_TIMED(WL_K_FLUX, (k_flux<T, D><<<dim3(nb_face, D), kBlock, 0, stream>>>(
+                              g[0], v3(uu), v3(uu0), v3(V), v3(ft), T(dt), T(desc.nu), hb, 0, sbox[0])));
+    }
+    WL_HIP(hipGetLastError());
+    return WL_OK;
+  }
+
   wl_status conv_diff() override {
     k_flux<T, D><<<dim3(nb_face, D), kBlock, 0, stream>>>(g[0], v3(u[cur]), v3(u[cur]), v3(V), v3(ft), T(0),
                                                           T(desc.nu), 0, 1, sbox[0]);
@@ -1114,8 +1163,7 @@ struct Impl : SimBase {
     T* const* B = u[1 - cur];
     const int hb = has_body ? 1 : 0;
     // predictor
-    WL_TIMED(WL_K_FLUX, (k_flux<T, D><<<dim3(nb_face, D), kBlock, 0, stream>>>(g[0], v3(A), v3(A), v3(V), v3(ft),
-                                                                              T(dt), T(desc.nu), hb, 0, sbox[0])));
+    if ((s = flux(A, A, hb)) != WL_OK) return s;
     WL_TIMED(WL_K_BDIM, (k_bdim<T, D, 0><<<dim3(nb_face, D), kBlock, 0, stream>>>(g[0], v3(ft), v3(V), v3(mu0),
                                                                                  v9(mu1), v3(B), hb, sbox[0])));
     const bool ex = desc.convective_exit != 0;
@@ -1141,8 +1189,7 @@ struct Impl : SimBase {
       WL_HIP(copy_field(recX1, x[0]));
     }
     // corrector
-    WL_TIMED(WL_K_FLUX, (k_flux<T, D><<<dim3(nb_face, D), kBlock, 0, stream>>>(g[0], v3(B), v3(A), v3(V), v3(ft),
-                                                                              T(dt), T(desc.nu), hb, 0, sbox[0])));
+    if ((s = flux(B, A, hb)) != WL_OK) return s;
     WL_TIMED(WL_K_BDIM, (k_bdim<T, D, 1><<<dim3(nb_face, D), kBlock, 0, stream>>>(g[0], v3(ft), v3(V), v3(mu0),
                                                                                  v9(mu1), v3(B), hb, sbox[0])));
     WL_HIP(hipGetLastError());

@@ -253,3 +253,68 @@ def test_large_grid_projection_is_divergence_free():
     # the corrector's residual tolerance holds for x; div u = r up to FP32 rounding of u
     assert d < 2 * w.tol
     gpu.close()
+
+
+@pytest.mark.parametrize("name", ["plate3d", "sphere3d_tiled", "circle2d"])
+def test_coefficients_are_body_free_outside_the_body_box(name):
+    """The kernels evaluate L, iD (every level) and mu0, mu1, V (fine level) in closed
+    form outside the body box; check that the stored fields hold exactly those values
+    there, for a moving body after several re-measures."""
+    _say("body box", name)
+    import torch
+    from paper_2407_16032_amd import Simulation
+    w = CASES[name]
+    gpu = Simulation(w.n, w.U, w.nu, w.body, periodic=w.periodic_mask(), convective_exit=w.convective_exit,
+                     prec="f64", tol=1e-8, device="cuda:0")
+    gpu.set_velocity(wlsynth.initial_velocity(w))
+    for _ in range(3):
+        gpu.step()
+    D = len(w.n)
+    per = w.periodic_mask() if w.periodic_mask() else [False] * D
+    levels = gpu.levels()
+    for lvl, n in enumerate(levels):
+        lo, hi = gpu.body_box(lvl)
+        Lstd = float(2 ** ((D - 2) * lvl))
+        # padded index grids, axis order of the arrays (components, z, y, x) -> (x, y[, z])
+        L = gpu.field("L", lvl).double().cpu().numpy()
+        iD = gpu.field("iD", lvl).double().cpu().numpy()[0]
+        if D == 2:
+            L = L[:, 0].transpose(0, 2, 1)
+            iD = iD[0].T
+        else:
+            L = L.transpose(0, 3, 2, 1)
+            iD = iD.transpose(2, 1, 0)
+        idx = np.meshgrid(*[np.arange(N + 2) for N in n], indexing="ij")
+
+        def outside(margin):
+            if lo[0] > hi[0]:
+                return np.ones(idx[0].shape, dtype=bool)
+            m = np.zeros(idx[0].shape, dtype=bool)
+            for a in range(D):
+                m |= (idx[a] < lo[a] - margin) | (idx[a] > hi[a] + margin)
+            return m
+
+        interior = np.ones(idx[0].shape, dtype=bool)
+        for a in range(D):
+            interior &= (idx[a] >= 1) & (idx[a] <= n[a])
+        # L on the faces of interior cells (face index 1..N along its own axis)
+        for a in range(D):
+            face = interior.copy()
+            expect = np.where(per[a] | ((idx[a] >= 2) & (idx[a] <= n[a])), Lstd, 0.0)
+            m = face & outside(0)
+            np.testing.assert_array_equal(L[a][m], expect[m])
+        cnt = np.full(idx[0].shape, 2 * D)
+        for a in range(D):
+            if not per[a]:
+                cnt = cnt - (idx[a] == 1) - (idx[a] == n[a])
+        m = interior & outside(1)
+        np.testing.assert_array_equal(iD[m], (1.0 / (-(Lstd * cnt)))[m])
+        _say("  level %d n %s box %s..%s: %d interior cells checked" % (lvl, n, lo, hi, int(m.sum())))
+        if lvl == 0 and w.body.kind != "none":
+            for fname in ("mu1", "V"):
+                f = gpu.field(fname).double().cpu().numpy()
+                f = f[:, 0].transpose(0, 2, 1) if D == 2 else f.transpose(0, 3, 2, 1)
+                m = outside(0)
+                for comp in range(f.shape[0]):
+                    assert np.all(f[comp][m] == 0.0), (fname, comp)
+    gpu.close()
