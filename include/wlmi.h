@@ -339,6 +339,12 @@ enum {
  * counters; 0 stops recording.  Timing adds one event pair per launch. */
 wl_status wl_profile(wl_sim* sim, int enable);
 
+/* As wl_profile, but only the groups whose bit is set in groups (bit k = group
+ * k of the enum above) are timed, so a timed region can carry events around
+ * one kernel group without the cost of an event pair per launch of every
+ * other group; groups = 0 stops recording. */
+wl_status wl_profile_groups(wl_sim* sim, uint32_t groups);
+
 /* Accumulated time (ms) and launch count of one kernel group since the last
  * wl_profile(sim, 1); call after the timed work has completed. */
 wl_status wl_profile_read(wl_sim* sim, int kernel, double* total_ms, int64_t* launches);

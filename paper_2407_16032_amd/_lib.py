@@ -18,7 +18,7 @@ FIELDS = {"u": 0, "u0": 1, "f": 2, "V": 3, "mu0": 4, "mu1": 5, "p": 6, "x": 7, "
 # every symbol include/wlmi.h declares
 EXPORTS = ["wl_workspace_bytes", "wl_sim_create", "wl_sim_destroy", "wl_measure_body", "wl_step",
            "wl_apply_bc", "wl_conv_diff", "wl_project", "wl_poisson_solve", "wl_forces", "wl_field",
-           "wl_levels", "wl_set_time", "wl_get_time", "wl_profile", "wl_profile_read", "wl_pg_set_weights",
+           "wl_levels", "wl_set_time", "wl_get_time", "wl_profile", "wl_profile_groups", "wl_profile_read", "wl_pg_set_weights",
            "wl_pg_get_weights", "wl_pg_mode", "wl_pg_forward", "wl_pg_train_step", "wl_pg_stats", "wl_body_update",
            "wl_body_box",
            "wl_adj_reset", "wl_adj_forces", "wl_adj_step", "wl_adj_body_grad", "wl_last_error"]
@@ -98,6 +98,8 @@ def load(path: str = LIB_PATH):
     lib.wl_get_time.argtypes = [P, C.POINTER(C.c_double), C.POINTER(C.c_double)]
     lib.wl_profile.restype = C.c_int
     lib.wl_profile.argtypes = [P, C.c_int]
+    lib.wl_profile_groups.restype = C.c_int
+    lib.wl_profile_groups.argtypes = [P, C.c_uint32]
     lib.wl_profile_read.restype = C.c_int
     lib.wl_profile_read.argtypes = [P, C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_int64)]
     FP = C.POINTER(C.c_float)

@@ -126,6 +126,29 @@ template <typename T> struct Vec16;
 template <> struct Vec16<float> { typedef float4 type; static constexpr int W = 4; };
 template <> struct Vec16<double> { typedef double2 type; static constexpr int W = 2; };
 
+// Streaming stores and loads: fields of the large levels are several times the
+// size of the last-level cache and are touched once per pass, so their stores
+// (and the loads no neighbouring tile re-reads) carry the non-temporal hint.
+#ifndef WL_NT_MODE
+#define WL_NT_MODE 1
+#endif
+template <typename T>
+__device__ __forceinline__ void st_stream(T* p, T v) {
+#if WL_NT_MODE >= 1
+  __builtin_nontemporal_store(v, p);
+#else
+  *p = v;
+#endif
+}
+template <typename T>
+__device__ __forceinline__ T ld_stream(const T* p) {
+#if WL_NT_MODE >= 2
+  return __builtin_nontemporal_load(p);
+#else
+  return *p;
+#endif
+}
+
 template <typename T>
 __device__ __forceinline__ T median3(T a, T b, T c) {
   return fmax(fmin(a, b), fmin(fmax(a, b), c));

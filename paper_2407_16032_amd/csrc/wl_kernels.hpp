@@ -9,7 +9,24 @@
 namespace wl {
 
 // tile of the z-marching stencil kernels: 64 x 8 columns, 32 planes deep
-constexpr int kTX = 64, kTY = 8, kTZ = 32, kTileThreads = kTX * kTY;
+#ifndef WL_TY
+#define WL_TY 8
+#endif
+#ifndef WL_TZ
+#define WL_TZ 32
+#endif
+#ifndef WL_TILE_ATTR
+#define WL_TILE_ATTR
+#endif
+constexpr int kTX = 64, kTY = WL_TY, kTZ = WL_TZ, kTileThreads = kTX * kTY;
+// planes between the issue of a marching tile's loads and their use
+#ifndef WL_PCG_PF
+#define WL_PCG_PF 2
+#endif
+constexpr int kPF = WL_PCG_PF;
+constexpr int kTileMinZ = 8;       // shortest march of a level's tiles
+constexpr int kTileTarget = 1024;  // tiles wanted per level (4 per compute unit)
+static_assert(kPF >= 2, "pass B consumes two planes per step");
 
 // ---------------------------------------------------------------------------
 // body description and rigid motion (the paper's AutoBody, analytic subset)
@@ -812,16 +829,16 @@ __device__ __forceinline__ void prolong_march(const Grid3& f, const Grid3& c, co
 }
 
 template <typename T>
-__global__ void __launch_bounds__(kTileThreads) k_prolong_tile(Grid3 f, Grid3 c, const T* xc, Vec3<T> L, const T* iD,
+__global__ void __launch_bounds__(kTileThreads) WL_TILE_ATTR k_prolong_tile(Grid3 f, Grid3 c, const T* xc, Vec3<T> L, const T* iD,
                                                       T* xf, T* rf, double* red, int* flag, int tiles_x,
-                                                      int tiles_y, int ntiles, StdBox B) {
+                                                      int tiles_y, int ntiles, int tz, StdBox B) {
   if (blockIdx.x == 0 && threadIdx.x == 0) *flag = 0;
   const int b = blockIdx.x;
   const int full = (ntiles / 8) * 8;
   const int tile = (b < full) ? (b % 8) * (ntiles / 8) + b / 8 : b;
   const int txi = tile % tiles_x, rem = tile / tiles_x, tyi = rem % tiles_y, tzi = rem / tiles_y;
-  const int x0 = 1 + txi * kTX, y0 = 1 + tyi * kTY, z0 = 1 + tzi * kTZ;
-  const int z1 = min(z0 + kTZ, f.n[2] + 1);
+  const int x0 = 1 + txi * kTX, y0 = 1 + tyi * kTY, z0 = 1 + tzi * tz;
+  const int z1 = min(z0 + tz, f.n[2] + 1);
   const int tx = threadIdx.x % kTX, ty = threadIdx.x / kTX;
   const int i = x0 + tx, j = y0 + ty;
   const bool own = i <= f.n[0] && j <= f.n[1];
@@ -932,7 +949,7 @@ struct TileGeo {
   int opx, opy;        // +x / +y face offsets of the own column (periodic wrap)
   bool fast;           // the stencil misses the body box: closed-form coefficients
 
-  __device__ TileGeo(const Grid3& g, const StdBox& B, int tiles_x, int tiles_y, int ntiles) {
+  __device__ TileGeo(const Grid3& g, const StdBox& B, int tiles_x, int tiles_y, int ntiles, int tz) {
     // XCD-aware tile order: consecutive hardware blocks round-robin over the 8 XCDs,
     // so give each XCD a contiguous range of tiles (shared halos stay in its L2)
     const int b = blockIdx.x;
@@ -941,8 +958,8 @@ struct TileGeo {
     const int txi = tile % tiles_x, rem = tile / tiles_x, tyi = rem % tiles_y, tzi = rem / tiles_y;
     x0 = 1 + txi * kTX;
     y0 = 1 + tyi * kTY;
-    z0 = 1 + tzi * kTZ;
-    z1 = min(z0 + kTZ, g.n[2] + 1);
+    z0 = 1 + tzi * tz;
+    z1 = min(z0 + tz, g.n[2] + 1);
     tx = threadIdx.x % kTX;
     ty = threadIdx.x / kTX;
     i = x0 + tx;
@@ -1036,10 +1053,10 @@ __device__ __forceinline__ void pcg_a_march(const Grid3& g, const Vec3<T>& L, co
   const Raw am = own(G.z0 - 1), a0 = own(G.z0);
   T em = eps3(am.d, am.r, am.e), ec = eps3(a0.d, a0.r, a0.e), dc = a0.d, rc = a0.r, L2c = a0.l;
   // one plane: consumes own plane z+1 (ap) and ring plane z (hr), issues the loads
-  // of own plane z+3 and ring plane z+2 (used two planes later)
+  // of own plane z+1+kPF and ring plane z+kPF (used kPF planes later)
   auto plane = [&](int z, const Raw& ap, const Raw& hr, Raw& a_new, Raw& h_new) {
-    a_new = own(z + 3);
-    h_new = ring(z + 2);
+    a_new = own(z + 1 + kPF);
+    h_new = ring(z + kPF);
     const T ep = eps3(ap.d, ap.r, ap.e), L2p = ap.l;
     T(*P)[kTX + 2] = sE[z & 1];
     P[G.ty + 1][G.tx + 1] = ec;
@@ -1058,7 +1075,7 @@ __device__ __forceinline__ void pcg_a_march(const Grid3& g, const Vec3<T>& L, co
         qq = qq + L2p * (ep - ec) - L2c * (ec - em);
         if (k == 0) rho0 += double(rc - mean) * double(ec);
       }
-      en[id] = ec;
+      st_stream(en + id, ec);
       if (STOREQ) q[id] = qq;
       sig += double(ec) * double(qq);
     }
@@ -1069,31 +1086,38 @@ __device__ __forceinline__ void pcg_a_march(const Grid3& g, const Vec3<T>& L, co
     rc = ap.r;
     L2c = L2p;
   };
-  // three planes per trip, so the register slots are renamed rather than copied
-  // (a copy of a register whose load is in flight would wait for it)
-  Raw A = own(G.z0 + 1), Bn = own(G.z0 + 2), C;
-  Raw HA = ring(G.z0), HB = ring(G.z0 + 1), HC;
-  for (int z = G.z0; z < G.z1; z += 3) {
-    plane(z, A, HA, C, HC);
-    if (z + 1 >= G.z1) break;
-    plane(z + 1, Bn, HB, A, HA);
-    if (z + 2 >= G.z1) break;
-    plane(z + 2, C, HC, Bn, HB);
+  // kPF + 1 planes per trip over kPF + 1 register slots indexed by constants, so
+  // the slots are renamed rather than copied (a copy of a register whose load is
+  // in flight would wait for it): own plane z0+1+m lives in S[m % NS], ring
+  // plane z0+m in H[m % NS]
+  constexpr int NS = kPF + 1;
+  Raw S[NS], H[NS];
+#pragma unroll
+  for (int m = 0; m < kPF; ++m) {
+    S[m] = own(G.z0 + 1 + m);
+    H[m] = ring(G.z0 + m);
+  }
+  for (int z = G.z0; z < G.z1; z += NS) {
+#pragma unroll
+    for (int u = 0; u < NS; ++u) {
+      if (z + u >= G.z1) break;
+      plane(z + u, S[u], H[u], S[(u + kPF) % NS], H[(u + kPF) % NS]);
+    }
   }
 }
 
 // PCG pass A, tiled form (see k_pcg_a for the arithmetic).  With STOREQ = 0,
 // q = A e is only reduced into sigma, not stored: the tiled pass B recomputes it.
 template <typename T, int FINE, int STOREQ = 1>
-__global__ void __launch_bounds__(kTileThreads) k_pcg_a_tile(Grid3 g, Vec3<T> L, const T* iD, const T* r,
+__global__ void __launch_bounds__(kTileThreads) WL_TILE_ATTR k_pcg_a_tile(Grid3 g, Vec3<T> L, const T* iD, const T* r,
                                                              const T* eo, T* en, T* q, double* red, int k,
                                                              RedN rn, double* part_sig, int* flag, int tiles_x,
-                                                             int tiles_y, int ntiles, StdBox B) {
+                                                             int tiles_y, int ntiles, int tz, StdBox B) {
   if (*flag) return;
   T beta, mean;
   if (!pcg_a_scalars<T, kTileThreads>(red, k, rn, flag, beta, mean)) return;
   __shared__ T sE[2][kTY + 2][kTX + 2];
-  const TileGeo G(g, B, tiles_x, tiles_y, ntiles);
+  const TileGeo G(g, B, tiles_x, tiles_y, ntiles, tz);
   double sig = 0.0, rho0 = 0.0;
   if (G.fast)
     pcg_a_march<T, STOREQ, true>(g, L, iD, r, eo, en, q, k, beta, mean, G, B, sE, sig, rho0);
@@ -1129,8 +1153,8 @@ __device__ __forceinline__ void pcg_b_march(const Grid3& g, const Vec3<T>& L, co
     Raw v;
     v.e = e[id];
     v.l = FAST ? L_std<T>(g, B, 2, zw) : L.c[2][id];
-    v.x = x[id];
-    v.r = r[id];
+    v.x = ld_stream(x + id);
+    v.r = ld_stream(r + id);
     v.d = FAST ? SD.at(g, wi, wj, zw) : iD[id];
     return v;
   };
@@ -1139,10 +1163,10 @@ __device__ __forceinline__ void pcg_b_march(const Grid3& g, const Vec3<T>& L, co
   const T Lyp0 = L_std<T>(g, B, 1, G.j + 1), Lyc0 = L_std<T>(g, B, 1, G.j);
   T em = own(G.z0 - 1).e;
   // one plane: consumes own planes z (cur) and z+1 (nxt) and ring plane z (hr),
-  // issues the loads of own plane z+2 and ring plane z+2
+  // issues the loads of own plane z+kPF and ring plane z+kPF
   auto plane = [&](int z, const Raw& cur, const Raw& nxt, const T& hr, Raw& a_new, T& h_new) {
-    a_new = own(z + 2);
-    h_new = ring(z + 2);
+    a_new = own(z + kPF);
+    h_new = ring(z + kPF);
     const T ec = cur.e, ep = nxt.e, L2c = cur.l, L2p = nxt.l, dc = cur.d;
     T(*P)[kTX + 2] = sE[z & 1];
     P[G.ty + 1][G.tx + 1] = ec;
@@ -1163,23 +1187,30 @@ __device__ __forceinline__ void pcg_b_march(const Grid3& g, const Vec3<T>& L, co
           qq = qq + Lyp * (yp - ec) - Lyc * (ec - ym);
           qq = qq + L2p * (ep - ec) - L2c * (ec - em);
         }
-        x[id] = cur.x + alpha * ec;
+        st_stream(x + id, cur.x + alpha * ec);
         rr = rr - alpha * qq;
       }
-      if (!skip || mean != T(0)) r[id] = rr;
+      if (!skip || mean != T(0)) st_stream(r + id, rr);
       rho += double(rr) * (double(dc) * double(rr));
       mx = fmax(mx, fabs(double(rr)));
     }
     em = ec;
   };
-  Raw A = own(G.z0), Bn = own(G.z0 + 1), C;
-  T HA = ring(G.z0), HB = ring(G.z0 + 1), HC;
-  for (int z = G.z0; z < G.z1; z += 3) {
-    plane(z, A, Bn, HA, C, HC);
-    if (z + 1 >= G.z1) break;
-    plane(z + 1, Bn, C, HB, A, HA);
-    if (z + 2 >= G.z1) break;
-    plane(z + 2, C, A, HC, Bn, HB);
+  // slots as in pcg_a_march: own plane z0+m in S[m % NS], ring plane z0+m in H[m % NS]
+  constexpr int NS = kPF + 1;
+  Raw S[NS];
+  T H[NS];
+#pragma unroll
+  for (int m = 0; m < kPF; ++m) {
+    S[m] = own(G.z0 + m);
+    H[m] = ring(G.z0 + m);
+  }
+  for (int z = G.z0; z < G.z1; z += NS) {
+#pragma unroll
+    for (int u = 0; u < NS; ++u) {
+      if (z + u >= G.z1) break;
+      plane(z + u, S[u], S[(u + 1) % NS], H[u], S[(u + kPF) % NS], H[(u + kPF) % NS]);
+    }
   }
 }
 
@@ -1188,10 +1219,10 @@ __device__ __forceinline__ void pcg_b_march(const Grid3& g, const Vec3<T>& L, co
 // r -= alpha q on the interior, with the same scalars, stopping rule, mean removal
 // (sweep 0) and partials (rho_{k+1}, max|r|) as the flat pass B.
 template <typename T, int FINE>
-__global__ void __launch_bounds__(kTileThreads) k_pcg_b_tile(Grid3 g, Vec3<T> L, const T* iD, const T* e, T* x,
+__global__ void __launch_bounds__(kTileThreads) WL_TILE_ATTR k_pcg_b_tile(Grid3 g, Vec3<T> L, const T* iD, const T* e, T* x,
                                                              T* r, double* red, int k, RedN rn, double* part_rho_next,
                                                              double* part_max, int want_rho, int want_max, int* flag,
-                                                             int tiles_x, int tiles_y, int ntiles, StdBox B) {
+                                                             int tiles_x, int tiles_y, int ntiles, int tz, StdBox B) {
   bool skip = (*flag) != 0;
   T alpha = T(0);
   const T mean = (k == 0) ? T(residual_mean<kTileThreads>(red, rn.mean)) : T(0);
@@ -1206,7 +1237,7 @@ __global__ void __launch_bounds__(kTileThreads) k_pcg_b_tile(Grid3 g, Vec3<T> L,
   }
   if (skip && !want_max && mean == T(0)) return;  // grid-uniform
   __shared__ T sE[2][kTY + 2][kTX + 2];
-  const TileGeo G(g, B, tiles_x, tiles_y, ntiles);
+  const TileGeo G(g, B, tiles_x, tiles_y, ntiles, tz);
   double rho = 0.0, mx = 0.0;
   if (G.fast)
     pcg_b_march<T, true>(g, L, iD, e, x, r, alpha, mean, skip, G, B, sE, rho, mx);
@@ -1343,16 +1374,23 @@ __global__ void __launch_bounds__(kBlock) k_pcg_b(int64_t nvec, const T* iD, con
 }
 
 // ---------------------------------------------------------------------------
-// The smallest multigrid levels in one workgroup.  Below a few ten thousand
-// cells a level's passes are dominated by launch and reduction overhead, so
-// from level Lb down the whole remaining cycle runs in a single block of
-// kBottom threads: restriction down to the coarsest level, PCG there, then
-// prolongation + correction and PCG on the way up -- the same arithmetic as the
-// per-level kernels (the reductions are block-wide instead of per-block
-// partials, so sums differ only in rounding order).
+// The smallest multigrid levels in one workgroup.  Below a few thousand cells a
+// level's passes are dominated by launch and reduction overhead, so from level
+// Lb down the whole remaining cycle runs in a single block of kBottom threads:
+// restriction down to the coarsest level, PCG there, then prolongation +
+// correction and PCG on the way up -- the same arithmetic as the per-level
+// kernels (the reductions are block-wide instead of per-block partials, so sums
+// differ only in rounding order).  During a level's PCG each thread keeps its
+// cells' x, r, q, iD and face coefficients in registers and the search
+// direction lives in LDS (a compact copy of the padded level, ghosts zero), so
+// the sweeps touch no global memory.
 // ---------------------------------------------------------------------------
 constexpr int kBottom = 1024;
-constexpr int kBottomCells = 32768;  // a level this small or smaller joins the bottom solve
+constexpr int kBottomCPT = 4;                          // cells per thread
+constexpr int kBottomCells = kBottom * kBottomCPT;     // a level this small or smaller joins the bottom solve
+constexpr int kBottomLdsBytes = 49152;                 // LDS for the search direction of one level
+template <typename T>
+constexpr int bottom_lds_elems() { return kBottomLdsBytes / (int)sizeof(T); }
 
 template <typename T>
 struct LevelRef {
@@ -1368,80 +1406,137 @@ struct BottomLevels {
   LevelRef<T> lv[kBottomMax];
 };
 
-template <typename T, int D>
-__device__ __forceinline__ T apply_A_cell(const LevelRef<T>& v, const T* x, const int I[3], int idx) {
-  int op[3], om[3];
-  nbr_offsets<D>(v.g, I, op, om);
-  const T xc = x[idx];
-  T Ax = T(0);
-  for (int a = 0; a < D; ++a)
-    Ax = Ax + v.L.c[a][idx + op[a]] * (x[idx + op[a]] - xc) - v.L.c[a][idx] * (xc - x[idx + om[a]]);
-  return Ax;
+// two block sums for the price of one set of barriers
+template <int NT>
+__device__ __forceinline__ void block_sum2(double& a, double& b) {
+  __shared__ double sh2[2][NT / 64];
+  a = wave_sum(a);
+  b = wave_sum(b);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) {
+    sh2[0][w] = a;
+    sh2[1][w] = b;
+  }
+  __syncthreads();
+  double ra = sh2[0][0], rb = sh2[1][0];
+#pragma unroll
+  for (int i = 1; i < NT / 64; ++i) {
+    ra += sh2[0][i];
+    rb += sh2[1][i];
+  }
+  __syncthreads();
+  a = ra;
+  b = rb;
 }
 
-// PCG(K) on one level with the residual's mean removed first (as k_pcg_a/b)
+// PCG(K) on one level with the residual's mean removed first (as k_pcg_a/b).
+// sE holds the level's padded cells compactly: (n0+2) x (n1+2) [x (n2+2)].
 template <typename T, int D>
-__device__ void bottom_pcg(const LevelRef<T>& v, int K) {
+__device__ void bottom_pcg(const LevelRef<T>& v, int K, T* sE) {
   const Grid3& g = v.g;
   const int total = g.n[0] * g.n[1] * ((D == 3) ? g.n[2] : 1);
+  const int m0 = g.n[0] + 2, m1 = g.n[1] + 2;
+  const int lsz = m0 * m1 * ((D == 3) ? g.n[2] + 2 : 1);
+  const int ls[3] = {1, m0, m0 * m1};
+  // LDS offsets of the + and - neighbours, and their periodic-wrap forms
+  int lp[3], lm[3], lpw[3], lmw[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    lp[a] = ls[a];
+    lm[a] = -ls[a];
+    lpw[a] = -(g.n[a] - 1) * ls[a];
+    lmw[a] = (g.n[a] - 1) * ls[a];
+  }
+  for (int i = threadIdx.x; i < lsz; i += kBottom) sE[i] = T(0);
+  // this thread's cells (wrap: bit 2a for +a, bit 2a+1 for -a)
+  bool ok[kBottomCPT];
+  int gid[kBottomCPT], lid[kBottomCPT], wrap[kBottomCPT];
+  T di[kBottomCPT], xr[kBottomCPT], rr[kBottomCPT], qq[kBottomCPT], ec[kBottomCPT];
+  T Lp[kBottomCPT][3], Lm[kBottomCPT][3];
   double s = 0.0, c = 0.0;
-  for (int lin = threadIdx.x; lin < total; lin += kBottom) {
-    int I[3], idx;
-    cell_of<D>(g, lin, I, idx);
-    if (v.iD[idx] != T(0)) {
-      s += double(v.r[idx]);
+#pragma unroll
+  for (int k = 0; k < kBottomCPT; ++k) {
+    const int lin = threadIdx.x + k * kBottom;
+    ok[k] = lin < total;
+    int I[3], idx, op[3], om[3];
+    cell_of<D>(g, ok[k] ? lin : 0, I, idx);
+    nbr_offsets<D>(g, I, op, om);
+    gid[k] = idx;
+    lid[k] = I[0] + I[1] * ls[1] + ((D == 3) ? I[2] * ls[2] : 0);
+    wrap[k] = 0;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      if (a < D && g.per[a] && I[a] == g.n[a]) wrap[k] |= 1 << (2 * a);
+      if (a < D && g.per[a] && I[a] == 1) wrap[k] |= 2 << (2 * a);
+      Lp[k][a] = (a < D) ? v.L.c[a][idx + op[a]] : T(0);
+      Lm[k][a] = (a < D) ? v.L.c[a][idx] : T(0);
+    }
+    di[k] = ok[k] ? v.iD[idx] : T(0);
+    rr[k] = v.r[idx];
+    xr[k] = v.x[idx];
+    qq[k] = T(0);
+    ec[k] = T(0);
+    if (di[k] != T(0)) {
+      s += double(rr[k]);
       c += 1.0;
     }
   }
-  s = block_sum<kBottom>(s);
-  c = block_sum<kBottom>(c);
+  block_sum2<kBottom>(s, c);  // also orders the LDS clear before the first writes
   const T mean = T(c > 0.0 ? s / c : 0.0);
   double rho = 0.0, rho_prev = 0.0;
-  for (int k = 0; k < K; ++k) {
+  for (int it = 0; it < K; ++it) {
     T beta = T(0);
-    if (k > 0) {
-      if (rho == 0.0) return;
+    if (it > 0) {
+      if (rho == 0.0) break;
       beta = T(rho / rho_prev);
     }
-    for (int lin = threadIdx.x; lin < total; lin += kBottom) {
-      int I[3], idx;
-      cell_of<D>(g, lin, I, idx);
-      const T di = v.iD[idx];
-      v.e[idx] = (k > 0) ? di * v.r[idx] + beta * v.e[idx] : di * (v.r[idx] - mean);
+#pragma unroll
+    for (int k = 0; k < kBottomCPT; ++k) {
+      ec[k] = (it > 0) ? di[k] * rr[k] + beta * ec[k] : di[k] * (rr[k] - mean);
+      if (ok[k]) sE[lid[k]] = ec[k];
     }
     __syncthreads();
     double sig = 0.0, r0 = 0.0;
-    for (int lin = threadIdx.x; lin < total; lin += kBottom) {
-      int I[3], idx;
-      cell_of<D>(g, lin, I, idx);
-      const T ec = v.e[idx];
-      T qq = T(0);
-      if (v.iD[idx] != T(0)) {
-        qq = apply_A_cell<T, D>(v, v.e, I, idx);
-        if (k == 0) r0 += double(v.r[idx] - mean) * double(ec);
+#pragma unroll
+    for (int k = 0; k < kBottomCPT; ++k) {
+      T Ae = T(0);
+      if (di[k] != T(0)) {
+#pragma unroll
+        for (int a = 0; a < D; ++a) {
+          const int op = ((wrap[k] >> (2 * a)) & 1) ? lpw[a] : lp[a];
+          const int om = ((wrap[k] >> (2 * a)) & 2) ? lmw[a] : lm[a];
+          Ae = Ae + Lp[k][a] * (sE[lid[k] + op] - ec[k]) - Lm[k][a] * (ec[k] - sE[lid[k] + om]);
+        }
+        if (it == 0) r0 += double(rr[k] - mean) * double(ec[k]);
       }
-      v.q[idx] = qq;
-      sig += double(ec) * double(qq);
+      qq[k] = Ae;
+      sig += double(ec[k]) * double(Ae);
     }
-    sig = block_sum<kBottom>(sig);
-    if (k == 0) rho = block_sum<kBottom>(r0);
-    if (fabs(sig) < 1e-300) return;
+    block_sum2<kBottom>(sig, r0);  // its barriers also end this sweep's LDS reads
+    if (it == 0) rho = r0;
+    if (fabs(sig) < 1e-300) break;
     const T alpha = T(rho / sig);
     double rn = 0.0;
-    for (int lin = threadIdx.x; lin < total; lin += kBottom) {
-      int I[3], idx;
-      cell_of<D>(g, lin, I, idx);
-      const T di = v.iD[idx];
-      T rr = v.r[idx];
-      if (k == 0 && di != T(0)) rr = rr - mean;
-      v.x[idx] = v.x[idx] + alpha * v.e[idx];
-      rr = rr - alpha * v.q[idx];
-      v.r[idx] = rr;
-      rn += double(rr) * (double(di) * double(rr));
+#pragma unroll
+    for (int k = 0; k < kBottomCPT; ++k) {
+      T r_ = rr[k];
+      if (it == 0 && di[k] != T(0)) r_ = r_ - mean;
+      xr[k] = xr[k] + alpha * ec[k];
+      r_ = r_ - alpha * qq[k];
+      rr[k] = r_;
+      rn += double(r_) * (double(di[k]) * double(r_));
     }
     rho_prev = rho;
-    rho = block_sum<kBottom>(rn);  // also orders this sweep's writes before the next
+    rho = block_sum<kBottom>(rn);
   }
+#pragma unroll
+  for (int k = 0; k < kBottomCPT; ++k)
+    if (ok[k]) {
+      v.x[gid[k]] = xr[k];
+      v.r[gid[k]] = rr[k];
+    }
+  __syncthreads();
 }
 
 // residual restriction f -> c (sum of the children, 0 on solid coarse cells), x_c = 0
@@ -1494,14 +1589,13 @@ __device__ void bottom_prolong(const LevelRef<T>& f, const LevelRef<T>& c) {
 // One block of kBottom threads.
 template <typename T, int D>
 __global__ void __launch_bounds__(kBottom) k_bottom(BottomLevels<T> bl) {
+  __shared__ T sE[bottom_lds_elems<T>()];
   const int last = bl.n - 1;
   for (int l = 0; l < last; ++l) bottom_restrict<T, D>(bl.lv[l], bl.lv[l + 1]);
-  bottom_pcg<T, D>(bl.lv[last], bl.pcg_iters);
-  __syncthreads();
+  bottom_pcg<T, D>(bl.lv[last], bl.pcg_iters, sE);
   for (int l = last - 1; l >= 0; --l) {
     bottom_prolong<T, D>(bl.lv[l], bl.lv[l + 1]);
-    bottom_pcg<T, D>(bl.lv[l], bl.pcg_iters);
-    __syncthreads();
+    bottom_pcg<T, D>(bl.lv[l], bl.pcg_iters, sE);
   }
 }
 

@@ -217,6 +217,7 @@ void host_motion(const wl_body_desc& b, double t, Motion& m) {
 struct Profiler {
   static constexpr int kPairs = 1024;
   bool on = false;
+  uint32_t groups = ~0u;  // bit k: group k is timed
   hipStream_t st = nullptr;
   std::vector<hipEvent_t> pool;
   std::vector<int> kid;
@@ -240,7 +241,7 @@ struct Profiler {
     return WL_OK;
   }
   void begin(int k) {
-    if (!on) return;
+    if (!on || !((groups >> k) & 1u)) return;
     if ((int)kid.size() == kPairs) flush();
     (void)hipEventRecord(pool[2 * kid.size()], st);
     cur = k;
@@ -306,8 +307,11 @@ struct SimBase {
   virtual wl_status adj_forces(const double dir[3], double weight, double* value) = 0;
   virtual wl_status adj_step(double tol, wl_step_stats* fst, wl_solve_stats* ast) = 0;
   virtual wl_status adj_body_grad(double* dR, double* dW) = 0;
-  virtual wl_status profile(int enable) {
-    if (enable) return prof.enable(stream);
+  virtual wl_status profile(uint32_t groups) {
+    if (groups) {
+      prof.groups = groups;
+      return prof.enable(stream);
+    }
     prof.flush();
     prof.on = false;
     return WL_OK;
@@ -372,7 +376,7 @@ struct Impl : SimBase {
   double *pgRed = nullptr, *pgScal = nullptr;
   PgBox bd{}, bcrop{};
   int64_t pgPc = 0;
-  int tiles[kMaxLevels][4] = {};  // tiled pass A: tiles_x, tiles_y, ntiles (0 = generic kernel)
+  int tiles[kMaxLevels][4] = {};  // tiled kernels: tiles_x, tiles_y, ntiles (0 = generic kernel), tile depth
   int lbot = 0;                   // first level of the single-workgroup bottom solve
   StdBox sbox[kMaxLevels] = {};   // per level: outside, coefficients are body-free
   // discrete adjoint
@@ -546,13 +550,20 @@ struct Impl : SimBase {
       g[l].s[1] = P.px;
       g[l].s[2] = P.px * P.py;
       nb[l] = blocks_for((int64_t)P.n[0] * P.n[1] * (D == 3 ? P.n[2] : 1));
-      tiles[l][0] = tiles[l][1] = tiles[l][2] = 0;
+      tiles[l][0] = tiles[l][1] = tiles[l][2] = tiles[l][3] = 0;
       if (D == 3 && P.n[0] >= 32 && P.n[1] >= 8 && (int64_t)P.n[0] * P.n[1] * P.n[2] >= (1 << 18)) {
-        const int tx = (P.n[0] + kTX - 1) / kTX, ty = (P.n[1] + kTY - 1) / kTY, tz = (P.n[2] + kTZ - 1) / kTZ;
+        const int tx = (P.n[0] + kTX - 1) / kTX, ty = (P.n[1] + kTY - 1) / kTY;
+        // march depth: kTZ planes, shortened on the smaller levels until there
+        // are about four tiles per compute unit (a march shorter than
+        // kTileMinZ planes would spend most of its loads on the pipeline fill)
+        int depth = kTZ;
+        while (depth > kTileMinZ && (int64_t)tx * ty * ((P.n[2] + depth - 1) / depth) < kTileTarget) depth /= 2;
+        const int tz = (P.n[2] + depth - 1) / depth;
         if ((int64_t)tx * ty * tz <= kMaxBlocks) {
           tiles[l][0] = tx;
           tiles[l][1] = ty;
           tiles[l][2] = tx * ty * tz;
+          tiles[l][3] = depth;
         }
       }
     }
@@ -740,11 +751,11 @@ struct Impl : SimBase {
         if (l == 0)
           WL_TIMED(kidA, (k_pcg_a_tile<T, 1, 0><<<ga, kTileThreads, 0, stream>>>(
                               g[l], v3(L[l]), iD[l], r[l], eo, en, q[l], red, k, rn, slot(kSlotSig0 + k),
-                              flags + l, tiles[l][0], tiles[l][1], tiles[l][2], sbox[l])));
+                              flags + l, tiles[l][0], tiles[l][1], tiles[l][2], tiles[l][3], sbox[l])));
         else
           WL_TIMED(kidA, (k_pcg_a_tile<T, 0, 0><<<ga, kTileThreads, 0, stream>>>(
                               g[l], v3(L[l]), iD[l], r[l], eo, en, q[l], red, k, rn, slot(kSlotSig0 + k),
-                              flags + l, tiles[l][0], tiles[l][1], tiles[l][2], sbox[l])));
+                              flags + l, tiles[l][0], tiles[l][1], tiles[l][2], tiles[l][3], sbox[l])));
       } else {
         ga = nb[l];
         if (l == 0)
@@ -769,11 +780,11 @@ struct Impl : SimBase {
         if (l == 0)
           WL_TIMED(kidB, (k_pcg_b_tile<T, 1><<<gbk, kTileThreads, 0, stream>>>(
                               g[l], v3(L[l]), iD[l], en, x[l], r[l], red, k, rn, slot(kSlotRho0 + k + 1),
-                              slot(kSlotRmax), wr, wm, flags + l, tiles[l][0], tiles[l][1], tiles[l][2], sbox[l])));
+                              slot(kSlotRmax), wr, wm, flags + l, tiles[l][0], tiles[l][1], tiles[l][2], tiles[l][3], sbox[l])));
         else
           WL_TIMED(kidB, (k_pcg_b_tile<T, 0><<<gbk, kTileThreads, 0, stream>>>(
                               g[l], v3(L[l]), iD[l], en, x[l], r[l], red, k, rn, slot(kSlotRho0 + k + 1),
-                              slot(kSlotRmax), wr, wm, flags + l, tiles[l][0], tiles[l][1], tiles[l][2], sbox[l])));
+                              slot(kSlotRmax), wr, wm, flags + l, tiles[l][0], tiles[l][1], tiles[l][2], tiles[l][3], sbox[l])));
       } else if (l == 0) {
         WL_TIMED(kidB, (k_pcg_b<T, D, 1><<<gb, kBlock, 0, stream>>>(nvec, b_iD, b_e, b_q, b_x, b_r, red, k, rn,
                                                                     slot(kSlotRho0 + k + 1), slot(kSlotRmax), wr,
@@ -793,9 +804,13 @@ struct Impl : SimBase {
   // coarse level with at most kBottomCells cells, if the levels below fit
   int bottom_level() const {
     for (int l = 1; l < nlev; ++l) {
-      int64_t cells = 1;
-      for (int a = 0; a < D; ++a) cells *= g[l].n[a];
-      if (cells <= kBottomCells) return (nlev - l <= kBottomMax) ? l : nlev;
+      int64_t cells = 1, padded = 1;
+      for (int a = 0; a < D; ++a) {
+        cells *= g[l].n[a];
+        padded *= g[l].n[a] + 2;
+      }
+      // the coarser levels are smaller still, so the first one decides
+      if (cells <= kBottomCells && padded <= bottom_lds_elems<T>()) return (nlev - l <= kBottomMax) ? l : nlev;
     }
     return nlev;
   }
@@ -832,7 +847,7 @@ struct Impl : SimBase {
       WL_TIMED(l == 0 ? WL_K_PROLONG : WL_K_COARSE,
                (k_prolong_tile<T><<<tiles[l][2], kTileThreads, 0, stream>>>(
                    g[l], g[l + 1], x[l + 1], v3(L[l]), iD[l], x[l], r[l], red, flags + l, tiles[l][0],
-                   tiles[l][1], tiles[l][2], sbox[l])));
+                   tiles[l][1], tiles[l][2], tiles[l][3], sbox[l])));
       set_mean_producer(tiles[l][2]);
     } else {
       WL_TIMED(l == 0 ? WL_K_PROLONG : WL_K_COARSE,
@@ -1664,7 +1679,12 @@ wl_status wl_get_time(wl_sim* sim, double* t, double* dt_next) {
 
 wl_status wl_profile(wl_sim* sim, int enable) {
   WL_SIM_CHECK(sim);
-  return sim->impl->profile(enable);
+  return sim->impl->profile(enable ? ~0u : 0u);
+}
+
+wl_status wl_profile_groups(wl_sim* sim, uint32_t groups) {
+  WL_SIM_CHECK(sim);
+  return sim->impl->profile(groups);
 }
 
 wl_status wl_profile_read(wl_sim* sim, int kernel, double* total_ms, int64_t* launches) {

@@ -167,8 +167,15 @@ class Simulation:
             out.append(tuple(nn)[:self.ndim])
         return out
 
-    def profile(self, enable: bool = True):
-        L.check(self.lib.wl_profile(self._h, 1 if enable else 0), "wl_profile")
+    def profile(self, enable: bool = True, groups=None):
+        """Per-launch event timing of every kernel group, or only of the named ones."""
+        if groups is None or not enable:
+            L.check(self.lib.wl_profile(self._h, 1 if enable else 0), "wl_profile")
+            return
+        mask = 0
+        for name in groups:
+            mask |= 1 << L.KERNELS.index(name)
+        L.check(self.lib.wl_profile_groups(self._h, mask), "wl_profile_groups")
 
     def profile_read(self) -> dict:
         out = {}
