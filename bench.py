@@ -252,6 +252,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="plate3d", choices=sorted(workloads().keys()))
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--solver-path", default="auto", choices=["auto", "tiles", "flat", "generic"],
+                    help="kernels of the large 3-D multigrid levels (same arithmetic)")
     ap.add_argument("--no-profile", action="store_true", help="skip per-kernel event timing")
     ap.add_argument("--adjoint", action="store_true",
                     help="run the rotating-cylinder gradient case instead (adjoint vs forward cost)")
@@ -284,7 +286,7 @@ def main():
     print("[bench] workload %s (%d cells), building initial field" % (w.name, w.cells), file=sys.stderr,
           flush=True)
     sim = Simulation(w.n, w.U, w.nu, body, periodic=w.periodic_mask(), convective_exit=w.convective_exit,
-                     prec="f32", tol=w.tol, itmax=32, device="cuda:0")
+                     prec="f32", tol=w.tol, itmax=32, device="cuda:0", solver_path=args.solver_path)
     sim.set_velocity(wlsynth.initial_velocity(w, seed=0))
     for k in range(args.warmup):
         sim.step()

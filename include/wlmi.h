@@ -78,6 +78,12 @@ typedef struct {
   int pcg_iters;         /* PCG smoothing iterations per level [6] */
   int learned_guess;     /* 1 -> plan the buffers of the learned initial guess (3-D only) */
   int adjoint;           /* 1 -> plan the buffers of the discrete adjoint (wl_adj_*) */
+  int solver_path;       /* kernels of the large 3-D multigrid levels (>= 2^18 cells):
+                            0 = automatic (fine level: z-marching tiles for PCG pass A and
+                            flat vector passes for pass B; tiles on the coarser large
+                            levels), 1 = tiles on every large level, 2 = as 0 but both fine
+                            passes flat, 3 = the generic grid-stride kernels only.  The
+                            arithmetic is the same; sums differ in rounding order only. [0] */
 } wl_sim_desc;
 
 typedef enum { WL_BODY_NONE = 0, WL_BODY_SPHERE = 1, WL_BODY_BOX = 2 } wl_body_kind;

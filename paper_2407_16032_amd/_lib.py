@@ -32,7 +32,8 @@ class SimDesc(C.Structure):
                 ("periodic_mask", C.c_uint), ("convective_exit", C.c_int), ("prec", C.c_int),
                 ("eps", C.c_double), ("dt0", C.c_double), ("dt_max", C.c_double),
                 ("cfl_nu_coef", C.c_double), ("mg_tol", C.c_double), ("mg_itmax", C.c_int),
-                ("pcg_iters", C.c_int), ("learned_guess", C.c_int), ("adjoint", C.c_int)]
+                ("pcg_iters", C.c_int), ("learned_guess", C.c_int), ("adjoint", C.c_int),
+                ("solver_path", C.c_int)]
 
 
 class BodyDesc(C.Structure):

@@ -102,12 +102,14 @@ __device__ __forceinline__ double block_max(double v) {
 // Sum / max of the n per-block partials a producer kernel wrote.
 template <int NT = kBlock>
 __device__ __forceinline__ double total_of(const double* part, int n) {
+  if (n == 1) return part[0];  // already reduced (uniform over the grid)
   double v = 0.0;
   for (int i = threadIdx.x; i < n; i += NT) v += part[i];
   return block_sum<NT>(v);
 }
 template <int NT = kBlock>
 __device__ __forceinline__ double max_of(const double* part, int n) {
+  if (n == 1) return part[0];
   double v = 0.0;
   for (int i = threadIdx.x; i < n; i += NT) v = fmax(v, part[i]);
   return block_max<NT>(v);

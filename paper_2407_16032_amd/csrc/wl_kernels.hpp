@@ -23,6 +23,9 @@ constexpr int kTX = 64, kTY = WL_TY, kTZ = WL_TZ, kTileThreads = kTX * kTY;
 #ifndef WL_PCG_PF
 #define WL_PCG_PF 2
 #endif
+#ifndef WL_PCGB_NOLDS
+#define WL_PCGB_NOLDS 0
+#endif
 constexpr int kPF = WL_PCG_PF;
 constexpr int kTileMinZ = 8;       // shortest march of a level's tiles
 constexpr int kTileTarget = 1024;  // tiles wanted per level (4 per compute unit)
@@ -1145,13 +1148,28 @@ __device__ __forceinline__ void pcg_b_march(const Grid3& g, const Vec3<T>& L, co
   const int hcol = G.hb ? G.hcol : col;
   const bool use_ring = G.ring && G.hb;
   // own column: e and L_z, x, r, iD of a plane (raw: used two iterations later)
+#if WL_PCGB_NOLDS
+  const int nxp = G.own ? G.opx : 0, nyp = G.own ? G.opy : 0;
+  const int nxm = G.own ? ((g.per[0] && G.i == 1) ? g.n[0] - 1 : -1) : 0;
+  const int nym = G.own ? ((g.per[1] && G.j == 1) ? (g.n[1] - 1) * s1 : -s1) : 0;
+  struct Raw {
+    T e, l, x, r, d, exm, exp, eym, eyp;
+  };
+#else
   struct Raw {
     T e, l, x, r, d;
   };
+#endif
   auto own = [&](int zz) -> Raw {
     const int zw = clamp_plane(g, min(zz, G.z1)), id = col + zw * s2;  // see pcg_a_march
     Raw v;
     v.e = e[id];
+#if WL_PCGB_NOLDS
+    v.exm = e[id + nxm];
+    v.exp = e[id + nxp];
+    v.eym = e[id + nym];
+    v.eyp = e[id + nyp];
+#endif
     v.l = FAST ? L_std<T>(g, B, 2, zw) : L.c[2][id];
     v.x = ld_stream(x + id);
     v.r = ld_stream(r + id);
@@ -1168,10 +1186,12 @@ __device__ __forceinline__ void pcg_b_march(const Grid3& g, const Vec3<T>& L, co
     a_new = own(z + kPF);
     h_new = ring(z + kPF);
     const T ec = cur.e, ep = nxt.e, L2c = cur.l, L2p = nxt.l, dc = cur.d;
+#if !WL_PCGB_NOLDS
     T(*P)[kTX + 2] = sE[z & 1];
     P[G.ty + 1][G.tx + 1] = ec;
     if (G.ring) P[G.sy][G.sx] = use_ring ? hr : T(0);
     __syncthreads();
+#endif
     if (G.own) {
       const int id = col + z * s2;
       T rr = cur.r;
@@ -1179,8 +1199,12 @@ __device__ __forceinline__ void pcg_b_march(const Grid3& g, const Vec3<T>& L, co
       if (!skip) {
         T qq = T(0);
         if (dc != T(0)) {
+#if WL_PCGB_NOLDS
+          const T xm = cur.exm, xp = cur.exp, ym = cur.eym, yp = cur.eyp;
+#else
           const T xm = P[G.ty + 1][G.tx], xp = P[G.ty + 1][G.tx + 2];
           const T ym = P[G.ty][G.tx + 1], yp = P[G.ty + 2][G.tx + 1];
+#endif
           const T Lxp = FAST ? Lxp0 : L.c[0][id + G.opx], Lxc = FAST ? Lxc0 : L.c[0][id];
           const T Lyp = FAST ? Lyp0 : L.c[1][id + G.opy], Lyc = FAST ? Lyc0 : L.c[1][id];
           qq = qq + Lxp * (xp - ec) - Lxc * (ec - xm);
@@ -1596,6 +1620,347 @@ __global__ void __launch_bounds__(kBottom) k_bottom(BottomLevels<T> bl) {
   for (int l = last - 1; l >= 0; --l) {
     bottom_prolong<T, D>(bl.lv[l], bl.lv[l + 1]);
     bottom_pcg<T, D>(bl.lv[l], bl.pcg_iters, sE);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Flat forms of the two PCG passes for a large 3-D level.  One thread per vector
+// of W = 16 bytes / sizeof(T) consecutive interior cells along x (the rows must
+// hold a whole number of vectors), consecutive threads along the rows, planes in
+// order, so at any moment the whole GPU works on a narrow, contiguous window of
+// each field.  The six neighbours come from the cache: the x neighbours are the
+// vector's own lanes plus one scalar at each end, the y and z neighbours are the
+// same-aligned vectors one row or one plane away, which neighbouring threads
+// have just loaded.  Every thread runs once (no loop), so the loads of many
+// short-lived waves overlap.  Each block leaves one FP64 partial per reduced
+// quantity; a single-block kernel sums them (k_finalize2) before the next pass
+// reads the total.
+// ---------------------------------------------------------------------------
+#ifndef WL_FLAT_THREADS
+#define WL_FLAT_THREADS 256
+#endif
+constexpr int kFlatThreads = WL_FLAT_THREADS;
+constexpr int kFinalizeThreads = 1024;
+constexpr int kFinalizeStage = 128;  // blocks of the first stage of a two-stage total
+
+// the thread's vector: first cell (i0, j, k), its field index, and whether it exists
+struct FlatVec {
+  int i0, j, k, id;
+  bool ok;
+};
+template <typename T>
+__device__ __forceinline__ FlatVec flat_vec(const Grid3& g) {
+  constexpr int W = Vec16<T>::W;
+  // 32-bit: the host takes this path only for fewer than 2^31 vectors
+  const unsigned vr = (unsigned)(g.n[0] / W), n1 = (unsigned)g.n[1];
+  const unsigned t = blockIdx.x * (unsigned)kFlatThreads + threadIdx.x;
+  const unsigned nv = vr * n1 * (unsigned)g.n[2];
+  FlatVec f;
+  f.ok = t < nv;
+  const unsigned tt = f.ok ? t : 0u;
+  const unsigned row = tt / vr;
+  f.i0 = 1 + (int)(tt - row * vr) * W;
+  const unsigned k0 = row / n1;
+  f.j = (int)(row - k0 * n1) + 1;
+  f.k = (int)k0 + 1;
+  f.id = f.i0 + f.j * g.s[1] + f.k * g.s[2];
+  return f;
+}
+
+// neighbour offsets of a vector (periodic wrap, else the ghost layer): x for the
+// first lane's -x and the last lane's +x neighbour, y and z for the whole vector
+template <int W>
+struct FlatNbr {
+  int xm, xp, ym, yp, zm, zp;
+  __device__ FlatNbr(const Grid3& g, const FlatVec& f) {
+    xm = (g.per[0] && f.i0 == 1) ? g.n[0] - 1 : -1;
+    xp = (g.per[0] && f.i0 + W - 1 == g.n[0]) ? -(g.n[0] - 1) : 1;
+    ym = (g.per[1] && f.j == 1) ? (g.n[1] - 1) * g.s[1] : -g.s[1];
+    yp = (g.per[1] && f.j == g.n[1]) ? -(g.n[1] - 1) * g.s[1] : g.s[1];
+    zm = (g.per[2] && f.k == 1) ? (g.n[2] - 1) * g.s[2] : -g.s[2];
+    zp = (g.per[2] && f.k == g.n[2]) ? -(g.n[2] - 1) * g.s[2] : g.s[2];
+  }
+};
+
+template <typename T>
+__device__ __forceinline__ typename Vec16<T>::type ldv(const T* p) {
+  return *reinterpret_cast<const typename Vec16<T>::type*>(p);
+}
+template <typename T>
+__device__ __forceinline__ void stv_stream(T* p, const typename Vec16<T>::type& v) {
+  constexpr int W = Vec16<T>::W;
+  const T* a = reinterpret_cast<const T*>(&v);
+  typedef T NV __attribute__((ext_vector_type(W)));
+  NV n;
+#pragma unroll
+  for (int w = 0; w < W; ++w) n[w] = a[w];
+#if WL_NT_MODE >= 1
+  __builtin_nontemporal_store(n, reinterpret_cast<NV*>(p));
+#else
+  *reinterpret_cast<NV*>(p) = n;
+#endif
+}
+
+// is the vector's stencil (with the margin the tiles use) outside the body box?
+template <int W>
+__device__ __forceinline__ bool flat_fast(const StdBox& B, const Grid3& g, const FlatVec& f) {
+  const int a[3] = {f.i0 - 2, f.j - 2, f.k - 2}, b[3] = {f.i0 + W + 1, f.j + 2, f.k + 2};
+  return std_miss<3>(B, g, a, b);
+}
+
+// Is the vector in the uniform bulk: body-free stencil, and every cell of it and
+// of its neighbours at least one cell away from a non-periodic boundary face?
+// Then every iD involved is 1/(-2 D Lstd) and every face coefficient Lstd.
+template <int W>
+__device__ __forceinline__ bool flat_uniform(const StdBox& B, const Grid3& g, const FlatVec& f) {
+  const bool ix = g.per[0] || (f.i0 >= 3 && f.i0 + W - 1 <= g.n[0] - 2);
+  const bool iy = g.per[1] || (f.j >= 3 && f.j <= g.n[1] - 2);
+  const bool iz = g.per[2] || (f.k >= 3 && f.k <= g.n[2] - 2);
+  return ix && iy && iz && flat_fast<W>(B, g, f);
+}
+
+// face coefficients of lane w (the faces at the cell and at its + neighbours)
+template <typename T, int W>
+__device__ __forceinline__ void flat_coef(const Grid3& g, const StdBox& B, const Vec3<T>& L, const FlatVec& f,
+                                          const FlatNbr<W>& o, bool uni, bool fast, int w, T& Lxp, T& Lxc, T& Lyp,
+                                          T& Lyc, T& Lzp, T& Lzc) {
+  if (uni) {
+    Lxp = Lxc = Lyp = Lyc = Lzp = Lzc = T(B.Lstd);
+    return;
+  }
+  const int i = f.i0 + w, cid = f.id + w;
+  if (fast) {
+    Lxp = L_std<T>(g, B, 0, i + 1);
+    Lxc = L_std<T>(g, B, 0, i);
+    Lyp = L_std<T>(g, B, 1, f.j + 1);
+    Lyc = L_std<T>(g, B, 1, f.j);
+    Lzp = L_std<T>(g, B, 2, f.k + 1);
+    Lzc = L_std<T>(g, B, 2, f.k);
+  } else {
+    const int opx = (g.per[0] && i == g.n[0]) ? -(g.n[0] - 1) : 1;
+    Lxp = L.c[0][cid + opx];
+    Lxc = L.c[0][cid];
+    Lyp = L.c[1][cid + o.yp];
+    Lyc = L.c[1][cid];
+    Lzp = L.c[2][cid + o.zp];
+    Lzc = L.c[2][cid];
+  }
+}
+
+// PCG pass A, flat form (arithmetic of k_pcg_a_tile with STOREQ = 0): e_new of
+// the vector and of its neighbours from r, e_old (and iD), sigma and rho_0 partials.
+template <typename T>
+__global__ void __launch_bounds__(kFlatThreads) k_pcg_a_flat(Grid3 g, Vec3<T> L, const T* iD, const T* r,
+                                                             const T* eo, T* en, double* red, int k, RedN rn,
+                                                             double* part_sig, double* part_rho0, int* flag,
+                                                             StdBox B) {
+  typedef typename Vec16<T>::type V;
+  constexpr int W = Vec16<T>::W;
+  if (*flag) return;
+  T beta, mean;
+  if (!pcg_a_scalars<T, kFlatThreads>(red, k, rn, flag, beta, mean)) return;
+  const FlatVec f = flat_vec<T>(g);
+  double sig = 0.0, rho0 = 0.0;
+  if (f.ok) {
+    const FlatNbr<W> o(g, f);
+    const int id = f.id;
+    const bool fast = flat_fast<W>(B, g, f);
+    // r and e_old of the vector, its y/z neighbour vectors and its two x neighbours
+    const V rc = ldv(r + id), ry0 = ldv(r + id + o.ym), ry1 = ldv(r + id + o.yp), rz0 = ldv(r + id + o.zm),
+            rz1 = ldv(r + id + o.zp);
+    const V ec_ = ldv(eo + id), ey0 = ldv(eo + id + o.ym), ey1 = ldv(eo + id + o.yp), ez0 = ldv(eo + id + o.zm),
+            ez1 = ldv(eo + id + o.zp);
+    const T rx0 = r[id + o.xm], rx1 = r[id + W - 1 + o.xp], ex0 = eo[id + o.xm], ex1 = eo[id + W - 1 + o.xp];
+    const T* R0 = reinterpret_cast<const T*>(&rc);
+    const T* E0 = reinterpret_cast<const T*>(&ec_);
+    const T *RY0 = reinterpret_cast<const T*>(&ry0), *RY1 = reinterpret_cast<const T*>(&ry1);
+    const T *RZ0 = reinterpret_cast<const T*>(&rz0), *RZ1 = reinterpret_cast<const T*>(&rz1);
+    const T *EY0 = reinterpret_cast<const T*>(&ey0), *EY1 = reinterpret_cast<const T*>(&ey1);
+    const T *EZ0 = reinterpret_cast<const T*>(&ez0), *EZ1 = reinterpret_cast<const T*>(&ez1);
+    auto eps = [&](T d, T rv, T ev) -> T { return (k > 0) ? d * rv + beta * ev : d * (rv - mean); };
+    const StdDiag<T, 3> SD(B);
+    const bool uni = flat_uniform<W>(B, g, f);
+    // inverse diagonals: one constant in the uniform bulk, closed form off the
+    // body box, else loaded
+    T dc[W], dy0[W], dy1[W], dz0[W], dz1[W], dx0, dx1;
+    const int wx0 = (g.per[0] && f.i0 == 1) ? g.n[0] : f.i0 - 1;
+    const int wx1 = (g.per[0] && f.i0 + W - 1 == g.n[0]) ? 1 : f.i0 + W;
+    const int jm = (g.per[1] && f.j == 1) ? g.n[1] : f.j - 1, jp = (g.per[1] && f.j == g.n[1]) ? 1 : f.j + 1;
+    const int km = (g.per[2] && f.k == 1) ? g.n[2] : f.k - 1, kp = (g.per[2] && f.k == g.n[2]) ? 1 : f.k + 1;
+    if (uni) {
+#pragma unroll
+      for (int w = 0; w < W; ++w) dc[w] = dy0[w] = dy1[w] = dz0[w] = dz1[w] = SD.v[0];
+      dx0 = dx1 = SD.v[0];
+    } else if (fast) {
+#pragma unroll
+      for (int w = 0; w < W; ++w) {
+        dc[w] = SD.at(g, f.i0 + w, f.j, f.k);
+        dy0[w] = SD.at(g, f.i0 + w, jm, f.k);
+        dy1[w] = SD.at(g, f.i0 + w, jp, f.k);
+        dz0[w] = SD.at(g, f.i0 + w, f.j, km);
+        dz1[w] = SD.at(g, f.i0 + w, f.j, kp);
+      }
+      dx0 = SD.at(g, wx0, f.j, f.k);
+      dx1 = SD.at(g, wx1, f.j, f.k);
+    } else {
+#pragma unroll
+      for (int w = 0; w < W; ++w) {
+        dc[w] = iD[id + w];
+        dy0[w] = iD[id + w + o.ym];
+        dy1[w] = iD[id + w + o.yp];
+        dz0[w] = iD[id + w + o.zm];
+        dz1[w] = iD[id + w + o.zp];
+      }
+      dx0 = iD[id + o.xm];
+      dx1 = iD[id + W - 1 + o.xp];
+    }
+    T e_new[W];
+#pragma unroll
+    for (int w = 0; w < W; ++w) e_new[w] = eps(dc[w], R0[w], E0[w]);
+    const T ex_m = eps(dx0, rx0, ex0), ex_p = eps(dx1, rx1, ex1);
+#pragma unroll
+    for (int w = 0; w < W; ++w) {
+      const T ec = e_new[w];
+      T qq = T(0);
+      if (dc[w] != T(0)) {
+        const int i = f.i0 + w, cid = id + w;
+        const T xm = (w > 0) ? e_new[w - 1] : ex_m, xp = (w < W - 1) ? e_new[w + 1] : ex_p;
+        const T ym = eps(dy0[w], RY0[w], EY0[w]), yp = eps(dy1[w], RY1[w], EY1[w]);
+        const T zm = eps(dz0[w], RZ0[w], EZ0[w]), zp = eps(dz1[w], RZ1[w], EZ1[w]);
+        T Lxp, Lxc, Lyp, Lyc, Lzp, Lzc;
+        flat_coef<T, W>(g, B, L, f, o, uni, fast, w, Lxp, Lxc, Lyp, Lyc, Lzp, Lzc);
+        qq = qq + Lxp * (xp - ec) - Lxc * (ec - xm);
+        qq = qq + Lyp * (yp - ec) - Lyc * (ec - ym);
+        qq = qq + Lzp * (zp - ec) - Lzc * (ec - zm);
+        if (k == 0) rho0 += double(R0[w] - mean) * double(ec);
+      }
+      sig += double(ec) * double(qq);
+    }
+    V ev;
+    T* EV = reinterpret_cast<T*>(&ev);
+#pragma unroll
+    for (int w = 0; w < W; ++w) EV[w] = e_new[w];
+    stv_stream<T>(en + id, ev);
+  }
+  sig = block_sum<kFlatThreads>(sig);
+  if (threadIdx.x == 0) part_sig[blockIdx.x] = sig;
+  if (k == 0) {
+    rho0 = block_sum<kFlatThreads>(rho0);
+    if (threadIdx.x == 0) part_rho0[blockIdx.x] = rho0;
+  }
+}
+
+// PCG pass B, flat form (arithmetic of k_pcg_b_tile): q = A e from e and its
+// neighbours, x += alpha e, r -= alpha q, partials of rho_{k+1} and max|r|.
+template <typename T>
+__global__ void __launch_bounds__(kFlatThreads) k_pcg_b_flat(Grid3 g, Vec3<T> L, const T* iD, const T* e, T* x,
+                                                             T* r, double* red, int k, RedN rn,
+                                                             double* part_rho_next, double* part_max, int want_rho,
+                                                             int want_max, int* flag, StdBox B) {
+  typedef typename Vec16<T>::type V;
+  constexpr int W = Vec16<T>::W;
+  bool skip = (*flag) != 0;
+  T alpha = T(0);
+  const T mean = (k == 0) ? T(residual_mean<kFlatThreads>(red, rn.mean)) : T(0);
+  if (!skip) {
+    const double sig = total_of<kFlatThreads>(red + (size_t)(kSlotSig0 + k) * kMaxBlocks, rn.sig);
+    if (fabs(sig) < 1e-300) {
+      skip = true;
+      if (blockIdx.x == 0 && threadIdx.x == 0) *flag = 1;
+    } else {
+      alpha = T(total_of<kFlatThreads>(red + (size_t)(kSlotRho0 + k) * kMaxBlocks, rn.rho) / sig);
+    }
+  }
+  if (skip && !want_max && mean == T(0)) return;  // grid-uniform
+  const FlatVec f = flat_vec<T>(g);
+  double rho = 0.0, mx = 0.0;
+  if (f.ok) {
+    const FlatNbr<W> o(g, f);
+    const int id = f.id;
+    const bool fast = flat_fast<W>(B, g, f);
+    const V ec_ = ldv(e + id), ey0 = ldv(e + id + o.ym), ey1 = ldv(e + id + o.yp), ez0 = ldv(e + id + o.zm),
+            ez1 = ldv(e + id + o.zp);
+    const T ex0 = e[id + o.xm], ex1 = e[id + W - 1 + o.xp];
+    const V xv = ldv(x + id), rv = ldv(r + id);
+    const T* E0 = reinterpret_cast<const T*>(&ec_);
+    const T *EY0 = reinterpret_cast<const T*>(&ey0), *EY1 = reinterpret_cast<const T*>(&ey1);
+    const T *EZ0 = reinterpret_cast<const T*>(&ez0), *EZ1 = reinterpret_cast<const T*>(&ez1);
+    const T* X0 = reinterpret_cast<const T*>(&xv);
+    const T* R0 = reinterpret_cast<const T*>(&rv);
+    const StdDiag<T, 3> SD(B);
+    const bool uni = flat_uniform<W>(B, g, f);
+    V xo, ro;
+    T* XO = reinterpret_cast<T*>(&xo);
+    T* RO = reinterpret_cast<T*>(&ro);
+#pragma unroll
+    for (int w = 0; w < W; ++w) {
+      const int i = f.i0 + w, cid = id + w;
+      const T ec = E0[w];
+      const T dc = uni ? SD.v[0] : fast ? SD.at(g, i, f.j, f.k) : iD[cid];
+      T rr = R0[w];
+      if (mean != T(0) && dc != T(0)) rr = rr - mean;
+      XO[w] = X0[w];
+      if (!skip) {
+        T qq = T(0);
+        if (dc != T(0)) {
+          const T xm = (w > 0) ? E0[w - 1] : ex0, xp = (w < W - 1) ? E0[w + 1] : ex1;
+          T Lxp, Lxc, Lyp, Lyc, Lzp, Lzc;
+          flat_coef<T, W>(g, B, L, f, o, uni, fast, w, Lxp, Lxc, Lyp, Lyc, Lzp, Lzc);
+          qq = qq + Lxp * (xp - ec) - Lxc * (ec - xm);
+          qq = qq + Lyp * (EY1[w] - ec) - Lyc * (ec - EY0[w]);
+          qq = qq + Lzp * (EZ1[w] - ec) - Lzc * (ec - EZ0[w]);
+        }
+        XO[w] = X0[w] + alpha * ec;
+        rr = rr - alpha * qq;
+      }
+      RO[w] = rr;
+      rho += double(rr) * (double(dc) * double(rr));
+      mx = fmax(mx, fabs(double(rr)));
+    }
+    if (!skip) stv_stream<T>(x + id, xo);
+    if (!skip || mean != T(0)) stv_stream<T>(r + id, ro);
+  }
+  if ((want_rho && !skip) || want_max) {
+    // one exchange for both: the sum of rho and the max of |r|
+    __shared__ double shr[kFlatThreads / 64], shm[kFlatThreads / 64];
+    rho = wave_sum(rho);
+    mx = wave_max(mx);
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    if (lane == 0) {
+      shr[wv] = rho;
+      shm[wv] = mx;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double sr = shr[0], sm = shm[0];
+#pragma unroll
+      for (int i = 1; i < kFlatThreads / 64; ++i) {
+        sr += shr[i];
+        sm = fmax(sm, shm[i]);
+      }
+      if (want_rho && !skip) part_rho_next[blockIdx.x] = sr;
+      if (want_max) part_max[blockIdx.x] = sm;
+    }
+  }
+}
+
+// out_a[b] = sum (or max, a_max) of block b's share of a[0..n), out_b[b] likewise
+// for b; either array may be NULL.  One block gives the total; G blocks leave G
+// partials.  Fixed order, so repeated runs agree bitwise.
+__global__ void __launch_bounds__(kFinalizeThreads) k_finalize2(const double* a, int a_max, const double* b,
+                                                                int b_max, int n, double* out_a, double* out_b) {
+  const int chunk = (n + gridDim.x - 1) / gridDim.x;
+  const int lo = blockIdx.x * chunk, hi = min(n, lo + chunk);
+  double sa = 0.0, sb = 0.0;
+  for (int i = lo + threadIdx.x; i < hi; i += kFinalizeThreads) {
+    if (a) sa = a_max ? fmax(sa, a[i]) : sa + a[i];
+    if (b) sb = b_max ? fmax(sb, b[i]) : sb + b[i];
+  }
+  if (a) sa = a_max ? block_max<kFinalizeThreads>(sa) : block_sum<kFinalizeThreads>(sa);
+  if (b) sb = b_max ? block_max<kFinalizeThreads>(sb) : block_sum<kFinalizeThreads>(sb);
+  if (threadIdx.x == 0) {
+    if (a) out_a[blockIdx.x] = sa;
+    if (b) out_b[blockIdx.x] = sb;
   }
 }
 

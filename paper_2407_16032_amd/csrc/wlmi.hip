@@ -85,6 +85,7 @@ wl_status validate_and_default(const wl_sim_desc* in, wl_sim_desc* d) {
   if (!(d->eps > 0.0) || !(d->dt0 > 0.0) || !(d->dt_max > 0.0) || !(d->mg_tol > 0.0) || d->mg_itmax < 1)
     return fail(WL_ERR_INVALID_ARG, "eps, dt0, dt_max, mg_tol must be > 0 and mg_itmax >= 1");
   if (d->pcg_iters < 1 || d->pcg_iters > kMaxPcg) return fail(WL_ERR_INVALID_ARG, "pcg_iters must be in [1, 15]");
+  if (d->solver_path < 0 || d->solver_path > 3) return fail(WL_ERR_INVALID_ARG, "solver_path must be in [0, 3]");
   if (d->convective_exit) {
     if (d->periodic_mask & 1u) return fail(WL_ERR_INVALID_ARG, "convective exit needs a non-periodic x axis");
     if (d->U[0] == 0.0) return fail(WL_ERR_INVALID_ARG, "convective exit needs U[0] != 0");
@@ -147,6 +148,17 @@ PgSizes pg_sizes(const Plan& P) {
 // the adjoint right-hand side
 constexpr int kAdjFields(int D) { return 8 * D + D * D + 4; }
 
+// Blocks of the flat PCG passes on the fine level, or 0 if it does not take them:
+// the solver path allows them, 3-D, at least 2^18 cells, and rows holding a whole
+// number of 16-byte vectors.
+int64_t flat_blocks(const wl_sim_desc& d, const LevelPlan& L, size_t esize) {
+  const int W = (int)(16 / esize);
+  if (d.ndim != 3 || L.n[0] % W != 0 || (d.solver_path != 0 && d.solver_path != 2)) return 0;
+  const int64_t cells = (int64_t)L.n[0] * L.n[1] * L.n[2];
+  if (cells < (1 << 18)) return 0;
+  return (cells / W + kFlatThreads - 1) / kFlatThreads;
+}
+
 Plan make_plan(const wl_sim_desc& d, bool has_body) {
   Plan P;
   P.ndim = d.ndim;
@@ -181,6 +193,10 @@ Plan make_plan(const wl_sim_desc& d, bool has_body) {
   b += align256((size_t)kNumSlots * kMaxBlocks * sizeof(double));
   b += align256(kNumScal * sizeof(double));
   b += align256(kMaxLevels * sizeof(int));
+  {
+    const int64_t nf = flat_blocks(d, P.lev[0], P.esize);  // flat-pass partials and their first stage
+    if (nf > 0) b += align256((size_t)(4 * nf + 2 * kFinalizeStage) * sizeof(double));
+  }
   if (d.adjoint) b += (size_t)kAdjFields(D) * f0;
   if (d.learned_guess && d.ndim == 3) {
     const PgSizes S = pg_sizes(P);
@@ -376,6 +392,10 @@ struct Impl : SimBase {
   double *pgRed = nullptr, *pgScal = nullptr;
   PgBox bd{}, bcrop{};
   int64_t pgPc = 0;
+  int64_t nflat = 0;       // blocks of the flat fine-level PCG passes (0: tiles or generic kernels)
+  double* wide = nullptr;  // their partials: sigma, rho_0, rho_{k+1}, max|r| (nflat each), then
+                           // 2 x kFinalizeStage first-stage sums
+  bool flat_a = false;     // pass A flat too (else tiled) when nflat > 0
   int tiles[kMaxLevels][4] = {};  // tiled kernels: tiles_x, tiles_y, ntiles (0 = generic kernel), tile depth
   int lbot = 0;                   // first level of the single-workgroup bottom solve
   StdBox sbox[kMaxLevels] = {};   // per level: outside, coefficients are body-free
@@ -446,6 +466,8 @@ struct Impl : SimBase {
     red = (double*)take((size_t)kNumSlots * kMaxBlocks * sizeof(double));
     scal = (double*)take(kNumScal * sizeof(double));
     flags = (int*)take(kMaxLevels * sizeof(int));
+    nflat = flat_blocks(desc, plan.lev[0], sizeof(T));
+    if (nflat > 0) wide = (double*)take((size_t)(4 * nflat + 2 * kFinalizeStage) * sizeof(double));
     adj_on = desc.adjoint != 0;
     if (adj_on) {
       for (int k = 0; k < D; ++k) au[0][k] = field(0);
@@ -551,7 +573,8 @@ struct Impl : SimBase {
       g[l].s[2] = P.px * P.py;
       nb[l] = blocks_for((int64_t)P.n[0] * P.n[1] * (D == 3 ? P.n[2] : 1));
       tiles[l][0] = tiles[l][1] = tiles[l][2] = tiles[l][3] = 0;
-      if (D == 3 && P.n[0] >= 32 && P.n[1] >= 8 && (int64_t)P.n[0] * P.n[1] * P.n[2] >= (1 << 18)) {
+      if (D == 3 && desc.solver_path != 3 && P.n[0] >= 32 && P.n[1] >= 8 &&
+          (int64_t)P.n[0] * P.n[1] * P.n[2] >= (1 << 18)) {
         const int tx = (P.n[0] + kTX - 1) / kTX, ty = (P.n[1] + kTY - 1) / kTY;
         // march depth: kTZ planes, shortened on the smaller levels until there
         // are about four tiles per compute unit (a march shorter than
@@ -567,6 +590,8 @@ struct Impl : SimBase {
         }
       }
     }
+    // automatic path: pass B flat on the fine level, pass A tiled when the level has tiles
+    flat_a = nflat > 0 && (desc.solver_path == 2 || tiles[0][2] == 0);
     nb_face = blocks_for((int64_t)(g[0].n[0] + 2) * (g[0].n[1] + 2) * (D == 3 ? g[0].n[2] + 2 : 1));
     planes.count = 0;
     int maxarea = 1;
@@ -734,6 +759,39 @@ struct Impl : SimBase {
 
   void set_mean_producer(int grid) { slot_n[kSlotSumR] = slot_n[kSlotCnt] = grid; }
 
+  // Sum (or max) a slot's partials into its first entry when a large grid left
+  // them: each block of the consumer would otherwise re-add all of them.
+  static constexpr int kCollapseMin = 2048;
+  // Totals of nflat-sized partial arrays into slot sa / sb (sb < 0: none): in two
+  // stages when there are many (a single block would wait on each load in turn).
+  void reduce_wide(const double* a, int a_max, const double* b, int b_max, int sa, int sb) {
+    const int n = (int)nflat;
+    double* out_b = sb >= 0 ? slot(sb) : nullptr;
+    if (n > 4 * kFinalizeThreads) {
+      double* ta = wide + 4 * nflat;
+      double* tb = ta + kFinalizeStage;
+      WL_TIMED(WL_K_REDUCE, (k_finalize2<<<kFinalizeStage, kFinalizeThreads, 0, stream>>>(
+                                a, a_max, sb >= 0 ? b : nullptr, b_max, n, ta, tb)));
+      WL_TIMED(WL_K_REDUCE, (k_finalize2<<<1, kFinalizeThreads, 0, stream>>>(ta, a_max, sb >= 0 ? tb : nullptr, b_max,
+                                                                             kFinalizeStage, slot(sa), out_b)));
+    } else {
+      WL_TIMED(WL_K_REDUCE, (k_finalize2<<<1, kFinalizeThreads, 0, stream>>>(a, a_max, sb >= 0 ? b : nullptr, b_max, n,
+                                                                             slot(sa), out_b)));
+    }
+    slot_n[sa] = 1;
+    if (sb >= 0) slot_n[sb] = 1;
+  }
+
+  void collapse(int sa, int a_max, int sb, int b_max) {
+    const int n = slot_n[sa];
+    if (n <= kCollapseMin) return;
+    WL_TIMED(WL_K_REDUCE, (k_finalize2<<<1, kFinalizeThreads, 0, stream>>>(
+                              slot(sa), a_max, sb >= 0 ? slot(sb) : nullptr, b_max, n, slot(sa),
+                              sb >= 0 ? slot(sb) : nullptr)));
+    slot_n[sa] = 1;
+    if (sb >= 0) slot_n[sb] = 1;
+  }
+
   void pcg(int l, bool fine) {
     const int K = desc.pcg_iters;
     T* eo = e[l][0];
@@ -741,11 +799,17 @@ struct Impl : SimBase {
     const int64_t nvec = plan.lev[l].alloc / Vec16<T>::W;
     const int gb = blocks_for(nvec);
     const int kidA = l == 0 ? WL_K_PCG_A : WL_K_COARSE, kidB = l == 0 ? WL_K_PCG_B : WL_K_COARSE;
+    collapse(kSlotSumR, 0, kSlotCnt, 0);
     for (int k = 0; k < K; ++k) {
       const int wr = k < K - 1 ? 1 : 0, wm = (fine && k == K - 1) ? 1 : 0;
       RedN rn{slot_n[kSlotSumR], slot_n[kSlotRho0 + k], k > 0 ? slot_n[kSlotRho0 + k - 1] : 0, 0};
       int ga;
-      if (tiles[l][2] > 0) {
+      if (l == 0 && nflat > 0 && flat_a) {
+        const int nf = (int)nflat;
+        WL_TIMED(kidA, (k_pcg_a_flat<T><<<nf, kFlatThreads, 0, stream>>>(g[l], v3(L[l]), iD[l], r[l], eo, en, red, k,
+                                                                         rn, wide, wide + nf, flags + l, sbox[l])));
+        ga = 1;
+      } else if (tiles[l][2] > 0) {
         ga = tiles[l][2];
         // q is not stored: the tiled pass B recomputes it
         if (l == 0)
@@ -765,9 +829,14 @@ struct Impl : SimBase {
           WL_TIMED(kidA, (k_pcg_a<T, D, 0><<<ga, kBlock, 0, stream>>>(g[l], v3(L[l]), iD[l], r[l], eo, en, q[l],
                                                                       red, k, rn, slot(kSlotSig0 + k), flags + l)));
       }
-      slot_n[kSlotSig0 + k] = ga;
-      if (k == 0) slot_n[kSlotRho0] = ga;
-      rn.sig = ga;
+      if (l == 0 && nflat > 0 && flat_a) {
+        reduce_wide(wide, 0, wide + nflat, 0, kSlotSig0 + k, k == 0 ? kSlotRho0 : -1);
+      } else {
+        slot_n[kSlotSig0 + k] = ga;
+        if (k == 0) slot_n[kSlotRho0] = ga;
+        collapse(kSlotSig0 + k, 0, k == 0 ? kSlotRho0 : -1, 0);
+      }
+      rn.sig = slot_n[kSlotSig0 + k];
       rn.rho = slot_n[kSlotRho0 + k];
       T* b_iD = iD[l] - kFrontPad;
       T* b_e = en - kFrontPad;
@@ -775,7 +844,17 @@ struct Impl : SimBase {
       T* b_x = x[l] - kFrontPad;
       T* b_r = r[l] - kFrontPad;
       int gbk = gb;
-      if (tiles[l][2] > 0) {
+      if (l == 0 && nflat > 0) {
+        const int nf = (int)nflat;
+        WL_TIMED(kidB, (k_pcg_b_flat<T><<<nf, kFlatThreads, 0, stream>>>(g[l], v3(L[l]), iD[l], en, x[l], r[l], red,
+                                                                         k, rn, wide + 2 * nf, wide + 3 * nf, wr, wm,
+                                                                         flags + l, sbox[l])));
+        if (wr)
+          reduce_wide(wide + 2 * nf, 0, wide + 3 * nf, 1, kSlotRho0 + k + 1, wm ? kSlotRmax : -1);
+        else if (wm)
+          reduce_wide(wide + 3 * nf, 1, nullptr, 0, kSlotRmax, -1);
+        gbk = 1;
+      } else if (tiles[l][2] > 0) {
         gbk = tiles[l][2];
         if (l == 0)
           WL_TIMED(kidB, (k_pcg_b_tile<T, 1><<<gbk, kTileThreads, 0, stream>>>(
@@ -794,8 +873,14 @@ struct Impl : SimBase {
                                                                     slot(kSlotRho0 + k + 1), slot(kSlotRmax), wr,
                                                                     wm, flags + l, g[l], sbox[l])));
       }
-      if (wr) slot_n[kSlotRho0 + k + 1] = gbk;
-      if (wm) slot_n[kSlotRmax] = gbk;
+      if (!(l == 0 && nflat > 0)) {
+        if (wr) slot_n[kSlotRho0 + k + 1] = gbk;
+        if (wm) slot_n[kSlotRmax] = gbk;
+        if (wr)
+          collapse(kSlotRho0 + k + 1, 0, wm ? kSlotRmax : -1, 1);
+        else if (wm)
+          collapse(kSlotRmax, 1, -1, 0);
+      }
       std::swap(eo, en);
     }
   }

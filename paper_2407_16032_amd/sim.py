@@ -43,7 +43,7 @@ class Simulation:
                  eps: float = 1.0, dt0: float = 0.25, dt_max: float = 10.0, cfl_nu: float = 5.0,
                  tol: float = 1e-6, itmax: int = 32, pcg_iters: int = 6, device="cuda:0",
                  stream: Optional[torch.cuda.Stream] = None, learned_guess: bool = False,
-                 adjoint: bool = False):
+                 adjoint: bool = False, solver_path: str = "auto"):
         self.lib = L.load()
         nd = len(n)
         d = L.SimDesc()
@@ -59,6 +59,7 @@ class Simulation:
         d.mg_tol, d.mg_itmax, d.pcg_iters = tol, itmax, pcg_iters
         d.learned_guess = 1 if learned_guess else 0
         d.adjoint = 1 if adjoint else 0
+        d.solver_path = {"auto": 0, "tiles": 1, "flat": 2, "generic": 3}[solver_path]
         self.desc = d
         self.bdesc = _body_desc(body)
         self.ndim = nd

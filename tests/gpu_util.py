@@ -28,7 +28,7 @@ def small_cases():
             "sphere3d_tiled": sphere_t, "tgv3d_tiled": tgv_t}
 
 
-def make_pair(w, prec, tol, itmax=200, seed=0):
+def make_pair(w, prec, tol, itmax=200, seed=0, solver_path="auto"):
     from paper_2407_16032_amd import Simulation
     u0 = wlsynth.initial_velocity(w, seed=seed)
     body = w.body if w.body.kind != "none" else None
@@ -36,7 +36,7 @@ def make_pair(w, prec, tol, itmax=200, seed=0):
                      convective_exit=w.convective_exit, tol=min(tol, 1e-12), itmax=itmax)
     ref.set_velocity(u0)
     gpu = Simulation(w.n, w.U, w.nu, body, periodic=w.periodic_mask(), convective_exit=w.convective_exit,
-                     prec=prec, tol=tol, itmax=itmax, device="cuda:0")
+                     prec=prec, tol=tol, itmax=itmax, device="cuda:0", solver_path=solver_path)
     gpu.set_velocity(u0)
     return ref, gpu
 

@@ -164,6 +164,50 @@ def test_one_step_fp32(name):
     gpu.close()
 
 
+@pytest.mark.parametrize("name", ["sphere3d_tiled", "tgv3d_tiled"])
+@pytest.mark.parametrize("path", ["tiles", "flat", "generic"])
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_one_step_other_solver_paths(name, path, prec):
+    """By default the 64^3 cases run PCG pass A in z-marching tiles and pass B in
+    flat vectors on the fine level (the tests above); here the fine level runs
+    tiles for both, flat vectors for both, or the generic kernels."""
+    _say("step", prec, name, path)
+    w = CASES[name]
+    ref, gpu = make_pair(w, prec, 1e-13 if prec == "f64" else 1e-6, solver_path=path)
+    ref.tol = 1e-13
+    ref.step()
+    gpu.step()
+    err = rel_l2(gpu.get("u"), ref.u, ref.grid)
+    _say("  rel-L2 u", err)
+    assert err <= (FP64_STEP if prec == "f64" else FP32_STEP)
+    gpu.close()
+
+
+def test_solver_paths_agree_on_a_large_grid():
+    """256 x 128 x 128 sphere wake in FP64: the fine level takes the flat passes
+    (automatic), the z-marching tiles or the generic kernels, and the first coarse
+    level (128 x 64 x 64) tiles or generic kernels; one step of each agrees to
+    the solver tolerance (sums differ only in rounding order)."""
+    from paper_2407_16032_amd import Simulation
+    w = wlsynth.sphere_3d()
+    u0 = wlsynth.initial_velocity(w)
+    out = {}
+    for path in ("auto", "tiles", "flat", "generic"):
+        _say("large grid FP64 step", path)
+        gpu = Simulation(w.n, w.U, w.nu, w.body, convective_exit=True, prec="f64", tol=1e-11, itmax=64,
+                         device="cuda:0", solver_path=path)
+        gpu.set_velocity(u0)
+        st = gpu.step()
+        assert st["converged"], st
+        out[path] = gpu.get("u")
+        gpu.close()
+    g = oracle.Grid(w.n)
+    for path in ("tiles", "flat", "generic"):
+        err = rel_l2(out[path], out["auto"], g)
+        _say("  rel-L2 u", path, "vs auto", err)
+        assert err <= 1e-10
+
+
 @pytest.mark.parametrize("name", ["circle2d", "sphere3d"])
 def test_ten_steps_fp32(name):
     _say("10 steps f32", name)
