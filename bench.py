@@ -36,7 +36,7 @@ def workloads():
 
 
 def kernel_bytes(name, ndim, cells, faces, esize, has_body, pcg_iters, box_cells=None, box_faces=None,
-                 tiled=False):
+                 tiled=False, flat=False):
     """Algorithmic bytes of one launch of the kernels as built: each field the pass
     needs is read once, each output written once.
 
@@ -44,15 +44,20 @@ def kernel_bytes(name, ndim, cells, faces, esize, has_body, pcg_iters, box_cells
     Coefficient fields (L, iD on cells; V, mu0, mu1 on faces) are only needed inside
     the body box (box_cells / box_faces): outside it the kernels evaluate their
     body-free closed form.  On tiled levels (3-D, large) pass A does not store q and
-    pass B recomputes it from e (pass B then needs L and iD in the box).
+    pass B recomputes it from e (pass B then needs L and iD in the box); the flat
+    form of the fine level (``flat``) moves the same fields, pass A in two launches.
     """
     n = ndim
     bc = cells if box_cells is None else box_cells
     bf = faces if box_faces is None else box_faces
     if name == "pcg_a":
-        # reads r, and e_old except in the first sweep; writes e_new (and q if not tiled); iD, L (n) in the box
+        # reads r, and e_old except in the first sweep; writes e_new (and q if not tiled); iD, L (n) in the
+        # box.  Flat form (two launches): this one is pointwise (iD in the box)
         fields = (1 + (pcg_iters - 1) / pcg_iters) + (1 if tiled else 2)
-        return (fields * cells + (1 + n) * bc) * esize
+        return (fields * cells + (1 if flat else 1 + n) * bc) * esize
+    if name == "pcg_a2":
+        # flat form, second launch: reads e_new; iD, L (n) in the box
+        return (cells + (1 + n) * bc) * esize
     if name == "pcg_b":
         if tiled:  # reads e, x, r; writes x, r; iD and L (n) in the box
             return (5 * cells + (1 + n) * bc) * esize
@@ -74,6 +79,14 @@ def kernel_bytes(name, ndim, cells, faces, esize, has_body, pcg_iters, box_cells
     if name == "cfl":
         return n * cells * esize
     return None
+
+
+def fine_level_flat(n, esize=4, solver_path="auto"):
+    """The fine level takes the flat passes when it is 3-D with >= 2^18 cells and
+    rows of whole 16-byte vectors, unless the solver path asks for tiles or the
+    generic kernels."""
+    return (len(n) == 3 and solver_path in ("auto", "flat") and n[0] % (16 // esize) == 0
+            and n[0] * n[1] * n[2] >= (1 << 18))
 
 
 def fine_level_tiled(n):
@@ -151,7 +164,7 @@ def measured_traffic(workload, kernel):
     path = os.path.join(ROOT, "profiles", "pmc_%s.md" % workload)
     if not os.path.exists(path):
         return None
-    key = {"pcg_a": "k_pcg_a_tile_fine", "pcg_b": "k_pcg_b_fine"}.get(kernel)
+    key = {"pcg_a": "k_pcg_a1_flat_fine", "pcg_a2": "k_pcg_a2_flat_fine", "pcg_b": "k_pcg_b_flat_fine"}.get(kernel)
     src, val = None, None
     with open(path) as f:
         for line in f:
@@ -298,10 +311,11 @@ def main():
     for N in w.n:
         faces *= N + 2
     bcells, bfaces = box_counts(sim, w.n)
-    tiled = fine_level_tiled(w.n)
+    flat = fine_level_flat(w.n, 4, args.solver_path)
+    tiled = flat or (args.solver_path != "generic" and fine_level_tiled(w.n))
 
     def launch_bytes(name):
-        return kernel_bytes(name, w.ndim, cells, faces, 4, body is not None, 6, bcells, bfaces, tiled)
+        return kernel_bytes(name, w.ndim, cells, faces, 4, body is not None, 6, bcells, bfaces, tiled, flat)
 
     # Breakdown: a few extra steps with an event pair around every launch (the
     # events cost a few per cent of the step, so these steps are not the timed ones)

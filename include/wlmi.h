@@ -79,10 +79,9 @@ typedef struct {
   int learned_guess;     /* 1 -> plan the buffers of the learned initial guess (3-D only) */
   int adjoint;           /* 1 -> plan the buffers of the discrete adjoint (wl_adj_*) */
   int solver_path;       /* kernels of the large 3-D multigrid levels (>= 2^18 cells):
-                            0 = automatic (fine level: z-marching tiles for PCG pass A and
-                            flat vector passes for pass B; tiles on the coarser large
-                            levels), 1 = tiles on every large level, 2 = as 0 but both fine
-                            passes flat, 3 = the generic grid-stride kernels only.  The
+                            0 = automatic (flat vector passes on the fine level, z-marching
+                            tiles on the coarser large levels), 1 = tiles on every large
+                            level, 2 = as 0, 3 = the generic grid-stride kernels only.  The
                             arithmetic is the same; sums differ in rounding order only. [0] */
 } wl_sim_desc;
 
@@ -325,7 +324,7 @@ enum {
   WL_K_BC = 4,       /* boundary conditions */
   WL_K_EXIT = 5,     /* convective exit plane */
   WL_K_DIVRES = 6,   /* divergence and initial residual */
-  WL_K_PCG_A = 7,    /* fine PCG pass A: search direction and A e */
+  WL_K_PCG_A = 7,    /* fine PCG pass A: search direction and A e (flat form: the direction only) */
   WL_K_PCG_B = 8,    /* fine PCG pass B: x and r update */
   WL_K_RESTRICT = 9, /* fine -> first coarse residual restriction */
   WL_K_PROLONG = 10, /* first coarse -> fine prolongation and correction */
@@ -337,7 +336,8 @@ enum {
   WL_K_PG_INFER = 16,/* learned guess: features, conv net, guess */
   WL_K_PG_TRAIN = 17,/* learned guess: snapshots, training steps */
   WL_K_ADJOINT = 18, /* transposes of the step's kernels (adjoint solves count as multigrid) */
-  WL_K_COUNT = 19
+  WL_K_PCG_A2 = 19,  /* fine PCG pass A, second launch of its flat form: sigma = e.Ae */
+  WL_K_COUNT = 20
 };
 
 /* Per-kernel timing with HIP events recorded around each launch on the sim's

@@ -132,7 +132,21 @@ constexpr double kMu0Cut = 1e-6;  // faces with mu0 below this are solid
 struct StdBox {
   int lo[3], hi[3];  // empty when lo[0] > hi[0]
   double Lstd;       // 1 on the fine level, times 2^(D-2) per coarsening
+  // iD of a cell with c non-periodic boundary faces, 1/(-(Lstd (2D - c))), in each
+  // precision (the host's correctly rounded division gives the device's value)
+  float iDf[4];
+  double iDd[4];
 };
+template <typename T>
+__device__ __forceinline__ T std_iD(const StdBox& B, int c);
+template <>
+__device__ __forceinline__ float std_iD<float>(const StdBox& B, int c) {
+  return B.iDf[c];
+}
+template <>
+__device__ __forceinline__ double std_iD<double>(const StdBox& B, int c) {
+  return B.iDd[c];
+}
 
 // Does the index range [a_k, b_k] per axis (may extend past the padded range) miss
 // the box?  On a periodic axis a range that leaves 1..N is taken as the whole axis.
@@ -177,7 +191,7 @@ struct StdDiag {
   T v[4];
   __device__ explicit StdDiag(const StdBox& B) {
 #pragma unroll
-    for (int c = 0; c < 4; ++c) v[c] = T(1) / (-(T(B.Lstd) * T(2 * D - c)));
+    for (int c = 0; c < 4; ++c) v[c] = std_iD<T>(B, c);
   }
   __device__ __forceinline__ T at(const Grid3& g, int i, int j, int k) const {
     const int I[3] = {i, j, k};
@@ -1651,34 +1665,43 @@ struct FlatVec {
 template <typename T>
 __device__ __forceinline__ FlatVec flat_vec(const Grid3& g) {
   constexpr int W = Vec16<T>::W;
-  // 32-bit: the host takes this path only for fewer than 2^31 vectors
-  const unsigned vr = (unsigned)(g.n[0] / W), n1 = (unsigned)g.n[1];
+  // grid: x = the blocks of one plane, y = the plane
+  const unsigned vr = (unsigned)(g.n[0] / W);
   const unsigned t = blockIdx.x * (unsigned)kFlatThreads + threadIdx.x;
-  const unsigned nv = vr * n1 * (unsigned)g.n[2];
   FlatVec f;
-  f.ok = t < nv;
+  f.ok = t < vr * (unsigned)g.n[1];
   const unsigned tt = f.ok ? t : 0u;
   const unsigned row = tt / vr;
   f.i0 = 1 + (int)(tt - row * vr) * W;
-  const unsigned k0 = row / n1;
-  f.j = (int)(row - k0 * n1) + 1;
-  f.k = (int)k0 + 1;
+  f.j = (int)row + 1;
+  f.k = (int)blockIdx.y + 1;
   f.id = f.i0 + f.j * g.s[1] + f.k * g.s[2];
   return f;
 }
+// linear block index of a flat launch (its partial's slot)
+__device__ __forceinline__ int flat_block() { return blockIdx.y * gridDim.x + blockIdx.x; }
 
 // neighbour offsets of a vector (periodic wrap, else the ghost layer): x for the
-// first lane's -x and the last lane's +x neighbour, y and z for the whole vector
-template <int W>
+// first lane's -x and the last lane's +x neighbour, y and z for the whole vector.
+// PER = false: no periodic axis, so the offsets are constants.
+template <int W, bool PER>
 struct FlatNbr {
   int xm, xp, ym, yp, zm, zp;
   __device__ FlatNbr(const Grid3& g, const FlatVec& f) {
-    xm = (g.per[0] && f.i0 == 1) ? g.n[0] - 1 : -1;
-    xp = (g.per[0] && f.i0 + W - 1 == g.n[0]) ? -(g.n[0] - 1) : 1;
-    ym = (g.per[1] && f.j == 1) ? (g.n[1] - 1) * g.s[1] : -g.s[1];
-    yp = (g.per[1] && f.j == g.n[1]) ? -(g.n[1] - 1) * g.s[1] : g.s[1];
-    zm = (g.per[2] && f.k == 1) ? (g.n[2] - 1) * g.s[2] : -g.s[2];
-    zp = (g.per[2] && f.k == g.n[2]) ? -(g.n[2] - 1) * g.s[2] : g.s[2];
+    xm = -1;
+    xp = 1;
+    ym = -g.s[1];
+    yp = g.s[1];
+    zm = -g.s[2];
+    zp = g.s[2];
+    if (PER) {
+      if (g.per[0] && f.i0 == 1) xm = g.n[0] - 1;
+      if (g.per[0] && f.i0 + W - 1 == g.n[0]) xp = -(g.n[0] - 1);
+      if (g.per[1] && f.j == 1) ym = (g.n[1] - 1) * g.s[1];
+      if (g.per[1] && f.j == g.n[1]) yp = -(g.n[1] - 1) * g.s[1];
+      if (g.per[2] && f.k == 1) zm = (g.n[2] - 1) * g.s[2];
+      if (g.per[2] && f.k == g.n[2]) zp = -(g.n[2] - 1) * g.s[2];
+    }
   }
 };
 
@@ -1708,151 +1731,182 @@ __device__ __forceinline__ bool flat_fast(const StdBox& B, const Grid3& g, const
   return std_miss<3>(B, g, a, b);
 }
 
-// Is the vector in the uniform bulk: body-free stencil, and every cell of it and
-// of its neighbours at least one cell away from a non-periodic boundary face?
-// Then every iD involved is 1/(-2 D Lstd) and every face coefficient Lstd.
-template <int W>
-__device__ __forceinline__ bool flat_uniform(const StdBox& B, const Grid3& g, const FlatVec& f) {
-  const bool ix = g.per[0] || (f.i0 >= 3 && f.i0 + W - 1 <= g.n[0] - 2);
-  const bool iy = g.per[1] || (f.j >= 3 && f.j <= g.n[1] - 2);
-  const bool iz = g.per[2] || (f.k >= 3 && f.k <= g.n[2] - 2);
-  return ix && iy && iz && flat_fast<W>(B, g, f);
-}
-
-// face coefficients of lane w (the faces at the cell and at its + neighbours)
-template <typename T, int W>
-__device__ __forceinline__ void flat_coef(const Grid3& g, const StdBox& B, const Vec3<T>& L, const FlatVec& f,
-                                          const FlatNbr<W>& o, bool uni, bool fast, int w, T& Lxp, T& Lxc, T& Lyp,
-                                          T& Lyc, T& Lzp, T& Lzc) {
-  if (uni) {
-    Lxp = Lxc = Lyp = Lyc = Lzp = Lzc = T(B.Lstd);
-    return;
-  }
-  const int i = f.i0 + w, cid = f.id + w;
-  if (fast) {
-    Lxp = L_std<T>(g, B, 0, i + 1);
-    Lxc = L_std<T>(g, B, 0, i);
-    Lyp = L_std<T>(g, B, 1, f.j + 1);
-    Lyc = L_std<T>(g, B, 1, f.j);
-    Lzp = L_std<T>(g, B, 2, f.k + 1);
-    Lzc = L_std<T>(g, B, 2, f.k);
-  } else {
-    const int opx = (g.per[0] && i == g.n[0]) ? -(g.n[0] - 1) : 1;
-    Lxp = L.c[0][cid + opx];
-    Lxc = L.c[0][cid];
-    Lyp = L.c[1][cid + o.yp];
-    Lyc = L.c[1][cid];
-    Lzp = L.c[2][cid + o.zp];
-    Lzc = L.c[2][cid];
-  }
-}
-
-// PCG pass A, flat form (arithmetic of k_pcg_a_tile with STOREQ = 0): e_new of
-// the vector and of its neighbours from r, e_old (and iD), sigma and rho_0 partials.
+// closed-form iD of a cell from the count of its non-periodic boundary faces
+// (a chain of selects on thresholds: an equality chain is turned into an indexed
+// table, which lives in scratch memory)
 template <typename T>
-__global__ void __launch_bounds__(kFlatThreads) k_pcg_a_flat(Grid3 g, Vec3<T> L, const T* iD, const T* r,
-                                                             const T* eo, T* en, double* red, int k, RedN rn,
-                                                             double* part_sig, double* part_rho0, int* flag,
-                                                             StdBox B) {
+__device__ __forceinline__ T std_iD_nb(const StdBox& B, int nb) {
+  T r = std_iD<T>(B, 0);
+  r = nb >= 1 ? std_iD<T>(B, 1) : r;
+  r = nb >= 2 ? std_iD<T>(B, 2) : r;
+  r = nb >= 3 ? std_iD<T>(B, 3) : r;
+  return r;
+}
+
+// Coefficients of lane w of a vector: the inverse diagonal of its cell and the
+// face coefficients at the cell and at its + neighbours.  Off the body box they
+// are the closed form, evaluated without branches: the boundary faces of
+// non-periodic axes carry 0 and a cell's iD depends on how many it has.  The
+// vectors start at x = 1 and rows hold whole vectors, so only the first lane can
+// touch the -x boundary and only the last the +x one; the y and z terms are the
+// same for the whole vector.  Inside the box the coefficients are loaded.
+template <typename T, int W, bool PER>
+struct FlatStd {
+  T Ls, Lyc, Lyp, Lzc, Lzp;
+  int nbyz;
+  bool x0, x1;
+  __device__ __forceinline__ FlatStd(const Grid3& g, const StdBox& B, const FlatVec& f) {
+    const bool px = PER && g.per[0], py = PER && g.per[1], pz = PER && g.per[2];
+    Ls = T(B.Lstd);
+    x0 = !px && f.i0 == 1;
+    x1 = !px && f.i0 + W - 1 == g.n[0];
+    const bool y0 = !py && f.j == 1, y1 = !py && f.j == g.n[1];
+    const bool z0 = !pz && f.k == 1, z1 = !pz && f.k == g.n[2];
+    nbyz = int(y0) + int(y1) + int(z0) + int(z1);
+    Lyc = y0 ? T(0) : Ls;
+    Lyp = y1 ? T(0) : Ls;
+    Lzc = z0 ? T(0) : Ls;
+    Lzp = z1 ? T(0) : Ls;
+  }
+  __device__ __forceinline__ bool xlo(int w) const { return w == 0 && x0; }
+  __device__ __forceinline__ bool xhi(int w) const { return w == W - 1 && x1; }
+  __device__ __forceinline__ T d(const StdBox& B, int w) const {
+    return std_iD_nb<T>(B, nbyz + int(xlo(w)) + int(xhi(w)));
+  }
+};
+
+// the coefficients of a vector near the body, loaded as whole vectors
+template <typename T, int W, bool PER>
+struct FlatLoaded {
+  typename Vec16<T>::type d, lx, ly0, ly1, lz0, lz1;
+  T lxe;  // x face past the last lane
+  __device__ __forceinline__ FlatLoaded(const Grid3& g, const Vec3<T>& L, const T* iD, const FlatVec& f,
+                                        const FlatNbr<W, PER>& o) {
+    const int id = f.id;
+    d = ldv(iD + id);
+    lx = ldv(L.c[0] + id);
+    lxe = L.c[0][id + W - 1 + ((PER && g.per[0] && f.i0 + W - 1 == g.n[0]) ? -(g.n[0] - 1) : 1)];
+    ly0 = ldv(L.c[1] + id);
+    ly1 = ldv(L.c[1] + id + o.yp);
+    lz0 = ldv(L.c[2] + id);
+    lz1 = ldv(L.c[2] + id + o.zp);
+  }
+};
+
+template <typename T, int W, bool PER>
+struct FlatCoef {
+  T d, Lxp, Lxc, Lyp, Lyc, Lzp, Lzc;
+  // closed form
+  __device__ __forceinline__ FlatCoef(const FlatStd<T, W, PER>& S, const StdBox& B, int w) {
+    d = S.d(B, w);
+    Lxc = S.xlo(w) ? T(0) : S.Ls;
+    Lxp = S.xhi(w) ? T(0) : S.Ls;
+    Lyc = S.Lyc;
+    Lyp = S.Lyp;
+    Lzc = S.Lzc;
+    Lzp = S.Lzp;
+  }
+  // loaded
+  __device__ __forceinline__ FlatCoef(const FlatLoaded<T, W, PER>& C, int w) {
+    const T* D = reinterpret_cast<const T*>(&C.d);
+    const T* LX = reinterpret_cast<const T*>(&C.lx);
+    d = D[w];
+    Lxc = LX[w];
+    Lxp = (w < W - 1) ? LX[w + 1] : C.lxe;
+    Lyc = reinterpret_cast<const T*>(&C.ly0)[w];
+    Lyp = reinterpret_cast<const T*>(&C.ly1)[w];
+    Lzc = reinterpret_cast<const T*>(&C.lz0)[w];
+    Lzp = reinterpret_cast<const T*>(&C.lz1)[w];
+  }
+};
+
+// PCG pass A, flat form, in two launches (arithmetic of k_pcg_a_tile with
+// STOREQ = 0).  A1 is pointwise: e_new = iD r + beta e_old (sweep 0: iD (r - m),
+// without reading e_old) and the rho_0 partial; A2 reads e_new with its
+// neighbours and leaves the sigma = e.Ae partial.  Together they move one field
+// more than the tiled pass, but both stream at the flat kernels' rate.
+template <typename T, bool PER>
+__global__ void __launch_bounds__(kFlatThreads) k_pcg_a1_flat(Grid3 g, const T* iD, const T* r, const T* eo, T* en,
+                                                              double* red, int k, RedN rn, double* part_rho0,
+                                                              int* flag, StdBox B) {
   typedef typename Vec16<T>::type V;
   constexpr int W = Vec16<T>::W;
   if (*flag) return;
   T beta, mean;
   if (!pcg_a_scalars<T, kFlatThreads>(red, k, rn, flag, beta, mean)) return;
   const FlatVec f = flat_vec<T>(g);
-  double sig = 0.0, rho0 = 0.0;
+  double rho0 = 0.0;
   if (f.ok) {
-    const FlatNbr<W> o(g, f);
     const int id = f.id;
+    const V rv = ldv(r + id);
+    V ev;
+    if (k > 0) ev = ldv(eo + id);  // grid-uniform branch
+    const T* R0 = reinterpret_cast<const T*>(&rv);
+    const T* E0 = reinterpret_cast<const T*>(&ev);
     const bool fast = flat_fast<W>(B, g, f);
-    // r and e_old of the vector, its y/z neighbour vectors and its two x neighbours
-    const V rc = ldv(r + id), ry0 = ldv(r + id + o.ym), ry1 = ldv(r + id + o.yp), rz0 = ldv(r + id + o.zm),
-            rz1 = ldv(r + id + o.zp);
-    const V ec_ = ldv(eo + id), ey0 = ldv(eo + id + o.ym), ey1 = ldv(eo + id + o.yp), ez0 = ldv(eo + id + o.zm),
-            ez1 = ldv(eo + id + o.zp);
-    const T rx0 = r[id + o.xm], rx1 = r[id + W - 1 + o.xp], ex0 = eo[id + o.xm], ex1 = eo[id + W - 1 + o.xp];
-    const T* R0 = reinterpret_cast<const T*>(&rc);
-    const T* E0 = reinterpret_cast<const T*>(&ec_);
-    const T *RY0 = reinterpret_cast<const T*>(&ry0), *RY1 = reinterpret_cast<const T*>(&ry1);
-    const T *RZ0 = reinterpret_cast<const T*>(&rz0), *RZ1 = reinterpret_cast<const T*>(&rz1);
-    const T *EY0 = reinterpret_cast<const T*>(&ey0), *EY1 = reinterpret_cast<const T*>(&ey1);
-    const T *EZ0 = reinterpret_cast<const T*>(&ez0), *EZ1 = reinterpret_cast<const T*>(&ez1);
-    auto eps = [&](T d, T rv, T ev) -> T { return (k > 0) ? d * rv + beta * ev : d * (rv - mean); };
-    const StdDiag<T, 3> SD(B);
-    const bool uni = flat_uniform<W>(B, g, f);
-    // inverse diagonals: one constant in the uniform bulk, closed form off the
-    // body box, else loaded
-    T dc[W], dy0[W], dy1[W], dz0[W], dz1[W], dx0, dx1;
-    const int wx0 = (g.per[0] && f.i0 == 1) ? g.n[0] : f.i0 - 1;
-    const int wx1 = (g.per[0] && f.i0 + W - 1 == g.n[0]) ? 1 : f.i0 + W;
-    const int jm = (g.per[1] && f.j == 1) ? g.n[1] : f.j - 1, jp = (g.per[1] && f.j == g.n[1]) ? 1 : f.j + 1;
-    const int km = (g.per[2] && f.k == 1) ? g.n[2] : f.k - 1, kp = (g.per[2] && f.k == g.n[2]) ? 1 : f.k + 1;
-    if (uni) {
-#pragma unroll
-      for (int w = 0; w < W; ++w) dc[w] = dy0[w] = dy1[w] = dz0[w] = dz1[w] = SD.v[0];
-      dx0 = dx1 = SD.v[0];
-    } else if (fast) {
-#pragma unroll
-      for (int w = 0; w < W; ++w) {
-        dc[w] = SD.at(g, f.i0 + w, f.j, f.k);
-        dy0[w] = SD.at(g, f.i0 + w, jm, f.k);
-        dy1[w] = SD.at(g, f.i0 + w, jp, f.k);
-        dz0[w] = SD.at(g, f.i0 + w, f.j, km);
-        dz1[w] = SD.at(g, f.i0 + w, f.j, kp);
-      }
-      dx0 = SD.at(g, wx0, f.j, f.k);
-      dx1 = SD.at(g, wx1, f.j, f.k);
-    } else {
-#pragma unroll
-      for (int w = 0; w < W; ++w) {
-        dc[w] = iD[id + w];
-        dy0[w] = iD[id + w + o.ym];
-        dy1[w] = iD[id + w + o.yp];
-        dz0[w] = iD[id + w + o.zm];
-        dz1[w] = iD[id + w + o.zp];
-      }
-      dx0 = iD[id + o.xm];
-      dx1 = iD[id + W - 1 + o.xp];
-    }
-    T e_new[W];
-#pragma unroll
-    for (int w = 0; w < W; ++w) e_new[w] = eps(dc[w], R0[w], E0[w]);
-    const T ex_m = eps(dx0, rx0, ex0), ex_p = eps(dx1, rx1, ex1);
+    const FlatStd<T, W, PER> S(g, B, f);
+    V out;
+    T* O = reinterpret_cast<T*>(&out);
 #pragma unroll
     for (int w = 0; w < W; ++w) {
-      const T ec = e_new[w];
-      T qq = T(0);
-      if (dc[w] != T(0)) {
-        const int i = f.i0 + w, cid = id + w;
-        const T xm = (w > 0) ? e_new[w - 1] : ex_m, xp = (w < W - 1) ? e_new[w + 1] : ex_p;
-        const T ym = eps(dy0[w], RY0[w], EY0[w]), yp = eps(dy1[w], RY1[w], EY1[w]);
-        const T zm = eps(dz0[w], RZ0[w], EZ0[w]), zp = eps(dz1[w], RZ1[w], EZ1[w]);
-        T Lxp, Lxc, Lyp, Lyc, Lzp, Lzc;
-        flat_coef<T, W>(g, B, L, f, o, uni, fast, w, Lxp, Lxc, Lyp, Lyc, Lzp, Lzc);
-        qq = qq + Lxp * (xp - ec) - Lxc * (ec - xm);
-        qq = qq + Lyp * (yp - ec) - Lyc * (ec - ym);
-        qq = qq + Lzp * (zp - ec) - Lzc * (ec - zm);
-        if (k == 0) rho0 += double(R0[w] - mean) * double(ec);
-      }
-      sig += double(ec) * double(qq);
+      const T d = fast ? S.d(B, w) : iD[id + w];
+      const T ec = (k > 0) ? d * R0[w] + beta * E0[w] : d * (R0[w] - mean);
+      O[w] = ec;
+      if (k == 0 && d != T(0)) rho0 += double(R0[w] - mean) * double(ec);
     }
-    V ev;
-    T* EV = reinterpret_cast<T*>(&ev);
-#pragma unroll
-    for (int w = 0; w < W; ++w) EV[w] = e_new[w];
-    stv_stream<T>(en + id, ev);
+    stv_stream<T>(en + id, out);
   }
-  sig = block_sum<kFlatThreads>(sig);
-  if (threadIdx.x == 0) part_sig[blockIdx.x] = sig;
   if (k == 0) {
     rho0 = block_sum<kFlatThreads>(rho0);
-    if (threadIdx.x == 0) part_rho0[blockIdx.x] = rho0;
+    if (threadIdx.x == 0) part_rho0[flat_block()] = rho0;
   }
+}
+
+template <typename T, bool PER>
+__global__ void __launch_bounds__(kFlatThreads) k_pcg_a2_flat(Grid3 g, Vec3<T> L, const T* iD, const T* e,
+                                                              double* part_sig, int* flag, StdBox B) {
+  typedef typename Vec16<T>::type V;
+  constexpr int W = Vec16<T>::W;
+  if (*flag) return;
+  const FlatVec f = flat_vec<T>(g);
+  double sig = 0.0;
+  if (f.ok) {
+    const FlatNbr<W, PER> o(g, f);
+    const int id = f.id;
+    const V ec_ = ldv(e + id), ey0 = ldv(e + id + o.ym), ey1 = ldv(e + id + o.yp), ez0 = ldv(e + id + o.zm),
+            ez1 = ldv(e + id + o.zp);
+    const T ex0 = e[id + o.xm], ex1 = e[id + W - 1 + o.xp];
+    const T* E0 = reinterpret_cast<const T*>(&ec_);
+    const T *EY0 = reinterpret_cast<const T*>(&ey0), *EY1 = reinterpret_cast<const T*>(&ey1);
+    const T *EZ0 = reinterpret_cast<const T*>(&ez0), *EZ1 = reinterpret_cast<const T*>(&ez1);
+    auto lane = [&](const FlatCoef<T, W, PER>& c, int w) {
+      const T ec = E0[w];
+      T qq = T(0);
+      if (c.d != T(0)) {
+        const T xm = (w > 0) ? E0[w - 1] : ex0, xp = (w < W - 1) ? E0[w + 1] : ex1;
+        qq = qq + c.Lxp * (xp - ec) - c.Lxc * (ec - xm);
+        qq = qq + c.Lyp * (EY1[w] - ec) - c.Lyc * (ec - EY0[w]);
+        qq = qq + c.Lzp * (EZ1[w] - ec) - c.Lzc * (ec - EZ0[w]);
+      }
+      sig += double(ec) * double(qq);
+    };
+    if (flat_fast<W>(B, g, f)) {
+      const FlatStd<T, W, PER> S(g, B, f);
+#pragma unroll
+      for (int w = 0; w < W; ++w) lane(FlatCoef<T, W, PER>(S, B, w), w);
+    } else {
+      const FlatLoaded<T, W, PER> C(g, L, iD, f, o);
+#pragma unroll
+      for (int w = 0; w < W; ++w) lane(FlatCoef<T, W, PER>(C, w), w);
+    }
+  }
+  sig = block_sum<kFlatThreads>(sig);
+  if (threadIdx.x == 0) part_sig[flat_block()] = sig;
 }
 
 // PCG pass B, flat form (arithmetic of k_pcg_b_tile): q = A e from e and its
 // neighbours, x += alpha e, r -= alpha q, partials of rho_{k+1} and max|r|.
-template <typename T>
+template <typename T, bool PER>
 __global__ void __launch_bounds__(kFlatThreads) k_pcg_b_flat(Grid3 g, Vec3<T> L, const T* iD, const T* e, T* x,
                                                              T* r, double* red, int k, RedN rn,
                                                              double* part_rho_next, double* part_max, int want_rho,
@@ -1866,7 +1920,7 @@ __global__ void __launch_bounds__(kFlatThreads) k_pcg_b_flat(Grid3 g, Vec3<T> L,
     const double sig = total_of<kFlatThreads>(red + (size_t)(kSlotSig0 + k) * kMaxBlocks, rn.sig);
     if (fabs(sig) < 1e-300) {
       skip = true;
-      if (blockIdx.x == 0 && threadIdx.x == 0) *flag = 1;
+      if (flat_block() == 0 && threadIdx.x == 0) *flag = 1;
     } else {
       alpha = T(total_of<kFlatThreads>(red + (size_t)(kSlotRho0 + k) * kMaxBlocks, rn.rho) / sig);
     }
@@ -1875,9 +1929,8 @@ __global__ void __launch_bounds__(kFlatThreads) k_pcg_b_flat(Grid3 g, Vec3<T> L,
   const FlatVec f = flat_vec<T>(g);
   double rho = 0.0, mx = 0.0;
   if (f.ok) {
-    const FlatNbr<W> o(g, f);
+    const FlatNbr<W, PER> o(g, f);
     const int id = f.id;
-    const bool fast = flat_fast<W>(B, g, f);
     const V ec_ = ldv(e + id), ey0 = ldv(e + id + o.ym), ey1 = ldv(e + id + o.yp), ez0 = ldv(e + id + o.zm),
             ez1 = ldv(e + id + o.zp);
     const T ex0 = e[id + o.xm], ex1 = e[id + W - 1 + o.xp];
@@ -1887,35 +1940,37 @@ __global__ void __launch_bounds__(kFlatThreads) k_pcg_b_flat(Grid3 g, Vec3<T> L,
     const T *EZ0 = reinterpret_cast<const T*>(&ez0), *EZ1 = reinterpret_cast<const T*>(&ez1);
     const T* X0 = reinterpret_cast<const T*>(&xv);
     const T* R0 = reinterpret_cast<const T*>(&rv);
-    const StdDiag<T, 3> SD(B);
-    const bool uni = flat_uniform<W>(B, g, f);
     V xo, ro;
     T* XO = reinterpret_cast<T*>(&xo);
     T* RO = reinterpret_cast<T*>(&ro);
-#pragma unroll
-    for (int w = 0; w < W; ++w) {
-      const int i = f.i0 + w, cid = id + w;
+    auto lane = [&](const FlatCoef<T, W, PER>& c, int w) {
       const T ec = E0[w];
-      const T dc = uni ? SD.v[0] : fast ? SD.at(g, i, f.j, f.k) : iD[cid];
       T rr = R0[w];
-      if (mean != T(0) && dc != T(0)) rr = rr - mean;
+      if (mean != T(0) && c.d != T(0)) rr = rr - mean;
       XO[w] = X0[w];
       if (!skip) {
         T qq = T(0);
-        if (dc != T(0)) {
+        if (c.d != T(0)) {
           const T xm = (w > 0) ? E0[w - 1] : ex0, xp = (w < W - 1) ? E0[w + 1] : ex1;
-          T Lxp, Lxc, Lyp, Lyc, Lzp, Lzc;
-          flat_coef<T, W>(g, B, L, f, o, uni, fast, w, Lxp, Lxc, Lyp, Lyc, Lzp, Lzc);
-          qq = qq + Lxp * (xp - ec) - Lxc * (ec - xm);
-          qq = qq + Lyp * (EY1[w] - ec) - Lyc * (ec - EY0[w]);
-          qq = qq + Lzp * (EZ1[w] - ec) - Lzc * (ec - EZ0[w]);
+          qq = qq + c.Lxp * (xp - ec) - c.Lxc * (ec - xm);
+          qq = qq + c.Lyp * (EY1[w] - ec) - c.Lyc * (ec - EY0[w]);
+          qq = qq + c.Lzp * (EZ1[w] - ec) - c.Lzc * (ec - EZ0[w]);
         }
         XO[w] = X0[w] + alpha * ec;
         rr = rr - alpha * qq;
       }
       RO[w] = rr;
-      rho += double(rr) * (double(dc) * double(rr));
+      rho += double(rr) * (double(c.d) * double(rr));
       mx = fmax(mx, fabs(double(rr)));
+    };
+    if (flat_fast<W>(B, g, f)) {
+      const FlatStd<T, W, PER> S(g, B, f);
+#pragma unroll
+      for (int w = 0; w < W; ++w) lane(FlatCoef<T, W, PER>(S, B, w), w);
+    } else {
+      const FlatLoaded<T, W, PER> C(g, L, iD, f, o);
+#pragma unroll
+      for (int w = 0; w < W; ++w) lane(FlatCoef<T, W, PER>(C, w), w);
     }
     if (!skip) stv_stream<T>(x + id, xo);
     if (!skip || mean != T(0)) stv_stream<T>(r + id, ro);
@@ -1938,8 +1993,8 @@ __global__ void __launch_bounds__(kFlatThreads) k_pcg_b_flat(Grid3 g, Vec3<T> L,
         sr += shr[i];
         sm = fmax(sm, shm[i]);
       }
-      if (want_rho && !skip) part_rho_next[blockIdx.x] = sr;
-      if (want_max) part_max[blockIdx.x] = sm;
+      if (want_rho && !skip) part_rho_next[flat_block()] = sr;
+      if (want_max) part_max[flat_block()] = sm;
     }
   }
 }

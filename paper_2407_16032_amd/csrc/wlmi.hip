@@ -151,12 +151,17 @@ constexpr int kAdjFields(int D) { return 8 * D + D * D + 4; }
 // Blocks of the flat PCG passes on the fine level, or 0 if it does not take them:
 // the solver path allows them, 3-D, at least 2^18 cells, and rows holding a whole
 // number of 16-byte vectors.
+// (grid: flat_plane_blocks per plane x the planes)
+int64_t flat_plane_blocks(const LevelPlan& L, size_t esize) {
+  const int64_t W = (int64_t)(16 / esize);
+  return (L.n[0] / W * L.n[1] + kFlatThreads - 1) / kFlatThreads;
+}
 int64_t flat_blocks(const wl_sim_desc& d, const LevelPlan& L, size_t esize) {
   const int W = (int)(16 / esize);
   if (d.ndim != 3 || L.n[0] % W != 0 || (d.solver_path != 0 && d.solver_path != 2)) return 0;
   const int64_t cells = (int64_t)L.n[0] * L.n[1] * L.n[2];
   if (cells < (1 << 18)) return 0;
-  return (cells / W + kFlatThreads - 1) / kFlatThreads;
+  return flat_plane_blocks(L, esize) * L.n[2];
 }
 
 Plan make_plan(const wl_sim_desc& d, bool has_body) {
@@ -395,7 +400,7 @@ struct Impl : SimBase {
   int64_t nflat = 0;       // blocks of the flat fine-level PCG passes (0: tiles or generic kernels)
   double* wide = nullptr;  // their partials: sigma, rho_0, rho_{k+1}, max|r| (nflat each), then
                            // 2 x kFinalizeStage first-stage sums
-  bool flat_a = false;     // pass A flat too (else tiled) when nflat > 0
+  bool flat_a = false;     // pass A flat too (in two launches) when nflat > 0
   int tiles[kMaxLevels][4] = {};  // tiled kernels: tiles_x, tiles_y, ntiles (0 = generic kernel), tile depth
   int lbot = 0;                   // first level of the single-workgroup bottom solve
   StdBox sbox[kMaxLevels] = {};   // per level: outside, coefficients are body-free
@@ -590,8 +595,8 @@ struct Impl : SimBase {
         }
       }
     }
-    // automatic path: pass B flat on the fine level, pass A tiled when the level has tiles
-    flat_a = nflat > 0 && (desc.solver_path == 2 || tiles[0][2] == 0);
+    // both fine-level passes flat whenever the level takes the flat form
+    flat_a = nflat > 0;
     nb_face = blocks_for((int64_t)(g[0].n[0] + 2) * (g[0].n[1] + 2) * (D == 3 ? g[0].n[2] + 2 : 1));
     planes.count = 0;
     int maxarea = 1;
@@ -685,6 +690,10 @@ struct Impl : SimBase {
         sbox[l].hi[a] = hi[a];
       }
       sbox[l].Lstd = Ls;
+      for (int c = 0; c < 4; ++c) {
+        sbox[l].iDf[c] = 1.0f / (-((float)Ls * (float)(2 * D - c)));
+        sbox[l].iDd[c] = 1.0 / (-(Ls * (double)(2 * D - c)));
+      }
       if (lo[0] <= hi[0])
         for (int a = 0; a < D; ++a) {
           lo[a] = std::max(0, lo[a] / 2 - 1);
@@ -758,6 +767,7 @@ struct Impl : SimBase {
   }
 
   void set_mean_producer(int grid) { slot_n[kSlotSumR] = slot_n[kSlotCnt] = grid; }
+  dim3 flat_grid() const { return dim3((unsigned)flat_plane_blocks(plan.lev[0], sizeof(T)), (unsigned)g[0].n[2]); }
 
   // Sum (or max) a slot's partials into its first entry when a large grid left
   // them: each block of the consumer would otherwise re-add all of them.
@@ -806,8 +816,17 @@ struct Impl : SimBase {
       int ga;
       if (l == 0 && nflat > 0 && flat_a) {
         const int nf = (int)nflat;
-        WL_TIMED(kidA, (k_pcg_a_flat<T><<<nf, kFlatThreads, 0, stream>>>(g[l], v3(L[l]), iD[l], r[l], eo, en, red, k,
-                                                                         rn, wide, wide + nf, flags + l, sbox[l])));
+        if (desc.periodic_mask) {
+          WL_TIMED(kidA, (k_pcg_a1_flat<T, true><<<flat_grid(), kFlatThreads, 0, stream>>>(
+                              g[l], iD[l], r[l], eo, en, red, k, rn, wide + nf, flags + l, sbox[l])));
+          WL_TIMED(WL_K_PCG_A2, (k_pcg_a2_flat<T, true><<<flat_grid(), kFlatThreads, 0, stream>>>(
+                                    g[l], v3(L[l]), iD[l], en, wide, flags + l, sbox[l])));
+        } else {
+          WL_TIMED(kidA, (k_pcg_a1_flat<T, false><<<flat_grid(), kFlatThreads, 0, stream>>>(
+                              g[l], iD[l], r[l], eo, en, red, k, rn, wide + nf, flags + l, sbox[l])));
+          WL_TIMED(WL_K_PCG_A2, (k_pcg_a2_flat<T, false><<<flat_grid(), kFlatThreads, 0, stream>>>(
+                                    g[l], v3(L[l]), iD[l], en, wide, flags + l, sbox[l])));
+        }
         ga = 1;
       } else if (tiles[l][2] > 0) {
         ga = tiles[l][2];
@@ -846,9 +865,14 @@ struct Impl : SimBase {
       int gbk = gb;
       if (l == 0 && nflat > 0) {
         const int nf = (int)nflat;
-        WL_TIMED(kidB, (k_pcg_b_flat<T><<<nf, kFlatThreads, 0, stream>>>(g[l], v3(L[l]), iD[l], en, x[l], r[l], red,
-                                                                         k, rn, wide + 2 * nf, wide + 3 * nf, wr, wm,
-                                                                         flags + l, sbox[l])));
+        if (desc.periodic_mask)
+          WL_TIMED(kidB, (k_pcg_b_flat<T, true><<<flat_grid(), kFlatThreads, 0, stream>>>(
+                              g[l], v3(L[l]), iD[l], en, x[l], r[l], red, k, rn, wide + 2 * nf, wide + 3 * nf, wr, wm,
+                              flags + l, sbox[l])));
+        else
+          WL_TIMED(kidB, (k_pcg_b_flat<T, false><<<flat_grid(), kFlatThreads, 0, stream>>>(
+                              g[l], v3(L[l]), iD[l], en, x[l], r[l], red, k, rn, wide + 2 * nf, wide + 3 * nf, wr, wm,
+                              flags + l, sbox[l])));
         if (wr)
           reduce_wide(wide + 2 * nf, 0, wide + 3 * nf, 1, kSlotRho0 + k + 1, wm ? kSlotRmax : -1);
         else if (wm)
