@@ -78,11 +78,13 @@ typedef struct {
   int pcg_iters;         /* PCG smoothing iterations per level [6] */
   int learned_guess;     /* 1 -> plan the buffers of the learned initial guess (3-D only) */
   int adjoint;           /* 1 -> plan the buffers of the discrete adjoint (wl_adj_*) */
-  int solver_path;       /* kernels of the large 3-D multigrid levels (>= 2^18 cells):
-                            0 = automatic (flat vector passes on the fine level, z-marching
-                            tiles on the coarser large levels), 1 = tiles on every large
-                            level, 2 = as 0, 3 = the generic grid-stride kernels only.  The
-                            arithmetic is the same; sums differ in rounding order only. [0] */
+  int solver_path;       /* PCG kernels of the 3-D multigrid levels: 0 = automatic (flat
+                            vector passes on every level of >= 2^15 cells whose rows hold
+                            whole 16-byte vectors), 1 = z-marching tiles on the levels of
+                            >= 2^18 cells, 2 = as 0, 3 = the generic grid-stride kernels
+                            only.  The levels of <= 4096 cells run the single-workgroup
+                            bottom solve in every case.  The arithmetic is the same; sums
+                            differ in rounding order only. [0] */
 } wl_sim_desc;
 
 typedef enum { WL_BODY_NONE = 0, WL_BODY_SPHERE = 1, WL_BODY_BOX = 2 } wl_body_kind;

@@ -148,10 +148,11 @@ PgSizes pg_sizes(const Plan& P) {
 // the adjoint right-hand side
 constexpr int kAdjFields(int D) { return 8 * D + D * D + 4; }
 
-// Blocks of the flat PCG passes on the fine level, or 0 if it does not take them:
-// the solver path allows them, 3-D, at least 2^18 cells, and rows holding a whole
-// number of 16-byte vectors.
-// (grid: flat_plane_blocks per plane x the planes)
+// Blocks of the flat PCG passes on a level, or 0 if it does not take them: the
+// solver path allows them, 3-D, at least 2^15 cells (smaller levels are launch
+// bound and go to the generic kernels or the bottom solve), and rows holding a
+// whole number of 16-byte vectors.  (grid: flat_plane_blocks per plane x planes)
+constexpr int64_t kFlatMinCells = 1 << 15;
 int64_t flat_plane_blocks(const LevelPlan& L, size_t esize) {
   const int64_t W = (int64_t)(16 / esize);
   return (L.n[0] / W * L.n[1] + kFlatThreads - 1) / kFlatThreads;
@@ -160,8 +161,14 @@ int64_t flat_blocks(const wl_sim_desc& d, const LevelPlan& L, size_t esize) {
   const int W = (int)(16 / esize);
   if (d.ndim != 3 || L.n[0] % W != 0 || (d.solver_path != 0 && d.solver_path != 2)) return 0;
   const int64_t cells = (int64_t)L.n[0] * L.n[1] * L.n[2];
-  if (cells < (1 << 18)) return 0;
+  if (cells < kFlatMinCells) return 0;
   return flat_plane_blocks(L, esize) * L.n[2];
+}
+// the most flat-pass blocks of any level (they share one partials area)
+int64_t flat_blocks_max(const wl_sim_desc& d, const Plan& P) {
+  int64_t m = 0;
+  for (int l = 0; l < P.nlev; ++l) m = std::max(m, flat_blocks(d, P.lev[l], P.esize));
+  return m;
 }
 
 Plan make_plan(const wl_sim_desc& d, bool has_body) {
@@ -199,7 +206,7 @@ Plan make_plan(const wl_sim_desc& d, bool has_body) {
   b += align256(kNumScal * sizeof(double));
   b += align256(kMaxLevels * sizeof(int));
   {
-    const int64_t nf = flat_blocks(d, P.lev[0], P.esize);  // flat-pass partials and their first stage
+    const int64_t nf = flat_blocks_max(d, P);  // flat-pass partials and their first stage
     if (nf > 0) b += align256((size_t)(4 * nf + 2 * kFinalizeStage) * sizeof(double));
   }
   if (d.adjoint) b += (size_t)kAdjFields(D) * f0;
@@ -397,10 +404,10 @@ struct Impl : SimBase {
   double *pgRed = nullptr, *pgScal = nullptr;
   PgBox bd{}, bcrop{};
   int64_t pgPc = 0;
-  int64_t nflat = 0;       // blocks of the flat fine-level PCG passes (0: tiles or generic kernels)
-  double* wide = nullptr;  // their partials: sigma, rho_0, rho_{k+1}, max|r| (nflat each), then
-                           // 2 x kFinalizeStage first-stage sums
-  bool flat_a = false;     // pass A flat too (in two launches) when nflat > 0
+  int64_t nflat[kMaxLevels] = {};  // blocks of a level's flat PCG passes (0: tiles or generic kernels)
+  int64_t wide_n = 0;              // the largest of them
+  double* wide = nullptr;          // their partials: sigma, rho_0, rho_{k+1}, max|r| (wide_n
+                                   // apart), then 2 x kFinalizeStage first-stage sums
   int tiles[kMaxLevels][4] = {};  // tiled kernels: tiles_x, tiles_y, ntiles (0 = generic kernel), tile depth
   int lbot = 0;                   // first level of the single-workgroup bottom solve
   StdBox sbox[kMaxLevels] = {};   // per level: outside, coefficients are body-free
@@ -471,8 +478,9 @@ struct Impl : SimBase {
     red = (double*)take((size_t)kNumSlots * kMaxBlocks * sizeof(double));
     scal = (double*)take(kNumScal * sizeof(double));
     flags = (int*)take(kMaxLevels * sizeof(int));
-    nflat = flat_blocks(desc, plan.lev[0], sizeof(T));
-    if (nflat > 0) wide = (double*)take((size_t)(4 * nflat + 2 * kFinalizeStage) * sizeof(double));
+    wide_n = flat_blocks_max(desc, plan);
+    for (int l = 0; l < plan.nlev; ++l) nflat[l] = flat_blocks(desc, plan.lev[l], sizeof(T));
+    if (wide_n > 0) wide = (double*)take((size_t)(4 * wide_n + 2 * kFinalizeStage) * sizeof(double));
     adj_on = desc.adjoint != 0;
     if (adj_on) {
       for (int k = 0; k < D; ++k) au[0][k] = field(0);
@@ -595,8 +603,6 @@ struct Impl : SimBase {
         }
       }
     }
-    // both fine-level passes flat whenever the level takes the flat form
-    flat_a = nflat > 0;
     nb_face = blocks_for((int64_t)(g[0].n[0] + 2) * (g[0].n[1] + 2) * (D == 3 ? g[0].n[2] + 2 : 1));
     planes.count = 0;
     int maxarea = 1;
@@ -767,18 +773,19 @@ struct Impl : SimBase {
   }
 
   void set_mean_producer(int grid) { slot_n[kSlotSumR] = slot_n[kSlotCnt] = grid; }
-  dim3 flat_grid() const { return dim3((unsigned)flat_plane_blocks(plan.lev[0], sizeof(T)), (unsigned)g[0].n[2]); }
+  dim3 flat_grid(int l) const {
+    return dim3((unsigned)flat_plane_blocks(plan.lev[l], sizeof(T)), (unsigned)g[l].n[2]);
+  }
 
   // Sum (or max) a slot's partials into its first entry when a large grid left
   // them: each block of the consumer would otherwise re-add all of them.
   static constexpr int kCollapseMin = 2048;
-  // Totals of nflat-sized partial arrays into slot sa / sb (sb < 0: none): in two
-  // stages when there are many (a single block would wait on each load in turn).
-  void reduce_wide(const double* a, int a_max, const double* b, int b_max, int sa, int sb) {
-    const int n = (int)nflat;
+  // Totals of n partials into slot sa / sb (sb < 0: none): in two stages when
+  // there are many (a single block would wait on each load in turn).
+  void reduce_wide(const double* a, int a_max, const double* b, int b_max, int n, int sa, int sb) {
     double* out_b = sb >= 0 ? slot(sb) : nullptr;
     if (n > 4 * kFinalizeThreads) {
-      double* ta = wide + 4 * nflat;
+      double* ta = wide + 4 * wide_n;
       double* tb = ta + kFinalizeStage;
       WL_TIMED(WL_K_REDUCE, (k_finalize2<<<kFinalizeStage, kFinalizeThreads, 0, stream>>>(
                                 a, a_max, sb >= 0 ? b : nullptr, b_max, n, ta, tb)));
@@ -809,23 +816,30 @@ struct Impl : SimBase {
     const int64_t nvec = plan.lev[l].alloc / Vec16<T>::W;
     const int gb = blocks_for(nvec);
     const int kidA = l == 0 ? WL_K_PCG_A : WL_K_COARSE, kidB = l == 0 ? WL_K_PCG_B : WL_K_COARSE;
+    const int kidA2 = l == 0 ? WL_K_PCG_A2 : WL_K_COARSE;
+    const int nf = (int)nflat[l];
+    // a flat level with few blocks leaves its partials in the slots, as the tiles do
+    const bool direct = nf > 0 && nf <= kCollapseMin;
     collapse(kSlotSumR, 0, kSlotCnt, 0);
     for (int k = 0; k < K; ++k) {
       const int wr = k < K - 1 ? 1 : 0, wm = (fine && k == K - 1) ? 1 : 0;
       RedN rn{slot_n[kSlotSumR], slot_n[kSlotRho0 + k], k > 0 ? slot_n[kSlotRho0 + k - 1] : 0, 0};
       int ga;
-      if (l == 0 && nflat > 0 && flat_a) {
-        const int nf = (int)nflat;
+      double* const wsig = direct ? slot(kSlotSig0 + k) : wide;
+      double* const wrho0 = direct ? slot(kSlotRho0) : wide + wide_n;
+      double* const wrho = direct ? slot(kSlotRho0 + k + 1) : wide + 2 * wide_n;
+      double* const wmax = direct ? slot(kSlotRmax) : wide + 3 * wide_n;
+      if (nf > 0) {
         if (desc.periodic_mask) {
-          WL_TIMED(kidA, (k_pcg_a1_flat<T, true><<<flat_grid(), kFlatThreads, 0, stream>>>(
-                              g[l], iD[l], r[l], eo, en, red, k, rn, wide + nf, flags + l, sbox[l])));
-          WL_TIMED(WL_K_PCG_A2, (k_pcg_a2_flat<T, true><<<flat_grid(), kFlatThreads, 0, stream>>>(
-                                    g[l], v3(L[l]), iD[l], en, wide, flags + l, sbox[l])));
+          WL_TIMED(kidA, (k_pcg_a1_flat<T, true><<<flat_grid(l), kFlatThreads, 0, stream>>>(
+                              g[l], iD[l], r[l], eo, en, red, k, rn, wrho0, flags + l, sbox[l])));
+          WL_TIMED(kidA2, (k_pcg_a2_flat<T, true><<<flat_grid(l), kFlatThreads, 0, stream>>>(
+                              g[l], v3(L[l]), iD[l], en, wsig, flags + l, sbox[l])));
         } else {
-          WL_TIMED(kidA, (k_pcg_a1_flat<T, false><<<flat_grid(), kFlatThreads, 0, stream>>>(
-                              g[l], iD[l], r[l], eo, en, red, k, rn, wide + nf, flags + l, sbox[l])));
-          WL_TIMED(WL_K_PCG_A2, (k_pcg_a2_flat<T, false><<<flat_grid(), kFlatThreads, 0, stream>>>(
-                                    g[l], v3(L[l]), iD[l], en, wide, flags + l, sbox[l])));
+          WL_TIMED(kidA, (k_pcg_a1_flat<T, false><<<flat_grid(l), kFlatThreads, 0, stream>>>(
+                              g[l], iD[l], r[l], eo, en, red, k, rn, wrho0, flags + l, sbox[l])));
+          WL_TIMED(kidA2, (k_pcg_a2_flat<T, false><<<flat_grid(l), kFlatThreads, 0, stream>>>(
+                              g[l], v3(L[l]), iD[l], en, wsig, flags + l, sbox[l])));
         }
         ga = 1;
       } else if (tiles[l][2] > 0) {
@@ -848,8 +862,11 @@ struct Impl : SimBase {
           WL_TIMED(kidA, (k_pcg_a<T, D, 0><<<ga, kBlock, 0, stream>>>(g[l], v3(L[l]), iD[l], r[l], eo, en, q[l],
                                                                       red, k, rn, slot(kSlotSig0 + k), flags + l)));
       }
-      if (l == 0 && nflat > 0 && flat_a) {
-        reduce_wide(wide, 0, wide + nflat, 0, kSlotSig0 + k, k == 0 ? kSlotRho0 : -1);
+      if (nf > 0 && !direct) {
+        reduce_wide(wsig, 0, wrho0, 0, nf, kSlotSig0 + k, k == 0 ? kSlotRho0 : -1);
+      } else if (nf > 0) {
+        slot_n[kSlotSig0 + k] = nf;
+        if (k == 0) slot_n[kSlotRho0] = nf;
       } else {
         slot_n[kSlotSig0 + k] = ga;
         if (k == 0) slot_n[kSlotRho0] = ga;
@@ -863,20 +880,23 @@ struct Impl : SimBase {
       T* b_x = x[l] - kFrontPad;
       T* b_r = r[l] - kFrontPad;
       int gbk = gb;
-      if (l == 0 && nflat > 0) {
-        const int nf = (int)nflat;
+      if (nf > 0) {
         if (desc.periodic_mask)
-          WL_TIMED(kidB, (k_pcg_b_flat<T, true><<<flat_grid(), kFlatThreads, 0, stream>>>(
-                              g[l], v3(L[l]), iD[l], en, x[l], r[l], red, k, rn, wide + 2 * nf, wide + 3 * nf, wr, wm,
-                              flags + l, sbox[l])));
+          WL_TIMED(kidB, (k_pcg_b_flat<T, true><<<flat_grid(l), kFlatThreads, 0, stream>>>(
+                              g[l], v3(L[l]), iD[l], en, x[l], r[l], red, k, rn, wrho, wmax, wr, wm, flags + l,
+                              sbox[l])));
         else
-          WL_TIMED(kidB, (k_pcg_b_flat<T, false><<<flat_grid(), kFlatThreads, 0, stream>>>(
-                              g[l], v3(L[l]), iD[l], en, x[l], r[l], red, k, rn, wide + 2 * nf, wide + 3 * nf, wr, wm,
-                              flags + l, sbox[l])));
-        if (wr)
-          reduce_wide(wide + 2 * nf, 0, wide + 3 * nf, 1, kSlotRho0 + k + 1, wm ? kSlotRmax : -1);
-        else if (wm)
-          reduce_wide(wide + 3 * nf, 1, nullptr, 0, kSlotRmax, -1);
+          WL_TIMED(kidB, (k_pcg_b_flat<T, false><<<flat_grid(l), kFlatThreads, 0, stream>>>(
+                              g[l], v3(L[l]), iD[l], en, x[l], r[l], red, k, rn, wrho, wmax, wr, wm, flags + l,
+                              sbox[l])));
+        if (direct) {
+          if (wr) slot_n[kSlotRho0 + k + 1] = nf;
+          if (wm) slot_n[kSlotRmax] = nf;
+        } else if (wr) {
+          reduce_wide(wrho, 0, wmax, 1, nf, kSlotRho0 + k + 1, wm ? kSlotRmax : -1);
+        } else if (wm) {
+          reduce_wide(wmax, 1, nullptr, 0, nf, kSlotRmax, -1);
+        }
         gbk = 1;
       } else if (tiles[l][2] > 0) {
         gbk = tiles[l][2];
@@ -897,7 +917,7 @@ struct Impl : SimBase {
                                                                     slot(kSlotRho0 + k + 1), slot(kSlotRmax), wr,
                                                                     wm, flags + l, g[l], sbox[l])));
       }
-      if (!(l == 0 && nflat > 0)) {
+      if (nf == 0) {
         if (wr) slot_n[kSlotRho0 + k + 1] = gbk;
         if (wm) slot_n[kSlotRmax] = gbk;
         if (wr)
