@@ -419,9 +419,15 @@ __global__ void __launch_bounds__(kBlock) k_flux(Grid3 g, Vec3<T> u, Vec3<T> u0,
 // its column in z, so the +-2 neighbours of the stencil are re-read from cache; the
 // bricks are handed out XCD-aware (each XCD takes a contiguous range of bricks,
 // x fastest), which keeps the y/z halos of neighbouring bricks in one L2.
-constexpr int kFX = 64, kFY = 4, kFZ = 16;
+#ifndef WL_FY
+#define WL_FY 4
+#endif
+#ifndef WL_FZ
+#define WL_FZ 16
+#endif
+constexpr int kFX = 64, kFY = WL_FY, kFZ = WL_FZ, kFluxThreads = kFX * kFY;
 template <typename T>
-__global__ void __launch_bounds__(kBlock) k_flux_bricks(Grid3 g, Vec3<T> u, Vec3<T> u0, Vec3<T> V, Vec3<T> f,
+__global__ void __launch_bounds__(kFluxThreads) k_flux_bricks(Grid3 g, Vec3<T> u, Vec3<T> u0, Vec3<T> V, Vec3<T> f,
                                                         T dt, T nu, int has_body, StdBox B, int nbx, int nby,
                                                         int nbz) {
   const int c = blockIdx.y;

@@ -149,10 +149,10 @@ PgSizes pg_sizes(const Plan& P) {
 constexpr int kAdjFields(int D) { return 8 * D + D * D + 4; }
 
 // Blocks of the flat PCG passes on a level, or 0 if it does not take them: the
-// solver path allows them, 3-D, at least 2^15 cells (smaller levels are launch
+// solver path allows them, 3-D, at least 2^14 cells (smaller levels are launch
 // bound and go to the generic kernels or the bottom solve), and rows holding a
 // whole number of 16-byte vectors.  (grid: flat_plane_blocks per plane x planes)
-constexpr int64_t kFlatMinCells = 1 << 15;
+constexpr int64_t kFlatMinCells = 1 << 14;
 int64_t flat_plane_blocks(const LevelPlan& L, size_t esize) {
   const int64_t W = (int64_t)(16 / esize);
   return (L.n[0] / W * L.n[1] + kFlatThreads - 1) / kFlatThreads;
@@ -1280,7 +1280,7 @@ struct Impl : SimBase {
     if (D == 3) {
       const int nbx = (g[0].n[0] + 2 + kFX - 1) / kFX, nby = (g[0].n[1] + 2 + kFY - 1) / kFY,
                 nbz = (g[0].n[2] + 2 + kFZ - 1) / kFZ;
-      WL_TIMED(WL_K_FLUX, (k_flux_bricks<T><<<dim3(nbx * nby * nbz, D), kBlock, 0, stream>>>(
+      WL_TIMED(WL_K_FLUX, (k_flux_bricks<T><<<dim3(nbx * nby * nbz, D), kFluxThreads, 0, stream>>>(
                               g[0], v3(uu), v3(uu0), v3(V), v3(ft), T(dt), T(desc.nu), hb, sbox[0], nbx, nby, nbz)));
     } else {
       WL_TIMED(WL_K_FLUX, (k_flux<T, D><<<dim3(nb_face, D), kBlock, 0, stream>>>(
