@@ -2005,6 +2005,140 @@ __global__ void __launch_bounds__(kFlatThreads) k_pcg_b_flat(Grid3 g, Vec3<T> L,
   }
 }
 
+// Residual restriction, flat form (arithmetic of k_restrict): one thread per
+// vector of W coarse cells, whose 2 x 2 x 2 children are two fine vectors in each
+// of two rows of two planes (the vectors of both levels start at odd x).  r_c is
+// the children's sum on active coarse cells (0 elsewhere), x_c = 0, and the
+// partials of the mean of r_c.
+template <typename T, bool PER>
+__global__ void __launch_bounds__(kFlatThreads) k_restrict_flat(Grid3 f, Grid3 c, const T* rf, const T* iDc, T* rc,
+                                                                T* xc, double* part_sum, double* part_cnt, int* flag,
+                                                                StdBox Bc) {
+  typedef typename Vec16<T>::type V;
+  constexpr int W = Vec16<T>::W;
+  if (flat_block() == 0 && threadIdx.x == 0) *flag = 0;
+  const FlatVec cv = flat_vec<T>(c);
+  double sr = 0.0, cnt = 0.0;
+  if (cv.ok) {
+    const int fb = (2 * cv.i0 - 1) + (2 * cv.j - 1) * f.s[1] + (2 * cv.k - 1) * f.s[2];
+    const int s1 = f.s[1], s2 = f.s[2];
+    // rows (y, z) = (0,0), (1,0), (0,1), (1,1); two vectors each
+    const V a0 = ldv(rf + fb), a1 = ldv(rf + fb + W), b0 = ldv(rf + fb + s1), b1 = ldv(rf + fb + s1 + W);
+    const V c0 = ldv(rf + fb + s2), c1 = ldv(rf + fb + s2 + W), d0 = ldv(rf + fb + s2 + s1),
+            d1 = ldv(rf + fb + s2 + s1 + W);
+    auto at = [](const V& lo, const V& hi, int q) -> T {
+      return q < W ? reinterpret_cast<const T*>(&lo)[q] : reinterpret_cast<const T*>(&hi)[q - W];
+    };
+    V ro, xo;
+    T* RO = reinterpret_cast<T*>(&ro);
+    T* XO = reinterpret_cast<T*>(&xo);
+    const bool fast = flat_fast<W>(Bc, c, cv);
+    V dl;
+    if (!fast) dl = ldv(iDc + cv.id);
+    const FlatStd<T, W, PER> S(c, Bc, cv);
+#pragma unroll
+    for (int w = 0; w < W; ++w) {
+      const int q = 2 * w;
+      T sm = at(a0, a1, q) + at(a0, a1, q + 1) + at(b0, b1, q) + at(b0, b1, q + 1);
+      sm = sm + (at(c0, c1, q) + at(c0, c1, q + 1) + at(d0, d1, q) + at(d0, d1, q + 1));
+      const T di = fast ? S.d(Bc, w) : reinterpret_cast<const T*>(&dl)[w];
+      RO[w] = (di != T(0)) ? sm : T(0);
+      XO[w] = T(0);
+      if (di != T(0)) {
+        sr += double(RO[w]);
+        cnt += 1.0;
+      }
+    }
+    stv_stream<T>(rc + cv.id, ro);
+    stv_stream<T>(xc + cv.id, xo);
+  }
+  sr = block_sum<kFlatThreads>(sr);
+  cnt = block_sum<kFlatThreads>(cnt);
+  if (threadIdx.x == 0) {
+    part_sum[flat_block()] = sr;
+    part_cnt[flat_block()] = cnt;
+  }
+}
+
+// Prolongation + correction, flat form (arithmetic of k_prolong): e = x_c of the
+// parent, x += e, and on active cells r -= A e; partials of the mean of the new
+// r.  With the vectors starting at odd x, lanes 2h and 2h+1 share the coarse
+// parent h; the other parents the stencil reaches are the x neighbours of the
+// end lanes and one coarse row and plane beside (whichever of j - 1, j + 1 and
+// k - 1, k + 1 leaves the parent's row or plane).
+template <typename T, bool PER>
+__global__ void __launch_bounds__(kFlatThreads) k_prolong_flat(Grid3 f, Grid3 c, const T* xc, Vec3<T> L,
+                                                               const T* iD, T* xf, T* rf, double* part_sum,
+                                                               double* part_cnt, int* flag, StdBox B) {
+  typedef typename Vec16<T>::type V;
+  constexpr int W = Vec16<T>::W, H = W / 2;
+  if (flat_block() == 0 && threadIdx.x == 0) *flag = 0;
+  const FlatVec fv = flat_vec<T>(f);
+  double sr = 0.0, cnt = 0.0;
+  if (fv.ok) {
+    const FlatNbr<W, PER> o(f, fv);
+    const int id = fv.id;
+    const V xv = ldv(xf + id), rv = ldv(rf + id);
+    const int Ic0 = (fv.i0 + 1) >> 1, J = (fv.j + 1) >> 1, K = (fv.k + 1) >> 1;
+    const int im = (PER && f.per[0] && fv.i0 == 1) ? f.n[0] : fv.i0 - 1;
+    const int ip = (PER && f.per[0] && fv.i0 + W - 1 == f.n[0]) ? 1 : fv.i0 + W;
+    const bool jodd = (fv.j & 1) != 0, kodd = (fv.k & 1) != 0;
+    int jn = jodd ? fv.j - 1 : fv.j + 1, kn = kodd ? fv.k - 1 : fv.k + 1;
+    if (PER && f.per[1]) jn = wrapc(jn, 1, f);
+    if (PER && f.per[2]) kn = wrapc(kn, 2, f);
+    const int Jo = (jn + 1) >> 1, Ko = (kn + 1) >> 1;
+    const int row = J * c.s[1] + K * c.s[2];
+    T ec[H], ey[H], ez[H];
+#pragma unroll
+    for (int h = 0; h < H; ++h) {
+      ec[h] = xc[Ic0 + h + row];
+      ey[h] = xc[Ic0 + h + Jo * c.s[1] + K * c.s[2]];
+      ez[h] = xc[Ic0 + h + J * c.s[1] + Ko * c.s[2]];
+    }
+    const T ecm = xc[((im + 1) >> 1) + row], ecp = xc[((ip + 1) >> 1) + row];
+    const T* X0 = reinterpret_cast<const T*>(&xv);
+    const T* R0 = reinterpret_cast<const T*>(&rv);
+    V xo, ro;
+    T* XO = reinterpret_cast<T*>(&xo);
+    T* RO = reinterpret_cast<T*>(&ro);
+    auto lane = [&](const FlatCoef<T, W, PER>& cf, int w) {
+      const T e0 = ec[w >> 1];
+      XO[w] = X0[w] + e0;
+      T rr = R0[w];
+      if (cf.d != T(0)) {
+        const T xm = (w == 0) ? ecm : ec[(w - 1) >> 1], xp = (w == W - 1) ? ecp : ec[(w + 1) >> 1];
+        const T ym = jodd ? ey[w >> 1] : e0, yp = jodd ? e0 : ey[w >> 1];
+        const T zm = kodd ? ez[w >> 1] : e0, zp = kodd ? e0 : ez[w >> 1];
+        T Ae = T(0);
+        Ae = Ae + cf.Lxp * (xp - e0) - cf.Lxc * (e0 - xm);
+        Ae = Ae + cf.Lyp * (yp - e0) - cf.Lyc * (e0 - ym);
+        Ae = Ae + cf.Lzp * (zp - e0) - cf.Lzc * (e0 - zm);
+        rr = rr - Ae;
+        sr += double(rr);
+        cnt += 1.0;
+      }
+      RO[w] = rr;
+    };
+    if (flat_fast<W>(B, f, fv)) {
+      const FlatStd<T, W, PER> S(f, B, fv);
+#pragma unroll
+      for (int w = 0; w < W; ++w) lane(FlatCoef<T, W, PER>(S, B, w), w);
+    } else {
+      const FlatLoaded<T, W, PER> C(f, L, iD, fv, o);
+#pragma unroll
+      for (int w = 0; w < W; ++w) lane(FlatCoef<T, W, PER>(C, w), w);
+    }
+    stv_stream<T>(xf + id, xo);
+    stv_stream<T>(rf + id, ro);
+  }
+  sr = block_sum<kFlatThreads>(sr);
+  cnt = block_sum<kFlatThreads>(cnt);
+  if (threadIdx.x == 0) {
+    part_sum[flat_block()] = sr;
+    part_cnt[flat_block()] = cnt;
+  }
+}
+
 // out_a[b] = sum (or max, a_max) of block b's share of a[0..n), out_b[b] likewise
 // for b; either array may be NULL.  One block gives the total; G blocks leave G
 // partials.  Fixed order, so repeated runs agree bitwise.

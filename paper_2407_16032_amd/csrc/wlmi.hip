@@ -962,17 +962,53 @@ struct Impl : SimBase {
   }
 
   void vcycle(int l) {
-    WL_TIMED(l == 0 ? WL_K_RESTRICT : WL_K_COARSE,
-             (k_restrict<T, D><<<nb[l + 1], kBlock, 0, stream>>>(g[l], g[l + 1], r[l], iD[l + 1], r[l + 1],
-                                                                 x[l + 1], red, flags + l + 1)));
-    set_mean_producer(nb[l + 1]);
+    if (nflat[l + 1] > 0) {
+      const int nf = (int)nflat[l + 1];
+      const bool direct = nf <= kCollapseMin;
+      double* const psum = direct ? slot(kSlotSumR) : wide;
+      double* const pcnt = direct ? slot(kSlotCnt) : wide + wide_n;
+      if (desc.periodic_mask)
+        WL_TIMED(l == 0 ? WL_K_RESTRICT : WL_K_COARSE,
+                 (k_restrict_flat<T, true><<<flat_grid(l + 1), kFlatThreads, 0, stream>>>(
+                     g[l], g[l + 1], r[l], iD[l + 1], r[l + 1], x[l + 1], psum, pcnt, flags + l + 1, sbox[l + 1])));
+      else
+        WL_TIMED(l == 0 ? WL_K_RESTRICT : WL_K_COARSE,
+                 (k_restrict_flat<T, false><<<flat_grid(l + 1), kFlatThreads, 0, stream>>>(
+                     g[l], g[l + 1], r[l], iD[l + 1], r[l + 1], x[l + 1], psum, pcnt, flags + l + 1, sbox[l + 1])));
+      if (direct)
+        set_mean_producer(nf);
+      else
+        reduce_wide(psum, 0, pcnt, 0, nf, kSlotSumR, kSlotCnt);
+    } else {
+      WL_TIMED(l == 0 ? WL_K_RESTRICT : WL_K_COARSE,
+               (k_restrict<T, D><<<nb[l + 1], kBlock, 0, stream>>>(g[l], g[l + 1], r[l], iD[l + 1], r[l + 1],
+                                                                   x[l + 1], red, flags + l + 1)));
+      set_mean_producer(nb[l + 1]);
+    }
     if (l + 1 == lbot) {
       bottom(l + 1);  // the rest of the cycle below, and PCG on level l+1
     } else {
       if (l + 2 < nlev) vcycle(l + 1);
       pcg(l + 1, false);
     }
-    if (tiles[l][2] > 0) {
+    if (nflat[l] > 0) {
+      const int nf = (int)nflat[l];
+      const bool direct = nf <= kCollapseMin;
+      double* const psum = direct ? slot(kSlotSumR) : wide;
+      double* const pcnt = direct ? slot(kSlotCnt) : wide + wide_n;
+      if (desc.periodic_mask)
+        WL_TIMED(l == 0 ? WL_K_PROLONG : WL_K_COARSE,
+                 (k_prolong_flat<T, true><<<flat_grid(l), kFlatThreads, 0, stream>>>(
+                     g[l], g[l + 1], x[l + 1], v3(L[l]), iD[l], x[l], r[l], psum, pcnt, flags + l, sbox[l])));
+      else
+        WL_TIMED(l == 0 ? WL_K_PROLONG : WL_K_COARSE,
+                 (k_prolong_flat<T, false><<<flat_grid(l), kFlatThreads, 0, stream>>>(
+                     g[l], g[l + 1], x[l + 1], v3(L[l]), iD[l], x[l], r[l], psum, pcnt, flags + l, sbox[l])));
+      if (direct)
+        set_mean_producer(nf);
+      else
+        reduce_wide(psum, 0, pcnt, 0, nf, kSlotSumR, kSlotCnt);
+    } else if (tiles[l][2] > 0) {
       WL_TIMED(l == 0 ? WL_K_PROLONG : WL_K_COARSE,
                (k_prolong_tile<T><<<tiles[l][2], kTileThreads, 0, stream>>>(
                    g[l], g[l + 1], x[l + 1], v3(L[l]), iD[l], x[l], r[l], red, flags + l, tiles[l][0],
