@@ -446,8 +446,51 @@ __global__ void __launch_bounds__(kFluxThreads) k_flux_bricks(Grid3 g, Vec3<T> u
   }
 }
 
-// BDIM blend: out = V + mu0 f + sum_j mu1_cj (f[I+e_j]-f[I-e_j])/2.
-// CORR = 0: u = out (predictor); CORR = 1: u = (u + out)/2 (corrector).
+// BDIM blend of face I of component c: out = V + mu0 f + sum_j mu1_cj
+// (f[I+e_j]-f[I-e_j])/2.  CORR = 0: u = out (predictor); CORR = 1: u = (u + out)/2
+// (corrector).
+template <typename T, int D, int CORR>
+__device__ __forceinline__ void bdim_face(const Grid3& g, const Vec3<T>& f, const Vec3<T>& V, const Vec3<T>& mu0,
+                                          const Vec9<T>& mu1, const Vec3<T>& u, int has_body, const StdBox& B,
+                                          int c, const int I[3], int idx) {
+  T acc;
+  bool fast = true;
+  for (int a = 0; a < D; ++a) fast = fast && I[a] >= 2 && I[a] <= g.n[a] - 1;
+  if (has_body && std_point<D>(B, g, I, 0)) {
+    acc = L_std<T>(g, B, c, I[c]) * f.c[c][idx];  // V = 0, mu0 = L, mu1 = 0 outside the box
+  } else if (has_body && fast) {
+    acc = V.c[c][idx] + mu0.c[c][idx] * f.c[c][idx];
+#pragma unroll
+    for (int j = 0; j < D; ++j) {
+      const int sj = g.s[j];
+      acc = acc + mu1.c[c * D + j][idx] * (T(0.5) * (f.c[c][idx + sj] - f.c[c][idx - sj]));
+    }
+  } else if (has_body) {
+    acc = V.c[c][idx] + mu0.c[c][idx] * f.c[c][idx];
+    for (int j = 0; j < D; ++j) {
+      int Jp[3] = {I[0], I[1], I[2]}, Jm[3] = {I[0], I[1], I[2]};
+      const int xp = I[j] + 1, xm = I[j] - 1;
+      bool ok = true;
+      if (g.per[j]) {
+        Jp[j] = wrapc(xp, j, g);
+        Jm[j] = wrapc(xm, j, g);
+      } else {
+        ok = xp <= g.n[j] + 1 && xm >= 0;
+        Jp[j] = xp;
+        Jm[j] = xm;
+      }
+      T grad = T(0);
+      if (ok)
+        grad = T(0.5) * (f.c[c][lin3<T, D>(g, Jp[0], Jp[1], Jp[2])] - f.c[c][lin3<T, D>(g, Jm[0], Jm[1], Jm[2])]);
+      acc = acc + mu1.c[c * D + j][idx] * grad;
+    }
+  } else {
+    acc = f.c[c][idx];  // mu0 = 1, mu1 = 0, V = 0 (boundary faces are reset by the BCs)
+  }
+  if (CORR) u.c[c][idx] = T(0.5) * (u.c[c][idx] + acc);
+  else u.c[c][idx] = acc;
+}
+
 template <typename T, int D, int CORR>
 __global__ void __launch_bounds__(kBlock) k_bdim(Grid3 g, Vec3<T> f, Vec3<T> V, Vec3<T> mu0,
                                                  Vec9<T> mu1, Vec3<T> u, int has_body, StdBox B) {
@@ -457,44 +500,7 @@ __global__ void __launch_bounds__(kBlock) k_bdim(Grid3 g, Vec3<T> f, Vec3<T> V, 
   for (int lin = blockIdx.x * kBlock + threadIdx.x; lin < total; lin += gridDim.x * kBlock) {
     const int I0 = lin % P0, t = lin / P0, I1 = t % P1, I2 = t / P1;
     const int I[3] = {I0, I1, I2};
-    const int idx = lin3<T, D>(g, I0, I1, I2);
-    T acc;
-    bool fast = true;
-    for (int a = 0; a < D; ++a) fast = fast && I[a] >= 2 && I[a] <= g.n[a] - 1;
-    if (has_body && std_point<D>(B, g, I, 0)) {
-      acc = L_std<T>(g, B, c, I[c]) * f.c[c][idx];  // V = 0, mu0 = L, mu1 = 0 outside the box
-    } else if (has_body && fast) {
-      acc = V.c[c][idx] + mu0.c[c][idx] * f.c[c][idx];
-#pragma unroll
-      for (int j = 0; j < D; ++j) {
-        const int sj = g.s[j];
-        acc = acc + mu1.c[c * D + j][idx] * (T(0.5) * (f.c[c][idx + sj] - f.c[c][idx - sj]));
-      }
-    } else if (has_body) {
-      acc = V.c[c][idx] + mu0.c[c][idx] * f.c[c][idx];
-      for (int j = 0; j < D; ++j) {
-        int Jp[3] = {I0, I1, I2}, Jm[3] = {I0, I1, I2};
-        const int xp = I[j] + 1, xm = I[j] - 1;
-        bool ok = true;
-        if (g.per[j]) {
-          Jp[j] = wrapc(xp, j, g);
-          Jm[j] = wrapc(xm, j, g);
-        } else {
-          ok = xp <= g.n[j] + 1 && xm >= 0;
-          Jp[j] = xp;
-          Jm[j] = xm;
-        }
-        T grad = T(0);
-        if (ok)
-          grad = T(0.5) * (f.c[c][lin3<T, D>(g, Jp[0], Jp[1], Jp[2])] -
-                           f.c[c][lin3<T, D>(g, Jm[0], Jm[1], Jm[2])]);
-        acc = acc + mu1.c[c * D + j][idx] * grad;
-      }
-    } else {
-      acc = f.c[c][idx];  // mu0 = 1, mu1 = 0, V = 0 (boundary faces are reset by the BCs)
-    }
-    if (CORR) u.c[c][idx] = T(0.5) * (u.c[c][idx] + acc);
-    else u.c[c][idx] = acc;
+    bdim_face<T, D, CORR>(g, f, V, mu0, mu1, u, has_body, B, c, I, lin3<T, D>(g, I0, I1, I2));
   }
 }
 
@@ -2001,6 +2007,189 @@ __global__ void __launch_bounds__(kFlatThreads) k_pcg_b_flat(Grid3 g, Vec3<T> L,
       }
       if (want_rho && !skip) part_rho_next[flat_block()] = sr;
       if (want_max) part_max[flat_block()] = sm;
+    }
+  }
+}
+
+// Divergence (or a given right-hand side), warm start and initial residual,
+// flat form (arithmetic of k_div_res): x = p wdt (if p) else the current x,
+// r = z - A x on active cells (0 elsewhere); partials of max|r| and of the mean
+// of r over the active cells.
+template <typename T, bool PER>
+__global__ void __launch_bounds__(kFlatThreads) k_div_res_flat(Grid3 g, Vec3<T> u, const T* rhs, const T* p, T wdt,
+                                                               Vec3<T> L, const T* iD, T* x, T* r, double* part_max,
+                                                               double* part_sum, double* part_cnt, int* flag,
+                                                               StdBox B) {
+  typedef typename Vec16<T>::type V;
+  constexpr int W = Vec16<T>::W;
+  if (flat_block() == 0 && threadIdx.x == 0) *flag = 0;
+  const FlatVec fv = flat_vec<T>(g);
+  double mx = 0.0, sr = 0.0, cnt = 0.0;
+  if (fv.ok) {
+    const FlatNbr<W, PER> o(g, fv);
+    const int id = fv.id;
+    const T* xs = p ? p : x;
+    const T sx = p ? wdt : T(1);
+    const V xv = ldv(xs + id), xy0 = ldv(xs + id + o.ym), xy1 = ldv(xs + id + o.yp), xz0 = ldv(xs + id + o.zm),
+            xz1 = ldv(xs + id + o.zp);
+    const T xm0 = xs[id + o.xm] * sx, xp0 = xs[id + W - 1 + o.xp] * sx;
+    V zv;
+    T* Z = reinterpret_cast<T*>(&zv);
+    if (rhs) {
+      zv = ldv(rhs + id);
+    } else {
+      const V ux = ldv(u.c[0] + id), uy = ldv(u.c[1] + id), uy1 = ldv(u.c[1] + id + o.yp), uz = ldv(u.c[2] + id),
+              uz1 = ldv(u.c[2] + id + o.zp);
+      const T ux1 = u.c[0][id + W - 1 + o.xp];
+      const T* UX = reinterpret_cast<const T*>(&ux);
+#pragma unroll
+      for (int w = 0; w < W; ++w) {
+        const T uxp = (w < W - 1) ? UX[w + 1] : ux1;
+        T z = T(0);
+        z = z + (uxp - UX[w]);
+        z = z + (reinterpret_cast<const T*>(&uy1)[w] - reinterpret_cast<const T*>(&uy)[w]);
+        z = z + (reinterpret_cast<const T*>(&uz1)[w] - reinterpret_cast<const T*>(&uz)[w]);
+        Z[w] = z;
+      }
+    }
+    T xc[W];
+#pragma unroll
+    for (int w = 0; w < W; ++w) xc[w] = reinterpret_cast<const T*>(&xv)[w] * sx;
+    V ro, xo;
+    T* RO = reinterpret_cast<T*>(&ro);
+    T* XO = reinterpret_cast<T*>(&xo);
+    auto lane = [&](const FlatCoef<T, W, PER>& cf, int w) {
+      T rr = T(0);
+      if (cf.d != T(0)) {
+        const T xm = (w > 0) ? xc[w - 1] : xm0, xp = (w < W - 1) ? xc[w + 1] : xp0;
+        const T ym = reinterpret_cast<const T*>(&xy0)[w] * sx, yp = reinterpret_cast<const T*>(&xy1)[w] * sx;
+        const T zm = reinterpret_cast<const T*>(&xz0)[w] * sx, zp = reinterpret_cast<const T*>(&xz1)[w] * sx;
+        T Ax = T(0);
+        Ax = Ax + cf.Lxp * (xp - xc[w]) - cf.Lxc * (xc[w] - xm);
+        Ax = Ax + cf.Lyp * (yp - xc[w]) - cf.Lyc * (xc[w] - ym);
+        Ax = Ax + cf.Lzp * (zp - xc[w]) - cf.Lzc * (xc[w] - zm);
+        rr = Z[w] - Ax;
+        sr += double(rr);
+        cnt += 1.0;
+      }
+      RO[w] = rr;
+      XO[w] = xc[w];
+      mx = fmax(mx, fabs(double(rr)));
+    };
+    if (flat_fast<W>(B, g, fv)) {
+      const FlatStd<T, W, PER> S(g, B, fv);
+#pragma unroll
+      for (int w = 0; w < W; ++w) lane(FlatCoef<T, W, PER>(S, B, w), w);
+    } else {
+      const FlatLoaded<T, W, PER> C(g, L, iD, fv, o);
+#pragma unroll
+      for (int w = 0; w < W; ++w) lane(FlatCoef<T, W, PER>(C, w), w);
+    }
+    if (p) stv_stream<T>(x + id, xo);
+    stv_stream<T>(r + id, ro);
+  }
+  sr = block_sum<kFlatThreads>(sr);
+  cnt = block_sum<kFlatThreads>(cnt);
+  mx = block_max<kFlatThreads>(mx);
+  if (threadIdx.x == 0) {
+    part_max[flat_block()] = mx;
+    part_sum[flat_block()] = sr;
+    part_cnt[flat_block()] = cnt;
+  }
+}
+
+// Projection update, flat form (arithmetic of k_project): u_a -= L_a (x[I] -
+// x[I-e_a]) on the interior faces of each vector, p = x / wdt.
+template <typename T, bool PER>
+__global__ void __launch_bounds__(kFlatThreads) k_project_flat(Grid3 g, Vec3<T> u, Vec3<T> L, const T* x, T* p,
+                                                               T wdt, StdBox B) {
+  typedef typename Vec16<T>::type V;
+  constexpr int W = Vec16<T>::W;
+  const FlatVec fv = flat_vec<T>(g);
+  if (!fv.ok) return;  // no barrier in this kernel
+  const FlatNbr<W, PER> o(g, fv);
+  const int id = fv.id;
+  const V xv = ldv(x + id), xy = ldv(x + id + o.ym), xz = ldv(x + id + o.zm);
+  const T xm0 = x[id + o.xm];
+  V u0 = ldv(u.c[0] + id), u1 = ldv(u.c[1] + id), u2 = ldv(u.c[2] + id);
+  const int a[3] = {fv.i0, fv.j, fv.k}, b[3] = {fv.i0 + W - 1, fv.j, fv.k};
+  const bool fast = std_miss<3>(B, g, a, b);
+  V l0, l1, l2;
+  if (!fast) {
+    l0 = ldv(L.c[0] + id);
+    l1 = ldv(L.c[1] + id);
+    l2 = ldv(L.c[2] + id);
+  }
+  const T* X = reinterpret_cast<const T*>(&xv);
+  const T* XY = reinterpret_cast<const T*>(&xy);
+  const T* XZ = reinterpret_cast<const T*>(&xz);
+  T* U0 = reinterpret_cast<T*>(&u0);
+  T* U1 = reinterpret_cast<T*>(&u1);
+  T* U2 = reinterpret_cast<T*>(&u2);
+  V pv;
+  T* PV = reinterpret_cast<T*>(&pv);
+  const T Ly = L_std<T>(g, B, 1, fv.j), Lz = L_std<T>(g, B, 2, fv.k);
+#pragma unroll
+  for (int w = 0; w < W; ++w) {
+    const T xc = X[w];
+    const T xmx = (w > 0) ? X[w - 1] : xm0;
+    const T L0 = fast ? L_std<T>(g, B, 0, fv.i0 + w) : reinterpret_cast<const T*>(&l0)[w];
+    const T L1 = fast ? Ly : reinterpret_cast<const T*>(&l1)[w];
+    const T L2 = fast ? Lz : reinterpret_cast<const T*>(&l2)[w];
+    U0[w] = U0[w] - L0 * (xc - xmx);
+    U1[w] = U1[w] - L1 * (xc - XY[w]);
+    U2[w] = U2[w] - L2 * (xc - XZ[w]);
+    PV[w] = xc / wdt;
+  }
+  stv_stream<T>(u.c[0] + id, u0);
+  stv_stream<T>(u.c[1] + id, u1);
+  stv_stream<T>(u.c[2] + id, u2);
+  if (p) stv_stream<T>(p + id, pv);
+}
+
+// BDIM blend, flat form (arithmetic of k_bdim) over the padded faces of one
+// component (blockIdx.z): vectors whose faces all lie outside the body box take
+// the closed form (u = L f, or u = f with no body) with vector loads and stores;
+// the others, and the vectors that reach past the padded row, go face by face.
+template <typename T, int CORR>
+__global__ void __launch_bounds__(kFlatThreads) k_bdim_flat(Grid3 g, Vec3<T> f, Vec3<T> V, Vec3<T> mu0,
+                                                            Vec9<T> mu1, Vec3<T> u, int has_body, StdBox B) {
+  typedef typename Vec16<T>::type VT;
+  constexpr int W = Vec16<T>::W;
+  const int c = blockIdx.z;
+  const int vr2 = g.n[0] / W + 2;  // vectors of a padded row: first cells 1 - W, 1, 1 + W, ...
+  const int P1 = g.n[1] + 2;
+  const int t = blockIdx.x * kFlatThreads + threadIdx.x;
+  if (t >= vr2 * P1) return;  // no barrier in this kernel
+  const int m = t % vr2, j = t / vr2, k = blockIdx.y;
+  const int i0 = 1 - W + m * W;
+  const int id = i0 + j * g.s[1] + k * g.s[2];
+  const bool whole = i0 >= 0 && i0 + W - 1 <= g.n[0] + 1;
+  bool fastv = true;
+  if (has_body) {
+    const int a[3] = {i0, j, k}, b[3] = {i0 + W - 1, j, k};
+    fastv = std_miss<3>(B, g, a, b);
+  }
+  if (fastv && whole) {
+    const VT fv = ldv(f.c[c] + id);
+    VT uv;
+    if (CORR) uv = ldv(u.c[c] + id);
+    const T* F = reinterpret_cast<const T*>(&fv);
+    T* U = reinterpret_cast<T*>(&uv);
+#pragma unroll
+    for (int w = 0; w < W; ++w) {
+      const int Ic = (c == 0) ? i0 + w : (c == 1 ? j : k);
+      const T acc = has_body ? L_std<T>(g, B, c, Ic) * F[w] : F[w];
+      U[w] = CORR ? T(0.5) * (U[w] + acc) : acc;
+    }
+    stv_stream<T>(u.c[c] + id, uv);
+  } else {
+#pragma unroll
+    for (int w = 0; w < W; ++w) {
+      const int i = i0 + w;
+      if (i < 0 || i > g.n[0] + 1) continue;
+      const int I[3] = {i, j, k};
+      bdim_face<T, 3, CORR>(g, f, V, mu0, mu1, u, has_body, B, c, I, id + w);
     }
   }
 }

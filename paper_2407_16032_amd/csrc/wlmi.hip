@@ -773,6 +773,12 @@ struct Impl : SimBase {
   }
 
   void set_mean_producer(int grid) { slot_n[kSlotSumR] = slot_n[kSlotCnt] = grid; }
+  // flat BDIM blend: the vectors of the padded rows of a plane x the padded planes x D
+  dim3 bdim_grid() const {
+    const int vr2 = g[0].n[0] / Vec16<T>::W + 2;
+    return dim3((unsigned)((vr2 * (g[0].n[1] + 2) + kFlatThreads - 1) / kFlatThreads), (unsigned)(g[0].n[2] + 2),
+                (unsigned)D);
+  }
   dim3 flat_grid(int l) const {
     return dim3((unsigned)flat_plane_blocks(plan.lev[l], sizeof(T)), (unsigned)g[l].n[2]);
   }
@@ -1051,6 +1057,42 @@ struct Impl : SimBase {
     return WL_OK;
   }
 
+  // divergence (or rhs), warm start and initial residual on the fine level; leaves
+  // the max|r| and mean partials with their counts set
+  void div_res(T* const uu[3], const T* rhs, const T* pp, T wdt) {
+    const int nf = (int)nflat[0];
+    // the flat kernel reads rhs in 16-byte vectors starting at x = 1: a caller's
+    // array without the fields' front padding takes the generic kernel
+    const bool aligned = rhs == nullptr || (reinterpret_cast<uintptr_t>(rhs + 1) % 16) == 0;
+    if (nf > 0 && aligned) {
+      const bool direct = nf <= kCollapseMin;
+      double* const pmax = direct ? slot(kSlotRmax) : wide;
+      double* const psum = direct ? slot(kSlotSumR) : wide + wide_n;
+      double* const pcnt = direct ? slot(kSlotCnt) : wide + 2 * wide_n;
+      if (desc.periodic_mask)
+        WL_TIMED(WL_K_DIVRES, (k_div_res_flat<T, true><<<flat_grid(0), kFlatThreads, 0, stream>>>(
+                                  g[0], v3(uu), rhs, pp, wdt, v3(L[0]), iD[0], x[0], r[0], pmax, psum, pcnt, flags,
+                                  sbox[0])));
+      else
+        WL_TIMED(WL_K_DIVRES, (k_div_res_flat<T, false><<<flat_grid(0), kFlatThreads, 0, stream>>>(
+                                  g[0], v3(uu), rhs, pp, wdt, v3(L[0]), iD[0], x[0], r[0], pmax, psum, pcnt, flags,
+                                  sbox[0])));
+      if (direct) {
+        slot_n[kSlotRmax] = nf;
+        set_mean_producer(nf);
+      } else {
+        reduce_wide(psum, 0, pcnt, 0, nf, kSlotSumR, kSlotCnt);
+        reduce_wide(pmax, 1, nullptr, 0, nf, kSlotRmax, -1);
+      }
+    } else {
+      WL_TIMED(WL_K_DIVRES, (k_div_res<T, D><<<nb[0], kBlock, 0, stream>>>(g[0], v3(uu), rhs, pp, wdt, v3(L[0]),
+                                                                            iD[0], x[0], r[0], slot(kSlotRmax), red,
+                                                                            flags, sbox[0])));
+      slot_n[kSlotRmax] = nb[0];
+      set_mean_producer(nb[0]);
+    }
+  }
+
   wl_status project(T* const uu[3], double w, wl_solve_stats* st) {
     const T wdt = T(w * dt);
     const bool guided = pg_on && pg_mode >= 1 && pg_hist >= 2;
@@ -1058,39 +1100,37 @@ struct Impl : SimBase {
       // multigrid judges the guess: it is used only if its initial residual is below
       // that of the plain warm start x0 = p w dt
       double res_plain = 0.0, res_guess = 0.0;
-      WL_TIMED(WL_K_DIVRES, (k_div_res<T, D><<<nb[0], kBlock, 0, stream>>>(g[0], v3(uu), nullptr, p, wdt, v3(L[0]),
-                                                                            iD[0], x[0], r[0], slot(kSlotRmax), red,
-                                                                            flags, sbox[0])));
-      slot_n[kSlotRmax] = nb[0];
+      div_res(uu, nullptr, p, wdt);
       wl_status s0 = read_scalar_max(kSlotRmax, &res_plain);
       if (s0 != WL_OK) return s0;
       pg_guess(uu, w * dt);  // x[0] = learned guess
-      WL_TIMED(WL_K_DIVRES, (k_div_res<T, D><<<nb[0], kBlock, 0, stream>>>(g[0], v3(uu), nullptr, nullptr, wdt,
-                                                                            v3(L[0]), iD[0], x[0], r[0],
-                                                                            slot(kSlotRmax), red, flags, sbox[0])));
+      div_res(uu, nullptr, nullptr, wdt);
       if ((s0 = read_scalar_max(kSlotRmax, &res_guess)) != WL_OK) return s0;
       ++pg_tried;
       if (res_guess < res_plain) {
         ++pg_used;
       } else {
-        WL_TIMED(WL_K_DIVRES, (k_div_res<T, D><<<nb[0], kBlock, 0, stream>>>(g[0], v3(uu), nullptr, p, wdt,
-                                                                              v3(L[0]), iD[0], x[0], r[0],
-                                                                              slot(kSlotRmax), red, flags, sbox[0])));
+        div_res(uu, nullptr, p, wdt);
       }
     } else {
-      WL_TIMED(WL_K_DIVRES, (k_div_res<T, D><<<nb[0], kBlock, 0, stream>>>(g[0], v3(uu), nullptr, p, wdt, v3(L[0]),
-                                                                            iD[0], x[0], r[0], slot(kSlotRmax), red,
-                                                                            flags, sbox[0])));
+      div_res(uu, nullptr, p, wdt);
     }
-    set_mean_producer(nb[0]);
-    slot_n[kSlotRmax] = nb[0];
     WL_HIP(hipGetLastError());
     wl_status s = mg_loop(desc.mg_tol, desc.mg_itmax, st);
     if (s != WL_OK) return s;
     if (guided && pg_mode == 2) pg_snapshot(w * dt);
     if (pg_on) WL_HIP(hipMemcpyAsync(p2, p, plan.lev[0].elems * sizeof(T), hipMemcpyDeviceToDevice, stream));
-    WL_TIMED(WL_K_PROJECT, (k_project<T, D><<<nb[0], kBlock, 0, stream>>>(g[0], v3(uu), v3(L[0]), x[0], p, wdt,
-                                                                          sbox[0])));
+    if (nflat[0] > 0) {
+      if (desc.periodic_mask)
+        WL_TIMED(WL_K_PROJECT, (k_project_flat<T, true><<<flat_grid(0), kFlatThreads, 0, stream>>>(
+                                   g[0], v3(uu), v3(L[0]), x[0], p, wdt, sbox[0])));
+      else
+        WL_TIMED(WL_K_PROJECT, (k_project_flat<T, false><<<flat_grid(0), kFlatThreads, 0, stream>>>(
+                                   g[0], v3(uu), v3(L[0]), x[0], p, wdt, sbox[0])));
+    } else {
+      WL_TIMED(WL_K_PROJECT, (k_project<T, D><<<nb[0], kBlock, 0, stream>>>(g[0], v3(uu), v3(L[0]), x[0], p, wdt,
+                                                                            sbox[0])));
+    }
     WL_HIP(hipGetLastError());
     if (pg_on) ++pg_hist;
     if (pg_on && pg_mode == 2 && ring_used > 0) {
@@ -1299,12 +1339,8 @@ struct Impl : SimBase {
     // the internal fine-level x, which the vectorised kernels require
     const size_t bytes = (size_t)plan.lev[0].elems * sizeof(T);
     if (xin) WL_HIP(hipMemcpyAsync(x[0], xin, bytes, hipMemcpyDeviceToDevice, stream));
-    WL_TIMED(WL_K_DIVRES, (k_div_res<T, D><<<nb[0], kBlock, 0, stream>>>(g[0], v3(u[cur]), (const T*)rhs, nullptr,
-                                                                          T(0), v3(L[0]), iD[0], x[0], r[0],
-                                                                          slot(kSlotRmax), red, flags, sbox[0])));
+    div_res(u[cur], (const T*)rhs, nullptr, T(0));
     WL_HIP(hipGetLastError());
-    set_mean_producer(nb[0]);
-    slot_n[kSlotRmax] = nb[0];
     wl_status s = mg_loop(tol > 0 ? tol : desc.mg_tol, itmax > 0 ? itmax : desc.mg_itmax, st);
     if (s != WL_OK) return s;
     if (xin) WL_HIP(hipMemcpyAsync(xin, x[0], bytes, hipMemcpyDeviceToDevice, stream));
@@ -1344,8 +1380,12 @@ struct Impl : SimBase {
     const int hb = has_body ? 1 : 0;
     // predictor
     if ((s = flux(A, A, hb)) != WL_OK) return s;
-    WL_TIMED(WL_K_BDIM, (k_bdim<T, D, 0><<<dim3(nb_face, D), kBlock, 0, stream>>>(g[0], v3(ft), v3(V), v3(mu0),
-                                                                                 v9(mu1), v3(B), hb, sbox[0])));
+    if (nflat[0] > 0)
+      WL_TIMED(WL_K_BDIM, (k_bdim_flat<T, 0><<<bdim_grid(), kFlatThreads, 0, stream>>>(g[0], v3(ft), v3(V), v3(mu0),
+                                                                                    v9(mu1), v3(B), hb, sbox[0])));
+    else
+      WL_TIMED(WL_K_BDIM, (k_bdim<T, D, 0><<<dim3(nb_face, D), kBlock, 0, stream>>>(g[0], v3(ft), v3(V), v3(mu0),
+                                                                                   v9(mu1), v3(B), hb, sbox[0])));
     const bool ex = desc.convective_exit != 0;
     if (ex) {
       const int m = g[0].n[1] * (D == 3 ? g[0].n[2] : 1);
@@ -1370,8 +1410,12 @@ struct Impl : SimBase {
     }
     // corrector
     if ((s = flux(B, A, hb)) != WL_OK) return s;
-    WL_TIMED(WL_K_BDIM, (k_bdim<T, D, 1><<<dim3(nb_face, D), kBlock, 0, stream>>>(g[0], v3(ft), v3(V), v3(mu0),
-                                                                                 v9(mu1), v3(B), hb, sbox[0])));
+    if (nflat[0] > 0)
+      WL_TIMED(WL_K_BDIM, (k_bdim_flat<T, 1><<<bdim_grid(), kFlatThreads, 0, stream>>>(g[0], v3(ft), v3(V), v3(mu0),
+                                                                                    v9(mu1), v3(B), hb, sbox[0])));
+    else
+      WL_TIMED(WL_K_BDIM, (k_bdim<T, D, 1><<<dim3(nb_face, D), kBlock, 0, stream>>>(g[0], v3(ft), v3(V), v3(mu0),
+                                                                                   v9(mu1), v3(B), hb, sbox[0])));
     WL_HIP(hipGetLastError());
     if ((s = bc(B, ex)) != WL_OK) return s;
     if ((s = project(B, 0.5, &s2)) != WL_OK) return s;
@@ -1503,11 +1547,7 @@ struct Impl : SimBase {
     WL_TIMED(WL_K_ADJOINT, (k_adj_proj_rhs<T, D><<<nb[0], kBlock, 0, stream>>>(
                                g[0], v3(w), v3(L[0]), with_p ? apb : nullptr, T(1.0 / wdt), iD[0], arhs)));
     fill_field(x[0], T(0));
-    WL_TIMED(WL_K_DIVRES, (k_div_res<T, D><<<nb[0], kBlock, 0, stream>>>(g[0], v3(u[cur]), arhs, nullptr, T(0),
-                                                                          v3(L[0]), iD[0], x[0], r[0],
-                                                                          slot(kSlotRmax), red, flags, sbox[0])));
-    set_mean_producer(nb[0]);
-    slot_n[kSlotRmax] = nb[0];
+    div_res(u[cur], arhs, nullptr, T(0));
     WL_HIP(hipGetLastError());
     wl_status s = mg_loop(tol, desc.mg_itmax, st);
     if (s != WL_OK) return s;
