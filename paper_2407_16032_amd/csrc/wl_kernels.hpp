@@ -2183,6 +2183,32 @@ __global__ void __launch_bounds__(kFlatThreads) k_bdim_flat(Grid3 g, Vec3<T> f, 
       U[w] = CORR ? T(0.5) * (U[w] + acc) : acc;
     }
     stv_stream<T>(u.c[c] + id, uv);
+  } else if (whole && i0 >= 2 && i0 + W - 1 <= g.n[0] - 1 && j >= 2 && j <= g.n[1] - 1 && k >= 2 &&
+             k <= g.n[2] - 1) {
+    // near the body, away from the domain boundary: the blend of bdim_face with
+    // whole-vector loads of f, V, mu0, mu1 (the x neighbours of f from the lanes)
+    const T* fc = f.c[c];
+    const VT fv = ldv(fc + id), fy0 = ldv(fc + id - g.s[1]), fy1 = ldv(fc + id + g.s[1]),
+             fz0 = ldv(fc + id - g.s[2]), fz1 = ldv(fc + id + g.s[2]);
+    const T fx0 = fc[id - 1], fx1 = fc[id + W];
+    const VT vv = ldv(V.c[c] + id), m0 = ldv(mu0.c[c] + id), mx = ldv(mu1.c[c * 3] + id),
+             my = ldv(mu1.c[c * 3 + 1] + id), mz = ldv(mu1.c[c * 3 + 2] + id);
+    VT uv;
+    if (CORR) uv = ldv(u.c[c] + id);
+    const T* F = reinterpret_cast<const T*>(&fv);
+    T* U = reinterpret_cast<T*>(&uv);
+#pragma unroll
+    for (int w = 0; w < W; ++w) {
+      const T xm = (w > 0) ? F[w - 1] : fx0, xp = (w < W - 1) ? F[w + 1] : fx1;
+      T acc = reinterpret_cast<const T*>(&vv)[w] + reinterpret_cast<const T*>(&m0)[w] * F[w];
+      acc = acc + reinterpret_cast<const T*>(&mx)[w] * (T(0.5) * (xp - xm));
+      acc = acc + reinterpret_cast<const T*>(&my)[w] *
+                      (T(0.5) * (reinterpret_cast<const T*>(&fy1)[w] - reinterpret_cast<const T*>(&fy0)[w]));
+      acc = acc + reinterpret_cast<const T*>(&mz)[w] *
+                      (T(0.5) * (reinterpret_cast<const T*>(&fz1)[w] - reinterpret_cast<const T*>(&fz0)[w]));
+      U[w] = CORR ? T(0.5) * (U[w] + acc) : acc;
+    }
+    stv_stream<T>(u.c[c] + id, uv);
   } else {
 #pragma unroll
     for (int w = 0; w < W; ++w) {
