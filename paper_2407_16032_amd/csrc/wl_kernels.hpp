@@ -1,8 +1,10 @@
 // HIP kernels of the BDIM projection step (gfx950).  Each kernel cites the
 // part of the method it computes; the discrete formulas are documented in
-// include/wlmi.h and the design notes.  All kernels are grid-stride loops
-// with kBlock threads and at most kMaxBlocks blocks, so that per-block
-// partial sums fit the reduction slots.
+// include/wlmi.h.  Three forms share the arithmetic: generic grid-stride
+// kernels (kBlock threads, at most kMaxBlocks blocks, so that per-block partial
+// sums fit the reduction slots), z-marching tiles for the large 3-D levels, and
+// flat one-vector-per-thread kernels, whose many blocks leave their partials
+// in a separate area that a two-stage sum reduces.
 #pragma once
 #include "wl_device.hpp"
 
@@ -15,16 +17,10 @@ namespace wl {
 #ifndef WL_TZ
 #define WL_TZ 32
 #endif
-#ifndef WL_TILE_ATTR
-#define WL_TILE_ATTR
-#endif
 constexpr int kTX = 64, kTY = WL_TY, kTZ = WL_TZ, kTileThreads = kTX * kTY;
 // planes between the issue of a marching tile's loads and their use
 #ifndef WL_PCG_PF
 #define WL_PCG_PF 2
-#endif
-#ifndef WL_PCGB_NOLDS
-#define WL_PCGB_NOLDS 0
 #endif
 constexpr int kPF = WL_PCG_PF;
 constexpr int kTileMinZ = 8;       // shortest march of a level's tiles
@@ -858,7 +854,7 @@ __device__ __forceinline__ void prolong_march(const Grid3& f, const Grid3& c, co
 }
 
 template <typename T>
-__global__ void __launch_bounds__(kTileThreads) WL_TILE_ATTR k_prolong_tile(Grid3 f, Grid3 c, const T* xc, Vec3<T> L, const T* iD,
+__global__ void __launch_bounds__(kTileThreads) k_prolong_tile(Grid3 f, Grid3 c, const T* xc, Vec3<T> L, const T* iD,
                                                       T* xf, T* rf, double* red, int* flag, int tiles_x,
                                                       int tiles_y, int ntiles, int tz, StdBox B) {
   if (blockIdx.x == 0 && threadIdx.x == 0) *flag = 0;
@@ -1138,7 +1134,7 @@ __device__ __forceinline__ void pcg_a_march(const Grid3& g, const Vec3<T>& L, co
 // PCG pass A, tiled form (see k_pcg_a for the arithmetic).  With STOREQ = 0,
 // q = A e is only reduced into sigma, not stored: the tiled pass B recomputes it.
 template <typename T, int FINE, int STOREQ = 1>
-__global__ void __launch_bounds__(kTileThreads) WL_TILE_ATTR k_pcg_a_tile(Grid3 g, Vec3<T> L, const T* iD, const T* r,
+__global__ void __launch_bounds__(kTileThreads) k_pcg_a_tile(Grid3 g, Vec3<T> L, const T* iD, const T* r,
                                                              const T* eo, T* en, T* q, double* red, int k,
                                                              RedN rn, double* part_sig, int* flag, int tiles_x,
                                                              int tiles_y, int ntiles, int tz, StdBox B) {
@@ -1174,28 +1170,13 @@ __device__ __forceinline__ void pcg_b_march(const Grid3& g, const Vec3<T>& L, co
   const int hcol = G.hb ? G.hcol : col;
   const bool use_ring = G.ring && G.hb;
   // own column: e and L_z, x, r, iD of a plane (raw: used two iterations later)
-#if WL_PCGB_NOLDS
-  const int nxp = G.own ? G.opx : 0, nyp = G.own ? G.opy : 0;
-  const int nxm = G.own ? ((g.per[0] && G.i == 1) ? g.n[0] - 1 : -1) : 0;
-  const int nym = G.own ? ((g.per[1] && G.j == 1) ? (g.n[1] - 1) * s1 : -s1) : 0;
-  struct Raw {
-    T e, l, x, r, d, exm, exp, eym, eyp;
-  };
-#else
   struct Raw {
     T e, l, x, r, d;
   };
-#endif
   auto own = [&](int zz) -> Raw {
     const int zw = clamp_plane(g, min(zz, G.z1)), id = col + zw * s2;  // see pcg_a_march
     Raw v;
     v.e = e[id];
-#if WL_PCGB_NOLDS
-    v.exm = e[id + nxm];
-    v.exp = e[id + nxp];
-    v.eym = e[id + nym];
-    v.eyp = e[id + nyp];
-#endif
     v.l = FAST ? L_std<T>(g, B, 2, zw) : L.c[2][id];
     v.x = ld_stream(x + id);
     v.r = ld_stream(r + id);
@@ -1212,12 +1193,10 @@ __device__ __forceinline__ void pcg_b_march(const Grid3& g, const Vec3<T>& L, co
     a_new = own(z + kPF);
     h_new = ring(z + kPF);
     const T ec = cur.e, ep = nxt.e, L2c = cur.l, L2p = nxt.l, dc = cur.d;
-#if !WL_PCGB_NOLDS
     T(*P)[kTX + 2] = sE[z & 1];
     P[G.ty + 1][G.tx + 1] = ec;
     if (G.ring) P[G.sy][G.sx] = use_ring ? hr : T(0);
     __syncthreads();
-#endif
     if (G.own) {
       const int id = col + z * s2;
       T rr = cur.r;
@@ -1225,12 +1204,8 @@ __device__ __forceinline__ void pcg_b_march(const Grid3& g, const Vec3<T>& L, co
       if (!skip) {
         T qq = T(0);
         if (dc != T(0)) {
-#if WL_PCGB_NOLDS
-          const T xm = cur.exm, xp = cur.exp, ym = cur.eym, yp = cur.eyp;
-#else
           const T xm = P[G.ty + 1][G.tx], xp = P[G.ty + 1][G.tx + 2];
           const T ym = P[G.ty][G.tx + 1], yp = P[G.ty + 2][G.tx + 1];
-#endif
           const T Lxp = FAST ? Lxp0 : L.c[0][id + G.opx], Lxc = FAST ? Lxc0 : L.c[0][id];
           const T Lyp = FAST ? Lyp0 : L.c[1][id + G.opy], Lyc = FAST ? Lyc0 : L.c[1][id];
           qq = qq + Lxp * (xp - ec) - Lxc * (ec - xm);
@@ -1269,7 +1244,7 @@ __device__ __forceinline__ void pcg_b_march(const Grid3& g, const Vec3<T>& L, co
 // r -= alpha q on the interior, with the same scalars, stopping rule, mean removal
 // (sweep 0) and partials (rho_{k+1}, max|r|) as the flat pass B.
 template <typename T, int FINE>
-__global__ void __launch_bounds__(kTileThreads) WL_TILE_ATTR k_pcg_b_tile(Grid3 g, Vec3<T> L, const T* iD, const T* e, T* x,
+__global__ void __launch_bounds__(kTileThreads) k_pcg_b_tile(Grid3 g, Vec3<T> L, const T* iD, const T* e, T* x,
                                                              T* r, double* red, int k, RedN rn, double* part_rho_next,
                                                              double* part_max, int want_rho, int want_max, int* flag,
                                                              int tiles_x, int tiles_y, int ntiles, int tz, StdBox B) {
