@@ -1807,12 +1807,14 @@ struct FlatCoef {
   }
 };
 
+// (FINE = 1 only makes the fine-level launches of the flat kernels separate
+// symbols in kernel traces.)
 // PCG pass A, flat form, in two launches (arithmetic of k_pcg_a_tile with
 // STOREQ = 0).  A1 is pointwise: e_new = iD r + beta e_old (sweep 0: iD (r - m),
 // without reading e_old) and the rho_0 partial; A2 reads e_new with its
 // neighbours and leaves the sigma = e.Ae partial.  Together they move one field
 // more than the tiled pass, but both stream at the flat kernels' rate.
-template <typename T, bool PER>
+template <typename T, bool PER, int FINE>
 __global__ void __launch_bounds__(kFlatThreads) k_pcg_a1_flat(Grid3 g, const T* iD, const T* r, const T* eo, T* en,
                                                               double* red, int k, RedN rn, double* part_rho0,
                                                               int* flag, StdBox B) {
@@ -1849,7 +1851,7 @@ __global__ void __launch_bounds__(kFlatThreads) k_pcg_a1_flat(Grid3 g, const T* 
   }
 }
 
-template <typename T, bool PER>
+template <typename T, bool PER, int FINE>
 __global__ void __launch_bounds__(kFlatThreads) k_pcg_a2_flat(Grid3 g, Vec3<T> L, const T* iD, const T* e,
                                                               double* part_sig, int* flag, StdBox B) {
   typedef typename Vec16<T>::type V;
@@ -1893,7 +1895,7 @@ __global__ void __launch_bounds__(kFlatThreads) k_pcg_a2_flat(Grid3 g, Vec3<T> L
 
 // PCG pass B, flat form (arithmetic of k_pcg_b_tile): q = A e from e and its
 // neighbours, x += alpha e, r -= alpha q, partials of rho_{k+1} and max|r|.
-template <typename T, bool PER>
+template <typename T, bool PER, int FINE>
 __global__ void __launch_bounds__(kFlatThreads) k_pcg_b_flat(Grid3 g, Vec3<T> L, const T* iD, const T* e, T* x,
                                                              T* r, double* red, int k, RedN rn,
                                                              double* part_rho_next, double* part_max, int want_rho,
@@ -2200,7 +2202,7 @@ __global__ void __launch_bounds__(kFlatThreads) k_bdim_flat(Grid3 g, Vec3<T> f, 
 // of two rows of two planes (the vectors of both levels start at odd x).  r_c is
 // the children's sum on active coarse cells (0 elsewhere), x_c = 0, and the
 // partials of the mean of r_c.
-template <typename T, bool PER>
+template <typename T, bool PER, int FINE>
 __global__ void __launch_bounds__(kFlatThreads) k_restrict_flat(Grid3 f, Grid3 c, const T* rf, const T* iDc, T* rc,
                                                                 T* xc, double* part_sum, double* part_cnt, int* flag,
                                                                 StdBox Bc) {
@@ -2256,7 +2258,7 @@ __global__ void __launch_bounds__(kFlatThreads) k_restrict_flat(Grid3 f, Grid3 c
 // parent h; the other parents the stencil reaches are the x neighbours of the
 // end lanes and one coarse row and plane beside (whichever of j - 1, j + 1 and
 // k - 1, k + 1 leaves the parent's row or plane).
-template <typename T, bool PER>
+template <typename T, bool PER, int FINE>
 __global__ void __launch_bounds__(kFlatThreads) k_prolong_flat(Grid3 f, Grid3 c, const T* xc, Vec3<T> L,
                                                                const T* iD, T* xf, T* rf, double* part_sum,
                                                                double* part_cnt, int* flag, StdBox B) {

@@ -837,15 +837,39 @@ struct Impl : SimBase {
       double* const wmax = direct ? slot(kSlotRmax) : wide + 3 * wide_n;
       if (nf > 0) {
         if (desc.periodic_mask) {
-          WL_TIMED(kidA, (k_pcg_a1_flat<T, true><<<flat_grid(l), kFlatThreads, 0, stream>>>(
-                              g[l], iD[l], r[l], eo, en, red, k, rn, wrho0, flags + l, sbox[l])));
-          WL_TIMED(kidA2, (k_pcg_a2_flat<T, true><<<flat_grid(l), kFlatThreads, 0, stream>>>(
-                              g[l], v3(L[l]), iD[l], en, wsig, flags + l, sbox[l])));
+          {
+            if (l == 0)
+              WL_TIMED(kidA, (k_pcg_a1_flat<T, true, 1><<<flat_grid(l), kFlatThreads, 0, stream>>>(
+                                  g[l], iD[l], r[l], eo, en, red, k, rn, wrho0, flags + l, sbox[l])));
+            else
+              WL_TIMED(kidA, (k_pcg_a1_flat<T, true, 0><<<flat_grid(l), kFlatThreads, 0, stream>>>(
+                                  g[l], iD[l], r[l], eo, en, red, k, rn, wrho0, flags + l, sbox[l])));
+          }
+          {
+            if (l == 0)
+              WL_TIMED(kidA2, (k_pcg_a2_flat<T, true, 1><<<flat_grid(l), kFlatThreads, 0, stream>>>(
+                                  g[l], v3(L[l]), iD[l], en, wsig, flags + l, sbox[l])));
+            else
+              WL_TIMED(kidA2, (k_pcg_a2_flat<T, true, 0><<<flat_grid(l), kFlatThreads, 0, stream>>>(
+                                  g[l], v3(L[l]), iD[l], en, wsig, flags + l, sbox[l])));
+          }
         } else {
-          WL_TIMED(kidA, (k_pcg_a1_flat<T, false><<<flat_grid(l), kFlatThreads, 0, stream>>>(
-                              g[l], iD[l], r[l], eo, en, red, k, rn, wrho0, flags + l, sbox[l])));
-          WL_TIMED(kidA2, (k_pcg_a2_flat<T, false><<<flat_grid(l), kFlatThreads, 0, stream>>>(
-                              g[l], v3(L[l]), iD[l], en, wsig, flags + l, sbox[l])));
+          {
+            if (l == 0)
+              WL_TIMED(kidA, (k_pcg_a1_flat<T, false, 1><<<flat_grid(l), kFlatThreads, 0, stream>>>(
+                                  g[l], iD[l], r[l], eo, en, red, k, rn, wrho0, flags + l, sbox[l])));
+            else
+              WL_TIMED(kidA, (k_pcg_a1_flat<T, false, 0><<<flat_grid(l), kFlatThreads, 0, stream>>>(
+                                  g[l], iD[l], r[l], eo, en, red, k, rn, wrho0, flags + l, sbox[l])));
+          }
+          {
+            if (l == 0)
+              WL_TIMED(kidA2, (k_pcg_a2_flat<T, false, 1><<<flat_grid(l), kFlatThreads, 0, stream>>>(
+                                  g[l], v3(L[l]), iD[l], en, wsig, flags + l, sbox[l])));
+            else
+              WL_TIMED(kidA2, (k_pcg_a2_flat<T, false, 0><<<flat_grid(l), kFlatThreads, 0, stream>>>(
+                                  g[l], v3(L[l]), iD[l], en, wsig, flags + l, sbox[l])));
+          }
         }
         ga = 1;
       } else if (tiles[l][2] > 0) {
@@ -888,13 +912,27 @@ struct Impl : SimBase {
       int gbk = gb;
       if (nf > 0) {
         if (desc.periodic_mask)
-          WL_TIMED(kidB, (k_pcg_b_flat<T, true><<<flat_grid(l), kFlatThreads, 0, stream>>>(
-                              g[l], v3(L[l]), iD[l], en, x[l], r[l], red, k, rn, wrho, wmax, wr, wm, flags + l,
-                              sbox[l])));
+          {
+            if (l == 0)
+              WL_TIMED(kidB, (k_pcg_b_flat<T, true, 1><<<flat_grid(l), kFlatThreads, 0, stream>>>(
+                                  g[l], v3(L[l]), iD[l], en, x[l], r[l], red, k, rn, wrho, wmax, wr, wm, flags + l,
+                                  sbox[l])));
+            else
+              WL_TIMED(kidB, (k_pcg_b_flat<T, true, 0><<<flat_grid(l), kFlatThreads, 0, stream>>>(
+                                  g[l], v3(L[l]), iD[l], en, x[l], r[l], red, k, rn, wrho, wmax, wr, wm, flags + l,
+                                  sbox[l])));
+          }
         else
-          WL_TIMED(kidB, (k_pcg_b_flat<T, false><<<flat_grid(l), kFlatThreads, 0, stream>>>(
-                              g[l], v3(L[l]), iD[l], en, x[l], r[l], red, k, rn, wrho, wmax, wr, wm, flags + l,
-                              sbox[l])));
+          {
+            if (l == 0)
+              WL_TIMED(kidB, (k_pcg_b_flat<T, false, 1><<<flat_grid(l), kFlatThreads, 0, stream>>>(
+                                  g[l], v3(L[l]), iD[l], en, x[l], r[l], red, k, rn, wrho, wmax, wr, wm, flags + l,
+                                  sbox[l])));
+            else
+              WL_TIMED(kidB, (k_pcg_b_flat<T, false, 0><<<flat_grid(l), kFlatThreads, 0, stream>>>(
+                                  g[l], v3(L[l]), iD[l], en, x[l], r[l], red, k, rn, wrho, wmax, wr, wm, flags + l,
+                                  sbox[l])));
+          }
         if (direct) {
           if (wr) slot_n[kSlotRho0 + k + 1] = nf;
           if (wm) slot_n[kSlotRmax] = nf;
@@ -974,13 +1012,27 @@ struct Impl : SimBase {
       double* const psum = direct ? slot(kSlotSumR) : wide;
       double* const pcnt = direct ? slot(kSlotCnt) : wide + wide_n;
       if (desc.periodic_mask)
-        WL_TIMED(l == 0 ? WL_K_RESTRICT : WL_K_COARSE,
-                 (k_restrict_flat<T, true><<<flat_grid(l + 1), kFlatThreads, 0, stream>>>(
-                     g[l], g[l + 1], r[l], iD[l + 1], r[l + 1], x[l + 1], psum, pcnt, flags + l + 1, sbox[l + 1])));
+        {
+          if (l == 0)
+            WL_TIMED(l == 0 ? WL_K_RESTRICT : WL_K_COARSE,
+                     (k_restrict_flat<T, true, 1><<<flat_grid(l + 1), kFlatThreads, 0, stream>>>(
+                         g[l], g[l + 1], r[l], iD[l + 1], r[l + 1], x[l + 1], psum, pcnt, flags + l + 1, sbox[l + 1])));
+          else
+            WL_TIMED(l == 0 ? WL_K_RESTRICT : WL_K_COARSE,
+                     (k_restrict_flat<T, true, 0><<<flat_grid(l + 1), kFlatThreads, 0, stream>>>(
+                         g[l], g[l + 1], r[l], iD[l + 1], r[l + 1], x[l + 1], psum, pcnt, flags + l + 1, sbox[l + 1])));
+        }
       else
-        WL_TIMED(l == 0 ? WL_K_RESTRICT : WL_K_COARSE,
-                 (k_restrict_flat<T, false><<<flat_grid(l + 1), kFlatThreads, 0, stream>>>(
-                     g[l], g[l + 1], r[l], iD[l + 1], r[l + 1], x[l + 1], psum, pcnt, flags + l + 1, sbox[l + 1])));
+        {
+          if (l == 0)
+            WL_TIMED(l == 0 ? WL_K_RESTRICT : WL_K_COARSE,
+                     (k_restrict_flat<T, false, 1><<<flat_grid(l + 1), kFlatThreads, 0, stream>>>(
+                         g[l], g[l + 1], r[l], iD[l + 1], r[l + 1], x[l + 1], psum, pcnt, flags + l + 1, sbox[l + 1])));
+          else
+            WL_TIMED(l == 0 ? WL_K_RESTRICT : WL_K_COARSE,
+                     (k_restrict_flat<T, false, 0><<<flat_grid(l + 1), kFlatThreads, 0, stream>>>(
+                         g[l], g[l + 1], r[l], iD[l + 1], r[l + 1], x[l + 1], psum, pcnt, flags + l + 1, sbox[l + 1])));
+        }
       if (direct)
         set_mean_producer(nf);
       else
@@ -1003,13 +1055,27 @@ struct Impl : SimBase {
       double* const psum = direct ? slot(kSlotSumR) : wide;
       double* const pcnt = direct ? slot(kSlotCnt) : wide + wide_n;
       if (desc.periodic_mask)
-        WL_TIMED(l == 0 ? WL_K_PROLONG : WL_K_COARSE,
-                 (k_prolong_flat<T, true><<<flat_grid(l), kFlatThreads, 0, stream>>>(
-                     g[l], g[l + 1], x[l + 1], v3(L[l]), iD[l], x[l], r[l], psum, pcnt, flags + l, sbox[l])));
+        {
+          if (l == 0)
+            WL_TIMED(l == 0 ? WL_K_PROLONG : WL_K_COARSE,
+                     (k_prolong_flat<T, true, 1><<<flat_grid(l), kFlatThreads, 0, stream>>>(
+                         g[l], g[l + 1], x[l + 1], v3(L[l]), iD[l], x[l], r[l], psum, pcnt, flags + l, sbox[l])));
+          else
+            WL_TIMED(l == 0 ? WL_K_PROLONG : WL_K_COARSE,
+                     (k_prolong_flat<T, true, 0><<<flat_grid(l), kFlatThreads, 0, stream>>>(
+                         g[l], g[l + 1], x[l + 1], v3(L[l]), iD[l], x[l], r[l], psum, pcnt, flags + l, sbox[l])));
+        }
       else
-        WL_TIMED(l == 0 ? WL_K_PROLONG : WL_K_COARSE,
-                 (k_prolong_flat<T, false><<<flat_grid(l), kFlatThreads, 0, stream>>>(
-                     g[l], g[l + 1], x[l + 1], v3(L[l]), iD[l], x[l], r[l], psum, pcnt, flags + l, sbox[l])));
+        {
+          if (l == 0)
+            WL_TIMED(l == 0 ? WL_K_PROLONG : WL_K_COARSE,
+                     (k_prolong_flat<T, false, 1><<<flat_grid(l), kFlatThreads, 0, stream>>>(
+                         g[l], g[l + 1], x[l + 1], v3(L[l]), iD[l], x[l], r[l], psum, pcnt, flags + l, sbox[l])));
+          else
+            WL_TIMED(l == 0 ? WL_K_PROLONG : WL_K_COARSE,
+                     (k_prolong_flat<T, false, 0><<<flat_grid(l), kFlatThreads, 0, stream>>>(
+                         g[l], g[l + 1], x[l + 1], v3(L[l]), iD[l], x[l], r[l], psum, pcnt, flags + l, sbox[l])));
+        }
       if (direct)
         set_mean_producer(nf);
       else
