@@ -2339,9 +2339,24 @@ __global__ void __launch_bounds__(kFinalizeThreads) k_finalize2(const double* a,
   const int chunk = (n + gridDim.x - 1) / gridDim.x;
   const int lo = blockIdx.x * chunk, hi = min(n, lo + chunk);
   double sa = 0.0, sb = 0.0;
-  for (int i = lo + threadIdx.x; i < hi; i += kFinalizeThreads) {
-    if (a) sa = a_max ? fmax(sa, a[i]) : sa + a[i];
-    if (b) sb = b_max ? fmax(sb, b[i]) : sb + b[i];
+  // four loads in flight per thread and trip: a single block then sums ~16 k
+  // partials in a few memory round trips
+  constexpr int U = 4;
+  for (int i0 = lo + threadIdx.x; i0 < hi; i0 += U * kFinalizeThreads) {
+    double va[U], vb[U];
+#pragma unroll
+    for (int q = 0; q < U; ++q) {
+      const int i = i0 + q * kFinalizeThreads;
+      const bool in = i < hi;
+      va[q] = (a && in) ? a[i] : 0.0;
+      vb[q] = (b && in) ? b[i] : 0.0;
+    }
+#pragma unroll
+    for (int q = 0; q < U; ++q) {
+      if (i0 + q * kFinalizeThreads >= hi) break;
+      if (a) sa = a_max ? fmax(sa, va[q]) : sa + va[q];
+      if (b) sb = b_max ? fmax(sb, vb[q]) : sb + vb[q];
+    }
   }
   if (a) sa = a_max ? block_max<kFinalizeThreads>(sa) : block_sum<kFinalizeThreads>(sa);
   if (b) sb = b_max ? block_max<kFinalizeThreads>(sb) : block_sum<kFinalizeThreads>(sb);

@@ -790,7 +790,7 @@ struct Impl : SimBase {
   // there are many (a single block would wait on each load in turn).
   void reduce_wide(const double* a, int a_max, const double* b, int b_max, int n, int sa, int sb) {
     double* out_b = sb >= 0 ? slot(sb) : nullptr;
-    if (n > 4 * kFinalizeThreads) {
+    if (n > 16 * kFinalizeThreads) {
       double* ta = wide + 4 * wide_n;
       double* tb = ta + kFinalizeStage;
       WL_TIMED(WL_K_REDUCE, (k_finalize2<<<kFinalizeStage, kFinalizeThreads, 0, stream>>>(
