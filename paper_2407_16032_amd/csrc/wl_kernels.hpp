@@ -248,10 +248,12 @@ __global__ void __launch_bounds__(kBlock) k_measure(Grid3 g, BodyP b, Motion m, 
 // multigrid coefficients: inverse diagonal and coefficient restriction
 // ---------------------------------------------------------------------------
 template <typename T, int D>
-__global__ void __launch_bounds__(kBlock) k_inv_diag(Grid3 g, Vec3<T> L, T* iD) {
-  const int total = g.n[0] * g.n[1] * ((D == 3) ? g.n[2] : 1);
+__global__ void __launch_bounds__(kBlock) k_inv_diag(Grid3 g, Vec3<T> L, T* iD, int3 lo, int3 hi) {
+  // the cells lo..hi (interior indices, inclusive) only
+  const int m0 = hi.x - lo.x + 1, m1 = hi.y - lo.y + 1, m2 = (D == 3) ? hi.z - lo.z + 1 : 1;
+  const int total = m0 * m1 * m2;
   for (int lin = blockIdx.x * kBlock + threadIdx.x; lin < total; lin += gridDim.x * kBlock) {
-    const int I0 = lin % g.n[0] + 1, t = lin / g.n[0], I1 = t % g.n[1] + 1, I2 = (D == 3) ? t / g.n[1] + 1 : 0;
+    const int I0 = lin % m0 + lo.x, t = lin / m0, I1 = t % m1 + lo.y, I2 = (D == 3) ? t / m1 + lo.z : 0;
     const int I[3] = {I0, I1, I2};
     const int idx = I0 + I1 * g.s[1] + I2 * g.s[2];
     T Dg = T(0);
@@ -265,14 +267,19 @@ __global__ void __launch_bounds__(kBlock) k_inv_diag(Grid3 g, Vec3<T> L, T* iD) 
 
 // L_c,a[J] = 1/2 * sum of the fine a-faces covering the coarse a-face.  blockIdx.y = a.
 template <typename T, int D>
-__global__ void __launch_bounds__(kBlock) k_restrict_L(Grid3 f, Grid3 c, Vec3<T> Lf, Vec3<T> Lc) {
+__global__ void __launch_bounds__(kBlock) k_restrict_L(Grid3 f, Grid3 c, Vec3<T> Lf, Vec3<T> Lc, int3 lo, int3 hi) {
   const int a = blockIdx.y;
-  // coarse faces: J_a in 1..Nc_a+1, other axes 1..Nc
-  int m[3];
-  for (int k = 0; k < 3; ++k) m[k] = (k < D) ? (c.n[k] + (k == a ? 1 : 0)) : 1;
+  // coarse faces: J_a in 1..Nc_a+1, other axes 1..Nc, within lo..hi
+  const int l3[3] = {lo.x, lo.y, lo.z}, h3[3] = {hi.x, hi.y, hi.z};
+  int st[3], m[3];
+  for (int k = 0; k < 3; ++k) {
+    const int top = (k < D) ? (c.n[k] + (k == a ? 1 : 0)) : 1;
+    st[k] = (k < D) ? max(1, l3[k]) : 0;
+    m[k] = (k < D) ? max(0, min(top, h3[k]) - st[k] + 1) : 1;
+  }
   const int total = m[0] * m[1] * m[2];
   for (int lin = blockIdx.x * kBlock + threadIdx.x; lin < total; lin += gridDim.x * kBlock) {
-    const int J0 = lin % m[0] + 1, t = lin / m[0], J1 = t % m[1] + 1, J2 = (D == 3) ? t / m[1] + 1 : 0;
+    const int J0 = lin % m[0] + st[0], t = lin / m[0], J1 = t % m[1] + st[1], J2 = (D == 3) ? t / m[1] + st[2] : 0;
     const int J[3] = {J0, J1, J2};
     int base = 0;
     for (int k = 0; k < D; ++k) base += (2 * J[k] - 1) * f.s[k];

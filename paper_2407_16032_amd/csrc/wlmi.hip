@@ -641,14 +641,53 @@ struct Impl : SimBase {
     return measure(0.0);
   }
 
-  wl_status coefficients() {
-    WL_TIMED(WL_K_COEF, (k_inv_diag<T, D><<<nb[0], kBlock, 0, stream>>>(g[0], v3(L[0]), iD[0])));
-    for (int l = 1; l < nlev; ++l) {
-      int m = 1;
-      for (int a = 0; a < D; ++a) m *= g[l].n[a] + 1;
-      WL_TIMED(WL_K_COEF, (k_restrict_L<T, D><<<dim3(blocks_for(m), D), kBlock, 0, stream>>>(
-                              g[l - 1], g[l], v3(L[l - 1]), v3(L[l]))));
-      WL_TIMED(WL_K_COEF, (k_inv_diag<T, D><<<nb[l], kBlock, 0, stream>>>(g[l], v3(L[l]), iD[l])));
+  // Inverse diagonals and coarse coefficients after the faces lo..hi (padded
+  // indices, inclusive) of the fine level were re-measured: on every level only
+  // the faces that depend on them and the cells next to those faces.
+  wl_status coefficients(const int lo[3], const int hi[3]) {
+    int flo[3], fhi[3];  // changed faces of the current level
+    for (int a = 0; a < 3; ++a) {
+      flo[a] = a < D ? lo[a] : 0;
+      fhi[a] = a < D ? hi[a] : 0;
+    }
+    for (int l = 0; l < nlev; ++l) {
+      if (l > 0) {
+        // coarse face J takes the fine faces 2J-1 (its own axis) and 2J-1, 2J (the others)
+        int clo[3], chi[3], m = 1;
+        for (int a = 0; a < 3; ++a) {
+          clo[a] = a < D ? std::max(1, flo[a] / 2) : 0;
+          chi[a] = a < D ? std::min(g[l].n[a] + 1, (fhi[a] + 2) / 2) : 0;
+          if (a < D) m *= std::max(0, chi[a] - clo[a] + 1);
+        }
+        if (m > 0)
+          WL_TIMED(WL_K_COEF, (k_restrict_L<T, D><<<dim3(blocks_for(m), D), kBlock, 0, stream>>>(
+                                  g[l - 1], g[l], v3(L[l - 1]), v3(L[l]), make_int3(clo[0], clo[1], clo[2]),
+                                  make_int3(chi[0], chi[1], chi[2]))));
+        for (int a = 0; a < 3; ++a) {
+          flo[a] = clo[a];
+          fhi[a] = chi[a];
+        }
+      }
+      // cells whose faces (I, I+1 along each axis) changed; a periodic axis whose
+      // changed range reaches its ends is taken whole (the wrapped face)
+      int cl[3], ch[3];
+      int64_t m = 1;
+      for (int a = 0; a < 3; ++a) {
+        if (a >= D) {
+          cl[a] = ch[a] = 0;
+          continue;
+        }
+        cl[a] = std::max(1, flo[a] - 1);
+        ch[a] = std::min(g[l].n[a], fhi[a]);
+        if (g[l].per[a] && (flo[a] <= 1 || fhi[a] >= g[l].n[a])) {
+          cl[a] = 1;
+          ch[a] = g[l].n[a];
+        }
+        m *= std::max(0, ch[a] - cl[a] + 1);
+      }
+      if (m > 0)
+        WL_TIMED(WL_K_COEF, (k_inv_diag<T, D><<<blocks_for(m), kBlock, 0, stream>>>(
+                                g[l], v3(L[l]), iD[l], make_int3(cl[0], cl[1], cl[2]), make_int3(ch[0], ch[1], ch[2]))));
     }
     WL_HIP(hipGetLastError());
     return WL_OK;
@@ -718,7 +757,7 @@ struct Impl : SimBase {
     WL_TIMED(WL_K_MEASURE, (k_measure<T, D><<<dim3(blocks_for(vol), D), kBlock, 0, stream>>>(
                                g[0], body, m, desc.eps, v3(mu0), v9(mu1), v3(V), l3, h3)));
     WL_HIP(hipGetLastError());
-    return coefficients();
+    return coefficients(lo, hi);
   }
 
   // full-domain measure (creation and explicit calls)

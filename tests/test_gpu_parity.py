@@ -299,6 +299,30 @@ def test_large_grid_projection_is_divergence_free():
     gpu.close()
 
 
+@pytest.mark.parametrize("name", ["plate3d", "rotcyl2d"])
+def test_boxed_remeasure_matches_a_full_measure(name):
+    """After several steps of a moving body, whose per-step re-measure updates the
+    coefficients of every level only near the body, the stored L and iD equal those
+    of a full-domain measure at the same time, on every level."""
+    _say("boxed re-measure", name)
+    from paper_2407_16032_amd import Simulation
+    w = CASES[name]
+    sims = [Simulation(w.n, w.U, w.nu, w.body, periodic=w.periodic_mask(), convective_exit=w.convective_exit,
+                       prec="f64", tol=1e-8, device="cuda:0") for _ in range(2)]
+    sims[0].set_velocity(wlsynth.initial_velocity(w))
+    for _ in range(3):
+        sims[0].step()
+    t, _ = sims[0].time()
+    sims[0].step()  # re-measures at its start time t
+    sims[1].measure(t)
+    for lvl in range(len(sims[0].levels())):
+        for fname in ("L", "iD"):
+            a, b = (s.field(fname, lvl).double().cpu().numpy() for s in sims)
+            np.testing.assert_array_equal(a, b, err_msg="%s level %d" % (fname, lvl))
+    for s in sims:
+        s.close()
+
+
 @pytest.mark.parametrize("name", ["plate3d", "sphere3d_tiled", "circle2d"])
 def test_coefficients_are_body_free_outside_the_body_box(name):
     """The kernels evaluate L, iD (every level) and mu0, mu1, V (fine level) in closed
