@@ -56,8 +56,8 @@ def kernel_bytes(name, ndim, cells, faces, esize, has_body, pcg_iters, box_cells
         fields = (1 + (pcg_iters - 1) / pcg_iters) + (1 if tiled else 2)
         return (fields * cells + (1 if flat else 1 + n) * bc) * esize
     if name == "pcg_a2":
-        # flat form, second launch: reads e_new; iD, L (n) in the box
-        return (cells + (1 + n) * bc) * esize
+        # flat form, second launch: reads e_new; L (n) in the box
+        return (cells + n * bc) * esize
     if name == "pcg_b":
         if tiled:  # reads e, x, r; writes x, r; iD and L (n) in the box
             return (5 * cells + (1 + n) * bc) * esize

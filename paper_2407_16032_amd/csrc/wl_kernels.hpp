@@ -1858,9 +1858,14 @@ __global__ void __launch_bounds__(kFlatThreads) k_pcg_a1_flat(Grid3 g, const T* 
   }
 }
 
+// sigma = e.Ae summed over faces: A has the face coefficients off the diagonal
+// and minus their sum on it, so e.Ae = -sum over faces of L_f (e_i - e_j)^2.
+// Each cell takes its three - faces, so a vector reads its -x, -y and -z
+// neighbours only (a periodic axis wraps face 1 to cell N; a non-periodic
+// boundary face has L = 0).  A solid cell (iD = 0) has only zero faces.
 template <typename T, bool PER, int FINE>
-__global__ void __launch_bounds__(kFlatThreads) k_pcg_a2_flat(Grid3 g, Vec3<T> L, const T* iD, const T* e,
-                                                              double* part_sig, int* flag, StdBox B) {
+__global__ void __launch_bounds__(kFlatThreads) k_pcg_a2_flat(Grid3 g, Vec3<T> L, const T* e, double* part_sig,
+                                                              int* flag, StdBox B) {
   typedef typename Vec16<T>::type V;
   constexpr int W = Vec16<T>::W;
   if (*flag) return;
@@ -1869,31 +1874,25 @@ __global__ void __launch_bounds__(kFlatThreads) k_pcg_a2_flat(Grid3 g, Vec3<T> L
   if (f.ok) {
     const FlatNbr<W, PER> o(g, f);
     const int id = f.id;
-    const V ec_ = ldv(e + id), ey0 = ldv(e + id + o.ym), ey1 = ldv(e + id + o.yp), ez0 = ldv(e + id + o.zm),
-            ez1 = ldv(e + id + o.zp);
-    const T ex0 = e[id + o.xm], ex1 = e[id + W - 1 + o.xp];
+    const V ec_ = ldv(e + id), ey0 = ldv(e + id + o.ym), ez0 = ldv(e + id + o.zm);
+    const T ex0 = e[id + o.xm];
     const T* E0 = reinterpret_cast<const T*>(&ec_);
-    const T *EY0 = reinterpret_cast<const T*>(&ey0), *EY1 = reinterpret_cast<const T*>(&ey1);
-    const T *EZ0 = reinterpret_cast<const T*>(&ez0), *EZ1 = reinterpret_cast<const T*>(&ez1);
-    auto lane = [&](const FlatCoef<T, W, PER>& c, int w) {
-      const T ec = E0[w];
-      T qq = T(0);
-      if (c.d != T(0)) {
-        const T xm = (w > 0) ? E0[w - 1] : ex0, xp = (w < W - 1) ? E0[w + 1] : ex1;
-        qq = qq + c.Lxp * (xp - ec) - c.Lxc * (ec - xm);
-        qq = qq + c.Lyp * (EY1[w] - ec) - c.Lyc * (ec - EY0[w]);
-        qq = qq + c.Lzp * (EZ1[w] - ec) - c.Lzc * (ec - EZ0[w]);
-      }
-      sig += double(ec) * double(qq);
+    const T *EY0 = reinterpret_cast<const T*>(&ey0), *EZ0 = reinterpret_cast<const T*>(&ez0);
+    auto lane = [&](T Lx, T Ly, T Lz, int w) {
+      const T ec = E0[w], xm = (w > 0) ? E0[w - 1] : ex0;
+      const T dx = ec - xm, dy = ec - EY0[w], dz = ec - EZ0[w];
+      sig -= double(Lx * (dx * dx) + Ly * (dy * dy) + Lz * (dz * dz));
     };
     if (flat_fast<W>(B, g, f)) {
       const FlatStd<T, W, PER> S(g, B, f);
 #pragma unroll
-      for (int w = 0; w < W; ++w) lane(FlatCoef<T, W, PER>(S, B, w), w);
+      for (int w = 0; w < W; ++w) lane(S.xlo(w) ? T(0) : S.Ls, S.Lyc, S.Lzc, w);
     } else {
-      const FlatLoaded<T, W, PER> C(g, L, iD, f, o);
+      const V lx = ldv(L.c[0] + id), ly = ldv(L.c[1] + id), lz = ldv(L.c[2] + id);
+      const T *LX = reinterpret_cast<const T*>(&lx), *LY = reinterpret_cast<const T*>(&ly),
+              *LZ = reinterpret_cast<const T*>(&lz);
 #pragma unroll
-      for (int w = 0; w < W; ++w) lane(FlatCoef<T, W, PER>(C, w), w);
+      for (int w = 0; w < W; ++w) lane(LX[w], LY[w], LZ[w], w);
     }
   }
   sig = block_sum<kFlatThreads>(sig);

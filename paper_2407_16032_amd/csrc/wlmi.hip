@@ -887,10 +887,10 @@ struct Impl : SimBase {
           {
             if (l == 0)
               WL_TIMED(kidA2, (k_pcg_a2_flat<T, true, 1><<<flat_grid(l), kFlatThreads, 0, stream>>>(
-                                  g[l], v3(L[l]), iD[l], en, wsig, flags + l, sbox[l])));
+                                  g[l], v3(L[l]), en, wsig, flags + l, sbox[l])));
             else
               WL_TIMED(kidA2, (k_pcg_a2_flat<T, true, 0><<<flat_grid(l), kFlatThreads, 0, stream>>>(
-                                  g[l], v3(L[l]), iD[l], en, wsig, flags + l, sbox[l])));
+                                  g[l], v3(L[l]), en, wsig, flags + l, sbox[l])));
           }
         } else {
           {
@@ -904,10 +904,10 @@ struct Impl : SimBase {
           {
             if (l == 0)
               WL_TIMED(kidA2, (k_pcg_a2_flat<T, false, 1><<<flat_grid(l), kFlatThreads, 0, stream>>>(
-                                  g[l], v3(L[l]), iD[l], en, wsig, flags + l, sbox[l])));
+                                  g[l], v3(L[l]), en, wsig, flags + l, sbox[l])));
             else
               WL_TIMED(kidA2, (k_pcg_a2_flat<T, false, 0><<<flat_grid(l), kFlatThreads, 0, stream>>>(
-                                  g[l], v3(L[l]), iD[l], en, wsig, flags + l, sbox[l])));
+                                  g[l], v3(L[l]), en, wsig, flags + l, sbox[l])));
           }
         }
         ga = 1;
