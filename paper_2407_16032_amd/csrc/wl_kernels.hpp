@@ -418,34 +418,108 @@ __global__ void __launch_bounds__(kBlock) k_flux(Grid3 g, Vec3<T> u, Vec3<T> u0,
   }
 }
 
-// 3-D form: one block per brick of 64 x 4 columns x kFZ planes, each thread marching
-// its column in z, so the +-2 neighbours of the stencil are re-read from cache; the
-// bricks are handed out XCD-aware (each XCD takes a contiguous range of bricks,
-// x fastest), which keeps the y/z halos of neighbouring bricks in one L2.
-#ifndef WL_FY
-#define WL_FY 4
+// 3-D form that shares face fluxes between neighbouring faces: each thread
+// marches one column in z and carries phi_cz of the next plane to the next
+// step, and its +x flux is the next lane's own phi_cx, so a face costs four flux
+// evaluations instead of six.  Lane 63 only supplies that flux, so bricks step
+// by 63 columns; a block stacks kRW waves (rows) in y and needs no barrier.
+// Faces whose +1 neighbour wraps a periodic axis take the per-face form.
+#ifndef WL_RW
+#define WL_RW 1
 #endif
-#ifndef WL_FZ
-#define WL_FZ 16
+#ifndef WL_RZ
+#define WL_RZ 16
 #endif
-constexpr int kFX = 64, kFY = WL_FY, kFZ = WL_FZ, kFluxThreads = kFX * kFY;
+constexpr int kRX = 64, kRW = WL_RW, kRZ = WL_RZ, kReuseThreads = kRX * kRW;
+
+// the face fluxes an unknown face uses lie at 1..N_j + 1 along j and 1..N_a on
+// the other axes; phi_cj reads only valid points there
+__device__ __forceinline__ bool phi_needed(const Grid3& g, int j, int p0, int p1, int p2) {
+  const int P[3] = {p0, p1, p2};
+  bool ok = true;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) ok = ok && P[a] >= 1 && P[a] <= g.n[a] + (a == j ? 1 : 0);
+  return ok;
+}
+
+// phi_cj at P (0 where no unknown face uses it): the plain-offset form where no
+// point of its stencil wraps or needs the boundary rule, else the general one
+// (both compute the same value)
 template <typename T>
-__global__ void __launch_bounds__(kFluxThreads) k_flux_bricks(Grid3 g, Vec3<T> u, Vec3<T> u0, Vec3<T> V, Vec3<T> f,
-                                                        T dt, T nu, int has_body, StdBox B, int nbx, int nby,
-                                                        int nbz) {
-  const int c = blockIdx.y;
-  const int nb = nbx * nby * nbz;
+__device__ __forceinline__ T phi_at(const Grid3& g, const Vec3<T>& u, int c, int j, int p0, int p1, int p2, T nu) {
+  if (!phi_needed(g, j, p0, p1, p2)) return T(0);
+  const int P[3] = {p0, p1, p2};
+  if (P[j] >= 3 && P[j] <= g.n[j] - 1 && P[c] >= 2)
+    return phi_fast<T, 3>(u, c, j, lin3<T, 3>(g, p0, p1, p2), g.s[c], g.s[j], nu);
+  return phi_cj<T, 3>(g, u, c, j, P, nu);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kReuseThreads) k_flux_reuse(Grid3 g, Vec3<T> u, Vec3<T> u0, Vec3<T> V, Vec3<T> f,
+                                                              T dt, T nu, int has_body, StdBox B, int nbx, int nby,
+                                                              int nbz) {
+  // one block per brick and component; the XCDs take contiguous ranges of
+  // (brick, component) with the component fastest, so the three blocks of a brick
+  // run together on one XCD and share the velocity they read through its L2
+  const int nb = nbx * nby * nbz * 3;
   const int b = blockIdx.x;
   const int full = (nb / 8) * 8;
-  const int t = (b < full) ? (b % 8) * (nb / 8) + b / 8 : b;
+  const int tc = (b < full) ? (b % 8) * (nb / 8) + b / 8 : b;
+  const int c = tc % 3, t = tc / 3;
   const int bx = t % nbx, r1 = t / nbx, by = r1 % nby, bz = r1 / nby;
-  const int I0 = bx * kFX + (int)threadIdx.x % kFX, I1 = by * kFY + (int)threadIdx.x / kFX;
+  const int lane = (int)threadIdx.x % kRX;
+  const int I0 = bx * (kRX - 1) + lane, I1 = by * kRW + (int)threadIdx.x / kRX;
   const int P0 = g.n[0] + 2, P1 = g.n[1] + 2, P2 = g.n[2] + 2;
-  if (I0 >= P0 || I1 >= P1) return;  // no barrier in this kernel
-  const int z1 = min((bz + 1) * kFZ, P2);
-  for (int I2 = bz * kFZ; I2 < z1; ++I2) {
-    const int I[3] = {I0, I1, I2};
-    flux_face<T, 3>(g, u, u0, V, f, dt, nu, has_body, 0, B, c, I);
+  if (I1 >= P1) return;  // whole waves: no lane of the wave is needed, and no barrier follows
+  const bool col = lane < kRX - 1 && I0 < P0;
+  const int z0 = bz * kRZ, z1 = min(z0 + kRZ, P2);
+  T phz = phi_at<T>(g, u, c, 2, I0, I1, z0, nu);
+  // x and y of the column are interior enough for the plain-offset form (with z)
+  const bool fxy = I0 >= 3 && I0 <= g.n[0] - 2 && I1 >= 3 && I1 <= g.n[1] - 2;
+  for (int I2 = z0; I2 < z1; ++I2) {
+    T phx, phy, phyn, phzn;
+    if (fxy && I2 >= 3 && I2 <= g.n[2] - 2) {
+      // one straight block, so all its loads are in flight together
+      const int id = lin3<T, 3>(g, I0, I1, I2), sc = g.s[c];
+      phx = phi_fast<T, 3>(u, c, 0, id, sc, g.s[0], nu);
+      phy = phi_fast<T, 3>(u, c, 1, id, sc, g.s[1], nu);
+      phyn = phi_fast<T, 3>(u, c, 1, id + g.s[1], sc, g.s[1], nu);
+      phzn = phi_fast<T, 3>(u, c, 2, id + g.s[2], sc, g.s[2], nu);
+    } else {
+      phx = phi_at<T>(g, u, c, 0, I0, I1, I2, nu);
+      phy = phi_at<T>(g, u, c, 1, I0, I1, I2, nu);
+      phyn = phi_at<T>(g, u, c, 1, I0, I1 + 1, I2, nu);
+      phzn = phi_at<T>(g, u, c, 2, I0, I1, I2 + 1, nu);
+    }
+    const T phxn = __shfl_down(phx, 1, kRX);  // every lane of the wave takes part
+    if (col) {
+      const int I[3] = {I0, I1, I2};
+      const int idx = lin3<T, 3>(g, I0, I1, I2);
+      bool unknown = true, wraps = false;
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        const int lo = (a == c && !g.per[a]) ? 2 : 1;
+        unknown = unknown && I[a] >= lo && I[a] <= g.n[a];
+        wraps = wraps || (g.per[a] && I[a] == g.n[a]);
+      }
+      const bool needV = has_body && !std_point<3>(B, g, I, 0);  // V = 0 outside the box
+      const T vb = needV ? V.c[c][idx] : T(0);
+      const T u0v = u0.c[c][idx];
+      T R = T(0);
+      if (unknown) {
+        if (wraps) {
+          R = resid_c<T, 3>(g, u, c, I, nu);
+        } else {
+          R = R + (phx - phxn);
+          R = R + (phy - phyn);
+          R = R + (phz - phzn);
+        }
+      }
+      T v = u0v + dt * R;
+      if (needV) v = v - vb;
+      f.c[c][idx] = v;
+    }
+    phz = phzn;
   }
 }
 

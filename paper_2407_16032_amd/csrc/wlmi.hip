@@ -1455,9 +1455,10 @@ struct Impl : SimBase {
   // f~ = u0 + dt R(u) - V on every padded face
   wl_status flux(T* const uu[3], T* const uu0[3], int hb) {
     if (D == 3) {
-      const int nbx = (g[0].n[0] + 2 + kFX - 1) / kFX, nby = (g[0].n[1] + 2 + kFY - 1) / kFY,
-                nbz = (g[0].n[2] + 2 + kFZ - 1) / kFZ;
-      WL_TIMED(WL_K_FLUX, (k_flux_bricks<T><<<dim3(nbx * nby * nbz, D), kFluxThreads, 0, stream>>>(
+      // output bricks of 63 columns x kRW rows x kRZ planes
+      const int nbx = (g[0].n[0] + 2 + kRX - 2) / (kRX - 1), nby = (g[0].n[1] + 2 + kRW - 1) / kRW,
+                nbz = (g[0].n[2] + 2 + kRZ - 1) / kRZ;
+      WL_TIMED(WL_K_FLUX, (k_flux_reuse<T><<<dim3(nbx * nby * nbz * 3), kReuseThreads, 0, stream>>>(
                               g[0], v3(uu), v3(uu0), v3(V), v3(ft), T(dt), T(desc.nu), hb, sbox[0], nbx, nby, nbz)));
     } else {
       WL_TIMED(WL_K_FLUX, (k_flux<T, D><<<dim3(nb_face, D), kBlock, 0, stream>>>(
