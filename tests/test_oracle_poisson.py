@@ -115,6 +115,35 @@ def test_operator_symmetric_and_negative():
     assert P.dot(P.apply_A(lev, a), a) < 0
 
 
+@pytest.mark.parametrize("n,periodic", [((7, 6, 5), (False, True, False)), ((9, 7), (True, False))])
+def test_energy_is_minus_the_face_sum(n, periodic):
+    """e.Ae = -sum over faces of L_f (e_i - e_j)^2 on every level: A holds the face
+    coefficients off the diagonal and minus their sum on it.  Faces are walked one by
+    one (a periodic axis closes through face 1, a non-periodic boundary face has
+    L = 0); the GPU's sigma pass of the PCG smoother sums this form."""
+    nd = len(n)
+    body = wlsynth.Body("sphere", center=tuple(0.5 * N + 0.3 for N in n), radius=1.9)
+    g, levels = _levels(n, periodic, body)
+    rng = np.random.default_rng(7)
+    for lev in levels:
+        gl = lev.grid
+        e = gl.zeros()
+        e[gl.interior()] = rng.normal(size=gl.n)
+        lhs = P.dot(P.apply_A(lev, e), e)
+        rhs = 0.0
+        for c in itertools.product(*[range(1, N + 1) for N in gl.n]):
+            for i in range(nd):
+                lo = list(c)
+                lo[i] -= 1                # face c along i joins cell c - e_i and cell c
+                if lo[i] == 0:
+                    if not gl.periodic[i]:
+                        assert lev.L[i][c] == 0.0
+                        continue
+                    lo[i] = gl.n[i]
+                rhs -= lev.L[i][c] * (e[c] - e[tuple(lo)]) ** 2
+        assert abs(lhs - rhs) <= 1e-12 * max(1.0, abs(rhs)), (gl.n, lhs, rhs)
+
+
 def test_coarse_coefficients_rediscretise_constant_L():
     # constant L = 1 -> coarse interior L = 2^(n-2)
     for n in [(16, 8), (8, 8, 8)]:
