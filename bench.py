@@ -45,19 +45,16 @@ def kernel_bytes(name, ndim, cells, faces, esize, has_body, pcg_iters, box_cells
     the body box (box_cells / box_faces): outside it the kernels evaluate their
     body-free closed form.  On tiled levels (3-D, large) pass A does not store q and
     pass B recomputes it from e (pass B then needs L and iD in the box); the flat
-    form of the fine level (``flat``) moves the same fields, pass A in two launches.
+    form of the fine level (``flat``) moves the same fields.
     """
     n = ndim
     bc = cells if box_cells is None else box_cells
     bf = faces if box_faces is None else box_faces
     if name == "pcg_a":
-        # reads r, and e_old except in the first sweep; writes e_new (and q if not tiled); iD, L (n) in the
-        # box.  Flat form (two launches): this one is pointwise (iD in the box)
-        fields = (1 + (pcg_iters - 1) / pcg_iters) + (1 if tiled else 2)
-        return (fields * cells + (1 if flat else 1 + n) * bc) * esize
-    if name == "pcg_a2":
-        # flat form, second launch: reads e_new; L (n) in the box
-        return (cells + n * bc) * esize
+        # reads r, and e_old except in the first sweep; writes e_new (and q on the generic
+        # path); iD, L (n) in the box
+        fields = (1 + (pcg_iters - 1) / pcg_iters) + (1 if (tiled or flat) else 2)
+        return (fields * cells + (1 + n) * bc) * esize
     if name == "pcg_b":
         if tiled:  # reads e, x, r; writes x, r; iD and L (n) in the box
             return (5 * cells + (1 + n) * bc) * esize
@@ -164,7 +161,7 @@ def measured_traffic(workload, kernel):
     path = os.path.join(ROOT, "profiles", "pmc_%s.md" % workload)
     if not os.path.exists(path):
         return None
-    key = {"pcg_a": "k_pcg_a1_flat_fine", "pcg_a2": "k_pcg_a2_flat_fine", "pcg_b": "k_pcg_b_flat_fine"}.get(kernel)
+    key = {"pcg_a": "k_pcg_a_flat_fine", "pcg_b": "k_pcg_b_flat_fine"}.get(kernel)
     src, val = None, None
     with open(path) as f:
         for line in f:

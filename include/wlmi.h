@@ -338,8 +338,7 @@ enum {
   WL_K_PG_INFER = 16,/* learned guess: features, conv net, guess */
   WL_K_PG_TRAIN = 17,/* learned guess: snapshots, training steps */
   WL_K_ADJOINT = 18, /* transposes of the step's kernels (adjoint solves count as multigrid) */
-  WL_K_PCG_A2 = 19,  /* fine PCG pass A, second launch of its flat form: sigma = e.Ae */
-  WL_K_COUNT = 20
+  WL_K_COUNT = 19
 };
 
 /* Per-kernel timing with HIP events recorded around each launch on the sim's

@@ -24,7 +24,7 @@ EXPORTS = ["wl_workspace_bytes", "wl_sim_create", "wl_sim_destroy", "wl_measure_
            "wl_adj_reset", "wl_adj_forces", "wl_adj_step", "wl_adj_body_grad", "wl_last_error"]
 PG_PARAMS = 8673
 KERNELS = ["measure", "coef", "flux", "bdim", "bc", "exit", "divres", "pcg_a", "pcg_b", "restrict",
-           "prolong", "project", "cfl", "forces", "coarse", "reduce", "pg_infer", "pg_train", "adjoint", "pcg_a2"]
+           "prolong", "project", "cfl", "forces", "coarse", "reduce", "pg_infer", "pg_train", "adjoint"]
 
 
 class SimDesc(C.Structure):

@@ -1888,89 +1888,112 @@ struct FlatCoef {
   }
 };
 
+// e_new of one cell: iD r + beta e_old (sweep 0: iD (r - m)).  One function, so a
+// cell recomputed as a neighbour gets the value its own thread stores.
+template <typename T>
+__device__ __forceinline__ T pcg_e(T d, T r, T e, T beta, T mean, int k) {
+  return (k > 0) ? d * r + beta * e : d * (r - mean);
+}
+
 // (FINE = 1 only makes the fine-level launches of the flat kernels separate
 // symbols in kernel traces.)
-// PCG pass A, flat form, in two launches (arithmetic of k_pcg_a_tile with
-// STOREQ = 0).  A1 is pointwise: e_new = iD r + beta e_old (sweep 0: iD (r - m),
-// without reading e_old) and the rho_0 partial; A2 reads e_new with its
-// neighbours and leaves the sigma = e.Ae partial.  Together they move one field
-// more than the tiled pass, but both stream at the flat kernels' rate.
+// PCG pass A, flat form (arithmetic of k_pcg_a_tile with STOREQ = 0): e_new of
+// the vector (stored) and of its -x, -y and -z neighbour cells (recomputed from
+// their r, e_old and iD), the sigma = e.Ae partial and, in sweep 0, the rho_0
+// partial.  sigma is summed over faces: A holds the face coefficients off the
+// diagonal and minus their sum on it, so e.Ae = -sum over faces of
+// L_f (e_i - e_j)^2; each cell takes its three - faces (a periodic axis wraps
+// face 1 to cell N; a non-periodic boundary face has L = 0, and a solid cell,
+// iD = 0, has only zero faces).
 template <typename T, bool PER, int FINE>
-__global__ void __launch_bounds__(kFlatThreads) k_pcg_a1_flat(Grid3 g, const T* iD, const T* r, const T* eo, T* en,
-                                                              double* red, int k, RedN rn, double* part_rho0,
-                                                              int* flag, StdBox B) {
+__global__ void __launch_bounds__(kFlatThreads) k_pcg_a_fused_flat(Grid3 g, Vec3<T> L, const T* iD, const T* r,
+                                                                   const T* eo, T* en, double* red, int k, RedN rn,
+                                                                   double* part_sig, double* part_rho0, int* flag,
+                                                                   StdBox B) {
   typedef typename Vec16<T>::type V;
   constexpr int W = Vec16<T>::W;
   if (*flag) return;
   T beta, mean;
   if (!pcg_a_scalars<T, kFlatThreads>(red, k, rn, flag, beta, mean)) return;
   const FlatVec f = flat_vec<T>(g);
-  double rho0 = 0.0;
+  double sig = 0.0, rho0 = 0.0;
   if (f.ok) {
+    const FlatNbr<W, PER> o(g, f);
     const int id = f.id;
-    const V rv = ldv(r + id);
-    V ev;
-    if (k > 0) ev = ldv(eo + id);  // grid-uniform branch
-    const T* R0 = reinterpret_cast<const T*>(&rv);
-    const T* E0 = reinterpret_cast<const T*>(&ev);
-    const bool fast = flat_fast<W>(B, g, f);
-    const FlatStd<T, W, PER> S(g, B, f);
+    // grid-uniform branch on k: sweep 0 reads no e_old
+    V r0 = ldv(r + id), ry = ldv(r + id + o.ym), rz = ldv(r + id + o.zm), e0 = {}, ey = {}, ez = {};
+    const T rx = r[id + o.xm];
+    T ex = T(0);
+    if (k > 0) {
+      e0 = ldv(eo + id);
+      ey = ldv(eo + id + o.ym);
+      ez = ldv(eo + id + o.zm);
+      ex = eo[id + o.xm];
+    }
+    const T *R0 = reinterpret_cast<const T*>(&r0), *RY = reinterpret_cast<const T*>(&ry),
+            *RZ = reinterpret_cast<const T*>(&rz);
+    const T *E0 = reinterpret_cast<const T*>(&e0), *EY = reinterpret_cast<const T*>(&ey),
+            *EZ = reinterpret_cast<const T*>(&ez);
+    T d[W], dy[W], dz[W], dx, lx[W], ly[W], lz[W];
+    if (flat_fast<W>(B, g, f)) {
+      // closed form; a neighbour cell's iD counts its own non-periodic boundary faces
+      const bool py = PER && g.per[1], pz = PER && g.per[2];
+      const FlatStd<T, W, PER> S(g, B, f);
+      const int cy = int(!py && f.j == 1) + int(!py && f.j == g.n[1]);
+      const int cz = int(!pz && f.k == 1) + int(!pz && f.k == g.n[2]);
+      const int cym = int(!py && f.j - 1 == 1) + int(!py && f.j - 1 == g.n[1]);
+      const int czm = int(!pz && f.k - 1 == 1) + int(!pz && f.k - 1 == g.n[2]);
+#pragma unroll
+      for (int w = 0; w < W; ++w) {
+        const int cx = int(S.xlo(w)) + int(S.xhi(w));
+        d[w] = std_iD_nb<T>(B, cx + cy + cz);
+        dy[w] = std_iD_nb<T>(B, cx + cym + cz);
+        dz[w] = std_iD_nb<T>(B, cx + cy + czm);
+        lx[w] = S.xlo(w) ? T(0) : S.Ls;
+        ly[w] = S.Lyc;
+        lz[w] = S.Lzc;
+      }
+      // the -x neighbour of the first lane is interior in x, or the wrapped last
+      // cell of a periodic row (a non-periodic boundary face has L = 0)
+      dx = std_iD_nb<T>(B, cy + cz);
+    } else {
+      const V d0 = ldv(iD + id), dyv = ldv(iD + id + o.ym), dzv = ldv(iD + id + o.zm);
+      const V lxv = ldv(L.c[0] + id), lyv = ldv(L.c[1] + id), lzv = ldv(L.c[2] + id);
+      dx = iD[id + o.xm];
+#pragma unroll
+      for (int w = 0; w < W; ++w) {
+        d[w] = reinterpret_cast<const T*>(&d0)[w];
+        dy[w] = reinterpret_cast<const T*>(&dyv)[w];
+        dz[w] = reinterpret_cast<const T*>(&dzv)[w];
+        lx[w] = reinterpret_cast<const T*>(&lxv)[w];
+        ly[w] = reinterpret_cast<const T*>(&lyv)[w];
+        lz[w] = reinterpret_cast<const T*>(&lzv)[w];
+      }
+    }
     V out;
     T* O = reinterpret_cast<T*>(&out);
+    T prev = pcg_e<T>(dx, rx, ex, beta, mean, k);
 #pragma unroll
     for (int w = 0; w < W; ++w) {
-      const T d = fast ? S.d(B, w) : iD[id + w];
-      const T ec = (k > 0) ? d * R0[w] + beta * E0[w] : d * (R0[w] - mean);
+      const T ec = pcg_e<T>(d[w], R0[w], E0[w], beta, mean, k);
+      const T eym = pcg_e<T>(dy[w], RY[w], EY[w], beta, mean, k);
+      const T ezm = pcg_e<T>(dz[w], RZ[w], EZ[w], beta, mean, k);
       O[w] = ec;
-      if (k == 0 && d != T(0)) rho0 += double(R0[w] - mean) * double(ec);
+      // a zero face adds nothing (and its neighbour may be a ghost cell)
+      const T jx = lx[w] != T(0) ? ec - prev : T(0), jy = ly[w] != T(0) ? ec - eym : T(0),
+              jz = lz[w] != T(0) ? ec - ezm : T(0);
+      sig -= double(lx[w] * (jx * jx) + ly[w] * (jy * jy) + lz[w] * (jz * jz));
+      if (k == 0 && d[w] != T(0)) rho0 += double(R0[w] - mean) * double(ec);
+      prev = ec;
     }
     stv_stream<T>(en + id, out);
   }
+  sig = block_sum<kFlatThreads>(sig);
+  if (threadIdx.x == 0) part_sig[flat_block()] = sig;
   if (k == 0) {
     rho0 = block_sum<kFlatThreads>(rho0);
     if (threadIdx.x == 0) part_rho0[flat_block()] = rho0;
   }
-}
-
-// sigma = e.Ae summed over faces: A has the face coefficients off the diagonal
-// and minus their sum on it, so e.Ae = -sum over faces of L_f (e_i - e_j)^2.
-// Each cell takes its three - faces, so a vector reads its -x, -y and -z
-// neighbours only (a periodic axis wraps face 1 to cell N; a non-periodic
-// boundary face has L = 0).  A solid cell (iD = 0) has only zero faces.
-template <typename T, bool PER, int FINE>
-__global__ void __launch_bounds__(kFlatThreads) k_pcg_a2_flat(Grid3 g, Vec3<T> L, const T* e, double* part_sig,
-                                                              int* flag, StdBox B) {
-  typedef typename Vec16<T>::type V;
-  constexpr int W = Vec16<T>::W;
-  if (*flag) return;
-  const FlatVec f = flat_vec<T>(g);
-  double sig = 0.0;
-  if (f.ok) {
-    const FlatNbr<W, PER> o(g, f);
-    const int id = f.id;
-    const V ec_ = ldv(e + id), ey0 = ldv(e + id + o.ym), ez0 = ldv(e + id + o.zm);
-    const T ex0 = e[id + o.xm];
-    const T* E0 = reinterpret_cast<const T*>(&ec_);
-    const T *EY0 = reinterpret_cast<const T*>(&ey0), *EZ0 = reinterpret_cast<const T*>(&ez0);
-    auto lane = [&](T Lx, T Ly, T Lz, int w) {
-      const T ec = E0[w], xm = (w > 0) ? E0[w - 1] : ex0;
-      const T dx = ec - xm, dy = ec - EY0[w], dz = ec - EZ0[w];
-      sig -= double(Lx * (dx * dx) + Ly * (dy * dy) + Lz * (dz * dz));
-    };
-    if (flat_fast<W>(B, g, f)) {
-      const FlatStd<T, W, PER> S(g, B, f);
-#pragma unroll
-      for (int w = 0; w < W; ++w) lane(S.xlo(w) ? T(0) : S.Ls, S.Lyc, S.Lzc, w);
-    } else {
-      const V lx = ldv(L.c[0] + id), ly = ldv(L.c[1] + id), lz = ldv(L.c[2] + id);
-      const T *LX = reinterpret_cast<const T*>(&lx), *LY = reinterpret_cast<const T*>(&ly),
-              *LZ = reinterpret_cast<const T*>(&lz);
-#pragma unroll
-      for (int w = 0; w < W; ++w) lane(LX[w], LY[w], LZ[w], w);
-    }
-  }
-  sig = block_sum<kFlatThreads>(sig);
-  if (threadIdx.x == 0) part_sig[flat_block()] = sig;
 }
 
 // PCG pass B, flat form (arithmetic of k_pcg_b_tile): q = A e from e and its

@@ -861,7 +861,6 @@ struct Impl : SimBase {
     const int64_t nvec = plan.lev[l].alloc / Vec16<T>::W;
     const int gb = blocks_for(nvec);
     const int kidA = l == 0 ? WL_K_PCG_A : WL_K_COARSE, kidB = l == 0 ? WL_K_PCG_B : WL_K_COARSE;
-    const int kidA2 = l == 0 ? WL_K_PCG_A2 : WL_K_COARSE;
     const int nf = (int)nflat[l];
     // a flat level with few blocks leaves its partials in the slots, as the tiles do
     const bool direct = nf > 0 && nf <= kCollapseMin;
@@ -876,39 +875,19 @@ struct Impl : SimBase {
       double* const wmax = direct ? slot(kSlotRmax) : wide + 3 * wide_n;
       if (nf > 0) {
         if (desc.periodic_mask) {
-          {
-            if (l == 0)
-              WL_TIMED(kidA, (k_pcg_a1_flat<T, true, 1><<<flat_grid(l), kFlatThreads, 0, stream>>>(
-                                  g[l], iD[l], r[l], eo, en, red, k, rn, wrho0, flags + l, sbox[l])));
-            else
-              WL_TIMED(kidA, (k_pcg_a1_flat<T, true, 0><<<flat_grid(l), kFlatThreads, 0, stream>>>(
-                                  g[l], iD[l], r[l], eo, en, red, k, rn, wrho0, flags + l, sbox[l])));
-          }
-          {
-            if (l == 0)
-              WL_TIMED(kidA2, (k_pcg_a2_flat<T, true, 1><<<flat_grid(l), kFlatThreads, 0, stream>>>(
-                                  g[l], v3(L[l]), en, wsig, flags + l, sbox[l])));
-            else
-              WL_TIMED(kidA2, (k_pcg_a2_flat<T, true, 0><<<flat_grid(l), kFlatThreads, 0, stream>>>(
-                                  g[l], v3(L[l]), en, wsig, flags + l, sbox[l])));
-          }
+          if (l == 0)
+            WL_TIMED(kidA, (k_pcg_a_fused_flat<T, true, 1><<<flat_grid(l), kFlatThreads, 0, stream>>>(
+                                g[l], v3(L[l]), iD[l], r[l], eo, en, red, k, rn, wsig, wrho0, flags + l, sbox[l])));
+          else
+            WL_TIMED(kidA, (k_pcg_a_fused_flat<T, true, 0><<<flat_grid(l), kFlatThreads, 0, stream>>>(
+                                g[l], v3(L[l]), iD[l], r[l], eo, en, red, k, rn, wsig, wrho0, flags + l, sbox[l])));
         } else {
-          {
-            if (l == 0)
-              WL_TIMED(kidA, (k_pcg_a1_flat<T, false, 1><<<flat_grid(l), kFlatThreads, 0, stream>>>(
-                                  g[l], iD[l], r[l], eo, en, red, k, rn, wrho0, flags + l, sbox[l])));
-            else
-              WL_TIMED(kidA, (k_pcg_a1_flat<T, false, 0><<<flat_grid(l), kFlatThreads, 0, stream>>>(
-                                  g[l], iD[l], r[l], eo, en, red, k, rn, wrho0, flags + l, sbox[l])));
-          }
-          {
-            if (l == 0)
-              WL_TIMED(kidA2, (k_pcg_a2_flat<T, false, 1><<<flat_grid(l), kFlatThreads, 0, stream>>>(
-                                  g[l], v3(L[l]), en, wsig, flags + l, sbox[l])));
-            else
-              WL_TIMED(kidA2, (k_pcg_a2_flat<T, false, 0><<<flat_grid(l), kFlatThreads, 0, stream>>>(
-                                  g[l], v3(L[l]), en, wsig, flags + l, sbox[l])));
-          }
+          if (l == 0)
+            WL_TIMED(kidA, (k_pcg_a_fused_flat<T, false, 1><<<flat_grid(l), kFlatThreads, 0, stream>>>(
+                                g[l], v3(L[l]), iD[l], r[l], eo, en, red, k, rn, wsig, wrho0, flags + l, sbox[l])));
+          else
+            WL_TIMED(kidA, (k_pcg_a_fused_flat<T, false, 0><<<flat_grid(l), kFlatThreads, 0, stream>>>(
+                                g[l], v3(L[l]), iD[l], r[l], eo, en, red, k, rn, wsig, wrho0, flags + l, sbox[l])));
         }
         ga = 1;
       } else if (tiles[l][2] > 0) {
