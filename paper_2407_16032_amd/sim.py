@@ -20,12 +20,13 @@ def _body_desc(body) -> L.BodyDesc:
     b.kind = L.BODY_KIND[body.kind]
     for k, v in enumerate(tuple(body.center)[:3]):
         b.center[k] = v
-    b.radius = float(body.radius)
-    for k, v in enumerate(tuple(body.half_extent)[:3]):
+    # a field the body object does not carry keeps its zero default (no motion)
+    b.radius = float(getattr(body, "radius", 0.0))
+    for k, v in enumerate(tuple(getattr(body, "half_extent", ()))[:3]):
         b.half_extent[k] = v
-    b.heave_amp, b.pitch_amp, b.freq = float(body.heave_amp), float(body.pitch_amp), float(body.freq)
-    b.phase_h, b.phase_p, b.spin_omega = float(body.phase_h), float(body.phase_p), float(body.spin_omega)
-    for k, v in enumerate(tuple(body.pivot_offset)[:3]):
+    for name in ("heave_amp", "pitch_amp", "freq", "phase_h", "phase_p", "spin_omega"):
+        setattr(b, name, float(getattr(body, name, 0.0)))
+    for k, v in enumerate(tuple(getattr(body, "pivot_offset", ()))[:3]):
         b.pivot_offset[k] = v
     return b
 
