@@ -2228,29 +2228,39 @@ __global__ void __launch_bounds__(kFlatThreads) k_project_flat(Grid3 g, Vec3<T> 
 }
 
 // BDIM blend, flat form (arithmetic of k_bdim) over the padded faces of one
-// component (blockIdx.z): vectors whose faces all lie outside the body box take
-// the closed form (u = L f, or u = f with no body) with vector loads and stores;
-// the others, and the vectors that reach past the padded row, go face by face.
+// component (blockIdx.z) and plane (blockIdx.y).  The first threads of a plane
+// take the vectors of x-faces 1..N of every padded row: those whose faces all lie
+// outside the body box take the closed form (u = L f, or u = f with no body)
+// with vector loads and stores, the others near the body the blend with vector
+// loads, or face by face next to the domain boundary.  The last 2 (N_y + 2)
+// threads take the x ghost faces 0 and N + 1 of each row, so no wave of vectors
+// also runs the per-face path.
 template <typename T, int CORR>
 __global__ void __launch_bounds__(kFlatThreads) k_bdim_flat(Grid3 g, Vec3<T> f, Vec3<T> V, Vec3<T> mu0,
                                                             Vec9<T> mu1, Vec3<T> u, int has_body, StdBox B) {
   typedef typename Vec16<T>::type VT;
   constexpr int W = Vec16<T>::W;
   const int c = blockIdx.z;
-  const int vr2 = g.n[0] / W + 2;  // vectors of a padded row: first cells 1 - W, 1, 1 + W, ...
+  const int vr = g.n[0] / W;  // vectors of a row: first cells 1, 1 + W, ...
   const int P1 = g.n[1] + 2;
   const int t = blockIdx.x * kFlatThreads + threadIdx.x;
-  if (t >= vr2 * P1) return;  // no barrier in this kernel
-  const int m = t % vr2, j = t / vr2, k = blockIdx.y;
-  const int i0 = 1 - W + m * W;
+  const int k = blockIdx.y;
+  if (t >= vr * P1) {
+    const int e = t - vr * P1;
+    if (e >= 2 * P1) return;  // no barrier in this kernel
+    const int I[3] = {(e & 1) ? g.n[0] + 1 : 0, e >> 1, k};
+    bdim_face<T, 3, CORR>(g, f, V, mu0, mu1, u, has_body, B, c, I, lin3<T, 3>(g, I[0], I[1], I[2]));
+    return;
+  }
+  const int m = t % vr, j = t / vr;
+  const int i0 = 1 + m * W;
   const int id = i0 + j * g.s[1] + k * g.s[2];
-  const bool whole = i0 >= 0 && i0 + W - 1 <= g.n[0] + 1;
   bool fastv = true;
   if (has_body) {
     const int a[3] = {i0, j, k}, b[3] = {i0 + W - 1, j, k};
     fastv = std_miss<3>(B, g, a, b);
   }
-  if (fastv && whole) {
+  if (fastv) {
     const VT fv = ldv(f.c[c] + id);
     VT uv;
     if (CORR) uv = ldv(u.c[c] + id);
@@ -2263,7 +2273,7 @@ __global__ void __launch_bounds__(kFlatThreads) k_bdim_flat(Grid3 g, Vec3<T> f, 
       U[w] = CORR ? T(0.5) * (U[w] + acc) : acc;
     }
     stv_stream<T>(u.c[c] + id, uv);
-  } else if (whole && i0 >= 2 && i0 + W - 1 <= g.n[0] - 1 && j >= 2 && j <= g.n[1] - 1 && k >= 2 &&
+  } else if (i0 >= 2 && i0 + W - 1 <= g.n[0] - 1 && j >= 2 && j <= g.n[1] - 1 && k >= 2 &&
              k <= g.n[2] - 1) {
     // near the body, away from the domain boundary: the blend of bdim_face with
     // whole-vector loads of f, V, mu0, mu1 (the x neighbours of f from the lanes)
@@ -2292,9 +2302,7 @@ __global__ void __launch_bounds__(kFlatThreads) k_bdim_flat(Grid3 g, Vec3<T> f, 
   } else {
 #pragma unroll
     for (int w = 0; w < W; ++w) {
-      const int i = i0 + w;
-      if (i < 0 || i > g.n[0] + 1) continue;
-      const int I[3] = {i, j, k};
+      const int I[3] = {i0 + w, j, k};
       bdim_face<T, 3, CORR>(g, f, V, mu0, mu1, u, has_body, B, c, I, id + w);
     }
   }

@@ -813,6 +813,8 @@ struct Impl : SimBase {
 
   void set_mean_producer(int grid) { slot_n[kSlotSumR] = slot_n[kSlotCnt] = grid; }
   // flat BDIM blend: the vectors of the padded rows of a plane x the padded planes x D
+  // k_bdim_flat: the row vectors of x-faces 1..N, then the two x ghost faces of
+  // every row, of each padded plane and component
   dim3 bdim_grid() const {
     const int vr2 = g[0].n[0] / Vec16<T>::W + 2;
     return dim3((unsigned)((vr2 * (g[0].n[1] + 2) + kFlatThreads - 1) / kFlatThreads), (unsigned)(g[0].n[2] + 2),
