@@ -277,7 +277,7 @@ wl_status wl_adj_body_grad(wl_sim* sim, double* dJ_dradius, double* dJ_dspin);
  * pressures and the current divergence, normalised by the mean and RMS
  * deviation of p_{m-1} over active cells, to the pressure change of the next
  * solve; x0 = (p_{m-1} + s * out) w dt replaces the warm start x0 = p w dt.  The
- * multigrid solve to the same tolerance stays the judge of the guess.  Online
+ * multigrid solve to the same tolerance decides whether the guess is used.  Online
  * training: after each guided solve, random crops (64^3 or the grid) of the
  * features and the target (p_m - p_{m-1})/s enter a ring buffer; each solve then
  * runs train_iters Adam steps (FP32 master weights) on ring crops, loss = mean
@@ -312,7 +312,7 @@ wl_status wl_pg_train_step(wl_sim* sim, const void* x_box, const float* target, 
 /* Loss of the last training step, training steps and snapshots taken so far, and
  * how many guided solves used the guess out of those that tried it: a guess is
  * used only if its initial residual max-norm is below that of the plain warm
- * start (multigrid stays the fallback and the judge).  Any pointer may be NULL. */
+ * start (multigrid stays the fallback and decides).  Any pointer may be NULL. */
 wl_status wl_pg_stats(wl_sim* sim, double* last_loss, int64_t* train_steps, int64_t* snapshots,
                       int64_t* guesses_used, int64_t* guesses_tried);
 
@@ -326,7 +326,7 @@ enum {
   WL_K_BC = 4,       /* boundary conditions */
   WL_K_EXIT = 5,     /* convective exit plane */
   WL_K_DIVRES = 6,   /* divergence and initial residual */
-  WL_K_PCG_A = 7,    /* fine PCG pass A: search direction and A e (flat form: the direction only) */
+  WL_K_PCG_A = 7,    /* fine PCG pass A: search direction and sigma = e.Ae (generic form: also A e) */
   WL_K_PCG_B = 8,    /* fine PCG pass B: x and r update */
   WL_K_RESTRICT = 9, /* fine -> first coarse residual restriction */
   WL_K_PROLONG = 10, /* first coarse -> fine prolongation and correction */
@@ -334,7 +334,7 @@ enum {
   WL_K_CFL = 12,     /* CFL outflux maximum */
   WL_K_FORCES = 13,  /* force integrals */
   WL_K_COARSE = 14,  /* all work on multigrid levels >= 1 */
-  WL_K_REDUCE = 15,  /* single-block finalisations of reductions */
+  WL_K_REDUCE = 15,  /* totals of per-block partial sums (one block, or two stages) */
   WL_K_PG_INFER = 16,/* learned guess: features, conv net, guess */
   WL_K_PG_TRAIN = 17,/* learned guess: snapshots, training steps */
   WL_K_ADJOINT = 18, /* transposes of the step's kernels (adjoint solves count as multigrid) */

@@ -1183,7 +1183,7 @@ struct Impl : SimBase {
     const T wdt = T(w * dt);
     const bool guided = pg_on && pg_mode >= 1 && pg_hist >= 2;
     if (guided) {
-      // multigrid judges the guess: it is used only if its initial residual is below
+      // multigrid decides on the guess: it is used only if its initial residual is below
       // that of the plain warm start x0 = p w dt
       double res_plain = 0.0, res_guess = 0.0;
       div_res(uu, nullptr, p, wdt);

@@ -152,7 +152,7 @@ def test_trained_guess_gain_over_plain_warm_start():
     Sphere wake, 128 x 64 x 64 (tiled multigrid), FP32, tolerance 1e-6: a learned run
     trains online for 40 steps (starting from a zero output layer, i.e. from the
     plain warm start), then runs 20 guided steps; a plain run takes the same steps.
-    Multigrid judges every guess (it is used only if its initial residual is below
+    Multigrid decides on every guess (it is used only if its initial residual is below
     the warm start's), so the guided solves need no more cycles than the plain ones
     beyond what the slightly different flows explain; the V-cycles saved per step
     (possibly zero) are reported.
