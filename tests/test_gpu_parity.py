@@ -183,6 +183,28 @@ def test_one_step_other_solver_paths(name, path, prec):
     gpu.close()
 
 
+@pytest.mark.parametrize("n,periodic", [((130, 18, 14), (True, False, True)), ((75, 18, 17), (False, False, False)),
+                                         ((66, 11, 17), (False, True, False))])
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_one_step_ragged_3d_grids(n, periodic, prec):
+    """The 3-D flux shares face fluxes between neighbouring lanes and planes in bricks
+    of 63 columns: grids of two or three bricks with a ragged last one, periodic and
+    bounded axes and a body, one step against the oracle."""
+    _say("ragged step", prec, n, periodic)
+    # radius 2 keeps the body's reach (radius + 3) 3 cells from every bounded wall
+    body = wlsynth.Body("sphere", center=(0.3 * n[0], 0.5 * n[1] + 0.2, 0.5 * n[2] - 0.3), radius=2.0)
+    w = wlsynth.Workload("ragged", n, (1.0, 0.0, 0.0), 0.02, body, periodic=periodic,
+                         convective_exit=not periodic[0], tol=1e-13)
+    ref, gpu = make_pair(w, prec, 1e-13 if prec == "f64" else 1e-6)
+    ref.tol = 1e-13
+    ref.step()
+    gpu.step()
+    err = rel_l2(gpu.get("u"), ref.u, ref.grid)
+    _say("  rel-L2 u", err)
+    assert err <= (FP64_STEP if prec == "f64" else FP32_STEP)
+    gpu.close()
+
+
 def test_solver_paths_agree_on_a_large_grid():
     """256 x 128 x 128 sphere wake in FP64: the fine level takes the flat passes
     (automatic), the z-marching tiles or the generic kernels, and the first coarse
