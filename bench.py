@@ -79,11 +79,11 @@ def kernel_bytes(name, ndim, cells, faces, esize, has_body, pcg_iters, box_cells
 
 
 def fine_level_flat(n, esize=4, solver_path="auto"):
-    """The fine level takes the flat passes when it is 3-D with >= 2^15 cells and
+    """The fine level takes the flat passes when it is 3-D with >= 2^14 cells and
     rows of whole 16-byte vectors, unless the solver path asks for tiles or the
-    generic kernels."""
+    generic kernels (the library's rule)."""
     return (len(n) == 3 and solver_path in ("auto", "flat") and n[0] % (16 // esize) == 0
-            and n[0] * n[1] * n[2] >= (1 << 15))
+            and n[0] * n[1] * n[2] >= (1 << 14))
 
 
 def fine_level_tiled(n):
