@@ -275,8 +275,8 @@ def main():
         copy_probe(args.copy_probe)
         return
     if args.gpus != 1:
-        print("bench.py: this build runs on one GPU only (the multi-GPU domain decomposition is a "
-              "design, not an implementation); use --gpus 1", file=sys.stderr)
+        print("bench.py: the solver runs on one GPU (its multi-GPU domain decomposition is designed, not "
+              "implemented); use --gpus 1", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
