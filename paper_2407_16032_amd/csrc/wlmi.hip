@@ -826,9 +826,12 @@ struct Impl : SimBase {
 
   // Sum (or max) a slot's partials into its first entry when a large grid left
   // them: each block of the consumer would otherwise re-add all of them.
-  // (256 against 2048 saves ~0.15 % of the plate step: one finalize launch costs
-  // less than every block of a 1728-block level re-adding the partials)
-  static constexpr int kCollapseMin = 256;
+  static constexpr int kCollapseMin = 2048;
+  // A flat launch leaves its partials in the slots for the consumers to add only
+  // up to this many blocks, else they are totalled first (256 against 2048 saves
+  // ~0.15 % of the plate step: one finalize launch costs less than every block of
+  // a 1728-block level re-adding the partials).
+  static constexpr int kFlatDirectMax = 256;
   // Totals of n partials into slot sa / sb (sb < 0: none): in two stages when
   // there are many (a single block would wait on each load in turn).
   void reduce_wide(const double* a, int a_max, const double* b, int b_max, int n, int sa, int sb) {
@@ -867,7 +870,7 @@ struct Impl : SimBase {
     const int kidA = l == 0 ? WL_K_PCG_A : WL_K_COARSE, kidB = l == 0 ? WL_K_PCG_B : WL_K_COARSE;
     const int nf = (int)nflat[l];
     // a flat level with few blocks leaves its partials in the slots, as the tiles do
-    const bool direct = nf > 0 && nf <= kCollapseMin;
+    const bool direct = nf > 0 && nf <= kFlatDirectMax;
     collapse(kSlotSumR, 0, kSlotCnt, 0);
     for (int k = 0; k < K; ++k) {
       const int wr = k < K - 1 ? 1 : 0, wm = (fine && k == K - 1) ? 1 : 0;
@@ -1030,7 +1033,7 @@ struct Impl : SimBase {
   void vcycle(int l) {
     if (nflat[l + 1] > 0) {
       const int nf = (int)nflat[l + 1];
-      const bool direct = nf <= kCollapseMin;
+      const bool direct = nf <= kFlatDirectMax;
       double* const psum = direct ? slot(kSlotSumR) : wide;
       double* const pcnt = direct ? slot(kSlotCnt) : wide + wide_n;
       if (desc.periodic_mask)
@@ -1073,7 +1076,7 @@ struct Impl : SimBase {
     }
     if (nflat[l] > 0) {
       const int nf = (int)nflat[l];
-      const bool direct = nf <= kCollapseMin;
+      const bool direct = nf <= kFlatDirectMax;
       double* const psum = direct ? slot(kSlotSumR) : wide;
       double* const pcnt = direct ? slot(kSlotCnt) : wide + wide_n;
       if (desc.periodic_mask)
@@ -1153,7 +1156,7 @@ struct Impl : SimBase {
     // array without the fields' front padding takes the generic kernel
     const bool aligned = rhs == nullptr || (reinterpret_cast<uintptr_t>(rhs + 1) % 16) == 0;
     if (nf > 0 && aligned) {
-      const bool direct = nf <= kCollapseMin;
+      const bool direct = nf <= kFlatDirectMax;
       double* const pmax = direct ? slot(kSlotRmax) : wide;
       double* const psum = direct ? slot(kSlotSumR) : wide + wide_n;
       double* const pcnt = direct ? slot(kSlotCnt) : wide + 2 * wide_n;
