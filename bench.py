@@ -56,7 +56,7 @@ def kernel_bytes(name, ndim, cells, faces, esize, has_body, pcg_iters, box_cells
         fields = (1 + (pcg_iters - 1) / pcg_iters) + (1 if (tiled or flat) else 2)
         return (fields * cells + (1 + n) * bc) * esize
     if name == "pcg_b":
-        if tiled:  # reads e, x, r; writes x, r; iD and L (n) in the box
+        if tiled or flat:  # reads e, x, r; writes x, r; iD and L (n) in the box
             return (5 * cells + (1 + n) * bc) * esize
         return ((4 + 2) * cells + bc) * esize    # reads e, q, x, r; writes x, r; iD in the box
     if name == "divres":
@@ -147,9 +147,10 @@ def run_cpu_baseline(w_name):
 
 
 def kernel_source_hash():
+    """Hash of the step's kernels and of the host code that launches them."""
     import hashlib
     h = hashlib.sha256()
-    for f in ("wl_kernels.hpp", "wl_device.hpp"):
+    for f in ("wl_kernels.hpp", "wl_device.hpp", "wlmi.hip"):
         with open(os.path.join(ROOT, "paper_2407_16032_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
