@@ -3,14 +3,24 @@
 The paper's AutoBody holds a signed-distance function and a coordinate map;
 ``measure!`` turns them into the signed distance d, normal n and body
 velocity V at the velocity points and then into the kernel moments.  This
-oracle covers the analytic subset: a circle/sphere or a box, moved rigidly
-by heave along e_y and a rotation about e_z through a pivot.
+oracle covers rigid bodies: a circle/sphere, a box, or a signed distance
+sampled on a grid, moved by a uniform translation, heave along e_y and a
+rotation about e_z through a pivot.
 
-Body description (``wlsynth.Body``): centre c(t) = center + A_h sin(2 pi f t +
-phi_h) e_y; angle theta(t) = A_p sin(2 pi f t + phi_p) + Omega t about e_z
-through P(t) = c(t) + pivot_offset.  A world point x maps to the body frame by
-x_b = Rot(-theta)(x - P) + pivot_offset; the shape is centred at the origin of
-that frame; SDF < 0 inside.  The rigid velocity is V = dc/dt + theta' e_z x (x - P).
+Body description (``wlsynth.Body``): centre c(t) = center + velocity t +
+A_h sin(2 pi f t + phi_h) e_y; angle theta(t) = A_p sin(2 pi f t + phi_p) +
+Omega t about e_z through P(t) = c(t) + pivot_offset.  A world point x maps to
+the body frame by x_b = Rot(-theta)(x - P) + pivot_offset; the shape is centred
+at the origin of that frame; SDF < 0 inside.  The rigid velocity is
+V = dc/dt + theta' e_z x (x - P).
+
+Gridded signed distance (reading; the paper's AutoBody takes any SDF and gets
+the normal by automatic differentiation, a sampled SDF has no derivative of
+its own): d(x_b) is the trilinear (bilinear in 2-D) interpolant of the samples;
+the normal is the interpolant, with the same weights, of the per-sample
+gradient taken by central differences of the samples (one-sided at the
+grid's edges), normalised; a point outside the sampled box is fluid beyond the
+kernel's reach (d = +inf).  Both are exact for a linear distance field.
 """
 from __future__ import annotations
 
@@ -29,12 +39,14 @@ def motion(body, t):
     """(c, P, theta, cdot, omega) at time t (numpy scalars, so that complex parameters
     carry complex-step derivatives)."""
     w = 2.0 * math.pi * body.freq
+    vel = list(getattr(body, "velocity", ())) + [0.0] * 3
     c = list(body.center) + [0.0] * (3 - len(body.center))
+    c = [c[k] + vel[k] * t for k in range(3)]
     c[1] += body.heave_amp * np.sin(w * t + body.phase_h)
     po = list(body.pivot_offset) + [0.0] * (3 - len(body.pivot_offset))
     P = [c[k] + po[k] for k in range(3)]
     theta = body.pitch_amp * np.sin(w * t + body.phase_p) + body.spin_omega * t
-    cdot = [0.0, body.heave_amp * w * np.cos(w * t + body.phase_h), 0.0]
+    cdot = [vel[0], vel[1] + body.heave_amp * w * np.cos(w * t + body.phase_h), vel[2]]
     omega = body.pitch_amp * w * np.cos(w * t + body.phase_p) + body.spin_omega
     return c, P, theta, cdot, omega
 
@@ -82,6 +94,8 @@ def sdf_normal_velocity(body, X, t):
         safe = np.where(outside, olen, 1.0)
         nb = [np.where(outside, sgn[k] * o[k] / safe, np.where(arg == k, sgn[k], 0.0))
               for k in range(ndim)]
+    elif body.kind == "grid":
+        d, nb, Vs = grid_sdf(body, xb)
     else:
         raise ValueError("unknown body kind %r" % body.kind)
     # rotate the normal back to the world frame
@@ -91,7 +105,57 @@ def sdf_normal_velocity(body, X, t):
     V = [cdot[0] - omega * ry, cdot[1] + omega * rx]
     if ndim == 3:
         V.append(np.zeros_like(rx) + cdot[2])
+    if body.kind == "grid" and Vs is not None:
+        V = [V[k] + Vs[k] for k in range(ndim)]
     return d, n, V
+
+
+def _trilinear(samples, u):
+    """Multilinear interpolant of ``samples`` (indexed [i, j(, k)]) at fractional
+    sample coordinates u (list of arrays, all inside [0, n-1])."""
+    nd = len(u)
+    shape = samples.shape
+    i0 = [np.clip(np.floor(u[k]).astype(np.int64), 0, shape[k] - 2) for k in range(nd)]
+    fr = [u[k] - i0[k] for k in range(nd)]
+    out = np.zeros(np.shape(u[0]))
+    for corner in range(1 << nd):
+        wgt = np.ones(np.shape(u[0]))
+        idx = []
+        for k in range(nd):
+            bit = (corner >> k) & 1
+            wgt = wgt * (fr[k] if bit else 1.0 - fr[k])
+            idx.append(i0[k] + bit)
+        out = out + wgt * samples[tuple(idx)]
+    return out
+
+
+def grid_sdf(body, xb):
+    """Signed distance, unit normal (body frame) and sampled velocity (list or None)
+    of a gridded body at body-frame points xb (see the module docstring)."""
+    nd = len(xb)
+    s = np.asarray(body.sdf_grid, dtype=np.float64)
+    if s.ndim != nd or min(s.shape) < 2:
+        raise ValueError("sdf_grid must have ndim axes of at least 2 samples")
+    h = float(body.grid_h)
+    o = list(body.grid_origin) + [0.0] * 3
+    u = [(np.asarray(xb[k], dtype=np.float64) - o[k]) / h for k in range(nd)]
+    inside = np.ones(np.shape(u[0]), dtype=bool)
+    for k in range(nd):
+        inside &= (u[k] >= 0.0) & (u[k] <= s.shape[k] - 1)
+    uc = [np.where(inside, u[k], 0.0) for k in range(nd)]
+    d = np.where(inside, _trilinear(s, uc), np.inf)
+    # per-sample gradient: central differences, one-sided at the edges
+    grads = np.gradient(s, h, edge_order=1) if nd > 1 else [np.gradient(s, h, edge_order=1)]
+    gn = [_trilinear(grads[k], uc) for k in range(nd)]
+    mag = np.sqrt(sum(v * v for v in gn))
+    ok = inside & (mag > 0)
+    safe = np.where(ok, mag, 1.0)
+    nb = [np.where(ok, gn[k] / safe, 1.0 if k == 0 else 0.0) for k in range(nd)]
+    Vs = None
+    if getattr(body, "vel_grid", None) is not None:
+        vg = np.asarray(body.vel_grid, dtype=np.float64)
+        Vs = [np.where(inside, _trilinear(vg[k], uc), 0.0) for k in range(nd)]
+    return d, nb, Vs
 
 
 def face_points(grid, comp):

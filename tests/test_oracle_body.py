@@ -6,7 +6,7 @@ import pytest
 
 import wlsynth
 from oracle import Grid
-from oracle.body import cell_points, forces, measure, sdf_normal_velocity
+from oracle.body import cell_points, face_points, forces, measure, sdf_normal_velocity
 
 
 def test_box_sdf_known_points():
@@ -90,3 +90,133 @@ def test_forces_viscous_constant_strain_integrates_to_zero():
     u = [np.tile(0.2 * y, (42, 1)), np.zeros(g.shape)]
     _, Fv = forces(g, b, 0.0, u, np.zeros(g.shape), nu=0.5)
     assert np.abs(Fv).max() < 1e-12
+
+
+@pytest.mark.parametrize("comp", [0, 1])
+def test_forces_viscous_quadratic_shear_on_circle(comp):
+    # u_comp = (other coordinate)^2: S has one off-diagonal entry equal to that
+    # coordinate, whose divergence is the unit vector e_comp, so by the divergence
+    # theorem F_v = 2 nu (area) e_comp (central differences are exact on a quadratic)
+    R, nu = 8.0, 0.3
+    g = Grid((48, 48))
+    b = wlsynth.Body("sphere", center=(24.2, 23.7), radius=R)
+    other = 1 - comp
+    u = [np.zeros(g.shape), np.zeros(g.shape)]
+    X = face_points(g, comp)
+    u[comp] = (X[other] - b.center[other]) ** 2
+    _, Fv = forces(g, b, 0.0, u, np.zeros(g.shape), nu=nu)
+    expect = np.zeros(2)
+    expect[comp] = 2 * nu * math.pi * R * R
+    assert abs(Fv[comp] - expect[comp]) < 1e-2 * expect[comp]
+    assert abs(Fv[other]) < 1e-3 * expect[comp]
+
+
+def test_forces_viscous_quadratic_shear_on_sphere():
+    R, nu = 7.0, 0.2
+    g = Grid((32, 32, 32))
+    b = wlsynth.Body("sphere", center=(16.1, 15.8, 16.3), radius=R)
+    X = face_points(g, 0)
+    u = [(X[1] - b.center[1]) ** 2, np.zeros(g.shape), np.zeros(g.shape)]
+    _, Fv = forces(g, b, 0.0, u, np.zeros(g.shape), nu=nu)
+    expect = 2 * nu * 4.0 / 3.0 * math.pi * R ** 3
+    assert abs(Fv[0] - expect) < 1e-2 * expect
+    assert np.abs(Fv[1:]).max() < 1e-3 * expect
+
+
+def test_translating_body_motion():
+    b = wlsynth.Body("sphere", center=(10.0, 8.0), radius=2.0, velocity=(0.7, -0.2))
+    assert b.moving
+    X = [np.array([12.0, 10.0]), np.array([8.0, 8.5])]
+    t = 3.0
+    d, _, V = sdf_normal_velocity(b, X, t)
+    c = (10.0 + 0.7 * t, 8.0 - 0.2 * t)
+    np.testing.assert_allclose(d, np.hypot(X[0] - c[0], X[1] - c[1]) - 2.0, atol=1e-14)
+    np.testing.assert_array_equal(V[0], 0.7)
+    np.testing.assert_array_equal(V[1], -0.2)
+
+
+# ---------------------------------------------------------------------------
+# gridded signed distance
+# ---------------------------------------------------------------------------
+def _plane_body(ndim, normal, offset, h=0.7, pitch=0.0):
+    nrm = np.asarray(normal, dtype=np.float64)
+    nrm = nrm / np.linalg.norm(nrm)
+    sdf, origin = wlsynth.sampled_sdf(lambda X: sum(nrm[k] * X[k] for k in range(ndim)) - offset, 6.0, h, ndim)
+    ctr = (20.0, 20.0, 20.0)[:ndim]
+    return wlsynth.Body("grid", center=ctr, sdf_grid=sdf, grid_origin=origin, grid_h=h, pitch_amp=pitch,
+                        phase_p=math.pi / 2), nrm
+
+
+@pytest.mark.parametrize("ndim", [2, 3])
+def test_grid_sdf_exact_on_a_linear_field(ndim):
+    # multilinear interpolation and central/one-sided differences are exact on a
+    # linear function: d and n equal the plane's at any point of the sampled box
+    normal = (0.3, -0.8, 0.52)[:ndim]
+    b, nrm = _plane_body(ndim, normal, 0.4)
+    rng = np.random.default_rng(5)
+    Xb = [rng.uniform(-5.9, 5.9, 500) for _ in range(ndim)]
+    X = [Xb[k] + b.center[k] for k in range(ndim)]
+    d, n, V = sdf_normal_velocity(b, X, 0.0)
+    np.testing.assert_allclose(d, sum(nrm[k] * Xb[k] for k in range(ndim)) - 0.4, atol=1e-12)
+    for k in range(ndim):
+        np.testing.assert_allclose(n[k], nrm[k], atol=1e-12)
+        assert np.all(V[k] == 0.0)
+
+
+def test_grid_sdf_rotated_normal_follows_the_body():
+    b, nrm = _plane_body(2, (1.0, 0.0), 0.0, pitch=0.5)
+    X = [np.array([20.5, 21.0]), np.array([20.2, 19.1])]
+    d, n, _ = sdf_normal_velocity(b, X, 0.0)
+    np.testing.assert_allclose(n[0], math.cos(0.5), atol=1e-12)
+    np.testing.assert_allclose(n[1], math.sin(0.5), atol=1e-12)
+
+
+def test_grid_sdf_interpolates_the_samples_and_is_fluid_outside():
+    rng = np.random.default_rng(2)
+    sdf = rng.normal(size=(5, 6, 4))
+    b = wlsynth.Body("grid", center=(0.0, 0.0, 0.0), sdf_grid=sdf, grid_origin=(1.0, 2.0, 3.0), grid_h=0.5)
+    I = np.array([0, 4, 2, 3]), np.array([0, 5, 1, 4]), np.array([0, 3, 2, 1])
+    X = [1.0 + 0.5 * I[0], 2.0 + 0.5 * I[1], 3.0 + 0.5 * I[2]]
+    d, _, _ = sdf_normal_velocity(b, X, 0.0)
+    np.testing.assert_allclose(d, sdf[I], atol=1e-14)
+    d, n, _ = sdf_normal_velocity(b, [np.array([0.9]), np.array([3.0]), np.array([4.0])], 0.0)
+    assert np.isinf(d[0]) and d[0] > 0
+
+
+def test_grid_sdf_sampled_velocity_adds_to_the_rigid_one():
+    sdf, origin = wlsynth.sampled_sdf(lambda X: np.hypot(X[0], X[1]) - 3.0, 6.0, 0.5, 2)
+    vg = np.stack([np.full(sdf.shape, 0.25), np.full(sdf.shape, -0.5)])
+    b = wlsynth.Body("grid", center=(10.0, 10.0), sdf_grid=sdf, vel_grid=vg, grid_origin=origin, grid_h=0.5,
+                     velocity=(1.0, 0.0))
+    _, _, V = sdf_normal_velocity(b, [np.array([11.0]), np.array([9.0])], 0.0)
+    np.testing.assert_allclose([V[0][0], V[1][0]], [1.25, -0.5], atol=1e-15)
+
+
+@pytest.mark.parametrize("ndim", [2, 3])
+def test_grid_sdf_sphere_moments_converge_second_order(ndim):
+    # the sampled sphere reproduces the analytic sphere's mu0, mu1 and V with an
+    # O(h^2) error: halving the sample spacing cuts it by about 4
+    R = 6.0
+    n = (32, 32) if ndim == 2 else (24, 24, 24)
+    ctr = (16.3, 15.6, 12.2)[:ndim] if ndim == 2 else (12.3, 11.6, 12.2)
+    g = Grid(n)
+    ref = wlsynth.Body("sphere", center=ctr, radius=R, spin_omega=0.05)
+    m0r, m1r, Vr = measure(g, ref, 0.0)
+    # V is cut off at d = 2 + eps: faces within 0.1 of the cut may fall on either side
+    keep = []
+    for i in range(ndim):
+        d, _, _ = sdf_normal_velocity(ref, face_points(g, i), 0.0)
+        keep.append(np.abs(d - 3.0) > 0.1)
+    errs = []
+    for h in (0.8, 0.4):
+        gb = wlsynth.grid_sphere_body(R, h, ndim, ctr, spin_omega=0.05)
+        m0, m1, V = measure(g, gb, 0.0)
+        e = 0.0
+        for i in range(ndim):
+            e = max(e, float(np.max(np.abs(m0[i] - m0r[i]))))
+            for j in range(ndim):
+                e = max(e, float(np.max(np.abs(m1[i][j] - m1r[i][j]))))
+            e = max(e, float(np.max(np.abs(V[i] - Vr[i])[keep[i]])))
+        errs.append(e)
+    assert errs[1] < 1e-2
+    assert errs[0] / errs[1] > 3.0, errs

@@ -59,11 +59,16 @@ def face_noise(shape: Sequence[int], comp: int, amp: float, seed: int = 0) -> np
 # ---------------------------------------------------------------------------
 @dataclasses.dataclass
 class Body:
-    """Analytic rigid body.  ``kind`` is 'none', 'sphere' (circle in 2-D) or 'box'.
+    """Rigid body.  ``kind`` is 'none', 'sphere' (circle in 2-D), 'box' or 'grid'.
 
-    Motion: centre c(t) = center + heave_amp*sin(2 pi freq t + phase_h) e_y;
+    Motion: centre c(t) = center + velocity*t + heave_amp*sin(2 pi freq t + phase_h) e_y;
     rotation angle about e_z through c(t) + pivot_offset:
     theta(t) = pitch_amp*sin(2 pi freq t + phase_p) + spin_omega*t.
+
+    'grid': the signed distance is sampled in the body frame, sample (i, j[, k]) of
+    ``sdf_grid`` (numpy, indexed [i, j(, k)], x first) sitting at
+    ``grid_origin + (i, j, k) * grid_h``; ``vel_grid`` (optional, shape (ndim,) +
+    sdf_grid.shape) adds a sampled velocity to the rigid one.
     """
     kind: str = "none"
     center: Tuple[float, ...] = (0.0, 0.0, 0.0)
@@ -76,11 +81,17 @@ class Body:
     phase_p: float = 0.0
     pivot_offset: Tuple[float, ...] = (0.0, 0.0, 0.0)
     spin_omega: float = 0.0
+    velocity: Tuple[float, ...] = (0.0, 0.0, 0.0)
+    sdf_grid: Optional[np.ndarray] = None
+    vel_grid: Optional[np.ndarray] = None
+    grid_origin: Tuple[float, ...] = (0.0, 0.0, 0.0)
+    grid_h: float = 1.0
 
     @property
     def moving(self) -> bool:
         return self.kind != "none" and (self.heave_amp != 0.0 or self.pitch_amp != 0.0
-                                        or self.spin_omega != 0.0)
+                                        or self.spin_omega != 0.0
+                                        or any(v != 0.0 for v in self.velocity))
 
 
 @dataclasses.dataclass
@@ -166,6 +177,23 @@ def plate_3d(scale: int = 1, steps=200, tol=1e-5) -> Workload:
                 pivot_offset=(-c / 4, 0.0, 0.0))
     return Workload("plate3d_%dx%dx%d" % n, n, (1.0, 0.0, 0.0), c / 5000.0, body,
                     convective_exit=True, steps=steps, tol=tol, L=c)
+
+
+def sampled_sdf(fn, half_width: float, h: float, ndim: int):
+    """Samples of a body-frame signed distance ``fn(list of coordinate arrays)`` on the
+    grid origin + (i, j, k) h covering [-half_width, half_width]^ndim.  Returns
+    (samples indexed [i, j(, k)], origin tuple)."""
+    n = int(math.ceil(2.0 * half_width / h)) + 1
+    origin = -0.5 * (n - 1) * h
+    ax = origin + h * np.arange(n, dtype=np.float64)
+    X = np.meshgrid(*([ax] * ndim), indexing="ij")
+    return np.ascontiguousarray(fn(X), dtype=np.float64), (origin,) * ndim
+
+
+def grid_sphere_body(R: float, h: float, ndim: int, center, margin: float = 5.0, **motion) -> Body:
+    """A 'grid' body holding samples of the sphere (circle) distance |x_b| - R."""
+    sdf, origin = sampled_sdf(lambda X: np.sqrt(sum(x * x for x in X)) - R, R + margin, h, ndim)
+    return Body("grid", center=tuple(center), sdf_grid=sdf, grid_origin=origin, grid_h=h, **motion)
 
 
 # ---------------------------------------------------------------------------
