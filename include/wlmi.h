@@ -64,6 +64,8 @@ typedef enum { WL_F32 = 0, WL_F64 = 1 } wl_prec;
 typedef struct {
   int ndim;              /* 2 or 3 */
   int64_t n[3];          /* interior cells per axis; n[2] ignored in 2-D.  Each >= 4. */
+  double L;              /* characteristic length in cells (the paper's Simulation argument L):
+                            wl_sim_time reports t |U| / L [1] */
   double U[3];           /* free-stream velocity (inflow/slip normal faces take U_i) */
   double nu;             /* kinematic viscosity (>= 0) */
   unsigned periodic_mask;/* bit d set -> axis d periodic */
@@ -79,7 +81,7 @@ typedef struct {
   int learned_guess;     /* 1 -> plan the buffers of the learned initial guess (3-D only) */
   int adjoint;           /* 1 -> plan the buffers of the discrete adjoint (wl_adj_*) */
   int solver_path;       /* PCG kernels of the 3-D multigrid levels: 0 = automatic (flat
-                            vector passes on every level of >= 2^15 cells whose rows hold
+                            vector passes on every level of >= 2^14 cells whose rows hold
                             whole 16-byte vectors), 1 = z-marching tiles on the levels of
                             >= 2^18 cells, 2 = as 0, 3 = the generic grid-stride kernels
                             only.  The levels of <= 4096 cells run the single-workgroup
@@ -87,22 +89,76 @@ typedef struct {
                             differ in rounding order only. [0] */
 } wl_sim_desc;
 
-typedef enum { WL_BODY_NONE = 0, WL_BODY_SPHERE = 1, WL_BODY_BOX = 2 } wl_body_kind;
+typedef enum {
+  WL_BODY_NONE = 0,
+  WL_BODY_SPHERE = 1,   /* |x_b| - radius (a circle in 2-D) */
+  WL_BODY_BOX = 2,      /* box of half extents half_extent, centred at the body-frame origin */
+  WL_BODY_GRID_SDF = 3, /* signed distance sampled on a grid in the body frame (see below) */
+  WL_BODY_PLANE = 4     /* half space normal . x_b - radius <= 0 (normal: body frame, unit) */
+} wl_body_kind;
 
-/* Analytic rigid body (the paper's AutoBody restricted to a sphere/circle or
- * a box moved rigidly).  Centre c(t) = center + heave_amp*sin(2 pi freq t +
- * phase_h) e_y.  Rotation angle about e_z through P(t) = c(t) + pivot_offset:
- * theta(t) = pitch_amp*sin(2 pi freq t + phase_p) + spin_omega*t.  Body-frame
- * coordinates x_b = Rot(-theta)(x - P) + pivot_offset; SDF < 0 inside.
- * The body must stay at least 3 cells away from non-periodic domain faces. */
-typedef struct {
+/* How a part combines with the body formed by the parts before it (paper,
+ * applications section: bodies are combined by the arithmetic of their signed
+ * distances).  UNION takes the part nearer to the point (min of d), INTERSECT
+ * the farther (max of d), SUBTRACT the body minus the part (max of d and -d_part).
+ * The point takes d, n and V of the part that wins, n flipped with d for a
+ * subtracted part. */
+typedef enum { WL_OP_UNION = 0, WL_OP_INTERSECT = 1, WL_OP_SUBTRACT = 2 } wl_body_op;
+
+/* A body (the paper's AutoBody: a signed-distance function and a coordinate
+ * map; software-design section).  One descriptor is one part; parts chain
+ * through `next` (at most 8), each combined with those before it by its `op`
+ * (ignored on the first).
+ *
+ * Map of a part from world coordinates x to its body frame x_b:
+ *   x_b = S(t) * (Rot(-theta(t)) (x - P(t))) + pivot_offset     (* per axis)
+ *   P(t) = center + velocity t + heave_amp sin(2 pi freq t + phase_h) e_h + pivot_offset
+ *   theta(t) = pitch_amp sin(2 pi freq t + phase_p) + spin_omega t  (about e_z)
+ *   S_a(t) = 1 + scale_amp[a] sin(2 pi freq t + phase_s)
+ * with e_h = heave_dir normalised (e_y when heave_dir is zero).  The shape is
+ * defined in the body frame around its origin; SDF < 0 inside; shell > 0 makes
+ * the part hollow (|SDF| - shell).
+ * Measured quantities at a point (paper: every geometric property comes from
+ * derivatives of the SDF and of the map): the normal n is the world gradient of
+ * the part's SDF through the map, normalised, and d is the SDF divided by that
+ * gradient's magnitude (the two agree with the SDF and its normal when the map is
+ * rigid, S = 1); the body velocity is V = -J^{-1} dx_b/dt with J = dx_b/dx, the
+ * velocity of the material point the map holds fixed (rigid motion: the velocity
+ * of P plus the angular velocity times x - P).
+ * Gridded SDF: sdf_grid holds grid_n[0] x grid_n[1] (x grid_n[2]) samples (each
+ * >= 2), in the simulation's precision, x fastest: sample (i, j, k) at index
+ * (k grid_n[1] + j) grid_n[0] + i sits at body-frame point grid_origin +
+ * (i, j, k) grid_h.  d is the multilinear interpolant of the samples; the
+ * normal is the interpolant, with the same weights, of the samples' gradients by
+ * central differences (one-sided on the grid's faces), normalised; outside the
+ * sampled box the point is fluid beyond the kernel's reach.  vel_grid (may be
+ * NULL) holds ndim components of the same shape, one after the other, whose
+ * interpolant is added to the map's velocity.  Both arrays are device pointers,
+ * read at creation (and by wl_body_update) into the workspace, so the caller may
+ * free them afterwards.
+ * The body must stay at least 3 cells away from non-periodic domain faces
+ * (checked at every measure of a moving body). */
+typedef struct wl_body_desc {
   int kind;                 /* wl_body_kind */
   double center[3];
-  double radius;            /* sphere/circle */
+  double radius;            /* sphere/circle radius; plane offset */
   double half_extent[3];    /* box */
   double heave_amp, pitch_amp, freq, phase_h, phase_p;
   double pivot_offset[3];
   double spin_omega;
+  double velocity[3];       /* uniform translation of P */
+  double heave_dir[3];      /* direction of the heave (zero: e_y) */
+  double scale_amp[3];      /* per-axis amplitude of the map's scale S(t) */
+  double phase_s;           /* phase of S(t) */
+  double normal[3];         /* plane normal in the body frame */
+  double shell;             /* > 0: hollow part of this half thickness */
+  const void* sdf_grid;     /* WL_BODY_GRID_SDF: device samples (simulation precision) */
+  const void* vel_grid;     /* optional sampled velocity, ndim components */
+  int64_t grid_n[3];
+  double grid_origin[3];
+  double grid_h;
+  int op;                   /* wl_body_op: combination with the parts before this one */
+  const struct wl_body_desc* next;  /* next part or NULL */
 } wl_body_desc;
 
 typedef struct {
@@ -111,6 +167,8 @@ typedef struct {
   double dt_next;       /* CFL step for the next call */
   int vcycles[2];       /* predictor / corrector multigrid V-cycles */
   double res_linf[2];   /* final residual max-norms of the two solves (FP64) */
+  double res_l2[2];     /* final residual 2-norms over the active cells (FP64 sums) */
+  double div_linf;      /* max |div u| over the active cells after the step (FP64) */
   int converged;        /* 1 if both solves met mg_tol */
 } wl_step_stats;
 
@@ -118,6 +176,7 @@ typedef struct {
   int vcycles;
   double res0_linf;     /* residual max-norm before the first cycle */
   double res_linf;      /* after the last cycle */
+  double res_l2;        /* 2-norm of the final residual over the active cells (FP64 sums) */
   int converged;
 } wl_solve_stats;
 
@@ -208,6 +267,10 @@ wl_status wl_levels(wl_sim* sim, int* nlevels, int level, int64_t n_out[3]);
 /* Set the clock and the next time step. */
 wl_status wl_set_time(wl_sim* sim, double t, double dt_next);
 wl_status wl_get_time(wl_sim* sim, double* t, double* dt_next);
+
+/* Convective time t* = t |U| / L of the current clock (the paper's time scale
+ * tU/L), with |U| the magnitude of desc.U, taken as 1 when U = 0. */
+wl_status wl_sim_time(wl_sim* sim, double* t_star);
 
 /* Replace the body's parameters (same kind) and re-measure at the current time. */
 wl_status wl_body_update(wl_sim* sim, const wl_body_desc* body);

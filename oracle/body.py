@@ -21,6 +21,22 @@ the normal is the interpolant, with the same weights, of the per-sample
 gradient taken by central differences of the samples (one-sided at the
 grid's edges), normalised; a point outside the sampled box is fluid beyond the
 kernel's reach (d = +inf).  Both are exact for a linear distance field.
+
+General bodies (the paper's AutoBody: any SDF and any coordinate map, with
+every geometric property taken from derivatives, which the paper obtains by
+automatic differentiation).  A body is a chain of parts, each a shape (sphere,
+box, plane, gridded SDF, optionally hollowed to |SDF| - shell) seen through its
+own map x_b = S(t) * Rot(-theta(t)) (x - P(t)) + pivot_offset.  Reading of the
+measured quantities: with g the world gradient of SDF(x_b(x, t)),
+n = g / |g| and d = SDF / |g| (the map need not preserve distances; the ratio
+is the distance to first order, and equals the SDF when the map is rigid);
+V = -J^{-1} dx_b/dt with J = dx_b/dx (the velocity of the material point that
+the map holds fixed).  The oracle takes g, J and dx_b/dt by the complex step
+(exact derivatives, independent of any hand derivation).  Parts combine in
+order by the arithmetic of signed distances (the paper's body = a + b, a - b):
+union keeps the nearer part, intersection the farther, subtraction compares
+with the negated part; the winning part supplies d, n and V (n and d negated
+for a subtracted part); ties keep the earlier parts.
 """
 from __future__ import annotations
 
@@ -35,18 +51,31 @@ from .moments import kernel_eps, mu0, mu1
 MU0_CUT = 1e-6
 
 
+def _vec3(v):
+    v = list(v) if v is not None else []
+    return [v[k] if k < len(v) else 0.0 for k in range(3)]
+
+
+def heave_direction(body):
+    e = _vec3(getattr(body, "heave_dir", ()))
+    m = math.sqrt(sum(v * v for v in e))
+    return [0.0, 1.0, 0.0] if m == 0.0 else [v / m for v in e]
+
+
 def motion(body, t):
     """(c, P, theta, cdot, omega) at time t (numpy scalars, so that complex parameters
     carry complex-step derivatives)."""
     w = 2.0 * math.pi * body.freq
-    vel = list(getattr(body, "velocity", ())) + [0.0] * 3
-    c = list(body.center) + [0.0] * (3 - len(body.center))
-    c = [c[k] + vel[k] * t for k in range(3)]
-    c[1] += body.heave_amp * np.sin(w * t + body.phase_h)
-    po = list(body.pivot_offset) + [0.0] * (3 - len(body.pivot_offset))
+    vel = _vec3(getattr(body, "velocity", ()))
+    eh = heave_direction(body)
+    c = _vec3(body.center)
+    hv = body.heave_amp * np.sin(w * t + body.phase_h)
+    hd = body.heave_amp * w * np.cos(w * t + body.phase_h)
+    c = [c[k] + vel[k] * t + hv * eh[k] for k in range(3)]
+    po = _vec3(body.pivot_offset)
     P = [c[k] + po[k] for k in range(3)]
     theta = body.pitch_amp * np.sin(w * t + body.phase_p) + body.spin_omega * t
-    cdot = [vel[0], vel[1] + body.heave_amp * w * np.cos(w * t + body.phase_h), vel[2]]
+    cdot = [vel[k] + hd * eh[k] for k in range(3)]
     omega = body.pitch_amp * w * np.cos(w * t + body.phase_p) + body.spin_omega
     return c, P, theta, cdot, omega
 
@@ -58,6 +87,8 @@ def sdf_normal_velocity(body, X, t):
     the box inside region, the face of largest q = |x_b| - h wins (first axis
     on ties); sign(0) counts as +.
     """
+    if getattr(body, "composite", False):
+        return general_eval(body, X, t)
     ndim = len(X)
     c, P, theta, cdot, omega = motion(body, t)
     po = list(body.pivot_offset) + [0.0] * 3
@@ -156,6 +187,137 @@ def grid_sdf(body, xb):
         vg = np.asarray(body.vel_grid, dtype=np.float64)
         Vs = [np.where(inside, _trilinear(vg[k], uc), 0.0) for k in range(nd)]
     return d, nb, Vs
+
+
+# ---------------------------------------------------------------------------
+# general bodies: complex-step derivatives of map and SDF, and their arithmetic
+# ---------------------------------------------------------------------------
+_CS = 1e-30  # complex step
+
+
+def _cabs(z):
+    return np.where(np.real(z) < 0, -z, z)
+
+
+def _cmax_first(a, b):
+    """max by real part; a tie keeps a."""
+    return np.where(np.real(b) > np.real(a), b, a)
+
+
+def part_map(part, X, t):
+    """Body-frame coordinates x_b of world points X (list of ndim arrays) at time t.
+    Complex inputs carry complex-step derivatives."""
+    nd = len(X)
+    _, P, theta, _, _ = motion(part, t)
+    w = 2.0 * math.pi * part.freq
+    sa = _vec3(getattr(part, "scale_amp", ()))
+    S = [1.0 + sa[k] * np.sin(w * t + getattr(part, "phase_s", 0.0)) for k in range(3)]
+    po = _vec3(part.pivot_offset)
+    ct, st = np.cos(theta), np.sin(theta)
+    rx = X[0] - P[0]
+    ry = X[1] - P[1]
+    xb = [S[0] * (ct * rx + st * ry) + po[0], S[1] * (-st * rx + ct * ry) + po[1]]
+    if nd == 3:
+        xb.append(S[2] * (X[2] - P[2]) + po[2])
+    return xb
+
+
+def shape_sdf(part, xb):
+    """Signed distance of an analytic shape (before any hollowing), complex-capable."""
+    nd = len(xb)
+    if part.kind == "sphere":
+        return np.sqrt(sum(v * v for v in xb)) - part.radius
+    if part.kind == "box":
+        h = _vec3(part.half_extent)
+        q = [_cabs(xb[k]) - h[k] for k in range(nd)]
+        o = [np.where(np.real(qk) > 0.0, qk, 0.0 * qk) for qk in q]
+        olen = np.sqrt(sum(v * v for v in o))
+        qmax = q[0]
+        for k in range(1, nd):
+            qmax = _cmax_first(qmax, q[k])
+        return olen + np.where(np.real(qmax) < 0.0, qmax, 0.0 * qmax)
+    if part.kind == "plane":
+        nrm = _vec3(part.normal)[:nd]
+        m = math.sqrt(sum(v * v for v in nrm))
+        return sum((nrm[k] / m) * xb[k] for k in range(nd)) - part.radius
+    raise ValueError("no analytic SDF for kind %r" % part.kind)
+
+
+def part_general(part, X, t):
+    """d, n, V of one part at world points X (general evaluation)."""
+    nd = len(X)
+    X = [np.asarray(x, dtype=np.float64) for x in X]
+    xb = part_map(part, X, t)
+    # J[j][k] = d x_b_j / d x_k and d x_b / dt by the complex step
+    J = [[None] * nd for _ in range(nd)]
+    for k in range(nd):
+        Xk = [X[m] + (1j * _CS if m == k else 0.0) for m in range(nd)]
+        xbk = part_map(part, Xk, t)
+        for j in range(nd):
+            J[j][k] = np.imag(xbk[j]) / _CS
+    xbt = part_map(part, X, t + 1j * _CS)
+    dxdt = [np.imag(v) / _CS for v in xbt]
+    shell = float(getattr(part, "shell", 0.0))
+    Vs = None
+    if part.kind == "grid":
+        dt_, nb, Vs = grid_sdf(part, xb)
+        if shell > 0.0:
+            sg = np.where(dt_ < 0.0, -1.0, 1.0)
+            nb = [sg * v for v in nb]
+            dt_ = np.abs(dt_) - shell
+        g = [sum(J[j][k] * nb[j] for j in range(nd)) for k in range(nd)]
+    else:
+        def f(xx):
+            v = shape_sdf(part, xx)
+            return _cabs(v) - shell if shell > 0.0 else v
+        dt_ = np.real(f(xb))
+        g = []
+        for k in range(nd):
+            Xk = [X[m] + (1j * _CS if m == k else 0.0) for m in range(nd)]
+            g.append(np.imag(f(part_map(part, Xk, t))) / _CS)
+        if part.kind == "sphere":
+            # the centre: the body-frame normal is e_x there (as for the rigid sphere)
+            r0 = np.sqrt(sum(np.real(v) ** 2 for v in xb)) == 0.0
+            if np.any(r0):
+                nb0 = [1.0 if j == 0 else 0.0 for j in range(nd)]
+                sg = 1.0
+                g = [np.where(r0, sg * sum(J[j][k] * nb0[j] for j in range(nd)), g[k]) for k in range(nd)]
+    gm = np.sqrt(sum(v * v for v in g))
+    ok = gm > 0.0
+    safe = np.where(ok, gm, 1.0)
+    d = np.where(ok, dt_ / safe, dt_)
+    n = [np.where(ok, g[k] / safe, 1.0 if k == 0 else 0.0) for k in range(nd)]
+    # V = -J^{-1} dx_b/dt, point by point
+    Jm = np.stack([np.stack([np.broadcast_to(J[j][k], d.shape) for k in range(nd)], axis=-1)
+                   for j in range(nd)], axis=-2)
+    rhs = np.stack([np.broadcast_to(v, d.shape) for v in dxdt], axis=-1)[..., None]
+    sol = np.linalg.solve(Jm, rhs)[..., 0]
+    V = [-sol[..., k] for k in range(nd)]
+    if Vs is not None:
+        V = [V[k] + Vs[k] for k in range(nd)]
+    return d, n, V
+
+
+def general_eval(body, X, t):
+    """d, n, V of a chain of parts combined by signed-distance arithmetic."""
+    parts = body.parts()
+    d, n, V = part_general(parts[0], X, t)
+    for p in parts[1:]:
+        db, nb, Vb = part_general(p, X, t)
+        if p.op == "union":
+            take = db < d
+        elif p.op == "intersect":
+            take = db > d
+        elif p.op == "subtract":
+            db = -db
+            nb = [-v for v in nb]
+            take = db > d
+        else:
+            raise ValueError("unknown op %r" % p.op)
+        d = np.where(take, db, d)
+        n = [np.where(take, nb[k], n[k]) for k in range(len(n))]
+        V = [np.where(take, Vb[k], V[k]) for k in range(len(V))]
+    return d, n, V
 
 
 def face_points(grid, comp):

@@ -59,16 +59,24 @@ def face_noise(shape: Sequence[int], comp: int, amp: float, seed: int = 0) -> np
 # ---------------------------------------------------------------------------
 @dataclasses.dataclass
 class Body:
-    """Rigid body.  ``kind`` is 'none', 'sphere' (circle in 2-D), 'box' or 'grid'.
+    """One part of a body (the fields mirror ``wl_body_desc``).
 
-    Motion: centre c(t) = center + velocity*t + heave_amp*sin(2 pi freq t + phase_h) e_y;
-    rotation angle about e_z through c(t) + pivot_offset:
-    theta(t) = pitch_amp*sin(2 pi freq t + phase_p) + spin_omega*t.
+    ``kind`` is 'none', 'sphere' (circle in 2-D), 'box', 'grid' or 'plane'.
+
+    Map of the part from world to body frame:
+    x_b = S(t) * Rot(-theta(t)) (x - P(t)) + pivot_offset, with
+    P(t) = center + velocity*t + heave_amp*sin(2 pi freq t + phase_h) e_h + pivot_offset
+    (e_h = heave_dir normalised, e_y when zero), theta(t) = pitch_amp*sin(2 pi freq t +
+    phase_p) + spin_omega*t about e_z, S_a(t) = 1 + scale_amp[a]*sin(2 pi freq t + phase_s).
 
     'grid': the signed distance is sampled in the body frame, sample (i, j[, k]) of
     ``sdf_grid`` (numpy, indexed [i, j(, k)], x first) sitting at
     ``grid_origin + (i, j, k) * grid_h``; ``vel_grid`` (optional, shape (ndim,) +
-    sdf_grid.shape) adds a sampled velocity to the rigid one.
+    sdf_grid.shape) adds a sampled velocity to the map's.  'plane': the half space
+    normal . x_b - radius <= 0.  ``shell`` > 0 makes the part hollow.
+
+    Parts chain through ``next``; each later part combines with the ones before it
+    by ``op`` ('union', 'intersect', 'subtract').
     """
     kind: str = "none"
     center: Tuple[float, ...] = (0.0, 0.0, 0.0)
@@ -82,16 +90,55 @@ class Body:
     pivot_offset: Tuple[float, ...] = (0.0, 0.0, 0.0)
     spin_omega: float = 0.0
     velocity: Tuple[float, ...] = (0.0, 0.0, 0.0)
+    heave_dir: Tuple[float, ...] = (0.0, 0.0, 0.0)
+    scale_amp: Tuple[float, ...] = (0.0, 0.0, 0.0)
+    phase_s: float = 0.0
+    normal: Tuple[float, ...] = (0.0, 0.0, 0.0)
+    shell: float = 0.0
     sdf_grid: Optional[np.ndarray] = None
     vel_grid: Optional[np.ndarray] = None
     grid_origin: Tuple[float, ...] = (0.0, 0.0, 0.0)
     grid_h: float = 1.0
+    op: str = "union"
+    next: Optional["Body"] = None
+
+    def parts(self):
+        """The chain of parts starting here."""
+        out, b = [], self
+        while b is not None:
+            out.append(b)
+            b = b.next
+        return out
+
+    def _part_moving(self) -> bool:
+        return (self.heave_amp != 0.0 or self.pitch_amp != 0.0 or self.spin_omega != 0.0
+                or any(v != 0.0 for v in self.velocity)
+                or (self.freq != 0.0 and any(v != 0.0 for v in self.scale_amp)))
 
     @property
     def moving(self) -> bool:
-        return self.kind != "none" and (self.heave_amp != 0.0 or self.pitch_amp != 0.0
-                                        or self.spin_omega != 0.0
-                                        or any(v != 0.0 for v in self.velocity))
+        return self.kind != "none" and any(p._part_moving() for p in self.parts())
+
+    @property
+    def composite(self) -> bool:
+        """True when the body needs the general evaluation (several parts, a plane, a
+        hollow part or a scaled map)."""
+        for p in self.parts():
+            if p.kind == "plane" or p.shell != 0.0 or any(v != 0.0 for v in p.scale_amp):
+                return True
+        return self.next is not None
+
+
+def combine(first: Body, *rest) -> Body:
+    """A body made of ``first`` and the (op, part) pairs of ``rest`` in order; the parts
+    are copied so the arguments stay unchained."""
+    head = dataclasses.replace(first, next=None)
+    tail = head
+    for op, part in rest:
+        nxt = dataclasses.replace(part, op=op, next=None)
+        tail.next = nxt
+        tail = nxt
+    return head
 
 
 @dataclasses.dataclass
@@ -177,6 +224,33 @@ def plate_3d(scale: int = 1, steps=200, tol=1e-5) -> Workload:
                 pivot_offset=(-c / 4, 0.0, 0.0))
     return Workload("plate3d_%dx%dx%d" % n, n, (1.0, 0.0, 0.0), c / 5000.0, body,
                     convective_exit=True, steps=steps, tol=tol, L=c)
+
+
+def jelly_3d(n: int = 32, Re: float = 500.0, U: float = 1.0, steps: int = 100, tol: float = 1e-6) -> Workload:
+    """A pulsing jellyfish-like bell (paper, applications section: a hollow sphere
+    whose map scales x and y harmonically and heaves it along z, minus a half space
+    that moves with the same heave), in a downward stream -U e_z.  Radius R = 2n/3,
+    shell half thickness 1, angular frequency 2U/R, scale amplitude 0.1.  The bell
+    is centred in x and y of a (2n, 2n, 4n + n/2) box instead of on the corner of a
+    quarter domain with symmetry planes (the extra n/2 above keeps its reach clear
+    of the top face)."""
+    R = 2.0 * n / 3.0
+    hgt = 4.0 * n - 2.0 * R
+    w = 2.0 * U / R
+    f = w / (2.0 * math.pi)
+    cx = cy = float(n)
+    # sphere: x_b = A(t) (x - P) with A_xy = 1 - 0.1 cos(w t) and the centre at
+    # P_z = hgt + R/4 - (R/4)(cos w t + sin w t)
+    bell = Body("sphere", center=(cx, cy, hgt + R / 4.0), radius=R, shell=1.0,
+                scale_amp=(0.1, 0.1, 0.0), phase_s=-math.pi / 2.0, freq=f,
+                heave_amp=math.sqrt(2.0) * R / 4.0, heave_dir=(0.0, 0.0, -1.0), phase_h=math.pi / 4.0)
+    # half space z_b > 0 removed, its plane at P_z = hgt - (R/4) sin w t
+    cut = Body("plane", center=(cx, cy, hgt), normal=(0.0, 0.0, 1.0), freq=f,
+               heave_amp=R / 4.0, heave_dir=(0.0, 0.0, -1.0))
+    body = combine(bell, ("subtract", cut))
+    nz = 4 * n + n // 2
+    return Workload("jelly3d_%dx%dx%d" % (2 * n, 2 * n, nz), (2 * n, 2 * n, nz), (0.0, 0.0, -U),
+                    U * R / Re, body, steps=steps, tol=tol, L=R)
 
 
 def sampled_sdf(fn, half_width: float, h: float, ndim: int):
