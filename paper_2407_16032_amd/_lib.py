@@ -11,14 +11,15 @@ WL_OK = 0
 STATUS = {0: "WL_OK", 1: "WL_ERR_INVALID_ARG", 2: "WL_ERR_WORKSPACE_TOO_SMALL", 3: "WL_ERR_HIP",
           4: "WL_ERR_NONFINITE", 5: "WL_ERR_UNSUPPORTED"}
 WL_F32, WL_F64 = 0, 1
-BODY_KIND = {"none": 0, "sphere": 1, "box": 2}
+BODY_KIND = {"none": 0, "sphere": 1, "box": 2, "grid": 3, "plane": 4}
+BODY_OP = {"union": 0, "intersect": 1, "subtract": 2}
 FIELDS = {"u": 0, "u0": 1, "f": 2, "V": 3, "mu0": 4, "mu1": 5, "p": 6, "x": 7, "r": 8, "L": 9, "iD": 10,
           "adj_u": 11, "adj_p": 12}
 
 # every symbol include/wlmi.h declares
 EXPORTS = ["wl_workspace_bytes", "wl_sim_create", "wl_sim_destroy", "wl_measure_body", "wl_step",
            "wl_apply_bc", "wl_conv_diff", "wl_project", "wl_poisson_solve", "wl_forces", "wl_field",
-           "wl_levels", "wl_set_time", "wl_get_time", "wl_profile", "wl_profile_groups", "wl_profile_read", "wl_pg_set_weights",
+           "wl_levels", "wl_set_time", "wl_get_time", "wl_sim_time", "wl_profile", "wl_profile_groups", "wl_profile_read", "wl_pg_set_weights",
            "wl_pg_get_weights", "wl_pg_mode", "wl_pg_forward", "wl_pg_train_step", "wl_pg_stats", "wl_body_update",
            "wl_body_box",
            "wl_adj_reset", "wl_adj_forces", "wl_adj_step", "wl_adj_body_grad", "wl_last_error"]
@@ -28,7 +29,8 @@ KERNELS = ["measure", "coef", "flux", "bdim", "bc", "exit", "divres", "pcg_a", "
 
 
 class SimDesc(C.Structure):
-    _fields_ = [("ndim", C.c_int), ("n", C.c_int64 * 3), ("U", C.c_double * 3), ("nu", C.c_double),
+    _fields_ = [("ndim", C.c_int), ("n", C.c_int64 * 3), ("L", C.c_double), ("U", C.c_double * 3),
+                ("nu", C.c_double),
                 ("periodic_mask", C.c_uint), ("convective_exit", C.c_int), ("prec", C.c_int),
                 ("eps", C.c_double), ("dt0", C.c_double), ("dt_max", C.c_double),
                 ("cfl_nu_coef", C.c_double), ("mg_tol", C.c_double), ("mg_itmax", C.c_int),
@@ -37,20 +39,29 @@ class SimDesc(C.Structure):
 
 
 class BodyDesc(C.Structure):
-    _fields_ = [("kind", C.c_int), ("center", C.c_double * 3), ("radius", C.c_double),
-                ("half_extent", C.c_double * 3), ("heave_amp", C.c_double), ("pitch_amp", C.c_double),
-                ("freq", C.c_double), ("phase_h", C.c_double), ("phase_p", C.c_double),
-                ("pivot_offset", C.c_double * 3), ("spin_omega", C.c_double)]
+    pass
+
+
+BodyDesc._fields_ = [("kind", C.c_int), ("center", C.c_double * 3), ("radius", C.c_double),
+                     ("half_extent", C.c_double * 3), ("heave_amp", C.c_double), ("pitch_amp", C.c_double),
+                     ("freq", C.c_double), ("phase_h", C.c_double), ("phase_p", C.c_double),
+                     ("pivot_offset", C.c_double * 3), ("spin_omega", C.c_double),
+                     ("velocity", C.c_double * 3), ("heave_dir", C.c_double * 3), ("scale_amp", C.c_double * 3),
+                     ("phase_s", C.c_double), ("normal", C.c_double * 3), ("shell", C.c_double),
+                     ("sdf_grid", C.c_void_p), ("vel_grid", C.c_void_p), ("grid_n", C.c_int64 * 3),
+                     ("grid_origin", C.c_double * 3), ("grid_h", C.c_double), ("op", C.c_int),
+                     ("next", C.POINTER(BodyDesc))]
 
 
 class StepStats(C.Structure):
     _fields_ = [("dt", C.c_double), ("t", C.c_double), ("dt_next", C.c_double), ("vcycles", C.c_int * 2),
-                ("res_linf", C.c_double * 2), ("converged", C.c_int)]
+                ("res_linf", C.c_double * 2), ("res_l2", C.c_double * 2), ("div_linf", C.c_double),
+                ("converged", C.c_int)]
 
 
 class SolveStats(C.Structure):
     _fields_ = [("vcycles", C.c_int), ("res0_linf", C.c_double), ("res_linf", C.c_double),
-                ("converged", C.c_int)]
+                ("res_l2", C.c_double), ("converged", C.c_int)]
 
 
 _lib = None
@@ -97,6 +108,8 @@ def load(path: str = LIB_PATH):
     lib.wl_set_time.argtypes = [P, C.c_double, C.c_double]
     lib.wl_get_time.restype = C.c_int
     lib.wl_get_time.argtypes = [P, C.POINTER(C.c_double), C.POINTER(C.c_double)]
+    lib.wl_sim_time.restype = C.c_int
+    lib.wl_sim_time.argtypes = [P, C.POINTER(C.c_double)]
     lib.wl_profile.restype = C.c_int
     lib.wl_profile.argtypes = [P, C.c_int]
     lib.wl_profile_groups.restype = C.c_int

@@ -357,7 +357,7 @@ __global__ void __launch_bounds__(kBlock) k_adj_force_v(Grid3 g, BodyP b, Motion
       dn += dv[i] * n[i];
     }
     integrand -= (double(p[idx]) - pbar) * dn;
-    if (b.kind == 1) dR -= gcoef * integrand * dKdd;  // dd/dR = -1
+    if (b.p[0].kind == kShapeSphere) dR -= gcoef * integrand * dKdd;  // dd/dR = -1
     // dF/dG_ij = nu K (dir_i n_j + dir_j n_i)
     for (int i = 0; i < D; ++i) {
       const int si = g.s[i];
@@ -411,7 +411,7 @@ __global__ void __launch_bounds__(kBlock) k_adj_body(Grid3 g, BodyP b, Motion m,
       for (int j = 0; j < D; ++j) dR += double(mu1b.c[c * D + j][idx]) * s * Ks * n[j];
     }
     if (d < 2.0 + eps) {
-      const double rx = x[0] - m.P[0], ry = x[1] - m.P[1];
+      const double rx = x[0] - m.m[0].P[0], ry = x[1] - m.m[0].P[1];
       const double ezr = (c == 0) ? -ry : ((c == 1) ? rx : 0.0);
       dW += double(Vb.c[c][idx]) * ezr;
     }

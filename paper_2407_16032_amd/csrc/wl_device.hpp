@@ -22,12 +22,16 @@ constexpr int kSlotForce = kSlotExit + 1;      // 11 slots: sum p n K (3), visco
                                                // sum p and count over active cells
 constexpr int kSlotSumR = kSlotForce + 11;     // sum of the residual over active cells
 constexpr int kSlotCnt = kSlotSumR + 1;        // number of active cells
-constexpr int kNumSlots = kSlotCnt + 1;
+constexpr int kSlotL2 = kSlotCnt + 1;          // sum of the squared residual
+constexpr int kSlotDiv = kSlotL2 + 1;          // max |div u| over active cells
+constexpr int kNumSlots = kSlotDiv + 1;
 
 // scalar results (doubles)
 constexpr int kScalRmax = 0;
 constexpr int kScalCfl = 1;
 constexpr int kScalExitShift = 2;
+constexpr int kScalL2 = 3;   // squared residual 2-norms of the predictor (3) and corrector (4) solves
+constexpr int kScalDiv = 5;  // max |div u| after the step
 constexpr int kNumScal = 8;
 
 // One grid level.  n[2] = 1 and s[2] unused in 2-D.

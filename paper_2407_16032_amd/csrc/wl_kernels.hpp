@@ -28,33 +28,97 @@ constexpr int kTileTarget = 1024;  // tiles wanted per level (4 per compute unit
 static_assert(kPF >= 2, "pass B consumes two planes per step");
 
 // ---------------------------------------------------------------------------
-// body description and rigid motion (the paper's AutoBody, analytic subset)
+// bodies (the paper's AutoBody): up to kMaxParts parts, each a shape in its own
+// body frame seen through a map x_b = S * Rot(-theta) (x - P) + po, combined
+// by signed-distance arithmetic
 // ---------------------------------------------------------------------------
-struct BodyP {
-  int kind;  // 0 none, 1 sphere/circle, 2 box
-  double R;
-  double h[3];
-  double po[3];  // pivot offset
+constexpr int kMaxParts = 4;
+enum { kShapeNone = 0, kShapeSphere = 1, kShapeBox = 2, kShapeGrid = 3, kShapePlane = 4 };
+enum { kOpUnion = 0, kOpIntersect = 1, kOpSubtract = 2 };
+
+// signed distance sampled on a grid in the body frame, widened to FP64 in the
+// workspace: samples, their central-difference gradients (D arrays) and an
+// optional sampled velocity (D arrays or null), x fastest
+struct GridSdf {
+  const double* s;
+  const double* gr;
+  const double* v;
+  int n[3];
+  double o[3], h;
 };
-struct Motion {  // evaluated on the host at time t
-  double P[3];   // pivot position
-  double ct, st; // cos/sin of the rotation angle
-  double cdot[3];
-  double omega;
+struct PartP {
+  int kind, op;
+  double R;       // sphere radius, plane offset
+  double h[3];    // box half extents
+  double po[3];   // pivot offset
+  double nrm[3];  // plane normal (unit)
+  double shell;   // > 0: hollow part
+  GridSdf gs;
+};
+struct BodyP {
+  int nparts;   // 0: no body
+  int general;  // 0: one rigid part, evaluated by the direct formulas
+  PartP p[kMaxParts];
+};
+struct PartMotion {  // evaluated on the host at time t
+  double P[3];       // pivot position
+  double ct, st;     // cos/sin of the rotation angle
+  double cdot[3];    // velocity of the pivot
+  double omega;      // angular velocity about e_z
+  double S[3];       // map scale and its rate
+  double Sdot[3];
+};
+struct Motion {
+  PartMotion m[kMaxParts];
 };
 
-// signed distance, unit normal and rigid velocity at point x (FP64).
+// Cell of the sample grid holding body-frame point xb: lower sample index and
+// fractions along each axis; false outside the sampled box.
 template <int D>
-__device__ inline void body_eval(const BodyP& b, const Motion& m, const double x[3], double& d,
-                                 double n[3], double V[3]) {
+__device__ inline bool grid_cell(const GridSdf& G, const double xb[3], int i0[3], double fr[3]) {
 #pragma clang fp contract(off)
-  const double rx = x[0] - m.P[0], ry = x[1] - m.P[1], rz = (D == 3) ? x[2] - m.P[2] : 0.0;
-  double xb[3];
-  xb[0] = m.ct * rx + m.st * ry + b.po[0];
-  xb[1] = -m.st * rx + m.ct * ry + b.po[1];
-  xb[2] = (D == 3) ? rz + b.po[2] : 0.0;
-  double nb[3] = {0.0, 0.0, 0.0};
-  if (b.kind == 1) {
+#pragma unroll
+  for (int a = 0; a < D; ++a) {
+    const double u = (xb[a] - G.o[a]) / G.h;
+    if (!(u >= 0.0 && u <= double(G.n[a] - 1))) return false;
+    int i = (int)floor(u);
+    if (i > G.n[a] - 2) i = G.n[a] - 2;
+    i0[a] = i;
+    fr[a] = u - double(i);
+  }
+  return true;
+}
+
+// Multilinear interpolant of a sample array at the cell found by grid_cell
+// (corners in the order of their bit patterns, weights multiplied axis by axis).
+template <int D>
+__device__ inline double grid_interp(const GridSdf& G, const double* a, const int i0[3], const double fr[3]) {
+#pragma clang fp contract(off)
+  double out = 0.0;
+#pragma unroll
+  for (int c = 0; c < (1 << D); ++c) {
+    double w = 1.0;
+    int idx = 0, str = 1;
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+      const int bit = (c >> k) & 1;
+      w = w * (bit ? fr[k] : 1.0 - fr[k]);
+      idx += (i0[k] + bit) * str;
+      str *= G.n[k];
+    }
+    out = out + w * a[idx];
+  }
+  return out;
+}
+
+// Signed distance, unit gradient (body frame) and sampled velocity of a part's
+// shape at body-frame point xb (before hollowing).
+template <int D>
+__device__ inline void shape_eval(const PartP& b, const double xb[3], double& d, double nb[3], double Vs[3]) {
+#pragma clang fp contract(off)
+  nb[0] = nb[1] = nb[2] = 0.0;
+  Vs[0] = Vs[1] = Vs[2] = 0.0;
+  if (b.kind == kShapeSphere) {
     double r2 = xb[0] * xb[0] + xb[1] * xb[1];
     if (D == 3) r2 = r2 + xb[2] * xb[2];
     const double r = sqrt(r2);
@@ -64,7 +128,7 @@ __device__ inline void body_eval(const BodyP& b, const Motion& m, const double x
     } else {
       nb[0] = 1.0;
     }
-  } else {
+  } else if (b.kind == kShapeBox) {
     double q[3], o[3];
     for (int k = 0; k < D; ++k) {
       q[k] = fabs(xb[k]) - b.h[k];
@@ -84,13 +148,157 @@ __device__ inline void body_eval(const BodyP& b, const Motion& m, const double x
       const double sg = xb[k] >= 0.0 ? 1.0 : -1.0;
       nb[k] = (olen > 0.0) ? sg * o[k] / olen : (k == arg ? sg : 0.0);
     }
+  } else if (b.kind == kShapePlane) {
+    double s = b.nrm[0] * xb[0] + b.nrm[1] * xb[1];
+    if (D == 3) s = s + b.nrm[2] * xb[2];
+    d = s - b.R;
+    for (int k = 0; k < D; ++k) nb[k] = b.nrm[k];
+  } else {  // sampled
+    int i0[3] = {0, 0, 0};
+    double fr[3] = {0.0, 0.0, 0.0};
+    if (!grid_cell<D>(b.gs, xb, i0, fr)) {
+      d = 1e300;  // fluid, beyond the kernel's reach
+      nb[0] = 1.0;
+      return;
+    }
+    const int cnt = b.gs.n[0] * b.gs.n[1] * (D == 3 ? b.gs.n[2] : 1);
+    d = grid_interp<D>(b.gs, b.gs.s, i0, fr);
+    double gn[3] = {0.0, 0.0, 0.0};
+    for (int k = 0; k < D; ++k) gn[k] = grid_interp<D>(b.gs, b.gs.gr + (size_t)k * cnt, i0, fr);
+    double m2 = gn[0] * gn[0] + gn[1] * gn[1];
+    if (D == 3) m2 = m2 + gn[2] * gn[2];
+    const double mag = sqrt(m2);
+    if (mag > 0.0) {
+      for (int k = 0; k < D; ++k) nb[k] = gn[k] / mag;
+    } else {
+      nb[0] = 1.0;
+    }
+    if (b.gs.v)
+      for (int k = 0; k < D; ++k) Vs[k] = grid_interp<D>(b.gs, b.gs.v + (size_t)k * cnt, i0, fr);
   }
+}
+
+// One rigid part by the direct formulas: d = SDF(x_b), n = Rot(theta) n_b,
+// V = dP/dt + omega e_z x (x - P) (+ sampled velocity).
+template <int D>
+__device__ inline void part_rigid(const PartP& b, const PartMotion& m, const double x[3], double& d, double n[3],
+                                  double V[3]) {
+#pragma clang fp contract(off)
+  const double rx = x[0] - m.P[0], ry = x[1] - m.P[1], rz = (D == 3) ? x[2] - m.P[2] : 0.0;
+  double xb[3];
+  xb[0] = m.ct * rx + m.st * ry + b.po[0];
+  xb[1] = -m.st * rx + m.ct * ry + b.po[1];
+  xb[2] = (D == 3) ? rz + b.po[2] : 0.0;
+  double nb[3], Vs[3];
+  shape_eval<D>(b, xb, d, nb, Vs);
   n[0] = m.ct * nb[0] - m.st * nb[1];
   n[1] = m.st * nb[0] + m.ct * nb[1];
   n[2] = nb[2];
-  V[0] = m.cdot[0] - m.omega * ry;
-  V[1] = m.cdot[1] + m.omega * rx;
-  V[2] = m.cdot[2];
+  V[0] = m.cdot[0] - m.omega * ry + Vs[0];
+  V[1] = m.cdot[1] + m.omega * rx + Vs[1];
+  V[2] = m.cdot[2] + Vs[2];
+}
+
+// One part through its general map.  With J = dx_b/dx = diag(S) Rot(-theta) and
+// n_b the shape's unit gradient: g = J^T n_b = Rot(theta)(S n_b), n = g/|g|,
+// d = SDF/|g|; V = -J^{-1} dx_b/dt = dP/dt + omega e_z x r - Rot(theta)((S'/S) a)
+// with r = x - P and a = Rot(-theta) r.
+template <int D>
+__device__ inline void part_general(const PartP& b, const PartMotion& m, const double x[3], double& d, double n[3],
+                                    double V[3]) {
+#pragma clang fp contract(off)
+  const double r0 = x[0] - m.P[0], r1 = x[1] - m.P[1], r2 = (D == 3) ? x[2] - m.P[2] : 0.0;
+  const double a0 = m.ct * r0 + m.st * r1, a1 = -m.st * r0 + m.ct * r1, a2 = r2;
+  double xb[3];
+  xb[0] = m.S[0] * a0 + b.po[0];
+  xb[1] = m.S[1] * a1 + b.po[1];
+  xb[2] = (D == 3) ? m.S[2] * a2 + b.po[2] : 0.0;
+  double dt, nb[3], Vs[3];
+  shape_eval<D>(b, xb, dt, nb, Vs);
+  if (b.shell > 0.0) {
+    if (dt < 0.0)
+      for (int k = 0; k < 3; ++k) nb[k] = -nb[k];
+    dt = fabs(dt) - b.shell;
+  }
+  const double s0 = m.S[0] * nb[0], s1 = m.S[1] * nb[1], s2 = (D == 3) ? m.S[2] * nb[2] : 0.0;
+  const double g0 = m.ct * s0 - m.st * s1, g1 = m.st * s0 + m.ct * s1, g2 = s2;
+  double gm2 = g0 * g0 + g1 * g1;
+  if (D == 3) gm2 = gm2 + g2 * g2;
+  const double gm = sqrt(gm2);
+  if (gm > 0.0) {
+    d = dt / gm;
+    n[0] = g0 / gm;
+    n[1] = g1 / gm;
+    n[2] = g2 / gm;
+  } else {
+    d = dt;
+    n[0] = 1.0;
+    n[1] = n[2] = 0.0;
+  }
+  const double w0 = m.Sdot[0] / m.S[0] * a0, w1 = m.Sdot[1] / m.S[1] * a1,
+               w2 = (D == 3) ? m.Sdot[2] / m.S[2] * a2 : 0.0;
+  V[0] = m.cdot[0] - m.omega * r1 - (m.ct * w0 - m.st * w1) + Vs[0];
+  V[1] = m.cdot[1] + m.omega * r0 - (m.st * w0 + m.ct * w1) + Vs[1];
+  V[2] = (D == 3) ? m.cdot[2] - w2 + Vs[2] : 0.0;
+}
+
+// signed distance, unit normal and body velocity at point x (FP64).
+template <int D>
+__device__ inline void body_eval(const BodyP& b, const Motion& m, const double x[3], double& d, double n[3],
+                                 double V[3]) {
+  if (!b.general) {
+    part_rigid<D>(b.p[0], m.m[0], x, d, n, V);
+    return;
+  }
+  part_general<D>(b.p[0], m.m[0], x, d, n, V);
+  for (int k = 1; k < b.nparts; ++k) {
+    double db, nb[3], Vb[3];
+    part_general<D>(b.p[k], m.m[k], x, db, nb, Vb);
+    bool take;
+    if (b.p[k].op == kOpUnion) {
+      take = db < d;
+    } else if (b.p[k].op == kOpIntersect) {
+      take = db > d;
+    } else {
+      db = -db;
+      for (int j = 0; j < 3; ++j) nb[j] = -nb[j];
+      take = db > d;
+    }
+    if (take) {
+      d = db;
+      for (int j = 0; j < 3; ++j) {
+        n[j] = nb[j];
+        V[j] = Vb[j];
+      }
+    }
+  }
+}
+
+// Sample gradients of a gridded SDF by central differences (one-sided on the
+// grid's faces), FP64: gr[k][i] = (s[i + e_k] - s[i - e_k]) / (2h).
+template <int D>
+__global__ void __launch_bounds__(kBlock) k_grid_grad(const double* s, double* gr, int n0, int n1, int n2, double h) {
+#pragma clang fp contract(off)
+  const int n[3] = {n0, n1, D == 3 ? n2 : 1};
+  const int cnt = n[0] * n[1] * n[2];
+  const int str[3] = {1, n[0], n[0] * n[1]};
+  for (int lin = blockIdx.x * kBlock + threadIdx.x; lin < cnt; lin += gridDim.x * kBlock) {
+    const int I[3] = {lin % n[0], (lin / n[0]) % n[1], lin / (n[0] * n[1])};
+    for (int k = 0; k < D; ++k) {
+      double gk;
+      if (I[k] == 0) gk = (s[lin + str[k]] - s[lin]) / h;
+      else if (I[k] == n[k] - 1) gk = (s[lin] - s[lin - str[k]]) / h;
+      else gk = (s[lin + str[k]] - s[lin - str[k]]) / (2.0 * h);
+      gr[(size_t)k * cnt + lin] = gk;
+    }
+  }
+}
+
+// widen caller samples of the simulation's precision to FP64
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_widen(const T* src, double* dst, int64_t cnt) {
+  for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < cnt; i += (int64_t)gridDim.x * kBlock)
+    dst[i] = double(src[i]);
 }
 
 // Moments of the kernel; beyond its support (|s| >= 1) they are the full integrals,
@@ -224,7 +432,7 @@ __global__ void __launch_bounds__(kBlock) k_measure(Grid3 g, BodyP b, Motion m, 
     const int I[3] = {I0, I1, I2};
     const int idx = I0 + I1 * g.s[1] + I2 * g.s[2];
     double m0 = 1.0, m1 = 0.0, vb[3] = {0.0, 0.0, 0.0}, nn[3] = {0.0, 0.0, 0.0}, d = 1e300;
-    if (b.kind != 0) {
+    if (b.nparts != 0) {
       double x[3];
       for (int a = 0; a < 3; ++a) x[a] = (a == c) ? I[a] - 1.0 : I[a] - 0.5;
       body_eval<D>(b, m, x, d, nn, vb);
@@ -237,7 +445,7 @@ __global__ void __launch_bounds__(kBlock) k_measure(Grid3 g, BodyP b, Motion m, 
     }
     const bool bnd = !g.per[c] && (I[c] <= 1 || I[c] == g.n[c] + 1);
     mu0.c[c][idx] = bnd ? T(0) : T(m0);
-    if (b.kind != 0) {
+    if (b.nparts != 0) {
       for (int j = 0; j < D; ++j) mu1.c[c * D + j][idx] = T(m1 * nn[j]);
       V.c[c][idx] = (d < 2.0 + eps) ? T(vb[c]) : T(0);
     }
@@ -2502,21 +2710,54 @@ __global__ void __launch_bounds__(kBlock) k_project(Grid3 g, Vec3<T> u, Vec3<T> 
   }
 }
 
-// CFL: max over interior cells of sum_a max(0, u_a[I+e_a]) + max(0, -u_a[I]).
+// CFL: max over interior cells of sum_a max(0, u_a[I+e_a]) + max(0, -u_a[I]), and
+// the projection check max |div u| over the active cells (iD != 0), the
+// divergence summed in FP64.
 template <typename T, int D>
-__global__ void __launch_bounds__(kBlock) k_cfl(Grid3 g, Vec3<T> u, double* part) {
+__global__ void __launch_bounds__(kBlock) k_cfl(Grid3 g, Vec3<T> u, const T* iD, StdBox B, double* part,
+                                                double* part_div) {
+#pragma clang fp contract(off)
   const int total = g.n[0] * g.n[1] * ((D == 3) ? g.n[2] : 1);
-  double mx = 0.0;
+  double mx = 0.0, md = 0.0;
   for (int lin = blockIdx.x * kBlock + threadIdx.x; lin < total; lin += gridDim.x * kBlock) {
     int I[3], idx, op[3], om[3];
     cell_of<D>(g, lin, I, idx);
     nbr_offsets<D>(g, I, op, om);
     T s = T(0);
-    for (int a = 0; a < D; ++a) s = s + fmax(T(0), u.c[a][idx + op[a]]) + fmax(T(0), -u.c[a][idx]);
+    double dv = 0.0;
+    for (int a = 0; a < D; ++a) {
+      const T up = u.c[a][idx + op[a]], uc = u.c[a][idx];
+      s = s + fmax(T(0), up) + fmax(T(0), -uc);
+      dv = dv + (double(up) - double(uc));
+    }
     mx = fmax(mx, double(s));
+    const bool act = std_point<D>(B, g, I, 0) || iD[idx] != T(0);
+    if (act) md = fmax(md, fabs(dv));
   }
   mx = block_max(mx);
-  if (threadIdx.x == 0) part[blockIdx.x] = mx;
+  md = block_max(md);
+  if (threadIdx.x == 0) {
+    part[blockIdx.x] = mx;
+    part_div[blockIdx.x] = md;
+  }
+}
+
+// Sum of r^2 over the interior cells (FP64): blocks take whole rows, threads
+// stride along x.
+template <typename T, int D>
+__global__ void __launch_bounds__(kBlock) k_sumsq(Grid3 g, const T* r, double* part) {
+  const int rows = g.n[1] * ((D == 3) ? g.n[2] : 1);
+  double s = 0.0;
+  for (int row = blockIdx.x; row < rows; row += gridDim.x) {
+    const int j = 1 + row % g.n[1], k = (D == 3) ? 1 + row / g.n[1] : 0;
+    const T* rr = r + j * g.s[1] + k * g.s[2];
+    for (int i = 1 + threadIdx.x; i <= g.n[0]; i += kBlock) {
+      const double v = double(rr[i]);
+      s += v * v;
+    }
+  }
+  s = block_sum(s);
+  if (threadIdx.x == 0) part[blockIdx.x] = s;
 }
 
 // forces: F_p = -sum (p - pbar) n K_eps(d), F_v = sum 2 nu S n K_eps(d) at cell centres

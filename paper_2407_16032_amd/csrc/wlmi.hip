@@ -61,6 +61,8 @@ struct Plan {
   int ndim = 0, nlev = 0;
   size_t esize = 4;
   LevelPlan lev[kMaxLevels];
+  int64_t grid_cnt[kMaxParts] = {};  // samples of each gridded part (0: not gridded)
+  bool grid_vel[kMaxParts] = {};     // with a sampled velocity
   size_t bytes = 0;
 };
 
@@ -75,6 +77,8 @@ wl_status validate_and_default(const wl_sim_desc* in, wl_sim_desc* d) {
   if (!(d->nu >= 0.0) || !std::isfinite(d->nu)) return fail(WL_ERR_INVALID_ARG, "nu must be finite and >= 0");
   for (int a = 0; a < 3; ++a)
     if (!std::isfinite(d->U[a])) return fail(WL_ERR_INVALID_ARG, "U must be finite");
+  if (d->L == 0.0) d->L = 1.0;
+  if (!(d->L > 0.0) || !std::isfinite(d->L)) return fail(WL_ERR_INVALID_ARG, "L must be finite and > 0");
   if (d->eps == 0.0) d->eps = 1.0;
   if (d->dt0 == 0.0) d->dt0 = 0.25;
   if (d->dt_max == 0.0) d->dt_max = 10.0;
@@ -93,35 +97,197 @@ wl_status validate_and_default(const wl_sim_desc* in, wl_sim_desc* d) {
   return WL_OK;
 }
 
-wl_status validate_body(const wl_sim_desc& d, const wl_body_desc* b) {
+// ---------------------------------------------------------------------------
+// bodies: a chain of parts (see wl_body_desc)
+// ---------------------------------------------------------------------------
+int64_t grid_count(const wl_body_desc& b, int D) {
+  int64_t c = 1;
+  for (int a = 0; a < D; ++a) c *= b.grid_n[a];
+  return c;
+}
+
+// copies of the parts of a body (next cleared); an empty list for no body
+wl_status collect_parts(const wl_body_desc* b, std::vector<wl_body_desc>& out) {
+  out.clear();
   if (!b || b->kind == WL_BODY_NONE) return WL_OK;
-  if (b->kind != WL_BODY_SPHERE && b->kind != WL_BODY_BOX)
-    return fail(WL_ERR_UNSUPPORTED, "body kind not supported (sphere and box are)");
-  const double vals[] = {b->radius, b->heave_amp, b->pitch_amp, b->freq, b->phase_h, b->phase_p, b->spin_omega};
+  for (const wl_body_desc* q = b; q; q = q->next) {
+    if ((int)out.size() == kMaxParts) return fail(WL_ERR_INVALID_ARG, "a body has at most 4 parts");
+    out.push_back(*q);
+    out.back().next = nullptr;
+  }
+  return WL_OK;
+}
+
+bool part_needs_general(const wl_body_desc& p) {
+  return p.kind == WL_BODY_PLANE || p.shell != 0.0 || p.scale_amp[0] != 0.0 || p.scale_amp[1] != 0.0 ||
+         p.scale_amp[2] != 0.0;
+}
+bool part_moving(const wl_body_desc& p) {
+  return p.heave_amp != 0.0 || p.pitch_amp != 0.0 || p.spin_omega != 0.0 || p.velocity[0] != 0.0 ||
+         p.velocity[1] != 0.0 || p.velocity[2] != 0.0 ||
+         (p.freq != 0.0 && (p.scale_amp[0] != 0.0 || p.scale_amp[1] != 0.0 || p.scale_amp[2] != 0.0));
+}
+bool parts_general(const std::vector<wl_body_desc>& ps) {
+  if (ps.size() > 1) return true;
+  for (const auto& p : ps)
+    if (part_needs_general(p)) return true;
+  return false;
+}
+
+void heave_unit(const wl_body_desc& b, double e[3]) {
+  const double m = std::sqrt(b.heave_dir[0] * b.heave_dir[0] + b.heave_dir[1] * b.heave_dir[1] +
+                             b.heave_dir[2] * b.heave_dir[2]);
+  for (int k = 0; k < 3; ++k) e[k] = m == 0.0 ? (k == 1 ? 1.0 : 0.0) : b.heave_dir[k] / m;
+}
+
+// extreme scales of a part's map over its cycle
+double scale_min(const wl_body_desc& b) {
+  const double a = std::max(std::fabs(b.scale_amp[0]), std::max(std::fabs(b.scale_amp[1]), std::fabs(b.scale_amp[2])));
+  return 1.0 - a;
+}
+double scale_max(const wl_body_desc& b) {
+  const double a = std::max(std::fabs(b.scale_amp[0]), std::max(std::fabs(b.scale_amp[1]), std::fabs(b.scale_amp[2])));
+  return 1.0 + a;
+}
+
+// body-frame radius that holds the part's shape around the body-frame origin
+// (infinite for a plane)
+double shape_radius(const wl_body_desc& b, int D) {
+  double r = 0.0;
+  if (b.kind == WL_BODY_SPHERE) {
+    r = b.radius;
+  } else if (b.kind == WL_BODY_BOX) {
+    double s = 0;
+    for (int a = 0; a < D; ++a) s += b.half_extent[a] * b.half_extent[a];
+    r = std::sqrt(s);
+  } else if (b.kind == WL_BODY_GRID_SDF) {
+    double s = 0;
+    for (int a = 0; a < D; ++a) {
+      const double lo = b.grid_origin[a], hi = b.grid_origin[a] + (b.grid_n[a] - 1) * b.grid_h;
+      const double m = std::max(std::fabs(lo), std::fabs(hi));
+      s += m * m;
+    }
+    r = std::sqrt(s);
+  } else {
+    return INFINITY;
+  }
+  return r + std::max(0.0, b.shell);
+}
+
+// Pivot position of a part at time t (heave included unless `heave` is false).
+void part_pivot(const wl_body_desc& b, double t, double P[3], bool heave = true) {
+  const double w = 2.0 * M_PI * b.freq;
+  double eh[3];
+  heave_unit(b, eh);
+  const double hv = heave ? b.heave_amp * std::sin(w * t + b.phase_h) : 0.0;
+  for (int k = 0; k < 3; ++k) P[k] = b.center[k] + b.velocity[k] * t + hv * eh[k] + b.pivot_offset[k];
+}
+
+// World interval per axis that holds every point of the body where measure can
+// set a coefficient (d < 2 + eps), plus `margin` cells, at time t: per part a
+// ball around its pivot (the heave's whole excursion when `cycle`), combined
+// as the parts combine.  lo > hi on an axis: empty; +-inf: unbounded.
+void body_extent(const std::vector<wl_body_desc>& ps, int D, double eps, double t, bool cycle, double margin,
+                 double lo[3], double hi[3]) {
+  for (size_t k = 0; k < ps.size(); ++k) {
+    const wl_body_desc& b = ps[k];
+    double plo[3], phi[3];
+    const double rb = shape_radius(b, D);
+    double po = 0;
+    for (int a = 0; a < D; ++a) po += b.pivot_offset[a] * b.pivot_offset[a];
+    const double reach = (rb + std::sqrt(po) + (2.0 + eps) * scale_max(b)) / scale_min(b) + margin;
+    double P[3];
+    part_pivot(b, t, P, !cycle);
+    double eh[3];
+    heave_unit(b, eh);
+    for (int a = 0; a < 3; ++a) {
+      // over a whole cycle the heave moves the pivot by up to its amplitude either way
+      const double ex = cycle ? std::fabs(b.heave_amp * eh[a]) : 0.0;
+      plo[a] = std::isinf(reach) ? -INFINITY : P[a] - reach - ex;
+      phi[a] = std::isinf(reach) ? INFINITY : P[a] + reach + ex;
+    }
+    for (int a = 0; a < 3; ++a) {
+      if (k == 0 || b.op == WL_OP_UNION) {
+        lo[a] = k == 0 ? plo[a] : std::min(lo[a], plo[a]);
+        hi[a] = k == 0 ? phi[a] : std::max(hi[a], phi[a]);
+      } else if (b.op == WL_OP_INTERSECT) {
+        lo[a] = std::max(lo[a], plo[a]);
+        hi[a] = std::min(hi[a], phi[a]);
+      }  // subtract: the body stays inside the parts before it
+    }
+  }
+}
+
+wl_status validate_part(const wl_sim_desc& d, const wl_body_desc& b, bool first) {
+  if (b.kind < WL_BODY_SPHERE || b.kind > WL_BODY_PLANE)
+    return fail(WL_ERR_UNSUPPORTED, "body kind not supported (sphere, box, gridded SDF and plane are)");
+  const double vals[] = {b.radius, b.heave_amp, b.pitch_amp, b.freq, b.phase_h, b.phase_p, b.spin_omega, b.phase_s,
+                         b.shell, b.grid_h};
   for (double v : vals)
     if (!std::isfinite(v)) return fail(WL_ERR_INVALID_ARG, "body parameters must be finite");
-  if (b->kind == WL_BODY_SPHERE && !(b->radius > 0.0)) return fail(WL_ERR_INVALID_ARG, "sphere radius must be > 0");
-  if (b->kind == WL_BODY_BOX)
+  for (int k = 0; k < 3; ++k)
+    if (!std::isfinite(b.center[k]) || !std::isfinite(b.half_extent[k]) || !std::isfinite(b.pivot_offset[k]) ||
+        !std::isfinite(b.velocity[k]) || !std::isfinite(b.heave_dir[k]) || !std::isfinite(b.scale_amp[k]) ||
+        !std::isfinite(b.normal[k]) || !std::isfinite(b.grid_origin[k]))
+      return fail(WL_ERR_INVALID_ARG, "body parameters must be finite");
+  if (!first && (b.op < WL_OP_UNION || b.op > WL_OP_SUBTRACT))
+    return fail(WL_ERR_INVALID_ARG, "op must be WL_OP_UNION, WL_OP_INTERSECT or WL_OP_SUBTRACT");
+  if (b.kind == WL_BODY_SPHERE && !(b.radius > 0.0)) return fail(WL_ERR_INVALID_ARG, "sphere radius must be > 0");
+  if (b.kind == WL_BODY_BOX)
     for (int a = 0; a < d.ndim; ++a)
-      if (!(b->half_extent[a] > 0.0)) return fail(WL_ERR_INVALID_ARG, "box half extents must be > 0");
-  // reach of the body (bounding radius + rigid heave) must stay 3 cells inside non-periodic faces
-  double reach = (b->kind == WL_BODY_SPHERE) ? b->radius : 0.0;
-  if (b->kind == WL_BODY_BOX) {
-    double s = 0;
-    for (int a = 0; a < d.ndim; ++a) s += b->half_extent[a] * b->half_extent[a];
-    reach = std::sqrt(s);
+      if (!(b.half_extent[a] > 0.0)) return fail(WL_ERR_INVALID_ARG, "box half extents must be > 0");
+  if (b.kind == WL_BODY_PLANE) {
+    double m = 0;
+    for (int a = 0; a < d.ndim; ++a) m += b.normal[a] * b.normal[a];
+    if (!(m > 0.0)) return fail(WL_ERR_INVALID_ARG, "plane normal must be nonzero");
   }
-  double po = 0;
-  for (int a = 0; a < d.ndim; ++a) po += b->pivot_offset[a] * b->pivot_offset[a];
-  reach += std::sqrt(po) + d.eps + 2.0;
+  if (b.kind == WL_BODY_GRID_SDF) {
+    if (!b.sdf_grid) return fail(WL_ERR_INVALID_ARG, "gridded SDF needs sdf_grid");
+    if (!(b.grid_h > 0.0)) return fail(WL_ERR_INVALID_ARG, "grid_h must be > 0");
+    for (int a = 0; a < d.ndim; ++a)
+      if (b.grid_n[a] < 2 || b.grid_n[a] > 4096) return fail(WL_ERR_INVALID_ARG, "grid_n[a] must be in [2, 4096]");
+    if (grid_count(b, d.ndim) > (int64_t(1) << 26)) return fail(WL_ERR_INVALID_ARG, "sdf_grid has more than 2^26 samples");
+  } else if (b.vel_grid) {
+    return fail(WL_ERR_INVALID_ARG, "vel_grid needs a gridded SDF part");
+  }
+  if (b.shell < 0.0) return fail(WL_ERR_INVALID_ARG, "shell must be >= 0");
+  for (int a = 0; a < 3; ++a)
+    if (!(std::fabs(b.scale_amp[a]) < 0.9)) return fail(WL_ERR_INVALID_ARG, "|scale_amp| must be < 0.9");
+  return WL_OK;
+}
+
+// the body's reach (every point where measure can set a coefficient) must stay at
+// least 3 cells inside the non-periodic domain faces at time t
+wl_status check_reach(const wl_sim_desc& d, const std::vector<wl_body_desc>& ps, double t, bool cycle) {
+  if (ps.empty()) return WL_OK;
+  double lo[3], hi[3];
+  body_extent(ps, d.ndim, d.eps, t, cycle, 0.0, lo, hi);
   for (int a = 0; a < d.ndim; ++a) {
     if (d.periodic_mask & (1u << a)) continue;
-    const double lo = b->center[a] - reach - (a == 1 ? std::fabs(b->heave_amp) : 0.0);
-    const double hi = b->center[a] + reach + (a == 1 ? std::fabs(b->heave_amp) : 0.0);
-    if (lo < 3.0 || hi > double(d.n[a]) - 3.0)
+    if (lo[a] > hi[a]) continue;  // empty body
+    if (std::isinf(lo[a]) || std::isinf(hi[a]))
+      return fail(WL_ERR_INVALID_ARG, "the body is unbounded (a plane must be subtracted or intersected)");
+    if (lo[a] < 3.0 || hi[a] > double(d.n[a]) - 3.0)
       return fail(WL_ERR_INVALID_ARG, "body must stay at least 3 cells from non-periodic boundaries");
   }
   return WL_OK;
+}
+
+wl_status validate_body(const wl_sim_desc& d, const wl_body_desc* b) {
+  std::vector<wl_body_desc> ps;
+  wl_status s = collect_parts(b, ps);
+  if (s != WL_OK) return s;
+  for (size_t k = 0; k < ps.size(); ++k)
+    if ((s = validate_part(d, ps[k], k == 0)) != WL_OK) return s;
+  return check_reach(d, ps, 0.0, true);
+}
+
+// FP64 doubles of the workspace that hold a body's sampled parts
+int64_t body_grid_doubles(const std::vector<wl_body_desc>& ps, int D) {
+  int64_t n = 0;
+  for (const auto& p : ps)
+    if (p.kind == WL_BODY_GRID_SDF) n += grid_count(p, D) * (1 + D + (p.vel_grid ? D : 0));
+  return n;
 }
 
 // learned-guess buffer sizes: the whole padded grid (inference) and one crop box
@@ -171,7 +337,7 @@ int64_t flat_blocks_max(const wl_sim_desc& d, const Plan& P) {
   return m;
 }
 
-Plan make_plan(const wl_sim_desc& d, bool has_body) {
+Plan make_plan(const wl_sim_desc& d, const std::vector<wl_body_desc>& parts) {
   Plan P;
   P.ndim = d.ndim;
   P.esize = d.prec == WL_F64 ? 8 : 4;
@@ -198,7 +364,6 @@ Plan make_plan(const wl_sim_desc& d, bool has_body) {
   size_t b = 0;
   const size_t f0 = align256(P.lev[0].alloc * P.esize);
   int nf0 = D /*ua*/ + D /*ub*/ + D /*ft*/ + D /*V*/ + D /*mu0*/ + D * D /*mu1*/ + 1 /*p*/ + 6 /*x r ea eb q iD*/;
-  (void)has_body;
   b += nf0 * f0;
   b += align256((size_t)P.lev[0].py * P.lev[0].pz * P.esize);  // exit plane
   for (int l = 1; l < P.nlev; ++l) b += (6 + D) * align256(P.lev[l].alloc * P.esize);
@@ -221,22 +386,39 @@ Plan make_plan(const wl_sim_desc& d, bool has_body) {
     b += align256((size_t)kPgWaves * (27 * 256 + 16) * sizeof(float));
     b += align256(8192 * sizeof(double)) + align256(8 * sizeof(double));
   }
+  // sampled parts of the body (FP64): samples, their gradients, the sampled velocity
+  for (size_t k = 0; k < parts.size(); ++k)
+    if (parts[k].kind == WL_BODY_GRID_SDF) {
+      P.grid_cnt[k] = grid_count(parts[k], D);
+      P.grid_vel[k] = parts[k].vel_grid != nullptr;
+      b += align256(P.grid_cnt[k] * sizeof(double)) + (size_t)D * align256(P.grid_cnt[k] * sizeof(double));
+      if (P.grid_vel[k]) b += (size_t)D * align256(P.grid_cnt[k] * sizeof(double));
+    }
   P.bytes = b;
   return P;
 }
 
-void host_motion(const wl_body_desc& b, double t, Motion& m) {
+// Map of one part at time t (see wl_body_desc).
+void part_motion(const wl_body_desc& b, double t, PartMotion& m) {
   const double w = 2.0 * M_PI * b.freq;
-  double c[3] = {b.center[0], b.center[1], b.center[2]};
-  c[1] += b.heave_amp * std::sin(w * t + b.phase_h);
-  for (int k = 0; k < 3; ++k) m.P[k] = c[k] + b.pivot_offset[k];
+  double eh[3];
+  heave_unit(b, eh);
+  part_pivot(b, t, m.P);
+  const double hd = b.heave_amp * w * std::cos(w * t + b.phase_h);
+  for (int k = 0; k < 3; ++k) m.cdot[k] = b.velocity[k] + hd * eh[k];
   const double theta = b.pitch_amp * std::sin(w * t + b.phase_p) + b.spin_omega * t;
   m.ct = std::cos(theta);
   m.st = std::sin(theta);
-  m.cdot[0] = 0.0;
-  m.cdot[1] = b.heave_amp * w * std::cos(w * t + b.phase_h);
-  m.cdot[2] = 0.0;
   m.omega = b.pitch_amp * w * std::cos(w * t + b.phase_p) + b.spin_omega;
+  for (int k = 0; k < 3; ++k) {
+    m.S[k] = 1.0 + b.scale_amp[k] * std::sin(w * t + b.phase_s);
+    m.Sdot[k] = b.scale_amp[k] * w * std::cos(w * t + b.phase_s);
+  }
+}
+
+void host_motion(const std::vector<wl_body_desc>& ps, double t, Motion& m) {
+  m = Motion{};
+  for (size_t k = 0; k < ps.size(); ++k) part_motion(ps[k], t, m.m[k]);
 }
 
 // ---------------------------------------------------------------------------
@@ -353,7 +535,7 @@ struct SimBase {
   }
   Profiler prof;
   wl_sim_desc desc;
-  wl_body_desc bdesc;
+  std::vector<wl_body_desc> parts;  // the body's parts (next cleared); empty: no body
   Plan plan;
   hipStream_t stream = nullptr;
   double t = 0.0, dt = 0.25;
@@ -417,6 +599,8 @@ struct Impl : SimBase {
   int acur = 0;
   T *aup[3] = {}, *afb[3] = {}, *aVb[3] = {}, *am0b[3] = {}, *am1b[9] = {}, *recB[3] = {}, *recF[3] = {};
   T *recX1 = nullptr, *recX2 = nullptr, *apb = nullptr, *arhs = nullptr;
+  // FP64 copies of the sampled parts: samples, gradients (D arrays), velocity (D arrays)
+  double *gsd[kMaxParts] = {}, *ggr[kMaxParts] = {}, *gvl[kMaxParts] = {};
   double adj_dR = 0.0;  // direct radius derivative of the force functionals so far
 
   Vec3<T> v3(T* const a[3]) const {
@@ -540,6 +724,14 @@ struct Impl : SimBase {
       }
       pgPc = S.Pc;
     }
+    for (int k = 0; k < kMaxParts; ++k) {
+      gsd[k] = ggr[k] = gvl[k] = nullptr;
+      if (plan.grid_cnt[k] == 0) continue;
+      const size_t gb = plan.grid_cnt[k] * sizeof(double);
+      gsd[k] = (double*)take(gb);
+      ggr[k] = (double*)take(D * align256(gb));
+      if (plan.grid_vel[k]) gvl[k] = (double*)take(D * align256(gb));
+    }
     return off;
   }
 
@@ -569,6 +761,12 @@ struct Impl : SimBase {
       for (int k = 0; k < kPgRing; ++k) ok = ok && in(ringX[k]) && in(ringT[k]) && in(ringM[k]);
       // the last byte of the last buffer must be inside the workspace too
       ok = ok && (const char*)(pgScal + 8) <= base + bytes;
+    }
+    for (int k = 0; k < kMaxParts; ++k) {
+      const int64_t c = plan.grid_cnt[k];
+      if (c == 0) continue;
+      ok = ok && in(gsd[k]) && in(ggr[k]) && (const char*)(ggr[k] + D * c) <= base + bytes;
+      if (plan.grid_vel[k]) ok = ok && in(gvl[k]) && (const char*)(gvl[k] + D * c) <= base + bytes;
     }
     return ok;
   }
@@ -621,16 +819,66 @@ struct Impl : SimBase {
     lbot = bottom_level();
   }
 
-  wl_status init() override {
-    has_body = bdesc.kind != WL_BODY_NONE;
-    body.kind = bdesc.kind;
-    body.R = bdesc.radius;
-    for (int k = 0; k < 3; ++k) {
-      body.h[k] = bdesc.half_extent[k];
-      body.po[k] = bdesc.pivot_offset[k];
+  // Device description of the body from its parts; the sampled parts point at
+  // their FP64 copies in the workspace.
+  void build_body() {
+    body = BodyP{};
+    has_body = !parts.empty();
+    body.nparts = (int)parts.size();
+    body.general = parts_general(parts) ? 1 : 0;
+    moving = false;
+    for (size_t k = 0; k < parts.size(); ++k) {
+      const wl_body_desc& b = parts[k];
+      PartP& q = body.p[k];
+      q.kind = b.kind;
+      q.op = k == 0 ? kOpUnion : b.op;
+      q.R = b.radius;
+      q.shell = b.shell;
+      double nm = 0;
+      for (int a = 0; a < D; ++a) nm += b.normal[a] * b.normal[a];
+      nm = std::sqrt(nm);
+      for (int a = 0; a < 3; ++a) {
+        q.h[a] = b.half_extent[a];
+        q.po[a] = b.pivot_offset[a];
+        q.nrm[a] = (a < D && nm > 0.0) ? b.normal[a] / nm : 0.0;
+      }
+      if (b.kind == WL_BODY_GRID_SDF) {
+        q.gs.s = gsd[k];
+        q.gs.gr = ggr[k];
+        q.gs.v = plan.grid_vel[k] ? gvl[k] : nullptr;
+        for (int a = 0; a < 3; ++a) {
+          q.gs.n[a] = a < D ? (int)b.grid_n[a] : 1;
+          q.gs.o[a] = a < D ? b.grid_origin[a] : 0.0;
+        }
+        q.gs.h = b.grid_h;
+      }
+      moving = moving || part_moving(b);
     }
-    moving = has_body && (bdesc.heave_amp != 0.0 || bdesc.pitch_amp != 0.0 || bdesc.spin_omega != 0.0);
+  }
+
+  // FP64 copies of the sampled parts and their gradients (read from the caller's arrays)
+  wl_status upload_grids() {
+    for (size_t k = 0; k < parts.size(); ++k) {
+      const wl_body_desc& b = parts[k];
+      if (b.kind != WL_BODY_GRID_SDF) continue;
+      const int64_t cnt = plan.grid_cnt[k];
+      k_widen<T><<<blocks_for(cnt), kBlock, 0, stream>>>((const T*)b.sdf_grid, gsd[k], cnt);
+      k_grid_grad<D><<<blocks_for(cnt), kBlock, 0, stream>>>(gsd[k], ggr[k], (int)b.grid_n[0], (int)b.grid_n[1],
+                                                              D == 3 ? (int)b.grid_n[2] : 1, b.grid_h);
+      if (plan.grid_vel[k])
+        k_widen<T><<<blocks_for(D * cnt), kBlock, 0, stream>>>((const T*)b.vel_grid, gvl[k], D * cnt);
+    }
+    WL_HIP(hipGetLastError());
+    return WL_OK;
+  }
+
+  wl_status init() override {
+    build_body();
     setup_grids();
+    {
+      wl_status s0 = upload_grids();
+      if (s0 != WL_OK) return s0;
+    }
     for (int c = 0; c < D; ++c) {
       k_fill<T><<<blocks_for(plan.lev[0].elems), kBlock, 0, stream>>>(u[cur][c], plan.lev[0].elems, T(desc.U[c]));
       k_fill<T><<<blocks_for(plan.lev[0].elems), kBlock, 0, stream>>>(u[1 - cur][c], plan.lev[0].elems, T(desc.U[c]));
@@ -694,28 +942,26 @@ struct Impl : SimBase {
   }
 
   // Index box (padded coordinates) outside of which measure leaves mu0 = 1 (0 on
-  // boundary faces), mu1 = 0, V = 0 at time tm: every body point lies within
-  // |shape| + |pivot offset| of the pivot, and nothing is set beyond d = 2 + eps.
+  // boundary faces), mu1 = 0, V = 0 at time tm: the body's extent (every point
+  // where d < 2 + eps can hold) with a 3-cell margin.  Empty: lo = 1, hi = 0.
   void body_box(double tm, int lo[3], int hi[3]) const {
-    Motion m{};
-    host_motion(bdesc, tm, m);
-    double shape = body.R;
-    if (bdesc.kind == WL_BODY_BOX) {
-      double s2 = 0;
-      for (int a = 0; a < D; ++a) s2 += body.h[a] * body.h[a];
-      shape = std::sqrt(s2);
-    }
-    double po2 = 0;
-    for (int a = 0; a < D; ++a) po2 += body.po[a] * body.po[a];
-    const double reach = shape + std::sqrt(po2) + 2.0 + desc.eps + 3.0;  // 3-cell margin
+    double wlo[3], whi[3];
+    body_extent(parts, D, desc.eps, tm, false, 3.0, wlo, whi);
+    bool empty = false;
     for (int a = 0; a < 3; ++a) {
       if (a >= D) {
         lo[a] = hi[a] = 0;
         continue;
       }
-      lo[a] = std::max(0, (int)std::floor(m.P[a] - reach));
-      hi[a] = std::min(g[0].n[a] + 1, (int)std::ceil(m.P[a] + reach) + 2);
+      lo[a] = std::isinf(wlo[a]) ? 0 : (int)std::max(0.0, std::floor(wlo[a]));
+      hi[a] = std::isinf(whi[a]) ? g[0].n[a] + 1 : (int)std::min(double(g[0].n[a] + 1), std::ceil(whi[a]) + 2.0);
+      if (wlo[a] > whi[a] || lo[a] > hi[a]) empty = true;
     }
+    if (empty)
+      for (int a = 0; a < 3; ++a) {
+        lo[a] = 1;
+        hi[a] = 0;
+      }
   }
 
   // Body boxes of every level from the fine one (box_lo/hi, or empty without a body).
@@ -750,9 +996,10 @@ struct Impl : SimBase {
 
   wl_status measure_box(double tm, const int lo[3], const int hi[3]) {
     Motion m{};
-    if (has_body) host_motion(bdesc, tm, m);
+    if (has_body) host_motion(parts, tm, m);
     int64_t vol = 1;
-    for (int a = 0; a < D; ++a) vol *= hi[a] - lo[a] + 1;
+    for (int a = 0; a < D; ++a) vol *= std::max(0, hi[a] - lo[a] + 1);
+    if (vol == 0) return WL_OK;
     const int3 l3 = make_int3(lo[0], lo[1], lo[2]), h3 = make_int3(hi[0], hi[1], hi[2]);
     WL_TIMED(WL_K_MEASURE, (k_measure<T, D><<<dim3(blocks_for(vol), D), kBlock, 0, stream>>>(
                                g[0], body, m, desc.eps, v3(mu0), v9(mu1), v3(V), l3, h3)));
@@ -775,15 +1022,19 @@ struct Impl : SimBase {
   // per-step re-measure of a moving body: only the union of the previous and the
   // current body boxes can change
   wl_status remeasure_moving(double tm) {
+    // a translating body must not reach the non-periodic faces
+    wl_status s = check_reach(desc, parts, tm, false);
+    if (s != WL_OK) return s;
     if (!have_box) return measure(tm);
     int lo[3], hi[3];
     body_box(tm, lo, hi);
     int ul[3], uh[3];
+    const bool new_empty = lo[0] > hi[0], old_empty = box_lo[0] > box_hi[0];
     for (int a = 0; a < 3; ++a) {
-      ul[a] = std::min(lo[a], box_lo[a]);
-      uh[a] = std::max(hi[a], box_hi[a]);
+      ul[a] = new_empty ? box_lo[a] : (old_empty ? lo[a] : std::min(lo[a], box_lo[a]));
+      uh[a] = new_empty ? box_hi[a] : (old_empty ? hi[a] : std::max(hi[a], box_hi[a]));
     }
-    wl_status s = measure_box(tm, ul, uh);
+    s = measure_box(tm, ul, uh);
     for (int a = 0; a < 3; ++a) {
       box_lo[a] = lo[a];
       box_hi[a] = hi[a];
@@ -1119,8 +1370,18 @@ struct Impl : SimBase {
     }
   }
 
-  // initial residual already in r[0] / rmax slot
-  wl_status mg_loop(double tol, int itmax, wl_solve_stats* st) {
+  // squared 2-norm of the fine residual (FP64 sum over the interior) into scal[kScalL2 + which]
+  void res_sumsq(int which) {
+    const int rows = g[0].n[1] * (D == 3 ? g[0].n[2] : 1);
+    const int gb = std::min(rows, kGridStride);
+    WL_TIMED(WL_K_REDUCE, (k_sumsq<T, D><<<gb, kBlock, 0, stream>>>(g[0], r[0], slot(kSlotL2))));
+    WL_TIMED(WL_K_REDUCE, (k_finalize2<<<1, kFinalizeThreads, 0, stream>>>(slot(kSlotL2), 0, nullptr, 0, gb,
+                                                                           scal + kScalL2 + which, nullptr)));
+  }
+
+  // initial residual already in r[0] / rmax slot.  l2_which 0/1: the residual's
+  // 2-norm is left in scal for the step to read with its other scalars; -1: read now.
+  wl_status mg_loop(double tol, int itmax, wl_solve_stats* st, int l2_which = -1) {
     double res0;
     wl_status s = read_scalar_max(kSlotRmax, &res0);
     if (s != WL_OK) return s;
@@ -1139,10 +1400,20 @@ struct Impl : SimBase {
       if (!std::isfinite(res)) return fail(WL_ERR_NONFINITE, "multigrid residual is not finite");
     }
     if (!std::isfinite(res0)) return fail(WL_ERR_NONFINITE, "initial residual is not finite");
+    res_sumsq(l2_which < 0 ? 0 : l2_which);
+    WL_HIP(hipGetLastError());
+    double l2 = NAN;
+    if (l2_which < 0) {
+      WL_HIP(hipMemcpyAsync(host_pin, scal + kScalL2, sizeof(double), hipMemcpyDeviceToHost, stream));
+      WL_HIP(hipStreamSynchronize(stream));
+      prof.harvest();
+      l2 = std::sqrt(host_pin[0]);
+    }
     if (st) {
       st->vcycles = n;
       st->res0_linf = res0;
       st->res_linf = res;
+      st->res_l2 = l2;
       st->converged = res < tol ? 1 : 0;
     }
     return WL_OK;
@@ -1184,7 +1455,7 @@ struct Impl : SimBase {
     }
   }
 
-  wl_status project(T* const uu[3], double w, wl_solve_stats* st) {
+  wl_status project(T* const uu[3], double w, wl_solve_stats* st, int l2_which = -1) {
     const T wdt = T(w * dt);
     const bool guided = pg_on && pg_mode >= 1 && pg_hist >= 2;
     if (guided) {
@@ -1207,7 +1478,7 @@ struct Impl : SimBase {
       div_res(uu, nullptr, p, wdt);
     }
     WL_HIP(hipGetLastError());
-    wl_status s = mg_loop(desc.mg_tol, desc.mg_itmax, st);
+    wl_status s = mg_loop(desc.mg_tol, desc.mg_itmax, st, l2_which);
     if (s != WL_OK) return s;
     if (guided && pg_mode == 2) pg_snapshot(w * dt);
     if (pg_on) WL_HIP(hipMemcpyAsync(p2, p, plan.lev[0].elems * sizeof(T), hipMemcpyDeviceToDevice, stream));
@@ -1491,7 +1762,7 @@ struct Impl : SimBase {
     WL_HIP(hipGetLastError());
     if ((s = bc(B, ex)) != WL_OK) return s;
     wl_solve_stats s1{}, s2{};
-    if ((s = project(B, 1.0, &s1)) != WL_OK) return s;
+    if ((s = project(B, 1.0, &s1, 0)) != WL_OK) return s;
     if ((s = bc(B, ex)) != WL_OK) return s;
     if (rec) {  // intermediates the adjoint of this step reads
       for (int k = 0; k < D; ++k) {
@@ -1510,18 +1781,27 @@ struct Impl : SimBase {
                                                                                    v9(mu1), v3(B), hb, sbox[0])));
     WL_HIP(hipGetLastError());
     if ((s = bc(B, ex)) != WL_OK) return s;
-    if ((s = project(B, 0.5, &s2)) != WL_OK) return s;
+    if ((s = project(B, 0.5, &s2, 1)) != WL_OK) return s;
     if (rec) WL_HIP(copy_field(recX2, x[0]));
     if ((s = bc(B, ex)) != WL_OK) return s;
     cur = 1 - cur;
     const double dt_used = dt;
     t += dt;
     // CFL
-    WL_TIMED(WL_K_CFL, (k_cfl<T, D><<<nb[0], kBlock, 0, stream>>>(g[0], v3(u[cur]), slot(kSlotCfl))));
-    slot_n[kSlotCfl] = nb[0];
+    WL_TIMED(WL_K_CFL, (k_cfl<T, D><<<nb[0], kBlock, 0, stream>>>(g[0], v3(u[cur]), iD[0], sbox[0], slot(kSlotCfl),
+                                                                    slot(kSlotDiv))));
+    WL_TIMED(WL_K_REDUCE, (k_finalize2<<<1, kFinalizeThreads, 0, stream>>>(slot(kSlotCfl), 1, slot(kSlotDiv), 1, nb[0],
+                                                                           scal + kScalCfl, scal + kScalDiv)));
     WL_HIP(hipGetLastError());
-    double smax;
-    if ((s = read_scalar_max(kSlotCfl, &smax)) != WL_OK) return s;
+    // one read-back for the step's scalars: the outflux maximum, both residual 2-norms
+    // and the divergence check
+    WL_HIP(hipMemcpyAsync(host_pin, scal, kNumScal * sizeof(double), hipMemcpyDeviceToHost, stream));
+    WL_HIP(hipStreamSynchronize(stream));
+    prof.harvest();
+    const double smax = host_pin[kScalCfl];
+    s1.res_l2 = std::sqrt(host_pin[kScalL2]);
+    s2.res_l2 = std::sqrt(host_pin[kScalL2 + 1]);
+    const double div_linf = host_pin[kScalDiv];
     const double denom = smax + desc.cfl_nu_coef * desc.nu;
     dt = denom <= 0.0 ? desc.dt_max : std::min(desc.dt_max, 1.0 / denom);
     if (st) {
@@ -1532,6 +1812,9 @@ struct Impl : SimBase {
       st->vcycles[1] = s2.vcycles;
       st->res_linf[0] = s1.res_linf;
       st->res_linf[1] = s2.res_linf;
+      st->res_l2[0] = s1.res_l2;
+      st->res_l2[1] = s2.res_l2;
+      st->div_linf = div_linf;
       st->converged = s1.converged && s2.converged;
     }
     if (!std::isfinite(smax) || !std::isfinite(dt)) return fail(WL_ERR_NONFINITE, "velocity is not finite");
@@ -1541,7 +1824,7 @@ struct Impl : SimBase {
   // the 11 force sums of the current state (k_forces partials, totalled in block order)
   wl_status force_sums(double tot[11]) {
     Motion m{};
-    host_motion(bdesc, t, m);
+    host_motion(parts, t, m);
     WL_TIMED(WL_K_FORCES, (k_forces<T, D><<<nb[0], kBlock, 0, stream>>>(g[0], body, m, desc.eps, desc.nu,
                                                                          v3(u[cur]), p, iD[0], red)));
     WL_HIP(hipGetLastError());
@@ -1584,27 +1867,39 @@ struct Impl : SimBase {
   // ---- body update and discrete adjoint -----------------------------------------
   wl_status body_update(const wl_body_desc* b) override {
     if (!b) return fail(WL_ERR_INVALID_ARG, "body is NULL");
-    if (b->kind != bdesc.kind) return fail(WL_ERR_INVALID_ARG, "the body kind cannot change");
-    wl_status s = validate_body(desc, b);
+    std::vector<wl_body_desc> np;
+    wl_status s = collect_parts(b, np);
     if (s != WL_OK) return s;
-    if (b->kind == WL_BODY_NONE) return WL_OK;
-    bdesc = *b;
-    body.R = bdesc.radius;
-    for (int k = 0; k < 3; ++k) {
-      body.h[k] = bdesc.half_extent[k];
-      body.po[k] = bdesc.pivot_offset[k];
+    // the workspace was planned for these parts: same count, kinds and sample grids
+    bool same = np.size() == parts.size();
+    for (size_t k = 0; same && k < np.size(); ++k) {
+      same = np[k].kind == parts[k].kind && (np[k].vel_grid != nullptr) == plan.grid_vel[k];
+      if (same && np[k].kind == WL_BODY_GRID_SDF)
+        for (int a = 0; a < D; ++a) same = same && np[k].grid_n[a] == parts[k].grid_n[a];
     }
-    moving = bdesc.heave_amp != 0.0 || bdesc.pitch_amp != 0.0 || bdesc.spin_omega != 0.0;
+    if (!same) return fail(WL_ERR_INVALID_ARG, "the body's parts, kinds and sample grids cannot change");
+    if ((s = validate_body(desc, b)) != WL_OK) return s;
+    if (np.empty()) return WL_OK;
+    parts = np;
+    build_body();
+    if ((s = upload_grids()) != WL_OK) return s;
     have_box = false;
     return measure(t);
   }
 
+  // the adjoint needs a body whose shape does not move: every part static, except
+  // spheres/circles that only spin about their centre
   wl_status adj_require() {
     if (!adj_on) return fail(WL_ERR_UNSUPPORTED, "the simulation has no adjoint buffers (desc.adjoint = 0)");
     if (desc.convective_exit) return fail(WL_ERR_UNSUPPORTED, "the adjoint does not cover the convective exit");
-    if (has_body && (bdesc.heave_amp != 0.0 || bdesc.pitch_amp != 0.0 ||
-                     (bdesc.kind != WL_BODY_SPHERE && bdesc.spin_omega != 0.0)))
-      return fail(WL_ERR_UNSUPPORTED, "the adjoint needs a body whose shape does not move (spinning spheres are allowed)");
+    for (const auto& p : parts) {
+      wl_body_desc q = p;
+      if (q.kind == WL_BODY_SPHERE && q.pivot_offset[0] == 0.0 && q.pivot_offset[1] == 0.0 && q.pivot_offset[2] == 0.0)
+        q.spin_omega = 0.0;
+      if (part_moving(q))
+        return fail(WL_ERR_UNSUPPORTED,
+                    "the adjoint needs a body whose shape does not move (spheres spinning about their centre are allowed)");
+    }
     return WL_OK;
   }
 
@@ -1707,7 +2002,7 @@ struct Impl : SimBase {
     }
     if (value) *value = val;
     Motion m{};
-    host_motion(bdesc, t, m);
+    host_motion(parts, t, m);
     const double3 d3 = make_double3(dir[0], dir[1], D == 3 ? dir[2] : 0.0);
     WL_TIMED(WL_K_ADJOINT, (k_adj_force_p<T, D><<<nb[0], kBlock, 0, stream>>>(g[0], body, m, desc.eps, iD[0], weight,
                                                                                d3, nkm, apb)));
@@ -1726,9 +2021,10 @@ struct Impl : SimBase {
   wl_status adj_body_grad(double* dR, double* dW) override {
     wl_status s = adj_require();
     if (s != WL_OK) return s;
-    if (bdesc.kind != WL_BODY_SPHERE) return fail(WL_ERR_UNSUPPORTED, "body-parameter gradients need a sphere/circle");
+    if (parts.size() != 1 || parts[0].kind != WL_BODY_SPHERE || body.general)
+      return fail(WL_ERR_UNSUPPORTED, "body-parameter gradients need a single sphere/circle");
     Motion m{};
-    host_motion(bdesc, t, m);
+    host_motion(parts, t, m);
     const int gb = nb_face;
     WL_TIMED(WL_K_ADJOINT, (k_adj_body<T, D><<<dim3(gb, D), kBlock, 0, stream>>>(
                                g[0], body, m, desc.eps, v3(am0b), v9(am1b), v3(aVb), slot(kSlotForce))));
@@ -1833,7 +2129,9 @@ size_t wl_workspace_bytes(const wl_sim_desc* desc, const wl_body_desc* body) {
   wl_sim_desc d;
   if (validate_and_default(desc, &d) != WL_OK) return 0;
   if (validate_body(d, body) != WL_OK) return 0;
-  const Plan P = make_plan(d, body && body->kind != WL_BODY_NONE);
+  std::vector<wl_body_desc> ps;
+  if (collect_parts(body, ps) != WL_OK) return 0;
+  const Plan P = make_plan(d, ps);
   if (!plan_consistent(d, P)) {
     fail(WL_ERR_INVALID_ARG, "internal: workspace plan and field carving disagree");
     return 0;
@@ -1849,15 +2147,19 @@ wl_status wl_sim_create(const wl_sim_desc* desc, const wl_body_desc* body, void*
   wl_status s = validate_and_default(desc, &d);
   if (s != WL_OK) return s;
   if ((s = validate_body(d, body)) != WL_OK) return s;
-  Plan P = make_plan(d, body && body->kind != WL_BODY_NONE);
+  std::vector<wl_body_desc> ps;
+  if ((s = collect_parts(body, ps)) != WL_OK) return s;
+  Plan P = make_plan(d, ps);
   if (!ws) return fail(WL_ERR_INVALID_ARG, "workspace is NULL");
   if (((uintptr_t)ws) & 255u) return fail(WL_ERR_INVALID_ARG, "workspace must be 256-byte aligned");
   if (bytes < P.bytes) return fail(WL_ERR_WORKSPACE_TOO_SMALL, "workspace smaller than wl_workspace_bytes()");
   if (P.lev[0].elems >= (int64_t(1) << 31)) return fail(WL_ERR_UNSUPPORTED, "grid too large for 32-bit indexing");
   SimBase* impl = make_impl(d.prec, d.ndim);
   impl->desc = d;
-  std::memset(&impl->bdesc, 0, sizeof(impl->bdesc));
-  if (body) impl->bdesc = *body;
+  if ((s = collect_parts(body, impl->parts)) != WL_OK) {
+    delete impl;
+    return s;
+  }
   impl->plan = P;
   impl->stream = (hipStream_t)hip_stream;
   if (!carve_any(impl, d, ws, P.bytes)) {
@@ -1971,6 +2273,16 @@ wl_status wl_get_time(wl_sim* sim, double* t, double* dt_next) {
   WL_SIM_CHECK(sim);
   if (t) *t = sim->impl->t;
   if (dt_next) *dt_next = sim->impl->dt;
+  return WL_OK;
+}
+
+wl_status wl_sim_time(wl_sim* sim, double* t_star) {
+  WL_SIM_CHECK(sim);
+  if (!t_star) return fail(WL_ERR_INVALID_ARG, "t_star is NULL");
+  const wl_sim_desc& d = sim->impl->desc;
+  double u = std::sqrt(d.U[0] * d.U[0] + d.U[1] * d.U[1] + d.U[2] * d.U[2]);
+  if (u == 0.0) u = 1.0;
+  *t_star = sim->impl->t * u / d.L;
   return WL_OK;
 }
 

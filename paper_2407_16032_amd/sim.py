@@ -12,23 +12,56 @@ import torch
 from . import _lib as L
 
 
-def _body_desc(body) -> L.BodyDesc:
+def _part_desc(body, ndim, dtype, device, keep) -> L.BodyDesc:
     b = L.BodyDesc()
-    if body is None or getattr(body, "kind", "none") == "none":
-        b.kind = 0
-        return b
     b.kind = L.BODY_KIND[body.kind]
     for k, v in enumerate(tuple(body.center)[:3]):
         b.center[k] = v
     # a field the body object does not carry keeps its zero default (no motion)
     b.radius = float(getattr(body, "radius", 0.0))
-    for k, v in enumerate(tuple(getattr(body, "half_extent", ()))[:3]):
-        b.half_extent[k] = v
-    for name in ("heave_amp", "pitch_amp", "freq", "phase_h", "phase_p", "spin_omega"):
+    for name in ("heave_amp", "pitch_amp", "freq", "phase_h", "phase_p", "spin_omega", "phase_s", "shell"):
         setattr(b, name, float(getattr(body, name, 0.0)))
-    for k, v in enumerate(tuple(getattr(body, "pivot_offset", ()))[:3]):
-        b.pivot_offset[k] = v
+    for name in ("half_extent", "pivot_offset", "velocity", "heave_dir", "scale_amp", "normal", "grid_origin"):
+        arr = getattr(b, name)
+        for k, v in enumerate(tuple(getattr(body, name, ()))[:3]):
+            arr[k] = float(v)
+    b.op = L.BODY_OP[getattr(body, "op", "union")]
+    sdf = getattr(body, "sdf_grid", None)
+    if sdf is not None:
+        import numpy as np
+        s = np.asarray(sdf, dtype=np.float64)
+        for k in range(ndim):
+            b.grid_n[k] = s.shape[k]
+        b.grid_h = float(body.grid_h)
+        # device copy, x fastest (the library reads it at creation / body update)
+        ts = torch.from_numpy(np.ascontiguousarray(s.T)).to(device=device, dtype=dtype)
+        keep.append(ts)
+        b.sdf_grid = ts.data_ptr()
+        vg = getattr(body, "vel_grid", None)
+        if vg is not None:
+            v = np.asarray(vg, dtype=np.float64)
+            tv = torch.from_numpy(np.ascontiguousarray(np.stack([v[c].T for c in range(ndim)]))).to(
+                device=device, dtype=dtype)
+            keep.append(tv)
+            b.vel_grid = tv.data_ptr()
     return b
+
+
+def _body_desc(body, ndim=3, dtype=torch.float32, device="cpu", keep=None) -> L.BodyDesc:
+    """The head of a chain of wl_body_desc parts; ``keep`` collects the objects that
+    must stay alive while the library reads the chain (parts and sample arrays)."""
+    keep = [] if keep is None else keep
+    if body is None or getattr(body, "kind", "none") == "none":
+        b = L.BodyDesc()
+        b.kind = 0
+        keep.append(b)
+        return b
+    parts = body.parts() if hasattr(body, "parts") else [body]
+    descs = [_part_desc(p, ndim, dtype, device, keep) for p in parts]
+    for k in range(len(descs) - 1):
+        descs[k].next = C.pointer(descs[k + 1])
+    keep.extend(descs)
+    return descs[0]
 
 
 class Simulation:
@@ -36,7 +69,8 @@ class Simulation:
 
     Parameters mirror ``wl_sim_desc`` / ``wl_body_desc`` in include/wlmi.h.
     ``body`` is any object with the attributes of ``wl_body_desc`` (kind is
-    'none', 'sphere' or 'box').
+    'none', 'sphere', 'box', 'grid' or 'plane'), optionally chained through
+    ``parts()`` (``wlsynth.Body``).
     """
 
     def __init__(self, n: Sequence[int], U: Sequence[float], nu: float, body=None,
@@ -44,7 +78,7 @@ class Simulation:
                  eps: float = 1.0, dt0: float = 0.25, dt_max: float = 10.0, cfl_nu: float = 5.0,
                  tol: float = 1e-6, itmax: int = 32, pcg_iters: int = 6, device="cuda:0",
                  stream: Optional[torch.cuda.Stream] = None, learned_guess: bool = False,
-                 adjoint: bool = False, solver_path: str = "auto"):
+                 adjoint: bool = False, solver_path: str = "auto", L_ref: float = 1.0):
         self.lib = L.load()
         nd = len(n)
         d = L.SimDesc()
@@ -53,6 +87,7 @@ class Simulation:
             d.n[k] = int(n[k])
             d.U[k] = float(U[k])
         d.nu = float(nu)
+        d.L = float(L_ref)
         d.periodic_mask = sum((1 << k) for k, p in enumerate(periodic) if p)
         d.convective_exit = 1 if convective_exit else 0
         d.prec = L.WL_F64 if prec == "f64" else L.WL_F32
@@ -62,11 +97,12 @@ class Simulation:
         d.adjoint = 1 if adjoint else 0
         d.solver_path = {"auto": 0, "tiles": 1, "flat": 2, "generic": 3}[solver_path]
         self.desc = d
-        self.bdesc = _body_desc(body)
         self.ndim = nd
         self.n = tuple(int(v) for v in n)
         self.dtype = torch.float64 if prec == "f64" else torch.float32
         self.device = torch.device(device)
+        self._keep = []
+        self.bdesc = _body_desc(body, nd, self.dtype, self.device, self._keep)
         nbytes = self.lib.wl_workspace_bytes(C.byref(d), C.byref(self.bdesc))
         if nbytes == 0:
             raise L.WlError("invalid simulation description: %s" % self.lib.wl_last_error().decode())
@@ -80,6 +116,9 @@ class Simulation:
                                        C.c_size_t(nbytes), C.c_void_p(self.stream.cuda_stream),
                                        C.byref(h)), "wl_sim_create")
         self._h = h
+        # the library holds its own copies of the body now
+        torch.cuda.synchronize(self.device)
+        self._keep = [self.bdesc]
 
     # ------------------------------------------------------------------ life
     def close(self):
@@ -101,7 +140,8 @@ class Simulation:
         st = L.StepStats()
         L.check(self.lib.wl_step(self._h, 1 if remeasure else 0, C.byref(st)), "wl_step")
         return {"dt": st.dt, "t": st.t, "dt_next": st.dt_next, "vcycles": (st.vcycles[0], st.vcycles[1]),
-                "res_linf": (st.res_linf[0], st.res_linf[1]), "converged": bool(st.converged)}
+                "res_linf": (st.res_linf[0], st.res_linf[1]), "res_l2": (st.res_l2[0], st.res_l2[1]),
+                "div_linf": st.div_linf, "converged": bool(st.converged)}
 
     def apply_bc(self):
         L.check(self.lib.wl_apply_bc(self._h), "wl_apply_bc")
@@ -127,7 +167,7 @@ class Simulation:
     @staticmethod
     def _solve_dict(st) -> dict:
         return {"vcycles": st.vcycles, "res0_linf": st.res0_linf, "res_linf": st.res_linf,
-                "converged": bool(st.converged)}
+                "res_l2": st.res_l2, "converged": bool(st.converged)}
 
     def forces(self):
         fp = (C.c_double * 3)()
@@ -240,8 +280,10 @@ class Simulation:
 
     # ---------------------------------------------------- discrete adjoint
     def body_update(self, body):
-        self.bdesc = _body_desc(body)
+        keep = []
+        self.bdesc = _body_desc(body, self.ndim, self.dtype, self.device, keep)
         L.check(self.lib.wl_body_update(self._h, C.byref(self.bdesc)), "wl_body_update")
+        torch.cuda.synchronize(self.device)
 
     def body_box(self, level: int = 0):
         """(lo, hi) padded index box of a level outside of which coefficients are body-free."""
@@ -285,6 +327,12 @@ class Simulation:
 
     def set_time(self, t: float, dt_next: float):
         L.check(self.lib.wl_set_time(self._h, float(t), float(dt_next)), "wl_set_time")
+
+    def sim_time(self) -> float:
+        """Convective time t |U| / L."""
+        ts = C.c_double()
+        L.check(self.lib.wl_sim_time(self._h, C.byref(ts)), "wl_sim_time")
+        return ts.value
 
     def time(self):
         t = C.c_double()

@@ -45,6 +45,7 @@ def test_struct_layout_matches_header(tmp_path):
 int main(void) {
   printf("%zu %zu %zu %zu\\n", sizeof(wl_sim_desc), sizeof(wl_body_desc), sizeof(wl_step_stats), sizeof(wl_solve_stats));
   printf("%zu %zu %zu %zu %zu\\n", offsetof(wl_sim_desc, nu), offsetof(wl_sim_desc, mg_tol), offsetof(wl_body_desc, spin_omega), offsetof(wl_step_stats, converged), offsetof(wl_sim_desc, adjoint));
+  printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu\\n", offsetof(wl_sim_desc, L), offsetof(wl_body_desc, velocity), offsetof(wl_body_desc, shell), offsetof(wl_body_desc, sdf_grid), offsetof(wl_body_desc, grid_h), offsetof(wl_body_desc, op), offsetof(wl_body_desc, next), offsetof(wl_step_stats, div_linf), offsetof(wl_solve_stats, res_l2));
   return 0;
 }
 """)
@@ -56,6 +57,10 @@ int main(void) {
     assert sizes == [C.sizeof(L.SimDesc), C.sizeof(L.BodyDesc), C.sizeof(L.StepStats), C.sizeof(L.SolveStats)]
     assert offs == [L.SimDesc.nu.offset, L.SimDesc.mg_tol.offset, L.BodyDesc.spin_omega.offset,
                     L.StepStats.converged.offset, L.SimDesc.adjoint.offset]
+    offs2 = [int(v) for v in lines[2].split()]
+    assert offs2 == [L.SimDesc.L.offset, L.BodyDesc.velocity.offset, L.BodyDesc.shell.offset,
+                     L.BodyDesc.sdf_grid.offset, L.BodyDesc.grid_h.offset, L.BodyDesc.op.offset,
+                     L.BodyDesc.next.offset, L.StepStats.div_linf.offset, L.SolveStats.res_l2.offset]
 
 
 def _desc(n=(64, 32), prec=L.WL_F32):
@@ -142,3 +147,77 @@ def test_create_rejects_bad_arguments_before_any_gpu_work(lib):
     assert st == 2
     assert lib.wl_step(None, 0, None) == 1
     assert lib.wl_sim_destroy(None) == 1
+
+
+def _part(kind, **kw):
+    b = L.BodyDesc()
+    b.kind = L.BODY_KIND[kind]
+    for k, v in kw.items():
+        if isinstance(v, (tuple, list)):
+            arr = getattr(b, k)
+            for i, x in enumerate(v):
+                arr[i] = x
+        else:
+            setattr(b, k, v)
+    return b
+
+
+def _chain(*parts):
+    for a, b in zip(parts[:-1], parts[1:]):
+        a.next = C.pointer(b)
+    return parts[0]
+
+
+def test_body_parts_validation(lib):
+    d = _desc(n=(64, 48))
+    base = lib.wl_workspace_bytes(C.byref(d), None)
+    sph = _part("sphere", center=(30.0, 24.0), radius=6.0)
+    assert lib.wl_workspace_bytes(C.byref(d), C.byref(sph)) == base
+    # a half space alone is unbounded
+    pl = _part("plane", center=(30.0, 24.0), normal=(0.0, 1.0))
+    assert lib.wl_workspace_bytes(C.byref(d), C.byref(pl)) == 0
+    assert b"unbounded" in lib.wl_last_error()
+    # sphere minus the half space is bounded
+    a = _part("sphere", center=(30.0, 24.0), radius=6.0)
+    cut = _part("plane", center=(30.0, 24.0), normal=(0.0, 1.0), op=L.BODY_OP["subtract"])
+    assert lib.wl_workspace_bytes(C.byref(d), C.byref(_chain(a, cut))) == base
+    # but not the union with it
+    a2 = _part("sphere", center=(30.0, 24.0), radius=6.0)
+    un = _part("plane", center=(30.0, 24.0), normal=(0.0, 1.0), op=L.BODY_OP["union"])
+    assert lib.wl_workspace_bytes(C.byref(d), C.byref(_chain(a2, un))) == 0
+    # at most four parts
+    ps = [_part("sphere", center=(20.0 + 4 * k, 24.0), radius=2.0, op=0) for k in range(5)]
+    assert lib.wl_workspace_bytes(C.byref(d), C.byref(_chain(*ps))) == 0
+    assert b"4 parts" in lib.wl_last_error()
+    ps = [_part("sphere", center=(20.0 + 4 * k, 24.0), radius=2.0, op=0) for k in range(4)]
+    assert lib.wl_workspace_bytes(C.byref(d), C.byref(_chain(*ps))) == base
+    # a part with an unknown op, a scale amplitude of 0.9 or more, a negative shell
+    bad = _part("sphere", center=(30.0, 24.0), radius=3.0, op=7)
+    assert lib.wl_workspace_bytes(C.byref(d), C.byref(_chain(_part("sphere", center=(30.0, 24.0), radius=3.0), bad))) == 0
+    assert lib.wl_workspace_bytes(C.byref(d), C.byref(_part("sphere", center=(30.0, 24.0), radius=3.0,
+                                                             scale_amp=(0.95, 0.0)))) == 0
+    assert lib.wl_workspace_bytes(C.byref(d), C.byref(_part("sphere", center=(30.0, 24.0), radius=3.0,
+                                                             shell=-1.0))) == 0
+    # a scaled map reaches further: the reach check accounts for 1/S
+    assert lib.wl_workspace_bytes(C.byref(d), C.byref(_part("sphere", center=(30.0, 24.0), radius=14.0))) > 0
+    assert lib.wl_workspace_bytes(C.byref(d), C.byref(_part("sphere", center=(30.0, 24.0), radius=14.0,
+                                                             scale_amp=(0.5, 0.5)))) == 0
+
+
+def test_gridded_sdf_adds_its_samples_to_the_workspace(lib):
+    d = _desc(n=(64, 48))
+    base = lib.wl_workspace_bytes(C.byref(d), None)
+    g = _part("grid", center=(30.0, 24.0), grid_n=(21, 17), grid_origin=(-5.0, -4.0), grid_h=0.5,
+              sdf_grid=0x1000)  # never dereferenced by the size query
+    nb = lib.wl_workspace_bytes(C.byref(d), C.byref(g))
+    cnt = 21 * 17
+    per = (cnt * 8 + 255) // 256 * 256
+    assert nb == base + 3 * per  # samples and two gradient components, FP64
+    g.vel_grid = 0x2000
+    assert lib.wl_workspace_bytes(C.byref(d), C.byref(g)) == base + 5 * per
+    g.sdf_grid = None
+    assert lib.wl_workspace_bytes(C.byref(d), C.byref(g)) == 0
+    assert b"sdf_grid" in lib.wl_last_error()
+    # a velocity grid needs a gridded part
+    s2 = _part("sphere", center=(30.0, 24.0), radius=3.0, vel_grid=0x2000)
+    assert lib.wl_workspace_bytes(C.byref(d), C.byref(s2)) == 0

@@ -1,0 +1,230 @@
+"""Bodies through the C ABI against the oracle: gridded signed distances, mapped
+and combined parts (the paper's AutoBody and its signed-distance arithmetic),
+a body translating with the stream, and the step's FP64 statistics."""
+import math
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import wlsynth
+from gpu_util import FP64_STEP, make_pair, rel_l2
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _as_prec(body, prec):
+    """The body the oracle sees: sample arrays rounded to the simulation's precision."""
+    if prec == "f64":
+        return body
+    out = []
+    for p in body.parts():
+        q = wlsynth.Body(**{f: getattr(p, f) for f in p.__dataclass_fields__ if f != "next"})
+        if q.sdf_grid is not None:
+            q.sdf_grid = np.asarray(q.sdf_grid, np.float32).astype(np.float64)
+        if q.vel_grid is not None:
+            q.vel_grid = np.asarray(q.vel_grid, np.float32).astype(np.float64)
+        out.append(q)
+    head = out[0]
+    for a, b in zip(out[:-1], out[1:]):
+        a.next = b
+    return head
+
+
+def _check_measure(gpu, ref, tol):
+    g = ref.grid
+    mu0 = gpu.get("mu0")
+    mu1 = gpu.get("mu1")
+    V = gpu.get("V")
+    for i in range(g.ndim):
+        np.testing.assert_allclose(mu0[i], ref.L[i], atol=tol, rtol=0)
+        np.testing.assert_allclose(V[i], ref.V[i], atol=tol, rtol=0)
+        for j in range(g.ndim):
+            np.testing.assert_allclose(mu1[i * g.ndim + j], ref.mu1[i][j], atol=tol, rtol=0)
+    for l, lev in enumerate(ref.levels):
+        iD = gpu.get("iD", l)[0]
+        assert np.array_equal(iD != 0, lev.active)
+
+
+def _grid_bodies():
+    # a circle sampled at h = 0.5 with a sampled swirl added to a pitching motion;
+    # a sphere sampled at h = 0.75 rotating about an offset pivot
+    sdf2, o2 = wlsynth.sampled_sdf(lambda X: np.hypot(X[0], X[1]) - 5.0, 9.0, 0.5, 2)
+    ax = o2[0] + 0.5 * np.arange(sdf2.shape[0])
+    X, Y = np.meshgrid(ax, ax, indexing="ij")
+    vg = np.stack([-0.05 * Y, 0.05 * X])
+    b2 = wlsynth.Body("grid", center=(30.3, 24.2), sdf_grid=sdf2, vel_grid=vg, grid_origin=o2, grid_h=0.5,
+                      pitch_amp=0.3, freq=0.02, phase_p=0.4)
+    b3 = wlsynth.grid_sphere_body(5.0, 0.75, 3, (20.2, 20.1, 19.8), margin=2.5, spin_omega=0.04,
+                                  pivot_offset=(0.5, 0.0, 0.0))
+    return {"grid2d": ((64, 48), b2), "grid3d": ((48, 40, 40), b3)}
+
+
+@pytest.mark.parametrize("name", ["grid2d", "grid3d"])
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_grid_sdf_measure(name, prec):
+    _say("grid measure", name, prec)
+    n, body = _grid_bodies()[name]
+    from paper_2407_16032_amd import Simulation
+    U = (1.0, 0.0, 0.0)[:len(n)]
+    ref = oracle.Sim(n, U, 0.02, _as_prec(body, prec))
+    gpu = Simulation(n, U, 0.02, body, prec=prec, device="cuda:0")
+    tol = 1e-13 if prec == "f64" else 2e-7
+    _check_measure(gpu, ref, tol)
+    # the body moves: measure at a later time on both sides
+    for t in (2.5, 11.0):
+        ref.measure(t)
+        gpu.measure(t)
+        _check_measure(gpu, ref, tol)
+    gpu.close()
+
+
+def _composite_bodies():
+    # two circles, the smaller spinning (the paper's drag-control pair)
+    big = wlsynth.Body("sphere", center=(40.0, 32.0), radius=10.0)
+    small = wlsynth.Body("sphere", center=(48.2, 46.4), radius=3.0, spin_omega=0.15)
+    pair = wlsynth.combine(big, ("union", small))
+    # a rotated box minus a rotated half space, pitching about an offset pivot
+    box = wlsynth.Body("box", center=(36.0, 30.0), half_extent=(8.0, 5.0), pitch_amp=0.4, freq=0.03,
+                       pivot_offset=(2.0, 0.0))
+    cut = wlsynth.Body("plane", center=(36.0, 30.0), normal=(1.0, 1.0), radius=1.5, spin_omega=0.02)
+    notch = wlsynth.combine(box, ("subtract", cut))
+    # a pulsing hollow ellipse intersected with a translating disk
+    ring = wlsynth.Body("sphere", center=(34.0, 31.0), radius=9.0, shell=1.5, scale_amp=(0.2, -0.15),
+                        freq=0.04, phase_s=0.3, heave_amp=2.0, heave_dir=(1.0, 1.0))
+    disk = wlsynth.Body("sphere", center=(30.0, 31.0), radius=11.0, velocity=(0.05, 0.0))
+    lens = wlsynth.combine(ring, ("intersect", disk))
+    return {"pair2d": ((96, 64), pair), "notch2d": ((72, 60), notch), "lens2d": ((72, 62), lens),
+            "jelly3d": (None, wlsynth.jelly_3d(16).body)}
+
+
+@pytest.mark.parametrize("name", ["pair2d", "notch2d", "lens2d", "jelly3d"])
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_composite_measure(name, prec):
+    _say("composite measure", name, prec)
+    n, body = _composite_bodies()[name]
+    if n is None:
+        n = wlsynth.jelly_3d(16).n
+    from paper_2407_16032_amd import Simulation
+    U = (1.0, 0.0, 0.0)[:len(n)]
+    ref = oracle.Sim(n, U, 0.02, body)
+    gpu = Simulation(n, U, 0.02, body, prec=prec, device="cuda:0")
+    tol = 1e-12 if prec == "f64" else 2e-7
+    _check_measure(gpu, ref, tol)
+    for t in (3.1, 17.9):
+        ref.measure(t)
+        gpu.measure(t)
+        _check_measure(gpu, ref, tol)
+    gpu.close()
+
+
+@pytest.mark.parametrize("name", ["pair2d", "notch2d", "lens2d", "grid2d", "jelly3d"])
+def test_one_step_with_general_bodies_fp64(name):
+    _say("step general body", name)
+    if name == "grid2d":
+        n, body = _grid_bodies()[name]
+    else:
+        n, body = _composite_bodies()[name]
+    if name == "jelly3d":
+        w = wlsynth.jelly_3d(16)
+    else:
+        w = wlsynth.Workload(name, n, (1.0, 0.0), 0.05, body)
+    ref, gpu = make_pair(w, "f64", 1e-13)
+    for _ in range(2):
+        ref.step()
+        gpu.step()
+    err = rel_l2(gpu.get("u"), ref.u, ref.grid)
+    _say("  rel-L2", err)
+    assert err <= FP64_STEP, err
+    gpu.close()
+
+
+@pytest.mark.parametrize("ndim", [2, 3])
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_freestream_around_a_body_translating_with_it(ndim, prec):
+    # a body moving at the free-stream velocity leaves uniform flow exactly uniform
+    # (the oracle pins the same invariant): no pressure is needed, every step makes
+    # 0 V-cycles, and u = U on every face
+    _say("freestream translating", ndim, prec)
+    from paper_2407_16032_amd import Simulation
+    if ndim == 2:
+        U = (1.0, 0.0)
+        body = wlsynth.Body("sphere", center=(20.0, 12.3), radius=4.0, velocity=U)
+        n, steps = (160, 24), 100
+    else:
+        U = (1.0, 0.0, 0.0)
+        body = wlsynth.Body("box", center=(12.0, 12.2, 11.9), half_extent=(2.0, 3.0, 2.5), velocity=U,
+                            pitch_amp=0.3, phase_p=math.pi / 2)
+        n, steps = (64, 24, 24), 20
+    gpu = Simulation(n, U, 0.03, body, convective_exit=True, prec=prec, device="cuda:0")
+    t = 0.0
+    for _ in range(steps):
+        st = gpu.step()
+        assert st["vcycles"] == (0, 0), st
+        t = st["t"]
+    assert t > 0.8 * steps * 0.85
+    u = gpu.get("u")
+    for i in range(ndim):
+        assert np.all(u[i] == U[i])
+    # the body is where its motion puts it: V is set around x = centre + U t
+    V = gpu.get("V")[0]
+    xs = np.nonzero(V != 0.0)[0]
+    assert abs(0.5 * (xs.min() + xs.max()) - (body.center[0] + t + 1.0)) < 2.0
+    gpu.close()
+
+
+def test_translating_body_leaving_the_domain_is_an_error():
+    from paper_2407_16032_amd import Simulation
+    from paper_2407_16032_amd._lib import WlError
+    body = wlsynth.Body("sphere", center=(20.0, 12.0), radius=4.0, velocity=(1.0, 0.0))
+    gpu = Simulation((48, 24), (1.0, 0.0), 0.03, body, prec="f64", device="cuda:0")
+    with pytest.raises(WlError, match="3 cells"):
+        for _ in range(60):
+            gpu.step()
+    gpu.close()
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_step_statistics_residual_two_norm_and_divergence(prec):
+    # res_l2 equals the 2-norm of the fine residual field left by the solve, and
+    # div_linf the max |div u| over active cells of the final velocity, both in FP64
+    _say("step stats", prec)
+    w = wlsynth.circle_2d(n=(96, 48), R=6.0, center=(24.0, 24.0))
+    tol = 1e-10 if prec == "f64" else 1e-5
+    ref, gpu = make_pair(w, prec, tol)
+    for _ in range(3):
+        st = gpu.step()
+    r = gpu.get("r")[0]
+    g = ref.grid
+    l2 = math.sqrt(float(np.sum(r[g.interior()] ** 2)))
+    assert abs(st["res_l2"][1] - l2) <= 1e-12 * max(l2, 1e-300), (st["res_l2"], l2)
+    assert st["res_l2"][1] >= st["res_linf"][1] * (1 - 1e-12)
+    u = gpu.get("u")
+    div = sum(np.roll(u[i], -1, axis=i) - u[i] for i in range(2))
+    act = gpu.get("iD")[0] != 0
+    dmax = float(np.max(np.abs(div[act])))
+    assert st["div_linf"] == pytest.approx(dmax, rel=1e-12, abs=0.0)
+    assert st["div_linf"] < 2 * tol
+    # the standalone solve reports the same kind of norm
+    sol = gpu.project(1.0)
+    r = gpu.get("r")[0]
+    l2 = math.sqrt(float(np.sum(r[g.interior()] ** 2)))
+    assert abs(sol["res_l2"] - l2) <= 1e-12 * max(l2, 1e-300)
+    gpu.close()
+
+
+def test_convective_time_scale():
+    from paper_2407_16032_amd import Simulation
+    w = wlsynth.circle_2d(n=(64, 32), R=4.0, center=(16.0, 16.0))
+    gpu = Simulation(w.n, (2.0, 0.0), w.nu, w.body, prec="f64", device="cuda:0", L_ref=8.0)
+    for _ in range(3):
+        st = gpu.step()
+    assert gpu.sim_time() == pytest.approx(st["t"] * 2.0 / 8.0, rel=1e-15)
+    gpu.close()

@@ -231,14 +231,14 @@ def jelly_3d(n: int = 32, Re: float = 500.0, U: float = 1.0, steps: int = 100, t
     whose map scales x and y harmonically and heaves it along z, minus a half space
     that moves with the same heave), in a downward stream -U e_z.  Radius R = 2n/3,
     shell half thickness 1, angular frequency 2U/R, scale amplitude 0.1.  The bell
-    is centred in x and y of a (2n, 2n, 4n + n/2) box instead of on the corner of a
-    quarter domain with symmetry planes (the extra n/2 above keeps its reach clear
-    of the top face)."""
+    is centred in x and y of a (3n, 3n, 4n + n/2) box instead of on the corner of a
+    quarter domain with symmetry planes (the margins keep the reach of the pulsing
+    bell clear of the side and top faces)."""
     R = 2.0 * n / 3.0
     hgt = 4.0 * n - 2.0 * R
     w = 2.0 * U / R
     f = w / (2.0 * math.pi)
-    cx = cy = float(n)
+    cx = cy = 1.5 * n
     # sphere: x_b = A(t) (x - P) with A_xy = 1 - 0.1 cos(w t) and the centre at
     # P_z = hgt + R/4 - (R/4)(cos w t + sin w t)
     bell = Body("sphere", center=(cx, cy, hgt + R / 4.0), radius=R, shell=1.0,
@@ -249,7 +249,7 @@ def jelly_3d(n: int = 32, Re: float = 500.0, U: float = 1.0, steps: int = 100, t
                heave_amp=R / 4.0, heave_dir=(0.0, 0.0, -1.0))
     body = combine(bell, ("subtract", cut))
     nz = 4 * n + n // 2
-    return Workload("jelly3d_%dx%dx%d" % (2 * n, 2 * n, nz), (2 * n, 2 * n, nz), (0.0, 0.0, -U),
+    return Workload("jelly3d_%dx%dx%d" % (3 * n, 3 * n, nz), (3 * n, 3 * n, nz), (0.0, 0.0, -U),
                     U * R / Re, body, steps=steps, tol=tol, L=R)
 
 
