@@ -235,7 +235,9 @@ def shape_sdf(part, xb):
         qmax = q[0]
         for k in range(1, nd):
             qmax = _cmax_first(qmax, q[k])
-        return olen + np.where(np.real(qmax) < 0.0, qmax, 0.0 * qmax)
+        # on a face (qmax = 0, no positive q) the inner branch is taken, so the
+        # derivative there is the face normal, as the rigid formulas define it
+        return olen + np.where(np.real(qmax) <= 0.0, qmax, 0.0 * qmax)
     if part.kind == "plane":
         nrm = _vec3(part.normal)[:nd]
         m = math.sqrt(sum(v * v for v in nrm))

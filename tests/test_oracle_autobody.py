@@ -39,6 +39,24 @@ def test_general_equals_rigid_formulas(kind, ndim):
         np.testing.assert_allclose(V2[k], V[k], atol=1e-12)
 
 
+@pytest.mark.parametrize("ndim", [2, 3])
+def test_general_box_normal_on_its_faces(ndim):
+    # points exactly on a face (d = 0, between the edges) take the face normal in
+    # both evaluations
+    b = wlsynth.Body("box", center=(10.0, 9.0, 8.0)[:ndim], half_extent=(4.0, 3.0, 2.0))
+    # on the +y face, on the +x face, the centre (the +z face in 3-D), inside
+    X = [np.array([10.5, 14.0, 10.0, 7.5]), np.array([12.0, 8.5, 9.0, 9.0])]
+    if ndim == 3:
+        X.append(np.array([8.0, 8.0, 10.0, 8.0]))
+    d, n, _ = sdf_normal_velocity(b, X, 0.0)
+    d2, n2, _ = part_general(b, X, 0.0)
+    np.testing.assert_array_equal(d[:2], 0.0)
+    np.testing.assert_allclose(d2, d, atol=1e-15)
+    for k in range(ndim):
+        np.testing.assert_allclose(n2[k], n[k], atol=1e-15)
+    np.testing.assert_allclose([n2[1][0], n2[0][1]], [1.0, 1.0], atol=1e-15)
+
+
 def test_general_equals_rigid_formulas_grid():
     sdf, origin = wlsynth.sampled_sdf(lambda X: np.hypot(X[0], X[1]) - 3.0, 6.0, 0.5, 2)
     b = wlsynth.Body("grid", center=(10.0, 10.0), sdf_grid=sdf, grid_origin=origin, grid_h=0.5,
