@@ -75,7 +75,7 @@ struct Motion {
 // Cell of the sample grid holding body-frame point xb: lower sample index and
 // fractions along each axis; false outside the sampled box.
 template <int D>
-__device__ inline bool grid_cell(const GridSdf& G, const double xb[3], int i0[3], double fr[3]) {
+__host__ __device__ inline bool grid_cell(const GridSdf& G, const double xb[3], int i0[3], double fr[3]) {
 #pragma clang fp contract(off)
 #pragma unroll
   for (int a = 0; a < D; ++a) {
@@ -92,7 +92,7 @@ __device__ inline bool grid_cell(const GridSdf& G, const double xb[3], int i0[3]
 // Multilinear interpolant of a sample array at the cell found by grid_cell
 // (corners in the order of their bit patterns, weights multiplied axis by axis).
 template <int D>
-__device__ inline double grid_interp(const GridSdf& G, const double* a, const int i0[3], const double fr[3]) {
+__host__ __device__ inline double grid_interp(const GridSdf& G, const double* a, const int i0[3], const double fr[3]) {
 #pragma clang fp contract(off)
   double out = 0.0;
 #pragma unroll
@@ -114,7 +114,7 @@ __device__ inline double grid_interp(const GridSdf& G, const double* a, const in
 // Signed distance, unit gradient (body frame) and sampled velocity of a part's
 // shape at body-frame point xb (before hollowing).
 template <int D>
-__device__ inline void shape_eval(const PartP& b, const double xb[3], double& d, double nb[3], double Vs[3]) {
+__host__ __device__ inline void shape_eval(const PartP& b, const double xb[3], double& d, double nb[3], double Vs[3]) {
 #pragma clang fp contract(off)
   nb[0] = nb[1] = nb[2] = 0.0;
   Vs[0] = Vs[1] = Vs[2] = 0.0;
@@ -181,7 +181,7 @@ __device__ inline void shape_eval(const PartP& b, const double xb[3], double& d,
 // One rigid part by the direct formulas: d = SDF(x_b), n = Rot(theta) n_b,
 // V = dP/dt + omega e_z x (x - P) (+ sampled velocity).
 template <int D>
-__device__ inline void part_rigid(const PartP& b, const PartMotion& m, const double x[3], double& d, double n[3],
+__host__ __device__ inline void part_rigid(const PartP& b, const PartMotion& m, const double x[3], double& d, double n[3],
                                   double V[3]) {
 #pragma clang fp contract(off)
   const double rx = x[0] - m.P[0], ry = x[1] - m.P[1], rz = (D == 3) ? x[2] - m.P[2] : 0.0;
@@ -204,7 +204,7 @@ __device__ inline void part_rigid(const PartP& b, const PartMotion& m, const dou
 // d = SDF/|g|; V = -J^{-1} dx_b/dt = dP/dt + omega e_z x r - Rot(theta)((S'/S) a)
 // with r = x - P and a = Rot(-theta) r.
 template <int D>
-__device__ inline void part_general(const PartP& b, const PartMotion& m, const double x[3], double& d, double n[3],
+__host__ __device__ inline void part_general(const PartP& b, const PartMotion& m, const double x[3], double& d, double n[3],
                                     double V[3]) {
 #pragma clang fp contract(off)
   const double r0 = x[0] - m.P[0], r1 = x[1] - m.P[1], r2 = (D == 3) ? x[2] - m.P[2] : 0.0;
@@ -216,8 +216,8 @@ __device__ inline void part_general(const PartP& b, const PartMotion& m, const d
   double dt, nb[3], Vs[3];
   shape_eval<D>(b, xb, dt, nb, Vs);
   if (b.shell > 0.0) {
-    if (dt < 0.0)
-      for (int k = 0; k < 3; ++k) nb[k] = -nb[k];
+    const double sg = dt < 0.0 ? -1.0 : 1.0;
+    for (int k = 0; k < 3; ++k) nb[k] = sg * nb[k];
     dt = fabs(dt) - b.shell;
   }
   const double s0 = m.S[0] * nb[0], s1 = m.S[1] * nb[1], s2 = (D == 3) ? m.S[2] * nb[2] : 0.0;
@@ -244,7 +244,7 @@ __device__ inline void part_general(const PartP& b, const PartMotion& m, const d
 
 // signed distance, unit normal and body velocity at point x (FP64).
 template <int D>
-__device__ inline void body_eval(const BodyP& b, const Motion& m, const double x[3], double& d, double n[3],
+__host__ __device__ inline void body_eval(const BodyP& b, const Motion& m, const double x[3], double& d, double n[3],
                                  double V[3]) {
   if (!b.general) {
     part_rigid<D>(b.p[0], m.m[0], x, d, n, V);
@@ -254,16 +254,14 @@ __device__ inline void body_eval(const BodyP& b, const Motion& m, const double x
   for (int k = 1; k < b.nparts; ++k) {
     double db, nb[3], Vb[3];
     part_general<D>(b.p[k], m.m[k], x, db, nb, Vb);
-    bool take;
-    if (b.p[k].op == kOpUnion) {
-      take = db < d;
-    } else if (b.p[k].op == kOpIntersect) {
-      take = db > d;
-    } else {
-      db = -db;
-      for (int j = 0; j < 3; ++j) nb[j] = -nb[j];
-      take = db > d;
-    }
+    // a subtracted part enters with d and n negated (a product with -1: the
+    // three-way branch on op, with the negation inside it, was compiled for
+    // gfx950 into a flow that skipped the negation)
+    const int op = b.p[k].op;
+    const double sg = (op == kOpSubtract) ? -1.0 : 1.0;
+    db = sg * db;
+    for (int j = 0; j < 3; ++j) nb[j] = sg * nb[j];
+    const bool take = (op == kOpUnion) ? (db < d) : (db > d);
     if (take) {
       d = db;
       for (int j = 0; j < 3; ++j) {

@@ -38,16 +38,38 @@ def _as_prec(body, prec):
     return head
 
 
-def _check_measure(gpu, ref, tol):
+def _near_ties(body, grid, comp, t):
+    """Faces where combining the parts compared two distances within 1e-10 of each
+    other: either part's normal and velocity is a correct result there."""
+    from oracle.body import face_points, part_general
+    X = face_points(grid, comp)
+    parts = body.parts()
+    if len(parts) < 2:
+        return np.zeros(grid.shape, dtype=bool)
+    d, _, _ = part_general(parts[0], X, t)
+    tie = np.zeros(np.shape(d), dtype=bool)
+    for p in parts[1:]:
+        db, _, _ = part_general(p, X, t)
+        if p.op == "subtract":
+            db = -db
+        tie |= np.abs(db - d) < 1e-10
+        take = db < d if p.op == "union" else db > d
+        d = np.where(take, db, d)
+    return tie
+
+
+def _check_measure(gpu, ref, tol, body=None, t=0.0):
     g = ref.grid
     mu0 = gpu.get("mu0")
     mu1 = gpu.get("mu1")
     V = gpu.get("V")
     for i in range(g.ndim):
         np.testing.assert_allclose(mu0[i], ref.L[i], atol=tol, rtol=0)
-        np.testing.assert_allclose(V[i], ref.V[i], atol=tol, rtol=0)
+        ok = np.ones(g.shape, dtype=bool) if body is None else ~_near_ties(body, g, i, t)
+        assert ok.mean() > 0.99
+        np.testing.assert_allclose(V[i][ok], ref.V[i][ok], atol=tol, rtol=0)
         for j in range(g.ndim):
-            np.testing.assert_allclose(mu1[i * g.ndim + j], ref.mu1[i][j], atol=tol, rtol=0)
+            np.testing.assert_allclose(mu1[i * g.ndim + j][ok], ref.mu1[i][j][ok], atol=tol, rtol=0)
     for l, lev in enumerate(ref.levels):
         iD = gpu.get("iD", l)[0]
         assert np.array_equal(iD != 0, lev.active)
@@ -117,11 +139,11 @@ def test_composite_measure(name, prec):
     ref = oracle.Sim(n, U, 0.02, body)
     gpu = Simulation(n, U, 0.02, body, prec=prec, device="cuda:0")
     tol = 1e-12 if prec == "f64" else 2e-7
-    _check_measure(gpu, ref, tol)
+    _check_measure(gpu, ref, tol, body, 0.0)
     for t in (3.1, 17.9):
         ref.measure(t)
         gpu.measure(t)
-        _check_measure(gpu, ref, tol)
+        _check_measure(gpu, ref, tol, body, t)
     gpu.close()
 
 
