@@ -122,28 +122,76 @@ def box_counts(sim, n):
     return cells, faces
 
 
-def run_cpu_baseline(w_name):
-    """The FP64 oracle (numpy, one thread) on a bounded sample: one step of the same
-    case at 1/3 of the linear size (plate: 256 x 128 x 128 cells)."""
+def cpu_sample_workload(w_name):
+    """The bounded CPU sample of a workload: the same case at 1/3 of the linear size
+    (plate: 256 x 128 x 128 cells)."""
+    import wlsynth
+    if w_name == "plate3d":
+        return wlsynth.plate_3d(scale=3)
+    if w_name == "tgv3d":
+        return wlsynth.tgv_3d(N=64)
+    if w_name == "sphere3d":
+        return wlsynth.sphere_3d(n=(128, 64, 64), D=16.0, center=(32.0, 32.0, 32.0))
+    return wlsynth.circle_2d()
+
+
+def _oracle_sample_step(job):
+    """One FP64 oracle step of the CPU sample (runs in a worker process)."""
+    w_name, seed = job
     import wlsynth
     import oracle
-    if w_name == "plate3d":
-        w = wlsynth.plate_3d(scale=3)
-    elif w_name == "tgv3d":
-        w = wlsynth.tgv_3d(N=64)
-    elif w_name == "sphere3d":
-        w = wlsynth.sphere_3d(n=(128, 64, 64), D=16.0, center=(32.0, 32.0, 32.0))
-    else:
-        w = wlsynth.circle_2d()
+    w = cpu_sample_workload(w_name)
     body = w.body if w.body.kind != "none" else None
     s = oracle.Sim(w.n, w.U, w.nu, body, periodic=w.periodic_mask(), convective_exit=w.convective_exit,
                    tol=w.tol)
-    s.set_velocity(wlsynth.initial_velocity(w))
+    s.set_velocity(wlsynth.initial_velocity(w, seed=seed))
     t0 = time.perf_counter()
     s.step()
-    dt = time.perf_counter() - t0
-    return {"value": dt / w.cells * 1e9, "unit": "ns/point/step", "cores": 1, "kind": "oracle",
-            "sample": "one FP64 step of %s (%d cells), numpy single thread, %.1f s" % (w.name, w.cells, dt)}
+    return time.perf_counter() - t0, w.cells, w.name
+
+
+def run_cpu_baseline(w_name):
+    """The FP64 oracle (numpy) on a bounded sample, timed on this host's cores in
+    worker processes that never touch the GPU: one step alone (one thread), then one
+    step per worker on all cores at once (up to 16 workers, independent seeds); the
+    all-core aggregate is the reported value."""
+    import multiprocessing as mp
+    ncpu = os.cpu_count() or 1
+    workers = max(1, min(16, ncpu))
+    old = os.environ.get("OMP_NUM_THREADS")
+    os.environ["OMP_NUM_THREADS"] = "1"  # the workers' numpy: one thread each
+    try:
+        ctx = mp.get_context("spawn")
+        with ctx.Pool(1) as pool:
+            dt1, cells, name = pool.map(_oracle_sample_step, [(w_name, 0)])[0]
+        print("[bench] oracle, one core: %.1f s for one step of %d cells" % (dt1, cells), file=sys.stderr,
+              flush=True)
+        with ctx.Pool(workers) as pool:
+            res = pool.map(_oracle_sample_step, [(w_name, k) for k in range(workers)], chunksize=1)
+    finally:
+        if old is None:
+            del os.environ["OMP_NUM_THREADS"]
+        else:
+            os.environ["OMP_NUM_THREADS"] = old
+    slowest = max(r[0] for r in res)
+    agg = slowest / (workers * cells) * 1e9
+    print("[bench] oracle, %d cores: %d steps in parallel, slowest %.1f s" % (workers, workers, slowest),
+          file=sys.stderr, flush=True)
+    return {"value": round(agg, 2), "unit": "ns/point/step", "cores": workers, "kind": "oracle",
+            "sample": "one FP64 step of %s (%d cells) per worker, %d single-threaded numpy workers at once on "
+                      "%d host CPUs; aggregate = slowest step / (workers x cells)" % (name, cells, workers, ncpu),
+            "host_cpu_count": ncpu,
+            "single_core": {"value": round(dt1 / cells * 1e9, 2), "unit": "ns/point/step", "cores": 1,
+                            "seconds": round(dt1, 2)}}
+
+
+def step_byte_model(ndim, has_body, k):
+    """Algorithmic bytes per fine cell of one whole FP32 step by the fixed model of the
+    method: 4 (F + 105.4 k) in 3-D (F = 79 with a body, 55 without) and 4 (52 + 115.3 k)
+    in 2-D, k = V-cycles per step (both solves)."""
+    if ndim == 3:
+        return 4.0 * ((79.0 if has_body else 55.0) + 105.4 * k)
+    return 4.0 * (52.0 + 115.3 * k)
 
 
 def kernel_source_hash():
@@ -260,7 +308,9 @@ def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--windows", type=int, default=3,
+                    help="timed windows of --steps steps each; the value is their median")
     ap.add_argument("--workload", default="plate3d", choices=sorted(workloads().keys()))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--solver-path", default="auto", choices=["auto", "tiles", "flat", "generic"],
@@ -279,6 +329,12 @@ def main():
         print("bench.py: the solver runs on one GPU (its multi-GPU domain decomposition is designed, not "
               "implemented); use --gpus 1", file=sys.stderr)
         sys.exit(2)
+
+    # the CPU baseline runs first, in worker processes, before this process touches the GPU
+    cpu = None
+    if not args.no_cpu_baseline and not args.adjoint:
+        print("[bench] timing the FP64 oracle on a bounded CPU sample", file=sys.stderr, flush=True)
+        cpu = run_cpu_baseline(args.workload)
 
     import numpy as np
     import torch
@@ -344,28 +400,38 @@ def main():
                 ("%7.0f GB/s" % ent["GBps"]) if "GBps" in ent else ""), file=sys.stderr, flush=True)
 
     # Timed region: events only around the dominant kernel's launches (its
-    # average launch duration for the roofline), none around the rest
+    # average launch duration for the roofline), none around the rest; --windows
+    # windows of exactly --steps steps, each bracketed by synchronisations
     if dominant is not None:
         sim.profile(True, groups=[dominant])
-    torch.cuda.synchronize()
-    start = torch.cuda.Event(enable_timing=True)
-    stop = torch.cuda.Event(enable_timing=True)
     stream = sim.stream
-    start.record(stream)
-    t0 = time.perf_counter()
-    vc = []
-    for k in range(args.steps):
-        st = sim.step()
-        vc.append(st["vcycles"][0] + st["vcycles"][1])
-    stop.record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    ms = start.elapsed_time(stop)
-    ms_per_step = ms / args.steps
+    vc, factors, windows = [], [], []
+    for wi in range(args.windows):
+        torch.cuda.synchronize()
+        start = torch.cuda.Event(enable_timing=True)
+        stop = torch.cuda.Event(enable_timing=True)
+        start.record(stream)
+        t0 = time.perf_counter()
+        for k in range(args.steps):
+            st = sim.step()
+            vc.append(st["vcycles"][0] + st["vcycles"][1])
+            for j in range(2):
+                n_c = st["vcycles"][j]
+                if n_c > 0 and st["res0_linf"][j] > 0 and st["res_linf"][j] > 0:
+                    factors.append((st["res_linf"][j] / st["res0_linf"][j]) ** (1.0 / n_c))
+        stop.record(stream)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        ms = start.elapsed_time(stop)
+        windows.append(ms / args.steps)
+        print("[bench] window %d: %d steps, %.3f ms/step (wall %.3f ms/step), %.4f ns/pt/step"
+              % (wi, args.steps, ms / args.steps, wall * 1e3 / args.steps, ms / args.steps * 1e6 / w.cells),
+              file=sys.stderr, flush=True)
+    ms_per_step = float(np.median(windows))
     ns_pt = ms_per_step * 1e6 / w.cells
-    print("[bench] timed %d steps: %.3f ms/step (wall %.3f ms/step), %.3f ns/pt/step, %.2f V-cycles/step"
-          % (args.steps, ms_per_step, wall * 1e3 / args.steps, ns_pt, float(np.mean(vc))), file=sys.stderr,
-          flush=True)
+    kmean = float(np.mean(vc))
+    print("[bench] median of %d windows: %.3f ms/step, %.4f ns/pt/step, %.2f V-cycles/step"
+          % (args.windows, ms_per_step, ns_pt, kmean), file=sys.stderr, flush=True)
 
     roof = None
     if dominant is not None:
@@ -381,11 +447,24 @@ def main():
                 "body_box_cells": bcells}
         print("[bench] %s over the timed region: %d launches, %.1f us avg, %.0f GB/s algorithmic"
               % (dominant, cnt, avg_ms * 1e3, ach), file=sys.stderr, flush=True)
-
-    cpu = None
-    if not args.no_cpu_baseline:
-        print("[bench] timing the FP64 oracle on a bounded CPU sample", file=sys.stderr, flush=True)
-        cpu = run_cpu_baseline(args.workload)
+        # one fine PCG iteration (passes A + B) on the bytes its kernels need,
+        # durations from the breakdown steps
+        if "pcg_a" in kernels and "pcg_b" in kernels:
+            ba, bb = launch_bytes("pcg_a"), launch_bytes("pcg_b")
+            ta, tb = kernels["pcg_a"]["avg_us"], kernels["pcg_b"]["avg_us"]
+            gbs = (ba + bb) / ((ta + tb) * 1e-6) / 1e9
+            roof["pcg_iteration"] = {"bytes": ba + bb, "us": round(ta + tb, 2), "achieved": round(gbs, 1),
+                                     "frac": round(gbs / HBM_PEAK_GBS, 4),
+                                     "dense_model_bytes": model_bytes("pcg_a", w.ndim, cells, 4)
+                                     + model_bytes("pcg_b", w.ndim, cells, 4)}
+        # the whole step by the fixed algorithmic model at the measured V-cycles per step
+        per_cell = step_byte_model(w.ndim, body is not None, kmean)
+        gbs = per_cell * cells / (ms_per_step * 1e-3) / 1e9
+        roof["step"] = {"model_bytes_per_cell": round(per_cell, 1), "bytes": per_cell * cells,
+                        "vcycles_per_step": round(kmean, 3), "achieved": round(gbs, 1),
+                        "frac": round(gbs / HBM_PEAK_GBS, 4)}
+        print("[bench] whole step by the byte model: %.0f B/cell, %.0f GB/s, %.3f of peak"
+              % (per_cell, gbs, gbs / HBM_PEAK_GBS), file=sys.stderr, flush=True)
 
     out = {
         "metric": "ns per grid point per time step (FP32 BDIM step)",
@@ -394,6 +473,7 @@ def main():
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
+        "windows": args.windows,
         "ms_per_step": round(ms_per_step, 3),
         "higher_is_better": False,
         "scaling": "weak",
@@ -403,7 +483,9 @@ def main():
         "config": {"workload": w.name, "cells": w.cells, "Re": round(w.U[0] * w.L / w.nu, 1) if w.nu else None,
                    "mg_tol": w.tol, "moving_body": bool(body is not None and body.moving),
                    "convective_exit": w.convective_exit, "parallelism": "single GPU"},
-        "vcycles_per_step": round(float(np.mean(vc)), 3),
+        "windows_ms_per_step": [round(v, 3) for v in windows],
+        "vcycles_per_step": round(kmean, 3),
+        "vcycle_factor": round(float(np.exp(np.mean(np.log(factors)))), 4) if factors else None,
         "roofline": roof,
         "kernels": kernels,
         "cpu_baseline": cpu,

@@ -166,6 +166,7 @@ typedef struct {
   double t;             /* time after the step */
   double dt_next;       /* CFL step for the next call */
   int vcycles[2];       /* predictor / corrector multigrid V-cycles */
+  double res0_linf[2];  /* residual max-norms of the two solves before their first cycle (FP64) */
   double res_linf[2];   /* final residual max-norms of the two solves (FP64) */
   double res_l2[2];     /* final residual 2-norms over the active cells (FP64 sums) */
   double div_linf;      /* max |div u| over the active cells after the step (FP64) */

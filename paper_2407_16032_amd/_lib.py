@@ -55,7 +55,7 @@ BodyDesc._fields_ = [("kind", C.c_int), ("center", C.c_double * 3), ("radius", C
 
 class StepStats(C.Structure):
     _fields_ = [("dt", C.c_double), ("t", C.c_double), ("dt_next", C.c_double), ("vcycles", C.c_int * 2),
-                ("res_linf", C.c_double * 2), ("res_l2", C.c_double * 2), ("div_linf", C.c_double),
+                ("res0_linf", C.c_double * 2), ("res_linf", C.c_double * 2), ("res_l2", C.c_double * 2), ("div_linf", C.c_double),
                 ("converged", C.c_int)]
 
 

@@ -1810,6 +1810,8 @@ struct Impl : SimBase {
       st->dt_next = dt;
       st->vcycles[0] = s1.vcycles;
       st->vcycles[1] = s2.vcycles;
+      st->res0_linf[0] = s1.res0_linf;
+      st->res0_linf[1] = s2.res0_linf;
       st->res_linf[0] = s1.res_linf;
       st->res_linf[1] = s2.res_linf;
       st->res_l2[0] = s1.res_l2;

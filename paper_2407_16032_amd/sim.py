@@ -140,6 +140,7 @@ class Simulation:
         st = L.StepStats()
         L.check(self.lib.wl_step(self._h, 1 if remeasure else 0, C.byref(st)), "wl_step")
         return {"dt": st.dt, "t": st.t, "dt_next": st.dt_next, "vcycles": (st.vcycles[0], st.vcycles[1]),
+                "res0_linf": (st.res0_linf[0], st.res0_linf[1]),
                 "res_linf": (st.res_linf[0], st.res_linf[1]), "res_l2": (st.res_l2[0], st.res_l2[1]),
                 "div_linf": st.div_linf, "converged": bool(st.converged)}
 

@@ -70,3 +70,19 @@ def test_byte_model_invariants():
     assert kb("pcg_b", 0, flat=False, tiled=False) == 6 * CELLS * 4
     # the dense fixed model (stored q, all coefficients) is an upper bound
     assert bench.model_bytes("pcg_b", 3, CELLS, 4) >= kb("pcg_b", BOX)
+
+
+def test_step_byte_model_matches_the_fixed_model():
+    # 3-D with a body at k = 4 V-cycles: 4 (79 + 4 x 105.4) = 2001.6 bytes per cell
+    assert bench.step_byte_model(3, True, 4.0) == pytest.approx(2001.6)
+    assert bench.step_byte_model(3, False, 0.0) == pytest.approx(220.0)
+    assert bench.step_byte_model(2, True, 2.0) == pytest.approx(4 * (52 + 230.6))
+
+
+def test_cpu_baseline_reports_both_legs_and_the_core_count():
+    out = bench.run_cpu_baseline("circle2d")
+    assert out["kind"] == "oracle" and out["unit"] == "ns/point/step"
+    assert out["host_cpu_count"] == os.cpu_count()
+    assert 1 <= out["cores"] <= 16
+    assert out["single_core"]["cores"] == 1
+    assert out["value"] > 0 and out["single_core"]["value"] > 0
