@@ -240,6 +240,20 @@ wl_status wl_poisson_solve(wl_sim* sim, const void* rhs, void* x_inout, double t
  * strain rate of u interpolated to the cell centre. */
 wl_status wl_forces(wl_sim* sim, double f_pressure[3], double f_viscous[3]);
 
+/* wl_forces for callers that cannot allocate (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid allocation): the same force sums,
+ * with their per-block partials and totals in a fixed static device array of
+ * 11 x 2048 + 16 doubles (about 176 KiB, held by each GPU the library runs on
+ * until the process ends) instead of the simulation's workspace.  Allocates
+ * nothing (no device, pinned or host memory) and reads the 11 totals back into
+ * the simulation's pinned buffer.  The sums are added in a different fixed order
+ * than wl_forces, so the two agree to rounding.  Every call on one GPU shares
+ * that array: calls that overlap on one GPU (two host threads, or two streams in
+ * flight at once) race and must be serialised by the caller.  Synchronises the
+ * simulation's stream.  A force grid larger than the array returns
+ * WL_ERR_UNSUPPORTED (the grid is at most 2048 blocks, so this does not occur). */
+wl_status wl_forces_static(wl_sim* sim, double f_pressure[3], double f_viscous[3]);
+
 enum {
   WL_FIELD_U = 0,     /* velocity, ndim components */
   WL_FIELD_U0 = 1,    /* start-of-step velocity (after a step: the previous velocity) */

@@ -18,7 +18,7 @@ FIELDS = {"u": 0, "u0": 1, "f": 2, "V": 3, "mu0": 4, "mu1": 5, "p": 6, "x": 7, "
 
 # every symbol include/wlmi.h declares
 EXPORTS = ["wl_workspace_bytes", "wl_sim_create", "wl_sim_destroy", "wl_measure_body", "wl_step",
-           "wl_apply_bc", "wl_conv_diff", "wl_project", "wl_poisson_solve", "wl_forces", "wl_field",
+           "wl_apply_bc", "wl_conv_diff", "wl_project", "wl_poisson_solve", "wl_forces", "wl_forces_static", "wl_field",
            "wl_levels", "wl_set_time", "wl_get_time", "wl_sim_time", "wl_profile", "wl_profile_groups", "wl_profile_read", "wl_pg_set_weights",
            "wl_pg_get_weights", "wl_pg_mode", "wl_pg_forward", "wl_pg_train_step", "wl_pg_stats", "wl_body_update",
            "wl_body_box",
@@ -100,6 +100,8 @@ def load(path: str = LIB_PATH):
     lib.wl_poisson_solve.argtypes = [P, P, P, C.c_double, C.c_int, C.POINTER(SolveStats)]
     lib.wl_forces.restype = C.c_int
     lib.wl_forces.argtypes = [P, C.POINTER(C.c_double), C.POINTER(C.c_double)]
+    lib.wl_forces_static.restype = C.c_int
+    lib.wl_forces_static.argtypes = [P, C.POINTER(C.c_double), C.POINTER(C.c_double)]
     lib.wl_field.restype = C.c_int
     lib.wl_field.argtypes = [P, C.c_int, C.c_int, C.POINTER(P), C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
     lib.wl_levels.restype = C.c_int

@@ -2763,7 +2763,8 @@ __global__ void __launch_bounds__(kBlock) k_sumsq(Grid3 g, const T* r, double* p
 // sum n K, sum_active p, active count; the host combines them.
 template <typename T, int D>
 __global__ void __launch_bounds__(kBlock) k_forces(Grid3 g, BodyP b, Motion m, double eps, double nu,
-                                                   Vec3<T> u, const T* p, const T* iD, double* red) {
+                                                   Vec3<T> u, const T* p, const T* iD, double* part,
+                                                   int stride) {
 #pragma clang fp contract(off)
   const int total = g.n[0] * g.n[1] * ((D == 3) ? g.n[2] : 1);
   double fp[3] = {0, 0, 0}, fv[3] = {0, 0, 0}, nk[3] = {0, 0, 0}, ps = 0.0, pc = 0.0;
@@ -2810,17 +2811,26 @@ __global__ void __launch_bounds__(kBlock) k_forces(Grid3 g, BodyP b, Motion m, d
     const double sv = block_sum(fv[a]);
     const double sn = block_sum(nk[a]);
     if (threadIdx.x == 0) {
-      red[(size_t)(kSlotForce + a) * kMaxBlocks + blockIdx.x] = sp;
-      red[(size_t)(kSlotForce + 3 + a) * kMaxBlocks + blockIdx.x] = sv;
-      red[(size_t)(kSlotForce + 6 + a) * kMaxBlocks + blockIdx.x] = sn;
+      part[(size_t)a * stride + blockIdx.x] = sp;
+      part[(size_t)(3 + a) * stride + blockIdx.x] = sv;
+      part[(size_t)(6 + a) * stride + blockIdx.x] = sn;
     }
   }
   ps = block_sum(ps);
   pc = block_sum(pc);
   if (threadIdx.x == 0) {
-    red[(size_t)(kSlotForce + 9) * kMaxBlocks + blockIdx.x] = ps;
-    red[(size_t)(kSlotForce + 10) * kMaxBlocks + blockIdx.x] = pc;
+    part[(size_t)9 * stride + blockIdx.x] = ps;
+    part[(size_t)10 * stride + blockIdx.x] = pc;
   }
+}
+
+// Totals of rows of partials: block r sums part[r * stride + 0 .. n-1] into out[r]
+// (fixed order: strided per thread, then the block tree).
+__global__ void __launch_bounds__(kBlock) k_sum_rows(const double* part, int n, int stride, double* out) {
+  double v = 0.0;
+  for (int i = threadIdx.x; i < n; i += kBlock) v += part[(size_t)blockIdx.x * stride + i];
+  v = block_sum(v);
+  if (threadIdx.x == 0) out[blockIdx.x] = v;
 }
 
 template <typename T>

@@ -12,6 +12,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -21,6 +22,14 @@
 #include "wl_adjoint.hpp"
 
 using namespace wl;
+
+// Scratch of the allocation-free force entry point (wl_forces_static): the 11
+// per-block partials of the force sums (kGridStride blocks at most, the grid
+// of k_forces) and their 11 totals.  Each GPU the library runs on holds one copy
+// until the process ends; every call on that GPU shares it.
+constexpr int kScratchRows = 11;
+constexpr int kScratchDoubles = kScratchRows * kGridStride + 16;
+static __device__ __align__(256) double scratch[kScratchDoubles];
 
 namespace {
 
@@ -493,6 +502,8 @@ struct Profiler {
 // ---------------------------------------------------------------------------
 // the simulation object
 // ---------------------------------------------------------------------------
+constexpr int kHostPin = 32;  // doubles of pinned host memory per sim (scalar read-back)
+
 struct SimBase {
   virtual ~SimBase() {}
   virtual wl_status init() = 0;
@@ -503,6 +514,7 @@ struct SimBase {
   virtual wl_status project_cur(double w, wl_solve_stats* st) = 0;
   virtual wl_status poisson(const void* rhs, void* x, double tol, int itmax, wl_solve_stats* st) = 0;
   virtual wl_status forces(double fp[3], double fv[3]) = 0;
+  virtual wl_status forces_static(double* scr, double fp[3], double fv[3]) = 0;
   virtual wl_status field(int which, int level, void** ptr, int64_t shape[4], int64_t strides[4]) = 0;
   virtual wl_status pg_set_weights(const float* w) = 0;
   virtual wl_status pg_get_weights(float* w) = 0;
@@ -539,7 +551,8 @@ struct SimBase {
   Plan plan;
   hipStream_t stream = nullptr;
   double t = 0.0, dt = 0.25;
-  double* host_pin = nullptr;
+  double* host_pin = nullptr;  // kHostPin doubles of pinned host memory for read-back
+  int device = 0;               // the GPU current at creation
 };
 
 template <typename T, int D>
@@ -1828,7 +1841,8 @@ struct Impl : SimBase {
     Motion m{};
     host_motion(parts, t, m);
     WL_TIMED(WL_K_FORCES, (k_forces<T, D><<<nb[0], kBlock, 0, stream>>>(g[0], body, m, desc.eps, desc.nu,
-                                                                         v3(u[cur]), p, iD[0], red)));
+                                                                         v3(u[cur]), p, iD[0],
+                                                                         slot(kSlotForce), kMaxBlocks)));
     WL_HIP(hipGetLastError());
     std::vector<double> h((size_t)11 * kMaxBlocks);
     WL_HIP(hipMemcpyAsync(h.data(), slot(kSlotForce), h.size() * sizeof(double), hipMemcpyDeviceToHost, stream));
@@ -1853,6 +1867,32 @@ struct Impl : SimBase {
     for (int a = 0; a < 3; ++a) {
       fp[a] = -(tot[a] - pbar * tot[6 + a]);
       fv[a] = tot[3 + a];
+    }
+    return WL_OK;
+  }
+
+  // wl_forces with its partial sums in the caller-free scratch array (scr: that
+  // array's device address): partials, their totals on the device, one 11-double
+  // read-back into the pinned buffer.  No allocation of any kind.
+  wl_status forces_static(double* scr, double fp[3], double fv[3]) override {
+    for (int a = 0; a < 3; ++a) fp[a] = fv[a] = 0.0;
+    if (!has_body) return WL_OK;
+    if (nb[0] > kGridStride) return fail(WL_ERR_UNSUPPORTED, "force grid exceeds the static scratch");
+    Motion m{};
+    host_motion(parts, t, m);
+    double* tot = scr + (size_t)kScratchRows * kGridStride;
+    WL_TIMED(WL_K_FORCES, (k_forces<T, D><<<nb[0], kBlock, 0, stream>>>(g[0], body, m, desc.eps, desc.nu,
+                                                                         v3(u[cur]), p, iD[0], scr, kGridStride)));
+    WL_TIMED(WL_K_FORCES, (k_sum_rows<<<kScratchRows, kBlock, 0, stream>>>(scr, nb[0], kGridStride, tot)));
+    WL_HIP(hipGetLastError());
+    WL_HIP(hipMemcpyAsync(host_pin, tot, kScratchRows * sizeof(double), hipMemcpyDeviceToHost, stream));
+    WL_HIP(hipStreamSynchronize(stream));
+    prof.harvest();
+    const double* h = host_pin;
+    const double pbar = h[10] > 0 ? h[9] / h[10] : 0.0;
+    for (int a = 0; a < 3; ++a) {
+      fp[a] = -(h[a] - pbar * h[6 + a]);
+      fv[a] = h[3 + a];
     }
     return WL_OK;
   }
@@ -2119,6 +2159,26 @@ bool plan_consistent(const wl_sim_desc& d, const Plan& P) {
   return ok;
 }
 
+// Device address of `scratch` on the current GPU, looked up once per device with
+// that device current (the array's name is a host-side stand-in, never an address).
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_dev[kMaxDevices] = {};
+
+wl_status scratch_address(int dev, double** out) {
+  if (dev < 0 || dev >= kMaxDevices) return fail(WL_ERR_UNSUPPORTED, "device index beyond the scratch table");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_dev[dev]) {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr)
+      return fail(WL_ERR_HIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    g_scratch_dev[dev] = ptr;
+  }
+  *out = (double*)g_scratch_dev[dev];
+  return WL_OK;
+}
+
 }  // namespace
 
 struct wl_sim {
@@ -2168,9 +2228,13 @@ wl_status wl_sim_create(const wl_sim_desc* desc, const wl_body_desc* body, void*
     delete impl;
     return fail(WL_ERR_WORKSPACE_TOO_SMALL, "internal: workspace plan and field carving disagree");
   }
-  if (hipHostMalloc((void**)&impl->host_pin, 64, hipHostMallocDefault) != hipSuccess) {
+  if (hipGetDevice(&impl->device) != hipSuccess) {
     delete impl;
-    return fail(WL_ERR_HIP, "hipHostMalloc of the 64-byte read-back buffer failed");
+    return fail(WL_ERR_HIP, "hipGetDevice failed");
+  }
+  if (hipHostMalloc((void**)&impl->host_pin, kHostPin * sizeof(double), hipHostMallocDefault) != hipSuccess) {
+    delete impl;
+    return fail(WL_ERR_HIP, "hipHostMalloc of the read-back buffer failed");
   }
 
   hipError_t he = hipMemsetAsync(ws, 0, P.bytes, impl->stream);
@@ -2243,6 +2307,21 @@ wl_status wl_forces(wl_sim* sim, double f_pressure[3], double f_viscous[3]) {
   WL_SIM_CHECK(sim);
   if (!f_pressure || !f_viscous) return fail(WL_ERR_INVALID_ARG, "force outputs are NULL");
   return sim->impl->forces(f_pressure, f_viscous);
+}
+
+wl_status wl_forces_static(wl_sim* sim, double f_pressure[3], double f_viscous[3]) {
+  WL_SIM_CHECK(sim);
+  if (!f_pressure || !f_viscous) return fail(WL_ERR_INVALID_ARG, "force outputs are NULL");
+  // the sim's GPU is made current for the lookup and the launches, then restored
+  int cur = 0;
+  WL_HIP(hipGetDevice(&cur));
+  const int dev = sim->impl->device;
+  if (cur != dev) WL_HIP(hipSetDevice(dev));
+  double* scr = nullptr;
+  wl_status s = scratch_address(dev, &scr);
+  if (s == WL_OK) s = sim->impl->forces_static(scr, f_pressure, f_viscous);
+  if (cur != dev) (void)hipSetDevice(cur);
+  return s;
 }
 
 wl_status wl_field(wl_sim* sim, int which, int level, void** dev_ptr, int64_t shape[4], int64_t strides[4]) {

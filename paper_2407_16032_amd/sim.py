@@ -176,6 +176,13 @@ class Simulation:
         L.check(self.lib.wl_forces(self._h, fp, fv), "wl_forces")
         return list(fp)[:self.ndim], list(fv)[:self.ndim]
 
+    def forces_static(self):
+        """wl_forces through the allocation-free entry point (static device scratch)."""
+        fp = (C.c_double * 3)()
+        fv = (C.c_double * 3)()
+        L.check(self.lib.wl_forces_static(self._h, fp, fv), "wl_forces_static")
+        return list(fp)[:self.ndim], list(fv)[:self.ndim]
+
     # ------------------------------------------------------------- state
     def field(self, name: str, level: int = 0) -> torch.Tensor:
         """Zero-copy view (components, pz, py, nx+2) into the workspace."""
