@@ -185,6 +185,17 @@ def tgv_3d(N=128, Re=1600.0, steps=500, tol=1e-6) -> Workload:
                     L=N / (2 * math.pi))
 
 
+def tgv_sym_3d(N=512, Re=1600.0, steps=100, tol=1e-5) -> Workload:
+    """Taylor-Green vortex on the symmetric subdomain (one eighth of the periodic
+    box of side 2N): N^3 cells spanning [0, pi/kappa]^3 with kappa = pi / N, symmetry
+    (slip, U = 0) on every face, the paper's signs u = -sin cos cos, v = cos sin cos,
+    w = 0, U = 1, Re = U / (kappa nu)."""
+    kappa = math.pi / N
+    return Workload("tgvsym3d_%d" % N, (N, N, N), (0.0, 0.0, 0.0), 1.0 / (kappa * Re),
+                    periodic=(False, False, False), steps=steps, tol=tol, noise=0.0, init="tgv_sym",
+                    L=1.0 / kappa)
+
+
 def sphere_3d(n=(256, 128, 128), D=32.0, center=(64.0, 64.0, 64.0), Re=3700.0, steps=1000,
               tol=1e-6) -> Workload:
     return Workload("sphere3d_%dx%dx%d" % tuple(n), tuple(n), (1.0, 0.0, 0.0), D / Re,
@@ -287,17 +298,20 @@ def initial_velocity(w: Workload, seed: int = 0):
 
     'uniform': u = U + U[-1e-3, 1e-3)*|U| iid noise (seeded SplitMix64).
     'tgv': u = sin(kx)cos(ky)cos(kz), v = -cos(kx)sin(ky)cos(kz), w = 0, k = 2 pi / N.
+    'tgv_sym': the same mode with the opposite signs and k = pi / N (the grid is one
+    eighth of the periodic box).
     """
     shape = tuple(N + 2 for N in w.n)
     out = []
-    if w.init == "tgv":
-        k = 2 * math.pi / w.n[0]
+    if w.init in ("tgv", "tgv_sym"):
+        k = (math.pi if w.init == "tgv_sym" else 2 * math.pi) / w.n[0]
+        sg = -1.0 if w.init == "tgv_sym" else 1.0
         for i in range(w.ndim):
             X = face_coords(w.n, i)
             if i == 0:
-                f = np.sin(k * X[0]) * np.cos(k * X[1])
+                f = sg * np.sin(k * X[0]) * np.cos(k * X[1])
             elif i == 1:
-                f = -np.cos(k * X[0]) * np.sin(k * X[1])
+                f = -sg * np.cos(k * X[0]) * np.sin(k * X[1])
             else:
                 f = np.zeros(shape)
             if w.ndim == 3 and i < 2:
