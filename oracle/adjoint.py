@@ -50,6 +50,16 @@ def objective(w, xi, R, steps, window_start, dt_schedule=None, tol=1e-12, itmax=
     return np.mean(cds), dts
 
 
+def gradient_cfl(w, xi, R, steps, window_start, tol=1e-12):
+    """(J, dJ/dxi, dJ/dR) by complex step with the CFL time steps live: each step's
+    dt follows the perturbed velocity through the largest outflux, so the
+    derivative includes the dependence of the time steps on the flow."""
+    J, dts = objective(w, xi, R, steps, window_start, tol=tol)
+    Jx, _ = objective(w, xi + 1j * H_CS, R, steps, window_start, tol=tol)
+    JR, _ = objective(w, xi, R + 1j * H_CS, steps, window_start, tol=tol)
+    return float(np.real(J)), float(np.imag(Jx) / H_CS), float(np.imag(JR) / H_CS), dts
+
+
 def gradient(w, xi, R, steps, window_start, tol=1e-12):
     """(J, dJ/dxi, dJ/dR) of the FP64 oracle by complex step, time steps frozen."""
     J, dts = objective(w, xi, R, steps, window_start, tol=tol)

@@ -21,3 +21,24 @@ def test_complex_step_gradient_matches_central_differences():
     assert gR == pytest.approx((Jp - Jm) / (2 * h), rel=1e-7, abs=1e-9)
     # spinning changes the drag: the derivative is not trivially zero
     assert abs(gx) > 1e-4 and abs(gR) > 1e-4
+
+
+def test_complex_step_with_live_cfl_matches_central_differences():
+    # with the time steps following the flow (dt = 1/(max outflux + 5 nu) each step),
+    # the complex step carries the derivative through the argmax cell of the outflux;
+    # central differences of the live-CFL rollout agree, and the result differs from
+    # the frozen-schedule derivative
+    w = wlsynth.rotating_cylinder_2d(n=(48, 24), D=6.0, center=(14.0, 12.0), xi=0.8)
+    xi, R = 0.8, 3.0
+    steps, win = 12, 6
+    J, gx, gR, dts = A.gradient_cfl(w, xi, R, steps, win)
+    h = 1e-6
+    Jp, dp = A.objective(w, xi + h, R, steps, win)
+    Jm, dm = A.objective(w, xi - h, R, steps, win)
+    assert dp != dts  # the steps really move with xi
+    assert gx == pytest.approx((Jp - Jm) / (2 * h), rel=1e-6, abs=1e-9)
+    Jp, _ = A.objective(w, xi, R + h, steps, win)
+    Jm, _ = A.objective(w, xi, R - h, steps, win)
+    assert gR == pytest.approx((Jp - Jm) / (2 * h), rel=1e-6, abs=1e-9)
+    _, fx, fR, _ = A.gradient(w, xi, R, steps, win)
+    assert abs(gx - fx) > 1e-6 * abs(fx)
