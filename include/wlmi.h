@@ -341,6 +341,20 @@ wl_status wl_adj_forces(wl_sim* sim, const double dir[3], double weight, double*
  * corrector adjoint solves' statistics, forward_stats the recomputed step's. */
 wl_status wl_adj_step(wl_sim* sim, double tol, wl_step_stats* forward_stats, wl_solve_stats adjoint_stats[2]);
 
+/* wl_adj_step for a rollout whose time steps follow the CFL rule (the step is not
+ * frozen): as wl_adj_step, and also the adjoint of the step's dt, which enters
+ * through f~ = u0 + dt R - V in both stages and p = x / (w dt),
+ *   dt_bar = [<fbar_1, f~_1 - u0 + V> + <fbar_2, f~_2 - u0 + V> - <pbar, p^{n+1}>] / dt,
+ * written to *dt_bar (may be NULL).  dt_from_cfl != 0 states that dt_n was
+ * min(dt_max, 1/(sigma_max(u^n) + cfl_nu_coef nu)) of the state u^n (not dt0 and not
+ * set by the caller): then, when below dt_max, dt_bar (-dt^2) d sigma(I*)/du^n is
+ * added to the adjoint of u^n, I* the cell of the largest outflux (the first such cell
+ * in x-fastest order), the derivative of the CFL map on its active branch.  The
+ * oracle's reference is the complex step of the rollout with the steps live.
+ * Synchronises the stream once more than wl_adj_step. */
+wl_status wl_adj_step_cfl(wl_sim* sim, double tol, int dt_from_cfl, double* dt_bar, wl_step_stats* forward_stats,
+                          wl_solve_stats adjoint_stats[2]);
+
 /* Gradient of the objective with respect to the sphere's radius (at fixed
  * spin rate) and spin rate omega, from the accumulators: mu0 = mu0(d) and
  * mu1 = mu1(d) n with d = |x - c| - R, V = omega e_z x (x - c) where

@@ -22,7 +22,7 @@ EXPORTS = ["wl_workspace_bytes", "wl_sim_create", "wl_sim_destroy", "wl_measure_
            "wl_levels", "wl_set_time", "wl_get_time", "wl_sim_time", "wl_profile", "wl_profile_groups", "wl_profile_read", "wl_pg_set_weights",
            "wl_pg_get_weights", "wl_pg_mode", "wl_pg_forward", "wl_pg_train_step", "wl_pg_stats", "wl_body_update",
            "wl_body_box",
-           "wl_adj_reset", "wl_adj_forces", "wl_adj_step", "wl_adj_body_grad", "wl_last_error"]
+           "wl_adj_reset", "wl_adj_forces", "wl_adj_step", "wl_adj_step_cfl", "wl_adj_body_grad", "wl_last_error"]
 PG_PARAMS = 8673
 KERNELS = ["measure", "coef", "flux", "bdim", "bc", "exit", "divres", "pcg_a", "pcg_b", "restrict",
            "prolong", "project", "cfl", "forces", "coarse", "reduce", "pg_infer", "pg_train", "adjoint"]
@@ -143,6 +143,8 @@ def load(path: str = LIB_PATH):
     lib.wl_adj_forces.argtypes = [P, DP, C.c_double, DP]
     lib.wl_adj_step.restype = C.c_int
     lib.wl_adj_step.argtypes = [P, C.c_double, C.POINTER(StepStats), C.POINTER(SolveStats)]
+    lib.wl_adj_step_cfl.restype = C.c_int
+    lib.wl_adj_step_cfl.argtypes = [P, C.c_double, C.c_int, DP, C.POINTER(StepStats), C.POINTER(SolveStats)]
     lib.wl_adj_body_grad.restype = C.c_int
     lib.wl_adj_body_grad.argtypes = [P, DP, DP]
     lib.wl_last_error.restype = C.c_char_p

@@ -13,7 +13,9 @@ HIP library.
 Objective (rotating cylinder): J = mean over the window of the drag
 coefficient C_D = 2 F_x / (U^2 A_ref), A_ref = 2 R, for a circle of radius R
 spinning counter-clockwise at omega = xi U / R (xi = D omega / (2 U)).  The
-time steps are frozen to the schedule recorded by the first forward run.
+time steps are either frozen to the schedule recorded by the first forward run,
+or (``live_dt``) follow the CFL rule in every run, and the gradient then includes
+their dependence on the flow (``wl_adj_step_cfl``).
 """
 from __future__ import annotations
 
@@ -35,7 +37,7 @@ class RotatingCylinderDrag:
     """
 
     def __init__(self, w, u0, steps: int, window_start: int, ckpt: int = 20, prec: str = "f64",
-                 tol: float = 1e-12, itmax: int = 200, device="cuda:0"):
+                 tol: float = 1e-12, itmax: int = 200, device="cuda:0", live_dt: bool = False):
         self.w = w
         self.u0 = u0
         self.steps = int(steps)
@@ -48,6 +50,8 @@ class RotatingCylinderDrag:
         self.sim = Simulation(w.n, w.U, w.nu, self._body(1.0, float(w.body.radius)), periodic=w.periodic_mask(),
                               prec=prec, tol=tol, itmax=itmax, device=device, adjoint=True)
         self.dts: Optional[List[float]] = None
+        self.live_dt = bool(live_dt)
+        self.last_dts: Optional[List[float]] = None  # the schedule of the last forward run
         self.stats = {}
 
     def _body(self, xi: float, R: float):
@@ -61,7 +65,8 @@ class RotatingCylinderDrag:
         s.body_update(self._body(xi, R))
         s.set_velocity(self.u0)
         s.field("p").zero_()
-        s.set_time(0.0, self.dts[0] if self.dts is not None else s.desc.dt0)
+        frozen = self.dts is not None and not self.live_dt
+        s.set_time(0.0, self.dts[0] if frozen else s.desc.dt0)
 
     def _cd(self, R: float) -> float:
         fp, fv = self.sim.forces()
@@ -76,7 +81,7 @@ class RotatingCylinderDrag:
         cds = []
         for k in range(self.steps):
             t, dt = s.time()
-            if self.dts is not None:
+            if self.dts is not None and not self.live_dt:
                 dt = self.dts[k]
                 s.set_time(t, dt)
             if record and k % self.ckpt == 0:
@@ -87,6 +92,7 @@ class RotatingCylinderDrag:
                 cds.append(self._cd(R))
         if self.dts is None:
             self.dts = dts
+        self.last_dts = dts
         J = sum(cds) / len(cds)
         return (J, ckpts) if record else J
 
@@ -98,6 +104,7 @@ class RotatingCylinderDrag:
     def gradient(self, xi: float, R: float, J: float, ckpts):
         """(dJ/dxi, dJ/dR) by the reverse sweep over the checkpoints of value(record=True)."""
         s = self.sim
+        dts = self.last_dts if self.live_dt else self.dts
         s.body_update(self._body(xi, R))
         nwin = self.steps - self.win
         weight = 1.0 / (nwin * self.U ** 2 * R)  # dJ/dF_x of each window state
@@ -108,10 +115,10 @@ class RotatingCylinderDrag:
         for s0 in reversed(sorted(ckpts)):
             s1 = min(s0 + self.ckpt, self.steps)
             # recompute the segment's states s0 .. s1
-            s.load_state(ckpts[s0], self.dts[s0])
+            s.load_state(ckpts[s0], dts[s0])
             states = [s.save_state()]
             for n in range(s0, s1):
-                s.set_time(s.time()[0], self.dts[n])
+                s.set_time(s.time()[0], dts[n])
                 st = s.step()
                 fwd_cycles += sum(st["vcycles"])
                 states.append(s.save_state())
@@ -119,8 +126,9 @@ class RotatingCylinderDrag:
                 if n >= self.win:  # C_D of the state after step n
                     s.load_state(states[n + 1 - s0])
                     s.adj_forces(ex, weight)
-                s.load_state(states[n - s0], self.dts[n])
-                st = s.adj_step(self.tol)
+                s.load_state(states[n - s0], dts[n])
+                # step 0 starts from dt0; every later step's dt is the CFL step of its state
+                st = s.adj_step_cfl(n > 0, self.tol) if self.live_dt else s.adj_step(self.tol)
                 adj_cycles += sum(st["adj_vcycles"])
                 fwd_cycles += sum(st["vcycles"])
         dR_w, dW = s.adj_body_grad()

@@ -424,4 +424,116 @@ __global__ void __launch_bounds__(kBlock) k_adj_body(Grid3 g, BodyP b, Motion m,
   }
 }
 
+// ---------------------------------------------------------------------------
+// Time-step derivative (steps whose dt follows the CFL rule).  Within one step
+// dt enters through f~ = u0 + dt R - V in both stages and through p = x / (w dt)
+// after the corrector (w = 1/2), so
+//   dtbar = [<fbar_1, f~_1 - u0 + V> + <fbar_2, f~_2 - u0 + V>] / dt - <pbar, p> / dt,
+// and dt_n = 1 / (sigma(I*) + 5 nu) of the state u^n, I* the cell of the largest
+// outflux sigma = sum_a max(0, u_a[I+e_a]) + max(0, -u_a[I]) (the first such cell
+// in x-fastest order), adds dtbar (-dt^2) d sigma(I*)/du to ubar of u^n.
+// ---------------------------------------------------------------------------
+// per-block partials of the sum over padded faces of fb . (f - u0 + V)
+template <typename T, int D>
+__global__ void __launch_bounds__(kBlock) k_adj_dt_flux(Grid3 g, Vec3<T> fb, Vec3<T> f, Vec3<T> u0, Vec3<T> V,
+                                                        double* part) {
+  const int P0 = g.n[0] + 2, P1 = g.n[1] + 2, P2 = (D == 3) ? g.n[2] + 2 : 1;
+  const int total = P0 * P1 * P2;
+  double s = 0.0;
+  for (int lin = blockIdx.x * kBlock + threadIdx.x; lin < total; lin += gridDim.x * kBlock) {
+    const int I0 = lin % P0, I1 = (lin / P0) % P1, I2 = (D == 3) ? lin / (P0 * P1) : 0;
+    const int idx = I0 + I1 * g.s[1] + I2 * g.s[2];
+    for (int c = 0; c < D; ++c) {
+      const double dR = double(f.c[c][idx]) - double(u0.c[c][idx]) + double(V.c[c][idx]);
+      s += double(fb.c[c][idx]) * dR;
+    }
+  }
+  s = block_sum(s);
+  if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+// per-block partials of the sum over interior cells of pb p
+template <typename T, int D>
+__global__ void __launch_bounds__(kBlock) k_adj_dt_press(Grid3 g, const T* pb, const T* p, double* part) {
+  const int total = g.n[0] * g.n[1] * ((D == 3) ? g.n[2] : 1);
+  double s = 0.0;
+  for (int lin = blockIdx.x * kBlock + threadIdx.x; lin < total; lin += gridDim.x * kBlock) {
+    int I[3], idx;
+    cell_of<D>(g, lin, I, idx);
+    s += double(pb[idx]) * double(p[idx]);
+  }
+  s = block_sum(s);
+  if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+// larger (v, i) pair: the larger value, on equal values the smaller index
+__device__ __forceinline__ bool arg_better(double v, double i, double bv, double bi) {
+  return v > bv || (v == bv && i < bi);
+}
+
+// per-block largest outflux over interior cells and its cell (linear index, x fastest)
+template <typename T, int D>
+__global__ void __launch_bounds__(kBlock) k_cfl_arg(Grid3 g, Vec3<T> u, double* part_v, double* part_i) {
+  const int total = g.n[0] * g.n[1] * ((D == 3) ? g.n[2] : 1);
+  double bv = -1.0, bi = 0.0;
+  for (int lin = blockIdx.x * kBlock + threadIdx.x; lin < total; lin += gridDim.x * kBlock) {
+    int I[3], idx, op[3], om[3];
+    cell_of<D>(g, lin, I, idx);
+    nbr_offsets<D>(g, I, op, om);
+    T s = T(0);
+    for (int a = 0; a < D; ++a) s = s + fmax(T(0), u.c[a][idx + op[a]]) + fmax(T(0), -u.c[a][idx]);
+    if (arg_better(double(s), double(lin), bv, bi)) {
+      bv = double(s);
+      bi = double(lin);
+    }
+  }
+  __shared__ double sv[kBlock], si[kBlock];
+  sv[threadIdx.x] = bv;
+  si[threadIdx.x] = bi;
+  __syncthreads();
+  for (int h = kBlock / 2; h > 0; h >>= 1) {
+    if (threadIdx.x < h && arg_better(sv[threadIdx.x + h], si[threadIdx.x + h], sv[threadIdx.x], si[threadIdx.x])) {
+      sv[threadIdx.x] = sv[threadIdx.x + h];
+      si[threadIdx.x] = si[threadIdx.x + h];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    part_v[blockIdx.x] = sv[0];
+    part_i[blockIdx.x] = si[0];
+  }
+}
+
+// One block: the argmax cell from the partials, then ubar += c d sigma/du at it
+// (c = dtbar (-dt^2)).
+template <typename T, int D>
+__global__ void __launch_bounds__(kBlock) k_adj_cfl(Grid3 g, Vec3<T> u, Vec3<T> ub, const double* part_v,
+                                                    const double* part_i, int n, double c) {
+  double bv = -1.0, bi = 0.0;
+  for (int k = threadIdx.x; k < n; k += kBlock)
+    if (arg_better(part_v[k], part_i[k], bv, bi)) {
+      bv = part_v[k];
+      bi = part_i[k];
+    }
+  __shared__ double sv[kBlock], si[kBlock];
+  sv[threadIdx.x] = bv;
+  si[threadIdx.x] = bi;
+  __syncthreads();
+  for (int h = kBlock / 2; h > 0; h >>= 1) {
+    if (threadIdx.x < h && arg_better(sv[threadIdx.x + h], si[threadIdx.x + h], sv[threadIdx.x], si[threadIdx.x])) {
+      sv[threadIdx.x] = sv[threadIdx.x + h];
+      si[threadIdx.x] = si[threadIdx.x + h];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x != 0) return;
+  int I[3], idx, op[3], om[3];
+  cell_of<D>(g, (int)si[0], I, idx);
+  nbr_offsets<D>(g, I, op, om);
+  for (int a = 0; a < D; ++a) {
+    if (u.c[a][idx + op[a]] > T(0)) ub.c[a][idx + op[a]] += T(c);
+    if (-u.c[a][idx] > T(0)) ub.c[a][idx] -= T(c);
+  }
+}
+
 }  // namespace wl

@@ -528,6 +528,8 @@ struct SimBase {
   virtual wl_status adj_reset() = 0;
   virtual wl_status adj_forces(const double dir[3], double weight, double* value) = 0;
   virtual wl_status adj_step(double tol, wl_step_stats* fst, wl_solve_stats* ast) = 0;
+  virtual wl_status adj_step_cfl(double tol, int from_cfl, double* dtbar, wl_step_stats* fst,
+                                 wl_solve_stats* ast) = 0;
   virtual wl_status adj_body_grad(double* dR, double* dW) = 0;
   virtual wl_status profile(uint32_t groups) {
     if (groups) {
@@ -1992,6 +1994,26 @@ struct Impl : SimBase {
   }
 
   wl_status adj_step(double tol, wl_step_stats* fst, wl_solve_stats* ast) override {
+    return adj_step_impl(tol, false, 0, nullptr, fst, ast);
+  }
+
+  wl_status adj_step_cfl(double tol, int from_cfl, double* dtbar, wl_step_stats* fst,
+                         wl_solve_stats* ast) override {
+    return adj_step_impl(tol, true, from_cfl, dtbar, fst, ast);
+  }
+
+  // sum of per-block partials into red[kSlotForce*kMaxBlocks + k] (a slot the
+  // multigrid solves never touch), k = 0..2
+  void adj_total(const double* part, int n, int k) {
+    WL_TIMED(WL_K_ADJOINT, (k_finalize2<<<1, kFinalizeThreads, 0, stream>>>(part, 0, nullptr, 0, n,
+                                                                            slot(kSlotForce) + k, nullptr)));
+  }
+
+  // Reverse of one step (see wl_adj_step).  want_dt: also the adjoint of the step's
+  // dt (returned in dtbar); from_cfl: dt came from the CFL rule of u^n, whose
+  // transpose then adds dtbar d dt/du^n to the adjoint of u^n.
+  wl_status adj_step_impl(double tol, bool want_dt, int from_cfl, double* dtbar, wl_step_stats* fst,
+                          wl_solve_stats* ast) {
     wl_status s = adj_require();
     if (s != WL_OK) return s;
     const double dts = dt;  // the (frozen) step of the recomputed forward
@@ -2005,6 +2027,10 @@ struct Impl : SimBase {
     T* const* ua = au[1 - acur];  // becomes the adjoint of u^n
     const int hb = has_body ? 1 : 0;
     for (int k = 0; k < D; ++k) fill_field(ua[k], T(0));
+    if (want_dt) {  // <pbar, p> of the state n+1, before the corrector's transpose consumes pbar
+      WL_TIMED(WL_K_ADJOINT, (k_adj_dt_press<T, D><<<nb[0], kBlock, 0, stream>>>(g[0], apb, p, slot(kSlotCfl))));
+      adj_total(slot(kSlotCfl), nb[0], 0);
+    }
     // corrector: bc, projection (w = 1/2, pbar), bc, blend (average), flux at the predictor state
     adj_bct(ub);
     if ((s = adj_project(ub, 0.5 * dts, recX2, true, atol, ast ? &ast[1] : nullptr)) != WL_OK) return s;
@@ -2012,6 +2038,11 @@ struct Impl : SimBase {
     WL_TIMED(WL_K_ADJOINT, (k_adj_bdim<T, D, 1><<<dim3(nb_face, D), kBlock, 0, stream>>>(
                                g[0], v3(ub), v3(ft), v3(mu0), v9(mu1), v3(afb), v3(aVb), v3(am0b), v9(am1b),
                                v3(aup), hb)));
+    if (want_dt) {  // <fbar_2, f~_2 - u0 + V>
+      WL_TIMED(WL_K_ADJOINT, (k_adj_dt_flux<T, D><<<nb_face, kBlock, 0, stream>>>(g[0], v3(afb), v3(ft), v3(A),
+                                                                                   v3(V), slot(kSlotCfl))));
+      adj_total(slot(kSlotCfl), nb_face, 1);
+    }
     WL_TIMED(WL_K_ADJOINT, (k_adj_flux<T, D><<<dim3(nb_face, D), kBlock, 0, stream>>>(
                                g[0], v3(recB), v3(afb), v3(aup), v3(ua), v3(aVb), T(dts), T(desc.nu), hb)));
     // predictor: bc, projection (w = 1), bc, blend, flux at u^n
@@ -2021,9 +2052,29 @@ struct Impl : SimBase {
     WL_TIMED(WL_K_ADJOINT, (k_adj_bdim<T, D, 0><<<dim3(nb_face, D), kBlock, 0, stream>>>(
                                g[0], v3(aup), v3(recF), v3(mu0), v9(mu1), v3(afb), v3(aVb), v3(am0b), v9(am1b),
                                v3(aup), hb)));
+    if (want_dt) {  // <fbar_1, f~_1 - u0 + V>
+      WL_TIMED(WL_K_ADJOINT, (k_adj_dt_flux<T, D><<<nb_face, kBlock, 0, stream>>>(g[0], v3(afb), v3(recF), v3(A),
+                                                                                   v3(V), slot(kSlotCfl))));
+      adj_total(slot(kSlotCfl), nb_face, 2);
+    }
     WL_TIMED(WL_K_ADJOINT, (k_adj_flux<T, D><<<dim3(nb_face, D), kBlock, 0, stream>>>(
                                g[0], v3(A), v3(afb), v3(ua), v3(ua), v3(aVb), T(dts), T(desc.nu), hb)));
     WL_HIP(hipGetLastError());
+    if (want_dt) {
+      WL_HIP(hipMemcpyAsync(host_pin, slot(kSlotForce), 3 * sizeof(double), hipMemcpyDeviceToHost, stream));
+      WL_HIP(hipStreamSynchronize(stream));
+      prof.harvest();
+      const double db = (host_pin[1] + host_pin[2]) / dts - host_pin[0] / dts;
+      if (dtbar) *dtbar = db;
+      // dt_n = 1 / (sigma(I*) + 5 nu) of u^n when below dt_max
+      if (from_cfl && dts < desc.dt_max) {
+        WL_TIMED(WL_K_ADJOINT, (k_cfl_arg<T, D><<<nb[0], kBlock, 0, stream>>>(g[0], v3(A), slot(kSlotCfl),
+                                                                               slot(kSlotDiv))));
+        WL_TIMED(WL_K_ADJOINT, (k_adj_cfl<T, D><<<1, kBlock, 0, stream>>>(g[0], v3(A), v3(ua), slot(kSlotCfl),
+                                                                          slot(kSlotDiv), nb[0], -db * dts * dts)));
+        WL_HIP(hipGetLastError());
+      }
+    }
     acur = 1 - acur;
     return WL_OK;
   }
@@ -2433,6 +2484,13 @@ wl_status wl_adj_step(wl_sim* sim, double tol, wl_step_stats* forward_stats, wl_
   WL_SIM_CHECK(sim);
   if (!(tol >= 0.0)) return fail(WL_ERR_INVALID_ARG, "tol must be >= 0");
   return sim->impl->adj_step(tol, forward_stats, adjoint_stats);
+}
+
+wl_status wl_adj_step_cfl(wl_sim* sim, double tol, int dt_from_cfl, double* dt_bar, wl_step_stats* forward_stats,
+                          wl_solve_stats adjoint_stats[2]) {
+  WL_SIM_CHECK(sim);
+  if (!(tol >= 0.0)) return fail(WL_ERR_INVALID_ARG, "tol must be >= 0");
+  return sim->impl->adj_step_cfl(tol, dt_from_cfl, dt_bar, forward_stats, adjoint_stats);
 }
 
 wl_status wl_adj_body_grad(wl_sim* sim, double* dJ_dradius, double* dJ_dspin) {

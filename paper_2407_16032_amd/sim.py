@@ -317,6 +317,17 @@ class Simulation:
                 "adj_vcycles": (ast[0].vcycles, ast[1].vcycles),
                 "adj_res_linf": (ast[0].res_linf, ast[1].res_linf)}
 
+    def adj_step_cfl(self, dt_from_cfl: bool, tol: float = 0.0) -> dict:
+        """Reverse of one step whose dt follows the CFL rule; also returns dt_bar."""
+        fst = L.StepStats()
+        ast = (L.SolveStats * 2)()
+        dtb = C.c_double()
+        L.check(self.lib.wl_adj_step_cfl(self._h, float(tol), 1 if dt_from_cfl else 0, C.byref(dtb), C.byref(fst),
+                                         ast), "wl_adj_step_cfl")
+        return {"dt": fst.dt, "vcycles": (fst.vcycles[0], fst.vcycles[1]), "dt_bar": dtb.value,
+                "adj_vcycles": (ast[0].vcycles, ast[1].vcycles),
+                "adj_res_linf": (ast[0].res_linf, ast[1].res_linf)}
+
     def adj_body_grad(self):
         dR = C.c_double()
         dW = C.c_double()

@@ -208,3 +208,41 @@ def test_rotcyl_512x256_gradient_matches_oracle():
     assert gx == pytest.approx(ref["dJ_dxi"], rel=1e-6, abs=1e-9)
     assert gR == pytest.approx(ref["dJ_dR"], rel=1e-6, abs=1e-9)
     prob.sim.close()
+
+
+@pytest.mark.parametrize("ckpt", [1, 5])
+def test_adjoint_with_live_time_steps_matches_oracle(ckpt):
+    # time steps follow the CFL rule in every run: the gradient includes the steps'
+    # dependence on the flow (wl_adj_step_cfl), against the oracle's complex step of
+    # the live-CFL rollout
+    from paper_2407_16032_amd.adjoint import RotatingCylinderDrag
+    w = _case()
+    J0, gx0, gR0, dts0 = OA.gradient_cfl(w, XI, R, STEPS, WIN)
+    _say("live-dt adjoint vs complex step, ckpt", ckpt)
+    prob = RotatingCylinderDrag(w, wlsynth.initial_velocity(w), STEPS, WIN, ckpt=ckpt, prec="f64", tol=1e-12,
+                                live_dt=True)
+    J, gx, gR = prob.value_and_grad(XI, R)
+    _say("  J %.12g / %.12g  dxi %.10g / %.10g  dR %.10g / %.10g" % (J, J0, gx, gx0, gR, gR0))
+    np.testing.assert_allclose(prob.last_dts, dts0, rtol=1e-10)
+    assert J == pytest.approx(J0, rel=1e-10)
+    assert gx == pytest.approx(gx0, rel=1e-6, abs=1e-10)
+    assert gR == pytest.approx(gR0, rel=1e-6, abs=1e-10)
+    # and it is not the frozen-schedule derivative
+    _, fx, _, _ = OA.gradient(w, XI, R, STEPS, WIN)
+    assert abs(gx - fx) > 1e-4 * abs(fx)
+    prob.sim.close()
+
+
+def test_adjoint_with_live_time_steps_matches_gpu_central_differences():
+    from paper_2407_16032_amd.adjoint import RotatingCylinderDrag
+    w = _case()
+    prob = RotatingCylinderDrag(w, wlsynth.initial_velocity(w), STEPS, WIN, ckpt=4, prec="f64", tol=1e-12,
+                                live_dt=True)
+    J, gx, gR = prob.value_and_grad(XI, R)
+    h = 1e-6
+    fx = (prob.value(XI + h, R) - prob.value(XI - h, R)) / (2 * h)
+    fR = (prob.value(XI, R + h) - prob.value(XI, R - h)) / (2 * h)
+    _say("  live dt: dxi %.10g fd %.10g   dR %.10g fd %.10g" % (gx, fx, gR, fR))
+    assert gx == pytest.approx(fx, rel=1e-5, abs=1e-8)
+    assert gR == pytest.approx(fR, rel=1e-5, abs=1e-8)
+    prob.sim.close()
