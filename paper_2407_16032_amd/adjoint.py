@@ -12,7 +12,9 @@ HIP library.
 
 Objective (rotating cylinder): J = mean over the window of the drag
 coefficient C_D = 2 F_x / (U^2 A_ref), A_ref = 2 R, for a circle of radius R
-spinning counter-clockwise at omega = xi U / R (xi = D omega / (2 U)).  The
+spinning counter-clockwise at omega = xi U / R (xi = D omega / (2 U)); or
+(``objective="lift_to_drag"``) the Magnus lift efficiency J = -mean C_L / mean C_D
+(C_L = 2 F_y / (U^2 A_ref); counter-clockwise spin in a +x stream lifts toward -y).  The
 time steps are either frozen to the schedule recorded by the first forward run,
 or (``live_dt``) follow the CFL rule in every run, and the gradient then includes
 their dependence on the flow (``wl_adj_step_cfl``).
@@ -37,7 +39,8 @@ class RotatingCylinderDrag:
     """
 
     def __init__(self, w, u0, steps: int, window_start: int, ckpt: int = 20, prec: str = "f64",
-                 tol: float = 1e-12, itmax: int = 200, device="cuda:0", live_dt: bool = False):
+                 tol: float = 1e-12, itmax: int = 200, device="cuda:0", live_dt: bool = False,
+                 objective: str = "drag"):
         self.w = w
         self.u0 = u0
         self.steps = int(steps)
@@ -51,6 +54,10 @@ class RotatingCylinderDrag:
                               prec=prec, tol=tol, itmax=itmax, device=device, adjoint=True)
         self.dts: Optional[List[float]] = None
         self.live_dt = bool(live_dt)
+        if objective not in ("drag", "lift_to_drag"):
+            raise ValueError("objective must be 'drag' or 'lift_to_drag'")
+        self.objective = objective
+        self.means = (0.0, 0.0)  # window means of C_D and C_L of the last forward run
         self.last_dts: Optional[List[float]] = None  # the schedule of the last forward run
         self.stats = {}
 
@@ -68,9 +75,10 @@ class RotatingCylinderDrag:
         frozen = self.dts is not None and not self.live_dt
         s.set_time(0.0, self.dts[0] if frozen else s.desc.dt0)
 
-    def _cd(self, R: float) -> float:
+    def _coefs(self, R: float):
         fp, fv = self.sim.forces()
-        return 2.0 * (fp[0] + fv[0]) / (self.U ** 2 * 2.0 * R)
+        q = self.U ** 2 * 2.0 * R
+        return 2.0 * (fp[0] + fv[0]) / q, 2.0 * (fp[1] + fv[1]) / q
 
     def value(self, xi: float, R: float, record: bool = False):
         """J and, if ``record``, the checkpoints of the run (dict step -> state)."""
@@ -78,7 +86,7 @@ class RotatingCylinderDrag:
         self._start(xi, R)
         ckpts = {}
         dts = []
-        cds = []
+        cds, cls = [], []
         for k in range(self.steps):
             t, dt = s.time()
             if self.dts is not None and not self.live_dt:
@@ -89,11 +97,15 @@ class RotatingCylinderDrag:
             dts.append(dt)
             s.step()
             if k >= self.win:
-                cds.append(self._cd(R))
+                cd, cl = self._coefs(R)
+                cds.append(cd)
+                cls.append(cl)
         if self.dts is None:
             self.dts = dts
         self.last_dts = dts
-        J = sum(cds) / len(cds)
+        mcd, mcl = sum(cds) / len(cds), sum(cls) / len(cls)
+        self.means = (mcd, mcl)
+        J = mcd if self.objective == "drag" else -mcl / mcd
         return (J, ckpts) if record else J
 
     def value_and_grad(self, xi: float, R: float):
@@ -107,8 +119,12 @@ class RotatingCylinderDrag:
         dts = self.last_dts if self.live_dt else self.dts
         s.body_update(self._body(xi, R))
         nwin = self.steps - self.win
-        weight = 1.0 / (nwin * self.U ** 2 * R)  # dJ/dF_x of each window state
-        ex = (1.0, 0.0, 0.0)
+        weight = 1.0 / (nwin * self.U ** 2 * R)  # d(mean C)/dF of each window state
+        if self.objective == "drag":
+            ex = (1.0, 0.0, 0.0)
+        else:  # J = -Lbar / Dbar: dJ/dCD_k = (Lbar / Dbar^2) / n, dJ/dCL_k = -(1 / Dbar) / n
+            mcd, mcl = self.means
+            ex = (mcl / mcd ** 2, -1.0 / mcd, 0.0)
         s.adj_reset()
         adj_cycles = 0
         fwd_cycles = 0
@@ -134,7 +150,8 @@ class RotatingCylinderDrag:
         dR_w, dW = s.adj_body_grad()
         omega = xi * self.U / R
         dxi = dW * self.U / R
-        dR = dR_w - dW * omega / R - J / R
+        # the drag's reference area 2R gives the direct term -J/R; the ratio has none
+        dR = dR_w - dW * omega / R - (J / R if self.objective == "drag" else 0.0)
         self.stats = {"adj_vcycles": adj_cycles, "recompute_vcycles": fwd_cycles}
         return dxi, dR
 
