@@ -87,6 +87,12 @@ typedef struct {
                             only.  The levels of <= 4096 cells run the single-workgroup
                             bottom solve in every case.  The arithmetic is the same; sums
                             differ in rounding order only. [0] */
+  int reduce_mode;       /* how the flat launches of the large 3-D levels total their
+                            per-block partial sums: 0 = automatic (up to 256 blocks the
+                            consumer kernels add them; more: a separate totalling launch,
+                            in two stages above 16384 partials), 1 = always a separate
+                            single-stage launch, 2 = always two stages.  Same arithmetic,
+                            sums in a different fixed order. [0] */
 } wl_sim_desc;
 
 typedef enum {

@@ -99,6 +99,7 @@ wl_status validate_and_default(const wl_sim_desc* in, wl_sim_desc* d) {
     return fail(WL_ERR_INVALID_ARG, "eps, dt0, dt_max, mg_tol must be > 0 and mg_itmax >= 1");
   if (d->pcg_iters < 1 || d->pcg_iters > kMaxPcg) return fail(WL_ERR_INVALID_ARG, "pcg_iters must be in [1, 15]");
   if (d->solver_path < 0 || d->solver_path > 3) return fail(WL_ERR_INVALID_ARG, "solver_path must be in [0, 3]");
+  if (d->reduce_mode < 0 || d->reduce_mode > 2) return fail(WL_ERR_INVALID_ARG, "reduce_mode must be in [0, 2]");
   if (d->convective_exit) {
     if (d->periodic_mask & 1u) return fail(WL_ERR_INVALID_ARG, "convective exit needs a non-periodic x axis");
     if (d->U[0] == 0.0) return fail(WL_ERR_INVALID_ARG, "convective exit needs U[0] != 0");
@@ -1102,7 +1103,7 @@ struct Impl : SimBase {
   // there are many (a single block would wait on each load in turn).
   void reduce_wide(const double* a, int a_max, const double* b, int b_max, int n, int sa, int sb) {
     double* out_b = sb >= 0 ? slot(sb) : nullptr;
-    if (n > 16 * kFinalizeThreads) {
+    if (n > 16 * kFinalizeThreads || desc.reduce_mode == 2) {
       double* ta = wide + 4 * wide_n;
       double* tb = ta + kFinalizeStage;
       WL_TIMED(WL_K_REDUCE, (k_finalize2<<<kFinalizeStage, kFinalizeThreads, 0, stream>>>(
@@ -1136,7 +1137,7 @@ struct Impl : SimBase {
     const int kidA = l == 0 ? WL_K_PCG_A : WL_K_COARSE, kidB = l == 0 ? WL_K_PCG_B : WL_K_COARSE;
     const int nf = (int)nflat[l];
     // a flat level with few blocks leaves its partials in the slots, as the tiles do
-    const bool direct = nf > 0 && nf <= kFlatDirectMax;
+    const bool direct = nf > 0 && nf <= kFlatDirectMax && desc.reduce_mode == 0;
     collapse(kSlotSumR, 0, kSlotCnt, 0);
     for (int k = 0; k < K; ++k) {
       const int wr = k < K - 1 ? 1 : 0, wm = (fine && k == K - 1) ? 1 : 0;
@@ -1299,7 +1300,7 @@ struct Impl : SimBase {
   void vcycle(int l) {
     if (nflat[l + 1] > 0) {
       const int nf = (int)nflat[l + 1];
-      const bool direct = nf <= kFlatDirectMax;
+      const bool direct = nf <= kFlatDirectMax && desc.reduce_mode == 0;
       double* const psum = direct ? slot(kSlotSumR) : wide;
       double* const pcnt = direct ? slot(kSlotCnt) : wide + wide_n;
       if (desc.periodic_mask)
@@ -1342,7 +1343,7 @@ struct Impl : SimBase {
     }
     if (nflat[l] > 0) {
       const int nf = (int)nflat[l];
-      const bool direct = nf <= kFlatDirectMax;
+      const bool direct = nf <= kFlatDirectMax && desc.reduce_mode == 0;
       double* const psum = direct ? slot(kSlotSumR) : wide;
       double* const pcnt = direct ? slot(kSlotCnt) : wide + wide_n;
       if (desc.periodic_mask)
@@ -1442,7 +1443,7 @@ struct Impl : SimBase {
     // array without the fields' front padding takes the generic kernel
     const bool aligned = rhs == nullptr || (reinterpret_cast<uintptr_t>(rhs + 1) % 16) == 0;
     if (nf > 0 && aligned) {
-      const bool direct = nf <= kFlatDirectMax;
+      const bool direct = nf <= kFlatDirectMax && desc.reduce_mode == 0;
       double* const pmax = direct ? slot(kSlotRmax) : wide;
       double* const psum = direct ? slot(kSlotSumR) : wide + wide_n;
       double* const pcnt = direct ? slot(kSlotCnt) : wide + 2 * wide_n;

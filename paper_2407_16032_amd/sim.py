@@ -78,7 +78,8 @@ class Simulation:
                  eps: float = 1.0, dt0: float = 0.25, dt_max: float = 10.0, cfl_nu: float = 5.0,
                  tol: float = 1e-6, itmax: int = 32, pcg_iters: int = 6, device="cuda:0",
                  stream: Optional[torch.cuda.Stream] = None, learned_guess: bool = False,
-                 adjoint: bool = False, solver_path: str = "auto", L_ref: float = 1.0):
+                 adjoint: bool = False, solver_path: str = "auto", L_ref: float = 1.0,
+                 reduce_mode: str = "auto"):
         self.lib = L.load()
         nd = len(n)
         d = L.SimDesc()
@@ -96,6 +97,7 @@ class Simulation:
         d.learned_guess = 1 if learned_guess else 0
         d.adjoint = 1 if adjoint else 0
         d.solver_path = {"auto": 0, "tiles": 1, "flat": 2, "generic": 3}[solver_path]
+        d.reduce_mode = {"auto": 0, "single": 1, "two_stage": 2}[reduce_mode]
         self.desc = d
         self.ndim = nd
         self.n = tuple(int(v) for v in n)

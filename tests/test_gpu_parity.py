@@ -461,3 +461,29 @@ def test_coefficients_are_body_free_outside_the_body_box(name):
                 for comp in range(f.shape[0]):
                     assert np.all(f[comp][m] == 0.0), (fname, comp)
     gpu.close()
+
+
+@pytest.mark.parametrize("mode", ["single", "two_stage", "auto"])
+@pytest.mark.parametrize("name", ["tgv3d", "sphere3d"])
+def test_one_step_fp64_every_partial_sum_path(name, mode):
+    # the flat levels' per-block partial sums totalled by one separate launch or by
+    # two (forced on these small grids) and the default (the consumers add them):
+    # the same step to FP64 rounding and the same V-cycle counts
+    _say("reduce path", name, mode)
+    w = CASES[name]
+    from paper_2407_16032_amd import Simulation
+    u0 = wlsynth.initial_velocity(w, seed=0)
+    body = w.body if w.body.kind != "none" else None
+    ref = oracle.Sim(w.n, w.U, w.nu, body, periodic=w.periodic_mask(), convective_exit=w.convective_exit,
+                     tol=1e-13, itmax=200)
+    ref.set_velocity(u0)
+    gpu = Simulation(w.n, w.U, w.nu, body, periodic=w.periodic_mask(), convective_exit=w.convective_exit,
+                     prec="f64", tol=1e-13, itmax=200, device="cuda:0", reduce_mode=mode)
+    gpu.set_velocity(u0)
+    st_r = ref.step()
+    st_g = gpu.step()
+    err = rel_l2(gpu.get("u"), ref.u, ref.grid)
+    _say("  rel-L2", err, st_g["vcycles"], st_r["vcycles"])
+    assert err <= FP64_STEP, err
+    assert all(abs(a - b) <= 1 for a, b in zip(st_g["vcycles"], st_r["vcycles"]))
+    gpu.close()
