@@ -284,8 +284,8 @@ def run_adjoint(args):
     h = 1e-3
     fx = (prob.value(xi + h, R) - prob.value(xi - h, R)) / (2 * h)
     fR = (prob.value(xi, R + h) - prob.value(xi, R - h)) / (2 * h)
-    # J is only piecewise smooth in R (faces cross the solid cut and the cutoff of
-    # the body velocity), so a smaller step is also reported
+    # J is only piecewise smooth at small scales (limiter branches switch as the
+    # parameters move), so a smaller step is also reported
     h2 = 1e-5
     fx2 = (prob.value(xi + h2, R) - prob.value(xi - h2, R)) / (2 * h2)
     fR2 = (prob.value(xi, R + h2) - prob.value(xi, R - h2)) / (2 * h2)

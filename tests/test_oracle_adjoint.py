@@ -42,3 +42,25 @@ def test_complex_step_with_live_cfl_matches_central_differences():
     assert gR == pytest.approx((Jp - Jm) / (2 * h), rel=1e-6, abs=1e-9)
     _, fx, fR, _ = A.gradient(w, xi, R, steps, win)
     assert abs(gx - fx) > 1e-6 * abs(fx)
+
+
+def test_rotcyl_radius_step_crosses_no_cut():
+    # Central differences of the 512 x 256 rotating-cylinder objective at h = 1e-3
+    # in R disagree with the exact derivative by a few 1e-3; no face changes sides of
+    # the solid cut (mu0 < 1e-6) or of the body velocity's cutoff (d < 2 + eps)
+    # between R - 1e-3 and R + 1e-3, so those jumps are not the cause.
+    import numpy as np
+    from oracle import Grid
+    from oracle.body import MU0_CUT, face_points, sdf_normal_velocity
+    from oracle.moments import mu0
+    w = wlsynth.rotating_cylinder_2d()
+    g = Grid(w.n)
+    R, h = float(w.body.radius), 1e-3
+    for i in range(2):
+        X = face_points(g, i)
+        ds = []
+        for RR in (R - h, R + h):
+            b = wlsynth.Body("sphere", center=w.body.center, radius=RR)
+            ds.append(sdf_normal_velocity(b, X, 0.0)[0])
+        assert np.array_equal(mu0(ds[0], 1.0) < MU0_CUT, mu0(ds[1], 1.0) < MU0_CUT)
+        assert np.array_equal(ds[0] < 3.0, ds[1] < 3.0)
