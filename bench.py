@@ -312,6 +312,65 @@ def run_adjoint(args):
     prob.sim.close()
 
 
+def run_learned(args):
+    """The learned multigrid guess at its configuration: sphere wake 256 x 128 x 128,
+    D = 32, Re = 3700, FP32, tolerance 1e-6; the net trains online on 2000 solver
+    snapshots (1000 steps, one crop per solve, 2 Adam steps per solve, from a zero
+    output layer), then guides the solves of 1000 evaluation steps with its weights
+    frozen; a plain run takes the same 2000 steps.  Both meet the same residual
+    tolerance in every solve; reported: ms and V-cycles per evaluation step."""
+    import numpy as np
+    import torch
+    import wlsynth
+    from paper_2407_16032_amd import Simulation
+    w = wlsynth.sphere_3d()
+    train = 1000
+    evals = args.steps if args.steps_given else 1000
+    kw = dict(convective_exit=True, prec="f32", tol=1e-6, itmax=32, device="cuda:0")
+    u0 = wlsynth.initial_velocity(w)
+    out = {}
+    for mode in ("plain", "learned"):
+        sim = Simulation(w.n, w.U, w.nu, w.body, learned_guess=(mode == "learned"), **kw)
+        sim.set_velocity(u0)
+        if mode == "learned":
+            sim.pg_set_weights(wlsynth.pg_init_weights(0, zero_output=True))
+            sim.pg_mode(2, lr=1e-3, train_iters=2, crops=1, seed=3)
+        t0 = time.perf_counter()
+        for k in range(train):
+            sim.step()
+        torch.cuda.synchronize()
+        t_train = time.perf_counter() - t0
+        if mode == "learned":
+            sim.pg_mode(1)
+        vc, res = [], []
+        t0 = time.perf_counter()
+        for k in range(evals):
+            st = sim.step()
+            vc.append(sum(st["vcycles"]))
+            res.append(max(st["res_linf"]))
+        torch.cuda.synchronize()
+        t_eval = time.perf_counter() - t0
+        ent = {"ms_per_step": round(t_eval / evals * 1e3, 3), "vcycles_per_step": round(float(np.mean(vc)), 3),
+               "max_final_residual": max(res), "first_steps_s": round(t_train, 2)}
+        if mode == "learned":
+            ent["pg"] = sim.pg_stats()
+        out[mode] = ent
+        print("[bench] %s: %.3f ms/step, %.3f V-cycles/step over %d steps (after %d steps, %.1f s)" % (
+            mode, ent["ms_per_step"], ent["vcycles_per_step"], evals, train, t_train), file=sys.stderr, flush=True)
+        sim.close()
+        del sim
+        torch.cuda.empty_cache()
+    print(json.dumps({
+        "metric": "learned multigrid guess: ms per step and V-cycles per step against the plain warm start",
+        "value": out["learned"]["ms_per_step"], "unit": "ms/step", "n_gpus": 1, "steps": evals,
+        "higher_is_better": False, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": w.name, "cells": w.cells, "mg_tol": 1e-6, "training_steps": train,
+                   "snapshots": 2 * train, "evaluation_steps": evals},
+        "plain": out["plain"], "learned": out["learned"],
+        "vcycles_saved_per_step": round(out["plain"]["vcycles_per_step"] - out["learned"]["vcycles_per_step"], 3),
+        "step_time_ratio": round(out["learned"]["ms_per_step"] / out["plain"]["ms_per_step"], 4)}))
+
+
 def run_optimize(args):
     """Davidon optimisation of the rotation rate of the rotating-cylinder case
     (512 x 256 cells, D = 32, Re = 200, 400 steps, window 200..399, FP64) for the
@@ -359,6 +418,8 @@ def main():
     ap.add_argument("--no-profile", action="store_true", help="skip per-kernel event timing")
     ap.add_argument("--adjoint", action="store_true",
                     help="run the rotating-cylinder gradient case instead (adjoint vs forward cost)")
+    ap.add_argument("--learned", action="store_true",
+                    help="run the learned-guess case (sphere wake, online training) against plain multigrid")
     ap.add_argument("--optimize", action="store_true",
                     help="run the Davidon optimisation of the rotating cylinder's rate instead")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
@@ -375,7 +436,7 @@ def main():
 
     # the CPU baseline runs first, in worker processes, before this process touches the GPU
     cpu = None
-    if not args.no_cpu_baseline and not args.adjoint and not args.optimize:
+    if not args.no_cpu_baseline and not args.adjoint and not args.optimize and not args.learned:
         print("[bench] timing the FP64 oracle on a bounded CPU sample", file=sys.stderr, flush=True)
         cpu = run_cpu_baseline(args.workload)
 
@@ -393,6 +454,9 @@ def main():
         return
     if args.optimize:
         run_optimize(args)
+        return
+    if args.learned:
+        run_learned(args)
         return
     w = workloads()[args.workload]
     body = w.body if w.body.kind != "none" else None
