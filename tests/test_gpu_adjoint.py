@@ -272,3 +272,16 @@ def test_adjoint_with_live_time_steps_matches_gpu_central_differences():
     assert gx == pytest.approx(fx, rel=1e-5, abs=1e-8)
     assert gR == pytest.approx(fR, rel=1e-5, abs=1e-8)
     prob.sim.close()
+
+
+def test_adjoint_fp32_variant(oracle_grad):
+    # the same reverse sweep with FP32 fields (FP64 dots): its error against the FP64
+    # oracle's complex-step gradient is reported and bounded
+    J0, gx0, gR0, dts = oracle_grad
+    prob = _problem(5, dts, prec="f32", tol=1e-6)
+    J, gx, gR = prob.value_and_grad(XI, R)
+    ex, eR = abs(gx - gx0) / abs(gx0), abs(gR - gR0) / abs(gR0)
+    _say("  FP32 adjoint: J rel %.2e  dJ/dxi rel %.2e  dJ/dR rel %.2e" % (abs(J - J0) / abs(J0), ex, eR))
+    assert abs(J - J0) < 1e-4 * abs(J0)
+    assert ex < 2e-2 and eR < 2e-2
+    prob.sim.close()
