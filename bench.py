@@ -42,7 +42,7 @@ def workloads():
 
 
 def kernel_bytes(name, ndim, cells, faces, esize, has_body, pcg_iters, box_cells=None, box_faces=None,
-                 tiled=False, flat=False):
+                 tiled=False, flat=False, fused=False):
     """Algorithmic bytes of one launch of the kernels as built: each field the pass
     needs is read once, each output written once.
 
@@ -51,7 +51,9 @@ def kernel_bytes(name, ndim, cells, faces, esize, has_body, pcg_iters, box_cells
     the body box (box_cells / box_faces): outside it the kernels evaluate their
     body-free closed form.  On tiled levels (3-D, large) pass A does not store q and
     pass B recomputes it from e (pass B then needs L and iD in the box); the flat
-    form of the fine level (``flat``) moves the same fields.
+    form of the fine level (``flat``) moves the same fields.  With ``fused`` (3-D
+    steps) the flux launch writes the blended velocity outside the body box and f~
+    only near it, and the blend launch covers the box's faces alone.
     """
     n = ndim
     bc = cells if box_cells is None else box_cells
@@ -74,10 +76,14 @@ def kernel_bytes(name, ndim, cells, faces, esize, has_body, pcg_iters, box_cells
     if name == "restrict":
         return (1 + 2 / 2 ** n) * cells * esize      # r; writes r_c, x_c
     if name == "flux":
-        # average of predictor (u = u0: n) and corrector (u, u0: 2n); writes f (n); V (n) in the box
-        return ((1.5 * n + n) * faces + (n * bf if has_body else 0)) * esize
+        # average of predictor (u = u0: n) and corrector (u, u0: 2n); writes f, or with
+        # ``fused`` u (n); V (n) in the box, and with ``fused`` f there too
+        box = ((2 if fused else 1) * n * bf) if has_body else 0
+        return ((1.5 * n + n) * faces + box) * esize
     if name == "bdim":
         body = (n + n + n * n) * bf if has_body else 0     # V, mu0, mu1 in the box
+        if fused:                                          # f, u (corrector), writes u: in the box
+            return ((n + 0.5 * n + n) * bf + body) * esize
         return ((n + 0.5 * n + n) * faces + body) * esize  # f, u (corrector); writes u
     if name == "cfl":
         return n * cells * esize
@@ -415,6 +421,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--solver-path", default="auto", choices=["auto", "tiles", "flat", "generic"],
                     help="kernels of the large 3-D multigrid levels (same arithmetic)")
+    ap.add_argument("--blend", default="auto", choices=["auto", "separate"],
+                    help="BDIM blend inside the 3-D flux launch outside the body box (auto) or a separate pass")
     ap.add_argument("--no-profile", action="store_true", help="skip per-kernel event timing")
     ap.add_argument("--adjoint", action="store_true",
                     help="run the rotating-cylinder gradient case instead (adjoint vs forward cost)")
@@ -463,7 +471,8 @@ def main():
     print("[bench] workload %s (%d cells), building initial field" % (w.name, w.cells), file=sys.stderr,
           flush=True)
     sim = Simulation(w.n, w.U, w.nu, body, periodic=w.periodic_mask(), convective_exit=w.convective_exit,
-                     prec="f32", tol=w.tol, itmax=32, device="cuda:0", solver_path=args.solver_path)
+                     prec="f32", tol=w.tol, itmax=32, device="cuda:0", solver_path=args.solver_path,
+                     blend_mode=args.blend)
     sim.set_velocity(wlsynth.initial_velocity(w, seed=0))
     for k in range(args.warmup):
         sim.step()
@@ -479,7 +488,8 @@ def main():
     tiled = flat or (args.solver_path != "generic" and fine_level_tiled(w.n))
 
     def launch_bytes(name):
-        return kernel_bytes(name, w.ndim, cells, faces, 4, body is not None, 6, bcells, bfaces, tiled, flat)
+        return kernel_bytes(name, w.ndim, cells, faces, 4, body is not None, 6, bcells, bfaces, tiled, flat,
+                            fused=w.ndim == 3 and args.blend == "auto")
 
     # Breakdown: a few extra steps with an event pair around every launch (the
     # events cost a few per cent of the step, so these steps are not the timed ones)
@@ -593,7 +603,7 @@ def main():
         "config": {"workload": w.name, "cells": w.cells,
                    "Re": round((math.sqrt(sum(u * u for u in w.U)) or 1.0) * w.L / w.nu, 1) if w.nu else None,
                    "mg_tol": w.tol, "moving_body": bool(body is not None and body.moving),
-                   "convective_exit": w.convective_exit, "parallelism": "single GPU"},
+                   "convective_exit": w.convective_exit, "blend": args.blend, "parallelism": "single GPU"},
         "windows_ms_per_step": [round(v, 3) for v in windows],
         "vcycles_per_step": round(kmean, 3),
         "vcycle_factor": round(float(np.exp(np.mean(np.log(factors)))), 4) if factors else None,

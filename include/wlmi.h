@@ -93,6 +93,14 @@ typedef struct {
                             in two stages above 16384 partials), 1 = always a separate
                             single-stage launch, 2 = always two stages.  Same arithmetic,
                             sums in a different fixed order. [0] */
+  int blend_mode;        /* where a step applies the BDIM blend: 0 = automatic (3-D steps
+                            that record nothing for the adjoint blend every face outside
+                            the body box inside the flux launch, where the coefficients
+                            are body-free, and the box's faces in a launch of their own;
+                            the corrector then writes the new velocity over the old one,
+                            so WL_FIELD_U0 afterwards holds the predictor's projected
+                            velocity), 1 = always a separate pass over every face after
+                            the flux launch.  Same arithmetic and the same results. [0] */
 } wl_sim_desc;
 
 typedef enum {
@@ -262,8 +270,11 @@ wl_status wl_forces_static(wl_sim* sim, double f_pressure[3], double f_viscous[3
 
 enum {
   WL_FIELD_U = 0,     /* velocity, ndim components */
-  WL_FIELD_U0 = 1,    /* start-of-step velocity (after a step: the previous velocity) */
-  WL_FIELD_F = 2,     /* scratch f~ / R, ndim components */
+  WL_FIELD_U0 = 1,    /* second velocity buffer: after a step the previous velocity, or
+                         the predictor's projected velocity when the step blended in the
+                         flux launch (blend_mode) */
+  WL_FIELD_F = 2,     /* scratch f~ / R, ndim components (after a blended-in-flux step,
+                         valid only within one face of the body box) */
   WL_FIELD_V = 3,     /* body velocity, ndim components */
   WL_FIELD_MU0 = 4,   /* mu0 = fine-level L, ndim components */
   WL_FIELD_MU1 = 5,   /* mu1_ij at component i*ndim + j */

@@ -35,7 +35,8 @@ class SimDesc(C.Structure):
                 ("eps", C.c_double), ("dt0", C.c_double), ("dt_max", C.c_double),
                 ("cfl_nu_coef", C.c_double), ("mg_tol", C.c_double), ("mg_itmax", C.c_int),
                 ("pcg_iters", C.c_int), ("learned_guess", C.c_int), ("adjoint", C.c_int),
-                ("solver_path", C.c_int), ("reduce_mode", C.c_int)]
+                ("solver_path", C.c_int), ("reduce_mode", C.c_int),
+                ("blend_mode", C.c_int)]
 
 
 class BodyDesc(C.Structure):

@@ -660,10 +660,25 @@ __device__ __forceinline__ T phi_at(const Grid3& g, const Vec3<T>& u, int c, int
   return phi_cj<T, 3>(g, u, c, j, P, nu);
 }
 
-template <typename T>
+// Is padded index I inside the box [lo, hi] itself (no periodic widening)?
+__device__ __forceinline__ bool in_box3(const StdBox& B, const int I[3]) {
+  return B.lo[0] <= B.hi[0] && I[0] >= B.lo[0] && I[0] <= B.hi[0] && I[1] >= B.lo[1] && I[1] <= B.hi[1] &&
+         I[2] >= B.lo[2] && I[2] <= B.hi[2];
+}
+
+// FUSE = 0: f = f~ on every face.  FUSE = 1 (predictor) / 2 (corrector): the BDIM
+// blend is applied here to every face outside the body box [lo, hi], where the
+// coefficients are body-free (mu0 = L, mu1 = 0, V = 0): uo = L f~, or with the
+// corrector uo = (u + L f~)/2, u being this stage's velocity at the same face.
+// f~ itself is stored only within one face of the box, for k_bdim_box, which
+// blends the faces of the box.  (On a periodic axis the body-free test also counts
+// the ghost faces 0 and N+1 as inside; ghost faces are rewritten by the boundary
+// conditions straight after the blend, so they take the body-free form here.)
+// uo may be u0: each face reads u0 only at its own index, before its store.
+template <typename T, int FUSE>
 __global__ void __launch_bounds__(kReuseThreads) k_flux_reuse(Grid3 g, Vec3<T> u, Vec3<T> u0, Vec3<T> V, Vec3<T> f,
-                                                              T dt, T nu, int has_body, StdBox B, int nbx, int nby,
-                                                              int nbz) {
+                                                              Vec3<T> uo, T dt, T nu, int has_body, StdBox B,
+                                                              int nbx, int nby, int nbz) {
   // one block per brick and component; the XCDs take contiguous ranges of
   // (brick, component) with the component fastest, so the three blocks of a brick
   // run together on one XCD and share the velocity they read through its L2
@@ -684,23 +699,29 @@ __global__ void __launch_bounds__(kReuseThreads) k_flux_reuse(Grid3 g, Vec3<T> u
   const bool fxy = I0 >= 3 && I0 <= g.n[0] - 2 && I1 >= 3 && I1 <= g.n[1] - 2;
   for (int I2 = z0; I2 < z1; ++I2) {
     T phx, phy, phyn, phzn;
+    // u0 at the face (column clamped into the row for the lanes that store nothing)
+    // is loaded ahead of the stencil; with FUSE = 2 also u at the face
+    const int idx = lin3<T, 3>(g, min(I0, P0 - 1), I1, I2);
+    const T u0v = u0.c[c][idx];
+    T uself = T(0);
     if (fxy && I2 >= 3 && I2 <= g.n[2] - 2) {
       // one straight block, so all its loads are in flight together
-      const int id = lin3<T, 3>(g, I0, I1, I2), sc = g.s[c];
+      const int id = idx, sc = g.s[c];
       phx = phi_fast<T, 3>(u, c, 0, id, sc, g.s[0], nu);
       phy = phi_fast<T, 3>(u, c, 1, id, sc, g.s[1], nu);
       phyn = phi_fast<T, 3>(u, c, 1, id + g.s[1], sc, g.s[1], nu);
       phzn = phi_fast<T, 3>(u, c, 2, id + g.s[2], sc, g.s[2], nu);
+      if (FUSE == 2) uself = u.c[c][id];
     } else {
       phx = phi_at<T>(g, u, c, 0, I0, I1, I2, nu);
       phy = phi_at<T>(g, u, c, 1, I0, I1, I2, nu);
       phyn = phi_at<T>(g, u, c, 1, I0, I1 + 1, I2, nu);
       phzn = phi_at<T>(g, u, c, 2, I0, I1, I2 + 1, nu);
+      if (FUSE == 2) uself = u.c[c][idx];
     }
     const T phxn = __shfl_down(phx, 1, kRX);  // every lane of the wave takes part
     if (col) {
       const int I[3] = {I0, I1, I2};
-      const int idx = lin3<T, 3>(g, I0, I1, I2);
       bool unknown = true, wraps = false;
 #pragma unroll
       for (int a = 0; a < 3; ++a) {
@@ -710,7 +731,6 @@ __global__ void __launch_bounds__(kReuseThreads) k_flux_reuse(Grid3 g, Vec3<T> u
       }
       const bool needV = has_body && !std_point<3>(B, g, I, 0);  // V = 0 outside the box
       const T vb = needV ? V.c[c][idx] : T(0);
-      const T u0v = u0.c[c][idx];
       T R = T(0);
       if (unknown) {
         if (wraps) {
@@ -723,19 +743,28 @@ __global__ void __launch_bounds__(kReuseThreads) k_flux_reuse(Grid3 g, Vec3<T> u
       }
       T v = u0v + dt * R;
       if (needV) v = v - vb;
-      f.c[c][idx] = v;
+      if (FUSE == 0) {
+        f.c[c][idx] = v;
+      } else {
+        if (has_body && !std_point<3>(B, g, I, 1)) f.c[c][idx] = v;
+        if (!in_box3(B, I)) {
+          T acc = has_body ? L_std<T>(g, B, c, I[c]) * v : v;
+          if (FUSE == 2) acc = T(0.5) * (uself + acc);
+          uo.c[c][idx] = acc;
+        }
+      }
     }
     phz = phzn;
   }
 }
 
 // BDIM blend of face I of component c: out = V + mu0 f + sum_j mu1_cj
-// (f[I+e_j]-f[I-e_j])/2.  CORR = 0: u = out (predictor); CORR = 1: u = (u + out)/2
-// (corrector).
+// (f[I+e_j]-f[I-e_j])/2.  CORR = 0: uo = out (predictor); CORR = 1: uo = (u + out)/2
+// (corrector).  uo may be u.
 template <typename T, int D, int CORR>
 __device__ __forceinline__ void bdim_face(const Grid3& g, const Vec3<T>& f, const Vec3<T>& V, const Vec3<T>& mu0,
                                           const Vec9<T>& mu1, const Vec3<T>& u, int has_body, const StdBox& B,
-                                          int c, const int I[3], int idx) {
+                                          int c, const int I[3], int idx, const Vec3<T>& uo) {
   T acc;
   bool fast = true;
   for (int a = 0; a < D; ++a) fast = fast && I[a] >= 2 && I[a] <= g.n[a] - 1;
@@ -770,8 +799,8 @@ __device__ __forceinline__ void bdim_face(const Grid3& g, const Vec3<T>& f, cons
   } else {
     acc = f.c[c][idx];  // mu0 = 1, mu1 = 0, V = 0 (boundary faces are reset by the BCs)
   }
-  if (CORR) u.c[c][idx] = T(0.5) * (u.c[c][idx] + acc);
-  else u.c[c][idx] = acc;
+  if (CORR) uo.c[c][idx] = T(0.5) * (u.c[c][idx] + acc);
+  else uo.c[c][idx] = acc;
 }
 
 template <typename T, int D, int CORR>
@@ -783,7 +812,20 @@ __global__ void __launch_bounds__(kBlock) k_bdim(Grid3 g, Vec3<T> f, Vec3<T> V, 
   for (int lin = blockIdx.x * kBlock + threadIdx.x; lin < total; lin += gridDim.x * kBlock) {
     const int I0 = lin % P0, t = lin / P0, I1 = t % P1, I2 = t / P1;
     const int I[3] = {I0, I1, I2};
-    bdim_face<T, D, CORR>(g, f, V, mu0, mu1, u, has_body, B, c, I, lin3<T, D>(g, I0, I1, I2));
+    bdim_face<T, D, CORR>(g, f, V, mu0, mu1, u, has_body, B, c, I, lin3<T, D>(g, I0, I1, I2), u);
+  }
+}
+
+// The blend of the faces of the body box [lo, lo + n) (padded indices, 3-D) after a
+// fused flux launch (k_flux_reuse with FUSE = 1 + CORR): reads f~, writes uo.
+template <typename T, int CORR>
+__global__ void __launch_bounds__(kBlock) k_bdim_box(Grid3 g, Vec3<T> f, Vec3<T> V, Vec3<T> mu0, Vec9<T> mu1,
+                                                     Vec3<T> u, Vec3<T> uo, StdBox B, int3 lo, int3 n) {
+  const int c = blockIdx.y;
+  const int64_t total = (int64_t)n.x * n.y * n.z;
+  for (int64_t lin = (int64_t)blockIdx.x * kBlock + threadIdx.x; lin < total; lin += (int64_t)gridDim.x * kBlock) {
+    const int I[3] = {lo.x + (int)(lin % n.x), lo.y + (int)((lin / n.x) % n.y), lo.z + (int)(lin / ((int64_t)n.x * n.y))};
+    bdim_face<T, 3, CORR>(g, f, V, mu0, mu1, u, 1, B, c, I, lin3<T, 3>(g, I[0], I[1], I[2]), uo);
   }
 }
 
@@ -2455,7 +2497,7 @@ __global__ void __launch_bounds__(kFlatThreads) k_bdim_flat(Grid3 g, Vec3<T> f, 
     const int e = t - vr * P1;
     if (e >= 2 * P1) return;  // no barrier in this kernel
     const int I[3] = {(e & 1) ? g.n[0] + 1 : 0, e >> 1, k};
-    bdim_face<T, 3, CORR>(g, f, V, mu0, mu1, u, has_body, B, c, I, lin3<T, 3>(g, I[0], I[1], I[2]));
+    bdim_face<T, 3, CORR>(g, f, V, mu0, mu1, u, has_body, B, c, I, lin3<T, 3>(g, I[0], I[1], I[2]), u);
     return;
   }
   const int m = t % vr, j = t / vr;
@@ -2509,7 +2551,7 @@ __global__ void __launch_bounds__(kFlatThreads) k_bdim_flat(Grid3 g, Vec3<T> f, 
 #pragma unroll
     for (int w = 0; w < W; ++w) {
       const int I[3] = {i0 + w, j, k};
-      bdim_face<T, 3, CORR>(g, f, V, mu0, mu1, u, has_body, B, c, I, id + w);
+      bdim_face<T, 3, CORR>(g, f, V, mu0, mu1, u, has_body, B, c, I, id + w, u);
     }
   }
 }

@@ -100,6 +100,7 @@ wl_status validate_and_default(const wl_sim_desc* in, wl_sim_desc* d) {
   if (d->pcg_iters < 1 || d->pcg_iters > kMaxPcg) return fail(WL_ERR_INVALID_ARG, "pcg_iters must be in [1, 15]");
   if (d->solver_path < 0 || d->solver_path > 3) return fail(WL_ERR_INVALID_ARG, "solver_path must be in [0, 3]");
   if (d->reduce_mode < 0 || d->reduce_mode > 2) return fail(WL_ERR_INVALID_ARG, "reduce_mode must be in [0, 2]");
+  if (d->blend_mode < 0 || d->blend_mode > 1) return fail(WL_ERR_INVALID_ARG, "blend_mode must be 0 or 1");
   if (d->convective_exit) {
     if (d->periodic_mask & 1u) return fail(WL_ERR_INVALID_ARG, "convective exit needs a non-periodic x axis");
     if (d->U[0] == 0.0) return fail(WL_ERR_INVALID_ARG, "convective exit needs U[0] != 0");
@@ -1725,18 +1726,54 @@ struct Impl : SimBase {
     return WL_OK;
   }
 
-  // f~ = u0 + dt R(u) - V on every padded face
-  wl_status flux(T* const uu[3], T* const uu0[3], int hb) {
+  // f~ = u0 + dt R(u) - V on every padded face (fuse = 0), or, in 3-D, the blend
+  // of the predictor (fuse = 1) or the corrector (fuse = 2) written to uo outside
+  // the body box and f~ kept near it (k_flux_reuse)
+  wl_status flux(T* const uu[3], T* const uu0[3], int hb, int fuse = 0, T* const uo[3] = nullptr) {
     if (D == 3) {
       // output bricks of 63 columns x kRW rows x kRZ planes
       const int nbx = (g[0].n[0] + 2 + kRX - 2) / (kRX - 1), nby = (g[0].n[1] + 2 + kRW - 1) / kRW,
                 nbz = (g[0].n[2] + 2 + kRZ - 1) / kRZ;
-      WL_TIMED(WL_K_FLUX, (k_flux_reuse<T><<<dim3(nbx * nby * nbz * 3), kReuseThreads, 0, stream>>>(
-                              g[0], v3(uu), v3(uu0), v3(V), v3(ft), T(dt), T(desc.nu), hb, sbox[0], nbx, nby, nbz)));
+      const dim3 grid(nbx * nby * nbz * 3);
+      const Vec3<T> o = v3(uo ? uo : ft);
+      if (fuse == 1)
+        WL_TIMED(WL_K_FLUX, (k_flux_reuse<T, 1><<<grid, kReuseThreads, 0, stream>>>(
+                                g[0], v3(uu), v3(uu0), v3(V), v3(ft), o, T(dt), T(desc.nu), hb, sbox[0], nbx, nby, nbz)));
+      else if (fuse == 2)
+        WL_TIMED(WL_K_FLUX, (k_flux_reuse<T, 2><<<grid, kReuseThreads, 0, stream>>>(
+                                g[0], v3(uu), v3(uu0), v3(V), v3(ft), o, T(dt), T(desc.nu), hb, sbox[0], nbx, nby, nbz)));
+      else
+        WL_TIMED(WL_K_FLUX, (k_flux_reuse<T, 0><<<grid, kReuseThreads, 0, stream>>>(
+                                g[0], v3(uu), v3(uu0), v3(V), v3(ft), o, T(dt), T(desc.nu), hb, sbox[0], nbx, nby, nbz)));
     } else {
       WL_TIMED(WL_K_FLUX, (k_flux<T, D><<<dim3(nb_face, D), kBlock, 0, stream>>>(
                               g[0], v3(uu), v3(uu0), v3(V), v3(ft), T(dt), T(desc.nu), hb, 0, sbox[0])));
     }
+    WL_HIP(hipGetLastError());
+    return WL_OK;
+  }
+
+  // blend of the body box's faces after a fused flux launch: uo from f~ and, for
+  // the corrector, this stage's velocity uu (nothing to do without a body box)
+  wl_status bdim_box(int corr, T* const uu[3], T* const uo[3]) {
+    const StdBox& Bx = sbox[0];
+    if (!has_body || Bx.lo[0] > Bx.hi[0]) return WL_OK;
+    int lo[3], cnt[3];
+    int64_t vol = 1;
+    for (int a = 0; a < 3; ++a) {
+      lo[a] = std::max(Bx.lo[a], 0);
+      cnt[a] = std::min(Bx.hi[a], g[0].n[a] + 1) - lo[a] + 1;
+      if (cnt[a] <= 0) return WL_OK;
+      vol *= cnt[a];
+    }
+    const dim3 grid(blocks_for(vol), D);
+    const int3 l3 = make_int3(lo[0], lo[1], lo[2]), n3 = make_int3(cnt[0], cnt[1], cnt[2]);
+    if (corr)
+      WL_TIMED(WL_K_BDIM, (k_bdim_box<T, 1><<<grid, kBlock, 0, stream>>>(g[0], v3(ft), v3(V), v3(mu0), v9(mu1), v3(uu),
+                                                                        v3(uo), Bx, l3, n3)));
+    else
+      WL_TIMED(WL_K_BDIM, (k_bdim_box<T, 0><<<grid, kBlock, 0, stream>>>(g[0], v3(ft), v3(V), v3(mu0), v9(mu1), v3(uu),
+                                                                        v3(uo), Bx, l3, n3)));
     WL_HIP(hipGetLastError());
     return WL_OK;
   }
@@ -1757,14 +1794,24 @@ struct Impl : SimBase {
     T* const* A = u[cur];
     T* const* B = u[1 - cur];
     const int hb = has_body ? 1 : 0;
+    // 3-D steps that record nothing for the adjoint blend in the flux launch away
+    // from the body; the corrector then writes u^{n+1} over u^n (A), which only the
+    // flux launch itself reads, face by face, and the buffers do not swap
+    const bool fuse = D == 3 && !rec && desc.blend_mode == 0;
+    T* const* C = fuse ? A : B;  // the corrector's output
     // predictor
-    if ((s = flux(A, A, hb)) != WL_OK) return s;
-    if (nflat[0] > 0)
-      WL_TIMED(WL_K_BDIM, (k_bdim_flat<T, 0><<<bdim_grid(), kFlatThreads, 0, stream>>>(g[0], v3(ft), v3(V), v3(mu0),
-                                                                                    v9(mu1), v3(B), hb, sbox[0])));
-    else
-      WL_TIMED(WL_K_BDIM, (k_bdim<T, D, 0><<<dim3(nb_face, D), kBlock, 0, stream>>>(g[0], v3(ft), v3(V), v3(mu0),
-                                                                                   v9(mu1), v3(B), hb, sbox[0])));
+    if (fuse) {
+      if ((s = flux(A, A, hb, 1, B)) != WL_OK) return s;
+      if ((s = bdim_box(0, B, B)) != WL_OK) return s;
+    } else {
+      if ((s = flux(A, A, hb)) != WL_OK) return s;
+      if (nflat[0] > 0)
+        WL_TIMED(WL_K_BDIM, (k_bdim_flat<T, 0><<<bdim_grid(), kFlatThreads, 0, stream>>>(
+                                g[0], v3(ft), v3(V), v3(mu0), v9(mu1), v3(B), hb, sbox[0])));
+      else
+        WL_TIMED(WL_K_BDIM, (k_bdim<T, D, 0><<<dim3(nb_face, D), kBlock, 0, stream>>>(
+                                g[0], v3(ft), v3(V), v3(mu0), v9(mu1), v3(B), hb, sbox[0])));
+    }
     const bool ex = desc.convective_exit != 0;
     if (ex) {
       const int m = g[0].n[1] * (D == 3 ? g[0].n[2] : 1);
@@ -1788,19 +1835,24 @@ struct Impl : SimBase {
       WL_HIP(copy_field(recX1, x[0]));
     }
     // corrector
-    if ((s = flux(B, A, hb)) != WL_OK) return s;
-    if (nflat[0] > 0)
-      WL_TIMED(WL_K_BDIM, (k_bdim_flat<T, 1><<<bdim_grid(), kFlatThreads, 0, stream>>>(g[0], v3(ft), v3(V), v3(mu0),
-                                                                                    v9(mu1), v3(B), hb, sbox[0])));
-    else
-      WL_TIMED(WL_K_BDIM, (k_bdim<T, D, 1><<<dim3(nb_face, D), kBlock, 0, stream>>>(g[0], v3(ft), v3(V), v3(mu0),
-                                                                                   v9(mu1), v3(B), hb, sbox[0])));
+    if (fuse) {
+      if ((s = flux(B, A, hb, 2, C)) != WL_OK) return s;
+      if ((s = bdim_box(1, B, C)) != WL_OK) return s;
+    } else {
+      if ((s = flux(B, A, hb)) != WL_OK) return s;
+      if (nflat[0] > 0)
+        WL_TIMED(WL_K_BDIM, (k_bdim_flat<T, 1><<<bdim_grid(), kFlatThreads, 0, stream>>>(
+                                g[0], v3(ft), v3(V), v3(mu0), v9(mu1), v3(B), hb, sbox[0])));
+      else
+        WL_TIMED(WL_K_BDIM, (k_bdim<T, D, 1><<<dim3(nb_face, D), kBlock, 0, stream>>>(
+                                g[0], v3(ft), v3(V), v3(mu0), v9(mu1), v3(B), hb, sbox[0])));
+    }
     WL_HIP(hipGetLastError());
-    if ((s = bc(B, ex)) != WL_OK) return s;
-    if ((s = project(B, 0.5, &s2, 1)) != WL_OK) return s;
+    if ((s = bc(C, ex)) != WL_OK) return s;
+    if ((s = project(C, 0.5, &s2, 1)) != WL_OK) return s;
     if (rec) WL_HIP(copy_field(recX2, x[0]));
-    if ((s = bc(B, ex)) != WL_OK) return s;
-    cur = 1 - cur;
+    if ((s = bc(C, ex)) != WL_OK) return s;
+    if (!fuse) cur = 1 - cur;
     const double dt_used = dt;
     t += dt;
     // CFL
