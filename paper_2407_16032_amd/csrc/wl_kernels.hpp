@@ -660,6 +660,33 @@ __device__ __forceinline__ T phi_at(const Grid3& g, const Vec3<T>& u, int c, int
   return phi_cj<T, 3>(g, u, c, j, P, nu);
 }
 
+// fm in the lanes whose bit of the wave mask is set, else fp.  In FP32 this is one
+// v_cndmask of its own: written as a select the compiler moves each far-point
+// load behind the upwind test (into a branch, or as a load from a selected
+// address), which costs a second round trip to memory per plane.
+template <typename T>
+__device__ __forceinline__ T pick_far(bool up, T fm, T fp) {
+  return up ? fm : fp;
+}
+template <>
+__device__ __forceinline__ float pick_far<float>(bool up, float fm, float fp) {
+  const uint64_t mask = __builtin_amdgcn_ballot_w64(up);
+  float r;
+  asm("v_cndmask_b32_e64 %0, %1, %2, %3" : "=v"(r) : "v"(fp), "v"(fm), "s"(mask));
+  return r;
+}
+
+// phi_fast's flux from values already loaded: a = (a0 + a1)/2, uc and m1 at the
+// face and its -j neighbour, fm / fp the far point for a >= 0 / a < 0
+template <typename T>
+__device__ __forceinline__ T phi_vals(T a0, T a1, T uc, T m1, T fm, T fp, T nu) {
+  const T a = T(0.5) * (a0 + a1);
+  const bool up = a >= T(0);
+  const T far = pick_far<T>(up, fm, fp);
+  const T Q = up ? quick_lim(far, m1, uc) : quick_lim(far, uc, m1);
+  return a * Q - nu * (uc - m1);
+}
+
 // Is padded index I inside the box [lo, hi] itself (no periodic widening)?
 __device__ __forceinline__ bool in_box3(const StdBox& B, const int I[3]) {
   return B.lo[0] <= B.hi[0] && I[0] >= B.lo[0] && I[0] <= B.hi[0] && I[1] >= B.lo[1] && I[1] <= B.hi[1] &&
@@ -705,13 +732,22 @@ __global__ void __launch_bounds__(kReuseThreads) k_flux_reuse(Grid3 g, Vec3<T> u
     const T u0v = u0.c[c][idx];
     T uself = T(0);
     if (fxy && I2 >= 3 && I2 <= g.n[2] - 2) {
-      // one straight block, so all its loads are in flight together
-      const int id = idx, sc = g.s[c];
-      phx = phi_fast<T, 3>(u, c, 0, id, sc, g.s[0], nu);
-      phy = phi_fast<T, 3>(u, c, 1, id, sc, g.s[1], nu);
-      phyn = phi_fast<T, 3>(u, c, 1, id + g.s[1], sc, g.s[1], nu);
-      phzn = phi_fast<T, 3>(u, c, 2, id + g.s[2], sc, g.s[2], nu);
-      if (FUSE == 2) uself = u.c[c][id];
+      // one straight block of loads: every value the four face fluxes can use,
+      // both QUICK far points of each included, so no address waits for the
+      // upwind test and the whole stencil is one round trip to memory
+      const int id = idx, sc = g.s[c], s1 = g.s[1], s2 = g.s[2];
+      const T* q = u.c[c];
+      const T c0 = q[id], xm1 = q[id - 1], xm2 = q[id - 2], xp1 = q[id + 1];
+      const T ym1 = q[id - s1], ym2 = q[id - 2 * s1], yp1 = q[id + s1], yp2 = q[id + 2 * s1];
+      const T zm1 = q[id - s2], zp1 = q[id + s2], zp2 = q[id + 2 * s2];
+      const T ax0 = u.c[0][id], ax1 = u.c[0][id - sc];
+      const T ay0 = u.c[1][id], ay1 = u.c[1][id - sc], ayn0 = u.c[1][id + s1], ayn1 = u.c[1][id + s1 - sc];
+      const T azn0 = u.c[2][id + s2], azn1 = u.c[2][id + s2 - sc];
+      phx = phi_vals<T>(ax0, ax1, c0, xm1, xm2, xp1, nu);
+      phy = phi_vals<T>(ay0, ay1, c0, ym1, ym2, yp1, nu);
+      phyn = phi_vals<T>(ayn0, ayn1, yp1, c0, ym1, yp2, nu);
+      phzn = phi_vals<T>(azn0, azn1, zp1, c0, zm1, zp2, nu);
+      if (FUSE == 2) uself = c0;
     } else {
       phx = phi_at<T>(g, u, c, 0, I0, I1, I2, nu);
       phy = phi_at<T>(g, u, c, 1, I0, I1, I2, nu);
