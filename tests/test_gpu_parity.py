@@ -169,9 +169,10 @@ def test_one_step_fp32(name):
 @pytest.mark.parametrize("path", ["tiles", "flat", "generic"])
 @pytest.mark.parametrize("prec", ["f64", "f32"])
 def test_one_step_other_solver_paths(name, path, prec):
-    """By default the 64^3 cases run PCG pass A in z-marching tiles and pass B in
-    flat vectors on the fine level (the tests above); here the fine level runs
-    tiles for both, flat vectors for both, or the generic kernels."""
+    """By default the 64^3 cases run both PCG passes of the fine level as flat
+    vector passes (2^18 cells, rows of whole 16-byte vectors; the tests above);
+    here the fine level runs z-marching tiles, the flat passes forced, or the
+    generic kernels."""
     _say("step", prec, name, path)
     w = CASES[name]
     ref, gpu = make_pair(w, prec, 1e-13 if prec == "f64" else 1e-6, solver_path=path)
