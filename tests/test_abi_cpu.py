@@ -91,6 +91,20 @@ def test_workspace_bytes_and_validation(lib):
     ex.convective_exit = 1
     ex.periodic_mask = 1
     assert lib.wl_workspace_bytes(C.byref(ex), C.byref(b)) == 0
+    # the mode switches take their documented values only; the blend's place does
+    # not change the workspace
+    for field, good, badv in (("solver_path", 3, 4), ("reduce_mode", 2, 3), ("blend_mode", 1, 2)):
+        m = _desc()
+        setattr(m, field, good)
+        assert lib.wl_workspace_bytes(C.byref(m), C.byref(b)) > 0, field
+        setattr(m, field, badv)
+        assert lib.wl_workspace_bytes(C.byref(m), C.byref(b)) == 0, field
+        assert field.encode() in lib.wl_last_error()
+        setattr(m, field, -1)
+        assert lib.wl_workspace_bytes(C.byref(m), C.byref(b)) == 0, field
+    sep = _desc()
+    sep.blend_mode = 1
+    assert lib.wl_workspace_bytes(C.byref(sep), C.byref(b)) == nb
     # a body too close to the boundary is rejected
     body = L.BodyDesc()
     body.kind = 1
