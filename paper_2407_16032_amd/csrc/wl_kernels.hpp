@@ -2280,6 +2280,78 @@ __global__ void __launch_bounds__(kFlatThreads) k_pcg_a_fused_flat(Grid3 g, Vec3
   }
 }
 
+// Sum of r^2 over the interior cells (FP64), flat form: one 16-byte vector of
+// cells per thread, the block's sum into part.
+template <typename T>
+__global__ void __launch_bounds__(kFlatThreads) k_sumsq_flat(Grid3 g, const T* r, double* part) {
+  typedef typename Vec16<T>::type V;
+  constexpr int W = Vec16<T>::W;
+  const FlatVec f = flat_vec<T>(g);
+  double s = 0.0;
+  if (f.ok) {
+    const V rv = ldv(r + f.id);
+    const T* R = reinterpret_cast<const T*>(&rv);
+#pragma unroll
+    for (int w = 0; w < W; ++w) s += double(R[w]) * double(R[w]);
+  }
+  s = block_sum<kFlatThreads>(s);
+  if (threadIdx.x == 0) part[flat_block()] = s;
+}
+
+// CFL and divergence check, flat form (arithmetic of k_cfl): one 16-byte vector
+// of cells per thread; per cell sigma = sum_a max(0, u_a[I + e_a]) + max(0,
+// -u_a[I]) and div = sum_a (u_a[I + e_a] - u_a[I]) in FP64, the block's maxima of
+// sigma and of |div| over the active cells into part / part_div.
+template <typename T, bool PER>
+__global__ void __launch_bounds__(kFlatThreads) k_cfl_flat(Grid3 g, Vec3<T> u, const T* iD, StdBox B,
+                                                           double* part, double* part_div) {
+#pragma clang fp contract(off)
+  typedef typename Vec16<T>::type V;
+  constexpr int W = Vec16<T>::W;
+  const FlatVec f = flat_vec<T>(g);
+  double mx = 0.0, md = 0.0;
+  if (f.ok) {
+    const FlatNbr<W, PER> o(g, f);
+    const int id = f.id;
+    const V u0 = ldv(u.c[0] + id), u1 = ldv(u.c[1] + id), u1p = ldv(u.c[1] + id + o.yp), u2 = ldv(u.c[2] + id),
+            u2p = ldv(u.c[2] + id + o.zp);
+    const T u0n = u.c[0][id + W - 1 + o.xp];
+    // cells of the vector outside the body box are active; inside, those with iD != 0
+    const int a[3] = {f.i0, f.j, f.k}, b[3] = {f.i0 + W - 1, f.j, f.k};
+    const bool all_act = std_miss<3>(B, g, a, b);
+    V dv_ = {};
+    if (!all_act) dv_ = ldv(iD + id);
+    const T *U0 = reinterpret_cast<const T*>(&u0), *U1 = reinterpret_cast<const T*>(&u1),
+            *U1P = reinterpret_cast<const T*>(&u1p), *U2 = reinterpret_cast<const T*>(&u2),
+            *U2P = reinterpret_cast<const T*>(&u2p), *DI = reinterpret_cast<const T*>(&dv_);
+#pragma unroll
+    for (int w = 0; w < W; ++w) {
+      const T up0 = (w < W - 1) ? U0[w + 1] : u0n;
+      T s = T(0);
+      s = s + fmax(T(0), up0) + fmax(T(0), -U0[w]);
+      s = s + fmax(T(0), U1P[w]) + fmax(T(0), -U1[w]);
+      s = s + fmax(T(0), U2P[w]) + fmax(T(0), -U2[w]);
+      double dv = 0.0;
+      dv = dv + (double(up0) - double(U0[w]));
+      dv = dv + (double(U1P[w]) - double(U1[w]));
+      dv = dv + (double(U2P[w]) - double(U2[w]));
+      mx = fmax(mx, double(s));
+      bool act = all_act;
+      if (!act) {
+        const int I[3] = {f.i0 + w, f.j, f.k};
+        act = std_point<3>(B, g, I, 0) || DI[w] != T(0);
+      }
+      if (act) md = fmax(md, fabs(dv));
+    }
+  }
+  mx = block_max<kFlatThreads>(mx);
+  md = block_max<kFlatThreads>(md);
+  if (threadIdx.x == 0) {
+    part[flat_block()] = mx;
+    part_div[flat_block()] = md;
+  }
+}
+
 // PCG pass B, flat form (arithmetic of k_pcg_b_tile): q = A e from e and its
 // neighbours, x += alpha e, r -= alpha q, partials of rho_{k+1} and max|r|.
 template <typename T, bool PER, int FINE>

@@ -1389,6 +1389,14 @@ struct Impl : SimBase {
 
   // squared 2-norm of the fine residual (FP64 sum over the interior) into scal[kScalL2 + which]
   void res_sumsq(int which) {
+    const int nf = (int)nflat[0];
+    if (D == 3 && nf > 0) {
+      WL_TIMED(WL_K_REDUCE, (k_sumsq_flat<T><<<flat_grid(0), kFlatThreads, 0, stream>>>(g[0], r[0], wide)));
+      reduce_wide(wide, 0, nullptr, 0, nf, kSlotL2, -1);
+      WL_TIMED(WL_K_REDUCE, (k_finalize2<<<1, kFinalizeThreads, 0, stream>>>(slot(kSlotL2), 0, nullptr, 0, 1,
+                                                                             scal + kScalL2 + which, nullptr)));
+      return;
+    }
     const int rows = g[0].n[1] * (D == 3 ? g[0].n[2] : 1);
     const int gb = std::min(rows, kGridStride);
     WL_TIMED(WL_K_REDUCE, (k_sumsq<T, D><<<gb, kBlock, 0, stream>>>(g[0], r[0], slot(kSlotL2))));
@@ -1753,6 +1761,32 @@ struct Impl : SimBase {
     return WL_OK;
   }
 
+  // max over the cells of the CFL sum and of |div u| over the active cells, into
+  // scal (kScalCfl, kScalDiv): flat vectors on a 3-D fine level that takes them
+  wl_status cfl_max() {
+    const int nf = (int)nflat[0];
+    if (D == 3 && nf > 0) {
+      double* const pa = wide;
+      double* const pb = wide + wide_n;
+      if (desc.periodic_mask)
+        WL_TIMED(WL_K_CFL, (k_cfl_flat<T, true><<<flat_grid(0), kFlatThreads, 0, stream>>>(
+                               g[0], v3(u[cur]), iD[0], sbox[0], pa, pb)));
+      else
+        WL_TIMED(WL_K_CFL, (k_cfl_flat<T, false><<<flat_grid(0), kFlatThreads, 0, stream>>>(
+                               g[0], v3(u[cur]), iD[0], sbox[0], pa, pb)));
+      reduce_wide(pa, 1, pb, 1, nf, kSlotCfl, kSlotDiv);
+      WL_TIMED(WL_K_REDUCE, (k_finalize2<<<1, kFinalizeThreads, 0, stream>>>(slot(kSlotCfl), 1, slot(kSlotDiv), 1, 1,
+                                                                             scal + kScalCfl, scal + kScalDiv)));
+    } else {
+      WL_TIMED(WL_K_CFL, (k_cfl<T, D><<<nb[0], kBlock, 0, stream>>>(g[0], v3(u[cur]), iD[0], sbox[0],
+                                                                      slot(kSlotCfl), slot(kSlotDiv))));
+      WL_TIMED(WL_K_REDUCE, (k_finalize2<<<1, kFinalizeThreads, 0, stream>>>(
+                                slot(kSlotCfl), 1, slot(kSlotDiv), 1, nb[0], scal + kScalCfl, scal + kScalDiv)));
+    }
+    WL_HIP(hipGetLastError());
+    return WL_OK;
+  }
+
   // blend of the body box's faces after a fused flux launch: uo from f~ and, for
   // the corrector, this stage's velocity uu (nothing to do without a body box)
   wl_status bdim_box(int corr, T* const uu[3], T* const uo[3]) {
@@ -1855,11 +1889,8 @@ struct Impl : SimBase {
     if (!fuse) cur = 1 - cur;
     const double dt_used = dt;
     t += dt;
-    // CFL
-    WL_TIMED(WL_K_CFL, (k_cfl<T, D><<<nb[0], kBlock, 0, stream>>>(g[0], v3(u[cur]), iD[0], sbox[0], slot(kSlotCfl),
-                                                                    slot(kSlotDiv))));
-    WL_TIMED(WL_K_REDUCE, (k_finalize2<<<1, kFinalizeThreads, 0, stream>>>(slot(kSlotCfl), 1, slot(kSlotDiv), 1, nb[0],
-                                                                           scal + kScalCfl, scal + kScalDiv)));
+    // CFL (and the divergence check)
+    if ((s = cfl_max()) != WL_OK) return s;
     WL_HIP(hipGetLastError());
     // one read-back for the step's scalars: the outflux maximum, both residual 2-norms
     // and the divergence check
