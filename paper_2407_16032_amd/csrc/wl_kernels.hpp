@@ -702,25 +702,16 @@ __device__ __forceinline__ bool in_box3(const StdBox& B, const int I[3]) {
 // the ghost faces 0 and N+1 as inside; ghost faces are rewritten by the boundary
 // conditions straight after the blend, so they take the body-free form here.)
 // uo may be u0: each face reads u0 only at its own index, before its store.
-template <typename T, int FUSE>
-__global__ void __launch_bounds__(kReuseThreads) k_flux_reuse(Grid3 g, Vec3<T> u, Vec3<T> u0, Vec3<T> V, Vec3<T> f,
-                                                              Vec3<T> uo, T dt, T nu, int has_body, StdBox B,
-                                                              int nbx, int nby, int nbz) {
-  // one block per brick and component; the XCDs take contiguous ranges of
-  // (brick, component) with the component fastest, so the three blocks of a brick
-  // run together on one XCD and share the velocity they read through its L2
-  const int nb = nbx * nby * nbz * 3;
-  const int b = blockIdx.x;
-  const int full = (nb / 8) * 8;
-  const int tc = (b < full) ? (b % 8) * (nb / 8) + b / 8 : b;
-  const int c = tc % 3, t = tc / 3;
-  const int bx = t % nbx, r1 = t / nbx, by = r1 % nby, bz = r1 / nby;
-  const int lane = (int)threadIdx.x % kRX;
-  const int I0 = bx * (kRX - 1) + lane, I1 = by * kRW + (int)threadIdx.x / kRX;
-  const int P0 = g.n[0] + 2, P1 = g.n[1] + 2, P2 = g.n[2] + 2;
-  if (I1 >= P1) return;  // whole waves: no lane of the wave is needed, and no barrier follows
+// The column march of k_flux_reuse for component C (a compile-time constant, so
+// the advecting velocities that coincide with stencil values of u_C are loaded once).
+template <typename T, int FUSE, int C>
+__device__ __forceinline__ void flux_column(const Grid3& g, const Vec3<T>& u, const Vec3<T>& u0, const Vec3<T>& V,
+                                            const Vec3<T>& f, const Vec3<T>& uo, T dt, T nu, int has_body,
+                                            const StdBox& B, int lane, int I0, int I1, int z0) {
+  constexpr int c = C;
+  const int P0 = g.n[0] + 2, P2 = g.n[2] + 2;
   const bool col = lane < kRX - 1 && I0 < P0;
-  const int z0 = bz * kRZ, z1 = min(z0 + kRZ, P2);
+  const int z1 = min(z0 + kRZ, P2);
   T phz = phi_at<T>(g, u, c, 2, I0, I1, z0, nu);
   // x and y of the column are interior enough for the plain-offset form (with z)
   const bool fxy = I0 >= 3 && I0 <= g.n[0] - 2 && I1 >= 3 && I1 <= g.n[1] - 2;
@@ -792,6 +783,29 @@ __global__ void __launch_bounds__(kReuseThreads) k_flux_reuse(Grid3 g, Vec3<T> u
     }
     phz = phzn;
   }
+}
+
+template <typename T, int FUSE>
+__global__ void __launch_bounds__(kReuseThreads) k_flux_reuse(Grid3 g, Vec3<T> u, Vec3<T> u0, Vec3<T> V, Vec3<T> f,
+                                                              Vec3<T> uo, T dt, T nu, int has_body, StdBox B,
+                                                              int nbx, int nby, int nbz) {
+  // one block per brick and component; the XCDs take contiguous ranges of
+  // (brick, component) with the component fastest, so the three blocks of a brick
+  // run together on one XCD and share the velocity they read through its L2
+  const int nb = nbx * nby * nbz * 3;
+  const int b = blockIdx.x;
+  const int full = (nb / 8) * 8;
+  const int tc = (b < full) ? (b % 8) * (nb / 8) + b / 8 : b;
+  const int c = tc % 3, t = tc / 3;
+  const int bx = t % nbx, r1 = t / nbx, by = r1 % nby, bz = r1 / nby;
+  const int lane = (int)threadIdx.x % kRX;
+  const int I0 = bx * (kRX - 1) + lane, I1 = by * kRW + (int)threadIdx.x / kRX;
+  if (I1 >= g.n[1] + 2) return;  // whole waves: no lane of the wave is needed, and no barrier follows
+  const int z0 = bz * kRZ;
+  // c is the same for the whole block
+  if (c == 0) flux_column<T, FUSE, 0>(g, u, u0, V, f, uo, dt, nu, has_body, B, lane, I0, I1, z0);
+  else if (c == 1) flux_column<T, FUSE, 1>(g, u, u0, V, f, uo, dt, nu, has_body, B, lane, I0, I1, z0);
+  else flux_column<T, FUSE, 2>(g, u, u0, V, f, uo, dt, nu, has_body, B, lane, I0, I1, z0);
 }
 
 // BDIM blend of face I of component c: out = V + mu0 f + sum_j mu1_cj
