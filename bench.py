@@ -423,6 +423,8 @@ def main():
                     help="kernels of the large 3-D multigrid levels (same arithmetic)")
     ap.add_argument("--blend", default="auto", choices=["auto", "separate"],
                     help="BDIM blend inside the 3-D flux launch outside the body box (auto) or a separate pass")
+    ap.add_argument("--vcycle-graph", default="auto", choices=["auto", "off", "on"],
+                    help="replay the coarse part of each multigrid cycle from a HIP graph (auto: unless the body moves)")
     ap.add_argument("--no-profile", action="store_true", help="skip per-kernel event timing")
     ap.add_argument("--adjoint", action="store_true",
                     help="run the rotating-cylinder gradient case instead (adjoint vs forward cost)")
@@ -472,7 +474,7 @@ def main():
           flush=True)
     sim = Simulation(w.n, w.U, w.nu, body, periodic=w.periodic_mask(), convective_exit=w.convective_exit,
                      prec="f32", tol=w.tol, itmax=32, device="cuda:0", solver_path=args.solver_path,
-                     blend_mode=args.blend)
+                     blend_mode=args.blend, vcycle_graph=args.vcycle_graph)
     sim.set_velocity(wlsynth.initial_velocity(w, seed=0))
     for k in range(args.warmup):
         sim.step()
@@ -603,7 +605,8 @@ def main():
         "config": {"workload": w.name, "cells": w.cells,
                    "Re": round((math.sqrt(sum(u * u for u in w.U)) or 1.0) * w.L / w.nu, 1) if w.nu else None,
                    "mg_tol": w.tol, "moving_body": bool(body is not None and body.moving),
-                   "convective_exit": w.convective_exit, "blend": args.blend, "parallelism": "single GPU"},
+                   "convective_exit": w.convective_exit, "blend": args.blend, "vcycle_graph": args.vcycle_graph,
+                   "parallelism": "single GPU"},
         "windows_ms_per_step": [round(v, 3) for v in windows],
         "vcycles_per_step": round(kmean, 3),
         "vcycle_factor": round(float(np.exp(np.mean(np.log(factors)))), 4) if factors else None,

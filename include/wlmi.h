@@ -101,6 +101,16 @@ typedef struct {
                             so WL_FIELD_U0 afterwards holds the predictor's projected
                             velocity), 1 = always a separate pass over every face after
                             the flux launch.  Same arithmetic and the same results. [0] */
+  int vcycle_graph;      /* 2 = the coarse part of each multigrid cycle (restriction, the
+                            coarse levels' PCG, the bottom solve, prolongation) is captured
+                            in a HIP graph (on a stream of the library's own) and
+                            replayed on the sim's stream while the partial-sum counts and
+                            body boxes it was captured with hold (not while the profiler
+                            times those kernels; a capture that fails turns graphs off for
+                            the sim); 1 = plain launches; 0 = automatic: as 2 unless the
+                            body moves (its box, a launch argument, then changes from step
+                            to step), else as 1.  The same kernels with the same
+                            arguments. [0] */
 } wl_sim_desc;
 
 typedef enum {

@@ -36,7 +36,7 @@ class SimDesc(C.Structure):
                 ("cfl_nu_coef", C.c_double), ("mg_tol", C.c_double), ("mg_itmax", C.c_int),
                 ("pcg_iters", C.c_int), ("learned_guess", C.c_int), ("adjoint", C.c_int),
                 ("solver_path", C.c_int), ("reduce_mode", C.c_int),
-                ("blend_mode", C.c_int)]
+                ("blend_mode", C.c_int), ("vcycle_graph", C.c_int)]
 
 
 class BodyDesc(C.Structure):

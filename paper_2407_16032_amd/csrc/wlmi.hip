@@ -101,6 +101,7 @@ wl_status validate_and_default(const wl_sim_desc* in, wl_sim_desc* d) {
   if (d->solver_path < 0 || d->solver_path > 3) return fail(WL_ERR_INVALID_ARG, "solver_path must be in [0, 3]");
   if (d->reduce_mode < 0 || d->reduce_mode > 2) return fail(WL_ERR_INVALID_ARG, "reduce_mode must be in [0, 2]");
   if (d->blend_mode < 0 || d->blend_mode > 1) return fail(WL_ERR_INVALID_ARG, "blend_mode must be 0 or 1");
+  if (d->vcycle_graph < 0 || d->vcycle_graph > 2) return fail(WL_ERR_INVALID_ARG, "vcycle_graph must be in [0, 2]");
   if (d->convective_exit) {
     if (d->periodic_mask & 1u) return fail(WL_ERR_INVALID_ARG, "convective exit needs a non-periodic x axis");
     if (d->U[0] == 0.0) return fail(WL_ERR_INVALID_ARG, "convective exit needs U[0] != 0");
@@ -578,6 +579,26 @@ struct Impl : SimBase {
   Planes planes{};
   int plane_blocks = 1;
   bool exit_valid = false;
+  // The coarse part of a multigrid cycle (restriction, the PCG of every coarse
+  // level, the bottom solve, prolongation) captured in HIP graphs and replayed:
+  // ~150 small launches per cycle, each dispatched faster from a graph (2-3 % of
+  // the step on grids of a few million cells).  A graph is reused when the
+  // host-side partial counts and the body boxes (launch arguments) are those it
+  // was captured with.
+  struct VcGraph {
+    bool valid = false;
+    int pre[kNumSlots] = {}, post[kNumSlots] = {};
+    StdBox box[kMaxLevels] = {};
+    hipGraphExec_t exec = nullptr;
+  };
+  static constexpr int kVcGraphs = 4;
+  VcGraph vcg[kVcGraphs];
+  int vcg_next = 0;
+  bool vcg_off = false;  // after a capture that failed: plain launches
+  // captures run on a stream of their own (the sim's stream may be the null stream,
+  // which cannot be captured); nothing captured executes until the graph is
+  // launched on the sim's stream
+  hipStream_t cap_stream = nullptr;
   int slot_n[kNumSlots] = {};  // partials written by the last producer of each slot
   int box_lo[3] = {}, box_hi[3] = {};
   bool have_box = false;
@@ -1298,6 +1319,75 @@ struct Impl : SimBase {
     WL_TIMED(WL_K_COARSE, (k_bottom<T, D><<<1, kBottom, 0, stream>>>(bl)));
   }
 
+  bool vcg_allowed() const {
+    if (vcg_off || desc.vcycle_graph == 1) return false;
+    // a moving body changes the body boxes (launch arguments) as it goes, and each
+    // new box costs a capture: automatic mode keeps plain launches for it
+    if (desc.vcycle_graph == 0 && moving) return false;
+    // events cannot be recorded inside a graph: no graph while its kernels are timed
+    constexpr uint32_t inside =
+        (1u << WL_K_RESTRICT) | (1u << WL_K_PROLONG) | (1u << WL_K_COARSE) | (1u << WL_K_REDUCE);
+    return !prof.on || (prof.groups & inside) == 0;
+  }
+
+  // vcycle(0), through a cached graph where one matches (else captured, then
+  // launched); plain launches where graphs are not allowed.  A failed capture
+  // turns graphs off for the sim (for instance when the caller is itself
+  // capturing the sim's stream).
+  wl_status vcycle_top() {
+    if (!vcg_allowed()) {
+      vcycle(0);
+      return WL_OK;
+    }
+    const size_t bbytes = sizeof(StdBox) * (size_t)nlev;
+    for (auto& gr : vcg)
+      if (gr.valid && std::memcmp(gr.pre, slot_n, sizeof(slot_n)) == 0 && std::memcmp(gr.box, sbox, bbytes) == 0) {
+        WL_HIP(hipGraphLaunch(gr.exec, stream));
+        std::memcpy(slot_n, gr.post, sizeof(slot_n));
+        return WL_OK;
+      }
+    int pre[kNumSlots];
+    std::memcpy(pre, slot_n, sizeof(slot_n));
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    hipError_t he = hipSuccess;
+    if (!cap_stream) he = hipStreamCreateWithFlags(&cap_stream, hipStreamNonBlocking);
+    if (he == hipSuccess) he = hipStreamBeginCapture(cap_stream, hipStreamCaptureModeThreadLocal);
+    if (he == hipSuccess) {
+      hipStream_t own = stream;
+      stream = cap_stream;  // every launch of the cycle goes to the capture
+      vcycle(0);
+      stream = own;
+      he = hipStreamEndCapture(cap_stream, &graph);
+    }
+    if (he == hipSuccess) he = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    if (graph) (void)hipGraphDestroy(graph);
+    if (he != hipSuccess) {
+      // nothing of the captured cycle ran: plain launches from here on
+      (void)hipGetLastError();
+      vcg_off = true;
+      std::memcpy(slot_n, pre, sizeof(slot_n));
+      vcycle(0);
+      return WL_OK;
+    }
+    VcGraph& gr = vcg[vcg_next];
+    vcg_next = (vcg_next + 1) % kVcGraphs;
+    if (gr.valid && gr.exec) (void)hipGraphExecDestroy(gr.exec);
+    gr.valid = true;
+    gr.exec = exec;
+    std::memcpy(gr.pre, pre, sizeof(pre));
+    std::memcpy(gr.post, slot_n, sizeof(slot_n));
+    std::memcpy(gr.box, sbox, bbytes);
+    WL_HIP(hipGraphLaunch(exec, stream));
+    return WL_OK;
+  }
+
+  ~Impl() override {
+    for (auto& gr : vcg)
+      if (gr.valid && gr.exec) (void)hipGraphExecDestroy(gr.exec);
+    if (cap_stream) (void)hipStreamDestroy(cap_stream);
+  }
+
   void vcycle(int l) {
     if (nflat[l + 1] > 0) {
       const int nf = (int)nflat[l + 1];
@@ -1413,7 +1503,9 @@ struct Impl : SimBase {
     double res = res0;
     int n = 0;
     while (res >= tol && n < itmax) {
-      if (nlev > 1) vcycle(0);
+      if (nlev > 1) {
+        if ((s = vcycle_top()) != WL_OK) return s;
+      }
       else {
         WL_TIMED(WL_K_DIVRES, (k_mean0<T, D><<<nb[0], kBlock, 0, stream>>>(g[0], iD[0], r[0], red, flags)));
         set_mean_producer(nb[0]);

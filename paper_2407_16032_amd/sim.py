@@ -79,7 +79,7 @@ class Simulation:
                  tol: float = 1e-6, itmax: int = 32, pcg_iters: int = 6, device="cuda:0",
                  stream: Optional[torch.cuda.Stream] = None, learned_guess: bool = False,
                  adjoint: bool = False, solver_path: str = "auto", L_ref: float = 1.0,
-                 reduce_mode: str = "auto", blend_mode: str = "auto"):
+                 reduce_mode: str = "auto", blend_mode: str = "auto", vcycle_graph: str = "auto"):
         self.lib = L.load()
         nd = len(n)
         d = L.SimDesc()
@@ -99,6 +99,7 @@ class Simulation:
         d.solver_path = {"auto": 0, "tiles": 1, "flat": 2, "generic": 3}[solver_path]
         d.reduce_mode = {"auto": 0, "single": 1, "two_stage": 2}[reduce_mode]
         d.blend_mode = {"auto": 0, "separate": 1}[blend_mode]
+        d.vcycle_graph = {"auto": 0, "off": 1, "on": 2}[vcycle_graph]
         self.desc = d
         self.ndim = nd
         self.n = tuple(int(v) for v in n)

@@ -93,7 +93,8 @@ def test_workspace_bytes_and_validation(lib):
     assert lib.wl_workspace_bytes(C.byref(ex), C.byref(b)) == 0
     # the mode switches take their documented values only; the blend's place does
     # not change the workspace
-    for field, good, badv in (("solver_path", 3, 4), ("reduce_mode", 2, 3), ("blend_mode", 1, 2)):
+    for field, good, badv in (("solver_path", 3, 4), ("reduce_mode", 2, 3), ("blend_mode", 1, 2),
+                              ("vcycle_graph", 2, 3)):
         m = _desc()
         setattr(m, field, good)
         assert lib.wl_workspace_bytes(C.byref(m), C.byref(b)) > 0, field
