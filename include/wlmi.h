@@ -110,7 +110,10 @@ typedef struct {
                             the sim); 1 = plain launches; 0 = automatic: as 2 unless the
                             body moves (its box, a launch argument, then changes from step
                             to step), else as 1.  The same kernels with the same
-                            arguments. [0] */
+                            arguments.  Graphs, and the one capture stream, are HIP runtime
+                            objects the library creates at the first step (no workspace
+                            memory); a caller that allows no runtime object creation after
+                            wl_sim_create sets 1. [0] */
 } wl_sim_desc;
 
 typedef enum {
