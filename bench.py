@@ -224,7 +224,7 @@ def measured_traffic(workload, kernel):
     path = os.path.join(ROOT, "profiles", "pmc_%s.md" % workload)
     if not os.path.exists(path):
         return None
-    key = {"pcg_a": "k_pcg_a_flat_fine", "pcg_b": "k_pcg_b_flat_fine"}.get(kernel)
+    key = {"pcg_a": "k_pcg_a_flat_fine", "pcg_b": "k_pcg_b_flat_fine", "flux": "k_flux_reuse_mean"}.get(kernel)
     src, val = None, None
     with open(path) as f:
         for line in f:
