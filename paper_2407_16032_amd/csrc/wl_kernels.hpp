@@ -2203,8 +2203,11 @@ __device__ __forceinline__ T pcg_e(T d, T r, T e, T beta, T mean, int k) {
 // L_f (e_i - e_j)^2; each cell takes its three - faces (a periodic axis wraps
 // face 1 to cell N; a non-periodic boundary face has L = 0, and a solid cell,
 // iD = 0, has only zero faces).
+// (FP32: at least 8 waves per SIMD, 61 registers without spills, 1 % faster
+// than the 66 the compiler picks by itself)
 template <typename T, bool PER, int FINE>
-__global__ void __launch_bounds__(kFlatThreads) k_pcg_a_fused_flat(Grid3 g, Vec3<T> L, const T* iD, const T* r,
+__global__ void __launch_bounds__(kFlatThreads) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 8 : 1)))
+k_pcg_a_fused_flat(Grid3 g, Vec3<T> L, const T* iD, const T* r,
                                                                    const T* eo, T* en, double* red, int k, RedN rn,
                                                                    double* part_sig, double* part_rho0, int* flag,
                                                                    StdBox B) {
