@@ -72,6 +72,19 @@ def test_byte_model_invariants():
     assert bench.model_bytes("pcg_b", 3, CELLS, 4) >= kb("pcg_b", BOX)
 
 
+def test_byte_model_of_the_blend_in_the_flux_launch():
+    # the 3-D step's flux launch writes the blended velocity instead of f~ (same
+    # bytes) and f~ again within one face of the body box; the blend launch then
+    # moves only the box's faces
+    kb = lambda name, fused, body=True: bench.kernel_bytes(  # noqa: E731
+        name, 3, CELLS, FACES, 4, body, 6, BOX, BOX, True, True, fused=fused)
+    assert kb("flux", True) == kb("flux", False) + 3 * BOX * 4
+    assert kb("flux", True, body=False) == kb("flux", False, body=False)
+    assert kb("bdim", True) < kb("bdim", False)
+    # outside the box nothing of the blend launch remains
+    assert kb("bdim", True) == (3 + 1.5 + 3 + 3 + 3 + 9) * BOX * 4
+
+
 def test_step_byte_model_matches_the_fixed_model():
     # 3-D with a body at k = 4 V-cycles: 4 (79 + 4 x 105.4) = 2002.4 bytes per cell
     assert bench.step_byte_model(3, True, 4.0) == pytest.approx(2002.4)
