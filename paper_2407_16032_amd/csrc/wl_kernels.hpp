@@ -2028,19 +2028,20 @@ struct FlatVec {
   int i0, j, k, id;
   bool ok;
 };
-template <typename T>
+template <typename T, bool REV = false>
 __device__ __forceinline__ FlatVec flat_vec(const Grid3& g) {
   constexpr int W = Vec16<T>::W;
-  // grid: x = the blocks of one plane, y = the plane
+  // grid: x = the blocks of one plane, y = the plane (REV: the last block first)
   const unsigned vr = (unsigned)(g.n[0] / W);
-  const unsigned t = blockIdx.x * (unsigned)kFlatThreads + threadIdx.x;
+  const unsigned bxx = REV ? gridDim.x - 1 - blockIdx.x : blockIdx.x;
+  const unsigned t = bxx * (unsigned)kFlatThreads + threadIdx.x;
   FlatVec f;
   f.ok = t < vr * (unsigned)g.n[1];
   const unsigned tt = f.ok ? t : 0u;
   const unsigned row = tt / vr;
   f.i0 = 1 + (int)(tt - row * vr) * W;
   f.j = (int)row + 1;
-  f.k = (int)blockIdx.y + 1;
+  f.k = (int)(REV ? gridDim.y - 1 - blockIdx.y : blockIdx.y) + 1;
   f.id = f.i0 + f.j * g.s[1] + f.k * g.s[2];
   return f;
 }
@@ -2406,7 +2407,9 @@ __global__ void __launch_bounds__(kFlatThreads) k_pcg_b_flat(Grid3 g, Vec3<T> L,
     }
   }
   if (skip && !want_max && mean == T(0)) return;  // grid-uniform
-  const FlatVec f = flat_vec<T>(g);
+  // the blocks in reverse order (the last vectors first): this pass and the pass A
+  // after it ran 0.5-0.8 % faster than with both in the same order
+  const FlatVec f = flat_vec<T, true>(g);
   double rho = 0.0, mx = 0.0;
   if (f.ok) {
     const FlatNbr<W, PER> o(g, f);
