@@ -6,6 +6,8 @@
 // flat one-vector-per-thread kernels, whose many blocks leave their partials
 // in a separate area that a two-stage sum reduces.
 #pragma once
+#include <type_traits>
+
 #include "wl_device.hpp"
 
 namespace wl {
@@ -713,27 +715,36 @@ __device__ __forceinline__ void flux_column(const Grid3& g, const Vec3<T>& u, co
   const bool col = lane < kRX - 1 && I0 < P0;
   const int z1 = min(z0 + kRZ, P2);
   T phz = phi_at<T>(g, u, c, 2, I0, I1, z0, nu);
-  // x and y of the column are interior enough for the plain-offset form (with z)
-  const bool fxy = I0 >= 3 && I0 <= g.n[0] - 2 && I1 >= 3 && I1 <= g.n[1] - 2;
-  for (int I2 = z0; I2 < z1; ++I2) {
+  // u_C at the face and at -1, +1 in z, carried from plane to plane on the fast path
+  T cz0 = T(0), cz1 = T(0), cz2 = T(0);
+  // one plane of the march; FAST (the plain-offset stencil, every lane of the
+  // wave interior enough for it) or the general form per lane
+  auto plane = [&](auto fast_tag, int I2) {
+    constexpr bool FAST = decltype(fast_tag)::value;
     T phx, phy, phyn, phzn;
     // u0 at the face (column clamped into the row for the lanes that store nothing)
     // is loaded ahead of the stencil; with FUSE = 2 also u at the face
     const int idx = lin3<T, 3>(g, min(I0, P0 - 1), I1, I2);
     const T u0v = u0.c[c][idx];
     T uself = T(0);
-    if (fxy && I2 >= 3 && I2 <= g.n[2] - 2) {
+    if (FAST) {
       // one straight block of loads: every value the four face fluxes can use,
       // both QUICK far points of each included, so no address waits for the
       // upwind test and the whole stencil is one round trip to memory
       const int id = idx, sc = g.s[c], s1 = g.s[1], s2 = g.s[2];
       const T* q = u.c[c];
-      const T c0 = q[id], xm1 = q[id - 1], xm2 = q[id - 2], xp1 = q[id + 1];
+      const T zm1 = cz0, c0 = cz1, zp1 = cz2;
+      const T xm1 = q[id - 1], xm2 = q[id - 2], xp1 = q[id + 1];
       const T ym1 = q[id - s1], ym2 = q[id - 2 * s1], yp1 = q[id + s1], yp2 = q[id + 2 * s1];
-      const T zm1 = q[id - s2], zp1 = q[id + s2], zp2 = q[id + 2 * s2];
-      const T ax0 = u.c[0][id], ax1 = u.c[0][id - sc];
-      const T ay0 = u.c[1][id], ay1 = u.c[1][id - sc], ayn0 = u.c[1][id + s1], ayn1 = u.c[1][id + s1 - sc];
-      const T azn0 = u.c[2][id + s2], azn1 = u.c[2][id + s2 - sc];
+      const T zp2 = q[id + 2 * s2];
+      cz0 = c0;
+      cz1 = zp1;
+      cz2 = zp2;
+      // the advecting velocities; those of component C are values of the stencil
+      const T ax0 = C == 0 ? c0 : u.c[0][id], ax1 = C == 0 ? xm1 : u.c[0][id - sc];
+      const T ay0 = C == 1 ? c0 : u.c[1][id], ay1 = C == 1 ? ym1 : u.c[1][id - sc];
+      const T ayn0 = C == 1 ? yp1 : u.c[1][id + s1], ayn1 = C == 1 ? c0 : u.c[1][id + s1 - sc];
+      const T azn0 = C == 2 ? zp1 : u.c[2][id + s2], azn1 = C == 2 ? c0 : u.c[2][id + s2 - sc];
       phx = phi_vals<T>(ax0, ax1, c0, xm1, xm2, xp1, nu);
       phy = phi_vals<T>(ay0, ay1, c0, ym1, ym2, yp1, nu);
       phyn = phi_vals<T>(ayn0, ayn1, yp1, c0, ym1, yp2, nu);
@@ -782,7 +793,25 @@ __device__ __forceinline__ void flux_column(const Grid3& g, const Vec3<T>& u, co
       }
     }
     phz = phzn;
+  };
+  // planes [za, zb) take the fast path: the march is split into three loops, so
+  // the fast loop's body has no branch whose join would make it wait for u0
+  // before the stencil's loads go out (the two may be in flight together)
+  int za = z0, zb = z0;
+  const bool fxy = I0 >= 3 && I0 <= g.n[0] - 2 && I1 >= 3 && I1 <= g.n[1] - 2;
+  if (__builtin_amdgcn_ballot_w64(fxy) == __builtin_amdgcn_read_exec()) {
+    za = min(max(z0, 3), z1);
+    zb = max(za, min(z1, g.n[2] - 1));
   }
+  for (int I2 = z0; I2 < za; ++I2) plane(std::false_type{}, I2);
+  if (za < zb) {
+    const int id = lin3<T, 3>(g, I0, I1, za), s2 = g.s[2];
+    cz0 = u.c[c][id - s2];
+    cz1 = u.c[c][id];
+    cz2 = u.c[c][id + s2];
+  }
+  for (int I2 = za; I2 < zb; ++I2) plane(std::true_type{}, I2);
+  for (int I2 = zb; I2 < z1; ++I2) plane(std::false_type{}, I2);
 }
 
 template <typename T, int FUSE>
