@@ -159,6 +159,11 @@ template <typename T>
 __device__ __forceinline__ T median3(T a, T b, T c) {
   return fmax(fmin(a, b), fmin(fmax(a, b), c));
 }
+// the same median in one instruction (finite arguments; the result is one of them)
+template <>
+__device__ __forceinline__ float median3<float>(float a, float b, float c) {
+  return __builtin_amdgcn_fmed3f(a, b, c);
+}
 
 // kappa = 1/3 upwind-biased face value, clamped by the median-form limiter.
 template <typename T>

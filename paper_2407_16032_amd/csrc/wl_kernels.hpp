@@ -678,6 +678,29 @@ __device__ __forceinline__ float pick_far<float>(bool up, float fm, float fp) {
   return r;
 }
 
+// p, the same in every lane, as a scalar value that the loop optimiser cannot
+// turn into per-lane pointers: each load's address is then that scalar base
+// plus a lane offset kept for the whole march (one add), instead of a 64-bit
+// pointer per field and plane held in vector registers
+typedef __attribute__((address_space(1))) char gchar;  // global memory
+__device__ __forceinline__ gchar* uniform_ptr(const void* p) {
+  const uint64_t v = reinterpret_cast<uint64_t>(p);
+  const uint32_t lo = __builtin_amdgcn_readfirstlane(uint32_t(v));
+  const uint32_t hi = __builtin_amdgcn_readfirstlane(uint32_t(v >> 32));
+  return reinterpret_cast<gchar*>((uint64_t(hi) << 32) | lo);
+}
+
+// x's value in the next lane (lane 63 gets an unspecified value): a DPP wave
+// shift in FP32, one VALU instruction instead of a permute through the LDS unit
+template <typename T>
+__device__ __forceinline__ T next_lane(T x) {
+  return __shfl_down(x, 1, 64);
+}
+template <>
+__device__ __forceinline__ float next_lane<float>(float x) {
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(x), 0x130, 0xf, 0xf, false));  // wave_shl:1
+}
+
 // phi_fast's flux from values already loaded: a = (a0 + a1)/2, uc and m1 at the
 // face and its -j neighbour, fm / fp the far point for a >= 0 / a < 0
 template <typename T>
@@ -685,7 +708,9 @@ __device__ __forceinline__ T phi_vals(T a0, T a1, T uc, T m1, T fm, T fp, T nu) 
   const T a = T(0.5) * (a0 + a1);
   const bool up = a >= T(0);
   const T far = pick_far<T>(up, fm, fp);
-  const T Q = up ? quick_lim(far, m1, uc) : quick_lim(far, uc, m1);
+  // one limiter on arguments picked by the upwind test (the same value as the
+  // two-sided select of the general form)
+  const T Q = quick_lim(far, up ? m1 : uc, up ? uc : m1);
   return a * Q - nu * (uc - m1);
 }
 
@@ -717,6 +742,27 @@ __device__ __forceinline__ void flux_column(const Grid3& g, const Vec3<T>& u, co
   T phz = phi_at<T>(g, u, c, 2, I0, I1, z0, nu);
   // u_C at the face and at -1, +1 in z, carried from plane to plane on the fast path
   T cz0 = T(0), cz1 = T(0), cz2 = T(0);
+  // fast-path addresses: a base per field and plane, the same for the whole wave,
+  // plus one of five 32-bit byte offsets per lane (the column and its +-1, +-2
+  // rows in y) and an immediate for the x offsets, so no lane computes a 64-bit
+  // address; the offsets are used only on the fast path, where I0, I1 >= 3
+  // fast-path addresses: a base per field and plane, the same for the whole wave,
+  // plus one of five 32-bit byte offsets per lane (the column and its +-1, +-2
+  // rows in y) and a constant for the x offsets, so that no lane computes a full
+  // address per load; the offsets are used only on the fast path (I0, I1 >= 3)
+  const int s1 = g.s[1], s2 = g.s[2];
+  constexpr int E = int(sizeof(T));
+  const uint32_t ob = uint32_t(I0 + I1 * s1) * uint32_t(E), sb = uint32_t(s1) * uint32_t(E);
+  const uint32_t oy[5] = {ob - 2 * sb, ob - sb, ob, ob + sb, ob + 2 * sb};
+  // value at row offset dy (-2..2) and x offset dx of plane I2 + dz of field q
+  typedef __attribute__((address_space(1))) T gT;
+  auto at = [&](const T* q, int I2, int dz, int dy, int dx) -> T {
+    gchar* base = uniform_ptr(q + size_t(I2 + dz) * size_t(s2));
+    return *reinterpret_cast<gT*>(base + size_t(oy[dy + 2]) + dx * E);
+  };
+  auto put_fast = [&](T* q, int I2, T val) {
+    *reinterpret_cast<gT*>(uniform_ptr(q + size_t(I2) * size_t(s2)) + size_t(ob)) = val;
+  };
   // one plane of the march; FAST (the plain-offset stencil, every lane of the
   // wave interior enough for it) or the general form per lane
   auto plane = [&](auto fast_tag, int I2) {
@@ -725,39 +771,46 @@ __device__ __forceinline__ void flux_column(const Grid3& g, const Vec3<T>& u, co
     // u0 at the face (column clamped into the row for the lanes that store nothing)
     // is loaded ahead of the stencil; with FUSE = 2 also u at the face
     const int idx = lin3<T, 3>(g, min(I0, P0 - 1), I1, I2);
-    const T u0v = u0.c[c][idx];
+    T u0v;
     T uself = T(0);
     if (FAST) {
+      u0v = at(u0.c[c], I2, 0, 0, 0);
+      // keeps the load here: the compiler would otherwise sink it into the
+      // store block below, after the fluxes, a second round trip per plane
+      asm volatile("" ::: "memory");
       // one straight block of loads: every value the four face fluxes can use,
       // both QUICK far points of each included, so no address waits for the
       // upwind test and the whole stencil is one round trip to memory
-      const int id = idx, sc = g.s[c], s1 = g.s[1], s2 = g.s[2];
       const T* q = u.c[c];
       const T zm1 = cz0, c0 = cz1, zp1 = cz2;
-      const T xm1 = q[id - 1], xm2 = q[id - 2], xp1 = q[id + 1];
-      const T ym1 = q[id - s1], ym2 = q[id - 2 * s1], yp1 = q[id + s1], yp2 = q[id + 2 * s1];
-      const T zp2 = q[id + 2 * s2];
+      const T xm1 = at(q, I2, 0, 0, -1), xm2 = at(q, I2, 0, 0, -2), xp1 = at(q, I2, 0, 0, 1);
+      const T ym1 = at(q, I2, 0, -1, 0), ym2 = at(q, I2, 0, -2, 0), yp1 = at(q, I2, 0, 1, 0),
+              yp2 = at(q, I2, 0, 2, 0);
+      const T zp2 = at(q, I2, 2, 0, 0);
       cz0 = c0;
       cz1 = zp1;
       cz2 = zp2;
-      // the advecting velocities; those of component C are values of the stencil
-      const T ax0 = C == 0 ? c0 : u.c[0][id], ax1 = C == 0 ? xm1 : u.c[0][id - sc];
-      const T ay0 = C == 1 ? c0 : u.c[1][id], ay1 = C == 1 ? ym1 : u.c[1][id - sc];
-      const T ayn0 = C == 1 ? yp1 : u.c[1][id + s1], ayn1 = C == 1 ? c0 : u.c[1][id + s1 - sc];
-      const T azn0 = C == 2 ? zp1 : u.c[2][id + s2], azn1 = C == 2 ? c0 : u.c[2][id + s2 - sc];
+      // the advecting velocities (at the face and at its -C neighbour); those of
+      // component C are values of the stencil
+      const int cx = C == 0 ? -1 : 0, cy = C == 1 ? -1 : 0, cz = C == 2 ? -1 : 0;
+      const T ax0 = C == 0 ? c0 : at(u.c[0], I2, 0, 0, 0), ax1 = C == 0 ? xm1 : at(u.c[0], I2, cz, cy, cx);
+      const T ay0 = C == 1 ? c0 : at(u.c[1], I2, 0, 0, 0), ay1 = C == 1 ? ym1 : at(u.c[1], I2, cz, cy, cx);
+      const T ayn0 = C == 1 ? yp1 : at(u.c[1], I2, 0, 1, 0), ayn1 = C == 1 ? c0 : at(u.c[1], I2, cz, 1 + cy, cx);
+      const T azn0 = C == 2 ? zp1 : at(u.c[2], I2, 1, 0, 0), azn1 = C == 2 ? c0 : at(u.c[2], I2, 1 + cz, cy, cx);
       phx = phi_vals<T>(ax0, ax1, c0, xm1, xm2, xp1, nu);
       phy = phi_vals<T>(ay0, ay1, c0, ym1, ym2, yp1, nu);
       phyn = phi_vals<T>(ayn0, ayn1, yp1, c0, ym1, yp2, nu);
       phzn = phi_vals<T>(azn0, azn1, zp1, c0, zm1, zp2, nu);
       if (FUSE == 2) uself = c0;
     } else {
+      u0v = u0.c[c][idx];
       phx = phi_at<T>(g, u, c, 0, I0, I1, I2, nu);
       phy = phi_at<T>(g, u, c, 1, I0, I1, I2, nu);
       phyn = phi_at<T>(g, u, c, 1, I0, I1 + 1, I2, nu);
       phzn = phi_at<T>(g, u, c, 2, I0, I1, I2 + 1, nu);
       if (FUSE == 2) uself = u.c[c][idx];
     }
-    const T phxn = __shfl_down(phx, 1, kRX);  // every lane of the wave takes part
+    const T phxn = next_lane<T>(phx);  // every lane of the wave takes part
     if (col) {
       const int I[3] = {I0, I1, I2};
       bool unknown = true, wraps = false;
@@ -768,7 +821,7 @@ __device__ __forceinline__ void flux_column(const Grid3& g, const Vec3<T>& u, co
         wraps = wraps || (g.per[a] && I[a] == g.n[a]);
       }
       const bool needV = has_body && !std_point<3>(B, g, I, 0);  // V = 0 outside the box
-      const T vb = needV ? V.c[c][idx] : T(0);
+      const T vb = needV ? (FAST ? at(V.c[c], I2, 0, 0, 0) : V.c[c][idx]) : T(0);
       T R = T(0);
       if (unknown) {
         if (wraps) {
@@ -781,14 +834,18 @@ __device__ __forceinline__ void flux_column(const Grid3& g, const Vec3<T>& u, co
       }
       T v = u0v + dt * R;
       if (needV) v = v - vb;
+      auto put = [&](T* q, T val) {
+        if (FAST) put_fast(q, I2, val);
+        else q[idx] = val;
+      };
       if (FUSE == 0) {
-        f.c[c][idx] = v;
+        put(f.c[c], v);
       } else {
-        if (has_body && !std_point<3>(B, g, I, 1)) f.c[c][idx] = v;
+        if (has_body && !std_point<3>(B, g, I, 1)) put(f.c[c], v);
         if (!in_box3(B, I)) {
           T acc = has_body ? L_std<T>(g, B, c, I[c]) * v : v;
           if (FUSE == 2) acc = T(0.5) * (uself + acc);
-          uo.c[c][idx] = acc;
+          put(uo.c[c], acc);
         }
       }
     }
@@ -805,10 +862,9 @@ __device__ __forceinline__ void flux_column(const Grid3& g, const Vec3<T>& u, co
   }
   for (int I2 = z0; I2 < za; ++I2) plane(std::false_type{}, I2);
   if (za < zb) {
-    const int id = lin3<T, 3>(g, I0, I1, za), s2 = g.s[2];
-    cz0 = u.c[c][id - s2];
-    cz1 = u.c[c][id];
-    cz2 = u.c[c][id + s2];
+    cz0 = at(u.c[c], za, -1, 0, 0);
+    cz1 = at(u.c[c], za, 0, 0, 0);
+    cz2 = at(u.c[c], za, 1, 0, 0);
   }
   for (int I2 = za; I2 < zb; ++I2) plane(std::true_type{}, I2);
   for (int I2 = zb; I2 < z1; ++I2) plane(std::false_type{}, I2);
