@@ -813,12 +813,16 @@ __device__ __forceinline__ void flux_column(const Grid3& g, const Vec3<T>& u, co
     const T phxn = next_lane<T>(phx);  // every lane of the wave takes part
     if (col) {
       const int I[3] = {I0, I1, I2};
+      // on the fast planes every face is an unknown two or more cells from each
+      // boundary: no wrap, and L = B.Lstd
       bool unknown = true, wraps = false;
+      if (!FAST) {
 #pragma unroll
-      for (int a = 0; a < 3; ++a) {
-        const int lo = (a == c && !g.per[a]) ? 2 : 1;
-        unknown = unknown && I[a] >= lo && I[a] <= g.n[a];
-        wraps = wraps || (g.per[a] && I[a] == g.n[a]);
+        for (int a = 0; a < 3; ++a) {
+          const int lo = (a == c && !g.per[a]) ? 2 : 1;
+          unknown = unknown && I[a] >= lo && I[a] <= g.n[a];
+          wraps = wraps || (g.per[a] && I[a] == g.n[a]);
+        }
       }
       const bool needV = has_body && !std_point<3>(B, g, I, 0);  // V = 0 outside the box
       const T vb = needV ? (FAST ? at(V.c[c], I2, 0, 0, 0) : V.c[c][idx]) : T(0);
@@ -843,7 +847,7 @@ __device__ __forceinline__ void flux_column(const Grid3& g, const Vec3<T>& u, co
       } else {
         if (has_body && !std_point<3>(B, g, I, 1)) put(f.c[c], v);
         if (!in_box3(B, I)) {
-          T acc = has_body ? L_std<T>(g, B, c, I[c]) * v : v;
+          T acc = has_body ? (FAST ? T(B.Lstd) : L_std<T>(g, B, c, I[c])) * v : v;
           if (FUSE == 2) acc = T(0.5) * (uself + acc);
           put(uo.c[c], acc);
         }
