@@ -208,13 +208,40 @@ def step_byte_model(ndim, has_body, k):
     return 4.0 * (52.0 + 115.3 * k)
 
 
+def code_text(src):
+    """C++ source without its comments, each line stripped, blank lines dropped:
+    two texts that differ only in comments or layout give the same code text."""
+    out, i, n = [], 0, len(src)
+    while i < n:
+        ch = src[i]
+        if ch in "\"'":  # string or character literal, copied whole
+            j = i + 1
+            while j < n and src[j] != ch:
+                j += 2 if src[j] == "\\" else 1
+            out.append(src[i:j + 1])
+            i = j + 1
+        elif src.startswith("//", i):
+            j = src.find("\n", i)
+            i = n if j < 0 else j
+        elif src.startswith("/*", i):
+            j = src.find("*/", i + 2)
+            i = n if j < 0 else j + 2
+            out.append(" ")
+        else:
+            out.append(ch)
+            i += 1
+    lines = (ln.strip() for ln in "".join(out).split("\n"))
+    return "\n".join(ln for ln in lines if ln)
+
+
 def kernel_source_hash():
-    """Hash of the step's kernels and of the host code that launches them."""
+    """Hash of the code (comments and layout aside) of the step's kernels and of
+    the host code that launches them."""
     import hashlib
     h = hashlib.sha256()
     for f in ("wl_kernels.hpp", "wl_device.hpp", "wlmi.hip"):
-        with open(os.path.join(ROOT, "paper_2407_16032_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(ROOT, "paper_2407_16032_amd", "csrc", f), encoding="utf-8") as fh:
+            h.update(code_text(fh.read()).encode("utf-8"))
     return h.hexdigest()[:16]
 
 

@@ -744,10 +744,6 @@ __device__ __forceinline__ void flux_column(const Grid3& g, const Vec3<T>& u, co
   T cz0 = T(0), cz1 = T(0), cz2 = T(0);
   // fast-path addresses: a base per field and plane, the same for the whole wave,
   // plus one of five 32-bit byte offsets per lane (the column and its +-1, +-2
-  // rows in y) and an immediate for the x offsets, so no lane computes a 64-bit
-  // address; the offsets are used only on the fast path, where I0, I1 >= 3
-  // fast-path addresses: a base per field and plane, the same for the whole wave,
-  // plus one of five 32-bit byte offsets per lane (the column and its +-1, +-2
   // rows in y) and a constant for the x offsets, so that no lane computes a full
   // address per load; the offsets are used only on the fast path (I0, I1 >= 3)
   const int s1 = g.s[1], s2 = g.s[2];

@@ -46,6 +46,15 @@ def test_traffic_goes_stale_when_the_sources_change(tmp_path, monkeypatch):
     assert bench.measured_traffic("w", "pcg_b") is None
 
 
+def test_source_hash_ignores_comments_but_not_code():
+    src = 'int f(int a) {\n  // twice a\n  return 2 * a; /* doubled */\n}\nconst char* s = "// kept";\n'
+    same = 'int f(int a) {\n  return 2 * a;\n\n}  // end\nconst char* s = "// kept";\n'
+    other = 'int f(int a) {\n  return 3 * a;\n}\nconst char* s = "// kept";\n'
+    assert bench.code_text(src) == bench.code_text(same)
+    assert bench.code_text(src) != bench.code_text(other)
+    assert '"// kept"' in bench.code_text(src)
+
+
 def test_flat_level_rule():
     assert bench.fine_level_flat(PLATE)
     assert bench.fine_level_flat((32, 32, 16))                  # 2^14 cells
