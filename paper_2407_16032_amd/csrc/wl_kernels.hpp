@@ -714,6 +714,22 @@ __device__ __forceinline__ T phi_vals(T a0, T a1, T uc, T m1, T fm, T fp, T nu) 
   return a * Q - nu * (uc - m1);
 }
 
+// phi_vals with the general form's rules for a face near a non-periodic x
+// boundary (its y and z stencil interior): 0 where no unknown face uses the flux
+// (need false), the central value where the far point for the upwind side lies
+// outside (up_ok / dn_ok false for a >= 0 / a < 0)
+template <typename T>
+__device__ __forceinline__ T phi_vals_edge(T a0, T a1, T uc, T m1, T fm, T fp, T nu, bool need, bool up_ok,
+                                           bool dn_ok) {
+  const T a = T(0.5) * (a0 + a1);
+  const bool up = a >= T(0);
+  const T far = pick_far<T>(up, fm, fp);
+  T Q = quick_lim(far, up ? m1 : uc, up ? uc : m1);
+  if (!(up ? up_ok : dn_ok)) Q = T(0.5) * (uc + m1);
+  const T r = a * Q - nu * (uc - m1);
+  return need ? r : T(0);
+}
+
 // Is padded index I inside the box [lo, hi] itself (no periodic widening)?
 __device__ __forceinline__ bool in_box3(const StdBox& B, const int I[3]) {
   return B.lo[0] <= B.hi[0] && I[0] >= B.lo[0] && I[0] <= B.hi[0] && I[1] >= B.lo[1] && I[1] <= B.hi[1] &&
@@ -748,8 +764,17 @@ __device__ __forceinline__ void flux_column(const Grid3& g, const Vec3<T>& u, co
   // address per load; the offsets are used only on the fast path (I0, I1 >= 3)
   const int s1 = g.s[1], s2 = g.s[2];
   constexpr int E = int(sizeof(T));
-  const uint32_t ob = uint32_t(I0 + I1 * s1) * uint32_t(E), sb = uint32_t(s1) * uint32_t(E);
+  // (lanes past the row, which store nothing, load at its last column)
+  const uint32_t ob = uint32_t(min(I0, P0 - 1) + I1 * s1) * uint32_t(E), sb = uint32_t(s1) * uint32_t(E);
   const uint32_t oy[5] = {ob - 2 * sb, ob - sb, ob, ob + sb, ob + 2 * sb};
+  // EDGE planes (the first and last bricks of a row on a non-periodic x axis):
+  // which of the lane's fluxes are used (x face; y and z faces), and whether the
+  // x face's far point lies inside for a >= 0 and for a < 0
+  // (an x-face flux is used on faces 1..N0 + 1 of every component, a y or z one on
+  // columns 1..N0; the far point of an x face is inside on 1..N0, or on 1..N0 + 1
+  // for u_x)
+  const bool need_x = I0 >= 1 && I0 <= g.n[0] + 1, need_o = I0 >= 1 && I0 <= g.n[0];
+  const bool up_ok = I0 >= 3, dn_ok = I0 + 1 <= g.n[0] + (c == 0 ? 1 : 0);
   // value at row offset dy (-2..2) and x offset dx of plane I2 + dz of field q
   typedef __attribute__((address_space(1))) T gT;
   auto at = [&](const T* q, int I2, int dz, int dy, int dx) -> T {
@@ -759,17 +784,20 @@ __device__ __forceinline__ void flux_column(const Grid3& g, const Vec3<T>& u, co
   auto put_fast = [&](T* q, int I2, T val) {
     *reinterpret_cast<gT*>(uniform_ptr(q + size_t(I2) * size_t(s2)) + size_t(ob)) = val;
   };
-  // one plane of the march; FAST (the plain-offset stencil, every lane of the
-  // wave interior enough for it) or the general form per lane
-  auto plane = [&](auto fast_tag, int I2) {
-    constexpr bool FAST = decltype(fast_tag)::value;
+  // one plane of the march: MODE 1 (FAST) the plain-offset stencil, every lane
+  // of the wave interior enough for it; MODE 2 (EDGE) the same loads with the
+  // general form's x-boundary rules per lane (non-periodic x, rows and planes
+  // interior); MODE 0 the general form per lane
+  auto plane = [&](auto mode_tag, int I2) {
+    constexpr int MODE = decltype(mode_tag)::value;
+    constexpr bool FAST = MODE == 1, LOADS = MODE != 0;
     T phx, phy, phyn, phzn;
     // u0 at the face (column clamped into the row for the lanes that store nothing)
     // is loaded ahead of the stencil; with FUSE = 2 also u at the face
     const int idx = lin3<T, 3>(g, min(I0, P0 - 1), I1, I2);
     T u0v;
     T uself = T(0);
-    if (FAST) {
+    if (LOADS) {
       u0v = at(u0.c[c], I2, 0, 0, 0);
       // keeps the load here: the compiler would otherwise sink it into the
       // store block below, after the fluxes, a second round trip per plane
@@ -793,10 +821,19 @@ __device__ __forceinline__ void flux_column(const Grid3& g, const Vec3<T>& u, co
       const T ay0 = C == 1 ? c0 : at(u.c[1], I2, 0, 0, 0), ay1 = C == 1 ? ym1 : at(u.c[1], I2, cz, cy, cx);
       const T ayn0 = C == 1 ? yp1 : at(u.c[1], I2, 0, 1, 0), ayn1 = C == 1 ? c0 : at(u.c[1], I2, cz, 1 + cy, cx);
       const T azn0 = C == 2 ? zp1 : at(u.c[2], I2, 1, 0, 0), azn1 = C == 2 ? c0 : at(u.c[2], I2, 1 + cz, cy, cx);
-      phx = phi_vals<T>(ax0, ax1, c0, xm1, xm2, xp1, nu);
+      if (FAST) {
+        phx = phi_vals<T>(ax0, ax1, c0, xm1, xm2, xp1, nu);
+      } else {
+        phx = phi_vals_edge<T>(ax0, ax1, c0, xm1, xm2, xp1, nu, need_x, up_ok, dn_ok);
+      }
       phy = phi_vals<T>(ay0, ay1, c0, ym1, ym2, yp1, nu);
       phyn = phi_vals<T>(ayn0, ayn1, yp1, c0, ym1, yp2, nu);
       phzn = phi_vals<T>(azn0, azn1, zp1, c0, zm1, zp2, nu);
+      if (!FAST) {
+        phy = need_o ? phy : T(0);
+        phyn = need_o ? phyn : T(0);
+        phzn = need_o ? phzn : T(0);
+      }
       if (FUSE == 2) uself = c0;
     } else {
       u0v = u0.c[c][idx];
@@ -810,9 +847,12 @@ __device__ __forceinline__ void flux_column(const Grid3& g, const Vec3<T>& u, co
     if (col) {
       const int I[3] = {I0, I1, I2};
       // on the fast planes every face is an unknown two or more cells from each
-      // boundary: no wrap, and L = B.Lstd
+      // boundary: no wrap, and L = B.Lstd; on the EDGE planes the same holds in y
+      // and z, and x (not periodic) decides
       bool unknown = true, wraps = false;
-      if (!FAST) {
+      if (MODE == 2) {
+        unknown = I0 >= (c == 0 ? 2 : 1) && I0 <= g.n[0];
+      } else if (MODE == 0) {
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
           const int lo = (a == c && !g.per[a]) ? 2 : 1;
@@ -821,10 +861,10 @@ __device__ __forceinline__ void flux_column(const Grid3& g, const Vec3<T>& u, co
         }
       }
       const bool needV = has_body && !std_point<3>(B, g, I, 0);  // V = 0 outside the box
-      const T vb = needV ? (FAST ? at(V.c[c], I2, 0, 0, 0) : V.c[c][idx]) : T(0);
+      const T vb = needV ? (LOADS ? at(V.c[c], I2, 0, 0, 0) : V.c[c][idx]) : T(0);
       T R = T(0);
       if (unknown) {
-        if (wraps) {
+        if (MODE == 0 && wraps) {
           R = resid_c<T, 3>(g, u, c, I, nu);
         } else {
           R = R + (phx - phxn);
@@ -835,7 +875,7 @@ __device__ __forceinline__ void flux_column(const Grid3& g, const Vec3<T>& u, co
       T v = u0v + dt * R;
       if (needV) v = v - vb;
       auto put = [&](T* q, T val) {
-        if (FAST) put_fast(q, I2, val);
+        if (LOADS) put_fast(q, I2, val);
         else q[idx] = val;
       };
       if (FUSE == 0) {
@@ -843,7 +883,9 @@ __device__ __forceinline__ void flux_column(const Grid3& g, const Vec3<T>& u, co
       } else {
         if (has_body && !std_point<3>(B, g, I, 1)) put(f.c[c], v);
         if (!in_box3(B, I)) {
-          T acc = has_body ? (FAST ? T(B.Lstd) : L_std<T>(g, B, c, I[c])) * v : v;
+          const T Lf = FAST ? T(B.Lstd) : MODE == 2 ? (c == 0 ? L_std<T>(g, B, 0, I0) : T(B.Lstd))
+                                                    : L_std<T>(g, B, c, I[c]);
+          T acc = has_body ? Lf * v : v;
           if (FUSE == 2) acc = T(0.5) * (uself + acc);
           put(uo.c[c], acc);
         }
@@ -851,23 +893,30 @@ __device__ __forceinline__ void flux_column(const Grid3& g, const Vec3<T>& u, co
     }
     phz = phzn;
   };
-  // planes [za, zb) take the fast path: the march is split into three loops, so
-  // the fast loop's body has no branch whose join would make it wait for u0
-  // before the stencil's loads go out (the two may be in flight together)
+  // planes [za, zb) take the fast or the EDGE path: the march is split into
+  // three loops, so that the middle loop's body has no branch whose join would
+  // make it wait for u0 before the stencil's loads go out (the two may be in
+  // flight together)
+  typedef std::integral_constant<int, 0> Gen;
   int za = z0, zb = z0;
-  const bool fxy = I0 >= 3 && I0 <= g.n[0] - 2 && I1 >= 3 && I1 <= g.n[1] - 2;
-  if (__builtin_amdgcn_ballot_w64(fxy) == __builtin_amdgcn_read_exec()) {
+  const bool fy = I1 >= 3 && I1 <= g.n[1] - 2;  // the same for the whole wave
+  const bool fx = __builtin_amdgcn_ballot_w64(I0 >= 3 && I0 <= g.n[0] - 2) == __builtin_amdgcn_read_exec();
+  if (fy && (fx || !g.per[0])) {
     za = min(max(z0, 3), z1);
     zb = max(za, min(z1, g.n[2] - 1));
   }
-  for (int I2 = z0; I2 < za; ++I2) plane(std::false_type{}, I2);
+  for (int I2 = z0; I2 < za; ++I2) plane(Gen{}, I2);
   if (za < zb) {
     cz0 = at(u.c[c], za, -1, 0, 0);
     cz1 = at(u.c[c], za, 0, 0, 0);
     cz2 = at(u.c[c], za, 1, 0, 0);
+    if (fx) {
+      for (int I2 = za; I2 < zb; ++I2) plane(std::integral_constant<int, 1>{}, I2);
+    } else {
+      for (int I2 = za; I2 < zb; ++I2) plane(std::integral_constant<int, 2>{}, I2);
+    }
   }
-  for (int I2 = za; I2 < zb; ++I2) plane(std::true_type{}, I2);
-  for (int I2 = zb; I2 < z1; ++I2) plane(std::false_type{}, I2);
+  for (int I2 = zb; I2 < z1; ++I2) plane(Gen{}, I2);
 }
 
 template <typename T, int FUSE>
