@@ -207,6 +207,32 @@ def test_one_step_ragged_3d_grids(n, periodic, prec):
     gpu.close()
 
 
+@pytest.mark.parametrize("n,bx", [((61, 12, 12), 0.3), ((62, 12, 11), 0.3), ((63, 11, 12), 0.3), ((124, 10, 9), 0.3),
+                                  ((63, 12, 12), None)])
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_one_step_x_brick_edges(n, bx, prec):
+    """Bricks of 63 columns against the x extent on a bounded x axis: padded rows of
+    exactly 63, 64, 65 and 126 columns (one brick with its supply lane past the
+    row; a last brick of one ghost column; of an interior column and the ghost; two
+    full bricks).  The first and last brick of each row take the fast loads with the
+    general form's boundary rules per lane; one step against the oracle, with the
+    body near the inlet or (bx None) 8 cells from the outlet (y and z periodic, so
+    that only the x walls bound the body's reach)."""
+    _say("x brick edges", prec, n, bx)
+    cx = 0.3 * n[0] if bx is not None else n[0] - 8.0
+    body = wlsynth.Body("sphere", center=(cx, 0.5 * n[1] + 0.2, 0.5 * n[2] - 0.3), radius=2.0)
+    w = wlsynth.Workload("xedges", n, (1.0, 0.0, 0.0), 0.02, body, periodic=(False, True, True),
+                         convective_exit=True, tol=1e-13)
+    ref, gpu = make_pair(w, prec, 1e-13 if prec == "f64" else 1e-6)
+    ref.tol = 1e-13
+    ref.step()
+    gpu.step()
+    err = rel_l2(gpu.get("u"), ref.u, ref.grid)
+    _say("  rel-L2 u", err)
+    assert err <= (FP64_STEP if prec == "f64" else FP32_STEP)
+    gpu.close()
+
+
 def test_solver_paths_agree_on_a_large_grid():
     """256 x 128 x 128 sphere wake in FP64: the fine level takes the flat passes
     (automatic), the z-marching tiles or the generic kernels, and the first coarse
